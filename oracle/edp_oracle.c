@@ -1,0 +1,293 @@
+/*
+ * Plain C oracle for scanline DP and EDP (Mozerov, arXiv 1410.7922).
+ *
+ * TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the CPU
+ * baseline of the benchmark load this library.  It shares no code with the
+ * GPU library and is written from the paper's definitions:
+ *
+ *   V(u)     truncated linear prior, Sec. 2 eq. Smooth_value_t with f(|a|)=|a|;
+ *            mode 0 truncates each label dimension, mode 1 the summed distance.
+ *   M(h)(v)  = min_v' h(v') + V(v - v')       Sec. 2 eq. M_strf
+ *            search 0: straightforward search over all v' (SFMS, the definition)
+ *            search 1: the linear RMS passes of Sec. 3.2 (eqs. L_dec3, L_dec5
+ *                      read as the mirror of L_dec3, L_dec6, clip of L_dec7).
+ *   DP       S(0)=C(0), S(x+1)=C(x+1)+M(S(x))  Sec. 2 eq. base, Sec. 4.1
+ *   EDP      Sec. 4.2 eq. DP_2D_base with C added, S/2 as floor division,
+ *            scans P1..P4 in place, eq. DP_2D_1 marginal, eq. DP_2D_2 argmin.
+ *
+ * All sums are computed in int64; EDP sums are stored as int32 after a range
+ * check (the check's failure is reported, never wrapped).  Single threaded.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_ARGS -1
+#define OR_E_RANGE -2
+#define OR_E_NOMEM -3
+
+typedef struct {
+    int qx, qy, q, lam, trunc, mode;
+} prior_t;
+
+static int64_t iabs64(int64_t a) { return a < 0 ? -a : a; }
+static int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+static int64_t prior_v(const prior_t *p, int v, int w) {
+    int64_t ax = iabs64((int64_t)(v % p->qx) - (w % p->qx));
+    int64_t ay = iabs64((int64_t)(v / p->qx) - (w / p->qx));
+    if (p->mode == 0) return (int64_t)p->lam * (imin64(ax, p->trunc) + imin64(ay, p->trunc));
+    return (int64_t)p->lam * imin64(ax + ay, p->trunc);
+}
+
+/* M by straightforward search; arg (nullable) receives the smallest minimising v'. */
+static void msearch_sfms(const prior_t *p, const int64_t *h, int64_t *out, int32_t *arg) {
+    for (int v = 0; v < p->q; ++v) {
+        int64_t best = h[0] + prior_v(p, v, 0);
+        int bi = 0;
+        for (int w = 1; w < p->q; ++w) {
+            int64_t t = h[w] + prior_v(p, v, w);
+            if (t < best) { best = t; bi = w; }
+        }
+        out[v] = best;
+        if (arg) arg[v] = bi;
+    }
+}
+
+/* One line of L_r: forward S+ (eq. L_dec3), backward S- over strictly larger
+ * labels with S-(last) = +inf (eq. L_dec5, mirrored), comparison (eq. L_dec6). */
+static void lrms_line(int64_t *line, int n, int stride, int64_t lam, int64_t *plus, int64_t *minus) {
+    plus[0] = line[0];
+    for (int v = 1; v < n; ++v) plus[v] = imin64(plus[v - 1] + lam, line[(size_t)v * stride]);
+    int have = 0;
+    for (int v = n - 2; v >= 0; --v) {
+        int64_t nxt = line[(size_t)(v + 1) * stride];
+        if (have) nxt = imin64(nxt, minus[v + 1]);
+        minus[v] = nxt + lam;
+        have = 1;
+    }
+    for (int v = 0; v < n; ++v) {
+        int64_t r = plus[v];
+        if (v < n - 1) r = imin64(r, minus[v]);
+        line[(size_t)v * stride] = r;
+    }
+}
+
+static void msearch_lrms(const prior_t *p, const int64_t *h, int64_t *out, int64_t *scratch) {
+    int64_t *plus = scratch, *minus = scratch + 4096;
+    int64_t lam = p->lam, clipd = (int64_t)p->lam * p->trunc;
+    int64_t gmin = h[0];
+    for (int v = 0; v < p->q; ++v) { out[v] = h[v]; if (h[v] < gmin) gmin = h[v]; }
+    for (int vy = 0; vy < p->qy; ++vy) {           /* dimension x: lines of fixed vy */
+        int64_t *line = out + (size_t)vy * p->qx;
+        int64_t lmin = line[0];
+        for (int vx = 1; vx < p->qx; ++vx) lmin = imin64(lmin, line[vx]);
+        lrms_line(line, p->qx, 1, lam, plus, minus);
+        if (p->mode == 0)
+            for (int vx = 0; vx < p->qx; ++vx) line[vx] = imin64(line[vx], lmin + clipd);
+    }
+    if (p->qy > 1) {
+        for (int vx = 0; vx < p->qx; ++vx) {       /* dimension y: lines of fixed vx */
+            int64_t *line = out + vx;
+            int64_t lmin = line[0];
+            for (int vy = 1; vy < p->qy; ++vy) lmin = imin64(lmin, line[(size_t)vy * p->qx]);
+            lrms_line(line, p->qy, p->qx, lam, plus, minus);
+            if (p->mode == 0)
+                for (int vy = 0; vy < p->qy; ++vy)
+                    line[(size_t)vy * p->qx] = imin64(line[(size_t)vy * p->qx], lmin + clipd);
+        }
+    }
+    if (p->mode == 1)
+        for (int v = 0; v < p->q; ++v) out[v] = imin64(out[v], gmin + clipd);
+}
+
+static void msearch(const prior_t *p, int search, const int64_t *h, int64_t *out, int64_t *scratch) {
+    if (search == 1) msearch_lrms(p, h, out, scratch);
+    else msearch_sfms(p, h, out, NULL);
+}
+
+static int check_args(int W, int H, int qx, int qy, int lam, int trunc, int mode) {
+    if (W < 1 || H < 1 || qx < 1 || qy < 1 || qx > 4096 || qy > 4096 || (int64_t)qx * qy > 4096) return 0;
+    if (lam < 0 || trunc < 1 || (mode != 0 && mode != 1)) return 0;
+    return 1;
+}
+
+/* Energy of eq. GE_objective_function; grid4 = 0: rows only, 1: 4-connected. */
+int64_t oracle_energy(int W, int H, int qx, int qy, int lam, int trunc, int mode, int grid4,
+                      const int32_t *cost, const int32_t *labels) {
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    int64_t e = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int l = labels[(size_t)y * W + x];
+            e += cost[((size_t)y * W + x) * p.q + l];
+            if (x + 1 < W) e += prior_v(&p, labels[(size_t)y * W + x + 1], l);
+            if (grid4 && y + 1 < H) e += prior_v(&p, labels[(size_t)(y + 1) * W + x], l);
+        }
+    return e;
+}
+
+/* Scanline DP over every row.  search 0: SFMS with stored choice indexes;
+ * search 1: LRMS values, and at backtracking the choice index at the chosen
+ * label is found by direct search over the stored S(x-1) (the same argmin). */
+int oracle_dp_scanline(int W, int H, int qx, int qy, int lam, int trunc, int mode, int search,
+                       const int32_t *cost, int32_t *labels, int64_t *row_energy, int64_t *total) {
+    if (!check_args(W, H, qx, qy, lam, trunc, mode)) return OR_E_ARGS;
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    int Q = p.q;
+    int64_t *S = malloc(sizeof(int64_t) * (size_t)W * Q);
+    int64_t *m = malloc(sizeof(int64_t) * Q);
+    int64_t *scratch = malloc(sizeof(int64_t) * 8192);
+    int32_t *ptr = malloc(sizeof(int32_t) * (size_t)W * Q);
+    if (!S || !m || !scratch || !ptr) { free(S); free(m); free(scratch); free(ptr); return OR_E_NOMEM; }
+    int64_t tot = 0;
+    for (int y = 0; y < H; ++y) {
+        const int32_t *c = cost + (size_t)y * W * Q;
+        for (int v = 0; v < Q; ++v) S[v] = c[v];
+        for (int x = 1; x < W; ++x) {
+            if (search == 1) msearch_lrms(&p, S + (size_t)(x - 1) * Q, m, scratch);
+            else msearch_sfms(&p, S + (size_t)(x - 1) * Q, m, ptr + (size_t)x * Q);
+            for (int v = 0; v < Q; ++v) S[(size_t)x * Q + v] = c[(size_t)x * Q + v] + m[v];
+        }
+        const int64_t *last = S + (size_t)(W - 1) * Q;
+        int bi = 0;
+        for (int v = 1; v < Q; ++v) if (last[v] < last[bi]) bi = v;
+        row_energy[y] = last[bi];
+        tot += last[bi];
+        int32_t *lab = labels + (size_t)y * W;
+        lab[W - 1] = bi;
+        for (int x = W - 1; x > 0; --x) {
+            int v = lab[x];
+            if (search == 1) {
+                const int64_t *prev = S + (size_t)(x - 1) * Q;
+                int64_t best = prev[0] + prior_v(&p, v, 0);
+                int b = 0;
+                for (int w = 1; w < Q; ++w) {
+                    int64_t t = prev[w] + prior_v(&p, v, w);
+                    if (t < best) { best = t; b = w; }
+                }
+                lab[x - 1] = b;
+            } else {
+                lab[x - 1] = ptr[(size_t)x * Q + v];
+            }
+        }
+    }
+    *total = tot;
+    free(S); free(m); free(scratch); free(ptr);
+    return OR_OK;
+}
+
+static int64_t floor_half(int64_t s) { return s >= 0 ? s / 2 : -((-s + 1) / 2); }
+
+/* direction k: 0 +x, 1 -x, 2 +y, 3 -y; predecessor x_k = x - sgn(k) e_|k| */
+static const int KDX[4] = {1, -1, 0, 0};
+static const int KDY[4] = {0, 0, 1, -1};
+static const int KOPP[4] = {1, 0, 3, 2};
+
+/* Literal EDP (Algorithm 1 steps 3-5).  sums: 4 x [H][W][Q] int32 (caller may pass
+ * NULL to let the oracle allocate).  marginal_out [H][W][Q] int64 is nullable. */
+int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
+               int search, const int32_t *cost, int32_t *labels, int64_t *energy_out,
+               int64_t *max_abs_out, int64_t *marginal_out) {
+    if (!check_args(W, H, qx, qy, lam, trunc, mode) || iterations < 0) return OR_E_ARGS;
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    int Q = p.q;
+    size_t cells = (size_t)W * H;
+    int32_t *S = calloc((size_t)4 * cells * Q, sizeof(int32_t));
+    int64_t *h = malloc(sizeof(int64_t) * Q);
+    int64_t *m = malloc(sizeof(int64_t) * 4 * Q);
+    int64_t *acc = malloc(sizeof(int64_t) * Q);
+    int64_t *scratch = malloc(sizeof(int64_t) * 8192);
+    int64_t *nw = malloc(sizeof(int64_t) * 2 * Q);
+    if (!S || !h || !m || !acc || !scratch || !nw) {
+        free(S); free(h); free(m); free(acc); free(scratch); free(nw);
+        return OR_E_NOMEM;
+    }
+    int64_t maxabs = 0;
+    int status = OR_OK;
+    /* scans: x order, y order, computed sums */
+    const int sx[4] = {1, -1, 1, -1}, sy[4] = {1, 1, -1, -1};
+    const int ka[4] = {0, 1, 0, 1}, kb[4] = {2, 2, 3, 3};
+    for (int it = 0; it < iterations; ++it) {
+        for (int pass = 0; pass < 4; ++pass) {
+            for (int yi = 0; yi < H; ++yi) {
+                int y = sy[pass] > 0 ? yi : H - 1 - yi;
+                for (int xi = 0; xi < W; ++xi) {
+                    int x = sx[pass] > 0 ? xi : W - 1 - xi;
+                    for (int k = 0; k < 4; ++k) {      /* m_k = M(S_k(x_k) / 2), 0 off grid */
+                        int px = x - KDX[k], py = y - KDY[k];
+                        int64_t *mk = m + (size_t)k * Q;
+                        if (px < 0 || px >= W || py < 0 || py >= H) {
+                            for (int v = 0; v < Q; ++v) mk[v] = 0;
+                            continue;
+                        }
+                        const int32_t *sk = S + ((size_t)k * cells + (size_t)py * W + px) * Q;
+                        for (int v = 0; v < Q; ++v) h[v] = floor_half(sk[v]);
+                        msearch(&p, search, h, mk, scratch);
+                    }
+                    const int32_t *c = cost + ((size_t)y * W + x) * Q;
+                    int comp[2] = {ka[pass], kb[pass]};
+                    for (int j = 0; j < 2; ++j) {       /* eq. DP_2D_base with C added */
+                        int kp = comp[j];
+                        for (int v = 0; v < Q; ++v) {
+                            int64_t s = c[v];
+                            for (int k = 0; k < 4; ++k)
+                                if (k != KOPP[kp]) s += m[(size_t)k * Q + v];
+                            s -= m[(size_t)KOPP[kp] * Q + v];
+                            nw[(size_t)j * Q + v] = s;
+                        }
+                    }
+                    for (int j = 0; j < 2; ++j) {
+                        int32_t *dst = S + ((size_t)comp[j] * cells + (size_t)y * W + x) * Q;
+                        for (int v = 0; v < Q; ++v) {
+                            int64_t s = nw[(size_t)j * Q + v];
+                            if (iabs64(s) > maxabs) maxabs = iabs64(s);
+                            if (s > INT32_MAX || s < INT32_MIN) status = OR_E_RANGE;
+                            dst[v] = (int32_t)s;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {                   /* eq. DP_2D_1 with C, eq. DP_2D_2 */
+            const int32_t *c = cost + ((size_t)y * W + x) * Q;
+            for (int v = 0; v < Q; ++v) acc[v] = c[v];
+            for (int k = 0; k < 4; ++k) {
+                int px = x - KDX[k], py = y - KDY[k];
+                if (px < 0 || px >= W || py < 0 || py >= H) continue;
+                const int32_t *sk = S + ((size_t)k * cells + (size_t)py * W + px) * Q;
+                for (int v = 0; v < Q; ++v) h[v] = floor_half(sk[v]);
+                msearch(&p, search, h, m, scratch);
+                for (int v = 0; v < Q; ++v) acc[v] += m[v];
+            }
+            int bi = 0;
+            for (int v = 1; v < Q; ++v) if (acc[v] < acc[bi]) bi = v;
+            labels[(size_t)y * W + x] = bi;
+            if (marginal_out)
+                memcpy(marginal_out + ((size_t)y * W + x) * Q, acc, sizeof(int64_t) * Q);
+        }
+    *energy_out = oracle_energy(W, H, qx, qy, lam, trunc, mode, 1, cost, labels);
+    *max_abs_out = maxabs;
+    free(S); free(h); free(m); free(acc); free(scratch); free(nw);
+    return status;
+}
+
+/* M on a batch of n vectors h[n][Q] (search 0: SFMS with arg (nullable); 1: LRMS). */
+int oracle_min_search(int qx, int qy, int lam, int trunc, int mode, int search, int n,
+                      const int64_t *h, int64_t *out, int32_t *arg) {
+    if (!check_args(1, 1, qx, qy, lam, trunc, mode) || n < 0) return OR_E_ARGS;
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    int64_t *scratch = malloc(sizeof(int64_t) * 8192);
+    if (!scratch) return OR_E_NOMEM;
+    for (int i = 0; i < n; ++i) {
+        const int64_t *hi = h + (size_t)i * p.q;
+        int64_t *oi = out + (size_t)i * p.q;
+        if (search == 1) msearch_lrms(&p, hi, oi, scratch);
+        else msearch_sfms(&p, hi, oi, arg ? arg + (size_t)i * p.q : NULL);
+    }
+    free(scratch);
+    return OR_OK;
+}

@@ -1,0 +1,355 @@
+"""Plain numpy / Python oracle -- TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Notation follows the paper (Mozerov, arXiv 1410.7922):
+
+* ``C[y][x][q]``  data cost (disparity space image), Sec. 2;
+  flat label ``q = vy * qx + vx``, 0-based (the paper counts from 1).
+* ``V(u)``        truncated linear prior, Sec. 2 eq. Smooth_value_t with
+  f(|a|) = |a|; ``mode`` 1 truncates the summed distance over the label
+  dimensions as the paper does, ``mode`` 0 truncates each dimension on its own.
+* ``M(h)(v) = min_v' h(v') + V(v - v')``  the minimum search operator,
+  Sec. 2 eq. M_strf; ``argM`` takes the smallest flat index among ties.
+* scanline DP: Sec. 2 eq. base with the zero boundary of Sec. 4.1 eq. DP_1D_2;
+* EDP: Sec. 4.2 eqs. DP_2D_1, DP_2D_base, DP_2D_2 and Algorithm 1.
+
+Readings where the paper is silent or garbled (each one is listed in the
+design notes of the repository):
+
+* the data cost C(x, v) is added in eqs. DP_2D_1 and DP_2D_base, as in the
+  one-dimensional forms eq. base and eq. DP_1D_3 (without it every sum stays 0);
+* ``S / D`` with D = 2 is floor division (``S // 2``), S can be negative;
+* before the first pass every S_k is 0, and off the grid S_k and M(S_k) are 0;
+* the four scans run P1, P2, P3, P4 in place; a scan reads the sums it does
+  not write with the values they hold when the scan starts;
+* every argmin returns the smallest flat label;
+* eq. L_dec5 (backward pass of the linear RMS) is read as the mirror of
+  eq. L_dec3: S^-(v) = min over v'' > v of S(v'') + lambda (v'' - v), with
+  S^-(v_max) = +inf.
+
+Every floating point question is absent: all arithmetic is on Python / int64
+integers, and every EDP sum is checked to fit in int32 (the GPU's type).
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+TRUNC_PER_DIM = 0
+TRUNC_JOINT = 1
+INT32_MAX = 2**31 - 1
+
+
+# ---------------------------------------------------------------------------
+# prior and minimum search
+# ---------------------------------------------------------------------------
+
+def prior_value(ux: int, uy: int, lam: int, trunc: int, mode: int) -> int:
+    """V(u) for a label difference u = (ux, uy): Sec. 2 eq. Smooth_value_t, f(|a|) = |a|."""
+    ax, ay = abs(int(ux)), abs(int(uy))
+    if mode == TRUNC_PER_DIM:
+        return lam * (min(ax, trunc) + min(ay, trunc))
+    return lam * min(ax + ay, trunc)
+
+
+def prior_matrix(qx: int, qy: int, lam: int, trunc: int, mode: int) -> np.ndarray:
+    """Vm[v, v'] = V(v - v') over flat labels, int64 [Q, Q]."""
+    q = np.arange(qx * qy)
+    vx, vy = q % qx, q // qx
+    ax = np.abs(vx[:, None] - vx[None, :])
+    ay = np.abs(vy[:, None] - vy[None, :])
+    if mode == TRUNC_PER_DIM:
+        return (lam * (np.minimum(ax, trunc) + np.minimum(ay, trunc))).astype(np.int64)
+    return (lam * np.minimum(ax + ay, trunc)).astype(np.int64)
+
+
+class OpCounter:
+    """Counts candidate comparisons per output label (Sec. 5.2, Table 1)."""
+
+    def __init__(self):
+        self.ops = 0
+        self.outputs = 0
+
+    @property
+    def per_vertex(self) -> float:
+        return self.ops / max(self.outputs, 1)
+
+
+def min_search_sfms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                    counter: OpCounter | None = None):
+    """Straightforward minimum search (SFMS, Sec. 3 end): the definition eq. M_strf.
+
+    ``h`` has shape [..., Q].  Returns (M(h), argM(h)); argM is the smallest
+    flat index v' attaining the minimum.
+    """
+    h = np.asarray(h, dtype=np.int64)
+    vm = prior_matrix(qx, qy, lam, trunc, mode)
+    tot = h[..., None, :] + vm                    # [..., v, v']
+    arg = np.argmin(tot, axis=-1)                 # first minimum = smallest v'
+    val = np.take_along_axis(tot, arg[..., None], axis=-1)[..., 0]
+    if counter is not None:
+        n_out = int(np.prod(h.shape))
+        counter.outputs += n_out
+        counter.ops += n_out * h.shape[-1]
+    return val, arg
+
+
+def _linear_rms_line(line: list, lam: int, counter: OpCounter | None):
+    """Operator L_r of Sec. 3.2 on one line: eq. L_dec3, eq. L_dec5 (read as its mirror), eq. L_dec6."""
+    n = len(line)
+    plus = [0] * n
+    plus[0] = line[0]                                  # S+(1) = S(1)
+    for v in range(1, n):                              # S+(v+1) = (S+(v) + lam) ^ S(v+1)
+        plus[v] = min(plus[v - 1] + lam, line[v])
+    minus = [None] * n                                 # S-(v_max) = +inf
+    for v in range(n - 2, -1, -1):                     # S-(v) = (S-(v+1) ^ S(v+1)) + lam
+        nxt = line[v + 1] if minus[v + 1] is None else min(minus[v + 1], line[v + 1])
+        minus[v] = nxt + lam
+    out = [plus[v] if minus[v] is None else min(plus[v], minus[v]) for v in range(n)]
+    if counter is not None:
+        counter.ops += 3 * n                           # forward, backward, comparison
+    return out
+
+
+def min_search_lrms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                    counter: OpCounter | None = None) -> np.ndarray:
+    """Linear RMS (LRMS, Sec. 3.2): per-dimension L_r passes and the clip of eq. L_dec7.
+
+    ``mode`` 1 (joint truncation, the paper's prior): M = L_y(L_x(h)) ^ (min h + lam*T),
+    eq. L_dec7.  ``mode`` 0 (per-dimension truncation): each dimension's prior is a
+    one-dimensional truncated linear prior, so the decomposition of eq. derivation2 applies
+    per dimension with its own clip (eq. derivation1 applied to that dimension):
+    M = clip_y(L_y(clip_x(L_x(h)))).  Only the values are returned.
+    """
+    h = np.asarray(h, dtype=np.int64)
+    lead = h.shape[:-1]
+    flat = h.reshape(-1, qy, qx)
+    out = np.empty_like(flat)
+    for n in range(flat.shape[0]):
+        g = [[int(flat[n, vy, vx]) for vx in range(qx)] for vy in range(qy)]
+        # dimension x (r = 1): lines of fixed vy
+        for vy in range(qy):
+            line = _linear_rms_line(g[vy], lam, counter)
+            if mode == TRUNC_PER_DIM:
+                clip = min(g[vy]) + lam * trunc
+                line = [min(a, clip) for a in line]
+            g[vy] = line
+        # dimension y (r = 2): lines of fixed vx
+        if qy > 1:
+            for vx in range(qx):
+                col = [g[vy][vx] for vy in range(qy)]
+                line = _linear_rms_line(col, lam, counter)
+                if mode == TRUNC_PER_DIM:
+                    clip = min(col) + lam * trunc
+                    line = [min(a, clip) for a in line]
+                for vy in range(qy):
+                    g[vy][vx] = line[vy]
+        if mode == TRUNC_JOINT:
+            clip = int(flat[n].min()) + lam * trunc
+            g = [[min(a, clip) for a in row] for row in g]
+        out[n] = np.array(g, dtype=np.int64)
+        if counter is not None:
+            counter.outputs += qx * qy
+    return out.reshape(*lead, qx * qy)
+
+
+# ---------------------------------------------------------------------------
+# energy (Sec. 2 eq. GE_objective_function)
+# ---------------------------------------------------------------------------
+
+def energy(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, trunc: int,
+           mode: int, grid4: bool) -> int:
+    """E = sum_x C(x, v(x)) + sum over neighbour pairs of V(v(x') - v(x)).
+
+    ``grid4`` False: horizontal pairs only (independent scanlines, eq. One_d);
+    True: horizontal and vertical pairs (the 2D energy EDP approximates).
+    """
+    cost = np.asarray(cost)
+    labels = np.asarray(labels, dtype=np.int64)
+    H, W, _ = cost.shape
+    yy, xx = np.mgrid[0:H, 0:W]
+    e = int(cost[yy, xx, labels].astype(np.int64).sum())
+    vx, vy = labels % qx, labels // qx
+
+    def pair(ax, ay):
+        if mode == TRUNC_PER_DIM:
+            return lam * (np.minimum(ax, trunc) + np.minimum(ay, trunc))
+        return lam * np.minimum(ax + ay, trunc)
+
+    e += int(pair(np.abs(vx[:, 1:] - vx[:, :-1]), np.abs(vy[:, 1:] - vy[:, :-1])).sum())
+    if grid4:
+        e += int(pair(np.abs(vx[1:, :] - vx[:-1, :]), np.abs(vy[1:, :] - vy[:-1, :])).sum())
+    return e
+
+
+# ---------------------------------------------------------------------------
+# scanline DP (Sec. 2 eq. One_d / eq. base, Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int):
+    """Brute-force scanline DP: every row is an independent chain.
+
+    S(0, v) = C(0, v) (zero boundary, eq. DP_1D_2), S(x+1) = C(x+1) + M(S(x)) (eq. base)
+    with M by straightforward search; E_row = min_v S(W-1, v); the labels are
+    recovered backwards from the stored optimal choice indexes.
+    Returns (labels [H][W] int64, row energies [H] int64, total energy int).
+    """
+    cost = np.asarray(cost, dtype=np.int64)
+    H, W, Q = cost.shape
+    ptr = np.zeros((H, W, Q), np.int64)
+    s = cost[:, 0, :].copy()
+    for x in range(1, W):
+        m, a = min_search_sfms(s, qx, qy, lam, trunc, mode)
+        ptr[:, x, :] = a
+        s = cost[:, x, :] + m
+    row_e = s.min(axis=1)
+    labels = np.zeros((H, W), np.int64)
+    labels[:, W - 1] = np.argmin(s, axis=1)
+    rows = np.arange(H)
+    for x in range(W - 1, 0, -1):
+        labels[:, x - 1] = ptr[rows, x, labels[:, x]]
+    return labels, row_e, int(row_e.sum())
+
+
+def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int):
+    """Modified DP of Sec. 4.1, eq. DP_1D_3: S_Omega(x) = M(S_1(x-1)) + C(x) + M(S_-1(x+1)).
+
+    S_1 runs left to right, S_-1 right to left, both with the zero boundary.
+    Returns S_Omega [W][Q].
+    """
+    c = np.asarray(cost_row, dtype=np.int64)
+    W, Q = c.shape
+    fwd = np.zeros((W, Q), np.int64)
+    bwd = np.zeros((W, Q), np.int64)
+    fwd[0] = c[0]
+    for x in range(1, W):
+        fwd[x] = c[x] + min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode)[0]
+    bwd[W - 1] = c[W - 1]
+    for x in range(W - 2, -1, -1):
+        bwd[x] = c[x] + min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode)[0]
+    marg = c.copy()
+    for x in range(W):
+        if x > 0:
+            marg[x] += min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode)[0]
+        if x < W - 1:
+            marg[x] += min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode)[0]
+    return marg
+
+
+# ---------------------------------------------------------------------------
+# exhaustive enumeration (tiny inputs)
+# ---------------------------------------------------------------------------
+
+def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int):
+    """All Q^W labellings of one chain.  Returns (E_min, canonical optimal labelling).
+
+    The canonical labelling is the reverse-lexicographic minimum among the optimal
+    ones (smallest v(W-1), then smallest v(W-2), ...).
+    """
+    c = np.asarray(cost_row, dtype=np.int64)
+    W, Q = c.shape
+    labs = np.array(list(itertools.product(range(Q), repeat=W)), dtype=np.int64)
+    e = c[np.arange(W)[None, :], labs].sum(axis=1)
+    vm = prior_matrix(qx, qy, lam, trunc, mode)
+    for x in range(W - 1):
+        e += vm[labs[:, x + 1], labs[:, x]]
+    best = e.min()
+    opt = labs[e == best]
+    order = np.lexsort(tuple(opt[:, x] for x in range(W)))   # last key (x = W-1) is primary
+    return int(best), opt[order[0]]
+
+
+def grid_exhaustive(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int) -> int:
+    """Minimum 4-connected energy over all Q^(W*H) labellings of a tiny grid."""
+    c = np.asarray(cost, dtype=np.int64)
+    H, W, Q = c.shape
+    n = H * W
+    labs = np.array(list(itertools.product(range(Q), repeat=n)), dtype=np.int64).reshape(-1, H, W)
+    yy, xx = np.mgrid[0:H, 0:W]
+    e = c[yy[None], xx[None], labs].reshape(labs.shape[0], -1).sum(axis=1)
+    vm = prior_matrix(qx, qy, lam, trunc, mode)
+    e += vm[labs[:, :, 1:], labs[:, :, :-1]].reshape(labs.shape[0], -1).sum(axis=1)
+    e += vm[labs[:, 1:, :], labs[:, :-1, :]].reshape(labs.shape[0], -1).sum(axis=1)
+    return int(e.min())
+
+
+# ---------------------------------------------------------------------------
+# EDP (Sec. 4.2, Algorithm 1)
+# ---------------------------------------------------------------------------
+
+# k in K = {+x, -x, +y, -y}: (axis step dx, dy) of sgn(k) along axis |k|.
+DIRECTIONS = {"+x": (1, 0), "-x": (-1, 0), "+y": (0, 1), "-y": (0, -1)}
+OPPOSITE = {"+x": "-x", "-x": "+x", "+y": "-y", "-y": "+y"}
+# The four scans of Sec. 4.2: (x order, y order, sums computed).
+SCANS = (
+    ("inc", "inc", ("+x", "+y")),   # P1
+    ("dec", "inc", ("-x", "+y")),   # P2
+    ("inc", "dec", ("+x", "-y")),   # P3
+    ("dec", "dec", ("-x", "-y")),   # P4
+)
+
+
+def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+        iterations: int = 1, search: str = "sfms", trace=None):
+    """Literal EDP, Algorithm 1 steps 3-5 (the DSI and the prior are the inputs).
+
+    For every scan P1..P4 and every vertex x in the scan's raster order, each sum
+    k' the scan computes is updated by eq. DP_2D_base with the data cost added:
+        S_k'(x) = C(x) + sum_{k != -k'} M(S_k(x_k) // 2) - M(S_-k'(x_-k') // 2),
+    where x_k = x - sgn(k) e_|k| and M(.) is 0 off the grid.  After ``iterations``
+    rounds of the four scans, S_Omega(x) = C(x) + sum_k M(S_k(x_k) // 2) (eq. DP_2D_1)
+    and the label is its smallest argmin (eq. DP_2D_2).
+
+    ``search`` selects M: "sfms" (definition) or "lrms" (Sec. 3.2 passes).
+    ``trace`` (optional) is called after every scan as trace(iteration, scan, sums).
+    Returns dict(labels, energy, marginal, sums, max_abs_sum).
+    """
+    c = np.asarray(cost, dtype=np.int64)
+    H, W, Q = c.shape
+    msearch = {"sfms": lambda h: min_search_sfms(h, qx, qy, lam, trunc, mode)[0],
+               "lrms": lambda h: min_search_lrms(h, qx, qy, lam, trunc, mode)}[search]
+    sums = {k: np.zeros((H, W, Q), np.int64) for k in DIRECTIONS}
+    max_abs = 0
+
+    def m_term(k, x, y):
+        dx, dy = DIRECTIONS[k]
+        px, py = x - dx, y - dy
+        if 0 <= px < W and 0 <= py < H:
+            return msearch(sums[k][py, px] // 2)
+        return np.zeros(Q, np.int64)
+
+    for it in range(iterations):
+        for scan, (xo, yo, computed) in enumerate(SCANS):
+            ys = range(H) if yo == "inc" else range(H - 1, -1, -1)
+            xs = range(W) if xo == "inc" else range(W - 1, -1, -1)
+            for y in ys:
+                for x in xs:
+                    m = {k: m_term(k, x, y) for k in DIRECTIONS}
+                    new = {}
+                    for kp in computed:
+                        acc = c[y, x].copy()
+                        for k in DIRECTIONS:
+                            if k != OPPOSITE[kp]:
+                                acc = acc + m[k]
+                        new[kp] = acc - m[OPPOSITE[kp]]
+                    for kp, val in new.items():
+                        sums[kp][y, x] = val
+                        max_abs = max(max_abs, int(np.abs(val).max()))
+            if trace is not None:
+                trace(it, scan, {k: v.copy() for k, v in sums.items()})
+    marg = c.copy()
+    for y in range(H):
+        for x in range(W):
+            for k in DIRECTIONS:
+                marg[y, x] += m_term(k, x, y)
+    labels = np.argmin(marg, axis=-1)
+    if max_abs > INT32_MAX:
+        raise OverflowError(f"EDP sum {max_abs} exceeds int32")
+    e = energy(c, labels, qx, qy, lam, trunc, mode, grid4=True)
+    return {"labels": labels, "energy": e, "marginal": marg, "sums": sums,
+            "max_abs_sum": max_abs}
+
+
+def wta(cost: np.ndarray) -> np.ndarray:
+    """Winner-take-all labels: per-pixel smallest argmin of C."""
+    return np.argmin(np.asarray(cost), axis=-1)
