@@ -1,0 +1,132 @@
+/*
+ * edp.h -- C ABI of the MI355X (gfx950) scanline-DP / EDP energy minimiser.
+ *
+ * Method: M. G. Mozerov, "Extended Dynamic Programming and Fast
+ * Multidimensional Search Algorithm for Energy Minimization in Stereo and
+ * Motion" (arXiv 1410.7922).
+ *
+ *   Energy (Sec. 2, eq. GE_objective_function with the truncated linear prior
+ *   of eq. Smooth_value_t, f(|a|) = |a|):
+ *       E(v) = sum_x C(x, v(x)) + sum over neighbour pairs (x, x') V(v(x') - v(x))
+ *       V(u) = lambda * (min(|ux|, T) + min(|uy|, T))   trunc_mode EDP_TRUNC_PER_DIM
+ *       V(u) = lambda * min(|ux| + |uy|, T)             trunc_mode EDP_TRUNC_JOINT
+ *   Minimum search (Sec. 2, eq. M_strf): M(h)(v) = min_v' h(v') + V(v - v'),
+ *   computed by the linear recursive minimum search of Sec. 3.2 (two passes
+ *   per label dimension plus the clip of eq. L_dec7), never by the O(Q^2) scan.
+ *
+ * Conventions shared by every entry point
+ *   - Cost volume: dense, row-major C[y][x][q], int16 or int32, caller-owned
+ *     device memory, aligned to the element size.  Labels are flat and 0-based:
+ *     q = vy * qx + vx (stereo: qy = 1).
+ *   - All d_* pointers are device pointers owned by the caller; the library
+ *     allocates nothing.  Scratch memory is the caller's workspace d_ws of at
+ *     least edp_workspace_size() bytes, 256-byte aligned; its contents are
+ *     undefined between calls and two calls in flight must not share it.
+ *   - stream is a hipStream_t (NULL = the default stream).  Calls only
+ *     enqueue work: outputs are valid after the stream is synchronised.
+ *   - Errors are returned, never thrown.  Argument errors are detected on the
+ *     host before anything is enqueued; nothing is written on error.
+ *   - Integer arithmetic only: results are bit-exact and deterministic.
+ *     Every argmin takes the smallest flat label.
+ */
+#ifndef EDP_H
+#define EDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EDP_OK = 0,
+    EDP_E_INVALID = -1,     /* bad argument: null pointer, size, dtype, mode, ... */
+    EDP_E_RANGE = -2,       /* the int32 range guard failed for these parameters */
+    EDP_E_WORKSPACE = -3,   /* workspace missing, misaligned or too small */
+    EDP_E_HIP = -4,         /* a HIP runtime call or kernel launch failed */
+    EDP_E_UNSUPPORTED = -5  /* valid problem outside what this build implements */
+} edp_status;
+
+typedef enum { EDP_I16 = 1, EDP_I32 = 2 } edp_dtype;
+typedef enum { EDP_TRUNC_PER_DIM = 0, EDP_TRUNC_JOINT = 1 } edp_trunc_mode;
+typedef enum { EDP_OP_DP = 0, EDP_OP_EDP = 1 } edp_op;
+
+/* One energy-minimisation instance (Sec. 2). */
+typedef struct {
+    int32_t width;       /* W = x_max >= 1 */
+    int32_t height;      /* H = y_max >= 1 */
+    int32_t qx;          /* labels along the first label dimension, >= 1 */
+    int32_t qy;          /* labels along the second label dimension, >= 1 (1 for stereo) */
+    int32_t dtype;       /* edp_dtype of the cost volume */
+    int32_t trunc_mode;  /* edp_trunc_mode; the two modes coincide when qy == 1 */
+    int32_t lambda;      /* prior weight, 0 <= lambda <= 65535 */
+    int32_t trunc;       /* truncation threshold T (the paper's g), 1 <= T <= 4096 */
+    int32_t iterations;  /* EDP iterations j >= 1 of Algorithm 1 (ignored by the DP) */
+    int32_t cost_bound;  /* promise |C| <= cost_bound; 0 = the dtype's range (int16 only) */
+} edp_problem;
+
+/* Optional tuning: which lane tile maps labels to lanes and how often a row
+ * band publishes progress to the next one.  NULL selects the built-in choice. */
+typedef struct {
+    int32_t tile;        /* tile id from edp_tiles(), or -1 for automatic */
+    int32_t chunk;       /* EDP columns per progress publication, 0 = automatic */
+} edp_tuning;
+
+/* Workspace bytes needed by op (edp_op) for prob under tuning (nullable). */
+edp_status edp_workspace_size(const edp_problem* prob, int32_t op, const edp_tuning* tuning,
+                              size_t* bytes);
+
+/*
+ * Independent scanline DP (Sec. 2 eq. One_d: vertical prior taken as zero).
+ * Every row y is a chain solved exactly by the recursion of eq. base,
+ * S(0, v) = C(0, v), S(x+1, v) = C(x+1, v) + M(S(x, .))(v) (zero boundary of
+ * Sec. 4.1 eq. DP_1D_2); its energy is min_v S(W-1, v) and its labels are read
+ * back from the stored optimal choice indexes (Sec. 4.1).  Among optimal
+ * labellings the reverse-lexicographically smallest one is returned.
+ *   d_cost        [H][W][Q] cost volume
+ *   d_labels      [H][W] int32 output labels
+ *   d_row_energy  [H] int64 output row energies (nullable)
+ *   d_energy      [1] int64 output: sum of the row energies (nullable)
+ */
+edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
+                           int32_t* d_labels, int64_t* d_row_energy, int64_t* d_energy,
+                           void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Extended DP (Sec. 4.2, Algorithm 1 steps 3-5) on the 4-connected grid:
+ * prob->iterations rounds of the scans P1..P4 of eq. DP_2D_base (with the data
+ * cost added and S/2 taken as floor division), then the marginal of eq. DP_2D_1
+ * and its smallest argmin (eq. DP_2D_2).
+ *   d_labels  [H][W] int32 output labels
+ *   d_energy  [1] int64 output: 4-connected energy of d_labels (nullable)
+ */
+edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
+                     int32_t* d_labels, int64_t* d_energy, void* d_ws, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * Energy of a labelling (Sec. 2 eq. GE_objective_function).
+ *   grid4      0: horizontal pairs only (the scanline energy), 1: 4-connected
+ *   d_labels   [H][W] int32 labels; labels outside [0, Q) contribute nothing
+ *   d_energy   [1] int64 output
+ *   d_invalid  [1] int64 output, count of labels outside [0, Q) (nullable)
+ */
+edp_status edp_energy(const edp_problem* prob, const void* d_cost, const int32_t* d_labels,
+                      int32_t grid4, int64_t* d_energy, int64_t* d_invalid, void* stream);
+
+/* Lane tiles usable for a (qx, qy) label space.  Writes up to max ids into ids
+ * (nullable) and returns how many exist; a negative value is an edp_status. */
+int32_t edp_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max);
+
+/* Shape of a tile: lanes px * py per cell, labels kx * ky per lane. */
+edp_status edp_tile_info(int32_t tile, int32_t* px, int32_t* kx, int32_t* py, int32_t* ky);
+
+/* Static text for a status code. */
+const char* edp_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EDP_H */

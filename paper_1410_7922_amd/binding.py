@@ -1,0 +1,196 @@
+"""Python binding of ``libedp.so`` (include/edp.h): argument marshalling only.
+
+Torch provides device memory and the current HIP stream; every step of the
+solvers runs in the library's HIP kernels.  There is no CPU fallback: if the
+library is missing or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libedp.so")
+
+EDP_OK = 0
+EDP_I16 = 1
+EDP_I32 = 2
+TRUNC_PER_DIM = 0
+TRUNC_JOINT = 1
+OP_DP = 0
+OP_EDP = 1
+
+EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
+           "edp_tile_info", "edp_status_string")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "width", "height", "qx", "qy", "dtype", "trunc_mode", "lam", "trunc", "iterations", "cost_bound")]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+
+class EdpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    pprob, ptun = ctypes.POINTER(Problem), ctypes.POINTER(Tuning)
+    L.edp_workspace_size.argtypes = [pprob, ctypes.c_int32, ptun, ctypes.POINTER(sz)]
+    L.edp_dp_scanline.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, sz, vp]
+    L.edp_solve.argtypes = [pprob, ptun, vp, vp, vp, vp, sz, vp]
+    L.edp_energy.argtypes = [pprob, vp, vp, ctypes.c_int32, vp, vp, vp]
+    L.edp_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    L.edp_tile_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
+    L.edp_status_string.argtypes = [ctypes.c_int32]
+    L.edp_status_string.restype = ctypes.c_char_p
+    for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
+                 "edp_tile_info"):
+        getattr(L, name).restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return load().edp_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != EDP_OK:
+        raise EdpError(status, where)
+
+
+def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mode: int = TRUNC_PER_DIM,
+                 iterations: int = 1, cost_bound: int = 0) -> Problem:
+    if cost.dim() != 3:
+        raise ValueError("cost must be [H][W][Q]")
+    if cost.dtype not in (torch.int16, torch.int32):
+        raise ValueError("cost must be int16 or int32")
+    H, W, Q = cost.shape
+    if Q != qx * qy:
+        raise ValueError(f"cost has {Q} labels, qx*qy = {qx * qy}")
+    return Problem(W, H, qx, qy, EDP_I16 if cost.dtype == torch.int16 else EDP_I32, mode, lam, trunc,
+                   iterations, cost_bound)
+
+
+def _tuning(tile: int, chunk: int):
+    return ctypes.byref(Tuning(tile, chunk)) if (tile >= 0 or chunk > 0) else None
+
+
+def _device_tensor(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream(dev) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def workspace_size(prob: Problem, op: int, tile: int = -1, chunk: int = 0) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().edp_workspace_size(ctypes.byref(prob), op, _tuning(tile, chunk), ctypes.byref(n)),
+           "edp_workspace_size")
+    return int(n.value)
+
+
+def tiles(qx: int, qy: int = 1) -> list:
+    L = load()
+    n = L.edp_tiles(qx, qy, None, 0)
+    if n < 0:
+        raise EdpError(n, "edp_tiles")
+    ids = (ctypes.c_int32 * max(n, 1))()
+    L.edp_tiles(qx, qy, ids, n)
+    return list(ids[:n])
+
+
+def tile_info(tile: int) -> tuple:
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(load().edp_tile_info(tile, *[ctypes.byref(x) for x in v]), "edp_tile_info")
+    return tuple(x.value for x in v)
+
+
+class Workspace:
+    """Reusable device workspace (grows on demand, never shrinks)."""
+
+    def __init__(self, device=None):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = Workspace()
+
+
+def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2,
+                mode: int = TRUNC_PER_DIM, cost_bound: int = 0, tile: int = -1, ws: Workspace | None = None):
+    """Independent scanline DP (edp_dp_scanline).  Returns (labels [H][W] int32,
+    row energies [H] int64, total energy [1] int64) as device tensors."""
+    _device_tensor(cost, "cost")
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound)
+    nbytes = workspace_size(prob, OP_DP, tile)
+    w = (ws or _default_ws).get(nbytes, cost.device)
+    H, W, _ = cost.shape
+    labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    row_e = torch.empty(H, dtype=torch.int64, device=cost.device)
+    tot = torch.empty(1, dtype=torch.int64, device=cost.device)
+    _check(load().edp_dp_scanline(ctypes.byref(prob), _tuning(tile, 0), cost.data_ptr(), labels.data_ptr(),
+                                  row_e.data_ptr(), tot.data_ptr(), w.data_ptr(), w.numel(),
+                                  _stream(cost.device)), "edp_dp_scanline")
+    return labels, row_e, tot
+
+
+def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,
+          iterations: int = 1, cost_bound: int = 0, tile: int = -1, chunk: int = 0,
+          ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None):
+    """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors."""
+    _device_tensor(cost, "cost")
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound)
+    nbytes = workspace_size(prob, OP_EDP, tile, chunk)
+    w = (ws or _default_ws).get(nbytes, cost.device)
+    H, W, _ = cost.shape
+    if labels is None:
+        labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    if energy is None:
+        energy = torch.empty(1, dtype=torch.int64, device=cost.device)
+    _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk), cost.data_ptr(), labels.data_ptr(),
+                            energy.data_ptr(), w.data_ptr(), w.numel(), _stream(cost.device)), "edp_solve")
+    return labels, energy
+
+
+def energy(cost: torch.Tensor, labels: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2,
+           mode: int = TRUNC_PER_DIM, grid4: bool = True, cost_bound: int = 0):
+    """Energy of a labelling (edp_energy).  Returns (energy [1] int64, invalid-label count [1] int64)."""
+    _device_tensor(cost, "cost")
+    _device_tensor(labels, "labels")
+    if labels.dtype != torch.int32 or tuple(labels.shape) != tuple(cost.shape[:2]):
+        raise ValueError("labels must be int32 [H][W]")
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound)
+    e = torch.empty(1, dtype=torch.int64, device=cost.device)
+    bad = torch.empty(1, dtype=torch.int64, device=cost.device)
+    _check(load().edp_energy(ctypes.byref(prob), cost.data_ptr(), labels.data_ptr(), int(bool(grid4)),
+                             e.data_ptr(), bad.data_ptr(), _stream(cost.device)), "edp_energy")
+    return e, bad

@@ -1,0 +1,113 @@
+// Energy of a labelling (Mozerov, arXiv 1410.7922, Sec. 2 eq.
+// GE_objective_function with the truncated linear prior) and small helpers.
+#include "edp_device.hpp"
+#include "edp_internal.hpp"
+
+namespace edp {
+
+__device__ __forceinline__ int64_t prior_pair(int32_t a, int32_t b, int32_t qx, int32_t lam,
+                                              int32_t trunc, bool joint) {
+    int32_t dx = a % qx - b % qx, dy = a / qx - b / qx;
+    dx = dx < 0 ? -dx : dx;
+    dy = dy < 0 ? -dy : dy;
+    if (joint) return (int64_t)lam * imin(dx + dy, trunc);
+    return (int64_t)lam * (imin(dx, trunc) + imin(dy, trunc));
+}
+
+template <class CT>
+__global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
+    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy;
+    const CT* __restrict__ cost = (const CT*)a.cost;
+    const bool joint = a.joint != 0;
+    int64_t acc = 0;
+    unsigned long long bad = 0;
+    const int64_t n = (int64_t)W * H;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t y = (int32_t)(idx / W), x = (int32_t)(idx % W);
+        const int32_t lab = a.labels[idx];
+        if (lab < 0 || lab >= Q) { ++bad; continue; }
+        acc += (int64_t)cost[idx * Q + lab];
+        if (x + 1 < W) {
+            const int32_t r = a.labels[idx + 1];
+            if (r >= 0 && r < Q) acc += prior_pair(lab, r, a.qx, a.lam, a.trunc, joint);
+        }
+        if (a.grid4 && y + 1 < H) {
+            const int32_t d = a.labels[idx + W];
+            if (d >= 0 && d < Q) acc += prior_pair(lab, d, a.qx, a.lam, a.trunc, joint);
+        }
+    }
+    __shared__ int64_t sacc[256];
+    __shared__ unsigned long long sbad[256];
+    sacc[threadIdx.x] = acc;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sacc[threadIdx.x] += sacc[threadIdx.x + st];
+            sbad[threadIdx.x] += sbad[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(a.energy, (unsigned long long)sacc[0]);
+        if (a.invalid) atomicAdd(a.invalid, sbad[0]);
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void sum_rows_kernel(const int64_t* rows, int32_t n, int64_t* out) {
+    __shared__ int64_t s[256];
+    int64_t acc = 0;
+    for (int32_t i = threadIdx.x; i < n; i += 256) acc += rows[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
+}
+
+__global__ void copy_i64_kernel(const int64_t* src, int64_t* dst, int32_t n) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s) {
+    const int64_t n = (int64_t)a.W * a.H;
+    int grid = (int)((n + 255) / 256);
+    if (grid > 2048) grid = 2048;
+    if (grid < 1) grid = 1;
+    if (dtype == 1)
+        hipLaunchKernelGGL(energy_kernel<int16_t>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(energy_kernel<int32_t>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t grid = (n + 255) / 256;
+    if (grid > 1024) grid = 1024;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)grid), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_rows(const int64_t* rows, int32_t n, int64_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(256), 0, s, rows, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStream_t s) {
+    int grid = (n + 255) / 256;
+    if (grid > 256) grid = 256;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(copy_i64_kernel, dim3(grid), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace edp

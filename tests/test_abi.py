@@ -1,0 +1,98 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared entry point, and
+rejects bad arguments on the host before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1410_7922_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "edp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:edp_status|int32_t|const char\*)\s+(edp_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    names = declared_functions()
+    assert len(names) >= 7
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(B.EXPORTS) <= set(names)
+
+
+def test_status_strings():
+    assert B.status_string(0) == "ok"
+    for s in (-1, -2, -3, -4, -5):
+        assert B.status_string(s) != "unknown status"
+    assert B.status_string(42) == "unknown status"
+
+
+def _prob(**kw):
+    d = dict(width=384, height=288, qx=32, qy=1, dtype=1, trunc_mode=0, lam=20, trunc=2, iterations=1,
+             cost_bound=50)
+    d.update(kw)
+    return B.Problem(*[d[f] for f, _ in B.Problem._fields_])
+
+
+def _ws(prob, op, tile=-1):
+    n = ctypes.c_size_t(0)
+    tu = ctypes.byref(B.Tuning(tile, 0)) if tile >= 0 else None
+    st = B.load().edp_workspace_size(ctypes.byref(prob), op, tu, ctypes.byref(n))
+    return st, n.value
+
+
+@pytest.mark.parametrize("field,value", [("width", 0), ("height", -1), ("qx", 0), ("qy", 0), ("dtype", 3),
+                                         ("trunc_mode", 2), ("lam", -1), ("lam", 70000), ("trunc", 0),
+                                         ("iterations", 0), ("cost_bound", -5), ("qx", 4097)])
+def test_invalid_problems_rejected(field, value):
+    st, _ = _ws(_prob(**{field: value}), B.OP_EDP)
+    assert st == -1
+
+
+def test_int32_costs_need_a_bound_and_range_guard():
+    assert _ws(_prob(dtype=2, cost_bound=0), B.OP_EDP)[0] == -1
+    assert _ws(_prob(dtype=2, cost_bound=2500), B.OP_EDP)[0] == 0
+    # a cost bound too large for the int32 EDP sums on this grid
+    assert _ws(_prob(dtype=2, cost_bound=10**6), B.OP_EDP)[0] == -2
+    # the DP packs the label index under the value: a huge lambda trips its guard
+    assert _ws(_prob(lam=60000, trunc=4000, qx=64), B.OP_DP)[0] == -2
+
+
+def test_tiles_and_workspace_sizes():
+    assert B.tiles(32) == [1, 2, 3, 4, 5, 6, 7, 8, 12, 15]
+    assert 10 in B.tiles(15, 15) and 0 not in B.tiles(15, 15)
+    assert B.tiles(65, 65) == []
+    st, n = _ws(_prob(qx=65, qy=65), B.OP_EDP)
+    assert st == -1                                  # more than 4096 labels
+    st, n = _ws(_prob(qx=200, qy=1), B.OP_EDP)
+    assert st == 0
+    st, n = _ws(_prob(qx=40, qy=40), B.OP_EDP)
+    assert st == -5                                  # 1600 labels: no tile compiled for 40 x 40
+    for tile in B.tiles(32):
+        st, n = _ws(_prob(), B.OP_EDP, tile)
+        px, kx, py, ky = B.tile_info(tile)
+        qt = px * kx * py * ky
+        assert st == 0 and n >= 4 * 384 * 288 * qt * 4
+    assert _ws(_prob(), B.OP_EDP, 0)[0] == -1        # tile 0 holds 16 labels only
+
+
+def test_workspace_and_pointer_errors_are_host_side():
+    lib = B.load()
+    p = _prob()
+    fake = ctypes.c_void_p(1 << 40)
+    st, need = _ws(p, B.OP_EDP)
+    assert st == 0
+    # too small, misaligned, null: rejected before any launch
+    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, fake, need - 1, None) == -3
+    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, ctypes.c_void_p((1 << 40) + 8), need, None) == -3
+    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, None, need, None) == -3
+    assert lib.edp_solve(ctypes.byref(p), None, None, fake, fake, fake, need, None) == -1
+    assert lib.edp_dp_scanline(ctypes.byref(p), None, fake, None, None, None, fake, 1 << 30, None) == -1
+    assert lib.edp_energy(ctypes.byref(p), fake, fake, 2, fake, None, None) == -1
+    assert lib.edp_solve(None, None, fake, fake, fake, fake, need, None) == -1

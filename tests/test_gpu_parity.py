@@ -1,0 +1,177 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact (integer labels and energies).
+
+Every call goes through the C ABI (paper_1410_7922_amd.binding -> libedp.so).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1410_7922_amd as edp
+import synth
+from oracle import cref
+from oracle import edp_ref as R
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def gpu_dp(p, tile=-1, cost_bound=0):
+    lab, row, tot = edp.dp_scanline(to_dev(p.cost), p.qx, p.qy, p.lam, p.trunc, p.mode,
+                                    cost_bound=cost_bound or int(np.abs(p.cost).max()) + 1, tile=tile)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy(), row.cpu().numpy(), int(tot.item())
+
+
+def gpu_edp(p, iterations=1, tile=-1, chunk=0, cost_bound=0):
+    lab, e = edp.solve(to_dev(p.cost), p.qx, p.qy, p.lam, p.trunc, p.mode, iterations=iterations,
+                       cost_bound=cost_bound or int(np.abs(p.cost).max()) + 1, tile=tile, chunk=chunk)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy(), int(e.item())
+
+
+def test_library_is_the_native_one():
+    lib = edp.load()
+    assert lib._name.endswith("libedp.so")
+    assert torch.cuda.is_available()
+
+
+# ---------------------------------------------------------------------------
+# scanline DP
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", edp.tiles(16))
+def test_dp_chain_workload_every_tile(tile):
+    p = synth.workload("chain64x48")
+    note(f"dp chain64x48 tile {tile}")
+    lab, row, tot = gpu_dp(p, tile)
+    rl, rr, rt = cref.dp_scanline(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode)
+    assert np.array_equal(lab, rl)
+    assert np.array_equal(row, rr)
+    assert tot == rt
+
+
+DP_CASES = [
+    # W, H, qx, qy, lam, T, mode, lo, hi, dtype
+    (1, 5, 7, 1, 5, 2, 0, -9, 9, np.int32),
+    (2, 1, 3, 1, 3, 1, 0, 0, 9, np.int32),
+    (37, 13, 16, 1, 9, 3, 0, -60, 255, np.int32),
+    (50, 9, 32, 1, 11, 4, 0, 0, 50, np.int16),
+    (23, 70, 64, 1, 4, 6, 0, 0, 120, np.int16),
+    (19, 11, 5, 1, 0, 1, 0, 0, 3, np.int32),          # lambda = 0, ties
+    (21, 7, 4, 4, 6, 2, 0, -20, 80, np.int32),
+    (21, 7, 4, 4, 6, 3, 1, -20, 80, np.int32),
+    (17, 6, 15, 15, 15, 3, 0, 0, 2500, np.int32),
+    (9, 5, 31, 31, 15, 3, 0, 0, 2500, np.int32),
+    (12, 6, 7, 5, 5, 2, 1, 0, 60, np.int16),
+    (30, 4, 200, 1, 3, 5, 0, 0, 90, np.int16),
+]
+
+
+@pytest.mark.parametrize("case", DP_CASES, ids=lambda c: f"{c[0]}x{c[1]}q{c[2]}x{c[3]}m{c[6]}")
+def test_dp_random_all_tiles(case):
+    W, H, qx, qy, lam, T, mode, lo, hi, dt = case
+    p = synth.random_problem(W * 31 + H, W, H, qx, qy, lam, T, mode, lo, hi, dt)
+    rl, rr, rt = cref.dp_scanline(p.cost, qx, qy, lam, T, mode)
+    for tile in edp.tiles(qx, qy):
+        note(f"dp {p.name} tile {tile}")
+        lab, row, tot = gpu_dp(p, tile)
+        assert np.array_equal(lab, rl), tile
+        assert np.array_equal(row, rr), tile
+        assert tot == rt, tile
+
+
+# ---------------------------------------------------------------------------
+# EDP
+# ---------------------------------------------------------------------------
+
+EDP_CASES = [
+    # W, H, qx, qy, lam, T, mode, lo, hi, dtype, iterations
+    (1, 1, 5, 1, 3, 1, 0, -9, 9, np.int32, 1),
+    (1, 9, 8, 1, 4, 2, 0, 0, 30, np.int32, 2),
+    (11, 1, 8, 1, 4, 2, 0, 0, 30, np.int32, 2),
+    (13, 10, 16, 1, 7, 2, 0, -30, 60, np.int32, 1),
+    (29, 37, 32, 1, 20, 2, 0, 0, 50, np.int16, 1),
+    (29, 37, 32, 1, 20, 2, 0, 0, 50, np.int16, 3),
+    (17, 23, 50, 1, 9, 3, 0, 0, 80, np.int16, 1),
+    (9, 15, 5, 1, 0, 1, 0, 0, 3, np.int32, 1),            # lambda = 0: winner-take-all
+    (10, 9, 4, 3, 5, 2, 0, -10, 40, np.int32, 1),
+    (10, 9, 4, 3, 5, 2, 1, -10, 40, np.int32, 2),
+    (12, 14, 15, 15, 15, 3, 0, 0, 2500, np.int32, 1),
+    (7, 9, 31, 31, 15, 3, 0, 0, 2500, np.int32, 1),
+    (8, 11, 7, 7, 6, 2, 1, 0, 70, np.int16, 1),
+    (6, 70, 16, 1, 5, 2, 0, 0, 40, np.int32, 1),          # many bands, short rows
+]
+
+
+@pytest.mark.parametrize("case", EDP_CASES, ids=lambda c: f"{c[0]}x{c[1]}q{c[2]}x{c[3]}m{c[6]}j{c[10]}")
+def test_edp_random_all_tiles(case):
+    W, H, qx, qy, lam, T, mode, lo, hi, dt, j = case
+    p = synth.random_problem(W * 17 + H + j, W, H, qx, qy, lam, T, mode, lo, hi, dt)
+    ref = cref.edp(p.cost, qx, qy, lam, T, mode, j, "lrms")
+    for tile in edp.tiles(qx, qy):
+        for chunk in (1, 4):
+            note(f"edp {p.name} j{j} tile {tile} chunk {chunk}")
+            lab, e = gpu_edp(p, j, tile, chunk)
+            assert np.array_equal(lab, ref["labels"]), (tile, chunk)
+            assert e == ref["energy"], (tile, chunk)
+
+
+def test_edp_worked_example():
+    cost = np.array([[[0, 5], [7, 0]], [[3, 1], [6, 2]]], np.int32)
+    p = synth.Problem(cost, 2, 1, 1, 1, 0)
+    note("edp worked 2x2")
+    lab, e = gpu_edp(p, 1)
+    assert lab.tolist() == [[0, 1], [1, 1]] and e == 5
+
+
+def test_edp_stereo_workload_full_size():
+    p = synth.workload("stereo384x288")
+    ref = cref.edp(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode, 1, "lrms")
+    for tile in (-1, 3, 4):
+        note(f"edp stereo384x288 tile {tile}")
+        lab, e = gpu_edp(p, 1, tile, cost_bound=50)
+        assert np.array_equal(lab, ref["labels"])
+        assert e == ref["energy"]
+
+
+def test_edp_motion_workload_full_size():
+    p = synth.workload("motion320x240")
+    ref = cref.edp(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode, 1, "lrms")
+    note("edp motion320x240")
+    lab, e = gpu_edp(p, 1, cost_bound=2500)
+    assert np.array_equal(lab, ref["labels"])
+    assert e == ref["energy"]
+
+
+def test_edp_deterministic_repeats():
+    p = synth.stereo_problem(seed=5, W=96, H=80, Q=24)
+    note("edp determinism")
+    runs = [gpu_edp(p, 2, cost_bound=50) for _ in range(3)]
+    for lab, e in runs[1:]:
+        assert np.array_equal(lab, runs[0][0]) and e == runs[0][1]
+
+
+def test_energy_kernel_matches_oracle():
+    rng = np.random.default_rng(3)
+    for qx, qy, mode in ((16, 1, 0), (5, 4, 0), (5, 4, 1)):
+        p = synth.random_problem(9, 33, 21, qx, qy, 7, 2, mode, -50, 50)
+        labels = rng.integers(0, qx * qy, size=(21, 33)).astype(np.int32)
+        note(f"energy {qx}x{qy} mode {mode}")
+        for grid4 in (False, True):
+            e, bad = edp.energy(to_dev(p.cost), to_dev(labels), qx, qy, 7, 2, mode, grid4, cost_bound=51)
+            torch.cuda.synchronize()
+            assert int(e.item()) == R.energy(p.cost, labels, qx, qy, 7, 2, mode, grid4)
+            assert int(bad.item()) == 0
+        labels[0, 0] = -1
+        labels[5, 7] = qx * qy
+        e, bad = edp.energy(to_dev(p.cost), to_dev(labels), qx, qy, 7, 2, mode, True, cost_bound=51)
+        torch.cuda.synchronize()
+        assert int(bad.item()) == 2
