@@ -67,10 +67,17 @@ typedef struct {
 } edp_problem;
 
 /* Optional tuning: which lane tile maps labels to lanes and how often a row
- * band publishes progress to the next one.  NULL selects the built-in choice. */
+ * band publishes progress to the next one.  NULL selects the built-in choice.
+ * events (nullable): caller-created hipEvent_t handles recorded on the call's
+ * stream so the caller can time kernels: edp_solve records events[2p] before
+ * and events[2p+1] after the p-th scan launch (p < n_events / 2);
+ * edp_dp_scanline records events[0], [1] around the forward sweep and
+ * events[2], [3] around the backtracking.  Handles past n_events are unused. */
 typedef struct {
     int32_t tile;        /* tile id from edp_tiles(), or -1 for automatic */
     int32_t chunk;       /* EDP columns per progress publication, 0 = automatic */
+    void* const* events; /* nullable, see above */
+    int32_t n_events;    /* number of handles in events */
 } edp_tuning;
 
 /* Workspace bytes needed by op (edp_op) for prob under tuning (nullable). */

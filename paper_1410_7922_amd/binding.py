@@ -32,7 +32,8 @@ class Problem(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+    _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("events", ctypes.POINTER(ctypes.c_void_p)), ("n_events", ctypes.c_int32)]
 
 
 class EdpError(RuntimeError):
@@ -91,8 +92,14 @@ def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mod
                    iterations, cost_bound)
 
 
-def _tuning(tile: int, chunk: int):
-    return ctypes.byref(Tuning(tile, chunk)) if (tile >= 0 or chunk > 0) else None
+def _tuning(tile: int, chunk: int, events=None):
+    if tile < 0 and chunk <= 0 and events is None:
+        return None
+    t = Tuning(tile, chunk, None, 0)
+    if events is not None:
+        t.events = ctypes.cast(events, ctypes.POINTER(ctypes.c_void_p))
+        t.n_events = len(events)
+    return ctypes.byref(t)
 
 
 def _device_tensor(t: torch.Tensor, name: str):
@@ -146,7 +153,8 @@ _default_ws = Workspace()
 
 
 def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2,
-                mode: int = TRUNC_PER_DIM, cost_bound: int = 0, tile: int = -1, ws: Workspace | None = None):
+                mode: int = TRUNC_PER_DIM, cost_bound: int = 0, tile: int = -1, ws: Workspace | None = None,
+                events=None):
     """Independent scanline DP (edp_dp_scanline).  Returns (labels [H][W] int32,
     row energies [H] int64, total energy [1] int64) as device tensors."""
     _device_tensor(cost, "cost")
@@ -157,7 +165,7 @@ def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: 
     labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
     row_e = torch.empty(H, dtype=torch.int64, device=cost.device)
     tot = torch.empty(1, dtype=torch.int64, device=cost.device)
-    _check(load().edp_dp_scanline(ctypes.byref(prob), _tuning(tile, 0), cost.data_ptr(), labels.data_ptr(),
+    _check(load().edp_dp_scanline(ctypes.byref(prob), _tuning(tile, 0, events), cost.data_ptr(), labels.data_ptr(),
                                   row_e.data_ptr(), tot.data_ptr(), w.data_ptr(), w.numel(),
                                   _stream(cost.device)), "edp_dp_scanline")
     return labels, row_e, tot
@@ -165,8 +173,11 @@ def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: 
 
 def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,
           iterations: int = 1, cost_bound: int = 0, tile: int = -1, chunk: int = 0,
-          ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None):
-    """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors."""
+          ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None,
+          events=None):
+    """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors.
+
+    ``events``: optional ctypes array of hipEvent_t handles recorded around the scan launches."""
     _device_tensor(cost, "cost")
     prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound)
     nbytes = workspace_size(prob, OP_EDP, tile, chunk)
@@ -176,7 +187,7 @@ def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 
         labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
     if energy is None:
         energy = torch.empty(1, dtype=torch.int64, device=cost.device)
-    _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk), cost.data_ptr(), labels.data_ptr(),
+    _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk, events), cost.data_ptr(), labels.data_ptr(),
                             energy.data_ptr(), w.data_ptr(), w.numel(), _stream(cost.device)), "edp_solve")
     return labels, energy
 

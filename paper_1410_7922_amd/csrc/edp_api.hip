@@ -197,6 +197,7 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     edp_status st = check_problem(prob, EDP_OP_DP);
     if (st != EDP_OK) return st;
     if (!d_cost || !d_labels) return EDP_E_INVALID;
+    if (tuning && (tuning->chunk < 0 || tuning->n_events < 0)) return EDP_E_INVALID;
     int tile = 0;
     st = pick_tile(prob, tuning, &tile);
     if (st != EDP_OK) return st;
@@ -220,8 +221,14 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     a.ibits = ibits_of(prob->qx * prob->qy);
     const int rows_per_block = (64 / group_of(tile)) * 4;
     const int grid = (prob->height + rows_per_block - 1) / rows_per_block;
+    // optional caller events: [0],[1] around the forward sweep, [2],[3] around the backtracking
+    auto mark = [&](int k) -> bool {
+        return !(tuning && tuning->events && k < tuning->n_events) ||
+               hipEventRecord((hipEvent_t)tuning->events[k], s) == hipSuccess;
+    };
+    if (!mark(0)) return EDP_E_HIP;
     hipError_t err = launch_dp_forward(tile, prob->dtype, a, grid, s);
-    if (err != hipSuccess) return EDP_E_HIP;
+    if (err != hipSuccess || !mark(1)) return EDP_E_HIP;
 
     BtArgs b{};
     b.ptr = a.ptr;
@@ -234,8 +241,9 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     const int pbytes = qt_of(tile) <= 256 ? 1 : 2;
     b.chunk = 32768 / (qt_of(tile) * pbytes);
     if (b.chunk < 1) b.chunk = 1;
+    if (!mark(2)) return EDP_E_HIP;
     err = launch_dp_backtrack(tile, b, s);
-    if (err != hipSuccess) return EDP_E_HIP;
+    if (err != hipSuccess || !mark(3)) return EDP_E_HIP;
     if (d_row_energy) {
         err = launch_copy_i64(a.row_energy, d_row_energy, prob->height, s);
         if (err != hipSuccess) return EDP_E_HIP;
@@ -252,7 +260,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     edp_status st = check_problem(prob, EDP_OP_EDP);
     if (st != EDP_OK) return st;
     if (!d_cost || !d_labels) return EDP_E_INVALID;
-    if (tuning && tuning->chunk < 0) return EDP_E_INVALID;
+    if (tuning && (tuning->chunk < 0 || tuning->n_events < 0)) return EDP_E_INVALID;
     int tile = 0;
     st = pick_tile(prob, tuning, &tile);
     if (st != EDP_OK) return st;
@@ -299,8 +307,13 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
             a.old_b_zero = (it == 0 && (p == 0 || p == 1)) ? 1 : 0; // -y before P3
             a.ticket = tickets + pass_index;
             a.epoch = (uint32_t)pass_index * (uint32_t)(prob->width + 1);
+            const bool timed = tuning && tuning->events && 2 * pass_index + 1 < tuning->n_events;
+            if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index], s) != hipSuccess)
+                return EDP_E_HIP;
             err = launch_edp_pass(tile, prob->dtype, a, grid, s);
             if (err != hipSuccess) return EDP_E_HIP;
+            if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index + 1], s) != hipSuccess)
+                return EDP_E_HIP;
         }
     }
     AggArgs g{};
