@@ -66,8 +66,13 @@ typedef struct {
     int32_t cost_bound;  /* promise |C| <= cost_bound; 0 = the dtype's range (int16 only) */
 } edp_problem;
 
-/* Optional tuning: which lane tile maps labels to lanes and how often a row
- * band publishes progress to the next one.  NULL selects the built-in choice.
+/* Optional tuning of the launch (results never depend on it).  NULL, or a
+ * zero / negative field, selects the built-in choice:
+ *   tile   lane tile mapping labels to lanes (edp_tiles(); -1 automatic)
+ *   chunk  EDP columns between two progress publications of a workgroup
+ *   split  1: every lane runs both minimum searches of a scan step;
+ *          2: the two searches run on two halves of the vertex's lanes
+ *   waves  wavefronts per EDP workgroup (1..8), handing rows over in LDS
  * events (nullable): caller-created hipEvent_t handles recorded on the call's
  * stream so the caller can time kernels: edp_solve records events[2p] before
  * and events[2p+1] after the p-th scan launch (p < n_events / 2);
@@ -76,6 +81,8 @@ typedef struct {
 typedef struct {
     int32_t tile;        /* tile id from edp_tiles(), or -1 for automatic */
     int32_t chunk;       /* EDP columns per progress publication, 0 = automatic */
+    int32_t split;       /* 1 or 2, 0 = automatic */
+    int32_t waves;       /* 1..8, 0 = automatic */
     void* const* events; /* nullable, see above */
     int32_t n_events;    /* number of handles in events */
 } edp_tuning;

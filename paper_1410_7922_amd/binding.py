@@ -32,8 +32,9 @@ class Problem(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("events", ctypes.POINTER(ctypes.c_void_p)), ("n_events", ctypes.c_int32)]
+    _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("events", ctypes.POINTER(ctypes.c_void_p)),
+                ("n_events", ctypes.c_int32)]
 
 
 class EdpError(RuntimeError):
@@ -92,10 +93,10 @@ def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mod
                    iterations, cost_bound)
 
 
-def _tuning(tile: int, chunk: int, events=None):
-    if tile < 0 and chunk <= 0 and events is None:
+def _tuning(tile: int, chunk: int, events=None, split: int = 0, waves: int = 0):
+    if tile < 0 and chunk <= 0 and split <= 0 and waves <= 0 and events is None:
         return None
-    t = Tuning(tile, chunk, None, 0)
+    t = Tuning(tile, chunk, split, waves, None, 0)
     if events is not None:
         t.events = ctypes.cast(events, ctypes.POINTER(ctypes.c_void_p))
         t.n_events = len(events)
@@ -113,9 +114,10 @@ def _stream(dev) -> int:
     return torch.cuda.current_stream(dev).cuda_stream
 
 
-def workspace_size(prob: Problem, op: int, tile: int = -1, chunk: int = 0) -> int:
+def workspace_size(prob: Problem, op: int, tile: int = -1, chunk: int = 0, split: int = 0, waves: int = 0) -> int:
     n = ctypes.c_size_t(0)
-    _check(load().edp_workspace_size(ctypes.byref(prob), op, _tuning(tile, chunk), ctypes.byref(n)),
+    _check(load().edp_workspace_size(ctypes.byref(prob), op, _tuning(tile, chunk, None, split, waves),
+                                     ctypes.byref(n)),
            "edp_workspace_size")
     return int(n.value)
 
@@ -174,20 +176,20 @@ def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: 
 def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,
           iterations: int = 1, cost_bound: int = 0, tile: int = -1, chunk: int = 0,
           ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None,
-          events=None):
+          events=None, split: int = 0, waves: int = 0):
     """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors.
 
     ``events``: optional ctypes array of hipEvent_t handles recorded around the scan launches."""
     _device_tensor(cost, "cost")
     prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound)
-    nbytes = workspace_size(prob, OP_EDP, tile, chunk)
+    nbytes = workspace_size(prob, OP_EDP, tile, chunk, split, waves)
     w = (ws or _default_ws).get(nbytes, cost.device)
     H, W, _ = cost.shape
     if labels is None:
         labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
     if energy is None:
         energy = torch.empty(1, dtype=torch.int64, device=cost.device)
-    _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk, events), cost.data_ptr(), labels.data_ptr(),
+    _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk, events, split, waves), cost.data_ptr(), labels.data_ptr(),
                             energy.data_ptr(), w.data_ptr(), w.numel(), _stream(cost.device)), "edp_solve")
     return labels, energy
 

@@ -98,6 +98,36 @@ edp_status pick_tile(const edp_problem* p, const edp_tuning* tu, int* tile) {
     return EDP_OK;
 }
 
+struct Launch {
+    int tile, split, waves, chunk, ring;
+    int rpw;            // scanlines per wavefront
+    int nbands, nsuper;
+};
+
+// Launch shape of the EDP scans for a problem and an optional tuning.
+edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
+    edp_status st = pick_tile(p, tu, &L->tile);
+    if (st != EDP_OK) return st;
+    const int g = group_of(L->tile);
+    int split = (tu && tu->split > 0) ? tu->split : (2 * g <= 64 ? 2 : 1);
+    if (split != 1 && split != 2) return EDP_E_INVALID;
+    if (split * g > 64) return EDP_E_INVALID;
+    int waves = (tu && tu->waves > 0) ? tu->waves : 4;
+    if (waves > 8) return EDP_E_INVALID;
+    L->split = split;
+    L->waves = waves;
+    L->chunk = (tu && tu->chunk > 0) ? tu->chunk : 8;
+    const int qt = qt_of(L->tile);
+    int ring = waves > 1 ? (int)((48 * 1024) / ((size_t)(waves - 1) * qt * 4)) : 1;
+    if (ring > 16) ring = 16;
+    if (ring < 2) ring = 2;
+    L->ring = ring;
+    L->rpw = 64 / (split * g);
+    L->nbands = (p->height + L->rpw - 1) / L->rpw;
+    L->nsuper = (L->nbands + waves - 1) / waves;
+    return EDP_OK;
+}
+
 struct EdpLayout {
     size_t t[4];
     size_t ctrl;        // flags, tickets, error word (uint32)
@@ -105,17 +135,16 @@ struct EdpLayout {
     size_t total;
 };
 
-EdpLayout edp_layout(const edp_problem* p, int tile) {
+EdpLayout edp_layout(const edp_problem* p, const Launch& la) {
     EdpLayout L{};
     const size_t cells = (size_t)p->width * p->height;
-    const size_t tbytes = up(cells * (size_t)qt_of(tile) * 4);
+    const size_t tbytes = up(cells * (size_t)qt_of(la.tile) * 4);
     size_t off = 0;
     for (int k = 0; k < 4; ++k) {
         L.t[k] = off;
         off += tbytes;
     }
-    const int rpw = 64 / group_of(tile);
-    L.nflags = (size_t)((p->height + rpw - 1) / rpw);
+    L.nflags = (size_t)la.nsuper;
     L.ntickets = (size_t)4 * p->iterations;
     L.nctrl = L.nflags + L.ntickets + 1;
     L.ctrl = off;
@@ -184,10 +213,17 @@ edp_status edp_workspace_size(const edp_problem* prob, int32_t op, const edp_tun
     if (!bytes || (op != EDP_OP_DP && op != EDP_OP_EDP)) return EDP_E_INVALID;
     edp_status st = check_problem(prob, op);
     if (st != EDP_OK) return st;
-    int tile = 0;
-    st = pick_tile(prob, tuning, &tile);
+    if (op == EDP_OP_DP) {
+        int tile = 0;
+        st = pick_tile(prob, tuning, &tile);
+        if (st != EDP_OK) return st;
+        *bytes = dp_layout(prob, tile).total;
+        return EDP_OK;
+    }
+    Launch la{};
+    st = pick_launch(prob, tuning, &la);
     if (st != EDP_OK) return st;
-    *bytes = op == EDP_OP_DP ? dp_layout(prob, tile).total : edp_layout(prob, tile).total;
+    *bytes = edp_layout(prob, la).total;
     return EDP_OK;
 }
 
@@ -261,10 +297,11 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     if (st != EDP_OK) return st;
     if (!d_cost || !d_labels) return EDP_E_INVALID;
     if (tuning && (tuning->chunk < 0 || tuning->n_events < 0)) return EDP_E_INVALID;
-    int tile = 0;
-    st = pick_tile(prob, tuning, &tile);
+    Launch la{};
+    st = pick_launch(prob, tuning, &la);
     if (st != EDP_OK) return st;
-    const EdpLayout L = edp_layout(prob, tile);
+    const int tile = la.tile;
+    const EdpLayout L = edp_layout(prob, la);
     if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < L.total) return EDP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)d_ws;
@@ -288,10 +325,12 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     a.lam = prob->lambda;
     a.clipd = prob->lambda * prob->trunc;
     a.joint = prob->trunc_mode == EDP_TRUNC_JOINT;
-    a.chunk = (tuning && tuning->chunk > 0) ? tuning->chunk : 8;
-    a.nbands = (int32_t)L.nflags;
-    const int cap = pass_capacity(tile, prob->dtype);
-    const int grid = a.nbands < cap ? a.nbands : cap;
+    a.chunk = la.chunk;
+    a.nbands = la.nbands;
+    a.nsuper = la.nsuper;
+    a.ring = la.ring;
+    const int cap = pass_capacity(tile, prob->dtype, la.split, la.waves, pass_lds_bytes(qt_of(tile), la.waves, la.ring));
+    const int grid = a.nsuper < cap ? a.nsuper : cap;
     // scans P1..P4: (sx, sy) and the arrays they write (0 +x, 1 -x, 2 +y, 3 -y)
     const int sx[4] = {1, -1, 1, -1}, sy[4] = {1, 1, -1, -1};
     const int ka[4] = {0, 1, 0, 1}, kb[4] = {2, 2, 3, 3};
@@ -307,10 +346,11 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
             a.old_b_zero = (it == 0 && (p == 0 || p == 1)) ? 1 : 0; // -y before P3
             a.ticket = tickets + pass_index;
             a.epoch = (uint32_t)pass_index * (uint32_t)(prob->width + 1);
+            a.b_live = (p == 1 || p == 3) ? 1 : 0;   // T+y of P1 and T-y of P3 die inside their scan
             const bool timed = tuning && tuning->events && 2 * pass_index + 1 < tuning->n_events;
             if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index], s) != hipSuccess)
                 return EDP_E_HIP;
-            err = launch_edp_pass(tile, prob->dtype, a, grid, s);
+            err = launch_edp_pass(tile, prob->dtype, la.split, a, grid, la.waves, s);
             if (err != hipSuccess) return EDP_E_HIP;
             if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index + 1], s) != hipSuccess)
                 return EDP_E_HIP;

@@ -5,7 +5,12 @@
 // lanes of a 64-wide wavefront.  Lane (px, py) of a group holds the KY x KX
 // block of labels vy = py*KY + ky, vx = px*KX + kx, so a line of the label
 // space along x lies in consecutive lanes of one lane row and a line along y
-// in lanes PX apart.  64 / G groups share a wavefront.
+// in lanes PX apart.
+//
+// Cross-lane exchange uses DPP inside 16-lane rows (row_shr / row_shl /
+// row_ror / mirrors / quad permutes, a few cycles each) and the gfx950
+// v_permlane16_swap / v_permlane32_swap instructions to move data between
+// rows; ds_bpermute is used by no hot loop.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,31 +28,151 @@ struct Tile {
     static constexpr int G = PX * PY;          // lanes per vertex
     static constexpr int E = KX * KY;          // labels per lane
     static constexpr int QT = G * E;           // padded labels per vertex
-    static constexpr int RPW = 64 / G;         // vertices (scanlines) per wavefront
     static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group must divide the wavefront");
     static_assert((PX & (PX - 1)) == 0 && (PY & (PY - 1)) == 0, "power-of-two lane grid");
+    static_assert(PY == 1 || PX * PY >= 16, "y lines must fill whole 16-lane rows");
 };
 
 __device__ __forceinline__ int32_t lane_id() { return (int32_t)__lane_id(); }
+__device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int32_t imin3(int32_t a, int32_t b, int32_t c) { return imin(imin(a, b), c); }
 
-// Value of v in lane src (all 64 lanes must execute the call).
-__device__ __forceinline__ int32_t from_lane(int32_t v, int32_t src) {
-    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+// ---- DPP (GFX9 encodings) --------------------------------------------------
+constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_MIRROR = 0x140;    // lane i <- 15 - i (within the row)
+constexpr int DPP_HALF_MIRROR = 0x141;   // lane i <- 7 - i (within each half row)
+constexpr int dpp_row_shr(int n) { return 0x110 + n; }   // lane i <- i - n, row lanes < n keep old
+constexpr int dpp_row_shl(int n) { return 0x100 + n; }   // lane i <- i + n, row lanes >= 16-n keep old
+constexpr int dpp_row_ror(int n) { return 0x120 + n; }   // lane i <- (i - n) mod 16
+
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp(int32_t old, int32_t v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+// rows r <- r - 1 (r = 1, 2, 3; row 0 gets row 0)
+__device__ __forceinline__ int32_t rows_up(int32_t v, int32_t lane) {
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);   // [r0 r0 r2 r2], [r1 r1 r3 r3]
+    const auto b = __builtin_amdgcn_permlane32_swap(a[1], a[1], false, false);  // [r1 r1 r1 r1]
+    return (lane >> 4) == 2 ? (int32_t)b[0] : (int32_t)a[0];
+}
+// rows r <- r + 1 (r = 0, 1, 2; row 3 gets row 3)
+__device__ __forceinline__ int32_t rows_down(int32_t v, int32_t lane) {
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(a[0], a[0], false, false);  // [r2 r2 r2 r2]
+    return (lane >> 4) == 1 ? (int32_t)b[1] : (int32_t)a[1];
+}
 
-// One dimension of the linear RMS on the lane tile: for every line along the
-// dimension, the L1 distance transform L(v) = min_v' h(v') + lam |v - v'|
-// as the forward pass of eq. L_dec3 and the backward pass of eq. L_dec5
-// (lines split over NL lanes, K labels per lane, STEP = lane distance between
-// neighbouring lanes of a line), followed by the per-line minimum.
-//   val[k]  the K labels of this lane along the line (in/out)
-//   pos     this lane's index along the line, 0..NL-1
-//   lmin    out: the minimum of the input line (over all NL lanes)
+// Value of lane (lane - N); lanes below N receive unspecified values.
+template <int N>
+__device__ __forceinline__ int32_t lanes_up(int32_t v, int32_t lane) {
+    static_assert(N >= 1 && N <= 32, "shift");
+    if constexpr (N == 32) {
+        return (int32_t)__builtin_amdgcn_permlane32_swap(v, v, false, false)[0];
+    } else if constexpr (N == 16) {
+        return rows_up(v, lane);
+    } else {
+        const int32_t t = dpp<dpp_row_ror(N)>(v, v);
+        return (lane & 15) >= N ? t : rows_up(t, lane);
+    }
+}
+// Value of lane (lane + N); lanes at or above 64 - N receive unspecified values.
+template <int N>
+__device__ __forceinline__ int32_t lanes_down(int32_t v, int32_t lane) {
+    static_assert(N >= 1 && N <= 32, "shift");
+    if constexpr (N == 32) {
+        return (int32_t)__builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+    } else if constexpr (N == 16) {
+        return rows_down(v, lane);
+    } else {
+        const int32_t t = dpp<dpp_row_ror(16 - N)>(v, v);
+        return (lane & 15) < 16 - N ? t : rows_down(t, lane);
+    }
+}
+// Value of lane (lane ^ N) for N = 16 or 32.
+template <int N>
+__device__ __forceinline__ int32_t lanes_xor(int32_t v, int32_t lane) {
+    if constexpr (N == 32) {
+        const auto a = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return lane < 32 ? (int32_t)a[1] : (int32_t)a[0];
+    } else {
+        static_assert(N == 16, "xor");
+        const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? (int32_t)a[0] : (int32_t)a[1];
+    }
+}
+
+// ---- lines of NL lanes, STEP lanes apart ------------------------------------
+// pos is the lane's index along its line.  Lines of x (STEP = 1) lie in one
+// lane row when NL <= 16; lines of y (STEP = PX) fill whole rows.
+
+// value at position pos - D of the line; own value when pos < D
+template <int NL, int STEP, int D>
+__device__ __forceinline__ int32_t line_up(int32_t v, int32_t pos, int32_t lane) {
+    constexpr int n = D * STEP;
+    if constexpr (NL * STEP <= 16) {
+        const int32_t r = dpp<dpp_row_shr(n)>(v, v);
+        if constexpr (NL * STEP == 16) return r;
+        else return pos >= D ? r : v;
+    } else {
+        const int32_t r = lanes_up<n>(v, lane);
+        return pos >= D ? r : v;
+    }
+}
+// value at position pos + D of the line; own value when pos + D >= NL
+template <int NL, int STEP, int D>
+__device__ __forceinline__ int32_t line_down(int32_t v, int32_t pos, int32_t lane) {
+    constexpr int n = D * STEP;
+    if constexpr (NL * STEP <= 16) {
+        const int32_t r = dpp<dpp_row_shl(n)>(v, v);
+        if constexpr (NL * STEP == 16) return r;
+        else return pos + D < NL ? r : v;
+    } else {
+        const int32_t r = lanes_down<n>(v, lane);
+        return pos + D < NL ? r : v;
+    }
+}
+// minimum over the NL lanes of the line
+template <int NL, int STEP>
+__device__ __forceinline__ int32_t line_min(int32_t v, int32_t lane) {
+    if constexpr (NL == 1) {
+        return v;
+    } else if constexpr (NL * STEP < 16) {
+        static_assert(STEP == 1, "short lines must run along x");
+        v = imin(v, dpp<DPP_QUAD_XOR1>(v, v));
+        if constexpr (NL >= 4) v = imin(v, dpp<DPP_QUAD_XOR2>(v, v));
+        if constexpr (NL >= 8) v = imin(v, dpp<DPP_HALF_MIRROR>(v, v));
+        return v;
+    } else {
+        // inside a row the line's lanes form a coset of the rotation by STEP
+        if constexpr (STEP == 1) {
+            v = imin(v, dpp<DPP_QUAD_XOR1>(v, v));
+            v = imin(v, dpp<DPP_QUAD_XOR2>(v, v));
+            v = imin(v, dpp<DPP_HALF_MIRROR>(v, v));
+            v = imin(v, dpp<DPP_ROW_MIRROR>(v, v));
+        } else {
+            if constexpr (STEP <= 1) v = imin(v, dpp<dpp_row_ror(1)>(v, v));
+            if constexpr (STEP <= 2) v = imin(v, dpp<dpp_row_ror(2)>(v, v));
+            if constexpr (STEP <= 4) v = imin(v, dpp<dpp_row_ror(4)>(v, v));
+            if constexpr (STEP <= 8) v = imin(v, dpp<dpp_row_ror(8)>(v, v));
+        }
+        if constexpr (NL * STEP >= 32) v = imin(v, lanes_xor<16>(v, lane));
+        if constexpr (NL * STEP >= 64) v = imin(v, lanes_xor<32>(v, lane));
+        return v;
+    }
+}
+
+// ---- linear RMS on one dimension -------------------------------------------
+// For every line along the dimension: the L1 distance transform
+//   L(v) = min_v' h(v') + lam |v - v'|
+// as the forward pass of eq. L_dec3 and the backward pass of eq. L_dec5, then
+// the clip min(L, line_min + clipd) when clip is set (per-dimension
+// truncation).  Lines are split over NL lanes, K labels per lane.
+// Returns the minimum of the input line.
 template <int NL, int K, int STEP>
-__device__ __forceinline__ void l1_line(int32_t (&val)[K], const int32_t lam, const int32_t pos,
-                                        const int32_t lane, int32_t& lmin) {
+__device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t lam, const int32_t clipd,
+                                           const bool clip, const int32_t pos, const int32_t lane) {
     int32_t f[K], b[K];
     f[0] = val[0];
 #pragma unroll
@@ -58,38 +183,56 @@ __device__ __forceinline__ void l1_line(int32_t (&val)[K], const int32_t lam, co
     int32_t m = val[0];
 #pragma unroll
     for (int k = 1; k < K; ++k) m = imin(m, val[k]);
+    int32_t cf = PADV, cb = PADV;
     if constexpr (NL > 1) {
-        int32_t tf = f[K - 1];      // value at this lane's last label, scanned forward
-        int32_t tb = b[0];          // value at this lane's first label, scanned backward
-#pragma unroll
-        for (int d = 1; d < NL; d <<= 1) {
-            const int32_t uf = from_lane(tf, pos >= d ? lane - d * STEP : lane);
-            const int32_t ub = from_lane(tb, pos + d < NL ? lane + d * STEP : lane);
-            const int32_t um = from_lane(m, lane ^ (d * STEP));
-            tf = imin(tf, uf + lam * (K * d));
-            tb = imin(tb, ub + lam * (K * d));
-            m = imin(m, um);
+        int32_t tf = f[K - 1];      // forward value at this lane's last label
+        int32_t tb = b[0];          // backward value at this lane's first label
+        // inclusive scans along the line: each lane hop adds lam * K per lane of distance
+        if constexpr (NL > 1) {
+            tf = imin(tf, line_up<NL, STEP, 1>(tf, pos, lane) + lam * K);
+            tb = imin(tb, line_down<NL, STEP, 1>(tb, pos, lane) + lam * K);
         }
-        int32_t cf = from_lane(tf, pos >= 1 ? lane - STEP : lane);
-        int32_t cb = from_lane(tb, pos + 1 < NL ? lane + STEP : lane);
+        if constexpr (NL > 2) {
+            tf = imin(tf, line_up<NL, STEP, 2>(tf, pos, lane) + lam * (2 * K));
+            tb = imin(tb, line_down<NL, STEP, 2>(tb, pos, lane) + lam * (2 * K));
+        }
+        if constexpr (NL > 4) {
+            tf = imin(tf, line_up<NL, STEP, 4>(tf, pos, lane) + lam * (4 * K));
+            tb = imin(tb, line_down<NL, STEP, 4>(tb, pos, lane) + lam * (4 * K));
+        }
+        if constexpr (NL > 8) {
+            tf = imin(tf, line_up<NL, STEP, 8>(tf, pos, lane) + lam * (8 * K));
+            tb = imin(tb, line_down<NL, STEP, 8>(tb, pos, lane) + lam * (8 * K));
+        }
+        if constexpr (NL > 16) {
+            tf = imin(tf, line_up<NL, STEP, 16>(tf, pos, lane) + lam * (16 * K));
+            tb = imin(tb, line_down<NL, STEP, 16>(tb, pos, lane) + lam * (16 * K));
+        }
+        if constexpr (NL > 32) {
+            tf = imin(tf, line_up<NL, STEP, 32>(tf, pos, lane) + lam * (32 * K));
+            tb = imin(tb, line_down<NL, STEP, 32>(tb, pos, lane) + lam * (32 * K));
+        }
+        // carries from the neighbouring lanes (their last / first label)
+        cf = line_up<NL, STEP, 1>(tf, pos, lane);
+        cb = line_down<NL, STEP, 1>(tb, pos, lane);
         if (pos == 0) cf = PADV;
         if (pos == NL - 1) cb = PADV;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            f[k] = imin(f[k], cf + lam * (k + 1));
-            b[k] = imin(b[k], cb + lam * (K - k));
-        }
+        m = line_min<NL, STEP>(m, lane);
     }
+    const int32_t cap = clip ? m + clipd : PADV;
 #pragma unroll
-    for (int k = 0; k < K; ++k) val[k] = imin(f[k], b[k]);
-    lmin = m;
+    for (int k = 0; k < K; ++k) {
+        const int32_t x = imin3(cf + lam * (k + 1), cb + lam * (K - k), cap);
+        val[k] = imin3(f[k], b[k], x);
+    }
+    return m;
 }
 
 // Minimum of v over the G lanes of this lane's group.
-template <int G>
+template <class T>
 __device__ __forceinline__ int32_t group_min(int32_t v, const int32_t lane) {
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) v = imin(v, from_lane(v, lane ^ d));
+    v = line_min<T::PX, 1>(v, lane);
+    if constexpr (T::PY > 1) v = line_min<T::PY, T::PX>(v, lane);
     return v;
 }
 
@@ -108,40 +251,36 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
                                               const int32_t lane) {
     const int32_t l = lane % T::G;
     const int32_t px = l % T::PX, py = l / T::PX;
+    const bool one_dim = T::PY * T::KY == 1;
     int32_t rowmin = PADV;
 #pragma unroll
     for (int ky = 0; ky < T::KY; ++ky) {
-        int32_t lm;
-        l1_line<T::PX, T::KX, 1>(h[ky], lam, px, lane, lm);
+        // with a single label dimension the final clip is the per-line clip
+        const int32_t lm = l1_line<T::PX, T::KX, 1>(h[ky], lam, clipd, !joint || one_dim, px, lane);
         rowmin = imin(rowmin, lm);
-        if (!joint) {
-#pragma unroll
-            for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], lm + clipd);
-        }
     }
-    // rowmin: min over this lane's lines of the input; the global min needs the y lanes too.
-    int32_t gmin = rowmin;
-#pragma unroll
-    for (int d = 1; d < T::PY; d <<= 1) gmin = imin(gmin, from_lane(gmin, lane ^ (d * T::PX)));
-    if constexpr (T::PY * T::KY > 1) {
+    if constexpr (T::PY * T::KY == 1) {
+        return rowmin;
+    } else {
+        int32_t gmin = rowmin;
+        if constexpr (T::PY > 1) gmin = line_min<T::PY, T::PX>(gmin, lane);
 #pragma unroll
         for (int kx = 0; kx < T::KX; ++kx) {
             int32_t col[T::KY];
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
-            int32_t lm;
-            l1_line<T::PY, T::KY, T::PX>(col, lam, py, lane, lm);
+            l1_line<T::PY, T::KY, T::PX>(col, lam, clipd, !joint, py, lane);
 #pragma unroll
-            for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = joint ? col[ky] : imin(col[ky], lm + clipd);
+            for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
         }
-    }
-    if (joint) {
+        if (joint) {
 #pragma unroll
-        for (int ky = 0; ky < T::KY; ++ky)
+            for (int ky = 0; ky < T::KY; ++ky)
 #pragma unroll
-            for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], gmin + clipd);
+                for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], gmin + clipd);
+        }
+        return gmin;
     }
-    return gmin;
 }
 
 }  // namespace edp

@@ -27,7 +27,8 @@ __device__ __forceinline__ int32_t pack(int32_t v, int32_t ib, int32_t q) {
 
 template <class T, class CT, class PT, int PF>
 __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
-    constexpr int G = T::G, KX = T::KX, KY = T::KY, RPW = T::RPW, QT = T::QT;
+    constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
+    constexpr int RPW = 64 / G;
     const int32_t lane = lane_id();
     const int32_t grp = lane / G, l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
@@ -37,7 +38,8 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     const int32_t y = wave * RPW + grp;
     const bool rowok = y < H;
     const CT* __restrict__ crow = (const CT*)a.cost + (size_t)(rowok ? y : 0) * W * Q;
-    PT* __restrict__ prow = (PT*)a.ptr + (size_t)(rowok ? y : 0) * W * QT + l;
+    // choice indexes, lane-major: the E labels of a lane are contiguous
+    PT* __restrict__ prow = (PT*)a.ptr + (size_t)(rowok ? y : 0) * W * QT + (size_t)l * E;
     const int32_t ib = a.ibits;
     const int32_t mask = (1 << ib) - 1;
     const int32_t lamk = a.lam << ib, clipk = a.clipd << ib;
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx) {
                         const int32_t k = key[ky][kx];
-                        if (rowok) pp[(ky * KX + kx) * G] = (PT)(k & mask);
+                        if (rowok) pp[ky * KX + kx] = (PT)(k & mask);
                         const int32_t v = rc[u][ky][kx] + (k >> ib) - norm;
                         key[ky][kx] = valid[ky][kx] ? pack(v, ib, coff[ky][kx]) : PADV;
                     }
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
         for (int kx = 0; kx < KX; ++kx) m = imin(m, key[ky][kx]);
-    m = group_min<G>(m, lane);
+    m = group_min<T>(m, lane);
     if (rowok && l == 0) {
         a.row_label[y] = m & mask;
         a.row_energy[y] = offset + (int64_t)(m >> ib);
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
 
 template <class T, class PT>
 __global__ __launch_bounds__(64) void dp_backtrack_kernel(const BtArgs a) {
-    constexpr int G = T::G, QT = T::QT;
+    constexpr int QT = T::QT;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint16_t tab[4096];
     PT* buf = (PT*)smem;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(64) void dp_backtrack_kernel(const BtArgs a) {
     for (int32_t q = t; q < Q; q += 64) {
         const int32_t vy = q / a.qx, vx = q % a.qx;
         const int32_t ppy = vy / T::KY, ky = vy % T::KY, ppx = vx / T::KX, kx = vx % T::KX;
-        tab[q] = (uint16_t)((ky * T::KX + kx) * G + ppy * T::PX + ppx);
+        tab[q] = (uint16_t)((ppy * T::PX + ppx) * T::E + ky * T::KX + kx);
     }
     int32_t lab = a.row_label[y];
     int32_t* out = a.labels + (size_t)y * W;

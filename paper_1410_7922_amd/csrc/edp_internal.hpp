@@ -43,7 +43,7 @@ constexpr uint32_t SPIN_LIMIT = 1u << 21;
 struct PassArgs {
     const void* cost;        // [H][W][Q] int16/int32
     int32_t* t[4];           // T arrays +x, -x, +y, -y in tile layout [H][W][QT]
-    uint32_t* flags;         // [nbands] progress, monotone across the scans of one solve
+    uint32_t* flags;         // [nsuper] progress, monotone across the scans of one solve
     uint32_t* ticket;        // band counter of this scan (zero before the scan)
     uint32_t* error;         // set to 1 when a wait exceeds SPIN_LIMIT
     int32_t W, H, qx, qy;
@@ -54,7 +54,10 @@ struct PassArgs {
     int32_t old_b_zero;      // the other y-direction array still holds its initial zeros
     uint32_t epoch;          // flag base of this scan
     int32_t chunk;           // columns per progress publication
-    int32_t nbands;          // scanline bands of 64/G rows
+    int32_t nbands;          // scanline bands (one wavefront each)
+    int32_t nsuper;          // workgroup bands (waves per workgroup consecutive bands each)
+    int32_t b_live;          // the y-direction sum is read by later scans: store it everywhere
+    int32_t ring;            // LDS hand-off slots between consecutive wavefronts of a workgroup
 };
 
 struct AggArgs {
@@ -92,7 +95,8 @@ struct EnergyArgs {
 };
 
 // Launchers (return hipSuccess or the launch error).  dtype: 1 int16, 2 int32.
-hipError_t launch_edp_pass(int tile, int dtype, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_edp_pass(int tile, int dtype, int split, const PassArgs& a, int grid, int waves,
+                           hipStream_t s);
 hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
 hipError_t launch_dp_forward(int tile, int dtype, const DpArgs& a, int grid, hipStream_t s);
 hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
@@ -101,7 +105,9 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_sum_rows(const int64_t* rows, int32_t n, int64_t* out, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStream_t s);
 
-// Resident waves of the pass kernel for a tile (occupancy x CUs), cached.
-int pass_capacity(int tile, int dtype);
+// Resident workgroups of the pass kernel (occupancy x CUs) for a launch shape.
+int pass_capacity(int tile, int dtype, int split, int waves, size_t lds_bytes);
+// LDS bytes of the pass kernel for a tile, wavefronts per workgroup and ring slots.
+size_t pass_lds_bytes(int qt, int waves, int ring);
 
 }  // namespace edp

@@ -12,33 +12,65 @@
 // in the one-dimensional forms (eq. base, eq. DP_1D_3).
 //
 // Schedule.  Inside a scan vertex (x, y) depends on (x - sx, y) and
-// (x, y - sy): a 2D wavefront.  A wavefront of 64 lanes owns a band of
-// 64/G consecutive scanlines (G lanes per vertex); its lane groups run one
-// column apart, so the T_b a group produces at step s is handed to the group
-// below at step s + 1 with one cross-lane read.  Bands are taken in scan
-// order from a ticket counter, so the band a wavefront waits on is always
-// held by a wavefront that is already running; the last scanline of a band
-// publishes its progress every `chunk` columns (release at agent scope) and
-// the next band's first scanline reads it from memory after an acquire.
-// Operands that do not depend on the scan (C and the two "old" arrays) are
-// prefetched PF steps ahead in a register ring.
+// (x, y - sy): a 2D wavefront, pipelined at three levels.
+//  * Lanes: a vertex takes SPLIT * G lanes.  With SPLIT = 2 the lower G lanes
+//    compute T_a and the upper G lanes T_b, each with one minimum search, and
+//    they exchange T_a / T_b through cross-row permutes every step.
+//  * Wavefront: 64 / (SPLIT * G) scanlines run one column apart; the T_b a
+//    scanline produces at step s reaches the scanline below at step s + 1.
+//  * Workgroup: its wavefronts take consecutive bands of scanlines; the last
+//    scanline of a band hands T_b to the next wavefront through an LDS ring
+//    (progress counters in LDS).  Workgroups take whole groups of bands in
+//    scan order from a ticket counter, so the group a workgroup waits on is
+//    always held by a running workgroup; the last band publishes its progress
+//    every `chunk` columns (release at agent scope) and the next workgroup
+//    reads it from memory after an acquire.
+// T_b written by P1 and P3 is only read inside the scan, so it reaches memory
+// only at workgroup boundaries.  Operands that do not depend on the scan (C
+// and the two "old" arrays) are prefetched PF steps ahead in a register ring.
 #include "edp_device.hpp"
 #include "edp_internal.hpp"
 
 namespace edp {
 
-template <class T, class CT, int PF>
-__global__ __launch_bounds__(64) void edp_pass_kernel(const PassArgs a) {
-    constexpr int G = T::G, KX = T::KX, KY = T::KY, RPW = T::RPW, QT = T::QT;
+constexpr int MAX_WAVES = 8;
+
+__device__ __forceinline__ int32_t lds_load(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void raise_error(uint32_t* error) {
+    __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T, class CT, int SPLIT, int PF>
+__global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs a) {
+    constexpr int G = T::G, KX = T::KX, KY = T::KY, QT = T::QT;
+    constexpr int CL = SPLIT * G;                  // lanes per vertex
+    constexpr int RPW = 64 / CL;                   // scanlines per wavefront
+    static_assert(CL <= 64, "vertex wider than a wavefront");
+    extern __shared__ int32_t lds[];
+    int32_t* prod = lds;                           // [MAX_WAVES] columns handed to the next wavefront
+    int32_t* cons = lds + MAX_WAVES;               // [MAX_WAVES] columns taken from the previous one
+    int32_t* misc = lds + 2 * MAX_WAVES;           // [0] ticket broadcast
+    int32_t* rings = lds + 2 * MAX_WAVES + 4;      // [NW-1][ring][QT]
+
     const int32_t lane = lane_id();
-    const int32_t grp = lane / G, l = lane % G;
+    const int32_t wave = (int32_t)(threadIdx.x >> 6);
+    const int32_t NW = (int32_t)(blockDim.x >> 6);
+    const int32_t grp = lane / CL;
+    const bool beta = SPLIT == 2 && ((lane / G) & 1);
+    const int32_t l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
-    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy;
+    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy, R = a.ring;
     const CT* __restrict__ cost = (const CT*)a.cost;
     int32_t* __restrict__ Ta = a.t[a.ka];
     int32_t* __restrict__ Tb = a.t[a.kb];
     const int32_t* __restrict__ Tma = a.t[a.ka ^ 1];
     const int32_t* __restrict__ Tmb = a.t[a.kb ^ 1];
+    const bool joint = a.joint != 0;
 
     int32_t coff[KY][KX];
     bool valid[KY][KX];
@@ -52,142 +84,221 @@ __global__ __launch_bounds__(64) void edp_pass_kernel(const PassArgs a) {
         }
 
     for (;;) {
-        int32_t band = 0;
-        if (lane == 0) band = (int32_t)atomicAdd(a.ticket, 1u);
-        band = __builtin_amdgcn_readfirstlane(band);
-        if (band >= a.nbands) break;
+        if (threadIdx.x == 0) misc[0] = (int32_t)atomicAdd(a.ticket, 1u);
+        if (threadIdx.x < 2 * MAX_WAVES) lds[threadIdx.x] = 0;
+        __syncthreads();
+        const int32_t super = misc[0];
+        __syncthreads();
+        if (super >= a.nsuper) break;
+        const int32_t band = super * NW + wave;
+        if (band < a.nbands) {
+            const int32_t j = band * RPW + grp;            // scan-order row index
+            const bool rowok = j < H;
+            const int32_t y = a.sy > 0 ? j : H - 1 - j;
+            const int32_t yp = y - a.sy;                   // previous row in scan order
+            const int32_t yn = y + a.sy;                   // next row in scan order
+            const bool has_next = j + 1 < H;
+            // where group 0 finds the row above: memory (first wavefront of a workgroup band
+            // that is not the first), LDS (other wavefronts), nowhere (the first row)
+            const bool from_global = wave == 0 && super > 0;
+            const bool from_lds = wave > 0;
+            // the band's last scanline feeds the next wavefront (LDS) or workgroup (memory)
+            const bool to_lds = wave + 1 < NW && band + 1 < a.nbands;
+            const bool to_global = wave == NW - 1 && band + 1 < a.nbands;
+            const bool store_b = a.b_live || (to_global && grp == RPW - 1);
+            const int32_t* ring_in = rings + (size_t)(wave > 0 ? wave - 1 : 0) * R * QT;
+            int32_t* ring_out = rings + (size_t)wave * R * QT;
+            uint32_t seen = 0;                             // columns published by the workgroup above
+            const int32_t nsteps = W + RPW - 1;
 
-        const int32_t j = band * RPW + grp;            // scan-order row index
-        const bool rowok = j < H;
-        const int32_t y = a.sy > 0 ? j : H - 1 - j;
-        const int32_t yp = y - a.sy;                   // previous row in scan order
-        const int32_t yn = y + a.sy;                   // next row in scan order
-        const bool has_next = j + 1 < H;
-        const bool global_b = band > 0;                // group 0 reads the band above from memory
-        uint32_t seen = 0;                             // columns the band above has published
-        const int32_t nsteps = W + RPW - 1;
-
-        int32_t rc[PF][KY][KX], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
-        int32_t carry[KY][KX], tbout[KY][KX];
-#pragma unroll
-        for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-            for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = tbout[ky][kx] = 0;
-
-        // Issue the loads of step t into ring slot u.
-        auto fetch = [&](const int32_t t, int32_t (&c)[KY][KX], int32_t (&ma)[KY][KX],
-                         int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX]) {
-            if (global_b && t < W) {                   // wave-uniform wait for the band above
-                const uint32_t need = (uint32_t)t + 1;
-                if (seen < need) {
-                    uint32_t got = 0;
-                    if (lane == 0) {
-                        uint32_t v = 0, spins = 0;
-                        for (;;) {
-                            v = __hip_atomic_load(a.flags + band - 1, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                            if (v >= a.epoch + need) break;
-                            // give up (and let every other waiter give up) instead of hanging
-                            if (++spins > SPIN_LIMIT ||
-                                __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                                __hip_atomic_store(a.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                v = a.epoch + (uint32_t)W;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                        }
-                        got = v - a.epoch;
-                    }
-                    seen = __builtin_amdgcn_readfirstlane(got);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                }
-            }
-            const int32_t i = t - grp;
-            const bool act = rowok && i >= 0 && i < W;
-            const int32_t x = a.sx > 0 ? i : W - 1 - i;
-            const int32_t xa = x + a.sx;
-            const bool ina = act && xa >= 0 && xa < W && !a.old_a_zero;
-            const bool inb = act && has_next && !a.old_b_zero;
-            const bool ing = act && global_b && grp == 0;
-            const size_t cell = (size_t)y * W + x;
-            const CT* cc = cost + cell * Q;
-            const int32_t* pa = Tma + ((size_t)y * W + xa) * QT + l;
-            const int32_t* pb = Tmb + ((size_t)yn * W + x) * QT + l;
-            const int32_t* pg = Tb + ((size_t)yp * W + x) * QT + l;
+            int32_t rc[PF][KY][KX], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
+            int32_t carry[KY][KX], out[KY][KX];
 #pragma unroll
             for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                for (int kx = 0; kx < KX; ++kx) {
-                    const int e = (ky * KX + kx) * G;
-                    c[ky][kx] = (act && valid[ky][kx]) ? (int32_t)cc[coff[ky][kx]] : 0;
-                    ma[ky][kx] = ina ? pa[e] : 0;
-                    mb[ky][kx] = inb ? pb[e] : 0;
-                    gb[ky][kx] = ing ? pg[e] : 0;
-                }
-        };
+                for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = out[ky][kx] = 0;
 
-#pragma unroll
-        for (int u = 0; u < PF; ++u) fetch(u, rc[u], rma[u], rmb[u], rb[u]);
-
-        for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
-#pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                const int32_t s = s0 + u;
-                if (s < nsteps) {
-                    const int32_t i = s - grp;
-                    const bool act = rowok && i >= 0 && i < W;
-                    const int32_t x = a.sx > 0 ? i : W - 1 - i;
-                    int32_t ha[KY][KX], hb[KY][KX];
-#pragma unroll
-                    for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                        for (int kx = 0; kx < KX; ++kx) {
-                            int32_t mbv = from_lane(tbout[ky][kx], (lane - G) & 63);
-                            if (grp == 0) mbv = rb[u][ky][kx];
-                            const int32_t A = rc[u][ky][kx] + carry[ky][kx] + mbv;
-                            const int32_t d = rmb[u][ky][kx] - rma[u][ky][kx];
-                            ha[ky][kx] = valid[ky][kx] ? ((A + d) >> 1) : PADV;
-                            hb[ky][kx] = valid[ky][kx] ? ((A - d) >> 1) : PADV;
+            // Issue the loads of step t into one ring slot.
+            auto fetch = [&](const int32_t t, int32_t (&c)[KY][KX], int32_t (&ma)[KY][KX],
+                             int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX]) {
+                if (from_global && t < W) {                // wave-uniform wait for the workgroup above
+                    const uint32_t need = (uint32_t)t + 1;
+                    if (seen < need) {
+                        uint32_t got = 0;
+                        if (lane == 0) {
+                            uint32_t v = 0, spins = 0;
+                            for (;;) {
+                                v = __hip_atomic_load(a.flags + super - 1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                                if (v >= a.epoch + need) break;
+                                // give up (and let every other waiter give up) instead of hanging
+                                if (++spins > SPIN_LIMIT ||
+                                    __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                    raise_error(a.error);
+                                    v = a.epoch + (uint32_t)W;
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                            got = v - a.epoch;
                         }
-                    min_search<T>(ha, a.lam, a.clipd, a.joint != 0, lane);
-                    min_search<T>(hb, a.lam, a.clipd, a.joint != 0, lane);
-                    if (act) {
-                        int32_t* oa = Ta + ((size_t)y * W + x) * QT + l;
-                        int32_t* ob = Tb + ((size_t)y * W + x) * QT + l;
+                        seen = __builtin_amdgcn_readfirstlane(got);
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                }
+                const int32_t i = t - grp;
+                const bool act = rowok && i >= 0 && i < W;
+                const int32_t x = a.sx > 0 ? i : W - 1 - i;
+                const int32_t xa = x + a.sx;
+                const bool ina = act && xa >= 0 && xa < W && !a.old_a_zero;
+                const bool inb = act && has_next && !a.old_b_zero;
+                const bool ing = act && from_global && grp == 0;
+                const size_t cell = (size_t)y * W + x;
+                const CT* cc = cost + cell * Q;
+                const int32_t* pa = Tma + ((size_t)y * W + xa) * QT + l;
+                const int32_t* pb = Tmb + ((size_t)yn * W + x) * QT + l;
+                const int32_t* pg = Tb + ((size_t)yp * W + x) * QT + l;
+#pragma unroll
+                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) {
+                        const int e = (ky * KX + kx) * G;
+                        c[ky][kx] = (act && valid[ky][kx]) ? (int32_t)cc[coff[ky][kx]] : 0;
+                        ma[ky][kx] = ina ? pa[e] : 0;
+                        mb[ky][kx] = inb ? pb[e] : 0;
+                        gb[ky][kx] = ing ? pg[e] : 0;
+                    }
+            };
+
+#pragma unroll
+            for (int u = 0; u < PF; ++u) fetch(u, rc[u], rma[u], rmb[u], rb[u]);
+
+            for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int32_t s = s0 + u;
+                    if (s < nsteps) {
+                        const int32_t i = s - grp;
+                        const bool act = rowok && i >= 0 && i < W;
+                        const int32_t x = a.sx > 0 ? i : W - 1 - i;
+                        // T_b of the row above at this column, for group 0 of an inner wavefront
+                        int32_t lb[KY][KX];
+#pragma unroll
+                        for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                            for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = 0;
+                        if (from_lds && s < W) {                 // wave-uniform
+                            const int32_t need = s + 1;
+                            uint32_t spins = 0;
+                            while (lds_load(prod + wave - 1) < need) {
+                                if (++spins > SPIN_LIMIT) {
+                                    raise_error(a.error);
+                                    break;
+                                }
+                            }
+                            if (grp == 0) {
+                                const int32_t* slot = ring_in + (size_t)(s % R) * QT + l;
+#pragma unroll
+                                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                                    for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = slot[(ky * KX + kx) * G];
+                            }
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                            if (lane == 0) lds_store(cons + wave, need);
+                        }
+                        int32_t h[KY][KX], h2[KY][KX];
 #pragma unroll
                         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
                             for (int kx = 0; kx < KX; ++kx) {
-                                const int e = (ky * KX + kx) * G;
-                                oa[e] = ha[ky][kx];
-                                ob[e] = hb[ky][kx];
-                                carry[ky][kx] = ha[ky][kx];
+                                const int32_t v = out[ky][kx];
+                                int32_t cr, mb;
+                                if constexpr (SPLIT == 1) {
+                                    cr = carry[ky][kx];
+                                    mb = 0;
+                                    if constexpr (RPW > 1) mb = lanes_up<(RPW > 1 ? CL : 1)>(v, lane);
+                                } else {
+                                    const int32_t x1 = lanes_up<G>(v, lane);
+                                    int32_t x2 = 0;
+                                    if constexpr (RPW > 1) x2 = lanes_up<(RPW > 1 ? 2 * G : 1)>(v, lane);
+                                    cr = beta ? x1 : v;
+                                    mb = beta ? x2 : x1;
+                                    if (i == 0) cr = 0;
+                                }
+                                if (grp == 0) mb = from_global ? rb[u][ky][kx] : lb[ky][kx];
+                                const int32_t A = rc[u][ky][kx] + cr + mb;
+                                const int32_t d = rmb[u][ky][kx] - rma[u][ky][kx];
+                                if constexpr (SPLIT == 1) {
+                                    h[ky][kx] = valid[ky][kx] ? ((A + d) >> 1) : PADV;
+                                    h2[ky][kx] = valid[ky][kx] ? ((A - d) >> 1) : PADV;
+                                } else {
+                                    h[ky][kx] = valid[ky][kx] ? ((A + (beta ? -d : d)) >> 1) : PADV;
+                                }
                             }
-                    }
+                        min_search<T>(h, a.lam, a.clipd, joint, lane);
+                        if constexpr (SPLIT == 1) min_search<T>(h2, a.lam, a.clipd, joint, lane);
+                        const size_t o = ((size_t)y * W + x) * QT + l;
+                        if (act) {
 #pragma unroll
-                    for (int ky = 0; ky < KY; ++ky)
+                            for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                        for (int kx = 0; kx < KX; ++kx) tbout[ky][kx] = hb[ky][kx];
-                    // publish the band's progress to the band below
-                    if (band + 1 < a.nbands) {
-                        const int32_t il = s - (RPW - 1);
-                        if (il >= 0 && il < W && (((il + 1) % a.chunk) == 0 || il == W - 1)) {
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                            if (lane == 0)
-                                __hip_atomic_store(a.flags + band, a.epoch + (uint32_t)(il + 1),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                for (int kx = 0; kx < KX; ++kx) {
+                                    const int e = (ky * KX + kx) * G;
+                                    if constexpr (SPLIT == 1) {
+                                        Ta[o + e] = h[ky][kx];
+                                        if (store_b) Tb[o + e] = h2[ky][kx];
+                                        carry[ky][kx] = h[ky][kx];
+                                    } else {
+                                        if (!beta) Ta[o + e] = h[ky][kx];
+                                        else if (store_b) Tb[o + e] = h[ky][kx];
+                                    }
+                                }
                         }
+#pragma unroll
+                        for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                            for (int kx = 0; kx < KX; ++kx) out[ky][kx] = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
+                        // hand the band's last scanline T_b to the next wavefront / workgroup
+                        const int32_t il = s - (RPW - 1);
+                        if (il >= 0 && il < W) {                 // wave-uniform
+                            if (to_lds) {
+                                uint32_t spins = 0;
+                                while (lds_load(cons + wave + 1) < il + 1 - R) {
+                                    if (++spins > SPIN_LIMIT) {
+                                        raise_error(a.error);
+                                        break;
+                                    }
+                                }
+                                if (grp == RPW - 1 && (SPLIT == 1 || beta)) {
+                                    int32_t* slot = ring_out + (size_t)(il % R) * QT + l;
+#pragma unroll
+                                    for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                                        for (int kx = 0; kx < KX; ++kx) slot[(ky * KX + kx) * G] = out[ky][kx];
+                                }
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                                if (lane == 0) lds_store(prod + wave, il + 1);
+                            }
+                            if (to_global && (((il + 1) % a.chunk) == 0 || il == W - 1)) {
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                                if (lane == 0)
+                                    __hip_atomic_store(a.flags + super, a.epoch + (uint32_t)(il + 1),
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            }
+                        }
+                        if (s + PF < nsteps) fetch(s + PF, rc[u], rma[u], rmb[u], rb[u]);
                     }
-                    if (s + PF < nsteps) fetch(s + PF, rc[u], rma[u], rmb[u], rb[u]);
                 }
             }
         }
+        __syncthreads();
     }
 }
 
 template <class T, class CT>
 __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
-    constexpr int G = T::G, KX = T::KX, KY = T::KY, RPW = T::RPW, QT = T::QT;
+    constexpr int G = T::G, KX = T::KX, KY = T::KY, QT = T::QT;
+    constexpr int RPW = 64 / G;
     const int32_t lane = lane_id();
     const int32_t grp = lane / G, l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
@@ -217,13 +328,10 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
                     if (v < best || (v == best && q < bq)) { best = v; bq = q; }
                 }
             }
-#pragma unroll
-        for (int d = 1; d < G; d <<= 1) {
-            const int32_t ob = from_lane(best, lane ^ d);
-            const int32_t oq = from_lane(bq, lane ^ d);
-            if (ob < best || (ob == best && oq < bq)) { best = ob; bq = oq; }
-        }
-        if (ok && l == 0) a.labels[cell] = bq;
+        // smallest value, then the smallest label among the lanes holding it
+        const int32_t vmin = group_min<T>(best, lane);
+        const int32_t qmin = group_min<T>(best == vmin ? bq : 0x7FFFFFFF, lane);
+        if (ok && l == 0) a.labels[cell] = qmin;
     }
 }
 
@@ -231,9 +339,14 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
 template <class T>
 constexpr int pass_pf() { return T::E <= 2 ? 4 : (T::E <= 4 ? 2 : 1); }
 
-template <class T, class CT>
-static hipError_t run_pass(const PassArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((edp_pass_kernel<T, CT, pass_pf<T>()>), dim3(grid), dim3(64), 0, s, a);
+size_t pass_lds_bytes(int qt, int waves, int ring) {
+    return (size_t)(2 * MAX_WAVES + 4) * 4 + (size_t)(waves > 1 ? waves - 1 : 0) * ring * qt * 4;
+}
+
+template <class T, class CT, int SPLIT>
+static hipError_t run_pass(const PassArgs& a, int grid, int waves, hipStream_t s) {
+    const size_t lds = pass_lds_bytes(T::QT, waves, a.ring);
+    hipLaunchKernelGGL((edp_pass_kernel<T, CT, SPLIT, pass_pf<T>()>), dim3(grid), dim3(64 * waves), lds, s, a);
     return hipGetLastError();
 }
 
@@ -243,21 +356,42 @@ static hipError_t run_agg(const AggArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class T, class CT>
-static int pass_occupancy() {
+template <class T, class CT, int SPLIT>
+static int pass_occupancy(int waves, size_t lds) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CT, pass_pf<T>()>, 64, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CT, SPLIT, pass_pf<T>()>,
+                                                     64 * waves, lds) != hipSuccess)
         blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
 
-hipError_t launch_edp_pass(int tile, int dtype, const PassArgs& a, int grid, hipStream_t s) {
+// SPLIT = 2 needs both halves of a vertex in one wavefront.
+template <class T, class CT>
+static hipError_t dispatch_pass(int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
+    if (split == 2) {
+        if constexpr (2 * T::G <= 64) return run_pass<T, CT, 2>(a, grid, waves, s);
+        return hipErrorInvalidValue;
+    }
+    return run_pass<T, CT, 1>(a, grid, waves, s);
+}
+
+template <class T, class CT>
+static int dispatch_occupancy(int split, int waves, size_t lds) {
+    if (split == 2) {
+        if constexpr (2 * T::G <= 64) return pass_occupancy<T, CT, 2>(waves, lds);
+        return 1;
+    }
+    return pass_occupancy<T, CT, 1>(waves, lds);
+}
+
+hipError_t launch_edp_pass(int tile, int dtype, int split, const PassArgs& a, int grid, int waves,
+                           hipStream_t s) {
+    if (waves < 1 || waves > MAX_WAVES) return hipErrorInvalidValue;
     switch (tile) {
-#define EDP_CASE(id, px, kx, py, ky)                                                   \
-    case id:                                                                           \
-        return dtype == 1 ? run_pass<Tile<px, kx, py, ky>, int16_t>(a, grid, s)        \
-                          : run_pass<Tile<px, kx, py, ky>, int32_t>(a, grid, s);
+#define EDP_CASE(id, px, kx, py, ky)                                                               \
+    case id:                                                                                       \
+        return dtype == 1 ? dispatch_pass<Tile<px, kx, py, ky>, int16_t>(split, a, grid, waves, s) \
+                          : dispatch_pass<Tile<px, kx, py, ky>, int32_t>(split, a, grid, waves, s);
         EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE
     }
@@ -276,28 +410,22 @@ hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid,
     return hipErrorInvalidValue;
 }
 
-int pass_capacity(int tile, int dtype) {
-    static int cache[NUM_TILES][2] = {};
-    const int di = dtype == 1 ? 0 : 1;
-    if (tile < 0 || tile >= NUM_TILES) return 1;
-    if (cache[tile][di] == 0) {
-        int per_cu = 1;
-        switch (tile) {
-#define EDP_CASE(id, px, kx, py, ky)                                                              \
-    case id:                                                                                      \
-        per_cu = dtype == 1 ? pass_occupancy<Tile<px, kx, py, ky>, int16_t>()                     \
-                            : pass_occupancy<Tile<px, kx, py, ky>, int32_t>();                    \
+int pass_capacity(int tile, int dtype, int split, int waves, size_t lds_bytes) {
+    int per_cu = 1;
+    switch (tile) {
+#define EDP_CASE(id, px, kx, py, ky)                                                                      \
+    case id:                                                                                              \
+        per_cu = dtype == 1 ? dispatch_occupancy<Tile<px, kx, py, ky>, int16_t>(split, waves, lds_bytes)  \
+                            : dispatch_occupancy<Tile<px, kx, py, ky>, int32_t>(split, waves, lds_bytes); \
         break;
-            EDP_TILE_LIST(EDP_CASE)
+        EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE
-        }
-        int dev = 0, cus = 1;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 1;
-        cache[tile][di] = per_cu * cus;
     }
-    return cache[tile][di];
+    int dev = 0, cus = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 1;
+    return per_cu * cus;
 }
 
 }  // namespace edp

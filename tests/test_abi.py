@@ -80,6 +80,13 @@ def test_tiles_and_workspace_sizes():
         qt = px * kx * py * ky
         assert st == 0 and n >= 4 * 384 * 288 * qt * 4
     assert _ws(_prob(), B.OP_EDP, 0)[0] == -1        # tile 0 holds 16 labels only
+    lib = B.load()
+    n = ctypes.c_size_t(0)
+    p = _prob()
+    bad_split = B.Tuning(2, 0, 2, 0, None, 0)          # tile 2 spans 64 lanes: no room for two halves
+    assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_split), ctypes.byref(n)) == -1
+    bad_waves = B.Tuning(-1, 0, 0, 9, None, 0)
+    assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_waves), ctypes.byref(n)) == -1
 
 
 def test_workspace_and_pointer_errors_are_host_side():
