@@ -237,6 +237,11 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     int tile = 0;
     st = pick_tile(prob, tuning, &tile);
     if (st != EDP_OK) return st;
+    // the DP kernels address the cost volume and the choice indexes with 32-bit byte offsets
+    const int64_t cells = (int64_t)prob->width * prob->height;
+    if (cells * qt_of(tile) * (qt_of(tile) <= 256 ? 1 : 2) >= 0x7FFF0000LL ||
+        cells * prob->qx * prob->qy * (prob->dtype == EDP_I16 ? 2 : 4) >= 0x7FFF0000LL)
+        return EDP_E_UNSUPPORTED;
     const DpLayout L = dp_layout(prob, tile);
     if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < L.total) return EDP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
@@ -301,6 +306,11 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     st = pick_launch(prob, tuning, &la);
     if (st != EDP_OK) return st;
     const int tile = la.tile;
+    // the scan kernel addresses each array with 32-bit byte offsets below 0x7FFF0000
+    const int64_t cells = (int64_t)prob->width * prob->height;
+    if (cells * qt_of(tile) * 4 >= 0x7FFF0000LL ||
+        cells * prob->qx * prob->qy * (prob->dtype == EDP_I16 ? 2 : 4) >= 0x7FFF0000LL)
+        return EDP_E_UNSUPPORTED;
     const EdpLayout L = edp_layout(prob, la);
     if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < L.total) return EDP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
@@ -364,7 +374,6 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     g.H = prob->height;
     g.qx = prob->qx;
     g.qy = prob->qy;
-    const int64_t cells = (int64_t)prob->width * prob->height;
     const int64_t per_block = (64 / group_of(tile)) * 4;
     int64_t agrid = (cells + per_block - 1) / per_block;
     if (agrid > 8192) agrid = 8192;

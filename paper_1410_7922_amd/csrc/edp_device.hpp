@@ -37,6 +37,25 @@ __device__ __forceinline__ int32_t lane_id() { return (int32_t)__lane_id(); }
 __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int32_t imin3(int32_t a, int32_t b, int32_t c) { return imin(imin(a, b), c); }
 
+// Raw buffer access.  Offsets are bytes; OOB lies beyond every buffer (all
+// buffers are below 2^31 - 2^16 bytes), so a load there returns 0 and a store
+// there is dropped.
+constexpr int32_t OOB = 0x7FFF0000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ int32_t load_i32(__amdgpu_buffer_rsrc_t r, int32_t off) {
+    return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ void store_i32(__amdgpu_buffer_rsrc_t r, int32_t off, int32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)v, r, off, 0, 0);
+}
+template <class CT>
+__device__ __forceinline__ int32_t load_cost(__amdgpu_buffer_rsrc_t r, int32_t off) {
+    if constexpr (sizeof(CT) == 2) return (int32_t)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
 // ---- DPP (GFX9 encodings) --------------------------------------------------
 constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2,3,0,1]

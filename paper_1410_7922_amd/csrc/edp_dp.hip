@@ -29,6 +29,7 @@ template <class T, class CT, class PT, int PF>
 __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int RPW = 64 / G;
+    constexpr int CB = (int)sizeof(CT);
     const int32_t lane = lane_id();
     const int32_t grp = lane / G, l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
@@ -37,14 +38,17 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     if (wave * RPW >= H) return;                       // whole wavefront past the last row
     const int32_t y = wave * RPW + grp;
     const bool rowok = y < H;
-    const CT* __restrict__ crow = (const CT*)a.cost + (size_t)(rowok ? y : 0) * W * Q;
-    // choice indexes, lane-major: the E labels of a lane are contiguous
-    PT* __restrict__ prow = (PT*)a.ptr + (size_t)(rowok ? y : 0) * W * QT + (size_t)l * E;
     const int32_t ib = a.ibits;
     const int32_t mask = (1 << ib) - 1;
     const int32_t lamk = a.lam << ib, clipk = a.clipd << ib;
+    // buffer resources (see the scan kernel): lanes without an operand use offset OOB
+    const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(a.cost, W * H * Q * CB);
+    const __amdgpu_buffer_rsrc_t rs_p = make_rsrc(a.ptr, W * H * QT * (int32_t)sizeof(PT));
+    const int32_t crow = rowok ? y * W * Q * CB : OOB;
+    // choice indexes, lane-major: the E labels of a lane are contiguous
+    const int32_t prow = rowok ? (y * W * QT + l * E) * (int32_t)sizeof(PT) : OOB;
 
-    int32_t coff[KY][KX];
+    int32_t coffb[KY][KX], q[KY][KX];
     bool valid[KY][KX];
 #pragma unroll
     for (int ky = 0; ky < KY; ++ky)
@@ -52,16 +56,17 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
         for (int kx = 0; kx < KX; ++kx) {
             const int32_t vy = py * KY + ky, vx = px * KX + kx;
             valid[ky][kx] = rowok && vx < a.qx && vy < a.qy;
-            coff[ky][kx] = vy * a.qx + vx;
+            q[ky][kx] = vy * a.qx + vx;
+            coffb[ky][kx] = valid[ky][kx] ? q[ky][kx] * CB : OOB;
         }
 
     int32_t rc[PF][KY][KX];
     auto fetch = [&](const int32_t x, int32_t (&c)[KY][KX]) {
+        const int32_t base = x < W ? crow + x * Q * CB : OOB;
 #pragma unroll
         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-            for (int kx = 0; kx < KX; ++kx)
-                c[ky][kx] = (valid[ky][kx] && x < W) ? (int32_t)crow[(size_t)x * Q + coff[ky][kx]] : 0;
+            for (int kx = 0; kx < KX; ++kx) c[ky][kx] = load_cost<CT>(rs_c, base + coffb[ky][kx]);
     };
 
     int32_t key[KY][KX];
@@ -72,32 +77,43 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
             for (int kx = 0; kx < KX; ++kx)
-                key[ky][kx] = valid[ky][kx] ? pack(c0[ky][kx], ib, coff[ky][kx]) : PADV;
+                key[ky][kx] = valid[ky][kx] ? pack(c0[ky][kx], ib, q[ky][kx]) : PADV;
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) fetch(1 + u, rc[u]);
 
     int64_t offset = 0;
-    for (int32_t x0 = 1; x0 < W; x0 += PF) {
+    // whole prefetch rounds (steps past W - 1 change nothing), see the scan kernel
+    const int32_t xend = 1 + (W - 1 + PF - 1) / PF * PF;
+    for (int32_t x0 = 1; x0 < xend; x0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int32_t x = x0 + u;
-            if (x < W) {
-                const int32_t g = min_search<T>(key, lamk, clipk, a.joint != 0, lane);
-                const int32_t norm = g >> ib;
-                PT* pp = prow + (size_t)x * QT;
+            const bool live = x < W;
+            const int32_t g = min_search<T>(key, lamk, clipk, a.joint != 0, lane);
+            const int32_t norm = g >> ib;
+            uint32_t packed = 0;
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky)
+            for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                    for (int kx = 0; kx < KX; ++kx) {
-                        const int32_t k = key[ky][kx];
-                        if (rowok) pp[ky * KX + kx] = (PT)(k & mask);
-                        const int32_t v = rc[u][ky][kx] + (k >> ib) - norm;
-                        key[ky][kx] = valid[ky][kx] ? pack(v, ib, coff[ky][kx]) : PADV;
+                for (int kx = 0; kx < KX; ++kx) {
+                    const int32_t k = key[ky][kx];
+                    packed |= (uint32_t)(k & mask) << (8 * sizeof(PT) * ((ky * KX + kx) % (4 / sizeof(PT))));
+                    if (((ky * KX + kx) + 1) % (4 / sizeof(PT)) == 0 || (ky * KX + kx) == E - 1) {
+                        const int32_t first = (ky * KX + kx) / (4 / sizeof(PT)) * (4 / sizeof(PT));
+                        const int32_t off = live ? prow + (x * QT + first) * (int32_t)sizeof(PT) : OOB;
+                        const int32_t nb = ((ky * KX + kx) - first + 1) * (int32_t)sizeof(PT);
+                        if (nb == 4) __builtin_amdgcn_raw_buffer_store_b32(packed, rs_p, off, 0, 0);
+                        else if (nb == 2) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)packed, rs_p, off, 0, 0);
+                        else __builtin_amdgcn_raw_buffer_store_b8((uint8_t)packed, rs_p, off, 0, 0);
+                        packed = 0;
                     }
-                offset += norm;
-                fetch(x + PF, rc[u]);
-            }
+                    const int32_t v = rc[u][ky][kx] + (k >> ib) - norm;
+                    const int32_t nk = valid[ky][kx] ? pack(v, ib, q[ky][kx]) : PADV;
+                    key[ky][kx] = live ? nk : key[ky][kx];
+                }
+            offset += live ? norm : 0;
+            fetch(x + PF, rc[u]);
         }
     }
     int32_t m = PADV;

@@ -35,11 +35,19 @@ namespace edp {
 
 constexpr int MAX_WAVES = 8;
 
-__device__ __forceinline__ int32_t lds_load(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Progress counters in LDS.  Every lane reads / writes the same word; the LDS
+// operations of one wavefront are performed in issue order, which orders a
+// counter against the ring slot written or read before it.
+__device__ __forceinline__ int32_t lds_get(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void lds_store(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ void lds_put(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// byte offset of a vertex (wrapping arithmetic: lanes off the grid discard it)
+__device__ __forceinline__ int32_t cell_off(int32_t cell, int32_t bytes) {
+    return (int32_t)((uint32_t)cell * (uint32_t)bytes);
 }
 __device__ __forceinline__ void raise_error(uint32_t* error) {
     __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -50,12 +58,14 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     constexpr int G = T::G, KX = T::KX, KY = T::KY, QT = T::QT;
     constexpr int CL = SPLIT * G;                  // lanes per vertex
     constexpr int RPW = 64 / CL;                   // scanlines per wavefront
+    constexpr int CB = (int)sizeof(CT);
     static_assert(CL <= 64, "vertex wider than a wavefront");
     extern __shared__ int32_t lds[];
     int32_t* prod = lds;                           // [MAX_WAVES] columns handed to the next wavefront
     int32_t* cons = lds + MAX_WAVES;               // [MAX_WAVES] columns taken from the previous one
     int32_t* misc = lds + 2 * MAX_WAVES;           // [0] ticket broadcast
-    int32_t* rings = lds + 2 * MAX_WAVES + 4;      // [NW-1][ring][QT]
+    int32_t* trash = lds + 2 * MAX_WAVES + 4;      // [QT] sink of the lanes that hand nothing over
+    int32_t* rings = trash + QT;                   // [NW-1][ring][QT]
 
     const int32_t lane = lane_id();
     const int32_t wave = (int32_t)(threadIdx.x >> 6);
@@ -65,14 +75,18 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     const int32_t l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
     const int32_t W = a.W, H = a.H, Q = a.qx * a.qy, R = a.ring;
-    const CT* __restrict__ cost = (const CT*)a.cost;
-    int32_t* __restrict__ Ta = a.t[a.ka];
-    int32_t* __restrict__ Tb = a.t[a.kb];
-    const int32_t* __restrict__ Tma = a.t[a.ka ^ 1];
-    const int32_t* __restrict__ Tmb = a.t[a.kb ^ 1];
     const bool joint = a.joint != 0;
+    // Buffer resources: a lane whose operand does not exist uses offset OOB, so
+    // its load returns 0 and its store is dropped, with no branch around it.
+    const int32_t tbytes = W * H * QT * 4;         // below 2^31 (checked by the host)
+    const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(a.cost, W * H * Q * CB);
+    const __amdgpu_buffer_rsrc_t rs_a = make_rsrc(a.t[a.ka], tbytes);
+    const __amdgpu_buffer_rsrc_t rs_b = make_rsrc(a.t[a.kb], tbytes);
+    const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(a.t[a.ka ^ 1], tbytes);
+    const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(a.t[a.kb ^ 1], tbytes);
+    const int32_t lofs = l * 4;                    // this lane's first element inside a vertex
 
-    int32_t coff[KY][KX];
+    int32_t coffb[KY][KX];                         // cost byte offset of each label, OOB for padding
     bool valid[KY][KX];
 #pragma unroll
     for (int ky = 0; ky < KY; ++ky)
@@ -80,7 +94,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
         for (int kx = 0; kx < KX; ++kx) {
             const int32_t vy = py * KY + ky, vx = px * KX + kx;
             valid[ky][kx] = vx < a.qx && vy < a.qy;
-            coff[ky][kx] = vy * a.qx + vx;
+            coffb[ky][kx] = valid[ky][kx] ? (vy * a.qx + vx) * CB : OOB;
         }
 
     for (;;) {
@@ -105,11 +119,16 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
             // the band's last scanline feeds the next wavefront (LDS) or workgroup (memory)
             const bool to_lds = wave + 1 < NW && band + 1 < a.nbands;
             const bool to_global = wave == NW - 1 && band + 1 < a.nbands;
-            const bool store_b = a.b_live || (to_global && grp == RPW - 1);
-            const int32_t* ring_in = rings + (size_t)(wave > 0 ? wave - 1 : 0) * R * QT;
-            int32_t* ring_out = rings + (size_t)wave * R * QT;
+            const bool store_a = SPLIT == 1 || !beta;
+            const bool store_b = (SPLIT == 1 || beta) && (a.b_live || (to_global && grp == RPW - 1));
+            const bool hands = grp == RPW - 1 && (SPLIT == 1 || beta);
+            const int32_t* ring_in = rings + (size_t)(wave > 0 ? wave - 1 : 0) * R * QT + l;
+            int32_t* ring_out = rings + (size_t)wave * R * QT + l;
             uint32_t seen = 0;                             // columns published by the workgroup above
-            const int32_t nsteps = W + RPW - 1;
+            // steps rounded up to whole prefetch rounds: the extra steps touch nothing (every lane
+            // is past the end of its row), and a fixed count of loads per step lets the compiler
+            // wait for exactly the slot in use instead of for every load in flight
+            const int32_t nsteps = (W + RPW - 1 + PF - 1) / PF * PF;
 
             int32_t rc[PF][KY][KX], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
             int32_t carry[KY][KX], out[KY][KX];
@@ -118,55 +137,45 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
 #pragma unroll
                 for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = out[ky][kx] = 0;
 
-            // Issue the loads of step t into one ring slot.
+            // Issue the loads of step t into one ring slot (no branch around a load).
             auto fetch = [&](const int32_t t, int32_t (&c)[KY][KX], int32_t (&ma)[KY][KX],
                              int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX]) {
-                if (from_global && t < W) {                // wave-uniform wait for the workgroup above
+                if (from_global && t < W && seen < (uint32_t)t + 1) {   // wave-uniform
                     const uint32_t need = (uint32_t)t + 1;
-                    if (seen < need) {
-                        uint32_t got = 0;
-                        if (lane == 0) {
-                            uint32_t v = 0, spins = 0;
-                            for (;;) {
-                                v = __hip_atomic_load(a.flags + super - 1, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                                if (v >= a.epoch + need) break;
-                                // give up (and let every other waiter give up) instead of hanging
-                                if (++spins > SPIN_LIMIT ||
-                                    __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                                    raise_error(a.error);
-                                    v = a.epoch + (uint32_t)W;
-                                    break;
-                                }
-                                __builtin_amdgcn_s_sleep(1);
-                            }
-                            got = v - a.epoch;
+                    uint32_t v = 0, spins = 0;
+                    for (;;) {
+                        v = __hip_atomic_load(a.flags + super - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        v = __builtin_amdgcn_readfirstlane(v);
+                        if (v >= a.epoch + need) break;
+                        // give up (and let every other waiter give up) instead of hanging
+                        if (++spins > SPIN_LIMIT ||
+                            __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            raise_error(a.error);
+                            v = a.epoch + (uint32_t)W;
+                            break;
                         }
-                        seen = __builtin_amdgcn_readfirstlane(got);
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        __builtin_amdgcn_s_sleep(1);
                     }
+                    seen = v - a.epoch;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 const int32_t i = t - grp;
                 const bool act = rowok && i >= 0 && i < W;
                 const int32_t x = a.sx > 0 ? i : W - 1 - i;
                 const int32_t xa = x + a.sx;
-                const bool ina = act && xa >= 0 && xa < W && !a.old_a_zero;
-                const bool inb = act && has_next && !a.old_b_zero;
-                const bool ing = act && from_global && grp == 0;
-                const size_t cell = (size_t)y * W + x;
-                const CT* cc = cost + cell * Q;
-                const int32_t* pa = Tma + ((size_t)y * W + xa) * QT + l;
-                const int32_t* pb = Tmb + ((size_t)yn * W + x) * QT + l;
-                const int32_t* pg = Tb + ((size_t)yp * W + x) * QT + l;
+                const int32_t offc = act ? cell_off(y * W + x, Q * CB) : OOB;
+                const int32_t offa = (act && xa >= 0 && xa < W && !a.old_a_zero) ? cell_off(y * W + xa, QT * 4) + lofs : OOB;
+                const int32_t offb = (act && has_next && !a.old_b_zero) ? cell_off(yn * W + x, QT * 4) + lofs : OOB;
+                const int32_t offg = (act && from_global && grp == 0) ? cell_off(yp * W + x, QT * 4) + lofs : OOB;
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx) {
-                        const int e = (ky * KX + kx) * G;
-                        c[ky][kx] = (act && valid[ky][kx]) ? (int32_t)cc[coff[ky][kx]] : 0;
-                        ma[ky][kx] = ina ? pa[e] : 0;
-                        mb[ky][kx] = inb ? pb[e] : 0;
-                        gb[ky][kx] = ing ? pg[e] : 0;
+                        const int e = (ky * KX + kx) * G * 4;
+                        c[ky][kx] = load_cost<CT>(rs_c, valid[ky][kx] ? offc + coffb[ky][kx] : OOB);
+                        ma[ky][kx] = load_i32(rs_ma, offa + e);
+                        mb[ky][kx] = load_i32(rs_mb, offb + e);
+                        gb[ky][kx] = load_i32(rs_b, offg + e);
                     }
             };
 
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
 #pragma unroll
                 for (int u = 0; u < PF; ++u) {
                     const int32_t s = s0 + u;
-                    if (s < nsteps) {
+                    {
                         const int32_t i = s - grp;
                         const bool act = rowok && i >= 0 && i < W;
                         const int32_t x = a.sx > 0 ? i : W - 1 - i;
@@ -188,23 +197,22 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
 #pragma unroll
                             for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = 0;
                         if (from_lds && s < W) {                 // wave-uniform
-                            const int32_t need = s + 1;
                             uint32_t spins = 0;
-                            while (lds_load(prod + wave - 1) < need) {
+                            while (lds_get(prod + wave - 1) < s + 1) {
                                 if (++spins > SPIN_LIMIT) {
                                     raise_error(a.error);
                                     break;
                                 }
                             }
-                            if (grp == 0) {
-                                const int32_t* slot = ring_in + (size_t)(s % R) * QT + l;
+                            const int32_t* slot = ring_in + (size_t)(s % R) * QT;
 #pragma unroll
-                                for (int ky = 0; ky < KY; ++ky)
+                            for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                                    for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = slot[(ky * KX + kx) * G];
-                            }
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                            if (lane == 0) lds_store(cons + wave, need);
+                                for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = slot[(ky * KX + kx) * G];
+                            // LDS operations of a wavefront complete in order: the slot is
+                            // read before the counter that frees it is written
+                            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                            lds_put(cons + wave, s + 1);
                         }
                         int32_t h[KY][KX], h2[KY][KX];
 #pragma unroll
@@ -237,47 +245,38 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                             }
                         min_search<T>(h, a.lam, a.clipd, joint, lane);
                         if constexpr (SPLIT == 1) min_search<T>(h2, a.lam, a.clipd, joint, lane);
-                        const size_t o = ((size_t)y * W + x) * QT + l;
-                        if (act) {
-#pragma unroll
-                            for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                                for (int kx = 0; kx < KX; ++kx) {
-                                    const int e = (ky * KX + kx) * G;
-                                    if constexpr (SPLIT == 1) {
-                                        Ta[o + e] = h[ky][kx];
-                                        if (store_b) Tb[o + e] = h2[ky][kx];
-                                        carry[ky][kx] = h[ky][kx];
-                                    } else {
-                                        if (!beta) Ta[o + e] = h[ky][kx];
-                                        else if (store_b) Tb[o + e] = h[ky][kx];
-                                    }
-                                }
-                        }
+                        const int32_t o = cell_off(y * W + x, QT * 4) + lofs;
+                        const int32_t oa = (act && store_a) ? o : OOB;
+                        const int32_t ob = (act && store_b) ? o : OOB;
 #pragma unroll
                         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                            for (int kx = 0; kx < KX; ++kx) out[ky][kx] = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
+                            for (int kx = 0; kx < KX; ++kx) {
+                                const int e = (ky * KX + kx) * G * 4;
+                                const int32_t tb = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
+                                store_i32(rs_a, oa + e, h[ky][kx]);
+                                store_i32(rs_b, ob + e, tb);
+                                if constexpr (SPLIT == 1) carry[ky][kx] = act ? h[ky][kx] : carry[ky][kx];
+                                out[ky][kx] = tb;
+                            }
                         // hand the band's last scanline T_b to the next wavefront / workgroup
                         const int32_t il = s - (RPW - 1);
                         if (il >= 0 && il < W) {                 // wave-uniform
                             if (to_lds) {
                                 uint32_t spins = 0;
-                                while (lds_load(cons + wave + 1) < il + 1 - R) {
+                                while (lds_get(cons + wave + 1) < il + 1 - R) {
                                     if (++spins > SPIN_LIMIT) {
                                         raise_error(a.error);
                                         break;
                                     }
                                 }
-                                if (grp == RPW - 1 && (SPLIT == 1 || beta)) {
-                                    int32_t* slot = ring_out + (size_t)(il % R) * QT + l;
+                                int32_t* dst = hands ? ring_out + (size_t)(il % R) * QT : trash + l;
 #pragma unroll
-                                    for (int ky = 0; ky < KY; ++ky)
+                                for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                                        for (int kx = 0; kx < KX; ++kx) slot[(ky * KX + kx) * G] = out[ky][kx];
-                                }
-                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                                if (lane == 0) lds_store(prod + wave, il + 1);
+                                    for (int kx = 0; kx < KX; ++kx) dst[(ky * KX + kx) * G] = out[ky][kx];
+                                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                                lds_put(prod + wave, il + 1);
                             }
                             if (to_global && (((il + 1) % a.chunk) == 0 || il == W - 1)) {
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -286,7 +285,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             }
                         }
-                        if (s + PF < nsteps) fetch(s + PF, rc[u], rma[u], rmb[u], rb[u]);
+                        fetch(s + PF, rc[u], rma[u], rmb[u], rb[u]);
                     }
                 }
             }
@@ -340,7 +339,7 @@ template <class T>
 constexpr int pass_pf() { return T::E <= 2 ? 4 : (T::E <= 4 ? 2 : 1); }
 
 size_t pass_lds_bytes(int qt, int waves, int ring) {
-    return (size_t)(2 * MAX_WAVES + 4) * 4 + (size_t)(waves > 1 ? waves - 1 : 0) * ring * qt * 4;
+    return (size_t)(2 * MAX_WAVES + 4 + qt) * 4 + (size_t)(waves > 1 ? waves - 1 : 0) * ring * qt * 4;
 }
 
 template <class T, class CT, int SPLIT>
