@@ -70,6 +70,7 @@ typedef struct {
  * zero / negative field, selects the built-in choice:
  *   tile   lane tile mapping labels to lanes (edp_tiles(); -1 automatic)
  *   chunk  EDP columns between two progress publications of a workgroup
+ *          (rounded up to a power of two)
  *   split  1: every lane runs both minimum searches of a scan step;
  *          2: the two searches run on two halves of the vertex's lanes
  *   waves  wavefronts per EDP workgroup (1..8), handing rows over in LDS

@@ -116,11 +116,14 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     if (waves > 8) return EDP_E_INVALID;
     L->split = split;
     L->waves = waves;
-    L->chunk = (tu && tu->chunk > 0) ? tu->chunk : 8;
+    // progress publication period and LDS ring depth are powers of two (masks, no division)
+    int chunk = (tu && tu->chunk > 0) ? tu->chunk : 8;
+    int c2 = 1;
+    while (c2 < chunk && c2 < 1024) c2 <<= 1;
+    L->chunk = c2;
     const int qt = qt_of(L->tile);
-    int ring = waves > 1 ? (int)((48 * 1024) / ((size_t)(waves - 1) * qt * 4)) : 1;
-    if (ring > 16) ring = 16;
-    if (ring < 2) ring = 2;
+    int ring = 16;
+    while (ring > 2 && (size_t)(waves - 1) * ring * qt * 4 > 48 * 1024) ring >>= 1;
     L->ring = ring;
     L->rpw = 64 / (split * g);
     L->nbands = (p->height + L->rpw - 1) / L->rpw;

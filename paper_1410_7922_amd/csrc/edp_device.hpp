@@ -155,95 +155,181 @@ __device__ __forceinline__ int32_t line_down(int32_t v, int32_t pos, int32_t lan
 // minimum over the NL lanes of the line
 template <int NL, int STEP>
 __device__ __forceinline__ int32_t line_min(int32_t v, int32_t lane) {
+    auto mx = [](int32_t x, int32_t y) { return imin(x, y); };
     if constexpr (NL == 1) {
         return v;
     } else if constexpr (NL * STEP < 16) {
         static_assert(STEP == 1, "short lines must run along x");
-        v = imin(v, dpp<DPP_QUAD_XOR1>(v, v));
-        if constexpr (NL >= 4) v = imin(v, dpp<DPP_QUAD_XOR2>(v, v));
-        if constexpr (NL >= 8) v = imin(v, dpp<DPP_HALF_MIRROR>(v, v));
+        v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, DPP_QUAD_XOR1, 0xF, 0xF, false));
+        if constexpr (NL >= 4) v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, DPP_QUAD_XOR2, 0xF, 0xF, false));
+        if constexpr (NL >= 8) v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, DPP_HALF_MIRROR, 0xF, 0xF, false));
         return v;
     } else {
         // inside a row the line's lanes form a coset of the rotation by STEP
         if constexpr (STEP == 1) {
-            v = imin(v, dpp<DPP_QUAD_XOR1>(v, v));
-            v = imin(v, dpp<DPP_QUAD_XOR2>(v, v));
-            v = imin(v, dpp<DPP_HALF_MIRROR>(v, v));
-            v = imin(v, dpp<DPP_ROW_MIRROR>(v, v));
+            v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, DPP_QUAD_XOR1, 0xF, 0xF, false));
+            v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, DPP_QUAD_XOR2, 0xF, 0xF, false));
+            v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, DPP_HALF_MIRROR, 0xF, 0xF, false));
+            v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, DPP_ROW_MIRROR, 0xF, 0xF, false));
         } else {
-            if constexpr (STEP <= 1) v = imin(v, dpp<dpp_row_ror(1)>(v, v));
-            if constexpr (STEP <= 2) v = imin(v, dpp<dpp_row_ror(2)>(v, v));
-            if constexpr (STEP <= 4) v = imin(v, dpp<dpp_row_ror(4)>(v, v));
-            if constexpr (STEP <= 8) v = imin(v, dpp<dpp_row_ror(8)>(v, v));
+            if constexpr (STEP <= 2) v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, dpp_row_ror(2), 0xF, 0xF, false));
+            if constexpr (STEP <= 4) v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, dpp_row_ror(4), 0xF, 0xF, false));
+            if constexpr (STEP <= 8) v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, dpp_row_ror(8), 0xF, 0xF, false));
         }
-        if constexpr (NL * STEP >= 32) v = imin(v, lanes_xor<16>(v, lane));
-        if constexpr (NL * STEP >= 64) v = imin(v, lanes_xor<32>(v, lane));
+        if constexpr (NL * STEP >= 32) v = mx(v, lanes_xor<16>(v, lane));
+        if constexpr (NL * STEP >= 64) v = mx(v, lanes_xor<32>(v, lane));
         return v;
+    }
+}
+
+// ---- fused min-scans ---------------------------------------------------------
+// dpp<...>(IDENT, v) reads IDENT where the source lane lies outside the row or
+// outside the enabled banks; min(x, that) then compiles to one v_min_i32_dpp.
+constexpr int32_t IDENT = 0x7FFFFFFF;
+constexpr int DPP_QP_SHR1 = 0x90;        // quad_perm [0,0,1,2]: lane i <- i-1 (lane 0 <- 0)
+constexpr int DPP_QP_SHR2 = 0x44;        // quad_perm [0,1,0,1]: lane i <- i-2 (lanes 0,1 <- self)
+constexpr int DPP_QP_SHL1 = 0xF9;        // quad_perm [1,2,3,3]: lane i <- i+1 (lane 3 <- 3)
+constexpr int DPP_QP_SHL2 = 0xEE;        // quad_perm [2,3,2,3]: lane i <- i+2 (lanes 2,3 <- self)
+constexpr int DPP_QP_BC3 = 0xFF;         // quad_perm [3,3,3,3]
+constexpr int DPP_QP_BC0 = 0x00;         // quad_perm [0,0,0,0]
+constexpr int DPP_QP_PAIR_SHR = 0xA0;    // quad_perm [0,0,2,2]: odd lanes <- even neighbour
+constexpr int DPP_QP_PAIR_SHL = 0xF5;    // quad_perm [1,1,3,3]: even lanes <- odd neighbour
+
+template <int CTRL, int BANKS = 0xF>
+__device__ __forceinline__ int32_t minx(int32_t x, int32_t src) {
+    return imin(x, __builtin_amdgcn_update_dpp(IDENT, src, CTRL, 0xF, BANKS, false));
+}
+
+// Inclusive prefix minimum along the line (positions 0..pos).
+template <int NL, int STEP>
+__device__ __forceinline__ int32_t scan_up(int32_t v, int32_t pos, int32_t lane) {
+    if constexpr (NL == 1) {
+        return v;
+    } else if constexpr (STEP == 1 && NL == 2) {
+        return minx<DPP_QP_PAIR_SHR>(v, v);
+    } else if constexpr (STEP == 1 && NL == 4) {
+        v = minx<DPP_QP_SHR1>(v, v);
+        return minx<DPP_QP_SHR2>(v, v);
+    } else if constexpr (STEP == 1 && NL == 8) {
+        v = minx<DPP_QP_SHR1>(v, v);
+        v = minx<DPP_QP_SHR2>(v, v);
+        const int32_t t = dpp<DPP_QP_BC3>(v, v);          // quad totals
+        return minx<dpp_row_shr(4), 0xA>(v, t);          // banks 1, 3 take the quad below
+    } else if constexpr (NL * STEP == 16) {
+        if constexpr (NL > 1) v = minx<dpp_row_shr(STEP)>(v, v);
+        if constexpr (NL > 2) v = minx<dpp_row_shr(2 * STEP)>(v, v);
+        if constexpr (NL > 4) v = minx<dpp_row_shr(4 * STEP)>(v, v);
+        if constexpr (NL > 8) v = minx<dpp_row_shr(8 * STEP)>(v, v);
+        return v;
+    } else {
+        // the line crosses 16-lane rows
+        if constexpr (NL > 1) v = imin(v, line_up<NL, STEP, 1>(v, pos, lane));
+        if constexpr (NL > 2) v = imin(v, line_up<NL, STEP, 2>(v, pos, lane));
+        if constexpr (NL > 4) v = imin(v, line_up<NL, STEP, 4>(v, pos, lane));
+        if constexpr (NL > 8) v = imin(v, line_up<NL, STEP, 8>(v, pos, lane));
+        if constexpr (NL > 16) v = imin(v, line_up<NL, STEP, 16>(v, pos, lane));
+        if constexpr (NL > 32) v = imin(v, line_up<NL, STEP, 32>(v, pos, lane));
+        return v;
+    }
+}
+
+// Inclusive suffix minimum along the line (positions pos..NL-1).
+template <int NL, int STEP>
+__device__ __forceinline__ int32_t scan_down(int32_t v, int32_t pos, int32_t lane) {
+    if constexpr (NL == 1) {
+        return v;
+    } else if constexpr (STEP == 1 && NL == 2) {
+        return minx<DPP_QP_PAIR_SHL>(v, v);
+    } else if constexpr (STEP == 1 && NL == 4) {
+        v = minx<DPP_QP_SHL1>(v, v);
+        return minx<DPP_QP_SHL2>(v, v);
+    } else if constexpr (STEP == 1 && NL == 8) {
+        v = minx<DPP_QP_SHL1>(v, v);
+        v = minx<DPP_QP_SHL2>(v, v);
+        const int32_t t = dpp<DPP_QP_BC0>(v, v);          // quad totals (from the top)
+        return minx<dpp_row_shl(4), 0x5>(v, t);          // banks 0, 2 take the quad above
+    } else if constexpr (NL * STEP == 16) {
+        if constexpr (NL > 1) v = minx<dpp_row_shl(STEP)>(v, v);
+        if constexpr (NL > 2) v = minx<dpp_row_shl(2 * STEP)>(v, v);
+        if constexpr (NL > 4) v = minx<dpp_row_shl(4 * STEP)>(v, v);
+        if constexpr (NL > 8) v = minx<dpp_row_shl(8 * STEP)>(v, v);
+        return v;
+    } else {
+        if constexpr (NL > 1) v = imin(v, line_down<NL, STEP, 1>(v, pos, lane));
+        if constexpr (NL > 2) v = imin(v, line_down<NL, STEP, 2>(v, pos, lane));
+        if constexpr (NL > 4) v = imin(v, line_down<NL, STEP, 4>(v, pos, lane));
+        if constexpr (NL > 8) v = imin(v, line_down<NL, STEP, 8>(v, pos, lane));
+        if constexpr (NL > 16) v = imin(v, line_down<NL, STEP, 16>(v, pos, lane));
+        if constexpr (NL > 32) v = imin(v, line_down<NL, STEP, 32>(v, pos, lane));
+        return v;
+    }
+}
+
+// Value at position pos - 1 of the line, IDENT at position 0.
+template <int NL, int STEP>
+__device__ __forceinline__ int32_t carry_up(int32_t v, int32_t pos, int32_t lane) {
+    if constexpr (NL * STEP == 16) {
+        return __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shr(STEP), 0xF, 0xF, false);
+    } else if constexpr (NL * STEP < 16) {
+        const int32_t r = __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shr(STEP), 0xF, 0xF, false);
+        return pos == 0 ? IDENT : r;
+    } else {
+        const int32_t r = lanes_up<STEP>(v, lane);
+        return pos == 0 ? IDENT : r;
+    }
+}
+// Value at position pos + 1 of the line, IDENT at position NL - 1.
+template <int NL, int STEP>
+__device__ __forceinline__ int32_t carry_down(int32_t v, int32_t pos, int32_t lane) {
+    if constexpr (NL * STEP == 16) {
+        return __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shl(STEP), 0xF, 0xF, false);
+    } else if constexpr (NL * STEP < 16) {
+        const int32_t r = __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shl(STEP), 0xF, 0xF, false);
+        return pos == NL - 1 ? IDENT : r;
+    } else {
+        const int32_t r = lanes_down<STEP>(v, lane);
+        return pos == NL - 1 ? IDENT : r;
     }
 }
 
 // ---- linear RMS on one dimension -------------------------------------------
 // For every line along the dimension: the L1 distance transform
 //   L(v) = min_v' h(v') + lam |v - v'|
-// as the forward pass of eq. L_dec3 and the backward pass of eq. L_dec5, then
-// the clip min(L, line_min + clipd) when clip is set (per-dimension
-// truncation).  Lines are split over NL lanes, K labels per lane.
-// Returns the minimum of the input line.
+// i.e. the forward pass of eq. L_dec3 and the backward pass of eq. L_dec5,
+// then the clip min(L, line_min + clipd) when clip is set (per-dimension
+// truncation).  Lines are split over NL lanes, K labels per lane.  The passes
+// run on g(v) = h(v) - lam v (forward) and h(v) + lam v (backward), where the
+// recursions become plain prefix / suffix minima:
+//   min_{v' <= v} h(v') + lam (v - v') = lam v + min_{v' <= v} g(v').
+// lv[k] = lam * (index of label k along the line).  Returns min h of the line.
 template <int NL, int K, int STEP>
-__device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t lam, const int32_t clipd,
+__device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t (&lv)[K], const int32_t clipd,
                                            const bool clip, const int32_t pos, const int32_t lane) {
-    int32_t f[K], b[K];
-    f[0] = val[0];
+    int32_t p[K], q[K];
+    p[0] = val[0] - lv[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) f[k] = imin(val[k], f[k - 1] + lam);
-    b[K - 1] = val[K - 1];
+    for (int k = 1; k < K; ++k) p[k] = imin(p[k - 1], val[k] - lv[k]);
+    q[K - 1] = val[K - 1] + lv[K - 1];
 #pragma unroll
-    for (int k = K - 2; k >= 0; --k) b[k] = imin(val[k], b[k + 1] + lam);
+    for (int k = K - 2; k >= 0; --k) q[k] = imin(q[k + 1], val[k] + lv[k]);
     int32_t m = val[0];
 #pragma unroll
     for (int k = 1; k < K; ++k) m = imin(m, val[k]);
-    int32_t cf = PADV, cb = PADV;
     if constexpr (NL > 1) {
-        int32_t tf = f[K - 1];      // forward value at this lane's last label
-        int32_t tb = b[0];          // backward value at this lane's first label
-        // inclusive scans along the line: each lane hop adds lam * K per lane of distance
-        if constexpr (NL > 1) {
-            tf = imin(tf, line_up<NL, STEP, 1>(tf, pos, lane) + lam * K);
-            tb = imin(tb, line_down<NL, STEP, 1>(tb, pos, lane) + lam * K);
-        }
-        if constexpr (NL > 2) {
-            tf = imin(tf, line_up<NL, STEP, 2>(tf, pos, lane) + lam * (2 * K));
-            tb = imin(tb, line_down<NL, STEP, 2>(tb, pos, lane) + lam * (2 * K));
-        }
-        if constexpr (NL > 4) {
-            tf = imin(tf, line_up<NL, STEP, 4>(tf, pos, lane) + lam * (4 * K));
-            tb = imin(tb, line_down<NL, STEP, 4>(tb, pos, lane) + lam * (4 * K));
-        }
-        if constexpr (NL > 8) {
-            tf = imin(tf, line_up<NL, STEP, 8>(tf, pos, lane) + lam * (8 * K));
-            tb = imin(tb, line_down<NL, STEP, 8>(tb, pos, lane) + lam * (8 * K));
-        }
-        if constexpr (NL > 16) {
-            tf = imin(tf, line_up<NL, STEP, 16>(tf, pos, lane) + lam * (16 * K));
-            tb = imin(tb, line_down<NL, STEP, 16>(tb, pos, lane) + lam * (16 * K));
-        }
-        if constexpr (NL > 32) {
-            tf = imin(tf, line_up<NL, STEP, 32>(tf, pos, lane) + lam * (32 * K));
-            tb = imin(tb, line_down<NL, STEP, 32>(tb, pos, lane) + lam * (32 * K));
-        }
-        // carries from the neighbouring lanes (their last / first label)
-        cf = line_up<NL, STEP, 1>(tf, pos, lane);
-        cb = line_down<NL, STEP, 1>(tb, pos, lane);
-        if (pos == 0) cf = PADV;
-        if (pos == NL - 1) cb = PADV;
+        const int32_t tf = scan_up<NL, STEP>(p[K - 1], pos, lane);
+        const int32_t tb = scan_down<NL, STEP>(q[0], pos, lane);
+        const int32_t cf = carry_up<NL, STEP>(tf, pos, lane);
+        const int32_t cb = carry_down<NL, STEP>(tb, pos, lane);
         m = line_min<NL, STEP>(m, lane);
-    }
-    const int32_t cap = clip ? m + clipd : PADV;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int32_t x = imin3(cf + lam * (k + 1), cb + lam * (K - k), cap);
-        val[k] = imin3(f[k], b[k], x);
+        for (int k = 0; k < K; ++k) {
+            p[k] = imin(p[k], cf);
+            q[k] = imin(q[k], cb);
+        }
     }
+    const int32_t cap = clip ? m + clipd : IDENT;
+#pragma unroll
+    for (int k = 0; k < K; ++k) val[k] = imin3(p[k] + lv[k], q[k] - lv[k], cap);
     return m;
 }
 
@@ -255,6 +341,20 @@ __device__ __forceinline__ int32_t group_min(int32_t v, const int32_t lane) {
     return v;
 }
 
+// Distance offsets of the lane's labels along x and y: lam * vx and lam * vy.
+template <class T>
+struct LineIndex {
+    int32_t lx[T::KX], ly[T::KY];
+    __device__ __forceinline__ LineIndex(const int32_t lam, const int32_t lane) {
+        const int32_t l = lane % T::G;
+        const int32_t px = l % T::PX, py = l / T::PX;
+#pragma unroll
+        for (int k = 0; k < T::KX; ++k) lx[k] = lam * (px * T::KX + k);
+#pragma unroll
+        for (int k = 0; k < T::KY; ++k) ly[k] = lam * (py * T::KY + k);
+    }
+};
+
 // The minimum search operator M (Sec. 2 eq. M_strf) for the truncated linear
 // prior, computed by the linear RMS of Sec. 3.2:
 //   joint == false (per-dimension truncation): each label dimension r gets the
@@ -265,20 +365,19 @@ __device__ __forceinline__ int32_t group_min(int32_t v, const int32_t lane) {
 // h holds the lane's KY x KX labels; padding labels must hold PADV on entry.
 // Returns min h over the whole vertex (the group).
 template <class T>
-__device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const int32_t lam,
-                                              const int32_t clipd, const bool joint,
-                                              const int32_t lane) {
+__device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const LineIndex<T>& li,
+                                              const int32_t clipd, const bool joint, const int32_t lane) {
     const int32_t l = lane % T::G;
     const int32_t px = l % T::PX, py = l / T::PX;
-    const bool one_dim = T::PY * T::KY == 1;
+    constexpr bool one_dim = T::PY * T::KY == 1;
     int32_t rowmin = PADV;
 #pragma unroll
     for (int ky = 0; ky < T::KY; ++ky) {
         // with a single label dimension the final clip is the per-line clip
-        const int32_t lm = l1_line<T::PX, T::KX, 1>(h[ky], lam, clipd, !joint || one_dim, px, lane);
+        const int32_t lm = l1_line<T::PX, T::KX, 1>(h[ky], li.lx, clipd, !joint || one_dim, px, lane);
         rowmin = imin(rowmin, lm);
     }
-    if constexpr (T::PY * T::KY == 1) {
+    if constexpr (one_dim) {
         return rowmin;
     } else {
         int32_t gmin = rowmin;
@@ -288,7 +387,7 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
             int32_t col[T::KY];
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
-            l1_line<T::PY, T::KY, T::PX>(col, lam, clipd, !joint, py, lane);
+            l1_line<T::PY, T::KY, T::PX>(col, li.ly, clipd, !joint, py, lane);
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
         }

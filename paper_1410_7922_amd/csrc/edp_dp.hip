@@ -34,13 +34,14 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     const int32_t grp = lane / G, l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
     const int32_t W = a.W, H = a.H, Q = a.qx * a.qy;
-    const int32_t wave = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     if (wave * RPW >= H) return;                       // whole wavefront past the last row
     const int32_t y = wave * RPW + grp;
     const bool rowok = y < H;
     const int32_t ib = a.ibits;
     const int32_t mask = (1 << ib) - 1;
     const int32_t lamk = a.lam << ib, clipk = a.clipd << ib;
+    const LineIndex<T> li(lamk, lane);
     // buffer resources (see the scan kernel): lanes without an operand use offset OOB
     const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(a.cost, W * H * Q * CB);
     const __amdgpu_buffer_rsrc_t rs_p = make_rsrc(a.ptr, W * H * QT * (int32_t)sizeof(PT));
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
         for (int u = 0; u < PF; ++u) {
             const int32_t x = x0 + u;
             const bool live = x < W;
-            const int32_t g = min_search<T>(key, lamk, clipk, a.joint != 0, lane);
+            const int32_t g = min_search<T>(key, li, clipk, a.joint != 0, lane);
             const int32_t norm = g >> ib;
             uint32_t packed = 0;
 #pragma unroll

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     int32_t* rings = trash + QT;                   // [NW-1][ring][QT]
 
     const int32_t lane = lane_id();
-    const int32_t wave = (int32_t)(threadIdx.x >> 6);
+    // wavefront-uniform values live in scalar registers, so control flow on them is scalar
+    const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     const int32_t NW = (int32_t)(blockDim.x >> 6);
     const int32_t grp = lane / CL;
     const bool beta = SPLIT == 2 && ((lane / G) & 1);
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     const int32_t px = l % T::PX, py = l / T::PX;
     const int32_t W = a.W, H = a.H, Q = a.qx * a.qy, R = a.ring;
     const bool joint = a.joint != 0;
+    const LineIndex<T> li(a.lam, lane);
     // Buffer resources: a lane whose operand does not exist uses offset OOB, so
     // its load returns 0 and its store is dropped, with no branch around it.
     const int32_t tbytes = W * H * QT * 4;         // below 2^31 (checked by the host)
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
         if (threadIdx.x == 0) misc[0] = (int32_t)atomicAdd(a.ticket, 1u);
         if (threadIdx.x < 2 * MAX_WAVES) lds[threadIdx.x] = 0;
         __syncthreads();
-        const int32_t super = misc[0];
+        const int32_t super = __builtin_amdgcn_readfirstlane(misc[0]);
         __syncthreads();
         if (super >= a.nsuper) break;
         const int32_t band = super * NW + wave;
@@ -143,6 +145,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 if (from_global && t < W && seen < (uint32_t)t + 1) {   // wave-uniform
                     const uint32_t need = (uint32_t)t + 1;
                     uint32_t v = 0, spins = 0;
+#pragma nounroll
                     for (;;) {
                         v = __hip_atomic_load(a.flags + super - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         v = __builtin_amdgcn_readfirstlane(v);
@@ -198,13 +201,14 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                             for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = 0;
                         if (from_lds && s < W) {                 // wave-uniform
                             uint32_t spins = 0;
+#pragma nounroll
                             while (lds_get(prod + wave - 1) < s + 1) {
                                 if (++spins > SPIN_LIMIT) {
                                     raise_error(a.error);
                                     break;
                                 }
                             }
-                            const int32_t* slot = ring_in + (size_t)(s % R) * QT;
+                            const int32_t* slot = ring_in + (size_t)(s & (R - 1)) * QT;
 #pragma unroll
                             for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
@@ -243,8 +247,8 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                     h[ky][kx] = valid[ky][kx] ? ((A + (beta ? -d : d)) >> 1) : PADV;
                                 }
                             }
-                        min_search<T>(h, a.lam, a.clipd, joint, lane);
-                        if constexpr (SPLIT == 1) min_search<T>(h2, a.lam, a.clipd, joint, lane);
+                        min_search<T>(h, li, a.clipd, joint, lane);
+                        if constexpr (SPLIT == 1) min_search<T>(h2, li, a.clipd, joint, lane);
                         const int32_t o = cell_off(y * W + x, QT * 4) + lofs;
                         const int32_t oa = (act && store_a) ? o : OOB;
                         const int32_t ob = (act && store_b) ? o : OOB;
@@ -264,13 +268,14 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                         if (il >= 0 && il < W) {                 // wave-uniform
                             if (to_lds) {
                                 uint32_t spins = 0;
+#pragma nounroll
                                 while (lds_get(cons + wave + 1) < il + 1 - R) {
                                     if (++spins > SPIN_LIMIT) {
                                         raise_error(a.error);
                                         break;
                                     }
                                 }
-                                int32_t* dst = hands ? ring_out + (size_t)(il % R) * QT : trash + l;
+                                int32_t* dst = hands ? ring_out + (size_t)(il & (R - 1)) * QT : trash + l;
 #pragma unroll
                                 for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                                 lds_put(prod + wave, il + 1);
                             }
-                            if (to_global && (((il + 1) % a.chunk) == 0 || il == W - 1)) {
+                            if (to_global && (((il + 1) & (a.chunk - 1)) == 0 || il == W - 1)) {
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                                 if (lane == 0)
                                     __hip_atomic_store(a.flags + super, a.epoch + (uint32_t)(il + 1),
