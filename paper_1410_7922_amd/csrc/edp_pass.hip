@@ -127,6 +127,15 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
             const int32_t* ring_in = rings + (size_t)(wave > 0 ? wave - 1 : 0) * R * QT + l;
             int32_t* ring_out = rings + (size_t)wave * R * QT + l;
             uint32_t seen = 0;                             // columns published by the workgroup above
+            // byte offsets at step 0 (column -grp) and per-step strides: at step t the lane's
+            // vertex is x = x0 + sx (t - grp) of row y
+            const int32_t x0 = (a.sx > 0 ? 0 : W - 1) - a.sx * grp;
+            const int32_t dc = a.sx * Q * CB, dt = a.sx * QT * 4;
+            const int32_t bc = cell_off(y * W + x0, Q * CB);
+            const int32_t bt = cell_off(y * W + x0, QT * 4) + lofs;
+            const int32_t ba = bt + dt;                    // (x + sx, y)
+            const int32_t bb = cell_off(yn * W + x0, QT * 4) + lofs;
+            const int32_t bg = cell_off(yp * W + x0, QT * 4) + lofs;
             // steps rounded up to whole prefetch rounds: the extra steps touch nothing (every lane
             // is past the end of its row), and a fixed count of loads per step lets the compiler
             // wait for exactly the slot in use instead of for every load in flight
@@ -162,14 +171,14 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                     seen = v - a.epoch;
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
-                const int32_t i = t - grp;
-                const bool act = rowok && i >= 0 && i < W;
-                const int32_t x = a.sx > 0 ? i : W - 1 - i;
-                const int32_t xa = x + a.sx;
-                const int32_t offc = act ? cell_off(y * W + x, Q * CB) : OOB;
-                const int32_t offa = (act && xa >= 0 && xa < W && !a.old_a_zero) ? cell_off(y * W + xa, QT * 4) + lofs : OOB;
-                const int32_t offb = (act && has_next && !a.old_b_zero) ? cell_off(yn * W + x, QT * 4) + lofs : OOB;
-                const int32_t offg = (act && from_global && grp == 0) ? cell_off(yp * W + x, QT * 4) + lofs : OOB;
+                // column i = t - grp of this lane's scanline; offsets move by a fixed stride per step
+                const uint32_t i = (uint32_t)(t - grp);
+                const bool act = rowok && i < (uint32_t)W;
+                const bool nxt = i + 1 < (uint32_t)W;     // the next column in scan order exists
+                const int32_t offc = act ? bc + t * dc : OOB;
+                const int32_t offa = (act && nxt && !a.old_a_zero) ? ba + t * dt : OOB;
+                const int32_t offb = (act && has_next && !a.old_b_zero) ? bb + t * dt : OOB;
+                const int32_t offg = (act && from_global && grp == 0) ? bg + t * dt : OOB;
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
@@ -191,8 +200,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                     const int32_t s = s0 + u;
                     {
                         const int32_t i = s - grp;
-                        const bool act = rowok && i >= 0 && i < W;
-                        const int32_t x = a.sx > 0 ? i : W - 1 - i;
+                        const bool act = rowok && (uint32_t)i < (uint32_t)W;
                         // T_b of the row above at this column, for group 0 of an inner wavefront
                         int32_t lb[KY][KX];
 #pragma unroll
@@ -249,7 +257,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                             }
                         min_search<T>(h, li, a.clipd, joint, lane);
                         if constexpr (SPLIT == 1) min_search<T>(h2, li, a.clipd, joint, lane);
-                        const int32_t o = cell_off(y * W + x, QT * 4) + lofs;
+                        const int32_t o = bt + s * dt;
                         const int32_t oa = (act && store_a) ? o : OOB;
                         const int32_t ob = (act && store_b) ? o : OOB;
 #pragma unroll
