@@ -342,7 +342,13 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     a.nbands = la.nbands;
     a.nsuper = la.nsuper;
     a.ring = la.ring;
-    const int cap = pass_capacity(tile, prob->dtype, la.split, la.waves, pass_lds_bytes(qt_of(tile), la.waves, la.ring));
+    // cost kind of the scan kernel: int16 costs load in dword pairs when every lane's run of
+    // labels starts on a 4-byte boundary
+    int kind = prob->dtype == EDP_I16 ? 1 : 2;
+    if (kind == 1 && kTiles[tile].kx % 2 == 0 && (prob->qx * prob->qy) % 2 == 0 &&
+        (prob->qy == 1 || prob->qx % 2 == 0) && ((uintptr_t)d_cost % 4) == 0)
+        kind = 3;
+    const int cap = pass_capacity(tile, kind, la.split, la.waves, pass_lds_bytes(qt_of(tile), la.waves, la.ring));
     const int grid = a.nsuper < cap ? a.nsuper : cap;
     // scans P1..P4: (sx, sy) and the arrays they write (0 +x, 1 -x, 2 +y, 3 -y)
     const int sx[4] = {1, -1, 1, -1}, sy[4] = {1, 1, -1, -1};
@@ -363,7 +369,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
             const bool timed = tuning && tuning->events && 2 * pass_index + 1 < tuning->n_events;
             if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index], s) != hipSuccess)
                 return EDP_E_HIP;
-            err = launch_edp_pass(tile, prob->dtype, la.split, a, grid, la.waves, s);
+            err = launch_edp_pass(tile, kind, la.split, a, grid, la.waves, s);
             if (err != hipSuccess) return EDP_E_HIP;
             if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index + 1], s) != hipSuccess)
                 return EDP_E_HIP;

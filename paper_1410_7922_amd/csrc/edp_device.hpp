@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace edp {
 
 // Value held by labels outside the label space.  It stays above every real
@@ -55,6 +57,66 @@ template <class CT>
 __device__ __forceinline__ int32_t load_cost(__amdgpu_buffer_rsrc_t r, int32_t off) {
     if constexpr (sizeof(CT) == 2) return (int32_t)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
     else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+// N consecutive int32 at byte offset off (dword aligned), widest loads first.
+template <int N>
+__device__ __forceinline__ void load_vec(__amdgpu_buffer_rsrc_t r, int32_t off, int32_t* dst) {
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < N; k += 4) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off + 4 * k, 0, 0);
+            dst[k] = (int32_t)v[0]; dst[k + 1] = (int32_t)v[1]; dst[k + 2] = (int32_t)v[2]; dst[k + 3] = (int32_t)v[3];
+        }
+    } else if constexpr (N == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        dst[0] = (int32_t)v[0]; dst[1] = (int32_t)v[1];
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) dst[k] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4 * k, 0, 0);
+    }
+}
+template <int N>
+__device__ __forceinline__ void store_vec(__amdgpu_buffer_rsrc_t r, int32_t off, const int32_t* src) {
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < N; k += 4) {
+            const uint32_t __attribute__((ext_vector_type(4))) v = {(uint32_t)src[k], (uint32_t)src[k + 1],
+                                                                    (uint32_t)src[k + 2], (uint32_t)src[k + 3]};
+            __builtin_amdgcn_raw_buffer_store_b128(v, r, off + 4 * k, 0, 0);
+        }
+    } else if constexpr (N == 2) {
+        const uint32_t __attribute__((ext_vector_type(2))) v = {(uint32_t)src[0], (uint32_t)src[1]};
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) __builtin_amdgcn_raw_buffer_store_b32((uint32_t)src[k], r, off + 4 * k, 0, 0);
+    }
+}
+
+// Cost element kinds: int16 one by one, int16 in aligned pairs, int32 in runs.
+struct Pair16 {};
+template <class CK> struct CostBytes { static constexpr int value = sizeof(CK); };
+template <> struct CostBytes<Pair16> { static constexpr int value = 2; };
+
+// N consecutive costs starting at byte offset off; OOB offsets give zeros.
+template <class CK, int N>
+__device__ __forceinline__ void load_cost_run(__amdgpu_buffer_rsrc_t r, int32_t off, int32_t* dst) {
+    if constexpr (sizeof(CK) == 4) {
+        load_vec<N>(r, off, dst);
+    } else if constexpr (std::is_same<CK, Pair16>::value && N % 2 == 0) {
+        int32_t w[N / 2];
+        load_vec<N / 2>(r, off, w);
+#pragma unroll
+        for (int k = 0; k < N / 2; ++k) {
+            dst[2 * k] = (int32_t)(int16_t)(w[k] & 0xFFFF);
+            dst[2 * k + 1] = w[k] >> 16;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            dst[k] = (int32_t)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off + 2 * k, 0, 0);
+    }
 }
 // ---- DPP (GFX9 encodings) --------------------------------------------------
 constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]

@@ -95,7 +95,10 @@ struct EnergyArgs {
 };
 
 // Launchers (return hipSuccess or the launch error).  dtype: 1 int16, 2 int32.
-hipError_t launch_edp_pass(int tile, int dtype, int split, const PassArgs& a, int grid, int waves,
+// The scan kernel takes a cost kind instead: 1 int16, 2 int32, 3 int16 read in
+// 4-byte aligned pairs (needs an even KX, an even label count, and qx even
+// unless qy == 1).
+hipError_t launch_edp_pass(int tile, int kind, int split, const PassArgs& a, int grid, int waves,
                            hipStream_t s);
 hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
 hipError_t launch_dp_forward(int tile, int dtype, const DpArgs& a, int grid, hipStream_t s);
@@ -106,7 +109,7 @@ hipError_t launch_sum_rows(const int64_t* rows, int32_t n, int64_t* out, hipStre
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStream_t s);
 
 // Resident workgroups of the pass kernel (occupancy x CUs) for a launch shape.
-int pass_capacity(int tile, int dtype, int split, int waves, size_t lds_bytes);
+int pass_capacity(int tile, int kind, int split, int waves, size_t lds_bytes);
 // LDS bytes of the pass kernel for a tile, wavefronts per workgroup and ring slots.
 size_t pass_lds_bytes(int qt, int waves, int ring);
 

@@ -53,12 +53,12 @@ __device__ __forceinline__ void raise_error(uint32_t* error) {
     __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class T, class CT, int SPLIT, int PF>
+template <class T, class CK, int SPLIT, int PF>
 __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs a) {
-    constexpr int G = T::G, KX = T::KX, KY = T::KY, QT = T::QT;
+    constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int CL = SPLIT * G;                  // lanes per vertex
     constexpr int RPW = 64 / CL;                   // scanlines per wavefront
-    constexpr int CB = (int)sizeof(CT);
+    constexpr int CB = CostBytes<CK>::value;
     static_assert(CL <= 64, "vertex wider than a wavefront");
     extern __shared__ int32_t lds[];
     int32_t* prod = lds;                           // [MAX_WAVES] columns handed to the next wavefront
@@ -86,18 +86,18 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     const __amdgpu_buffer_rsrc_t rs_b = make_rsrc(a.t[a.kb], tbytes);
     const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(a.t[a.ka ^ 1], tbytes);
     const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(a.t[a.kb ^ 1], tbytes);
-    const int32_t lofs = l * 4;                    // this lane's first element inside a vertex
+    // T arrays are lane-major inside a vertex: the lane's E labels are contiguous
+    const int32_t lofs = l * E * 4;
 
-    int32_t coffb[KY][KX];                         // cost byte offset of each label, OOB for padding
+    int32_t crun[KY];                              // cost byte offset of the lane's run of KX labels per ky
     bool valid[KY][KX];
 #pragma unroll
-    for (int ky = 0; ky < KY; ++ky)
+    for (int ky = 0; ky < KY; ++ky) {
+        const int32_t vy = py * KY + ky;
+        crun[ky] = (vy < a.qy && px * KX < a.qx) ? (vy * a.qx + px * KX) * CB : OOB;
 #pragma unroll
-        for (int kx = 0; kx < KX; ++kx) {
-            const int32_t vy = py * KY + ky, vx = px * KX + kx;
-            valid[ky][kx] = vx < a.qx && vy < a.qy;
-            coffb[ky][kx] = valid[ky][kx] ? (vy * a.qx + vx) * CB : OOB;
-        }
+        for (int kx = 0; kx < KX; ++kx) valid[ky][kx] = px * KX + kx < a.qx && vy < a.qy;
+    }
 
     for (;;) {
         if (threadIdx.x == 0) misc[0] = (int32_t)atomicAdd(a.ticket, 1u);
@@ -180,15 +180,10 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 const int32_t offb = (act && has_next && !a.old_b_zero) ? bb + t * dt : OOB;
                 const int32_t offg = (act && from_global && grp == 0) ? bg + t * dt : OOB;
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                    for (int kx = 0; kx < KX; ++kx) {
-                        const int e = (ky * KX + kx) * G * 4;
-                        c[ky][kx] = load_cost<CT>(rs_c, valid[ky][kx] ? offc + coffb[ky][kx] : OOB);
-                        ma[ky][kx] = load_i32(rs_ma, offa + e);
-                        mb[ky][kx] = load_i32(rs_mb, offb + e);
-                        gb[ky][kx] = load_i32(rs_b, offg + e);
-                    }
+                for (int ky = 0; ky < KY; ++ky) load_cost_run<CK, KX>(rs_c, offc + crun[ky], c[ky]);
+                load_vec<E>(rs_ma, offa, &ma[0][0]);
+                load_vec<E>(rs_mb, offb, &mb[0][0]);
+                load_vec<E>(rs_b, offg, &gb[0][0]);
             };
 
 #pragma unroll
@@ -260,17 +255,17 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                         const int32_t o = bt + s * dt;
                         const int32_t oa = (act && store_a) ? o : OOB;
                         const int32_t ob = (act && store_b) ? o : OOB;
+                        int32_t tbv[KY][KX];
 #pragma unroll
                         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
                             for (int kx = 0; kx < KX; ++kx) {
-                                const int e = (ky * KX + kx) * G * 4;
-                                const int32_t tb = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
-                                store_i32(rs_a, oa + e, h[ky][kx]);
-                                store_i32(rs_b, ob + e, tb);
+                                tbv[ky][kx] = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
                                 if constexpr (SPLIT == 1) carry[ky][kx] = act ? h[ky][kx] : carry[ky][kx];
-                                out[ky][kx] = tb;
+                                out[ky][kx] = tbv[ky][kx];
                             }
+                        store_vec<E>(rs_a, oa, &h[0][0]);
+                        store_vec<E>(rs_b, ob, &tbv[0][0]);
                         // hand the band's last scanline T_b to the next wavefront / workgroup
                         const int32_t il = s - (RPW - 1);
                         if (il >= 0 && il < W) {                 // wave-uniform
@@ -331,7 +326,7 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
                 const int32_t vy = py * KY + ky, vx = px * KX + kx;
                 if (ok && vx < a.qx && vy < a.qy) {
                     const int32_t q = vy * a.qx + vx;
-                    const int e = (ky * KX + kx) * G + l;
+                    const int e = l * T::E + ky * KX + kx;
                     int32_t v = (int32_t)cost[(size_t)cell * Q + q];
                     if (x > 0) v += a.t[0][(size_t)(cell - 1) * QT + e];
                     if (x + 1 < W) v += a.t[1][(size_t)(cell + 1) * QT + e];
@@ -347,18 +342,19 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     }
 }
 
-// Prefetch depth by labels per lane: more labels per lane, fewer ring slots.
+// Prefetch depth: enough steps in flight to cover the memory latency, within
+// the 63 outstanding vector memory operations a wavefront can count.
 template <class T>
-constexpr int pass_pf() { return T::E <= 2 ? 4 : (T::E <= 4 ? 2 : 1); }
+constexpr int pass_pf() { return T::E <= 4 ? 8 : (T::E <= 8 ? 4 : 2); }
 
 size_t pass_lds_bytes(int qt, int waves, int ring) {
     return (size_t)(2 * MAX_WAVES + 4 + qt) * 4 + (size_t)(waves > 1 ? waves - 1 : 0) * ring * qt * 4;
 }
 
-template <class T, class CT, int SPLIT>
+template <class T, class CK, int SPLIT>
 static hipError_t run_pass(const PassArgs& a, int grid, int waves, hipStream_t s) {
     const size_t lds = pass_lds_bytes(T::QT, waves, a.ring);
-    hipLaunchKernelGGL((edp_pass_kernel<T, CT, SPLIT, pass_pf<T>()>), dim3(grid), dim3(64 * waves), lds, s, a);
+    hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>), dim3(grid), dim3(64 * waves), lds, s, a);
     return hipGetLastError();
 }
 
@@ -368,42 +364,61 @@ static hipError_t run_agg(const AggArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class T, class CT, int SPLIT>
+template <class T, class CK, int SPLIT>
 static int pass_occupancy(int waves, size_t lds) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CT, SPLIT, pass_pf<T>()>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>,
                                                      64 * waves, lds) != hipSuccess)
         blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
 
 // SPLIT = 2 needs both halves of a vertex in one wavefront.
-template <class T, class CT>
+template <class T, class CK>
 static hipError_t dispatch_pass(int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
     if (split == 2) {
-        if constexpr (2 * T::G <= 64) return run_pass<T, CT, 2>(a, grid, waves, s);
+        if constexpr (2 * T::G <= 64) return run_pass<T, CK, 2>(a, grid, waves, s);
         return hipErrorInvalidValue;
     }
-    return run_pass<T, CT, 1>(a, grid, waves, s);
+    return run_pass<T, CK, 1>(a, grid, waves, s);
 }
 
-template <class T, class CT>
+template <class T, class CK>
 static int dispatch_occupancy(int split, int waves, size_t lds) {
     if (split == 2) {
-        if constexpr (2 * T::G <= 64) return pass_occupancy<T, CT, 2>(waves, lds);
+        if constexpr (2 * T::G <= 64) return pass_occupancy<T, CK, 2>(waves, lds);
         return 1;
     }
-    return pass_occupancy<T, CT, 1>(waves, lds);
+    return pass_occupancy<T, CK, 1>(waves, lds);
+}
+
+// cost kind: 1 int16 (element loads), 2 int32, 3 int16 in aligned pairs
+template <class T>
+static hipError_t dispatch_kind(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
+    if (kind == 1) return dispatch_pass<T, int16_t>(split, a, grid, waves, s);
+    if (kind == 3) {
+        if constexpr (T::KX % 2 == 0) return dispatch_pass<T, Pair16>(split, a, grid, waves, s);
+        return hipErrorInvalidValue;
+    }
+    return dispatch_pass<T, int32_t>(split, a, grid, waves, s);
+}
+template <class T>
+static int occupancy_kind(int kind, int split, int waves, size_t lds) {
+    if (kind == 1) return dispatch_occupancy<T, int16_t>(split, waves, lds);
+    if (kind == 3) {
+        if constexpr (T::KX % 2 == 0) return dispatch_occupancy<T, Pair16>(split, waves, lds);
+        return 1;
+    }
+    return dispatch_occupancy<T, int32_t>(split, waves, lds);
 }
 
 hipError_t launch_edp_pass(int tile, int dtype, int split, const PassArgs& a, int grid, int waves,
                            hipStream_t s) {
     if (waves < 1 || waves > MAX_WAVES) return hipErrorInvalidValue;
     switch (tile) {
-#define EDP_CASE(id, px, kx, py, ky)                                                               \
-    case id:                                                                                       \
-        return dtype == 1 ? dispatch_pass<Tile<px, kx, py, ky>, int16_t>(split, a, grid, waves, s) \
-                          : dispatch_pass<Tile<px, kx, py, ky>, int32_t>(split, a, grid, waves, s);
+#define EDP_CASE(id, px, kx, py, ky) \
+    case id:                         \
+        return dispatch_kind<Tile<px, kx, py, ky>>(dtype, split, a, grid, waves, s);
         EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE
     }
@@ -425,10 +440,9 @@ hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid,
 int pass_capacity(int tile, int dtype, int split, int waves, size_t lds_bytes) {
     int per_cu = 1;
     switch (tile) {
-#define EDP_CASE(id, px, kx, py, ky)                                                                      \
-    case id:                                                                                              \
-        per_cu = dtype == 1 ? dispatch_occupancy<Tile<px, kx, py, ky>, int16_t>(split, waves, lds_bytes)  \
-                            : dispatch_occupancy<Tile<px, kx, py, ky>, int32_t>(split, waves, lds_bytes); \
+#define EDP_CASE(id, px, kx, py, ky)                                               \
+    case id:                                                                       \
+        per_cu = occupancy_kind<Tile<px, kx, py, ky>>(dtype, split, waves, lds_bytes); \
         break;
         EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE
