@@ -35,15 +35,15 @@ bool fits(int tile, int qx, int qy) {
     return t.px * t.kx >= qx && t.py * t.ky >= qy;
 }
 
-// Built-in choice: least padding, then fewest labels per lane (shortest
-// dependent chain per vertex, which is what bounds a scan).
+// Built-in choice: least padding; then vertices that fill one 16-lane row
+// (every cross-lane step of the minimum search is a single DPP instruction);
+// then fewest labels per lane.
 int auto_tile(int qx, int qy) {
     int best = -1;
+    auto score = [](int t) { return (group_of(t) == 16 ? 0 : 1000) + elems_of(t); };
     for (int t = 0; t < NUM_TILES; ++t) {
         if (!fits(t, qx, qy)) continue;
-        if (best < 0 || qt_of(t) < qt_of(best) ||
-            (qt_of(t) == qt_of(best) && elems_of(t) < elems_of(best)))
-            best = t;
+        if (best < 0 || qt_of(t) < qt_of(best) || (qt_of(t) == qt_of(best) && score(t) < score(best))) best = t;
     }
     return best;
 }
@@ -109,7 +109,7 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     edp_status st = pick_tile(p, tu, &L->tile);
     if (st != EDP_OK) return st;
     const int g = group_of(L->tile);
-    int split = (tu && tu->split > 0) ? tu->split : (2 * g <= 64 ? 2 : 1);
+    int split = (tu && tu->split > 0) ? tu->split : 1;
     if (split != 1 && split != 2) return EDP_E_INVALID;
     if (split * g > 64) return EDP_E_INVALID;
     int waves = (tu && tu->waves > 0) ? tu->waves : 4;
@@ -117,7 +117,7 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     L->split = split;
     L->waves = waves;
     // progress publication period and LDS ring depth are powers of two (masks, no division)
-    int chunk = (tu && tu->chunk > 0) ? tu->chunk : 8;
+    int chunk = (tu && tu->chunk > 0) ? tu->chunk : 4;
     int c2 = 1;
     while (c2 < chunk && c2 < 1024) c2 <<= 1;
     L->chunk = c2;
