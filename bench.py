@@ -95,7 +95,7 @@ def measured_traffic(kernel_key, src_hash):
     return rec.get("bytes_per_launch")
 
 
-def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1):
+def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1, fuse=0):
     dev = torch.device("cuda:0")
     cost = torch.from_numpy(prob.cost).to(dev)
     bound = int(abs(prob.cost).max()) + 1
@@ -103,10 +103,10 @@ def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1):
     H, W, Q = prob.cost.shape
     labels = torch.empty((H, W), dtype=torch.int32, device=dev)
     energy = torch.empty(1, dtype=torch.int64, device=dev)
-    npass = 4 * iterations
-    ev = HipEvents(2 * npass * steps)
+    nlaunch = (4 if fuse == 1 else 2) * iterations     # scan launches per solve
+    ev = HipEvents(2 * nlaunch * steps)
     kw = dict(mode=prob.mode, iterations=iterations, cost_bound=bound, tile=tile, chunk=chunk, ws=ws,
-              labels=labels, energy=energy)
+              labels=labels, energy=energy, fuse=fuse)
     for _ in range(warmup):
         edp.solve(cost, prob.qx, prob.qy, prob.lam, prob.trunc, **kw)
     torch.cuda.synchronize()
@@ -114,15 +114,63 @@ def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1):
     torch.cuda.synchronize()
     start.record()
     for k in range(steps):
-        edp.solve(cost, prob.qx, prob.qy, prob.lam, prob.trunc, events=ev.view(2 * npass * k, 2 * npass), **kw)
+        edp.solve(cost, prob.qx, prob.qy, prob.lam, prob.trunc, events=ev.view(2 * nlaunch * k, 2 * nlaunch), **kw)
     stop.record()
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
-    pass_ms = [[ev.ms(2 * npass * k + 2 * p, 2 * npass * k + 2 * p + 1) for p in range(npass)]
-               for k in range(steps)]
+    launch_ms = [[ev.ms(2 * nlaunch * k + 2 * p, 2 * nlaunch * k + 2 * p + 1) for p in range(nlaunch)]
+                 for k in range(steps)]
     ev.close()
-    return {"ms_per_step": total_ms / steps, "pass_ms": pass_ms, "labels": labels.cpu().numpy(),
+    return {"ms_per_step": total_ms / steps, "launch_ms": launch_ms, "labels": labels.cpu().numpy(),
             "energy": int(energy.item()), "cost": cost}
+
+
+def bench_batch(edp, torch, steps, warmup):
+    """The 64-instance uneven stereo / motion batch, one plan, solves replayed from a hipGraph."""
+    import numpy as np
+    import synth
+    t0 = time.perf_counter()
+    probs = synth.batch_problems(64)
+    log(f"batch inputs generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    costs = [torch.from_numpy(p.cost).to(dev) for p in probs]
+    params = [dict(qx=p.qx, qy=p.qy, lam=p.lam, trunc=p.trunc, mode=p.mode, iterations=1,
+                   cost_bound=50 if p.cost.dtype == np.int16 else 2500) for p in probs]
+    plan = edp.BatchPlan(costs, params)
+    classes, launches = plan.info()
+    pl = sum(p.pixel_labels for p in probs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(max(1, warmup)):
+            plan.solve()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        plan.solve()
+    stop.record()
+    torch.cuda.synchronize()
+    eager_ms = start.elapsed_time(stop) / steps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.solve()
+    g.replay()
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        g.replay()
+    stop.record()
+    torch.cuda.synchronize()
+    graph_ms = start.elapsed_time(stop) / steps
+    energies = plan.energies.cpu().tolist()
+    del g
+    plan.close()
+    return {"workload": "64 instances: stereo 160x120..640x480 Q 16-64 int16, motion 9x9..21x21 labels int32",
+            "pixel_labels": pl, "classes": classes, "launches_per_solve": launches,
+            "graph_ms_per_solve": graph_ms, "eager_ms_per_solve": eager_ms,
+            "pixel_labels_per_s": pl / (graph_ms / 1e3), "energy_sum": int(sum(energies))}
 
 
 def bench_dp(edp, torch, steps, warmup, rows=4096, cols=2048, q=64, seed=0):
@@ -177,6 +225,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--fuse", type=int, default=0, help="EDP scans per launch (1 or 2; 0 = built-in)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the DP sweep and motion workloads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -213,17 +263,17 @@ def main():
     H, W, Q = prob.cost.shape
     pl = H * W * Q
     log(f"workload {prob.name} ({W}x{H}, Q={Q}, int16), {args.warmup} warmup + {args.steps} timed steps")
-    r = bench_edp(edp, torch, prob, args.steps, args.warmup, args.tile, args.chunk)
+    r = bench_edp(edp, torch, prob, args.steps, args.warmup, args.tile, args.chunk, fuse=args.fuse)
     ms = r["ms_per_step"]
     csize = prob.cost.dtype.itemsize
     per_pass_bytes = [b * pl for b in scan_bytes_per_pl(csize)]
-    pass_ms = np.array(r["pass_ms"])                      # [steps][4]
-    mean_pass_ms = pass_ms.mean(axis=0)
+    launch_ms = np.array(r["launch_ms"])                  # [steps][scan launches]
+    mean_launch_ms = launch_ms.mean(axis=0)
     alg_bytes = float(sum(per_pass_bytes))
-    achieved = alg_bytes / (mean_pass_ms.sum() / 1e3) / 1e9
+    achieved = alg_bytes / (mean_launch_ms.sum() / 1e3) / 1e9
     src_hash = kernel_source_hash(["edp_pass.hip", "edp_device.hpp"])
     traffic = measured_traffic("edp_pass_stereo384x288", src_hash)
-    log(f"step {ms:.3f} ms, scans {mean_pass_ms.round(4).tolist()} ms")
+    log(f"step {ms:.3f} ms, scan launches {mean_launch_ms.round(4).tolist()} ms")
 
     out = {
         "metric": "pixel-labels/sec (plain EDP solve, j=1); HBM GB/s of the EDP scan kernel",
@@ -240,26 +290,30 @@ def main():
         "data": "synthetic (seeded textured stereo pair, 6 planar disparity segments, sigma 4)",
         "config": {"workload": "plain EDP stereo 384x288, 32 disparities, int16 TAD costs (trunc 50), "
                                "lambda 20, T 2, j=1", "width": W, "height": H, "labels": Q,
-                   "iterations": 1, "tile": args.tile, "chunk": args.chunk},
-        "roofline": {"bound": "hbm", "kernel": "edp_pass_kernel (4 scans per step)",
+                   "iterations": 1, "tile": args.tile, "chunk": args.chunk, "fuse": args.fuse},
+        "roofline": {"bound": "hbm",
+                     "kernel": f"edp_pass_kernel ({len(mean_launch_ms)} scan launches per step)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_step_scans": alg_bytes,
-                     "mean_scan_ms": mean_pass_ms.tolist(), "source_hash": src_hash},
+                     "mean_launch_ms": mean_launch_ms.tolist(), "source_hash": src_hash},
         "energy": r["energy"],
     }
     extra = {}
     if not args.no_extra:
         log("motion 320x240 (15x15 labels, int32)")
         mp = synth.workload("motion320x240")
-        mr = bench_edp(edp, torch, mp, max(3, args.steps // 4), 1, -1, args.chunk)
+        mr = bench_edp(edp, torch, mp, max(3, args.steps // 4), 1, -1, args.chunk, fuse=args.fuse)
         mpl = mp.cost.shape[0] * mp.cost.shape[1] * mp.cost.shape[2]
         extra["motion320x240"] = {"pixel_labels_per_s": mpl / (mr["ms_per_step"] / 1e3),
                                   "ms_per_step": mr["ms_per_step"], "energy": mr["energy"],
-                                  "mean_scan_ms": np.array(mr["pass_ms"]).mean(axis=0).tolist()}
+                                  "mean_launch_ms": np.array(mr["launch_ms"]).mean(axis=0).tolist()}
         del mr
         log("scanline DP sweep 2048x4096, Q=64 int16")
         extra["dp_sweep"] = bench_dp(edp, torch, max(3, args.steps // 4), 1)
+    if not args.no_batch:
+        log("batch of 64 uneven instances (hipGraph replay)")
+        extra["batch64"] = bench_batch(edp, torch, max(3, args.steps // 4), 1)
     out["extra"] = extra
     if not args.no_cpu:
         log("CPU oracle baseline (about 10 s)")

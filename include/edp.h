@@ -74,9 +74,12 @@ typedef struct {
  *   split  1: every lane runs both minimum searches of a scan step;
  *          2: the two searches run on two halves of the vertex's lanes
  *   waves  wavefronts per EDP workgroup (1..8), handing rows over in LDS
+ *   fuse   EDP scans per launch: 1, or 2 (P1 with P2, P3 with P4: the two
+ *          scans of a pair sweep the rows in the same order, so the second
+ *          follows the first a few rows behind inside one launch)
  * events (nullable): caller-created hipEvent_t handles recorded on the call's
- * stream so the caller can time kernels: edp_solve records events[2p] before
- * and events[2p+1] after the p-th scan launch (p < n_events / 2);
+ * stream so the caller can time kernels: edp_solve records events[2l] before
+ * and events[2l+1] after its l-th scan launch (l < n_events / 2);
  * edp_dp_scanline records events[0], [1] around the forward sweep and
  * events[2], [3] around the backtracking.  Handles past n_events are unused. */
 typedef struct {
@@ -84,6 +87,7 @@ typedef struct {
     int32_t chunk;       /* EDP columns per progress publication, 0 = automatic */
     int32_t split;       /* 1 or 2, 0 = automatic */
     int32_t waves;       /* 1..8, 0 = automatic */
+    int32_t fuse;        /* 1 or 2, 0 = automatic */
     void* const* events; /* nullable, see above */
     int32_t n_events;    /* number of handles in events */
 } edp_tuning;
@@ -119,6 +123,53 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
 edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
                      int32_t* d_labels, int64_t* d_energy, void* d_ws, size_t ws_bytes,
                      void* stream);
+
+/*
+ * Batches: many independent EDP instances (Algorithm 1 each, any mix of grid
+ * sizes, label spaces, dtypes and parameters) solved by shared persistent
+ * launches.  Instances with the same launch shape (tile, cost kind, split,
+ * waves, chunk, fuse, iterations) form a class; each scan launch of a class
+ * walks a work queue over (scan, instance, workgroup band), longest instance
+ * first.  Classes run on library-owned streams forked from and joined back to
+ * the caller's stream.  Results are identical to edp_solve on each instance.
+ */
+typedef struct {
+    edp_problem problem;
+    const void* d_cost;    /* [H][W][Q] cost volume */
+    int32_t* d_labels;     /* [H][W] int32 output labels */
+    int64_t* d_energy;     /* [1] int64 output: 4-connected energy (nullable) */
+    edp_tuning tuning;     /* launch shape of this instance (events ignored) */
+} edp_batch_item;
+
+typedef struct edp_batch_plan edp_batch_plan;   /* opaque, host memory */
+
+/* Workspace bytes of a batch: every instance's arrays plus a descriptor table. */
+edp_status edp_batch_workspace_size(int32_t n, const edp_batch_item* items, size_t* bytes);
+
+/*
+ * Validate the batch, group it into classes and write the descriptor table
+ * into d_ws (a copy on stream that this call waits for: the one synchronising
+ * step, done once per batch layout).  The plan keeps d_ws and the item
+ * pointers; it stays valid until edp_batch_plan_destroy.  Errors leave *plan
+ * untouched.
+ */
+edp_status edp_batch_plan_create(int32_t n, const edp_batch_item* items, void* d_ws, size_t ws_bytes,
+                                 void* stream, edp_batch_plan** plan);
+
+/*
+ * Enqueue one solve of every instance of the plan on stream.  Only kernel
+ * launches and event records/waits are enqueued (no copies, no memsets, no
+ * allocation), so the call can be captured into a hipGraph and replayed.
+ * Solves of one plan must not overlap: they share its workspace.
+ */
+edp_status edp_batch_solve(const edp_batch_plan* plan, void* stream);
+
+/* Classes and kernel launches of one edp_batch_solve (either nullable). */
+edp_status edp_batch_plan_info(const edp_batch_plan* plan, int32_t* n_classes, int32_t* n_launches);
+
+/* Release the plan's host memory, streams and events (NULL is ignored).  The
+ * caller first synchronises every stream that ran the plan's solves. */
+void edp_batch_plan_destroy(edp_batch_plan* plan);
 
 /*
  * Energy of a labelling (Sec. 2 eq. GE_objective_function).

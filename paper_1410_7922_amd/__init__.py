@@ -5,5 +5,5 @@ Algorithm for Energy Minimization in Stereo and Motion", arXiv 1410.7922.
 The solvers live in ``libedp.so`` (C ABI: include/edp.h); ``binding`` marshals
 torch tensors into it.
 """
-from .binding import (TRUNC_JOINT, TRUNC_PER_DIM, EdpError, Workspace, dp_scanline, energy,  # noqa: F401
-                      load, solve, tile_info, tiles, workspace_size)
+from .binding import (TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace, dp_scanline,  # noqa: F401
+                      energy, load, solve, tile_info, tiles, workspace_size)

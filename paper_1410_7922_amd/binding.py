@@ -23,7 +23,8 @@ OP_DP = 0
 OP_EDP = 1
 
 EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
-           "edp_tile_info", "edp_status_string")
+           "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
+           "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy")
 
 
 class Problem(ctypes.Structure):
@@ -33,8 +34,13 @@ class Problem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("events", ctypes.POINTER(ctypes.c_void_p)),
+                ("waves", ctypes.c_int32), ("fuse", ctypes.c_int32), ("events", ctypes.POINTER(ctypes.c_void_p)),
                 ("n_events", ctypes.c_int32)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("problem", Problem), ("d_cost", ctypes.c_void_p), ("d_labels", ctypes.c_void_p),
+                ("d_energy", ctypes.c_void_p), ("tuning", Tuning)]
 
 
 class EdpError(RuntimeError):
@@ -64,8 +70,16 @@ def load(path: str = LIB_PATH):
     L.edp_tile_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
     L.edp_status_string.argtypes = [ctypes.c_int32]
     L.edp_status_string.restype = ctypes.c_char_p
+    pitem = ctypes.POINTER(BatchItem)
+    L.edp_batch_workspace_size.argtypes = [ctypes.c_int32, pitem, ctypes.POINTER(sz)]
+    L.edp_batch_plan_create.argtypes = [ctypes.c_int32, pitem, vp, sz, vp, ctypes.POINTER(vp)]
+    L.edp_batch_solve.argtypes = [vp, vp]
+    L.edp_batch_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.edp_batch_plan_destroy.argtypes = [vp]
+    L.edp_batch_plan_destroy.restype = None
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
-                 "edp_tile_info"):
+                 "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
+                 "edp_batch_plan_info"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -93,10 +107,10 @@ def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mod
                    iterations, cost_bound)
 
 
-def _tuning(tile: int, chunk: int, events=None, split: int = 0, waves: int = 0):
-    if tile < 0 and chunk <= 0 and split <= 0 and waves <= 0 and events is None:
+def _tuning(tile: int, chunk: int, events=None, split: int = 0, waves: int = 0, fuse: int = 0):
+    if tile < 0 and chunk <= 0 and split <= 0 and waves <= 0 and fuse <= 0 and events is None:
         return None
-    t = Tuning(tile, chunk, split, waves, None, 0)
+    t = Tuning(tile, chunk, split, waves, fuse, None, 0)
     if events is not None:
         t.events = ctypes.cast(events, ctypes.POINTER(ctypes.c_void_p))
         t.n_events = len(events)
@@ -114,9 +128,10 @@ def _stream(dev) -> int:
     return torch.cuda.current_stream(dev).cuda_stream
 
 
-def workspace_size(prob: Problem, op: int, tile: int = -1, chunk: int = 0, split: int = 0, waves: int = 0) -> int:
+def workspace_size(prob: Problem, op: int, tile: int = -1, chunk: int = 0, split: int = 0, waves: int = 0,
+                   fuse: int = 0) -> int:
     n = ctypes.c_size_t(0)
-    _check(load().edp_workspace_size(ctypes.byref(prob), op, _tuning(tile, chunk, None, split, waves),
+    _check(load().edp_workspace_size(ctypes.byref(prob), op, _tuning(tile, chunk, None, split, waves, fuse),
                                      ctypes.byref(n)),
            "edp_workspace_size")
     return int(n.value)
@@ -176,20 +191,21 @@ def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: 
 def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,
           iterations: int = 1, cost_bound: int = 0, tile: int = -1, chunk: int = 0,
           ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None,
-          events=None, split: int = 0, waves: int = 0):
+          events=None, split: int = 0, waves: int = 0, fuse: int = 0):
     """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors.
 
     ``events``: optional ctypes array of hipEvent_t handles recorded around the scan launches."""
     _device_tensor(cost, "cost")
     prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound)
-    nbytes = workspace_size(prob, OP_EDP, tile, chunk, split, waves)
+    nbytes = workspace_size(prob, OP_EDP, tile, chunk, split, waves, fuse)
     w = (ws or _default_ws).get(nbytes, cost.device)
     H, W, _ = cost.shape
     if labels is None:
         labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
     if energy is None:
         energy = torch.empty(1, dtype=torch.int64, device=cost.device)
-    _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk, events, split, waves), cost.data_ptr(), labels.data_ptr(),
+    _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk, events, split, waves, fuse), cost.data_ptr(),
+                            labels.data_ptr(),
                             energy.data_ptr(), w.data_ptr(), w.numel(), _stream(cost.device)), "edp_solve")
     return labels, energy
 
@@ -207,3 +223,71 @@ def energy(cost: torch.Tensor, labels: torch.Tensor, qx: int, qy: int = 1, lam: 
     _check(load().edp_energy(ctypes.byref(prob), cost.data_ptr(), labels.data_ptr(), int(bool(grid4)),
                              e.data_ptr(), bad.data_ptr(), _stream(cost.device)), "edp_energy")
     return e, bad
+
+
+def batch_items(costs, params, labels, energies, tunings=None):
+    """ctypes array of edp_batch_item for device tensors: params[i] holds qx, qy, lam, trunc, mode,
+    iterations, cost_bound; tunings[i] (optional) holds tile, chunk, split, waves, fuse."""
+    n = len(costs)
+    items = (BatchItem * n)()
+    for i in range(n):
+        _device_tensor(costs[i], f"costs[{i}]")
+        _device_tensor(labels[i], f"labels[{i}]")
+        pr = params[i]
+        items[i].problem = make_problem(costs[i], pr["qx"], pr.get("qy", 1), pr["lam"], pr["trunc"],
+                                        pr.get("mode", TRUNC_PER_DIM), pr.get("iterations", 1),
+                                        pr.get("cost_bound", 0))
+        items[i].d_cost = costs[i].data_ptr()
+        items[i].d_labels = labels[i].data_ptr()
+        items[i].d_energy = energies.data_ptr() + 8 * i if energies is not None else None
+        tu = (tunings[i] if tunings else None) or {}
+        items[i].tuning = Tuning(tu.get("tile", -1), tu.get("chunk", 0), tu.get("split", 0), tu.get("waves", 0),
+                                 tu.get("fuse", 0), None, 0)
+    return items
+
+
+def batch_workspace_size(items) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().edp_batch_workspace_size(len(items), items, ctypes.byref(n)), "edp_batch_workspace_size")
+    return int(n.value)
+
+
+class BatchPlan:
+    """A batch of EDP instances bound to their device tensors (edp_batch_plan_create).
+
+    ``solve()`` enqueues kernels only, so it may be captured into a hipGraph
+    (torch.cuda.graph) and replayed; outputs land in ``labels[i]`` and ``energies[i]``."""
+
+    def __init__(self, costs, params, tunings=None, device=None):
+        self.device = device or costs[0].device
+        self.costs = list(costs)
+        self.labels = [torch.empty(tuple(c.shape[:2]), dtype=torch.int32, device=self.device) for c in costs]
+        self.energies = torch.empty(len(costs), dtype=torch.int64, device=self.device)
+        self.items = batch_items(self.costs, params, self.labels, self.energies, tunings)
+        nbytes = batch_workspace_size(self.items)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(None)
+        _check(load().edp_batch_plan_create(len(self.items), self.items, self.ws.data_ptr(), self.ws.numel(),
+                                            _stream(self.device), ctypes.byref(h)), "edp_batch_plan_create")
+        self.handle = h
+
+    def solve(self):
+        _check(load().edp_batch_solve(self.handle, _stream(self.device)), "edp_batch_solve")
+        return self.labels, self.energies
+
+    def info(self) -> tuple:
+        c, l = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().edp_batch_plan_info(self.handle, ctypes.byref(c), ctypes.byref(l)), "edp_batch_plan_info")
+        return c.value, l.value
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            torch.cuda.synchronize(self.device)
+            load().edp_batch_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -3,9 +3,11 @@
 // Algorithm 1 for edp_solve, Sec. 2 eq. base and Sec. 4.1 for the DP).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "../../include/edp.h"
 #include "edp_internal.hpp"
@@ -99,7 +101,7 @@ edp_status pick_tile(const edp_problem* p, const edp_tuning* tu, int* tile) {
 }
 
 struct Launch {
-    int tile, split, waves, chunk, ring;
+    int tile, split, waves, chunk, ring, fuse;
     int rpw;            // scanlines per wavefront
     int nbands, nsuper;
 };
@@ -114,6 +116,9 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     if (split * g > 64) return EDP_E_INVALID;
     int waves = (tu && tu->waves > 0) ? tu->waves : 4;
     if (waves > 8) return EDP_E_INVALID;
+    const int fuse = (tu && tu->fuse > 0) ? tu->fuse : 2;
+    if (fuse != 1 && fuse != 2) return EDP_E_INVALID;
+    L->fuse = fuse;
     L->split = split;
     L->waves = waves;
     // progress publication period and LDS ring depth are powers of two (masks, no division)
@@ -131,28 +136,44 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     return EDP_OK;
 }
 
-struct EdpLayout {
+// Per-instance part of an EDP workspace: the four T arrays and the flags of the
+// scan launches (column progress of the first and second scan, bands done).
+struct InstLayout {
     size_t t[4];
-    size_t ctrl;        // flags, tickets, error word (uint32)
+    size_t tbytes;
+    size_t total;
+    size_t nflags;      // uint32 words, cleared before every solve
+};
+
+InstLayout inst_layout(const edp_problem* p, const Launch& la) {
+    InstLayout L{};
+    const size_t cells = (size_t)p->width * p->height;
+    L.tbytes = up(cells * (size_t)qt_of(la.tile) * 4);
+    for (int k = 0; k < 4; ++k) L.t[k] = k * L.tbytes;
+    L.total = 4 * L.tbytes;
+    L.nflags = (size_t)3 * la.nsuper;
+    return L;
+}
+
+int scan_launches(const edp_problem* p, const Launch& la) { return 4 / la.fuse * p->iterations; }
+
+// Single-instance workspace: T arrays, then the control words (flags, one
+// ticket counter per scan launch, the error word) that every solve clears.
+struct EdpLayout {
+    InstLayout inst;
+    size_t ctrl;
     size_t nflags, ntickets, nctrl;
     size_t total;
 };
 
 EdpLayout edp_layout(const edp_problem* p, const Launch& la) {
     EdpLayout L{};
-    const size_t cells = (size_t)p->width * p->height;
-    const size_t tbytes = up(cells * (size_t)qt_of(la.tile) * 4);
-    size_t off = 0;
-    for (int k = 0; k < 4; ++k) {
-        L.t[k] = off;
-        off += tbytes;
-    }
-    L.nflags = (size_t)la.nsuper;
-    L.ntickets = (size_t)4 * p->iterations;
+    L.inst = inst_layout(p, la);
+    L.nflags = L.inst.nflags;
+    L.ntickets = (size_t)scan_launches(p, la);
     L.nctrl = L.nflags + L.ntickets + 1;
-    L.ctrl = off;
-    off += up(L.nctrl * 4);
-    L.total = off;
+    L.ctrl = L.inst.total;
+    L.total = L.ctrl + up(L.nctrl * 4);
     return L;
 }
 
@@ -181,6 +202,124 @@ __global__ void flag_error_kernel(const uint32_t* error, int64_t* energy) {
     if (threadIdx.x == 0 && *error != 0) *energy = INT64_MIN;
 }
 
+// Batch: clear the energy words before the energy kernel adds into them, and
+// mark every energy of a class whose scans gave up waiting.
+__global__ void zero_energies_kernel(const InstDesc* descs, int32_t n) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (descs[i].energy) *descs[i].energy = 0ull;
+}
+__global__ void flag_error_batch_kernel(const uint32_t* error, const InstDesc* descs, int32_t n) {
+    if (*error == 0) return;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+        if (descs[i].energy) *descs[i].energy = (unsigned long long)INT64_MIN;
+}
+
+// Cost kind of the scan kernel: int16 costs load in dword pairs when every
+// lane's run of labels starts on a 4-byte boundary.
+int cost_kind(const edp_problem* p, int tile, const void* cost) {
+    int kind = p->dtype == EDP_I16 ? 1 : 2;
+    if (kind == 1 && kTiles[tile].kx % 2 == 0 && (p->qx * p->qy) % 2 == 0 &&
+        (p->qy == 1 || p->qx % 2 == 0) && ((uintptr_t)cost % 4) == 0)
+        kind = 3;
+    return kind;
+}
+
+// The scan kernel addresses each array with 32-bit byte offsets below 0x7FFF0000.
+bool edp_offsets_fit(const edp_problem* p, int tile) {
+    const int64_t cells = (int64_t)p->width * p->height;
+    return cells * qt_of(tile) * 4 < 0x7FFF0000LL &&
+           cells * p->qx * p->qy * (p->dtype == EDP_I16 ? 2 : 4) < 0x7FFF0000LL;
+}
+
+InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, char* base,
+                   uint32_t* flags, const void* cost, int32_t* labels, int64_t* energy) {
+    InstDesc d{};
+    d.cost = cost;
+    for (int k = 0; k < 4; ++k) d.t[k] = (int32_t*)(base + L.t[k]);
+    d.labels = labels;
+    d.energy = (unsigned long long*)energy;
+    d.flags = flags;
+    d.W = p->width;
+    d.H = p->height;
+    d.qx = p->qx;
+    d.qy = p->qy;
+    d.lam = p->lambda;
+    d.clipd = p->lambda * p->trunc;
+    d.joint = p->trunc_mode == EDP_TRUNC_JOINT;
+    d.trunc = p->trunc;
+    d.nbands = la.nbands;
+    d.nsuper = la.nsuper;
+    return d;
+}
+
+// Everything one launch shape needs to run its scans and the marginal.
+struct ClassRun {
+    int tile, kind, dtype, split, waves, chunk, ring, fuse, iterations;
+    InstDesc one;              // single instance (descs null)
+    const InstDesc* descs;     // device descriptor slice of a batch class
+    int ndesc;
+    int tickets_per_pass;
+    int agg_blocks, cells_per_block;
+    uint32_t* tickets;         // one counter per scan launch
+    uint32_t* error;
+};
+
+int agg_cells_per_block(int tile) { return (64 / group_of(tile)) * 4; }
+
+int scan_grid(const ClassRun& c) {
+    const int cap = pass_capacity(c.tile, c.kind, c.split, c.waves, pass_lds_bytes(qt_of(c.tile), c.waves, c.ring));
+    const int total = c.fuse * c.tickets_per_pass;
+    return total < cap ? total : cap;
+}
+
+// Scans P1..P4 of Algorithm 1 (arrays 0 +x, 1 -x, 2 +y, 3 -y), iterations
+// times, then the marginal of eq. DP_2D_1 with its smallest argmin.
+edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s) {
+    static const int sx[4] = {1, -1, 1, -1}, sy[4] = {1, 1, -1, -1};
+    static const int ka[4] = {0, 1, 0, 1}, kb[4] = {2, 2, 3, 3};
+    PassArgs a{};
+    a.one = c.one;
+    a.descs = c.descs;
+    a.ndesc = c.descs ? c.ndesc : 0;
+    a.tickets_per_pass = c.tickets_per_pass;
+    a.npass = c.fuse;
+    a.error = c.error;
+    a.chunk = c.chunk;
+    a.ring = c.ring;
+    const int grid = scan_grid(c);
+    int launch = 0;
+    for (int it = 0; it < c.iterations; ++it) {
+        for (int p = 0; p < 4; p += c.fuse, ++launch) {
+            for (int k = 0; k < c.fuse; ++k) {
+                const int q = p + k;
+                PassDir& d = a.dir[k];
+                d.sx = sx[q];
+                d.sy = sy[q];
+                d.ka = ka[q];
+                d.kb = kb[q];
+                // arrays not yet written in this solve still hold S = 0, i.e. T = M(0) = 0
+                d.old_a_zero = (it == 0 && q == 0) ? 1 : 0;             // -x before P2
+                d.old_b_zero = (it == 0 && (q == 0 || q == 1)) ? 1 : 0;  // -y before P3
+                d.b_live = (q == 1 || q == 3) ? 1 : 0;  // T+y of P1 and T-y of P3 die inside their scan
+                d.pass_index = it * 4 + q;
+            }
+            a.ticket = c.tickets + launch;
+            const bool timed = ev && ev->events && 2 * launch + 1 < ev->n_events;
+            if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch], s) != hipSuccess) return EDP_E_HIP;
+            if (launch_edp_pass(c.tile, c.kind, c.split, a, grid, c.waves, s) != hipSuccess) return EDP_E_HIP;
+            if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch + 1], s) != hipSuccess)
+                return EDP_E_HIP;
+        }
+    }
+    AggArgs g{};
+    g.one = c.one;
+    g.descs = c.descs;
+    g.ndesc = a.ndesc;
+    g.cells_per_block = c.cells_per_block;
+    if (launch_edp_aggregate(c.tile, c.dtype, g, c.agg_blocks, s) != hipSuccess) return EDP_E_HIP;
+    return EDP_OK;
+}
+
 edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t* labels, int grid4,
                           int64_t* energy, int64_t* invalid, hipStream_t s) {
     EnergyArgs e{};
@@ -202,6 +341,118 @@ edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t*
     return hip_status(err);
 }
 
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+constexpr int kEnergyRows = 2;   // rows per block of the batched energy kernel
+
+struct BatchEntry {
+    Launch la;
+    int kind;
+    InstLayout L;
+    size_t base;         // byte offset of the instance's T arrays in the workspace
+    size_t flags_word;   // first control word of the instance's flags
+    int64_t est;         // critical-path estimate in scan steps (sort key)
+};
+
+struct BatchClassPlan {
+    int tile, kind, dtype, split, waves, chunk, ring, fuse, iterations;
+    std::vector<int> members;   // items, longest first
+    int first_desc;
+    size_t tickets_word, error_word;
+    int tickets_per_pass, agg_blocks, cells_per_block, energy_blocks;
+};
+
+struct BatchLayout {
+    std::vector<BatchEntry> e;
+    std::vector<BatchClassPlan> classes;
+    size_t desc_off, ctrl_off, nctrl, total;
+};
+
+edp_status plan_batch(int32_t n, const edp_batch_item* items, BatchLayout* B) {
+    if (n < 1 || n > 65536 || !items) return EDP_E_INVALID;
+    B->e.assign(n, BatchEntry{});
+    B->classes.clear();
+    for (int i = 0; i < n; ++i) {
+        const edp_batch_item& it = items[i];
+        edp_status st = check_problem(&it.problem, EDP_OP_EDP);
+        if (st != EDP_OK) return st;
+        if (!it.d_cost || !it.d_labels) return EDP_E_INVALID;
+        if (it.tuning.chunk < 0) return EDP_E_INVALID;
+        BatchEntry& e = B->e[i];
+        st = pick_launch(&it.problem, &it.tuning, &e.la);
+        if (st != EDP_OK) return st;
+        if (!edp_offsets_fit(&it.problem, e.la.tile)) return EDP_E_UNSUPPORTED;
+        e.kind = cost_kind(&it.problem, e.la.tile, it.d_cost);
+        e.L = inst_layout(&it.problem, e.la);
+        e.est = (int64_t)it.problem.width + 4 * (int64_t)it.problem.height;
+        int c = 0;
+        for (; c < (int)B->classes.size(); ++c) {
+            const BatchClassPlan& k = B->classes[c];
+            if (k.tile == e.la.tile && k.kind == e.kind && k.split == e.la.split && k.waves == e.la.waves &&
+                k.chunk == e.la.chunk && k.ring == e.la.ring && k.fuse == e.la.fuse &&
+                k.iterations == it.problem.iterations)
+                break;
+        }
+        if (c == (int)B->classes.size()) {
+            BatchClassPlan k{};
+            k.tile = e.la.tile;
+            k.kind = e.kind;
+            k.dtype = it.problem.dtype;
+            k.split = e.la.split;
+            k.waves = e.la.waves;
+            k.chunk = e.la.chunk;
+            k.ring = e.la.ring;
+            k.fuse = e.la.fuse;
+            k.iterations = it.problem.iterations;
+            B->classes.push_back(k);
+        }
+        B->classes[c].members.push_back(i);
+    }
+    // workspace: descriptor table, every instance's T arrays, then the control words
+    size_t off = 0;
+    B->desc_off = off;
+    off += up((size_t)n * sizeof(InstDesc));
+    for (int i = 0; i < n; ++i) {
+        B->e[i].base = off;
+        off += B->e[i].L.total;
+    }
+    size_t word = 0;
+    for (int i = 0; i < n; ++i) {
+        B->e[i].flags_word = word;
+        word += B->e[i].L.nflags;
+    }
+    int first_desc = 0;
+    for (BatchClassPlan& k : B->classes) {
+        std::stable_sort(k.members.begin(), k.members.end(),
+                         [&](int a, int b) { return B->e[a].est > B->e[b].est; });
+        k.first_desc = first_desc;
+        first_desc += (int)k.members.size();
+        k.cells_per_block = agg_cells_per_block(k.tile);
+        int64_t tickets = 0, blocks = 0, eblocks = 0;
+        for (int i : k.members) {
+            const edp_problem& p = items[i].problem;
+            tickets += B->e[i].la.nsuper;
+            blocks += ((int64_t)p.width * p.height + k.cells_per_block - 1) / k.cells_per_block;
+            eblocks += (p.height + kEnergyRows - 1) / kEnergyRows;
+        }
+        if (tickets * k.fuse >= INT_MAX || blocks >= INT_MAX || eblocks >= INT_MAX) return EDP_E_UNSUPPORTED;
+        k.tickets_per_pass = (int)tickets;
+        k.agg_blocks = (int)blocks;
+        k.energy_blocks = (int)eblocks;
+        k.tickets_word = word;
+        word += (size_t)4 / k.fuse * k.iterations;
+        k.error_word = word;
+        word += 1;
+    }
+    B->ctrl_off = off;
+    B->nctrl = word;
+    off += up(word * 4);
+    B->total = off;
+    return EDP_OK;
+}
+
 }  // namespace
 
 TileShape tile_shape(int tile) { return kTiles[tile]; }
@@ -209,6 +460,28 @@ TileShape tile_shape(int tile) { return kTiles[tile]; }
 }  // namespace edp
 
 using namespace edp;
+
+struct edp_batch_plan {
+    int32_t n;
+    char* ws;
+    size_t ctrl_off, nctrl;
+    const InstDesc* descs;              // device descriptor table (in the workspace)
+    std::vector<BatchClassPlan> classes;
+    std::vector<hipStream_t> streams;   // one per class when there are several
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
+};
+
+namespace {
+
+void release_plan(edp_batch_plan* p) {
+    for (hipStream_t st : p->streams) hipStreamDestroy(st);
+    for (hipEvent_t ev : p->joins) hipEventDestroy(ev);
+    if (p->fork) hipEventDestroy(p->fork);
+    delete p;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -308,12 +581,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     Launch la{};
     st = pick_launch(prob, tuning, &la);
     if (st != EDP_OK) return st;
-    const int tile = la.tile;
-    // the scan kernel addresses each array with 32-bit byte offsets below 0x7FFF0000
-    const int64_t cells = (int64_t)prob->width * prob->height;
-    if (cells * qt_of(tile) * 4 >= 0x7FFF0000LL ||
-        cells * prob->qx * prob->qy * (prob->dtype == EDP_I16 ? 2 : 4) >= 0x7FFF0000LL)
-        return EDP_E_UNSUPPORTED;
+    if (!edp_offsets_fit(prob, la.tile)) return EDP_E_UNSUPPORTED;
     const EdpLayout L = edp_layout(prob, la);
     if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < L.total) return EDP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
@@ -323,71 +591,28 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     uint32_t* tickets = ctrl + L.nflags;
     uint32_t* error = tickets + L.ntickets;
 
-    hipError_t err = launch_fill_u32(ctrl, L.nctrl, 0, s);
-    if (err != hipSuccess) return EDP_E_HIP;
-
-    PassArgs a{};
-    a.cost = d_cost;
-    for (int k = 0; k < 4; ++k) a.t[k] = (int32_t*)(ws + L.t[k]);
-    a.flags = flags;
-    a.error = error;
-    a.W = prob->width;
-    a.H = prob->height;
-    a.qx = prob->qx;
-    a.qy = prob->qy;
-    a.lam = prob->lambda;
-    a.clipd = prob->lambda * prob->trunc;
-    a.joint = prob->trunc_mode == EDP_TRUNC_JOINT;
-    a.chunk = la.chunk;
-    a.nbands = la.nbands;
-    a.nsuper = la.nsuper;
-    a.ring = la.ring;
-    // cost kind of the scan kernel: int16 costs load in dword pairs when every lane's run of
-    // labels starts on a 4-byte boundary
-    int kind = prob->dtype == EDP_I16 ? 1 : 2;
-    if (kind == 1 && kTiles[tile].kx % 2 == 0 && (prob->qx * prob->qy) % 2 == 0 &&
-        (prob->qy == 1 || prob->qx % 2 == 0) && ((uintptr_t)d_cost % 4) == 0)
-        kind = 3;
-    const int cap = pass_capacity(tile, kind, la.split, la.waves, pass_lds_bytes(qt_of(tile), la.waves, la.ring));
-    const int grid = a.nsuper < cap ? a.nsuper : cap;
-    // scans P1..P4: (sx, sy) and the arrays they write (0 +x, 1 -x, 2 +y, 3 -y)
-    const int sx[4] = {1, -1, 1, -1}, sy[4] = {1, 1, -1, -1};
-    const int ka[4] = {0, 1, 0, 1}, kb[4] = {2, 2, 3, 3};
-    int pass_index = 0;
-    for (int it = 0; it < prob->iterations; ++it) {
-        for (int p = 0; p < 4; ++p, ++pass_index) {
-            a.sx = sx[p];
-            a.sy = sy[p];
-            a.ka = ka[p];
-            a.kb = kb[p];
-            // arrays not yet written in this solve still hold S = 0, i.e. T = M(0) = 0
-            a.old_a_zero = (it == 0 && p == 0) ? 1 : 0;            // -x before P2
-            a.old_b_zero = (it == 0 && (p == 0 || p == 1)) ? 1 : 0; // -y before P3
-            a.ticket = tickets + pass_index;
-            a.epoch = (uint32_t)pass_index * (uint32_t)(prob->width + 1);
-            a.b_live = (p == 1 || p == 3) ? 1 : 0;   // T+y of P1 and T-y of P3 die inside their scan
-            const bool timed = tuning && tuning->events && 2 * pass_index + 1 < tuning->n_events;
-            if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index], s) != hipSuccess)
-                return EDP_E_HIP;
-            err = launch_edp_pass(tile, kind, la.split, a, grid, la.waves, s);
-            if (err != hipSuccess) return EDP_E_HIP;
-            if (timed && hipEventRecord((hipEvent_t)tuning->events[2 * pass_index + 1], s) != hipSuccess)
-                return EDP_E_HIP;
-        }
-    }
-    AggArgs g{};
-    g.cost = d_cost;
-    for (int k = 0; k < 4; ++k) g.t[k] = a.t[k];
-    g.labels = d_labels;
-    g.W = prob->width;
-    g.H = prob->height;
-    g.qx = prob->qx;
-    g.qy = prob->qy;
-    const int64_t per_block = (64 / group_of(tile)) * 4;
-    int64_t agrid = (cells + per_block - 1) / per_block;
-    if (agrid > 8192) agrid = 8192;
-    err = launch_edp_aggregate(tile, prob->dtype, g, (int)agrid, s);
-    if (err != hipSuccess) return EDP_E_HIP;
+    if (launch_fill_u32(ctrl, L.nctrl, 0, s) != hipSuccess) return EDP_E_HIP;
+    ClassRun c{};
+    c.tile = la.tile;
+    c.kind = cost_kind(prob, la.tile, d_cost);
+    c.dtype = prob->dtype;
+    c.split = la.split;
+    c.waves = la.waves;
+    c.chunk = la.chunk;
+    c.ring = la.ring;
+    c.fuse = la.fuse;
+    c.iterations = prob->iterations;
+    c.one = make_desc(prob, la, L.inst, ws, flags, d_cost, d_labels, nullptr);
+    c.descs = nullptr;
+    c.ndesc = 1;
+    c.tickets_per_pass = la.nsuper;
+    c.cells_per_block = agg_cells_per_block(la.tile);
+    const int64_t cells = (int64_t)prob->width * prob->height;
+    c.agg_blocks = (int)((cells + c.cells_per_block - 1) / c.cells_per_block);
+    c.tickets = tickets;
+    c.error = error;
+    st = enqueue_class(c, tuning, s);
+    if (st != EDP_OK) return st;
     if (d_energy) {
         st = enqueue_energy(prob, d_cost, d_labels, 1, d_energy, nullptr, s);
         if (st != EDP_OK) return st;
@@ -395,6 +620,135 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
         if (hipGetLastError() != hipSuccess) return EDP_E_HIP;
     }
     return EDP_OK;
+}
+
+edp_status edp_batch_workspace_size(int32_t n, const edp_batch_item* items, size_t* bytes) {
+    if (!bytes) return EDP_E_INVALID;
+    BatchLayout B;
+    edp_status st = plan_batch(n, items, &B);
+    if (st != EDP_OK) return st;
+    *bytes = B.total;
+    return EDP_OK;
+}
+
+edp_status edp_batch_plan_create(int32_t n, const edp_batch_item* items, void* d_ws, size_t ws_bytes,
+                                 void* stream, edp_batch_plan** plan) {
+    if (!plan) return EDP_E_INVALID;
+    BatchLayout B;
+    edp_status st = plan_batch(n, items, &B);
+    if (st != EDP_OK) return st;
+    if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < B.total) return EDP_E_WORKSPACE;
+    char* ws = (char*)d_ws;
+    uint32_t* ctrl = (uint32_t*)(ws + B.ctrl_off);
+    std::vector<InstDesc> descs(n);
+    for (const BatchClassPlan& k : B.classes) {
+        int ticket = 0, block = 0, eblock = 0;
+        for (size_t m = 0; m < k.members.size(); ++m) {
+            const int i = k.members[m];
+            const edp_batch_item& it = items[i];
+            const BatchEntry& e = B.e[i];
+            InstDesc d = make_desc(&it.problem, e.la, e.L, ws + e.base, ctrl + e.flags_word, it.d_cost,
+                                   it.d_labels, it.d_energy);
+            d.first_ticket = ticket;
+            d.first_block = block;
+            d.first_eblock = eblock;
+            ticket += e.la.nsuper;
+            block += (int)(((int64_t)it.problem.width * it.problem.height + k.cells_per_block - 1) /
+                           k.cells_per_block);
+            eblock += (it.problem.height + kEnergyRows - 1) / kEnergyRows;
+            descs[k.first_desc + m] = d;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(ws + B.desc_off, descs.data(), (size_t)n * sizeof(InstDesc), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return EDP_E_HIP;
+    edp_batch_plan* p = new edp_batch_plan();
+    p->n = n;
+    p->ws = ws;
+    p->ctrl_off = B.ctrl_off;
+    p->nctrl = B.nctrl;
+    p->descs = (const InstDesc*)(ws + B.desc_off);
+    p->classes = B.classes;
+    if (p->classes.size() > 1) {
+        bool ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+        for (size_t c = 0; ok && c < p->classes.size(); ++c) {
+            hipStream_t cs = nullptr;
+            hipEvent_t ev = nullptr;
+            ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+            if (ok) p->streams.push_back(cs);
+            ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+            if (ok) p->joins.push_back(ev);
+        }
+        if (!ok) {
+            release_plan(p);
+            return EDP_E_HIP;
+        }
+    }
+    *plan = p;
+    return EDP_OK;
+}
+
+edp_status edp_batch_solve(const edp_batch_plan* plan, void* stream) {
+    if (!plan) return EDP_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* ctrl = (uint32_t*)(plan->ws + plan->ctrl_off);
+    if (launch_fill_u32(ctrl, plan->nctrl, 0, s) != hipSuccess) return EDP_E_HIP;
+    hipLaunchKernelGGL(zero_energies_kernel, dim3((plan->n + 255) / 256), dim3(256), 0, s, plan->descs, plan->n);
+    if (hipGetLastError() != hipSuccess) return EDP_E_HIP;
+    const bool fork = plan->classes.size() > 1;
+    if (fork && hipEventRecord(plan->fork, s) != hipSuccess) return EDP_E_HIP;
+    for (size_t ci = 0; ci < plan->classes.size(); ++ci) {
+        const BatchClassPlan& k = plan->classes[ci];
+        hipStream_t cs = fork ? plan->streams[ci] : s;
+        if (fork && hipStreamWaitEvent(cs, plan->fork, 0) != hipSuccess) return EDP_E_HIP;
+        ClassRun c{};
+        c.tile = k.tile;
+        c.kind = k.kind;
+        c.dtype = k.dtype;
+        c.split = k.split;
+        c.waves = k.waves;
+        c.chunk = k.chunk;
+        c.ring = k.ring;
+        c.fuse = k.fuse;
+        c.iterations = k.iterations;
+        c.descs = plan->descs + k.first_desc;
+        c.ndesc = (int)k.members.size();
+        c.tickets_per_pass = k.tickets_per_pass;
+        c.agg_blocks = k.agg_blocks;
+        c.cells_per_block = k.cells_per_block;
+        c.tickets = ctrl + k.tickets_word;
+        c.error = ctrl + k.error_word;
+        edp_status st = enqueue_class(c, nullptr, cs);
+        if (st != EDP_OK) return st;
+        BatchEnergyArgs ea{};
+        ea.descs = c.descs;
+        ea.ndesc = c.ndesc;
+        ea.rows_per_block = kEnergyRows;
+        if (launch_batch_energy(k.dtype, ea, k.energy_blocks, cs) != hipSuccess) return EDP_E_HIP;
+        hipLaunchKernelGGL(flag_error_batch_kernel, dim3(1), dim3(256), 0, cs, c.error, c.descs, c.ndesc);
+        if (hipGetLastError() != hipSuccess) return EDP_E_HIP;
+        if (fork && (hipEventRecord(plan->joins[ci], cs) != hipSuccess ||
+                     hipStreamWaitEvent(s, plan->joins[ci], 0) != hipSuccess))
+            return EDP_E_HIP;
+    }
+    return EDP_OK;
+}
+
+edp_status edp_batch_plan_info(const edp_batch_plan* plan, int32_t* n_classes, int32_t* n_launches) {
+    if (!plan) return EDP_E_INVALID;
+    if (n_classes) *n_classes = (int32_t)plan->classes.size();
+    if (n_launches) {
+        int32_t l = 2;   // clear the control words and the energies
+        for (const BatchClassPlan& k : plan->classes) l += 4 / k.fuse * k.iterations + 3;
+        *n_launches = l;
+    }
+    return EDP_OK;
+}
+
+void edp_batch_plan_destroy(edp_batch_plan* plan) {
+    if (plan) release_plan(plan);
 }
 
 edp_status edp_energy(const edp_problem* prob, const void* d_cost, const int32_t* d_labels, int32_t grid4,

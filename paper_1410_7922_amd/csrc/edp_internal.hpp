@@ -38,33 +38,89 @@ TileShape tile_shape(int tile);
 // many polls (of the order of a second) for its predecessor before giving up
 // with an error flag, so a broken schedule ends instead of hanging the device.
 constexpr uint32_t SPIN_LIMIT = 1u << 21;
+// The second scan of a fused pair waits for whole workgroup bands of the first.
+constexpr uint32_t SPIN_LIMIT_BAND = 1u << 22;
 
-// One EDP scan (P1..P4) over the grid, T-form: T_k = M(S_k >> 1).
-struct PassArgs {
-    const void* cost;        // [H][W][Q] int16/int32
-    int32_t* t[4];           // T arrays +x, -x, +y, -y in tile layout [H][W][QT]
-    uint32_t* flags;         // [nsuper] progress, monotone across the scans of one solve
-    uint32_t* ticket;        // band counter of this scan (zero before the scan)
-    uint32_t* error;         // set to 1 when a wait exceeds SPIN_LIMIT
+// One instance of the EDP solve (a batch holds many of them).
+struct InstDesc {
+    const void* cost;             // [H][W][Q] int16/int32
+    int32_t* t[4];                // T arrays +x, -x, +y, -y, [H][W][QT] lane-major
+    int32_t* labels;              // [H][W] output labels
+    unsigned long long* energy;   // [1] output energy (batched energy kernel), may be null
+    uint32_t* flags;              // [3][nsuper]: column progress of the first and the second scan of
+                                  // a launch, then the scans completed by each workgroup band
     int32_t W, H, qx, qy;
-    int32_t lam, clipd, joint;
+    int32_t lam, clipd, joint, trunc;
+    int32_t nbands, nsuper;       // wavefront bands, workgroup bands
+    int32_t first_ticket;         // first workgroup band of this instance in its launch
+    int32_t first_block;          // first marginal block of this instance
+    int32_t first_eblock;         // first energy block of this instance
+};
+
+// Locate the instance of a ticket or block: descs sorted by the key, ndesc >= 1;
+// by: 0 tickets, 1 marginal blocks, 2 energy blocks.
+__device__ __forceinline__ int32_t find_instance(const InstDesc* descs, int32_t ndesc, int32_t key,
+                                                 int by_block) {
+    int32_t lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        const int32_t first = by_block == 2 ? descs[mid].first_eblock
+                              : by_block ? descs[mid].first_block : descs[mid].first_ticket;
+        if (first <= key) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// A descriptor read from memory with every word made wavefront-uniform, so its
+// fields live in scalar registers and control flow on them stays scalar.
+__device__ __forceinline__ InstDesc uniform_desc(const InstDesc& src) {
+    constexpr int NW32 = (int)(sizeof(InstDesc) / 4);
+    int32_t w[NW32];
+    __builtin_memcpy(w, &src, sizeof(InstDesc));
+#pragma unroll
+    for (int i = 0; i < NW32; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    InstDesc d;
+    __builtin_memcpy(&d, w, sizeof(InstDesc));
+    return d;
+}
+
+// Direction set of one EDP scan (P1..P4 of Algorithm 1), T-form: T_k = M(S_k >> 1).
+struct PassDir {
     int32_t sx, sy;          // scan direction along x and y (+1 / -1)
     int32_t ka, kb;          // arrays written: ka = x-direction sum, kb = y-direction sum
     int32_t old_a_zero;      // the other x-direction array still holds its initial zeros
     int32_t old_b_zero;      // the other y-direction array still holds its initial zeros
-    uint32_t epoch;          // flag base of this scan
-    int32_t chunk;           // columns per progress publication
-    int32_t nbands;          // scanline bands (one wavefront each)
-    int32_t nsuper;          // workgroup bands (waves per workgroup consecutive bands each)
     int32_t b_live;          // the y-direction sum is read by later scans: store it everywhere
-    int32_t ring;            // LDS hand-off slots between consecutive wavefronts of a workgroup
+    int32_t pass_index;      // scans since the flags were cleared
 };
 
+// One launch of the scan kernel: one scan, or two consecutive scans that sweep
+// the rows in the same order (P1 with P2, P3 with P4), over one instance (ndesc
+// 0: the inline `one`) or every instance of a batch class.  Tickets run over
+// the workgroup bands of every instance for the first scan, then again for the
+// second; a band of the second scan starts once the first scan has finished
+// the bands holding its rows and the row after them.
+struct PassArgs {
+    InstDesc one;
+    const InstDesc* descs;
+    int32_t ndesc;
+    int32_t tickets_per_pass; // workgroup bands of the launch per scan (sum of nsuper)
+    int32_t npass;            // 1 or 2
+    PassDir dir[2];
+    uint32_t* ticket;         // band counter of this launch (zero before the launch)
+    uint32_t* error;          // set to 1 when a wait exceeds its limit
+    int32_t chunk;            // columns per progress publication (power of two)
+    int32_t ring;             // LDS hand-off slots between consecutive wavefronts (power of two)
+};
+
+// Marginal and argmin over one instance or a batch class: block b works on
+// cells [(b - first_block) * cells_per_block, ...) of its instance.
 struct AggArgs {
-    const void* cost;
-    const int32_t* t[4];
-    int32_t* labels;
-    int32_t W, H, qx, qy;
+    InstDesc one;
+    const InstDesc* descs;
+    int32_t ndesc;
+    int32_t cells_per_block;
 };
 
 struct DpArgs {
@@ -94,6 +150,14 @@ struct EnergyArgs {
     int32_t lam, trunc, joint, grid4;
 };
 
+// Energies of every instance of a batch (4-connected): block b works on rows of
+// its instance; outputs accumulate into each instance's energy word.
+struct BatchEnergyArgs {
+    const InstDesc* descs;
+    int32_t ndesc;
+    int32_t rows_per_block;
+};
+
 // Launchers (return hipSuccess or the launch error).  dtype: 1 int16, 2 int32.
 // The scan kernel takes a cost kind instead: 1 int16, 2 int32, 3 int16 read in
 // 4-byte aligned pairs (needs an even KX, an even label count, and qx even
@@ -104,6 +168,7 @@ hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid,
 hipError_t launch_dp_forward(int tile, int dtype, const DpArgs& a, int grid, hipStream_t s);
 hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
 hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);
+hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_sum_rows(const int64_t* rows, int32_t n, int64_t* out, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStream_t s);

@@ -55,6 +55,43 @@ __global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
     }
 }
 
+// Energies of a batch class: block b covers rows_per_block rows of the instance
+// that holds it and adds its share to that instance's energy word.
+template <class CT>
+__global__ __launch_bounds__(256) void batch_energy_kernel(const BatchEnergyArgs a) {
+    const InstDesc d = uniform_desc(a.descs[find_instance(a.descs, a.ndesc, (int32_t)blockIdx.x, 2)]);
+    const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
+    const CT* __restrict__ cost = (const CT*)d.cost;
+    const bool joint = d.joint != 0;
+    const int32_t y0 = ((int32_t)blockIdx.x - d.first_eblock) * a.rows_per_block;
+    const int32_t y1 = y0 + a.rows_per_block < H ? y0 + a.rows_per_block : H;
+    int64_t acc = 0;
+    for (int32_t y = y0; y < y1; ++y) {
+        for (int32_t x = threadIdx.x; x < W; x += blockDim.x) {
+            const int64_t idx = (int64_t)y * W + x;
+            const int32_t lab = d.labels[idx];
+            if (lab < 0 || lab >= Q) continue;
+            acc += (int64_t)cost[idx * Q + lab];
+            if (x + 1 < W) {
+                const int32_t r = d.labels[idx + 1];
+                if (r >= 0 && r < Q) acc += prior_pair(lab, r, d.qx, d.lam, d.trunc, joint);
+            }
+            if (y + 1 < H) {
+                const int32_t v = d.labels[idx + W];
+                if (v >= 0 && v < Q) acc += prior_pair(lab, v, d.qx, d.lam, d.trunc, joint);
+            }
+        }
+    }
+    __shared__ int64_t sacc[256];
+    sacc[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sacc[threadIdx.x] += sacc[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && d.energy) atomicAdd(d.energy, (unsigned long long)sacc[0]);
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -86,6 +123,15 @@ hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(energy_kernel<int16_t>, dim3(grid), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(energy_kernel<int32_t>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s) {
+    if (grid < 1) return hipSuccess;
+    if (dtype == 1)
+        hipLaunchKernelGGL(batch_energy_kernel<int16_t>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(batch_energy_kernel<int32_t>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

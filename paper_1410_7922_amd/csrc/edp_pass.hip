@@ -75,62 +75,107 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     const bool beta = SPLIT == 2 && ((lane / G) & 1);
     const int32_t l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
-    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy, R = a.ring;
-    const bool joint = a.joint != 0;
-    const LineIndex<T> li(a.lam, lane);
-    // Buffer resources: a lane whose operand does not exist uses offset OOB, so
-    // its load returns 0 and its store is dropped, with no branch around it.
-    const int32_t tbytes = W * H * QT * 4;         // below 2^31 (checked by the host)
-    const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(a.cost, W * H * Q * CB);
-    const __amdgpu_buffer_rsrc_t rs_a = make_rsrc(a.t[a.ka], tbytes);
-    const __amdgpu_buffer_rsrc_t rs_b = make_rsrc(a.t[a.kb], tbytes);
-    const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(a.t[a.ka ^ 1], tbytes);
-    const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(a.t[a.kb ^ 1], tbytes);
+    const int32_t R = a.ring;
     // T arrays are lane-major inside a vertex: the lane's E labels are contiguous
     const int32_t lofs = l * E * 4;
-
-    int32_t crun[KY];                              // cost byte offset of the lane's run of KX labels per ky
-    bool valid[KY][KX];
-#pragma unroll
-    for (int ky = 0; ky < KY; ++ky) {
-        const int32_t vy = py * KY + ky;
-        crun[ky] = (vy < a.qy && px * KX < a.qx) ? (vy * a.qx + px * KX) * CB : OOB;
-#pragma unroll
-        for (int kx = 0; kx < KX; ++kx) valid[ky][kx] = px * KX + kx < a.qx && vy < a.qy;
-    }
 
     for (;;) {
         if (threadIdx.x == 0) misc[0] = (int32_t)atomicAdd(a.ticket, 1u);
         if (threadIdx.x < 2 * MAX_WAVES) lds[threadIdx.x] = 0;
         __syncthreads();
-        const int32_t super = __builtin_amdgcn_readfirstlane(misc[0]);
+        const int32_t tk = __builtin_amdgcn_readfirstlane(misc[0]);
         __syncthreads();
-        if (super >= a.nsuper) break;
+        if (tk >= a.npass * a.tickets_per_pass) break;
+        // which scan of the launch, which instance, which workgroup band
+        const bool second = tk >= a.tickets_per_pass;
+        const int32_t rem = second ? tk - a.tickets_per_pass : tk;
+        const int32_t sx = second ? a.dir[1].sx : a.dir[0].sx;
+        const int32_t sy = second ? a.dir[1].sy : a.dir[0].sy;
+        const int32_t ka = second ? a.dir[1].ka : a.dir[0].ka;
+        const int32_t kb = second ? a.dir[1].kb : a.dir[0].kb;
+        const bool old_a_zero = (second ? a.dir[1].old_a_zero : a.dir[0].old_a_zero) != 0;
+        const bool old_b_zero = (second ? a.dir[1].old_b_zero : a.dir[0].old_b_zero) != 0;
+        const bool b_live = (second ? a.dir[1].b_live : a.dir[0].b_live) != 0;
+        const int32_t pass_index = second ? a.dir[1].pass_index : a.dir[0].pass_index;
+        const InstDesc d = a.ndesc > 0 ? uniform_desc(a.descs[find_instance(a.descs, a.ndesc, rem, 0)]) : a.one;
+        const int32_t super = rem - d.first_ticket;
+        const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
+        uint32_t* const progress = d.flags + (second ? d.nsuper : 0);
+        uint32_t* const done = d.flags + 2 * d.nsuper;
+        const uint32_t epoch = (uint32_t)pass_index * (uint32_t)(W + 1);
+        if (second) {
+            // The first scan reads, at its rows, the arrays this scan writes, and writes the
+            // array this scan reads along x; both sweep the rows in the same order.  Start
+            // once the first scan has completed this band and the next one (which holds the
+            // row after the band's last).
+            if (threadIdx.x == 0) {
+                const uint32_t want = (uint32_t)a.dir[0].pass_index + 1;
+                const int32_t last = super + 1 < d.nsuper ? super + 1 : super;
+                for (int32_t b = super; b <= last; ++b) {
+                    uint32_t spins = 0;
+#pragma nounroll
+                    while (__hip_atomic_load(done + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                        if (++spins > SPIN_LIMIT_BAND ||
+                            __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            raise_error(a.error);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        const bool joint = d.joint != 0;
+        const LineIndex<T> li(d.lam, lane);
+        // Buffer resources: a lane whose operand does not exist uses offset OOB, so
+        // its load returns 0 and its store is dropped, with no branch around it.
+        const int32_t tbytes = W * H * QT * 4;         // below 2^31 (checked by the host)
+        const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(d.cost, W * H * Q * CB);
+        // ka is 0 or 1 and kb 2 or 3: pick the arrays with selects (no indexed private array)
+        int32_t* const t_a = ka ? d.t[1] : d.t[0];
+        int32_t* const t_ma = ka ? d.t[0] : d.t[1];
+        int32_t* const t_b = kb == 3 ? d.t[3] : d.t[2];
+        int32_t* const t_mb = kb == 3 ? d.t[2] : d.t[3];
+        const __amdgpu_buffer_rsrc_t rs_a = make_rsrc(t_a, tbytes);
+        const __amdgpu_buffer_rsrc_t rs_b = make_rsrc(t_b, tbytes);
+        const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(t_ma, tbytes);
+        const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(t_mb, tbytes);
+        int32_t crun[KY];                              // cost byte offset of the lane's run of KX labels
+        bool valid[KY][KX];
+#pragma unroll
+        for (int ky = 0; ky < KY; ++ky) {
+            const int32_t vy = py * KY + ky;
+            crun[ky] = (vy < d.qy && px * KX < d.qx) ? (vy * d.qx + px * KX) * CB : OOB;
+#pragma unroll
+            for (int kx = 0; kx < KX; ++kx) valid[ky][kx] = px * KX + kx < d.qx && vy < d.qy;
+        }
         const int32_t band = super * NW + wave;
-        if (band < a.nbands) {
+        if (band < d.nbands) {
             const int32_t j = band * RPW + grp;            // scan-order row index
             const bool rowok = j < H;
-            const int32_t y = a.sy > 0 ? j : H - 1 - j;
-            const int32_t yp = y - a.sy;                   // previous row in scan order
-            const int32_t yn = y + a.sy;                   // next row in scan order
+            const int32_t y = sy > 0 ? j : H - 1 - j;
+            const int32_t yp = y - sy;                     // previous row in scan order
+            const int32_t yn = y + sy;                     // next row in scan order
             const bool has_next = j + 1 < H;
             // where group 0 finds the row above: memory (first wavefront of a workgroup band
             // that is not the first), LDS (other wavefronts), nowhere (the first row)
             const bool from_global = wave == 0 && super > 0;
             const bool from_lds = wave > 0;
             // the band's last scanline feeds the next wavefront (LDS) or workgroup (memory)
-            const bool to_lds = wave + 1 < NW && band + 1 < a.nbands;
-            const bool to_global = wave == NW - 1 && band + 1 < a.nbands;
+            const bool to_lds = wave + 1 < NW && band + 1 < d.nbands;
+            const bool to_global = wave == NW - 1 && band + 1 < d.nbands;
             const bool store_a = SPLIT == 1 || !beta;
-            const bool store_b = (SPLIT == 1 || beta) && (a.b_live || (to_global && grp == RPW - 1));
+            const bool store_b = (SPLIT == 1 || beta) && (b_live || (to_global && grp == RPW - 1));
             const bool hands = grp == RPW - 1 && (SPLIT == 1 || beta);
             const int32_t* ring_in = rings + (size_t)(wave > 0 ? wave - 1 : 0) * R * QT + l;
             int32_t* ring_out = rings + (size_t)wave * R * QT + l;
             uint32_t seen = 0;                             // columns published by the workgroup above
             // byte offsets at step 0 (column -grp) and per-step strides: at step t the lane's
             // vertex is x = x0 + sx (t - grp) of row y
-            const int32_t x0 = (a.sx > 0 ? 0 : W - 1) - a.sx * grp;
-            const int32_t dc = a.sx * Q * CB, dt = a.sx * QT * 4;
+            const int32_t x0 = (sx > 0 ? 0 : W - 1) - sx * grp;
+            const int32_t dc = sx * Q * CB, dt = sx * QT * 4;
             const int32_t bc = cell_off(y * W + x0, Q * CB);
             const int32_t bt = cell_off(y * W + x0, QT * 4) + lofs;
             const int32_t ba = bt + dt;                    // (x + sx, y)
@@ -156,19 +201,19 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                     uint32_t v = 0, spins = 0;
 #pragma nounroll
                     for (;;) {
-                        v = __hip_atomic_load(a.flags + super - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        v = __hip_atomic_load(progress + super - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         v = __builtin_amdgcn_readfirstlane(v);
-                        if (v >= a.epoch + need) break;
+                        if (v >= epoch + need) break;
                         // give up (and let every other waiter give up) instead of hanging
                         if (++spins > SPIN_LIMIT ||
                             __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                             raise_error(a.error);
-                            v = a.epoch + (uint32_t)W;
+                            v = epoch + (uint32_t)W;
                             break;
                         }
                         __builtin_amdgcn_s_sleep(1);
                     }
-                    seen = v - a.epoch;
+                    seen = v - epoch;
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 // column i = t - grp of this lane's scanline; offsets move by a fixed stride per step
@@ -176,8 +221,8 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 const bool act = rowok && i < (uint32_t)W;
                 const bool nxt = i + 1 < (uint32_t)W;     // the next column in scan order exists
                 const int32_t offc = act ? bc + t * dc : OOB;
-                const int32_t offa = (act && nxt && !a.old_a_zero) ? ba + t * dt : OOB;
-                const int32_t offb = (act && has_next && !a.old_b_zero) ? bb + t * dt : OOB;
+                const int32_t offa = (act && nxt && !old_a_zero) ? ba + t * dt : OOB;
+                const int32_t offb = (act && has_next && !old_b_zero) ? bb + t * dt : OOB;
                 const int32_t offg = (act && from_global && grp == 0) ? bg + t * dt : OOB;
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky) load_cost_run<CK, KX>(rs_c, offc + crun[ky], c[ky]);
@@ -250,8 +295,8 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                     h[ky][kx] = valid[ky][kx] ? ((A + (beta ? -d : d)) >> 1) : PADV;
                                 }
                             }
-                        min_search<T>(h, li, a.clipd, joint, lane);
-                        if constexpr (SPLIT == 1) min_search<T>(h2, li, a.clipd, joint, lane);
+                        min_search<T>(h, li, d.clipd, joint, lane);
+                        if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
                         const int32_t o = bt + s * dt;
                         const int32_t oa = (act && store_a) ? o : OOB;
                         const int32_t ob = (act && store_b) ? o : OOB;
@@ -289,7 +334,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                             if (to_global && (((il + 1) & (a.chunk - 1)) == 0 || il == W - 1)) {
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                                 if (lane == 0)
-                                    __hip_atomic_store(a.flags + super, a.epoch + (uint32_t)(il + 1),
+                                    __hip_atomic_store(progress + super, epoch + (uint32_t)(il + 1),
                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             }
                         }
@@ -298,7 +343,14 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 }
             }
         }
+        // Band complete: every wavefront makes its stores visible to the device before the
+        // workgroup records the scan as done for this band (read by a fused second scan).
+        if (a.npass > 1 && !second) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
+        if (a.npass > 1 && !second && threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(done + super, (uint32_t)pass_index + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -309,37 +361,36 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     const int32_t lane = lane_id();
     const int32_t grp = lane / G, l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
-    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy;
-    const CT* __restrict__ cost = (const CT*)a.cost;
-    const int32_t wave = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int32_t nwaves = (int32_t)((gridDim.x * blockDim.x) >> 6);
+    const int32_t blk = (int32_t)blockIdx.x;
+    const InstDesc d = a.ndesc > 0 ? uniform_desc(a.descs[find_instance(a.descs, a.ndesc, blk, 1)]) : a.one;
+    const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
+    const CT* __restrict__ cost = (const CT*)d.cost;
+    const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     const int32_t cells = W * H;
-    for (int32_t base = wave * RPW; base < cells; base += nwaves * RPW) {
-        const int32_t cell = base + grp;
-        const bool ok = cell < cells;
-        const int32_t y = ok ? cell / W : 0, x = ok ? cell % W : 0;
-        int32_t best = 0x7FFFFFFF, bq = 0x7FFFFFFF;
+    const int32_t cell = (blk - d.first_block) * a.cells_per_block + wave * RPW + grp;
+    const bool ok = cell < cells;
+    const int32_t y = ok ? cell / W : 0, x = ok ? cell % W : 0;
+    int32_t best = 0x7FFFFFFF, bq = 0x7FFFFFFF;
 #pragma unroll
-        for (int ky = 0; ky < KY; ++ky)
+    for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-            for (int kx = 0; kx < KX; ++kx) {
-                const int32_t vy = py * KY + ky, vx = px * KX + kx;
-                if (ok && vx < a.qx && vy < a.qy) {
-                    const int32_t q = vy * a.qx + vx;
-                    const int e = l * T::E + ky * KX + kx;
-                    int32_t v = (int32_t)cost[(size_t)cell * Q + q];
-                    if (x > 0) v += a.t[0][(size_t)(cell - 1) * QT + e];
-                    if (x + 1 < W) v += a.t[1][(size_t)(cell + 1) * QT + e];
-                    if (y > 0) v += a.t[2][(size_t)(cell - W) * QT + e];
-                    if (y + 1 < H) v += a.t[3][(size_t)(cell + W) * QT + e];
-                    if (v < best || (v == best && q < bq)) { best = v; bq = q; }
-                }
+        for (int kx = 0; kx < KX; ++kx) {
+            const int32_t vy = py * KY + ky, vx = px * KX + kx;
+            if (ok && vx < d.qx && vy < d.qy) {
+                const int32_t q = vy * d.qx + vx;
+                const int e = l * T::E + ky * KX + kx;
+                int32_t v = (int32_t)cost[(size_t)cell * Q + q];
+                if (x > 0) v += d.t[0][(size_t)(cell - 1) * QT + e];
+                if (x + 1 < W) v += d.t[1][(size_t)(cell + 1) * QT + e];
+                if (y > 0) v += d.t[2][(size_t)(cell - W) * QT + e];
+                if (y + 1 < H) v += d.t[3][(size_t)(cell + W) * QT + e];
+                if (v < best || (v == best && q < bq)) { best = v; bq = q; }
             }
-        // smallest value, then the smallest label among the lanes holding it
-        const int32_t vmin = group_min<T>(best, lane);
-        const int32_t qmin = group_min<T>(best == vmin ? bq : 0x7FFFFFFF, lane);
-        if (ok && l == 0) a.labels[cell] = qmin;
-    }
+        }
+    // smallest value, then the smallest label among the lanes holding it
+    const int32_t vmin = group_min<T>(best, lane);
+    const int32_t qmin = group_min<T>(best == vmin ? bq : 0x7FFFFFFF, lane);
+    if (ok && l == 0) d.labels[cell] = qmin;
 }
 
 // Prefetch depth: enough steps in flight to cover the memory latency, within

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "edp.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:edp_status|int32_t|const char\*)\s+(edp_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:edp_status|int32_t|const char\*|void)\s+(edp_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -42,7 +42,7 @@ def _prob(**kw):
 
 def _ws(prob, op, tile=-1):
     n = ctypes.c_size_t(0)
-    tu = ctypes.byref(B.Tuning(tile, 0)) if tile >= 0 else None
+    tu = ctypes.byref(B.Tuning(tile, 0, 0, 0, 0, None, 0)) if tile >= 0 else None
     st = B.load().edp_workspace_size(ctypes.byref(prob), op, tu, ctypes.byref(n))
     return st, n.value
 
@@ -83,10 +83,17 @@ def test_tiles_and_workspace_sizes():
     lib = B.load()
     n = ctypes.c_size_t(0)
     p = _prob()
-    bad_split = B.Tuning(2, 0, 2, 0, None, 0)          # tile 2 spans 64 lanes: no room for two halves
+    bad_split = B.Tuning(2, 0, 2, 0, 0, None, 0)          # tile 2 spans 64 lanes: no room for two halves
     assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_split), ctypes.byref(n)) == -1
-    bad_waves = B.Tuning(-1, 0, 0, 9, None, 0)
+    bad_waves = B.Tuning(-1, 0, 0, 9, 0, None, 0)
     assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_waves), ctypes.byref(n)) == -1
+    bad_fuse = B.Tuning(-1, 0, 0, 0, 3, None, 0)
+    assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_fuse), ctypes.byref(n)) == -1
+    # one scan per launch needs fewer ticket counters than the fused pairs, never more memory
+    one = B.Tuning(-1, 0, 0, 0, 1, None, 0)
+    n1 = ctypes.c_size_t(0)
+    assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(one), ctypes.byref(n1)) == 0
+    assert n1.value <= _ws(p, B.OP_EDP)[1]
 
 
 def test_workspace_and_pointer_errors_are_host_side():
@@ -103,3 +110,46 @@ def test_workspace_and_pointer_errors_are_host_side():
     assert lib.edp_dp_scanline(ctypes.byref(p), None, fake, None, None, None, fake, 1 << 30, None) == -1
     assert lib.edp_energy(ctypes.byref(p), fake, fake, 2, fake, None, None) == -1
     assert lib.edp_solve(None, None, fake, fake, fake, fake, need, None) == -1
+
+
+def _items(probs, fake=1 << 40):
+    items = (B.BatchItem * len(probs))()
+    for i, p in enumerate(probs):
+        items[i].problem = p
+        items[i].d_cost = fake
+        items[i].d_labels = fake + (1 << 30)
+        items[i].d_energy = None
+        items[i].tuning = B.Tuning(-1, 0, 0, 0, 0, None, 0)
+    return items
+
+
+def test_batch_workspace_and_host_side_errors():
+    lib = B.load()
+    n = ctypes.c_size_t(0)
+    probs = [_prob(width=160, height=120, qx=16), _prob(width=640, height=480, qx=64),
+             _prob(width=320, height=240, qx=15, qy=15, dtype=2, cost_bound=2500, lam=15, trunc=3)]
+    items = _items(probs)
+    assert lib.edp_batch_workspace_size(3, items, ctypes.byref(n)) == 0
+    single = sum(_ws(p, B.OP_EDP)[1] for p in probs)
+    # every instance's arrays plus a descriptor table; only the control words are shared differently
+    assert n.value >= single - 3 * 4096
+    assert lib.edp_batch_workspace_size(0, items, ctypes.byref(n)) == -1
+    assert lib.edp_batch_workspace_size(3, None, ctypes.byref(n)) == -1
+    assert lib.edp_batch_workspace_size(3, items, None) == -1
+    bad = _items(probs[:1] + [_prob(trunc=0)])
+    assert lib.edp_batch_workspace_size(2, bad, ctypes.byref(n)) == -1
+    nocost = _items(probs)
+    nocost[1].d_cost = None
+    assert lib.edp_batch_workspace_size(3, nocost, ctypes.byref(n)) == -1
+    wide = _items([_prob(qx=40, qy=40)])
+    assert lib.edp_batch_workspace_size(1, wide, ctypes.byref(n)) == -5
+    plan = ctypes.c_void_p(None)
+    assert lib.edp_batch_workspace_size(3, items, ctypes.byref(n)) == 0
+    fake = ctypes.c_void_p(1 << 40)
+    assert lib.edp_batch_plan_create(3, items, None, n.value, None, ctypes.byref(plan)) == -3
+    assert lib.edp_batch_plan_create(3, items, fake, n.value - 1, None, ctypes.byref(plan)) == -3
+    assert lib.edp_batch_plan_create(3, items, fake, n.value, None, None) == -1
+    assert plan.value is None
+    assert lib.edp_batch_solve(None, None) == -1
+    assert lib.edp_batch_plan_info(None, None, None) == -1
+    lib.edp_batch_plan_destroy(None)

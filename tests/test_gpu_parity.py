@@ -30,24 +30,26 @@ def gpu_dp(p, tile=-1, cost_bound=0):
     return lab.cpu().numpy(), row.cpu().numpy(), int(tot.item())
 
 
-def gpu_edp(p, iterations=1, tile=-1, chunk=0, cost_bound=0, split=0, waves=0):
+def gpu_edp(p, iterations=1, tile=-1, chunk=0, cost_bound=0, split=0, waves=0, fuse=0):
     lab, e = edp.solve(to_dev(p.cost), p.qx, p.qy, p.lam, p.trunc, p.mode, iterations=iterations,
                        cost_bound=cost_bound or int(np.abs(p.cost).max()) + 1, tile=tile, chunk=chunk,
-                       split=split, waves=waves)
+                       split=split, waves=waves, fuse=fuse)
     torch.cuda.synchronize()
     return lab.cpu().numpy(), int(e.item())
 
 
 def launch_variants(qx, qy):
-    """Every tile with the built-in launch, plus splits, workgroup sizes and chunks on two tiles."""
+    """Every tile with the built-in launch, plus splits, workgroup sizes, chunks and one scan per
+    launch on two tiles.  Entries: (tile, split, waves, chunk, fuse)."""
     tiles = edp.tiles(qx, qy)
-    out = [(t, 0, 0, 0) for t in tiles]
+    out = [(t, 0, 0, 0, 0) for t in tiles]
     for t in tiles[:1] + tiles[-1:]:
         px, kx, py, ky = edp.tile_info(t)
         for split in (1, 2) if 2 * px * py <= 64 else (1,):
             for waves in (1, 2, 3, 8):
-                out.append((t, split, waves, 1))
-        out.append((t, 0, 0, 16))
+                out.append((t, split, waves, 1, 2 if waves % 2 else 1))
+        out.append((t, 0, 0, 16, 0))
+        out.append((t, 0, 1, 0, 1))
     return out
 
 
@@ -132,11 +134,11 @@ def test_edp_random_all_tiles(case):
     W, H, qx, qy, lam, T, mode, lo, hi, dt, j = case
     p = synth.random_problem(W * 17 + H + j, W, H, qx, qy, lam, T, mode, lo, hi, dt)
     ref = cref.edp(p.cost, qx, qy, lam, T, mode, j, "lrms")
-    for tile, split, waves, chunk in launch_variants(qx, qy):
-        note(f"edp {p.name} j{j} tile {tile} split {split} waves {waves} chunk {chunk}")
-        lab, e = gpu_edp(p, j, tile, chunk, split=split, waves=waves)
-        assert np.array_equal(lab, ref["labels"]), (tile, split, waves, chunk)
-        assert e == ref["energy"], (tile, split, waves, chunk)
+    for tile, split, waves, chunk, fuse in launch_variants(qx, qy):
+        note(f"edp {p.name} j{j} tile {tile} split {split} waves {waves} chunk {chunk} fuse {fuse}")
+        lab, e = gpu_edp(p, j, tile, chunk, split=split, waves=waves, fuse=fuse)
+        assert np.array_equal(lab, ref["labels"]), (tile, split, waves, chunk, fuse)
+        assert e == ref["energy"], (tile, split, waves, chunk, fuse)
 
 
 def test_edp_worked_example():
@@ -150,9 +152,10 @@ def test_edp_worked_example():
 def test_edp_stereo_workload_full_size():
     p = synth.workload("stereo384x288")
     ref = cref.edp(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode, 1, "lrms")
-    for tile, split, waves in ((-1, 0, 0), (3, 2, 8), (4, 2, 4), (1, 1, 2), (5, 1, 1)):
-        note(f"edp stereo384x288 tile {tile} split {split} waves {waves}")
-        lab, e = gpu_edp(p, 1, tile, cost_bound=50, split=split, waves=waves)
+    for tile, split, waves, fuse in ((-1, 0, 0, 0), (-1, 0, 0, 1), (3, 2, 8, 2), (4, 2, 4, 1), (1, 1, 2, 2),
+                                     (5, 1, 1, 2)):
+        note(f"edp stereo384x288 tile {tile} split {split} waves {waves} fuse {fuse}")
+        lab, e = gpu_edp(p, 1, tile, cost_bound=50, split=split, waves=waves, fuse=fuse)
         assert np.array_equal(lab, ref["labels"])
         assert e == ref["energy"]
 
