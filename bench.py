@@ -173,8 +173,10 @@ def bench_batch(edp, torch, steps, warmup):
             "pixel_labels_per_s": pl / (graph_ms / 1e3), "energy_sum": int(sum(energies))}
 
 
-def bench_dp(edp, torch, steps, warmup, rows=4096, cols=2048, q=64, seed=0):
-    """Scanline DP sweep on uniform int16 costs in [0, 50] (a scaled bandwidth workload)."""
+def bench_dp(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0):
+    """Scanline DP sweep on uniform int16 costs in [0, 50]: 8192 independent scanlines of 1024
+    columns and 64 labels (16 stereo frames of 1024 x 512 with 64 disparities), a bandwidth
+    workload of 1 GiB of costs."""
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
@@ -309,7 +311,7 @@ def main():
                                   "ms_per_step": mr["ms_per_step"], "energy": mr["energy"],
                                   "mean_launch_ms": np.array(mr["launch_ms"]).mean(axis=0).tolist()}
         del mr
-        log("scanline DP sweep 2048x4096, Q=64 int16")
+        log("scanline DP sweep 8192 rows x 1024 columns, Q=64 int16")
         extra["dp_sweep"] = bench_dp(edp, torch, max(3, args.steps // 4), 1)
     if not args.no_batch:
         log("batch of 64 uneven instances (hipGraph replay)")

@@ -1,0 +1,143 @@
+"""Launch-shape autotuner for the EDP solver (tile, split, waves, chunk, fuse).
+
+The library's results never depend on the launch shape; only its speed does.
+For a label space (qx, qy), a cost dtype and a grid size, the tuner times
+candidate shapes of ``edp_solve`` on the caller's own cost volume and keeps the
+fastest, checking that every candidate returns the same labels and energy as
+the built-in shape.  Choices are cached in a JSON file keyed by
+``qx x qy : dtype : mode : W x H : iterations``.
+
+Search (staged, so a key costs a few dozen solves):
+  1. every tile that holds the label space with at most 4x padding, each split
+     the tile allows, with 4 wavefronts per workgroup;
+  2. the best (tile, split) with 1, 2, 4 and 8 wavefronts, one or two scans per launch;
+  3. the best so far with progress published every 1, 2, 4, 8 or 16 columns.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import binding as B
+
+SHAPE_KEYS = ("tile", "split", "waves", "chunk", "fuse")
+
+
+def key_of(qx, qy, dtype, mode, W, H, iterations=1) -> str:
+    d = "i16" if dtype in (torch.int16, "i16", 1) else "i32"
+    return f"{qx}x{qy}:{d}:{mode}:{W}x{H}:{iterations}"
+
+
+class TuneCache:
+    """JSON file of tuned launch shapes (read at start, written after each new key)."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path
+        self.table = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.table = json.load(f)
+
+    def get(self, key):
+        return self.table.get(key)
+
+    def put(self, key, shape):
+        self.table[key] = shape
+        if self.path:
+            os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.table, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+
+def _time_solve(cost, p, shape, reps, ws, labels, energy):
+    kw = dict(mode=p["mode"], iterations=p.get("iterations", 1), cost_bound=p["cost_bound"], ws=ws,
+              labels=labels, energy=energy, **{k: shape[k] for k in SHAPE_KEYS})
+    B.solve(cost, p["qx"], p["qy"], p["lam"], p["trunc"], **kw)      # warm-up
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        B.solve(cost, p["qx"], p["qy"], p["lam"], p["trunc"], **kw)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict:
+    """Fastest launch shape for one instance (cost on the GPU, params as for BatchPlan)."""
+    qx, qy = params["qx"], params.get("qy", 1)
+    p = dict(params, qy=qy, mode=params.get("mode", B.TRUNC_PER_DIM))
+    ws = B.Workspace()
+    H, W = cost.shape[:2]
+    labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    energy = torch.empty(1, dtype=torch.int64, device=cost.device)
+    ref_l, ref_e = B.solve(cost, qx, qy, p["lam"], p["trunc"], p["mode"], p.get("iterations", 1),
+                           cost_bound=p["cost_bound"])
+    torch.cuda.synchronize()
+    seen = {}
+
+    def trial(shape):
+        k = tuple(shape[x] for x in SHAPE_KEYS)
+        if k in seen:
+            return seen[k]
+        try:
+            ms = _time_solve(cost, p, shape, reps, ws, labels, energy)
+        except B.EdpError:
+            seen[k] = None
+            return None
+        if not (torch.equal(labels, ref_l) and torch.equal(energy, ref_e)):
+            raise RuntimeError(f"launch shape {shape} changed the result")
+        seen[k] = ms
+        if verbose:
+            print(f"[tune] {key_of(qx, qy, cost.dtype, p['mode'], W, H)} {shape} {ms:.3f} ms", flush=True)
+        return ms
+
+    q = qx * qy
+    tiles = [t for t in B.tiles(qx, qy)]
+    qts = {t: _qt(t) for t in tiles}
+    small = min(qts.values())
+    tiles = [t for t in tiles if qts[t] <= max(4 * q, small)]
+    best, best_ms = None, float("inf")
+
+    def consider(shape):
+        nonlocal best, best_ms
+        ms = trial(shape)
+        if ms is not None and ms < best_ms:
+            best, best_ms = dict(shape), ms
+
+    for t in tiles:
+        px, kx, py, ky = B.tile_info(t)
+        for split in (1, 2) if 2 * px * py <= 64 else (1,):
+            consider(dict(tile=t, split=split, waves=4, chunk=4, fuse=2))
+    base = dict(best)
+    for waves in (1, 2, 4, 8):
+        for fuse in (1, 2):
+            consider(dict(base, waves=waves, fuse=fuse))
+    base = dict(best)
+    for chunk in (1, 2, 4, 8, 16):
+        consider(dict(base, chunk=chunk))
+    return dict(best, ms=best_ms)
+
+
+def _qt(tile):
+    px, kx, py, ky = B.tile_info(tile)
+    return px * kx * py * ky
+
+
+def tune_batch(costs, params, cache: TuneCache | None = None, reps: int = 3, verbose=False) -> list:
+    """Launch shape for every instance of a batch: one tuning per key (largest grid of a label
+    space stands in for its smaller grids of the same key), reused from the cache when present."""
+    cache = cache or TuneCache(None)
+    out = []
+    for c, p in zip(costs, params):
+        H, W = c.shape[:2]
+        k = key_of(p["qx"], p.get("qy", 1), c.dtype, p.get("mode", 0), W, H, p.get("iterations", 1))
+        shape = cache.get(k)
+        if shape is None:
+            shape = tune(c, p, reps, verbose)
+            cache.put(k, shape)
+        out.append({x: shape[x] for x in SHAPE_KEYS})
+    return out

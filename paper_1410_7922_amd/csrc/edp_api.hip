@@ -544,7 +544,7 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
                hipEventRecord((hipEvent_t)tuning->events[k], s) == hipSuccess;
     };
     if (!mark(0)) return EDP_E_HIP;
-    hipError_t err = launch_dp_forward(tile, prob->dtype, a, grid, s);
+    hipError_t err = launch_dp_forward(tile, cost_kind(prob, tile, d_cost), a, grid, s);
     if (err != hipSuccess || !mark(1)) return EDP_E_HIP;
 
     BtArgs b{};

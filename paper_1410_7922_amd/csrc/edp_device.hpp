@@ -100,24 +100,35 @@ template <class CK> struct CostBytes { static constexpr int value = sizeof(CK); 
 template <> struct CostBytes<Pair16> { static constexpr int value = 2; };
 
 // N consecutive costs starting at byte offset off; OOB offsets give zeros.
+// The loaded words stay packed (cost_words) until a cost is used (cost_elem):
+// unpacking at the load would make the loop wait for the load where it is
+// issued instead of where its value is consumed.
 template <class CK, int N>
-__device__ __forceinline__ void load_cost_run(__amdgpu_buffer_rsrc_t r, int32_t off, int32_t* dst) {
+struct CostWords {
+    static constexpr int value = (std::is_same<CK, Pair16>::value && N % 2 == 0) ? N / 2 : N;
+};
+
+template <class CK, int N>
+__device__ __forceinline__ void load_cost_words(__amdgpu_buffer_rsrc_t r, int32_t off, int32_t* w) {
     if constexpr (sizeof(CK) == 4) {
-        load_vec<N>(r, off, dst);
+        load_vec<N>(r, off, w);
     } else if constexpr (std::is_same<CK, Pair16>::value && N % 2 == 0) {
-        int32_t w[N / 2];
         load_vec<N / 2>(r, off, w);
-#pragma unroll
-        for (int k = 0; k < N / 2; ++k) {
-            dst[2 * k] = (int32_t)(int16_t)(w[k] & 0xFFFF);
-            dst[2 * k + 1] = w[k] >> 16;
-        }
     } else {
 #pragma unroll
         for (int k = 0; k < N; ++k)
-            dst[k] = (int32_t)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off + 2 * k, 0, 0);
+            w[k] = (int32_t)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off + 2 * k, 0, 0);
     }
 }
+
+template <class CK, int N>
+__device__ __forceinline__ int32_t cost_elem(const int32_t* w, int k) {
+    if constexpr (std::is_same<CK, Pair16>::value && N % 2 == 0)
+        return (k & 1) ? (w[k >> 1] >> 16) : (int32_t)(int16_t)(w[k >> 1] & 0xFFFF);
+    else
+        return w[k];
+}
+
 // ---- DPP (GFX9 encodings) --------------------------------------------------
 constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2,3,0,1]

@@ -15,6 +15,8 @@
 // Backtracking.  One workgroup per scanline stages the choice indexes of a
 // block of columns in LDS with wide coalesced loads and walks them from
 // x = W-1 down to 1.
+#include <type_traits>
+
 #include "edp_device.hpp"
 #include "edp_internal.hpp"
 
@@ -25,11 +27,11 @@ __device__ __forceinline__ int32_t pack(int32_t v, int32_t ib, int32_t q) {
     return (int32_t)(((uint32_t)v << ib) | (uint32_t)q);
 }
 
-template <class T, class CT, class PT, int PF>
+template <class T, class CK, class PT, int PF>
 __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int RPW = 64 / G;
-    constexpr int CB = (int)sizeof(CT);
+    constexpr int CB = CostBytes<CK>::value;
     const int32_t lane = lane_id();
     const int32_t grp = lane / G, l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
@@ -49,73 +51,103 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     // choice indexes, lane-major: the E labels of a lane are contiguous
     const int32_t prow = rowok ? (y * W * QT + l * E) * (int32_t)sizeof(PT) : OOB;
 
-    int32_t coffb[KY][KX], q[KY][KX];
-    bool valid[KY][KX];
+    int32_t crun[KY], q[KY][KX];                      // cost byte offset of the lane's run of KX labels
+    // padding labels hold PADV: key = (key & keep) | pad, a single AND-OR with no branch
+    int32_t keep[KY][KX], pad[KY][KX];
 #pragma unroll
-    for (int ky = 0; ky < KY; ++ky)
+    for (int ky = 0; ky < KY; ++ky) {
+        const int32_t vy = py * KY + ky;
+        crun[ky] = (rowok && vy < a.qy && px * KX < a.qx) ? (vy * a.qx + px * KX) * CB : OOB;
 #pragma unroll
         for (int kx = 0; kx < KX; ++kx) {
-            const int32_t vy = py * KY + ky, vx = px * KX + kx;
-            valid[ky][kx] = rowok && vx < a.qx && vy < a.qy;
+            const int32_t vx = px * KX + kx;
+            const bool valid = rowok && vx < a.qx && vy < a.qy;
             q[ky][kx] = vy * a.qx + vx;
-            coffb[ky][kx] = valid[ky][kx] ? q[ky][kx] * CB : OOB;
+            keep[ky][kx] = valid ? -1 : 0;
+            pad[ky][kx] = valid ? 0 : PADV;
         }
+    }
 
-    int32_t rc[PF][KY][KX];
-    auto fetch = [&](const int32_t x, int32_t (&c)[KY][KX]) {
+    constexpr int CW = CostWords<CK, KX>::value;
+    int32_t rc[PF][KY][CW];
+    auto fetch = [&](const int32_t x, int32_t (&c)[KY][CW]) {
         const int32_t base = x < W ? crow + x * Q * CB : OOB;
 #pragma unroll
-        for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-            for (int kx = 0; kx < KX; ++kx) c[ky][kx] = load_cost<CT>(rs_c, base + coffb[ky][kx]);
+        for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, base + crun[ky], c[ky]);
     };
 
     int32_t key[KY][KX];
     {
-        int32_t c0[KY][KX];
+        int32_t c0[KY][CW];
         fetch(0, c0);
 #pragma unroll
         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
             for (int kx = 0; kx < KX; ++kx)
-                key[ky][kx] = valid[ky][kx] ? pack(c0[ky][kx], ib, q[ky][kx]) : PADV;
+                key[ky][kx] = (pack(cost_elem<CK, KX>(c0[ky], kx), ib, q[ky][kx]) & keep[ky][kx]) | pad[ky][kx];
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) fetch(1 + u, rc[u]);
 
     int64_t offset = 0;
-    // whole prefetch rounds (steps past W - 1 change nothing), see the scan kernel
-    const int32_t xend = 1 + (W - 1 + PF - 1) / PF * PF;
-    for (int32_t x0 = 1; x0 < xend; x0 += PF) {
+    const uint32_t mask4 = (uint32_t)mask * 0x01010101u;
+    // One step at column x: the choice indexes of x (stored), then S(x) = C(x) + M(S(x-1)).
+    // TAIL: the last, partial round of prefetch slots, whose steps past W - 1 change nothing.
+    auto step = [&](auto tail, const int u, const int32_t x) {
+        constexpr bool TAIL = decltype(tail)::value;
+        const bool live = !TAIL || x < W;
+        const int32_t g = min_search<T>(key, li, clipk, a.joint != 0, lane);
+        const int32_t norm = g >> ib;
+        if constexpr (sizeof(PT) == 1 && E % 4 == 0) {
+            // four choice indexes per dword: low bytes gathered by byte permutes, then masked
 #pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const int32_t x = x0 + u;
-            const bool live = x < W;
-            const int32_t g = min_search<T>(key, li, clipk, a.joint != 0, lane);
-            const int32_t norm = g >> ib;
+            for (int e = 0; e < E; e += 4) {
+                const int32_t* k = &key[0][0] + e;
+                const uint32_t lo = __builtin_amdgcn_perm((uint32_t)k[1], (uint32_t)k[0], 0x0c0c0400u);
+                const uint32_t hi = __builtin_amdgcn_perm((uint32_t)k[3], (uint32_t)k[2], 0x0c0c0400u);
+                const uint32_t w = __builtin_amdgcn_perm(hi, lo, 0x05040100u) & mask4;
+                const int32_t off = live ? prow + (x * QT + e) : OOB;
+                __builtin_amdgcn_raw_buffer_store_b32(w, rs_p, off, 0, 0);
+            }
+        } else {
             uint32_t packed = 0;
 #pragma unroll
-            for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                for (int kx = 0; kx < KX; ++kx) {
-                    const int32_t k = key[ky][kx];
-                    packed |= (uint32_t)(k & mask) << (8 * sizeof(PT) * ((ky * KX + kx) % (4 / sizeof(PT))));
-                    if (((ky * KX + kx) + 1) % (4 / sizeof(PT)) == 0 || (ky * KX + kx) == E - 1) {
-                        const int32_t first = (ky * KX + kx) / (4 / sizeof(PT)) * (4 / sizeof(PT));
-                        const int32_t off = live ? prow + (x * QT + first) * (int32_t)sizeof(PT) : OOB;
-                        const int32_t nb = ((ky * KX + kx) - first + 1) * (int32_t)sizeof(PT);
-                        if (nb == 4) __builtin_amdgcn_raw_buffer_store_b32(packed, rs_p, off, 0, 0);
-                        else if (nb == 2) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)packed, rs_p, off, 0, 0);
-                        else __builtin_amdgcn_raw_buffer_store_b8((uint8_t)packed, rs_p, off, 0, 0);
-                        packed = 0;
-                    }
-                    const int32_t v = rc[u][ky][kx] + (k >> ib) - norm;
-                    const int32_t nk = valid[ky][kx] ? pack(v, ib, q[ky][kx]) : PADV;
-                    key[ky][kx] = live ? nk : key[ky][kx];
+            for (int e = 0; e < E; ++e) {
+                const int32_t k = (&key[0][0])[e];
+                packed |= (uint32_t)(k & mask) << (8 * sizeof(PT) * (e % (4 / sizeof(PT))));
+                if ((e + 1) % (4 / sizeof(PT)) == 0 || e == E - 1) {
+                    const int32_t first = e / (4 / sizeof(PT)) * (4 / sizeof(PT));
+                    const int32_t off = live ? prow + (x * QT + first) * (int32_t)sizeof(PT) : OOB;
+                    const int32_t nb = (e - first + 1) * (int32_t)sizeof(PT);
+                    if (nb == 4) __builtin_amdgcn_raw_buffer_store_b32(packed, rs_p, off, 0, 0);
+                    else if (nb == 2) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)packed, rs_p, off, 0, 0);
+                    else __builtin_amdgcn_raw_buffer_store_b8((uint8_t)packed, rs_p, off, 0, 0);
+                    packed = 0;
                 }
-            offset += live ? norm : 0;
-            fetch(x + PF, rc[u]);
+            }
         }
+#pragma unroll
+        for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < KX; ++kx) {
+                const int32_t k = key[ky][kx];
+                const int32_t v = cost_elem<CK, KX>(rc[u][ky], kx) + (k >> ib) - norm;
+                const int32_t nk = (pack(v, ib, q[ky][kx]) & keep[ky][kx]) | pad[ky][kx];
+                key[ky][kx] = live ? nk : k;
+            }
+        offset += live ? norm : 0;
+        fetch(x + PF, rc[u]);
+    };
+    // whole prefetch rounds, then at most one partial round
+    const int32_t nfull = (W - 1) / PF;
+    int32_t x0 = 1;
+    for (int32_t r = 0; r < nfull; ++r, x0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) step(std::false_type{}, u, x0 + u);
+    }
+    if (x0 < W) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) step(std::true_type{}, u, x0 + u);
     }
     int32_t m = PADV;
 #pragma unroll
@@ -169,13 +201,24 @@ __global__ __launch_bounds__(64) void dp_backtrack_kernel(const BtArgs a) {
 template <class T>
 constexpr int dp_pf() { return T::E <= 4 ? 4 : 2; }
 
-template <class T, class CT>
+template <class T, class CK>
 static hipError_t run_fwd(const DpArgs& a, int grid, hipStream_t s) {
     if (T::QT <= 256)
-        hipLaunchKernelGGL((dp_forward_kernel<T, CT, uint8_t, dp_pf<T>()>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint8_t, dp_pf<T>()>), dim3(grid), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((dp_forward_kernel<T, CT, uint16_t, dp_pf<T>()>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint16_t, dp_pf<T>()>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+// cost kind as for the scan kernel: 1 int16, 2 int32, 3 int16 read in aligned pairs
+template <class T>
+static hipError_t fwd_kind(int kind, const DpArgs& a, int grid, hipStream_t s) {
+    if (kind == 1) return run_fwd<T, int16_t>(a, grid, s);
+    if (kind == 3) {
+        if constexpr (T::KX % 2 == 0) return run_fwd<T, Pair16>(a, grid, s);
+        return hipErrorInvalidValue;
+    }
+    return run_fwd<T, int32_t>(a, grid, s);
 }
 
 template <class T>
@@ -188,12 +231,11 @@ static hipError_t run_bt(const BtArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_dp_forward(int tile, int dtype, const DpArgs& a, int grid, hipStream_t s) {
+hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s) {
     switch (tile) {
-#define EDP_CASE(id, px, kx, py, ky)                                                  \
-    case id:                                                                          \
-        return dtype == 1 ? run_fwd<Tile<px, kx, py, ky>, int16_t>(a, grid, s)        \
-                          : run_fwd<Tile<px, kx, py, ky>, int32_t>(a, grid, s);
+#define EDP_CASE(id, px, kx, py, ky) \
+    case id:                         \
+        return fwd_kind<Tile<px, kx, py, ky>>(kind, a, grid, s);
         EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE
     }

@@ -165,7 +165,7 @@ struct BatchEnergyArgs {
 hipError_t launch_edp_pass(int tile, int kind, int split, const PassArgs& a, int grid, int waves,
                            hipStream_t s);
 hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
-hipError_t launch_dp_forward(int tile, int dtype, const DpArgs& a, int grid, hipStream_t s);
+hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s);
 hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
 hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);
 hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s);

@@ -49,9 +49,19 @@ __device__ __forceinline__ void lds_put(int32_t* p, int32_t v) {
 __device__ __forceinline__ int32_t cell_off(int32_t cell, int32_t bytes) {
     return (int32_t)((uint32_t)cell * (uint32_t)bytes);
 }
-__device__ __forceinline__ void raise_error(uint32_t* error) {
-    __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Flags and the error word are read and written as global (not flat) atomics:
+// flat accesses may complete out of order with the buffer loads of the
+// prefetch ring, which would force the compiler to drain every load in flight
+// wherever a prefetched value is used.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+__device__ __forceinline__ gu32* glob(uint32_t* p) { return (gu32*)p; }
+__device__ __forceinline__ uint32_t flag_get(uint32_t* p) {
+    return __hip_atomic_load(glob(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void flag_put(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(glob(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void raise_error(uint32_t* error) { flag_put(error, 1u); }
 
 template <class T, class CK, int SPLIT, int PF>
 __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs a) {
@@ -114,9 +124,9 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 for (int32_t b = super; b <= last; ++b) {
                     uint32_t spins = 0;
 #pragma nounroll
-                    while (__hip_atomic_load(done + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                    while (flag_get(done + b) < want) {
                         if (++spins > SPIN_LIMIT_BAND ||
-                            __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            flag_get(a.error) != 0) {
                             raise_error(a.error);
                             break;
                         }
@@ -186,7 +196,8 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
             // wait for exactly the slot in use instead of for every load in flight
             const int32_t nsteps = (W + RPW - 1 + PF - 1) / PF * PF;
 
-            int32_t rc[PF][KY][KX], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
+            constexpr int CW = CostWords<CK, KX>::value;
+            int32_t rc[PF][KY][CW], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
             int32_t carry[KY][KX], out[KY][KX];
 #pragma unroll
             for (int ky = 0; ky < KY; ++ky)
@@ -194,19 +205,19 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = out[ky][kx] = 0;
 
             // Issue the loads of step t into one ring slot (no branch around a load).
-            auto fetch = [&](const int32_t t, int32_t (&c)[KY][KX], int32_t (&ma)[KY][KX],
+            auto fetch = [&](const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX],
                              int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX]) {
                 if (from_global && t < W && seen < (uint32_t)t + 1) {   // wave-uniform
                     const uint32_t need = (uint32_t)t + 1;
                     uint32_t v = 0, spins = 0;
 #pragma nounroll
                     for (;;) {
-                        v = __hip_atomic_load(progress + super - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        v = flag_get(progress + super - 1);
                         v = __builtin_amdgcn_readfirstlane(v);
                         if (v >= epoch + need) break;
                         // give up (and let every other waiter give up) instead of hanging
                         if (++spins > SPIN_LIMIT ||
-                            __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            flag_get(a.error) != 0) {
                             raise_error(a.error);
                             v = epoch + (uint32_t)W;
                             break;
@@ -225,7 +236,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 const int32_t offb = (act && has_next && !old_b_zero) ? bb + t * dt : OOB;
                 const int32_t offg = (act && from_global && grp == 0) ? bg + t * dt : OOB;
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky) load_cost_run<CK, KX>(rs_c, offc + crun[ky], c[ky]);
+                for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, offc + crun[ky], c[ky]);
                 load_vec<E>(rs_ma, offa, &ma[0][0]);
                 load_vec<E>(rs_mb, offb, &mb[0][0]);
                 load_vec<E>(rs_b, offg, &gb[0][0]);
@@ -286,7 +297,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                     if (i == 0) cr = 0;
                                 }
                                 if (grp == 0) mb = from_global ? rb[u][ky][kx] : lb[ky][kx];
-                                const int32_t A = rc[u][ky][kx] + cr + mb;
+                                const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + cr + mb;
                                 const int32_t d = rmb[u][ky][kx] - rma[u][ky][kx];
                                 if constexpr (SPLIT == 1) {
                                     h[ky][kx] = valid[ky][kx] ? ((A + d) >> 1) : PADV;
@@ -334,8 +345,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                             if (to_global && (((il + 1) & (a.chunk - 1)) == 0 || il == W - 1)) {
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                                 if (lane == 0)
-                                    __hip_atomic_store(progress + super, epoch + (uint32_t)(il + 1),
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                    flag_put(progress + super, epoch + (uint32_t)(il + 1));
                             }
                         }
                         fetch(s + PF, rc[u], rma[u], rmb[u], rb[u]);
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
         __syncthreads();
         if (a.npass > 1 && !second && threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(done + super, (uint32_t)pass_index + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            flag_put(done + super, (uint32_t)pass_index + 1);
         }
     }
 }
