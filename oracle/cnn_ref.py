@@ -1,0 +1,166 @@
+"""Reference of the label-window network -- TEST INFRASTRUCTURE ONLY.
+
+Float64 NumPy forward and backward of the small convolutional network that
+predicts a per-pixel label window, on the same bf16-rounded operands the GPU
+kernels use (bf16 weights and activations, float accumulation).  Only tests
+and the smoke check import this module; it shares no code with the library.
+
+Network (per pixel of the half-resolution grid, channels last):
+  input   pooled cost volume: for each label block of 4 x 4 labels the minimum
+          cost over the block, averaged over the 2 x 2 pixels, divided by the
+          cost bound, rounded to bf16 (64 channels for a 31 x 31 label space)
+  conv3x3 64 -> 32, ReLU;  conv3x3 32 -> 32, ReLU;  conv3x3 32 -> 32, ReLU;
+  conv3x3 32 -> 2 * 31 logits (first half: label column, second: label row)
+  zero padding, weights [Cout][3][3][Cin] (bf16), bias [Cout] (float32)
+Training: softmax cross entropy per head against the label of the top-left
+pixel of each 2 x 2 block, averaged over pixels and summed over the heads;
+Adam on float32 master weights.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(f)
+    if np.any(nan):
+        out[nan] = np.nan
+    return out
+
+
+def label_blocks(q: int, block: int = 4):
+    """Label index ranges [lo, hi) of the pooling blocks along one label axis."""
+    return [(s, min(s + block, q)) for s in range(0, q, block)]
+
+
+def pool_cost(cost, qx, qy, cmax, block=4):
+    """cost [H][W][qy*qx] (H, W even) -> float64 [H/2][W/2][by*bx], bf16-rounded."""
+    H, W, Q = cost.shape
+    assert Q == qx * qy and H % 2 == 0 and W % 2 == 0
+    c = np.asarray(cost, dtype=np.int64).reshape(H, W, qy, qx)
+    bx, by = label_blocks(qx, block), label_blocks(qy, block)
+    out = np.zeros((H // 2, W // 2, len(by) * len(bx)), np.float64)
+    for j, (y0, y1) in enumerate(by):
+        for i, (x0, x1) in enumerate(bx):
+            m = c[:, :, y0:y1, x0:x1].min(axis=(2, 3))               # [H][W]
+            s = m[0::2, 0::2] + m[0::2, 1::2] + m[1::2, 0::2] + m[1::2, 1::2]
+            out[:, :, j * len(bx) + i] = s / (4.0 * cmax)
+    return bf16(out)
+
+
+def conv3x3(x, w, b):
+    """x [h][w][cin], w [cout][3][3][cin], b [cout] -> [h][w][cout] (zero padding)."""
+    h, wd, cin = x.shape
+    cout = w.shape[0]
+    xp = np.zeros((h + 2, wd + 2, cin))
+    xp[1:-1, 1:-1] = x
+    out = np.zeros((h, wd, cout)) + b
+    for dy in range(3):
+        for dx in range(3):
+            out += xp[dy:dy + h, dx:dx + wd] @ w[:, dy, dx, :].T
+    return out
+
+
+def conv3x3_backward(x, w, dy_):
+    """Gradients of conv3x3 w.r.t. its input and weights for output gradient dy_."""
+    h, wd, cin = x.shape
+    xp = np.zeros((h + 2, wd + 2, cin))
+    xp[1:-1, 1:-1] = x
+    dxp = np.zeros_like(xp)
+    dw = np.zeros_like(w)
+    for dy in range(3):
+        for dx in range(3):
+            dxp[dy:dy + h, dx:dx + wd] += dy_ @ w[:, dy, dx, :]
+            dw[:, dy, dx, :] = np.einsum("hwo,hwi->oi", dy_, xp[dy:dy + h, dx:dx + wd])
+    return dxp[1:-1, 1:-1], dw
+
+
+LAYERS = ((64, 32), (32, 32), (32, 32), (32, 62))
+
+
+def init_params(rng, layers=LAYERS):
+    """He-uniform float32 master weights [Cout][3][3][Cin] and zero biases."""
+    params = []
+    for cin, cout in layers:
+        bound = np.sqrt(6.0 / (9 * cin))
+        params.append({"w": rng.uniform(-bound, bound, (cout, 3, 3, cin)).astype(np.float32),
+                       "b": np.zeros(cout, np.float32)})
+    return params
+
+
+def forward(x, params):
+    """Returns (logits [h][w][62] float64, inputs of every layer (bf16-rounded))."""
+    acts = [bf16(x)]
+    for li, p in enumerate(params):
+        z = conv3x3(acts[-1], bf16(p["w"]), np.asarray(p["b"], np.float64))
+        if li + 1 < len(params):
+            acts.append(bf16(np.maximum(z, 0.0)))
+        else:
+            return z, acts
+    raise AssertionError
+
+
+def targets(labels, qx):
+    """Class targets of the half-resolution grid: the top-left label of each 2 x 2 block."""
+    lab = np.asarray(labels)[0::2, 0::2]
+    return lab % qx, lab // qx
+
+
+def ce_loss_grad(logits, tx, ty, nclass=31):
+    """Mean over pixels of the two heads' softmax cross entropies, and its logit gradient."""
+    h, w, _ = logits.shape
+    n = h * w
+    loss = 0.0
+    grad = np.zeros_like(logits)
+    for head, t in ((0, tx), (1, ty)):
+        z = logits[:, :, head * nclass:(head + 1) * nclass]
+        zmax = z.max(axis=2, keepdims=True)
+        e = np.exp(z - zmax)
+        s = e.sum(axis=2, keepdims=True)
+        lse = np.log(s)[:, :, 0] + zmax[:, :, 0]
+        picked = np.take_along_axis(z, np.asarray(t)[:, :, None], axis=2)[:, :, 0]
+        loss += float(np.sum(lse - picked)) / n
+        g = e / s
+        np.put_along_axis(g, np.asarray(t)[:, :, None], np.take_along_axis(g, np.asarray(t)[:, :, None], 2) - 1.0, 2)
+        grad[:, :, head * nclass:(head + 1) * nclass] = g / n
+    return loss, grad
+
+
+def backward(params, acts, dlogits):
+    """Gradients of every layer.  The output gradient of a layer enters the products rounded to
+    bf16 (as the GPU's matrix operands); bias gradients use it unrounded."""
+    grads = [None] * len(params)
+    d = dlogits
+    for li in range(len(params) - 1, -1, -1):
+        p = params[li]
+        db = d.sum(axis=(0, 1))
+        dx, dw = conv3x3_backward(acts[li], bf16(p["w"]), bf16(d))
+        grads[li] = {"w": dw, "b": db}
+        if li > 0:
+            d = dx * (acts[li] > 0)
+    return grads
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (bias-corrected) of the float master weights, in place."""
+    m[:] = b1 * m + (1 - b1) * g
+    v[:] = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    p[:] = p - lr * mh / (np.sqrt(vh) + eps)
+
+
+def decode(logits, qx, qy, win, nclass=31):
+    """Window centres at full resolution [2h][2w][2] = (cx, cy): per-head argmax (first maximum),
+    clamped so the win x win box lies inside the label space, repeated over each 2 x 2 block."""
+    r = win // 2
+    cx = np.clip(np.argmax(logits[:, :, :nclass], axis=2), r, qx - 1 - r)
+    cy = np.clip(np.argmax(logits[:, :, nclass:2 * nclass], axis=2), r, qy - 1 - r)
+    c = np.stack([cx, cy], axis=-1)
+    return np.repeat(np.repeat(c, 2, axis=0), 2, axis=1).astype(np.int32)

@@ -36,6 +36,8 @@ def lib():
         L.oracle_dp_scanline.argtypes = [i32] * 8 + [i32p, i32p, i64p, i64p]
         L.oracle_edp.restype = ctypes.c_int
         L.oracle_edp.argtypes = [i32] * 9 + [i32p, i32p, i64p, i64p, i64p]
+        L.oracle_edp_window.restype = ctypes.c_int
+        L.oracle_edp_window.argtypes = [i32] * 9 + [i32p, i32p, i32, i32p, i64p, i64p]
         L.oracle_min_search.restype = ctypes.c_int
         L.oracle_min_search.argtypes = [i32] * 7 + [i64p, i64p, i32p]
         _lib = L
@@ -108,3 +110,22 @@ def edp(cost, qx, qy, lam, trunc, mode, iterations=1, search: str = "lrms", marg
     if marginal:
         out["marginal"] = marg
     return out
+
+
+def edp_window(cost, centers, win, qx, qy, lam, trunc, mode, iterations=1, search: str = "lrms"):
+    """Windowed EDP: the plain EDP on the cost masked outside each vertex's win x win box
+    centred on centers[y][x] = (cx, cy).  Returns dict(labels, energy (unmasked cost), max_abs_sum)."""
+    c = _cost32(cost)
+    H, W, Q = c.shape
+    cen = np.ascontiguousarray(centers, dtype=np.int32)
+    assert cen.shape == (H, W, 2)
+    labels = np.zeros((H, W), np.int32)
+    e = np.zeros(1, np.int64)
+    mx = np.zeros(1, np.int64)
+    rc = lib().oracle_edp_window(W, H, qx, qy, lam, trunc, mode, iterations, SEARCH[search], _p32(c), _p32(cen),
+                                 int(win), _p32(labels), _p64(e), _p64(mx))
+    if rc == -2:
+        raise OverflowError("EDP sum exceeds int32")
+    if rc != 0:
+        raise RuntimeError(f"oracle_edp_window failed: {rc}")
+    return {"labels": labels, "energy": int(e[0]), "max_abs_sum": int(mx[0])}

@@ -14,9 +14,11 @@
  *   DP       S(0)=C(0), S(x+1)=C(x+1)+M(S(x))  Sec. 2 eq. base, Sec. 4.1
  *   EDP      Sec. 4.2 eq. DP_2D_base with C added, S/2 as floor division,
  *            scans P1..P4 in place, eq. DP_2D_1 marginal, eq. DP_2D_2 argmin.
+ *   windowed EDP: the same on a cost volume masked by a sentinel outside a
+ *            per-vertex label box (the definition of the label-window solve).
  *
- * All sums are computed in int64; EDP sums are stored as int32 after a range
- * check (the check's failure is reported, never wrapped).  Single threaded.
+ * All sums are computed and stored in int64 and range-checked against int32
+ * (the check's failure is reported, never wrapped).  Single threaded.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -185,16 +187,35 @@ static const int KDX[4] = {1, -1, 0, 0};
 static const int KDY[4] = {0, 0, 1, -1};
 static const int KOPP[4] = {1, 0, 3, 2};
 
-/* Literal EDP (Algorithm 1 steps 3-5).  sums: 4 x [H][W][Q] int32 (caller may pass
- * NULL to let the oracle allocate).  marginal_out [H][W][Q] int64 is nullable. */
-int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
-               int search, const int32_t *cost, int32_t *labels, int64_t *energy_out,
-               int64_t *max_abs_out, int64_t *marginal_out) {
+/* Literal EDP (Algorithm 1 steps 3-5) with an optional label window per vertex.
+ *
+ * Without a window (centers NULL) this is the plain EDP.  With a window, the
+ * cost of every label outside the win x win box centred on centers[y][x] =
+ * (cx, cy) is taken as the sentinel SENT, larger than any reachable sum of the
+ * in-box labels: the windowed EDP is defined as the plain EDP on that masked
+ * cost volume.  Sums are kept in int64; the int32 range check covers the
+ * in-box labels only (the out-of-box sums carry the sentinel).  The energy of
+ * the result is evaluated with the unmasked cost.
+ * marginal_out [H][W][Q] int64 is nullable. */
+#define SENT ((int64_t)1 << 40)
+
+static int in_box(const int32_t *centers, int win, int W, int qx, int x, int y, int v) {
+    if (!centers) return 1;
+    const int32_t *c = centers + ((size_t)y * W + x) * 2;
+    int r = win / 2;
+    int vx = v % qx, vy = v / qx;
+    return vx >= c[0] - r && vx <= c[0] + r && vy >= c[1] - r && vy <= c[1] + r;
+}
+
+static int edp_core(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
+                    int search, const int32_t *cost, const int32_t *centers, int win, int32_t *labels,
+                    int64_t *energy_out, int64_t *max_abs_out, int64_t *marginal_out) {
     if (!check_args(W, H, qx, qy, lam, trunc, mode) || iterations < 0) return OR_E_ARGS;
+    if (centers && (win < 1 || win % 2 == 0)) return OR_E_ARGS;
     prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
     int Q = p.q;
     size_t cells = (size_t)W * H;
-    int32_t *S = calloc((size_t)4 * cells * Q, sizeof(int32_t));
+    int64_t *S = calloc((size_t)4 * cells * Q, sizeof(int64_t));
     int64_t *h = malloc(sizeof(int64_t) * Q);
     int64_t *m = malloc(sizeof(int64_t) * 4 * Q);
     int64_t *acc = malloc(sizeof(int64_t) * Q);
@@ -222,7 +243,7 @@ int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int i
                             for (int v = 0; v < Q; ++v) mk[v] = 0;
                             continue;
                         }
-                        const int32_t *sk = S + ((size_t)k * cells + (size_t)py * W + px) * Q;
+                        const int64_t *sk = S + ((size_t)k * cells + (size_t)py * W + px) * Q;
                         for (int v = 0; v < Q; ++v) h[v] = floor_half(sk[v]);
                         msearch(&p, search, h, mk, scratch);
                     }
@@ -231,7 +252,7 @@ int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int i
                     for (int j = 0; j < 2; ++j) {       /* eq. DP_2D_base with C added */
                         int kp = comp[j];
                         for (int v = 0; v < Q; ++v) {
-                            int64_t s = c[v];
+                            int64_t s = in_box(centers, win, W, qx, x, y, v) ? (int64_t)c[v] : SENT;
                             for (int k = 0; k < 4; ++k)
                                 if (k != KOPP[kp]) s += m[(size_t)k * Q + v];
                             s -= m[(size_t)KOPP[kp] * Q + v];
@@ -239,12 +260,14 @@ int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int i
                         }
                     }
                     for (int j = 0; j < 2; ++j) {
-                        int32_t *dst = S + ((size_t)comp[j] * cells + (size_t)y * W + x) * Q;
+                        int64_t *dst = S + ((size_t)comp[j] * cells + (size_t)y * W + x) * Q;
                         for (int v = 0; v < Q; ++v) {
                             int64_t s = nw[(size_t)j * Q + v];
-                            if (iabs64(s) > maxabs) maxabs = iabs64(s);
-                            if (s > INT32_MAX || s < INT32_MIN) status = OR_E_RANGE;
-                            dst[v] = (int32_t)s;
+                            if (in_box(centers, win, W, qx, x, y, v)) {
+                                if (iabs64(s) > maxabs) maxabs = iabs64(s);
+                                if (s > INT32_MAX || s < INT32_MIN) status = OR_E_RANGE;
+                            }
+                            dst[v] = s;
                         }
                     }
                 }
@@ -254,11 +277,11 @@ int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int i
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {                   /* eq. DP_2D_1 with C, eq. DP_2D_2 */
             const int32_t *c = cost + ((size_t)y * W + x) * Q;
-            for (int v = 0; v < Q; ++v) acc[v] = c[v];
+            for (int v = 0; v < Q; ++v) acc[v] = in_box(centers, win, W, qx, x, y, v) ? (int64_t)c[v] : SENT;
             for (int k = 0; k < 4; ++k) {
                 int px = x - KDX[k], py = y - KDY[k];
                 if (px < 0 || px >= W || py < 0 || py >= H) continue;
-                const int32_t *sk = S + ((size_t)k * cells + (size_t)py * W + px) * Q;
+                const int64_t *sk = S + ((size_t)k * cells + (size_t)py * W + px) * Q;
                 for (int v = 0; v < Q; ++v) h[v] = floor_half(sk[v]);
                 msearch(&p, search, h, m, scratch);
                 for (int v = 0; v < Q; ++v) acc[v] += m[v];
@@ -273,6 +296,22 @@ int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int i
     *max_abs_out = maxabs;
     free(S); free(h); free(m); free(acc); free(scratch); free(nw);
     return status;
+}
+
+int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
+               int search, const int32_t *cost, int32_t *labels, int64_t *energy_out,
+               int64_t *max_abs_out, int64_t *marginal_out) {
+    return edp_core(W, H, qx, qy, lam, trunc, mode, iterations, search, cost, NULL, 1, labels,
+                    energy_out, max_abs_out, marginal_out);
+}
+
+/* Windowed EDP: centers [H][W][2] (cx, cy) label coordinates, odd window side win. */
+int oracle_edp_window(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
+                      int search, const int32_t *cost, const int32_t *centers, int win,
+                      int32_t *labels, int64_t *energy_out, int64_t *max_abs_out) {
+    if (!centers) return OR_E_ARGS;
+    return edp_core(W, H, qx, qy, lam, trunc, mode, iterations, search, cost, centers, win, labels,
+                    energy_out, max_abs_out, NULL);
 }
 
 /* M on a batch of n vectors h[n][Q] (search 0: SFMS with arg (nullable); 1: LRMS). */
