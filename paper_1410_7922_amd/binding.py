@@ -291,3 +291,105 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# label-window network (include/edp_learn.h)
+# ---------------------------------------------------------------------------
+
+LEARN_EXPORTS = ("edp_dsi_motion", "edp_pool_cost", "edp_conv3x3_forward", "edp_conv3x3_dgrad",
+                 "edp_conv3x3_wgrad", "edp_colsum", "edp_ce_loss", "edp_adam", "edp_decode_windows",
+                 "edp_window_targets")
+
+
+def _learn_lib():
+    L = load()
+    if getattr(L, "_learn_ready", False):
+        return L
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    sig = {
+        "edp_dsi_motion": [vp, vp, i32, i32, i32, i32, vp, vp],
+        "edp_pool_cost": [vp, i32, i32, i32, i32, i32, vp, vp],
+        "edp_conv3x3_forward": [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp],
+        "edp_conv3x3_dgrad": [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp],
+        "edp_conv3x3_wgrad": [vp, vp, i32, i32, i32, i32, vp, vp],
+        "edp_colsum": [vp, i32, i32, i32, vp, vp],
+        "edp_ce_loss": [vp, i32, i32, vp, vp, i32, vp, vp, vp, vp],
+        "edp_adam": [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, i32, vp],
+        "edp_decode_windows": [vp, i32, i32, i32, i32, i32, i32, i32, vp, vp],
+        "edp_window_targets": [vp, i32, i32, i32, vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L._learn_ready = True
+    return L
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def dsi_motion(i0: torch.Tensor, i1: torch.Tensor, r: int, cmax: int, out: torch.Tensor | None = None):
+    """Motion cost volume [H][W][(2r+1)^2] int32 from two uint8 frames (edp_dsi_motion)."""
+    _device_tensor(i0, "i0")
+    _device_tensor(i1, "i1")
+    H, W = i0.shape
+    n = 2 * r + 1
+    if out is None:
+        out = torch.empty((H, W, n * n), dtype=torch.int32, device=i0.device)
+    _check(_learn_lib().edp_dsi_motion(i0.data_ptr(), i1.data_ptr(), W, H, r, cmax, out.data_ptr(),
+                                       _stream(i0.device)), "edp_dsi_motion")
+    return out
+
+
+def pool_cost(cost: torch.Tensor, qx: int, qy: int, cmax: int, out: torch.Tensor | None = None):
+    """Network input [H/2][W/2][64] bf16 (as int16 storage) from an int32 cost volume (edp_pool_cost)."""
+    _device_tensor(cost, "cost")
+    H, W, _ = cost.shape
+    nch = ((qx + 3) // 4) * ((qy + 3) // 4)
+    if out is None:
+        out = torch.empty((H // 2, W // 2, nch), dtype=torch.int16, device=cost.device)
+    _check(_learn_lib().edp_pool_cost(cost.data_ptr(), W, H, qx, qy, cmax, out.data_ptr(), _stream(cost.device)),
+           "edp_pool_cost")
+    return out
+
+
+def conv3x3_forward(x, w, b, h, wd, cin, cout, relu, y_bf16=None, y_f32=None):
+    _check(_learn_lib().edp_conv3x3_forward(_ptr(x), _ptr(w), _ptr(b), h, wd, cin, cout, int(bool(relu)),
+                                            _ptr(y_bf16), _ptr(y_f32), _stream(x.device)), "edp_conv3x3_forward")
+
+
+def conv3x3_dgrad(dy, w, x, h, wd, cin, cout, wt, dx_f32, dx_bf16):
+    _check(_learn_lib().edp_conv3x3_dgrad(_ptr(dy), _ptr(w), _ptr(x), h, wd, cin, cout, _ptr(wt), _ptr(dx_f32),
+                                          _ptr(dx_bf16), _stream(dy.device)), "edp_conv3x3_dgrad")
+
+
+def conv3x3_wgrad(dy, x, h, wd, cin, cout, dw):
+    _check(_learn_lib().edp_conv3x3_wgrad(_ptr(dy), _ptr(x), h, wd, cin, cout, _ptr(dw), _stream(dy.device)),
+           "edp_conv3x3_wgrad")
+
+
+def colsum(a, rows, cols, ld, out):
+    _check(_learn_lib().edp_colsum(_ptr(a), rows, cols, ld, _ptr(out), _stream(a.device)), "edp_colsum")
+
+
+def ce_loss(logits, n, ld, tx, ty, nclass, grad_f32, grad_bf16, loss):
+    _check(_learn_lib().edp_ce_loss(_ptr(logits), n, ld, _ptr(tx), _ptr(ty), nclass, _ptr(grad_f32),
+                                    _ptr(grad_bf16), _ptr(loss), _stream(logits.device)), "edp_ce_loss")
+
+
+def adam(p, g, m, v, p_bf16, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(_learn_lib().edp_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(p_bf16), p.numel(), lr, beta1, beta2,
+                                 eps, t, _stream(p.device)), "edp_adam")
+
+
+def decode_windows(logits, h, wd, ld, qx, qy, win, nclass, centers):
+    _check(_learn_lib().edp_decode_windows(_ptr(logits), h, wd, ld, qx, qy, win, nclass, _ptr(centers),
+                                           _stream(logits.device)), "edp_decode_windows")
+
+
+def window_targets(labels, W, H, qx, tx, ty):
+    _check(_learn_lib().edp_window_targets(_ptr(labels), W, H, qx, _ptr(tx), _ptr(ty), _stream(labels.device)),
+           "edp_window_targets")

@@ -190,16 +190,14 @@ def stereo_problem(seed: int = 0, W: int = 384, H: int = 288, Q: int = 32, lam: 
                    name=f"stereo{W}x{H}q{Q}s{seed}", meta={"gt": disp})
 
 
-def motion_problem(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, lam: int = 15,
-                   trunc: int = 3, cmax: int = 2500, segments: int = 8, sigma: float = 4.0,
-                   mode: int = TRUNC_PER_DIM, dtype=np.int32) -> Problem:
-    """Two frames with affine motion over Voronoi segments, truncated squared difference cost.
+def motion_frames(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, segments: int = 8,
+                  sigma: float = 4.0):
+    """Two 8-bit frames with affine motion over Voronoi segments, and the planted flow.
 
-    Labels: q = (dy + r) * (2r + 1) + (dx + r), the cost of q at pixel (x, y)
-    compares I0(x, y) with I1(x + dx, y + dy).
+    Returns (i0, i1, fu, fv): uint8 [H][W] frames where I1(x + fu, y + fv) shows I0(x, y),
+    and the integer flow components in [-r, r].
     """
     rng = np.random.default_rng(seed)
-    n = 2 * r + 1
     img0 = textured_image(rng, W, H)
     seg, sx, sy = voronoi_segments(rng, W, H, segments)
     u0 = rng.uniform(-r, r, segments)
@@ -213,21 +211,43 @@ def motion_problem(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, lam: i
     fu = fu.astype(np.int64)
     fv = fv.astype(np.int64)
     img1 = _forward_splat(img0, xx + fu, yy + fv, depth[seg], rng)
-    i0 = _noisy_u8(rng, img0, sigma)
-    i1 = _noisy_u8(rng, img1, sigma)
+    i0 = _noisy_u8(rng, img0, sigma).astype(np.uint8)
+    i1 = _noisy_u8(rng, img1, sigma).astype(np.uint8)
+    return i0, i1, fu, fv
+
+
+def motion_cost(i0: np.ndarray, i1: np.ndarray, r: int, cmax: int) -> np.ndarray:
+    """Truncated squared difference cost [H][W][(2r+1)^2] int64: label q = (dy + r)(2r + 1) + (dx + r)
+    compares I0(x, y) with I1(x + dx, y + dy); a displaced position outside the frame costs cmax."""
+    H, W = i0.shape
+    n = 2 * r + 1
+    a = i0.astype(np.float64)
     pad = np.full((H + 2 * r, W + 2 * r), np.nan)
     pad[r:r + H, r:r + W] = i1
     cost = np.empty((n * n, H, W), np.int64)
     for dy in range(-r, r + 1):
         for dx in range(-r, r + 1):
             sh = pad[r + dy:r + dy + H, r + dx:r + dx + W]
-            d2 = (i0 - sh) ** 2
+            d2 = (a - sh) ** 2
             cq = np.where(np.isnan(d2), cmax, np.minimum(np.nan_to_num(d2, nan=0.0), cmax))
             cost[(dy + r) * n + (dx + r)] = cq.astype(np.int64)
-    cost = np.ascontiguousarray(np.moveaxis(cost, 0, -1).astype(dtype))
+    return np.ascontiguousarray(np.moveaxis(cost, 0, -1))
+
+
+def motion_problem(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, lam: int = 15,
+                   trunc: int = 3, cmax: int = 2500, segments: int = 8, sigma: float = 4.0,
+                   mode: int = TRUNC_PER_DIM, dtype=np.int32) -> Problem:
+    """Two frames with affine motion over Voronoi segments, truncated squared difference cost.
+
+    Labels: q = (dy + r) * (2r + 1) + (dx + r), the cost of q at pixel (x, y)
+    compares I0(x, y) with I1(x + dx, y + dy).
+    """
+    n = 2 * r + 1
+    i0, i1, fu, fv = motion_frames(seed, W, H, r, segments, sigma)
+    cost = np.ascontiguousarray(motion_cost(i0, i1, r, cmax).astype(dtype))
     gt = (fv + r) * n + (fu + r)
     return Problem(cost, n, n, lam, trunc, mode, name=f"motion{W}x{H}r{r}s{seed}",
-                   meta={"gt": gt})
+                   meta={"gt": gt, "frames": (i0, i1)})
 
 
 def random_problem(seed: int, W: int, H: int, qx: int, qy: int = 1, lam: int = 7, trunc: int = 2,

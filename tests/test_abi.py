@@ -9,11 +9,11 @@ import pytest
 from paper_1410_7922_amd import binding as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "edp.h")
+HEADERS = [os.path.join(ROOT, "include", n) for n in ("edp.h", "edp_learn.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^\s*(?:edp_status|int32_t|const char\*|void)\s+(edp_\w+)\s*\(", text, re.M)))
 
 
@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 7
     for n in names:
         assert hasattr(lib, n), n
-    assert set(B.EXPORTS) <= set(names)
+    assert set(B.EXPORTS) | set(B.LEARN_EXPORTS) <= set(names)
 
 
 def test_status_strings():
