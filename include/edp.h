@@ -125,6 +125,24 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
                      void* stream);
 
 /*
+ * Label-window EDP: the EDP of edp_solve restricted, at every vertex x, to the
+ * win x win box of labels centred on d_centers[y][x] = (cx, cy) -- by
+ * definition the plain EDP on the cost volume with every label outside the
+ * vertex's box given an infinite cost.  Each vertex keeps its box in a frame
+ * of 8 x 8 labels and every sum handed to a neighbour is evaluated in the
+ * neighbour's frame, so the work per vertex does not grow with Q.  win odd,
+ * 1 <= win <= 8, boxes inside the label space (win/2 <= cx < qx - win/2, same
+ * for cy); int32 costs.  The energy is that of the labels on the full cost.
+ * tuning: tile must be -1 or 14, split 1; waves, chunk, fuse as for edp_solve.
+ *   d_centers [H][W][2] int32;  d_labels [H][W] int32 labels of the full space
+ */
+edp_status edp_window_workspace_size(const edp_problem* prob, int32_t win, const edp_tuning* tuning,
+                                     size_t* bytes);
+edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
+                              const int32_t* d_centers, int32_t win, int32_t* d_labels, int64_t* d_energy,
+                              void* d_ws, size_t ws_bytes, void* stream);
+
+/*
  * Batches: many independent EDP instances (Algorithm 1 each, any mix of grid
  * sizes, label spaces, dtypes and parameters) solved by shared persistent
  * launches.  Instances with the same launch shape (tile, cost kind, split,

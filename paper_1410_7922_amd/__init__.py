@@ -6,4 +6,4 @@ The solvers live in ``libedp.so`` (C ABI: include/edp.h); ``binding`` marshals
 torch tensors into it.
 """
 from .binding import (TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace, dp_scanline,  # noqa: F401
-                      energy, load, solve, tile_info, tiles, workspace_size)
+                      energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)

@@ -24,7 +24,8 @@ OP_EDP = 1
 
 EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
            "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
-           "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy")
+           "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy", "edp_window_workspace_size",
+           "edp_solve_windowed")
 
 
 class Problem(ctypes.Structure):
@@ -77,9 +78,11 @@ def load(path: str = LIB_PATH):
     L.edp_batch_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.edp_batch_plan_destroy.argtypes = [vp]
     L.edp_batch_plan_destroy.restype = None
+    L.edp_window_workspace_size.argtypes = [pprob, ctypes.c_int32, ptun, ctypes.POINTER(sz)]
+    L.edp_solve_windowed.argtypes = [pprob, ptun, vp, vp, ctypes.c_int32, vp, vp, vp, sz, vp]
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
-                 "edp_batch_plan_info"):
+                 "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -207,6 +210,30 @@ def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 
     _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk, events, split, waves, fuse), cost.data_ptr(),
                             labels.data_ptr(),
                             energy.data_ptr(), w.data_ptr(), w.numel(), _stream(cost.device)), "edp_solve")
+    return labels, energy
+
+
+def solve_windowed(cost: torch.Tensor, centers: torch.Tensor, win: int, qx: int, qy: int, lam: int = 15,
+                   trunc: int = 3, mode: int = TRUNC_PER_DIM, iterations: int = 1, cost_bound: int = 0,
+                   ws: Workspace | None = None, labels: torch.Tensor | None = None,
+                   energy: torch.Tensor | None = None, events=None, waves: int = 0, chunk: int = 0, fuse: int = 0):
+    """Label-window EDP (edp_solve_windowed).  Returns (labels [H][W] int32, energy [1] int64)."""
+    _device_tensor(cost, "cost")
+    _device_tensor(centers, "centers")
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound)
+    tu = _tuning(-1, chunk, events, 0, waves, fuse)
+    n = ctypes.c_size_t(0)
+    _check(load().edp_window_workspace_size(ctypes.byref(prob), win, tu, ctypes.byref(n)),
+           "edp_window_workspace_size")
+    w = (ws or _default_ws).get(int(n.value), cost.device)
+    H, W, _ = cost.shape
+    if labels is None:
+        labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    if energy is None:
+        energy = torch.empty(1, dtype=torch.int64, device=cost.device)
+    _check(load().edp_solve_windowed(ctypes.byref(prob), tu, cost.data_ptr(), centers.data_ptr(), win,
+                                     labels.data_ptr(), energy.data_ptr(), w.data_ptr(), w.numel(),
+                                     _stream(cost.device)), "edp_solve_windowed")
     return labels, energy
 
 

@@ -316,8 +316,62 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
     g.descs = c.descs;
     g.ndesc = a.ndesc;
     g.cells_per_block = c.cells_per_block;
-    if (launch_edp_aggregate(c.tile, c.dtype, g, c.agg_blocks, s) != hipSuccess) return EDP_E_HIP;
+    const hipError_t e = c.kind == KIND_WINDOW ? launch_edp_aggregate_win(g, c.agg_blocks, s)
+                                               : launch_edp_aggregate(c.tile, c.dtype, g, c.agg_blocks, s);
+    return e == hipSuccess ? EDP_OK : EDP_E_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Label-window solve
+// ---------------------------------------------------------------------------
+
+// Costs outside a window inside the 8 x 8 frames: larger than any sum the range guard allows
+// for the window labels, small enough that sums with it stay inside int32.
+constexpr int32_t kWinBig = 1 << 29;
+
+// The frame problem the scans run on: 8 x 8 labels per vertex, int32 costs.
+edp_problem frame_problem(const edp_problem* p) {
+    edp_problem f = *p;
+    f.qx = WIN_FRAME;
+    f.qy = WIN_FRAME;
+    f.dtype = EDP_I32;
+    return f;
+}
+
+struct WinLayout {
+    EdpLayout edp;       // T arrays and control words of the frame problem
+    size_t cw, shifts;   // frame costs [cells][64] int32, shifts [cells][2] uint32
+    size_t total;
+};
+
+edp_status win_launch(const edp_problem* prob, int32_t win, const edp_tuning* tu, Launch* la) {
+    edp_status st = check_problem(prob, EDP_OP_EDP);
+    if (st != EDP_OK) return st;
+    if (win < 1 || win > WIN_FRAME || !(win & 1) || win > prob->qx || win > prob->qy) return EDP_E_INVALID;
+    if (prob->dtype != EDP_I32) return EDP_E_UNSUPPORTED;
+    if (tu && ((tu->tile >= 0 && tu->tile != WIN_TILE) || (tu->split > 1) || tu->chunk < 0 || tu->n_events < 0))
+        return EDP_E_INVALID;
+    edp_tuning t{};
+    if (tu) t = *tu;
+    t.tile = WIN_TILE;
+    t.split = 1;
+    const edp_problem f = frame_problem(prob);
+    st = pick_launch(&f, &t, la);
+    if (st != EDP_OK) return st;
+    const int64_t cells = (int64_t)prob->width * prob->height;
+    if (!edp_offsets_fit(&f, WIN_TILE) || cells * 8 >= 0x7FFF0000LL) return EDP_E_UNSUPPORTED;
     return EDP_OK;
+}
+
+WinLayout win_layout(const edp_problem* prob, const Launch& la) {
+    WinLayout L{};
+    const edp_problem f = frame_problem(prob);
+    L.edp = edp_layout(&f, la);
+    const size_t cells = (size_t)prob->width * prob->height;
+    L.cw = L.edp.total;
+    L.shifts = L.cw + up(cells * WIN_FRAME * WIN_FRAME * 4);
+    L.total = L.shifts + up(cells * 8);
+    return L;
 }
 
 edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t* labels, int grid4,
@@ -749,6 +803,74 @@ edp_status edp_batch_plan_info(const edp_batch_plan* plan, int32_t* n_classes, i
 
 void edp_batch_plan_destroy(edp_batch_plan* plan) {
     if (plan) release_plan(plan);
+}
+
+edp_status edp_window_workspace_size(const edp_problem* prob, int32_t win, const edp_tuning* tuning,
+                                     size_t* bytes) {
+    if (!bytes) return EDP_E_INVALID;
+    Launch la{};
+    edp_status st = win_launch(prob, win, tuning, &la);
+    if (st != EDP_OK) return st;
+    *bytes = win_layout(prob, la).total;
+    return EDP_OK;
+}
+
+edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
+                              const int32_t* d_centers, int32_t win, int32_t* d_labels, int64_t* d_energy,
+                              void* d_ws, size_t ws_bytes, void* stream) {
+    Launch la{};
+    edp_status st = win_launch(prob, win, tuning, &la);
+    if (st != EDP_OK) return st;
+    if (!d_cost || !d_centers || !d_labels) return EDP_E_INVALID;
+    const WinLayout L = win_layout(prob, la);
+    if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < L.total) return EDP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    const EdpLayout& E = L.edp;
+    uint32_t* ctrl = (uint32_t*)(ws + E.ctrl);
+    uint32_t* flags = ctrl;
+    uint32_t* tickets = ctrl + E.nflags;
+    uint32_t* error = tickets + E.ntickets;
+    int32_t* cw = (int32_t*)(ws + L.cw);
+    uint32_t* shifts = (uint32_t*)(ws + L.shifts);
+
+    if (launch_fill_u32(ctrl, E.nctrl, 0, s) != hipSuccess) return EDP_E_HIP;
+    if (launch_win_prep((const int32_t*)d_cost, d_centers, prob->width, prob->height, prob->qx, prob->qy, win, kWinBig,
+                        cw, shifts, s) != hipSuccess)
+        return EDP_E_HIP;
+    const edp_problem f = frame_problem(prob);
+    ClassRun c{};
+    c.tile = WIN_TILE;
+    c.kind = KIND_WINDOW;
+    c.dtype = EDP_I32;
+    c.split = 1;
+    c.waves = la.waves;
+    c.chunk = la.chunk;
+    c.ring = la.ring;
+    c.fuse = la.fuse;
+    c.iterations = prob->iterations;
+    c.one = make_desc(&f, la, E.inst, ws, flags, cw, d_labels, nullptr);
+    c.one.aux = shifts;
+    c.one.centers = d_centers;
+    c.one.win = win;
+    c.one.qx_full = prob->qx;
+    c.descs = nullptr;
+    c.ndesc = 1;
+    c.tickets_per_pass = la.nsuper;
+    c.cells_per_block = agg_cells_per_block(WIN_TILE);
+    const int64_t cells = (int64_t)prob->width * prob->height;
+    c.agg_blocks = (int)((cells + c.cells_per_block - 1) / c.cells_per_block);
+    c.tickets = tickets;
+    c.error = error;
+    st = enqueue_class(c, tuning, s);
+    if (st != EDP_OK) return st;
+    if (d_energy) {
+        st = enqueue_energy(prob, d_cost, d_labels, 1, d_energy, nullptr, s);
+        if (st != EDP_OK) return st;
+        hipLaunchKernelGGL(flag_error_kernel, dim3(1), dim3(64), 0, s, error, d_energy);
+        if (hipGetLastError() != hipSuccess) return EDP_E_HIP;
+    }
+    return EDP_OK;
 }
 
 edp_status edp_energy(const edp_problem* prob, const void* d_cost, const int32_t* d_labels, int32_t grid4,

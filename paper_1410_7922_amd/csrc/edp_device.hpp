@@ -406,6 +406,65 @@ __device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t (&lv
     return m;
 }
 
+// ---- minimum search between shifted label frames -----------------------------
+// The label-window solve keeps every vertex's labels in a frame of its own; the
+// sum handed to a neighbour is evaluated in the neighbour's frame, shifted by d
+// labels along the line.  With source labels i = 0..n-1 (n = NL K) and target
+// labels j (source position j + d):
+//   out(j) = min_i val(i) + lam |j + d - i|, clipped at (line min + clipd)
+// which is the L1 transform of l1_line read at the shifted position, with the
+// exact continuation outside the source range:
+//   forward part  min_{i <= s} g(i) + lam s      (s = j + d >= 0; s > n-1 takes all i)
+//   backward part min_{i >= s} (val(i) + lam i) - lam s   (s <= n-1; s < 0 takes all i)
+// The shifted reads go through a per-wavefront LDS area sp / sq of 64 K ints.
+template <int NL, int K, int STEP>
+__device__ __forceinline__ int32_t l1_line_shift(int32_t (&val)[K], const int32_t lam, const int32_t clipd,
+                                                 const bool clip, const int32_t pos, const int32_t lane,
+                                                 const int32_t d, int32_t* sp, int32_t* sq) {
+    int32_t p[K], q[K];
+    p[0] = val[0] - lam * (pos * K);
+#pragma unroll
+    for (int k = 1; k < K; ++k) p[k] = imin(p[k - 1], val[k] - lam * (pos * K + k));
+    q[K - 1] = val[K - 1] + lam * (pos * K + K - 1);
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) q[k] = imin(q[k + 1], val[k] + lam * (pos * K + k));
+    int32_t m = val[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) m = imin(m, val[k]);
+    if constexpr (NL > 1) {
+        const int32_t tf = scan_up<NL, STEP>(p[K - 1], pos, lane);
+        const int32_t tb = scan_down<NL, STEP>(q[0], pos, lane);
+        const int32_t cf = carry_up<NL, STEP>(tf, pos, lane);
+        const int32_t cb = carry_down<NL, STEP>(tb, pos, lane);
+        m = line_min<NL, STEP>(m, lane);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            p[k] = imin(p[k], cf);
+            q[k] = imin(q[k], cb);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        sp[lane * K + k] = p[k];
+        sq[lane * K + k] = q[k];
+    }
+    constexpr int32_t n = NL * K;
+    const int32_t cap = clip ? m + clipd : IDENT;
+    const int32_t base = lane - pos * STEP;           // lane of position 0 of this line
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int32_t s = pos * K + k + d;
+        const int32_t sf = s < n - 1 ? s : n - 1;
+        const int32_t sb = s > 0 ? s : 0;
+        const int32_t af = (base + (sf >= 0 ? sf : 0) / K * STEP) * K + (sf >= 0 ? sf : 0) % K;
+        const int32_t ab = (base + (sb < n ? sb : n - 1) / K * STEP) * K + (sb < n ? sb : n - 1) % K;
+        const int32_t vf = sp[af] + lam * s;
+        const int32_t vb = sq[ab] - lam * s;
+        val[k] = imin3(s >= 0 ? vf : IDENT, s <= n - 1 ? vb : IDENT, cap);
+    }
+    return m;
+}
+
 // Minimum of v over the G lanes of this lane's group.
 template <class T>
 __device__ __forceinline__ int32_t group_min(int32_t v, const int32_t lane) {
@@ -471,6 +530,41 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
                 for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], gmin + clipd);
         }
         return gmin;
+    }
+}
+
+// M between shifted frames (see l1_line_shift): h in the source frame, the
+// result in the frame shifted by (dx, dy) labels.  scratch: this wavefront's
+// LDS area of 2 * 64 * max(KX, KY) ints.
+template <class T>
+__device__ __forceinline__ void min_search_shift(int32_t (&h)[T::KY][T::KX], const int32_t lam, const int32_t clipd,
+                                                 const bool joint, const int32_t lane, const int32_t dx,
+                                                 const int32_t dy, int32_t* scratch) {
+    constexpr int KM = T::KX > T::KY ? T::KX : T::KY;
+    int32_t* sp = scratch;
+    int32_t* sq = scratch + 64 * KM;
+    const int32_t l = lane % T::G;
+    const int32_t px = l % T::PX, py = l / T::PX;
+    int32_t rowmin = PADV;
+#pragma unroll
+    for (int ky = 0; ky < T::KY; ++ky)
+        rowmin = imin(rowmin, l1_line_shift<T::PX, T::KX, 1>(h[ky], lam, clipd, !joint, px, lane, dx, sp, sq));
+    int32_t gmin = rowmin;
+    if constexpr (T::PY > 1) gmin = line_min<T::PY, T::PX>(gmin, lane);
+#pragma unroll
+    for (int kx = 0; kx < T::KX; ++kx) {
+        int32_t col[T::KY];
+#pragma unroll
+        for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
+        l1_line_shift<T::PY, T::KY, T::PX>(col, lam, clipd, !joint, py, lane, dy, sp, sq);
+#pragma unroll
+        for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
+    }
+    if (joint) {
+#pragma unroll
+        for (int ky = 0; ky < T::KY; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], gmin + clipd);
     }
 }
 

@@ -28,6 +28,10 @@
 namespace edp {
 
 constexpr int NUM_TILES = 16;
+// The label-window solve: 8 x 8 label frames on tile 14 (4 x 2 by 4 x 2), scan kernel kind 4.
+constexpr int WIN_TILE = 14;
+constexpr int KIND_WINDOW = 4;
+constexpr int WIN_FRAME = 8;
 
 struct TileShape {
     int px, kx, py, ky;
@@ -49,6 +53,9 @@ struct InstDesc {
     unsigned long long* energy;   // [1] output energy (batched energy kernel), may be null
     uint32_t* flags;              // [3][nsuper]: column progress of the first and the second scan of
                                   // a launch, then the scans completed by each workgroup band
+    const void* aux;              // label-window solve: int8 frame shifts [H][W][4][2], else null
+    const int32_t* centers;       // label-window solve: window centres [H][W][2], else null
+    int32_t win, qx_full;         // label-window solve: window side, labels along x of the full space
     int32_t W, H, qx, qy;
     int32_t lam, clipd, joint, trunc;
     int32_t nbands, nsuper;       // wavefront bands, workgroup bands
@@ -165,6 +172,10 @@ struct BatchEnergyArgs {
 hipError_t launch_edp_pass(int tile, int kind, int split, const PassArgs& a, int grid, int waves,
                            hipStream_t s);
 hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
+hipError_t launch_edp_aggregate_win(const AggArgs& a, int grid, hipStream_t s);
+// label-window solve: compact 8 x 8 frame costs (big outside the window) and frame shifts
+hipError_t launch_win_prep(const int32_t* cost, const int32_t* centers, int32_t W, int32_t H, int32_t qx, int32_t qy,
+                           int32_t win, int32_t big, int32_t* cw, uint32_t* shifts, hipStream_t s);
 hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s);
 hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
 hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);

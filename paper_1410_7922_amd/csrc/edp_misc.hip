@@ -126,6 +126,53 @@ hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Label-window solve, preparation: cw[cell][jy * 8 + jx] = C(cell, window label (jx, jy)) for
+// jx, jy < win, big elsewhere in the 8 x 8 frame; shifts[cell] = frame offsets (dx, dy) of the
+// four neighbours' windows relative to this vertex's (int8 pairs: +x, -x | +y, -y; 0 off grid).
+__global__ __launch_bounds__(256) void win_prep_kernel(const int32_t* cost, const int32_t* centers, int32_t W,
+                                                       int32_t H, int32_t qx, int32_t qy, int32_t win, int32_t big,
+                                                       int32_t* cw, uint32_t* shifts) {
+    const int64_t total = (int64_t)W * H * WIN_FRAME * WIN_FRAME;
+    const int32_t Q = qx * qy, r = win / 2;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cell = idx / (WIN_FRAME * WIN_FRAME);
+        const int32_t slot = (int32_t)(idx % (WIN_FRAME * WIN_FRAME));
+        const int32_t jx = slot % WIN_FRAME, jy = slot / WIN_FRAME;
+        const int32_t cx = centers[2 * cell], cy = centers[2 * cell + 1];
+        const int32_t vx = cx - r + jx, vy = cy - r + jy;
+        const bool in = jx < win && jy < win && vx >= 0 && vx < qx && vy >= 0 && vy < qy;
+        cw[idx] = in ? cost[cell * Q + vy * qx + vx] : big;
+        if (slot == 0) {
+            const int32_t x = (int32_t)(cell % W), y = (int32_t)(cell / W);
+            const int32_t nx[4] = {x + 1, x - 1, x, x}, ny[4] = {y, y, y + 1, y - 1};
+            uint32_t code[2] = {0u, 0u};
+            for (int k = 0; k < 4; ++k) {
+                int32_t ddx = 0, ddy = 0;
+                if (nx[k] >= 0 && nx[k] < W && ny[k] >= 0 && ny[k] < H) {
+                    const int64_t n = (int64_t)ny[k] * W + nx[k];
+                    ddx = centers[2 * n] - cx;
+                    ddy = centers[2 * n + 1] - cy;
+                }
+                const uint32_t pair = ((uint32_t)ddx & 0xFFu) | (((uint32_t)ddy & 0xFFu) << 8);
+                code[k >> 1] |= pair << (16 * (k & 1));
+            }
+            shifts[2 * cell] = code[0];
+            shifts[2 * cell + 1] = code[1];
+        }
+    }
+}
+
+hipError_t launch_win_prep(const int32_t* cost, const int32_t* centers, int32_t W, int32_t H, int32_t qx, int32_t qy,
+                           int32_t win, int32_t big, int32_t* cw, uint32_t* shifts, hipStream_t s) {
+    const int64_t n = (int64_t)W * H * WIN_FRAME * WIN_FRAME;
+    int64_t grid = (n + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(win_prep_kernel, dim3((unsigned)grid), dim3(256), 0, s, cost, centers, W, H, qx, qy, win, big,
+                       cw, shifts);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s) {
     if (grid < 1) return hipSuccess;
     if (dtype == 1)

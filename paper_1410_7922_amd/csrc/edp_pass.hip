@@ -63,7 +63,10 @@ __device__ __forceinline__ void flag_put(uint32_t* p, uint32_t v) {
 }
 __device__ __forceinline__ void raise_error(uint32_t* error) { flag_put(error, 1u); }
 
-template <class T, class CK, int SPLIT, int PF>
+// WIN: the label-window solve.  Every vertex holds an 8 x 8 frame of labels around its own
+// window (costs outside the window are large), d.aux holds the frame shifts towards the four
+// neighbours, and each sum handed on is evaluated in the receiving vertex's frame.
+template <class T, class CK, int SPLIT, int PF, bool WIN = false>
 __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int CL = SPLIT * G;                  // lanes per vertex
@@ -76,6 +79,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     int32_t* misc = lds + 2 * MAX_WAVES;           // [0] ticket broadcast
     int32_t* trash = lds + 2 * MAX_WAVES + 4;      // [QT] sink of the lanes that hand nothing over
     int32_t* rings = trash + QT;                   // [NW-1][ring][QT]
+    static_assert(!WIN || SPLIT == 1, "the window solve runs both searches on every lane");
 
     const int32_t lane = lane_id();
     // wavefront-uniform values live in scalar registers, so control flow on them is scalar
@@ -191,6 +195,11 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
             const int32_t ba = bt + dt;                    // (x + sx, y)
             const int32_t bb = cell_off(yn * W + x0, QT * 4) + lofs;
             const int32_t bg = cell_off(yp * W + x0, QT * 4) + lofs;
+            // window solve: frame-shift codes of the vertex (8 bytes per vertex)
+            const int32_t bsh = cell_off(y * W + x0, 8), dsh = sx * 8;
+            const __amdgpu_buffer_rsrc_t rs_sh = make_rsrc(d.aux, WIN ? W * H * 8 : 0);
+            int32_t* const wscr = rings + (size_t)(NW > 1 ? NW - 1 : 0) * R * QT +
+                                  (size_t)wave * 2 * 64 * (KX > KY ? KX : KY);
             // steps rounded up to whole prefetch rounds: the extra steps touch nothing (every lane
             // is past the end of its row), and a fixed count of loads per step lets the compiler
             // wait for exactly the slot in use instead of for every load in flight
@@ -198,6 +207,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
 
             constexpr int CW = CostWords<CK, KX>::value;
             int32_t rc[PF][KY][CW], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
+            int32_t rsh[PF][WIN ? 2 : 1];
             int32_t carry[KY][KX], out[KY][KX];
 #pragma unroll
             for (int ky = 0; ky < KY; ++ky)
@@ -206,7 +216,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
 
             // Issue the loads of step t into one ring slot (no branch around a load).
             auto fetch = [&](const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX],
-                             int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX]) {
+                             int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX], int32_t (&sh)[WIN ? 2 : 1]) {
                 if (from_global && t < W && seen < (uint32_t)t + 1) {   // wave-uniform
                     const uint32_t need = (uint32_t)t + 1;
                     uint32_t v = 0, spins = 0;
@@ -240,10 +250,11 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                 load_vec<E>(rs_ma, offa, &ma[0][0]);
                 load_vec<E>(rs_mb, offb, &mb[0][0]);
                 load_vec<E>(rs_b, offg, &gb[0][0]);
+                if constexpr (WIN) load_vec<2>(rs_sh, act ? bsh + t * dsh : OOB, sh);
             };
 
 #pragma unroll
-            for (int u = 0; u < PF; ++u) fetch(u, rc[u], rma[u], rmb[u], rb[u]);
+            for (int u = 0; u < PF; ++u) fetch(u, rc[u], rma[u], rmb[u], rb[u], rsh[u]);
 
             for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
 #pragma unroll
@@ -306,8 +317,18 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                     h[ky][kx] = valid[ky][kx] ? ((A + (beta ? -d : d)) >> 1) : PADV;
                                 }
                             }
-                        min_search<T>(h, li, d.clipd, joint, lane);
-                        if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
+                        if constexpr (WIN) {
+                            // shift codes: bytes (dx, dy) towards +x, -x (dword 0) and +y, -y (dword 1)
+                            const int32_t ca = rsh[u][0] >> (sx > 0 ? 0 : 16);
+                            const int32_t cb = rsh[u][1] >> (sy > 0 ? 0 : 16);
+                            const int32_t dxa = (int32_t)(int8_t)(ca & 0xFF), dya = (int32_t)(int8_t)((ca >> 8) & 0xFF);
+                            const int32_t dxb = (int32_t)(int8_t)(cb & 0xFF), dyb = (int32_t)(int8_t)((cb >> 8) & 0xFF);
+                            min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
+                            min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
+                        } else {
+                            min_search<T>(h, li, d.clipd, joint, lane);
+                            if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
+                        }
                         const int32_t o = bt + s * dt;
                         const int32_t oa = (act && store_a) ? o : OOB;
                         const int32_t ob = (act && store_b) ? o : OOB;
@@ -348,7 +369,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                     flag_put(progress + super, epoch + (uint32_t)(il + 1));
                             }
                         }
-                        fetch(s + PF, rc[u], rma[u], rmb[u], rb[u]);
+                        fetch(s + PF, rc[u], rma[u], rmb[u], rb[u], rsh[u]);
                     }
                 }
             }
@@ -364,7 +385,9 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
     }
 }
 
-template <class T, class CT>
+// Marginal of eq. DP_2D_1 and its smallest argmin.  WIN: frames of the label-window
+// solve; only the win x win window counts, and the label is read through the centre.
+template <class T, class CT, bool WIN = false>
 __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, QT = T::QT;
     constexpr int RPW = 64 / G;
@@ -380,13 +403,21 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     const int32_t cell = (blk - d.first_block) * a.cells_per_block + wave * RPW + grp;
     const bool ok = cell < cells;
     const int32_t y = ok ? cell / W : 0, x = ok ? cell % W : 0;
+    int32_t ox = 0, oy = 0;                        // window origin in the full label space
+    if constexpr (WIN) {
+        if (ok) {
+            ox = d.centers[2 * cell] - d.win / 2;
+            oy = d.centers[2 * cell + 1] - d.win / 2;
+        }
+    }
     int32_t best = 0x7FFFFFFF, bq = 0x7FFFFFFF;
 #pragma unroll
     for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
         for (int kx = 0; kx < KX; ++kx) {
             const int32_t vy = py * KY + ky, vx = px * KX + kx;
-            if (ok && vx < d.qx && vy < d.qy) {
+            const bool in = WIN ? (vx < d.win && vy < d.win) : (vx < d.qx && vy < d.qy);
+            if (ok && in) {
                 const int32_t q = vy * d.qx + vx;
                 const int e = l * T::E + ky * KX + kx;
                 int32_t v = (int32_t)cost[(size_t)cell * Q + q];
@@ -394,7 +425,8 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
                 if (x + 1 < W) v += d.t[1][(size_t)(cell + 1) * QT + e];
                 if (y > 0) v += d.t[2][(size_t)(cell - W) * QT + e];
                 if (y + 1 < H) v += d.t[3][(size_t)(cell + W) * QT + e];
-                if (v < best || (v == best && q < bq)) { best = v; bq = q; }
+                const int32_t lab = WIN ? (oy + vy) * d.qx_full + (ox + vx) : q;
+                if (v < best || (v == best && lab < bq)) { best = v; bq = lab; }
             }
         }
     // smallest value, then the smallest label among the lanes holding it
@@ -411,11 +443,22 @@ constexpr int pass_pf() { return T::E <= 4 ? 8 : (T::E <= 8 ? 4 : 2); }
 size_t pass_lds_bytes(int qt, int waves, int ring) {
     return (size_t)(2 * MAX_WAVES + 4 + qt) * 4 + (size_t)(waves > 1 ? waves - 1 : 0) * ring * qt * 4;
 }
+// the window solve adds a shifted-read area of 2 x 64 x 2 ints per wavefront
+static size_t win_lds_bytes(int waves) { return (size_t)waves * 2 * 64 * 2 * 4; }
 
 template <class T, class CK, int SPLIT>
 static hipError_t run_pass(const PassArgs& a, int grid, int waves, hipStream_t s) {
     const size_t lds = pass_lds_bytes(T::QT, waves, a.ring);
     hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>), dim3(grid), dim3(64 * waves), lds, s, a);
+    return hipGetLastError();
+}
+
+using WinTile = Tile<4, 2, 4, 2>;
+
+static hipError_t run_pass_win(const PassArgs& a, int grid, int waves, hipStream_t s) {
+    const size_t lds = pass_lds_bytes(WinTile::QT, waves, a.ring) + win_lds_bytes(waves);
+    hipLaunchKernelGGL((edp_pass_kernel<WinTile, int32_t, 1, pass_pf<WinTile>(), true>), dim3(grid), dim3(64 * waves),
+                       lds, s, a);
     return hipGetLastError();
 }
 
@@ -476,6 +519,7 @@ static int occupancy_kind(int kind, int split, int waves, size_t lds) {
 hipError_t launch_edp_pass(int tile, int dtype, int split, const PassArgs& a, int grid, int waves,
                            hipStream_t s) {
     if (waves < 1 || waves > MAX_WAVES) return hipErrorInvalidValue;
+    if (dtype == KIND_WINDOW) return tile == WIN_TILE && split == 1 ? run_pass_win(a, grid, waves, s) : hipErrorInvalidValue;
     switch (tile) {
 #define EDP_CASE(id, px, kx, py, ky) \
     case id:                         \
@@ -484,6 +528,11 @@ hipError_t launch_edp_pass(int tile, int dtype, int split, const PassArgs& a, in
 #undef EDP_CASE
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_edp_aggregate_win(const AggArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((edp_aggregate_kernel<WinTile, int32_t, true>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s) {
@@ -500,6 +549,13 @@ hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid,
 
 int pass_capacity(int tile, int dtype, int split, int waves, size_t lds_bytes) {
     int per_cu = 1;
+    if (dtype == KIND_WINDOW) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, edp_pass_kernel<WinTile, int32_t, 1, pass_pf<WinTile>(), true>, 64 * waves,
+                lds_bytes + win_lds_bytes(waves)) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        tile = -1;
+    }
     switch (tile) {
 #define EDP_CASE(id, px, kx, py, ky)                                               \
     case id:                                                                       \
