@@ -39,10 +39,11 @@ edp_status edp_dsi_motion(const uint8_t* d_i0, const uint8_t* d_i1, int32_t W, i
 /*
  * Network input: for each block of 4 x 4 labels (ceil(qx/4) * ceil(qy/4) = 64
  * channels) the minimum cost over the block, summed over the 2 x 2 pixels of a
- * half-resolution pixel, divided in float32 by 4 * cmax, rounded to bf16.
+ * half-resolution pixel, divided in float32 by 4 * scale (scale >= 1), rounded
+ * to bf16.
  *   d_cost [H][W][qy*qx] int32 (H, W even);  d_out [H/2][W/2][64] bf16
  */
-edp_status edp_pool_cost(const int32_t* d_cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t cmax,
+edp_status edp_pool_cost(const int32_t* d_cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
                          uint16_t* d_out, void* stream);
 
 /*

@@ -8,7 +8,7 @@ and the smoke check import this module; it shares no code with the library.
 Network (per pixel of the half-resolution grid, channels last):
   input   pooled cost volume: for each label block of 4 x 4 labels the minimum
           cost over the block, summed over the 2 x 2 pixels, divided (float32)
-          by 4 x the cost bound, rounded to bf16 (64 channels for 31 x 31 labels)
+          by 4 x a scale, rounded to bf16 (64 channels for 31 x 31 labels)
   conv3x3 64 -> 32, ReLU;  conv3x3 32 -> 32, ReLU;  conv3x3 32 -> 32, ReLU;
   conv3x3 32 -> 2 * 31 logits (first half: label column, second: label row)
   zero padding, weights [Cout][3][3][Cin] (bf16), bias [Cout] (float32)
@@ -39,7 +39,7 @@ def label_blocks(q: int, block: int = 4):
     return [(s, min(s + block, q)) for s in range(0, q, block)]
 
 
-def pool_cost(cost, qx, qy, cmax, block=4):
+def pool_cost(cost, qx, qy, scale, block=4):
     """cost [H][W][qy*qx] (H, W even) -> float64 [H/2][W/2][by*bx], bf16-rounded."""
     H, W, Q = cost.shape
     assert Q == qx * qy and H % 2 == 0 and W % 2 == 0
@@ -51,7 +51,7 @@ def pool_cost(cost, qx, qy, cmax, block=4):
             m = c[:, :, y0:y1, x0:x1].min(axis=(2, 3))               # [H][W]
             s = m[0::2, 0::2] + m[0::2, 1::2] + m[1::2, 0::2] + m[1::2, 1::2]
             # one correctly rounded float32 division of two exact integers
-            out[:, :, j * len(bx) + i] = s.astype(np.float32) / np.float32(4 * cmax)
+            out[:, :, j * len(bx) + i] = s.astype(np.float32) / np.float32(4 * scale)
     return bf16(out)
 
 

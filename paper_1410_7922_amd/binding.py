@@ -371,14 +371,14 @@ def dsi_motion(i0: torch.Tensor, i1: torch.Tensor, r: int, cmax: int, out: torch
     return out
 
 
-def pool_cost(cost: torch.Tensor, qx: int, qy: int, cmax: int, out: torch.Tensor | None = None):
+def pool_cost(cost: torch.Tensor, qx: int, qy: int, scale: int, out: torch.Tensor | None = None):
     """Network input [H/2][W/2][64] bf16 (as int16 storage) from an int32 cost volume (edp_pool_cost)."""
     _device_tensor(cost, "cost")
     H, W, _ = cost.shape
     nch = ((qx + 3) // 4) * ((qy + 3) // 4)
     if out is None:
         out = torch.empty((H // 2, W // 2, nch), dtype=torch.int16, device=cost.device)
-    _check(_learn_lib().edp_pool_cost(cost.data_ptr(), W, H, qx, qy, cmax, out.data_ptr(), _stream(cost.device)),
+    _check(_learn_lib().edp_pool_cost(cost.data_ptr(), W, H, qx, qy, scale, out.data_ptr(), _stream(cost.device)),
            "edp_pool_cost")
     return out
 

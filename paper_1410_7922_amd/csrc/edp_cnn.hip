@@ -55,7 +55,7 @@ __global__ void dsi_motion_kernel(const uint8_t* i0, const uint8_t* i1, int32_t 
 
 // One wavefront per half-resolution pixel, one lane per label block (bx * by <= 64).
 __global__ __launch_bounds__(256) void pool_kernel(const int32_t* cost, int32_t W, int32_t H, int32_t qx,
-                                                   int32_t qy, int32_t cmax, int32_t nbx, int32_t nch,
+                                                   int32_t qy, int32_t scale, int32_t nbx, int32_t nch,
                                                    uint16_t* out) {
     const int32_t w2 = W / 2, h2 = H / 2;
     const int64_t opix = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void pool_kernel(const int32_t* cost, int32_t 
             for (int32_t vx = x0; vx < x1; ++vx) m = min(m, c[vy * qx + vx]);
         sum += m;
     }
-    out[opix * nch + lane] = f2bf((float)sum / (float)(4 * cmax));
+    out[opix * nch + lane] = f2bf((float)sum / (float)(4 * scale));
 }
 
 // ---------------------------------------------------------------------------
@@ -356,10 +356,10 @@ hipError_t launch_dsi_motion(const uint8_t* i0, const uint8_t* i1, int32_t W, in
     return hipGetLastError();
 }
 
-hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t cmax,
+hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
                        int32_t nbx, int32_t nch, uint16_t* out, hipStream_t s) {
     const int64_t n = (int64_t)(W / 2) * (H / 2);
-    hipLaunchKernelGGL(pool_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, cost, W, H, qx, qy, cmax, nbx,
+    hipLaunchKernelGGL(pool_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, cost, W, H, qx, qy, scale, nbx,
                        nch, out);
     return hipGetLastError();
 }

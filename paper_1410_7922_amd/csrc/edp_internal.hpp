@@ -188,7 +188,7 @@ hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStrea
 // label-window network kernels (edp_cnn.hip)
 hipError_t launch_dsi_motion(const uint8_t* i0, const uint8_t* i1, int32_t W, int32_t H, int32_t r, int32_t cmax,
                              int32_t* out, hipStream_t s);
-hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t cmax,
+hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
                        int32_t nbx, int32_t nch, uint16_t* out, hipStream_t s);
 hipError_t launch_conv(int32_t cin, int32_t cout_pad, const uint16_t* in, const uint16_t* w, const float* bias,
                        int32_t h, int32_t wd, int32_t cout_real, int32_t relu, const uint16_t* mask, int32_t ld,

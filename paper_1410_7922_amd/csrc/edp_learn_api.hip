@@ -22,13 +22,13 @@ edp_status edp_dsi_motion(const uint8_t* d_i0, const uint8_t* d_i1, int32_t W, i
     return st(launch_dsi_motion(d_i0, d_i1, W, H, r, cmax, d_cost, (hipStream_t)stream));
 }
 
-edp_status edp_pool_cost(const int32_t* d_cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t cmax,
+edp_status edp_pool_cost(const int32_t* d_cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
                          uint16_t* d_out, void* stream) {
-    if (!d_cost || !d_out || W < 2 || H < 2 || (W & 1) || (H & 1) || qx < 1 || qy < 1 || cmax < 1)
+    if (!d_cost || !d_out || W < 2 || H < 2 || (W & 1) || (H & 1) || qx < 1 || qy < 1 || scale < 1)
         return EDP_E_INVALID;
     const int32_t nbx = (qx + 3) / 4, nby = (qy + 3) / 4;
     if (nbx * nby > 64) return EDP_E_UNSUPPORTED;
-    return st(launch_pool(d_cost, W, H, qx, qy, cmax, nbx, nbx * nby, d_out, (hipStream_t)stream));
+    return st(launch_pool(d_cost, W, H, qx, qy, scale, nbx, nbx * nby, d_out, (hipStream_t)stream));
 }
 
 edp_status edp_conv3x3_forward(const uint16_t* d_x, const uint16_t* d_w, const float* d_b, int32_t h, int32_t w,

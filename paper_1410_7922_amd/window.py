@@ -137,11 +137,12 @@ class WindowNet:
         return loss
 
     # ---- inference ----------------------------------------------------------
-    def windows(self, cost: torch.Tensor, qx: int, qy: int, cmax: int, win: int = 7,
+    def windows(self, cost: torch.Tensor, qx: int, qy: int, scale: int = 250, win: int = 7,
                 pooled: torch.Tensor | None = None, centers: torch.Tensor | None = None):
-        """Window centres [H][W][2] int32 for an int32 cost volume [H][W][qy*qx]."""
+        """Window centres [H][W][2] int32 for an int32 cost volume [H][W][qy*qx]; scale is the
+        input normaliser the network was trained with."""
         H, W, _ = cost.shape
-        x = B.pool_cost(cost, qx, qy, cmax, out=pooled)
+        x = B.pool_cost(cost, qx, qy, scale, out=pooled)
         logits = self.forward(x)
         if centers is None:
             centers = torch.empty((H, W, 2), dtype=torch.int32, device=cost.device)
