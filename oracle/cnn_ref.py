@@ -11,10 +11,12 @@ Network (per pixel of the half-resolution grid, channels last):
           by 4 x a scale, rounded to bf16 (64 channels for 31 x 31 labels)
   conv3x3 64 -> 32, ReLU;  conv3x3 32 -> 32, ReLU;  conv3x3 32 -> 32, ReLU;
   conv3x3 32 -> 2 * 31 logits (first half: label column, second: label row)
-  zero padding, weights [Cout][3][3][Cin] (bf16), bias [Cout] (float32)
-Training: softmax cross entropy per head against the label of the top-left
-pixel of each 2 x 2 block, averaged over pixels and summed over the heads;
-Adam on float32 master weights.
+  dilations 1, 2, 4, 8; zero padding; weights [Cout][3][3][Cin] (bf16), bias
+  [Cout] (float32)
+Training: per head the negative log softmax mass of the window of labels
+around the label of the top-left pixel of each 2 x 2 block (a window of one
+label is the softmax cross entropy), averaged over pixels and summed over the
+heads; Adam on float32 master weights.
 """
 from __future__ import annotations
 
@@ -55,34 +57,36 @@ def pool_cost(cost, qx, qy, scale, block=4):
     return bf16(out)
 
 
-def conv3x3(x, w, b):
-    """x [h][w][cin], w [cout][3][3][cin], b [cout] -> [h][w][cout] (zero padding)."""
+def conv3x3(x, w, b, dil=1):
+    """x [h][w][cin], w [cout][3][3][cin], b [cout] -> [h][w][cout] (zero padding, taps dil apart)."""
     h, wd, cin = x.shape
     cout = w.shape[0]
-    xp = np.zeros((h + 2, wd + 2, cin))
-    xp[1:-1, 1:-1] = x
+    xp = np.zeros((h + 2 * dil, wd + 2 * dil, cin))
+    xp[dil:dil + h, dil:dil + wd] = x
     out = np.zeros((h, wd, cout)) + b
     for dy in range(3):
         for dx in range(3):
-            out += xp[dy:dy + h, dx:dx + wd] @ w[:, dy, dx, :].T
+            out += xp[dy * dil:dy * dil + h, dx * dil:dx * dil + wd] @ w[:, dy, dx, :].T
     return out
 
 
-def conv3x3_backward(x, w, dy_):
+def conv3x3_backward(x, w, dy_, dil=1):
     """Gradients of conv3x3 w.r.t. its input and weights for output gradient dy_."""
     h, wd, cin = x.shape
-    xp = np.zeros((h + 2, wd + 2, cin))
-    xp[1:-1, 1:-1] = x
+    xp = np.zeros((h + 2 * dil, wd + 2 * dil, cin))
+    xp[dil:dil + h, dil:dil + wd] = x
     dxp = np.zeros_like(xp)
     dw = np.zeros_like(w)
     for dy in range(3):
         for dx in range(3):
-            dxp[dy:dy + h, dx:dx + wd] += dy_ @ w[:, dy, dx, :]
-            dw[:, dy, dx, :] = np.einsum("hwo,hwi->oi", dy_, xp[dy:dy + h, dx:dx + wd])
-    return dxp[1:-1, 1:-1], dw
+            sl = (slice(dy * dil, dy * dil + h), slice(dx * dil, dx * dil + wd))
+            dxp[sl] += dy_ @ w[:, dy, dx, :]
+            dw[:, dy, dx, :] = np.einsum("hwo,hwi->oi", dy_, xp[sl])
+    return dxp[dil:dil + h, dil:dil + wd], dw
 
 
 LAYERS = ((64, 32), (32, 32), (32, 32), (32, 62))
+DILATIONS = (1, 2, 4, 8)
 
 
 def init_params(rng, layers=LAYERS):
@@ -95,11 +99,11 @@ def init_params(rng, layers=LAYERS):
     return params
 
 
-def forward(x, params):
+def forward(x, params, dilations=DILATIONS):
     """Returns (logits [h][w][62] float64, inputs of every layer (bf16-rounded))."""
     acts = [bf16(x)]
     for li, p in enumerate(params):
-        z = conv3x3(acts[-1], bf16(p["w"]), np.asarray(p["b"], np.float64))
+        z = conv3x3(acts[-1], bf16(p["w"]), np.asarray(p["b"], np.float64), dilations[li])
         if li + 1 < len(params):
             acts.append(bf16(np.maximum(z, 0.0)))
         else:
@@ -113,27 +117,29 @@ def targets(labels, qx):
     return lab % qx, lab // qx
 
 
-def ce_loss_grad(logits, tx, ty, nclass=31):
-    """Mean over pixels of the two heads' softmax cross entropies, and its logit gradient."""
+def ce_loss_grad(logits, tx, ty, nclass=31, win=1):
+    """Mean over pixels of the two heads' window cross entropies -log(softmax mass of the win labels
+    around the target, the window clamped into the label range), and its logit gradient.  win = 1
+    is the softmax cross entropy."""
     h, w, _ = logits.shape
     n = h * w
+    r = win // 2
     loss = 0.0
     grad = np.zeros_like(logits)
     for head, t in ((0, tx), (1, ty)):
         z = logits[:, :, head * nclass:(head + 1) * nclass]
-        zmax = z.max(axis=2, keepdims=True)
-        e = np.exp(z - zmax)
-        s = e.sum(axis=2, keepdims=True)
-        lse = np.log(s)[:, :, 0] + zmax[:, :, 0]
-        picked = np.take_along_axis(z, np.asarray(t)[:, :, None], axis=2)[:, :, 0]
-        loss += float(np.sum(lse - picked)) / n
-        g = e / s
-        np.put_along_axis(g, np.asarray(t)[:, :, None], np.take_along_axis(g, np.asarray(t)[:, :, None], 2) - 1.0, 2)
-        grad[:, :, head * nclass:(head + 1) * nclass] = g / n
+        e = np.exp(z - z.max(axis=2, keepdims=True))
+        p = e / e.sum(axis=2, keepdims=True)
+        c = np.clip(np.asarray(t), r, nclass - 1 - r)
+        k = np.arange(nclass)[None, None, :]
+        inwin = np.abs(k - c[:, :, None]) <= r
+        mass = np.sum(p * inwin, axis=2)
+        loss += float(np.sum(-np.log(mass))) / n
+        grad[:, :, head * nclass:(head + 1) * nclass] = (p - p * inwin / mass[:, :, None]) / n
     return loss, grad
 
 
-def backward(params, acts, dlogits):
+def backward(params, acts, dlogits, dilations=DILATIONS):
     """Gradients of every layer.  The output gradient of a layer enters the products rounded to
     bf16 (as the GPU's matrix operands); bias gradients use it unrounded."""
     grads = [None] * len(params)
@@ -141,7 +147,7 @@ def backward(params, acts, dlogits):
     for li in range(len(params) - 1, -1, -1):
         p = params[li]
         db = d.sum(axis=(0, 1))
-        dx, dw = conv3x3_backward(acts[li], bf16(p["w"]), bf16(d))
+        dx, dw = conv3x3_backward(acts[li], bf16(p["w"]), bf16(d), dilations[li])
         grads[li] = {"w": dw, "b": db}
         if li > 0:
             d = dx * (acts[li] > 0)
@@ -157,11 +163,21 @@ def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     p[:] = p - lr * mh / (np.sqrt(vh) + eps)
 
 
-def decode(logits, qx, qy, win, nclass=31):
-    """Window centres at full resolution [2h][2w][2] = (cx, cy): per-head argmax (first maximum),
-    clamped so the win x win box lies inside the label space, repeated over each 2 x 2 block."""
+def window_mass(logits_head, q, win):
+    """Mass sum_{|k-c| <= win/2} exp(z_k - max z) of every admissible window [h][w][q - win + 1]."""
+    z = logits_head[:, :, :q]
+    e = np.exp(z - z.max(axis=2, keepdims=True))
+    return np.stack([e[:, :, c:c + win].sum(axis=2) for c in range(q - win + 1)], axis=2)
+
+
+def decode(logits, qx, qy, win, nclass=31, rel=1e-5):
+    """Window centres at full resolution [2h][2w][2] = (cx, cy): per head the first centre whose
+    window mass is within a factor (1 - rel) of the largest, repeated over each 2 x 2 block."""
     r = win // 2
-    cx = np.clip(np.argmax(logits[:, :, :nclass], axis=2), r, qx - 1 - r)
-    cy = np.clip(np.argmax(logits[:, :, nclass:2 * nclass], axis=2), r, qy - 1 - r)
-    c = np.stack([cx, cy], axis=-1)
+    out = []
+    for head, q in ((0, qx), (1, qy)):
+        m = window_mass(logits[:, :, head * nclass:(head + 1) * nclass], q, win)
+        ok = m >= m.max(axis=2, keepdims=True) * (1 - rel)
+        out.append(np.argmax(ok, axis=2) + r)
+    c = np.stack(out, axis=-1)
     return np.repeat(np.repeat(c, 2, axis=0), 2, axis=1).astype(np.int32)

@@ -326,7 +326,7 @@ class BatchPlan:
 
 LEARN_EXPORTS = ("edp_dsi_motion", "edp_pool_cost", "edp_conv3x3_forward", "edp_conv3x3_dgrad",
                  "edp_conv3x3_wgrad", "edp_colsum", "edp_ce_loss", "edp_adam", "edp_decode_windows",
-                 "edp_window_targets")
+                 "edp_window_targets", "edp_window_recenter")
 
 
 def _learn_lib():
@@ -337,14 +337,15 @@ def _learn_lib():
     sig = {
         "edp_dsi_motion": [vp, vp, i32, i32, i32, i32, vp, vp],
         "edp_pool_cost": [vp, i32, i32, i32, i32, i32, vp, vp],
-        "edp_conv3x3_forward": [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp],
-        "edp_conv3x3_dgrad": [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp],
-        "edp_conv3x3_wgrad": [vp, vp, i32, i32, i32, i32, vp, vp],
+        "edp_conv3x3_forward": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp],
+        "edp_conv3x3_dgrad": [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp],
+        "edp_conv3x3_wgrad": [vp, vp, i32, i32, i32, i32, i32, vp, vp],
         "edp_colsum": [vp, i32, i32, i32, vp, vp],
-        "edp_ce_loss": [vp, i32, i32, vp, vp, i32, vp, vp, vp, vp],
+        "edp_ce_loss": [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp],
         "edp_adam": [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, i32, vp],
         "edp_decode_windows": [vp, i32, i32, i32, i32, i32, i32, i32, vp, vp],
         "edp_window_targets": [vp, i32, i32, i32, vp, vp, vp],
+        "edp_window_recenter": [vp, i32, i32, i32, i32, i32, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -383,27 +384,27 @@ def pool_cost(cost: torch.Tensor, qx: int, qy: int, scale: int, out: torch.Tenso
     return out
 
 
-def conv3x3_forward(x, w, b, h, wd, cin, cout, relu, y_bf16=None, y_f32=None):
-    _check(_learn_lib().edp_conv3x3_forward(_ptr(x), _ptr(w), _ptr(b), h, wd, cin, cout, int(bool(relu)),
+def conv3x3_forward(x, w, b, h, wd, cin, cout, relu, y_bf16=None, y_f32=None, dilation=1):
+    _check(_learn_lib().edp_conv3x3_forward(_ptr(x), _ptr(w), _ptr(b), h, wd, cin, cout, dilation, int(bool(relu)),
                                             _ptr(y_bf16), _ptr(y_f32), _stream(x.device)), "edp_conv3x3_forward")
 
 
-def conv3x3_dgrad(dy, w, x, h, wd, cin, cout, wt, dx_f32, dx_bf16):
-    _check(_learn_lib().edp_conv3x3_dgrad(_ptr(dy), _ptr(w), _ptr(x), h, wd, cin, cout, _ptr(wt), _ptr(dx_f32),
-                                          _ptr(dx_bf16), _stream(dy.device)), "edp_conv3x3_dgrad")
+def conv3x3_dgrad(dy, w, x, h, wd, cin, cout, wt, dx_f32, dx_bf16, dilation=1):
+    _check(_learn_lib().edp_conv3x3_dgrad(_ptr(dy), _ptr(w), _ptr(x), h, wd, cin, cout, dilation, _ptr(wt),
+                                          _ptr(dx_f32), _ptr(dx_bf16), _stream(dy.device)), "edp_conv3x3_dgrad")
 
 
-def conv3x3_wgrad(dy, x, h, wd, cin, cout, dw):
-    _check(_learn_lib().edp_conv3x3_wgrad(_ptr(dy), _ptr(x), h, wd, cin, cout, _ptr(dw), _stream(dy.device)),
-           "edp_conv3x3_wgrad")
+def conv3x3_wgrad(dy, x, h, wd, cin, cout, dw, dilation=1):
+    _check(_learn_lib().edp_conv3x3_wgrad(_ptr(dy), _ptr(x), h, wd, cin, cout, dilation, _ptr(dw),
+                                          _stream(dy.device)), "edp_conv3x3_wgrad")
 
 
 def colsum(a, rows, cols, ld, out):
     _check(_learn_lib().edp_colsum(_ptr(a), rows, cols, ld, _ptr(out), _stream(a.device)), "edp_colsum")
 
 
-def ce_loss(logits, n, ld, tx, ty, nclass, grad_f32, grad_bf16, loss):
-    _check(_learn_lib().edp_ce_loss(_ptr(logits), n, ld, _ptr(tx), _ptr(ty), nclass, _ptr(grad_f32),
+def ce_loss(logits, n, ld, tx, ty, nclass, grad_f32, grad_bf16, loss, win=1):
+    _check(_learn_lib().edp_ce_loss(_ptr(logits), n, ld, _ptr(tx), _ptr(ty), nclass, win, _ptr(grad_f32),
                                     _ptr(grad_bf16), _ptr(loss), _stream(logits.device)), "edp_ce_loss")
 
 
@@ -420,3 +421,10 @@ def decode_windows(logits, h, wd, ld, qx, qy, win, nclass, centers):
 def window_targets(labels, W, H, qx, tx, ty):
     _check(_learn_lib().edp_window_targets(_ptr(labels), W, H, qx, _ptr(tx), _ptr(ty), _stream(labels.device)),
            "edp_window_targets")
+
+
+def window_recenter(labels, qx, qy, win, centers):
+    H, W = labels.shape
+    _check(_learn_lib().edp_window_recenter(_ptr(labels), W, H, qx, qy, win, _ptr(centers), _stream(labels.device)),
+           "edp_window_recenter")
+    return centers

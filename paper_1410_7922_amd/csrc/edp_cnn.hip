@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void pool_kernel(const int32_t* cost, int32_t 
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void conv_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                                    const float* __restrict__ bias, int32_t h, int32_t wd,
-                                                   int32_t cout_real, int32_t relu,
+                                                   int32_t cout_real, int32_t relu, int32_t dil,
                                                    const uint16_t* __restrict__ mask_in, int32_t ld_out,
                                                    uint16_t* __restrict__ out_bf, float* __restrict__ out_f) {
     constexpr int NT = COUT / 16;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t* __restrict__ 
     for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
-        const int32_t ys = ya + tap / 3 - 1, xs = xa + tap % 3 - 1;
+        const int32_t ys = ya + (tap / 3 - 1) * dil, xs = xa + (tap % 3 - 1) * dil;
         const bool ok = pa < P && ys >= 0 && ys < h && xs >= 0 && xs < wd;
         const uint16_t* src = in + ((int64_t)ys * wd + xs) * CIN + kq;
 #pragma unroll
@@ -157,7 +157,7 @@ __global__ void flip_kernel(const uint16_t* w, int32_t cin, int32_t cout, int32_
 // chunks of 32 pixels are staged transposed in LDS, so both operands read 16 contiguous bytes.
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x,
-                                                    int32_t h, int32_t wd, int32_t cout_real,
+                                                    int32_t h, int32_t wd, int32_t cout_real, int32_t dil,
                                                     float* __restrict__ dw) {
     constexpr int KS = 40;                          // LDS row stride (elements), 16-byte multiple
     constexpr int MT = COUT / 16, NTL = CIN / 16, TILES = MT * NTL;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
     __shared__ __align__(16) uint16_t xt[CIN * KS];
     const int32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t tap = blockIdx.x;
-    const int32_t dyo = tap / 3 - 1, dxo = tap % 3 - 1;
+    const int32_t dyo = (tap / 3 - 1) * dil, dxo = (tap % 3 - 1) * dil;
     const int64_t P = (int64_t)h * wd;
     const int64_t nchunk = (P + 31) / 32;
     f32x4 acc[PER];
@@ -229,26 +229,35 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* a, int32_t row
     atomicAdd(&out[c], s);
 }
 
-// Softmax cross entropy of two heads of nclass logits per pixel; grad = (softmax - onehot) / n.
+// Per pixel and head, the negative log softmax mass of the window of win labels (clamped into
+// [0, nclass)) around the target, averaged over the n pixels and summed over the heads; win = 1
+// is the softmax cross entropy.  d/dz_k = (p_k - [k in window] p_k / mass) / n.
 __global__ __launch_bounds__(256) void ce_kernel(const float* logits, int32_t n, int32_t ld, const int32_t* tx,
-                                                 const int32_t* ty, int32_t nclass, float* grad_f,
+                                                 const int32_t* ty, int32_t nclass, int32_t win, float* grad_f,
                                                  uint16_t* grad_bf, float* loss) {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.f;
     if (p < n) {
         const float* z = logits + (int64_t)p * ld;
+        const int32_t r = win / 2;
         for (int head = 0; head < 2; ++head) {
             const int32_t t = head == 0 ? tx[p] : ty[p];
+            const int32_t c = min(max(t, r), nclass - 1 - r);
             const float* zh = z + head * nclass;
             float m = zh[0];
             for (int k = 1; k < nclass; ++k) m = fmaxf(m, zh[k]);
-            float s = 0.f;
-            for (int k = 0; k < nclass; ++k) s += expf(zh[k] - m);
-            l += logf(s) + m - zh[t];
-            const float inv = 1.f / s;
+            float s = 0.f, sw = 0.f;
             for (int k = 0; k < nclass; ++k) {
-                float g = expf(zh[k] - m) * inv;
-                if (k == t) g -= 1.f;
+                const float e = expf(zh[k] - m);
+                s += e;
+                if (k >= c - r && k <= c + r) sw += e;
+            }
+            l += logf(s) - logf(sw);
+            const float inv = 1.f / s, invw = 1.f / sw;
+            for (int k = 0; k < nclass; ++k) {
+                const float e = expf(zh[k] - m);
+                float g = e * inv;
+                if (k >= c - r && k <= c + r) g -= e * invw;
                 g /= (float)n;
                 const int64_t o = (int64_t)p * ld + head * nclass + k;
                 grad_f[o] = g;
@@ -264,8 +273,8 @@ __global__ __launch_bounds__(256) void ce_kernel(const float* logits, int32_t n,
     __shared__ float red[256];
     red[threadIdx.x] = l;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
     if (threadIdx.x == 0 && loss) atomicAdd(loss, red[0] / (float)n);
@@ -285,27 +294,53 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v, uint16
     }
 }
 
-// Per half-resolution pixel: first maximum of each head, clamped so the window fits the label
-// space; written to the 2 x 2 full-resolution pixels it covers.
+// Per half-resolution pixel and head: the window of largest probability mass.  With
+// m_c = sum_{|k-c| <= win/2} exp(z_k - max z) for c in [win/2, q-1-win/2], the centre is the
+// first c with m_c >= (1 - 1e-5) max m (near-equal windows resolve to the lowest centre),
+// written to the 2 x 2 full-resolution pixels it covers.
 __global__ void decode_kernel(const float* logits, int32_t h, int32_t w, int32_t ld, int32_t qx, int32_t qy,
                               int32_t win, int32_t nclass, int32_t* centers) {
     const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= h * w) return;
     const float* z = logits + (int64_t)p * ld;
+    const int32_t r = win / 2;
     int32_t best[2];
     for (int head = 0; head < 2; ++head) {
-        int32_t b = 0;
-        for (int k = 1; k < nclass; ++k)
-            if (z[head * nclass + k] > z[head * nclass + b]) b = k;
+        const float* zh = z + head * nclass;
+        const int32_t q = head == 0 ? qx : qy;
+        float m = zh[0];
+        for (int k = 1; k < q; ++k) m = fmaxf(m, zh[k]);
+        float e[64], mass[64];
+        for (int k = 0; k < q; ++k) e[k] = expf(zh[k] - m);
+        float top = 0.f;
+        for (int c = r; c <= q - 1 - r; ++c) {
+            float s = 0.f;
+            for (int k = c - r; k <= c + r; ++k) s += e[k];
+            mass[c] = s;
+            top = fmaxf(top, s);
+        }
+        int32_t b = r;
+        for (int c = q - 1 - r; c >= r; --c)
+            if (mass[c] >= top * (1.f - 1e-5f)) b = c;
         best[head] = b;
     }
-    const int32_t r = win / 2;
-    const int32_t cx = min(max(best[0], r), qx - 1 - r), cy = min(max(best[1], r), qy - 1 - r);
+    const int32_t cx = best[0], cy = best[1];
     const int32_t Y = p / w, X = p % w, W = 2 * w;
     for (int k = 0; k < 4; ++k) {
         const int64_t o = ((int64_t)(2 * Y + (k >> 1)) * W + 2 * X + (k & 1)) * 2;
         centers[o] = cx;
         centers[o + 1] = cy;
+    }
+}
+
+// windows re-centred on a labelling: centre = label coordinates clamped so the box fits
+__global__ void recenter_kernel(const int32_t* labels, int64_t n, int32_t qx, int32_t qy, int32_t win,
+                                int32_t* centers) {
+    const int32_t r = win / 2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t lab = labels[i];
+        centers[2 * i] = min(max(lab % qx, r), qx - 1 - r);
+        centers[2 * i + 1] = min(max(lab / qx, r), qy - 1 - r);
     }
 }
 
@@ -327,22 +362,22 @@ int blocks_for(int64_t n, int per, int cap) {
 
 template <int CIN, int COUT>
 hipError_t run_conv(const uint16_t* in, const uint16_t* w, const float* bias, int32_t h, int32_t wd,
-                    int32_t cout_real, int32_t relu, const uint16_t* mask, int32_t ld, uint16_t* ob, float* of,
-                    hipStream_t s) {
+                    int32_t cout_real, int32_t relu, int32_t dil, const uint16_t* mask, int32_t ld, uint16_t* ob,
+                    float* of, hipStream_t s) {
     const int64_t P = (int64_t)h * wd;
     hipLaunchKernelGGL((conv_kernel<CIN, COUT>), dim3((unsigned)((P + 63) / 64)), dim3(256), 0, s, in, w, bias, h,
-                       wd, cout_real, relu, mask, ld, ob, of);
+                       wd, cout_real, relu, dil, mask, ld, ob, of);
     return hipGetLastError();
 }
 
 template <int CIN, int COUT>
-hipError_t run_wgrad(const uint16_t* dy, const uint16_t* x, int32_t h, int32_t wd, int32_t cout_real, float* dw,
-                     hipStream_t s) {
+hipError_t run_wgrad(const uint16_t* dy, const uint16_t* x, int32_t h, int32_t wd, int32_t cout_real, int32_t dil,
+                     float* dw, hipStream_t s) {
     const int64_t nchunk = ((int64_t)h * wd + 31) / 32;
     int stripes = (int)((nchunk + 15) / 16);
     if (stripes > 64) stripes = 64;
     if (stripes < 1) stripes = 1;
-    hipLaunchKernelGGL((wgrad_kernel<CIN, COUT>), dim3(9, stripes), dim3(256), 0, s, dy, x, h, wd, cout_real, dw);
+    hipLaunchKernelGGL((wgrad_kernel<CIN, COUT>), dim3(9, stripes), dim3(256), 0, s, dy, x, h, wd, cout_real, dil, dw);
     return hipGetLastError();
 }
 
@@ -366,12 +401,12 @@ hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, in
 
 // (cin, cout) pairs compiled: the network's layers and their input gradients
 hipError_t launch_conv(int32_t cin, int32_t cout_pad, const uint16_t* in, const uint16_t* w, const float* bias,
-                       int32_t h, int32_t wd, int32_t cout_real, int32_t relu, const uint16_t* mask, int32_t ld,
-                       uint16_t* ob, float* of, hipStream_t s) {
-    if (cin == 64 && cout_pad == 32) return run_conv<64, 32>(in, w, bias, h, wd, cout_real, relu, mask, ld, ob, of, s);
-    if (cin == 32 && cout_pad == 32) return run_conv<32, 32>(in, w, bias, h, wd, cout_real, relu, mask, ld, ob, of, s);
-    if (cin == 32 && cout_pad == 64) return run_conv<32, 64>(in, w, bias, h, wd, cout_real, relu, mask, ld, ob, of, s);
-    if (cin == 64 && cout_pad == 64) return run_conv<64, 64>(in, w, bias, h, wd, cout_real, relu, mask, ld, ob, of, s);
+                       int32_t h, int32_t wd, int32_t cout_real, int32_t relu, int32_t dil, const uint16_t* mask,
+                       int32_t ld, uint16_t* ob, float* of, hipStream_t s) {
+    if (cin == 64 && cout_pad == 32) return run_conv<64, 32>(in, w, bias, h, wd, cout_real, relu, dil, mask, ld, ob, of, s);
+    if (cin == 32 && cout_pad == 32) return run_conv<32, 32>(in, w, bias, h, wd, cout_real, relu, dil, mask, ld, ob, of, s);
+    if (cin == 32 && cout_pad == 64) return run_conv<32, 64>(in, w, bias, h, wd, cout_real, relu, dil, mask, ld, ob, of, s);
+    if (cin == 64 && cout_pad == 64) return run_conv<64, 64>(in, w, bias, h, wd, cout_real, relu, dil, mask, ld, ob, of, s);
     return hipErrorInvalidValue;
 }
 
@@ -382,11 +417,11 @@ hipError_t launch_flip(const uint16_t* w, int32_t cin, int32_t cout, int32_t cou
 }
 
 hipError_t launch_wgrad(int32_t cin, int32_t cout_pad, const uint16_t* dy, const uint16_t* x, int32_t h, int32_t wd,
-                        int32_t cout_real, float* dw, hipStream_t s) {
-    if (cin == 64 && cout_pad == 32) return run_wgrad<64, 32>(dy, x, h, wd, cout_real, dw, s);
-    if (cin == 32 && cout_pad == 32) return run_wgrad<32, 32>(dy, x, h, wd, cout_real, dw, s);
-    if (cin == 32 && cout_pad == 64) return run_wgrad<32, 64>(dy, x, h, wd, cout_real, dw, s);
-    if (cin == 64 && cout_pad == 64) return run_wgrad<64, 64>(dy, x, h, wd, cout_real, dw, s);
+                        int32_t cout_real, int32_t dil, float* dw, hipStream_t s) {
+    if (cin == 64 && cout_pad == 32) return run_wgrad<64, 32>(dy, x, h, wd, cout_real, dil, dw, s);
+    if (cin == 32 && cout_pad == 32) return run_wgrad<32, 32>(dy, x, h, wd, cout_real, dil, dw, s);
+    if (cin == 32 && cout_pad == 64) return run_wgrad<32, 64>(dy, x, h, wd, cout_real, dil, dw, s);
+    if (cin == 64 && cout_pad == 64) return run_wgrad<64, 64>(dy, x, h, wd, cout_real, dil, dw, s);
     return hipErrorInvalidValue;
 }
 
@@ -396,9 +431,9 @@ hipError_t launch_colsum(const float* a, int32_t rows, int32_t cols, int32_t ld,
 }
 
 hipError_t launch_ce(const float* logits, int32_t n, int32_t ld, const int32_t* tx, const int32_t* ty,
-                     int32_t nclass, float* gf, uint16_t* gb, float* loss, hipStream_t s) {
+                     int32_t nclass, int32_t win, float* gf, uint16_t* gb, float* loss, hipStream_t s) {
     hipLaunchKernelGGL(ce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, logits, n, ld, tx, ty, nclass,
-                       gf, gb, loss);
+                       win, gf, gb, loss);
     return hipGetLastError();
 }
 
@@ -414,6 +449,13 @@ hipError_t launch_decode(const float* logits, int32_t h, int32_t w, int32_t ld, 
                          int32_t nclass, int32_t* centers, hipStream_t s) {
     hipLaunchKernelGGL(decode_kernel, dim3(blocks_for((int64_t)h * w, 256, 1 << 20)), dim3(256), 0, s, logits, h, w,
                        ld, qx, qy, win, nclass, centers);
+    return hipGetLastError();
+}
+
+hipError_t launch_recenter(const int32_t* labels, int64_t n, int32_t qx, int32_t qy, int32_t win, int32_t* centers,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(recenter_kernel, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, labels, n, qx, qy, win,
+                       centers);
     return hipGetLastError();
 }
 

@@ -51,10 +51,19 @@ class LearnedWindowEDP:
         """Relative energy gap of the windowed result over the plain EDP's."""
         return (e_window - e_plain) / max(abs(e_plain), 1)
 
-    def solve(self, cost, e_plain: int | None = None):
-        """Windowed solve, judged against the plain energy (computed here when not given);
-        falls back to the plain EDP above max_gap.  Returns a dict."""
-        lab, e, centers = self.solve_windowed(cost)
+    def solve_refined(self, cost, refine: int = 0):
+        """Windowed solve, then `refine` rounds of re-centring the windows on the labels found and
+        solving again.  Returns (labels, energy tensor, centres of the last round)."""
+        lab, e, cen = self.solve_windowed(cost)
+        for _ in range(refine):
+            cen = B.window_recenter(lab, self.qx, self.qy, self.win, torch.empty_like(cen))
+            lab, e, _ = self.solve_windowed(cost, cen)
+        return lab, e, cen
+
+    def solve(self, cost, e_plain: int | None = None, refine: int = 0):
+        """Windowed solve (with refinement rounds), judged against the plain energy (computed here
+        when not given); falls back to the plain EDP above max_gap.  Returns a dict."""
+        lab, e, centers = self.solve_refined(cost, refine)
         ew = int(e.item())
         if e_plain is None:
             _, ep = self.solve_plain(cost)
@@ -66,6 +75,60 @@ class LearnedWindowEDP:
             lab2, e2 = self.solve_plain(cost)
             out["labels"], out["energy"] = lab2, int(e2.item())
         return out
+
+
+def _timed(fn, reps=1):
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        out = fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return out, start.elapsed_time(stop) / reps
+
+
+def evaluate(solver: "LearnedWindowEDP", frames, refine: int = 2, reps: int = 1, log=None):
+    """Plain against learned-window EDP on motion frame pairs [(i0, i1), ...] (uint8): per instance
+    the plain time and energy, the learned stages' times, the energy gap and the fallback; the
+    learned time counts the plain re-solve of every instance whose gap exceeds max_gap."""
+    dev = solver.net.device
+    rows = []
+    r = (solver.qx - 1) // 2
+    for k, (i0, i1) in enumerate(frames):
+        cost = B.dsi_motion(torch.from_numpy(i0).to(dev), torch.from_numpy(i1).to(dev), r, solver.cmax)
+        (lab_p, e_p), t_plain = _timed(lambda: solver.solve_plain(cost), reps)
+        ep = int(e_p.item())
+        cen, t_win = _timed(lambda: solver.windows(cost), reps)
+        (lab_w, e_w, _), t_solve = _timed(lambda: solver.solve_refined(cost, refine), reps)
+        ew = int(e_w.item())
+        gap = solver.judge(ew, ep)
+        fb = gap > solver.max_gap
+        rows.append({"plain_ms": t_plain, "proposal_ms": t_win, "windowed_ms": t_solve,
+                     "learned_ms": t_win + t_solve + (t_plain if fb else 0.0), "gap": gap, "fallback": fb,
+                     "plain_energy": ep, "windowed_energy": ew,
+                     "hit_rate": window_hit_rate(cen, lab_p, solver.qx, solver.win)})
+        if log:
+            log(f"instance {k}: plain {t_plain:.2f} ms, proposal {t_win:.2f} ms, windowed x{refine + 1} "
+                f"{t_solve:.2f} ms, gap {gap * 100:.3f}%{' (fallback)' if fb else ''}")
+        del cost
+    return rows
+
+
+def summarize(rows, H, W, Q):
+    pl = H * W * Q
+    plain = float(np.mean([r["plain_ms"] for r in rows]))
+    learned = float(np.mean([r["learned_ms"] for r in rows]))
+    raw = float(np.mean([r["proposal_ms"] + r["windowed_ms"] for r in rows]))
+    gaps = np.array([r["gap"] for r in rows])
+    return {"instances": len(rows), "plain_ms": plain, "learned_ms_with_fallback": learned,
+            "learned_ms_without_fallback": raw,
+            "plain_pixel_labels_per_s": pl / (plain / 1e3),
+            "learned_pixel_labels_per_s": pl / (learned / 1e3),
+            "raw_windowed_pixel_labels_per_s": pl / (raw / 1e3),
+            "speedup_at_gap_bound": plain / learned, "raw_speedup": plain / raw,
+            "gap_mean": float(gaps.mean()), "gap_median": float(np.median(gaps)), "gap_max": float(gaps.max()),
+            "fraction_within_gap": float(np.mean([not r["fallback"] for r in rows])),
+            "window_hit_rate": float(np.mean([r["hit_rate"] for r in rows]))}
 
 
 def window_hit_rate(centers: torch.Tensor, labels: torch.Tensor, qx: int, win: int) -> float:

@@ -58,6 +58,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--decay", type=float, default=0.7, help="learning-rate factor per epoch")
+    ap.add_argument("--loss-window", type=int, default=1, help="window of the training loss (1: cross entropy)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_1410_7922_amd", "weights", "window_net_31x31.npz"))
@@ -111,7 +112,7 @@ def main():
         for j in range(args.val):
             k = args.instances + j
             logits = net.forward(X[k])
-            net.backward(X[k], TX[k], TY[k])
+            net.backward(X[k], TX[k], TY[k], args.loss_window)
             losses.append(float(net.loss.item()))
             cen = torch.empty((H, W, 2), dtype=torch.int32, device=dev)
             B.decode_windows(logits, h, w, 64, 2 * R + 1, 2 * R + 1, 7, 31, cen)
@@ -127,7 +128,7 @@ def main():
         lr = args.lr * (args.decay ** ep)
         tot = torch.zeros(1, dtype=torch.float32, device=dev)
         for k in order:
-            loss = net.train_step(X[k], TX[k], TY[k], lr)
+            loss = net.train_step(X[k], TX[k], TY[k], lr, args.loss_window)
             tot += loss
             steps += 1
         vl, vh = validate()
@@ -138,7 +139,7 @@ def main():
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
     meta = {"instances": args.instances, "size": [W, H], "seed0": args.seed0, "val": args.val,
-            "epochs": args.epochs, "lr": args.lr, "decay": args.decay, "input_scale": SCALE, "steps": steps, "labelling_seconds": label_s,
+            "epochs": args.epochs, "lr": args.lr, "decay": args.decay, "loss_window": args.loss_window, "input_scale": SCALE, "steps": steps, "labelling_seconds": label_s,
             "training_seconds": time.time() - t2, "history": history,
             "problem": {"labels": [2 * R + 1, 2 * R + 1], "cmax": CMAX, "lambda": LAM, "trunc": TRUNC,
                         "mode": "per-dimension", "iterations": 1}}

@@ -1,7 +1,7 @@
 """Label-window network: predicts, per pixel, the centre of a win x win label window.
 
-Four 3x3 convolutions (64 -> 32 -> 32 -> 32 -> 2 x 31, ReLU between) on the
-pooled cost volume at half resolution; bf16 weights and activations, float32
+Four 3x3 convolutions (64 -> 32 -> 32 -> 32 -> 2 x 31, ReLU between, dilations
+1, 2, 4, 8) on the pooled cost volume at half resolution; bf16 weights and activations, float32
 accumulation and master weights, trained with softmax cross entropy per label
 axis and Adam.  Every operation runs in the library's kernels (edp_learn.h);
 torch only allocates the buffers.
@@ -14,6 +14,7 @@ import torch
 from . import binding as B
 
 LAYERS = ((64, 32), (32, 32), (32, 32), (32, 62))
+DILATIONS = (1, 2, 4, 8)        # receptive field of 31 x 31 half-resolution pixels
 NCLASS = 31
 
 
@@ -67,7 +68,8 @@ class WindowNet:
         return self.p.detach().cpu().numpy().copy()
 
     def save(self, path):
-        np.savez(path, params=self.params_numpy(), layers=np.array(LAYERS, np.int32))
+        np.savez(path, params=self.params_numpy(), layers=np.array(LAYERS, np.int32),
+                 dilations=np.array(DILATIONS, np.int32))
 
     @classmethod
     def load(cls, path, device):
@@ -100,39 +102,40 @@ class WindowNet:
         for i, (cin, cout) in enumerate(LAYERS):
             wb, b, _, _ = self.layer(i)
             if i + 1 < len(LAYERS):
-                B.conv3x3_forward(cur, wb, b, h, w, cin, cout, True, y_bf16=bufs["acts"][i])
+                B.conv3x3_forward(cur, wb, b, h, w, cin, cout, True, y_bf16=bufs["acts"][i], dilation=DILATIONS[i])
                 cur = bufs["acts"][i]
             else:
-                B.conv3x3_forward(cur, wb, b, h, w, cin, cout, False, y_f32=bufs["logits"])
+                B.conv3x3_forward(cur, wb, b, h, w, cin, cout, False, y_f32=bufs["logits"], dilation=DILATIONS[i])
         return bufs["logits"]
 
-    def backward(self, x: torch.Tensor, tx: torch.Tensor, ty: torch.Tensor):
-        """Loss of the last forward() and the gradients (into self.g); returns the loss tensor."""
+    def backward(self, x: torch.Tensor, tx: torch.Tensor, ty: torch.Tensor, win: int = 1):
+        """Loss of the last forward() and the gradients (into self.g); returns the loss tensor.
+        win > 1 trains the window mass around the target instead of the exact label."""
         h, w, _ = x.shape
         P = h * w
         bufs = self._buffers(h, w)
         self.g.zero_()
         self.loss.zero_()
         last = len(LAYERS) - 1
-        B.ce_loss(bufs["logits"], P, 64, tx, ty, NCLASS, bufs["gf"][last], bufs["gb"][last], self.loss)
+        B.ce_loss(bufs["logits"], P, 64, tx, ty, NCLASS, bufs["gf"][last], bufs["gb"][last], self.loss, win)
         inputs = [x] + bufs["acts"]
         for i in range(last, -1, -1):
             cin, cout = LAYERS[i]
             wb, _, gw, gbias = self.layer(i)
             B.colsum(bufs["gf"][i], P, cout, _pad(cout), gbias)
-            B.conv3x3_wgrad(bufs["gb"][i], inputs[i], h, w, cin, cout, gw)
+            B.conv3x3_wgrad(bufs["gb"][i], inputs[i], h, w, cin, cout, gw, dilation=DILATIONS[i])
             if i > 0:
                 B.conv3x3_dgrad(bufs["gb"][i], wb, inputs[i], h, w, cin, cout, bufs["wt"],
-                                bufs["gf"][i - 1], bufs["gb"][i - 1])
+                                bufs["gf"][i - 1], bufs["gb"][i - 1], dilation=DILATIONS[i])
         return self.loss
 
     def step(self, lr: float):
         self.t += 1
         B.adam(self.p, self.g, self.m, self.v, self.pb, lr, self.t)
 
-    def train_step(self, x, tx, ty, lr):
+    def train_step(self, x, tx, ty, lr, win: int = 1):
         self.forward(x)
-        loss = self.backward(x, tx, ty)
+        loss = self.backward(x, tx, ty, win)
         self.step(lr)
         return loss
 

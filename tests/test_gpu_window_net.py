@@ -35,19 +35,21 @@ def pad(c):
     return 32 if c <= 32 else 64
 
 
-@pytest.mark.parametrize("cin,cout", [(64, 32), (32, 32), (32, 62), (64, 64)])
-def test_conv_forward_matches_reference(cin, cout):
-    note(f"conv forward {cin}->{cout}")
+@pytest.mark.parametrize("cin,cout,dil", [(64, 32, 1), (32, 32, 2), (32, 62, 8), (64, 64, 4), (32, 32, 16)])
+def test_conv_forward_matches_reference(cin, cout, dil):
+    note(f"conv forward {cin}->{cout} dilation {dil}")
     rng = np.random.default_rng(cin * 100 + cout)
     h, w = 9, 13                                    # 117 pixels: two workgroups, ragged
     x = N.bf16(rng.normal(0, 1, (h, w, cin)))
     wt = N.bf16(rng.normal(0, 0.2, (cout, 3, 3, cin)))
     b = rng.normal(0, 0.1, cout).astype(np.float32)
-    ref = N.conv3x3(x, wt, b.astype(np.float64))
+    ref = N.conv3x3(x, wt, b.astype(np.float64), dil)
     yf = torch.empty((h, w, pad(cout)), dtype=torch.float32, device=DEV)
-    B.conv3x3_forward(to_bf16_dev(x), to_bf16_dev(wt), torch.from_numpy(b).to(DEV), h, w, cin, cout, False, y_f32=yf)
+    B.conv3x3_forward(to_bf16_dev(x), to_bf16_dev(wt), torch.from_numpy(b).to(DEV), h, w, cin, cout, False, y_f32=yf,
+                      dilation=dil)
     yb = torch.empty((h, w, pad(cout)), dtype=torch.int16, device=DEV)
-    B.conv3x3_forward(to_bf16_dev(x), to_bf16_dev(wt), torch.from_numpy(b).to(DEV), h, w, cin, cout, True, y_bf16=yb)
+    B.conv3x3_forward(to_bf16_dev(x), to_bf16_dev(wt), torch.from_numpy(b).to(DEV), h, w, cin, cout, True, y_bf16=yb,
+                      dilation=dil)
     torch.cuda.synchronize()
     got = yf.cpu().numpy()
     assert np.allclose(got[:, :, :cout], ref, rtol=1e-4, atol=1e-4)
@@ -58,16 +60,16 @@ def test_conv_forward_matches_reference(cin, cout):
     assert np.allclose(gb, rb, rtol=2 ** -7, atol=1e-6)
 
 
-@pytest.mark.parametrize("cin,cout", [(32, 32), (32, 62), (64, 32)])
-def test_conv_gradients_match_reference(cin, cout):
-    note(f"conv gradients {cin}->{cout}")
+@pytest.mark.parametrize("cin,cout,dil", [(32, 32, 1), (32, 62, 8), (64, 32, 2), (32, 32, 4)])
+def test_conv_gradients_match_reference(cin, cout, dil):
+    note(f"conv gradients {cin}->{cout} dilation {dil}")
     rng = np.random.default_rng(7 + cin + cout)
     h, w = 11, 7
     P = h * w
     x = N.bf16(np.maximum(rng.normal(0, 1, (h, w, cin)), 0))       # a ReLU output: mask matters
     wt = N.bf16(rng.normal(0, 0.2, (cout, 3, 3, cin)))
     d = rng.normal(0, 1e-2, (h, w, cout))
-    dx_ref, dw_ref = N.conv3x3_backward(x, wt, N.bf16(d))
+    dx_ref, dw_ref = N.conv3x3_backward(x, wt, N.bf16(d), dil)
     dx_ref = dx_ref * (x > 0)
     dpad = np.zeros((h, w, pad(cout)))
     dpad[:, :, :cout] = d
@@ -75,9 +77,9 @@ def test_conv_gradients_match_reference(cin, cout):
     scratch = torch.empty(64 * 9 * 64, dtype=torch.int16, device=DEV)
     dxf = torch.empty((P, cin), dtype=torch.float32, device=DEV)
     dxb = torch.empty((P, cin), dtype=torch.int16, device=DEV)
-    B.conv3x3_dgrad(dyb, to_bf16_dev(wt), to_bf16_dev(x), h, w, cin, cout, scratch, dxf, dxb)
+    B.conv3x3_dgrad(dyb, to_bf16_dev(wt), to_bf16_dev(x), h, w, cin, cout, scratch, dxf, dxb, dilation=dil)
     dw = torch.zeros((cout, 9, cin), dtype=torch.float32, device=DEV)
-    B.conv3x3_wgrad(dyb, to_bf16_dev(x), h, w, cin, cout, dw)
+    B.conv3x3_wgrad(dyb, to_bf16_dev(x), h, w, cin, cout, dw, dilation=dil)
     db = torch.zeros(cout, dtype=torch.float32, device=DEV)
     df = torch.from_numpy(dpad.reshape(P, -1).astype(np.float32)).to(DEV)
     B.colsum(df, P, cout, pad(cout), db)
@@ -96,18 +98,19 @@ def test_cross_entropy_adam_decode_targets():
     z = np.zeros((h, w, 64), np.float32)
     z[:, :, :62] = rng.normal(0, 2, (h, w, 62))
     tx, ty = rng.integers(0, 31, (h, w)), rng.integers(0, 31, (h, w))
-    loss_ref, g_ref = N.ce_loss_grad(z[:, :, :62].astype(np.float64), tx, ty)
-    gf = torch.empty((P, 64), dtype=torch.float32, device=DEV)
-    gb = torch.empty((P, 64), dtype=torch.int16, device=DEV)
-    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
     zt = torch.from_numpy(z).to(DEV)
     txd = torch.from_numpy(tx.astype(np.int32).ravel()).to(DEV)
     tyd = torch.from_numpy(ty.astype(np.int32).ravel()).to(DEV)
-    B.ce_loss(zt, P, 64, txd, tyd, 31, gf, gb, loss)
-    torch.cuda.synchronize()
-    assert float(loss.item()) == pytest.approx(loss_ref, rel=1e-5)
-    assert np.allclose(gf.cpu().numpy().reshape(h, w, 64)[:, :, :62], g_ref, rtol=1e-4, atol=1e-7)
-    assert np.all(gf.cpu().numpy().reshape(h, w, 64)[:, :, 62:] == 0)
+    for win in (1, 7):
+        loss_ref, g_ref = N.ce_loss_grad(z[:, :, :62].astype(np.float64), tx, ty, win=win)
+        gf = torch.empty((P, 64), dtype=torch.float32, device=DEV)
+        gb = torch.empty((P, 64), dtype=torch.int16, device=DEV)
+        loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+        B.ce_loss(zt, P, 64, txd, tyd, 31, gf, gb, loss, win)
+        torch.cuda.synchronize()
+        assert float(loss.item()) == pytest.approx(loss_ref, rel=1e-5)
+        assert np.allclose(gf.cpu().numpy().reshape(h, w, 64)[:, :, :62], g_ref, rtol=1e-4, atol=1e-7)
+        assert np.all(gf.cpu().numpy().reshape(h, w, 64)[:, :, 62:] == 0)
     # Adam: three steps against the reference
     p = rng.normal(0, 1, 1000).astype(np.float32)
     pd, m, v = torch.from_numpy(p.copy()).to(DEV), torch.zeros(1000, device=DEV), torch.zeros(1000, device=DEV)

@@ -16,14 +16,17 @@ def test_bf16_matches_torch():
     assert np.array_equal(N.bf16(x), ref)
 
 
-def test_conv_matches_scipy_correlate():
+@pytest.mark.parametrize("dil", [1, 2, 3])
+def test_conv_matches_scipy_correlate(dil):
     rng = np.random.default_rng(1)
-    x = rng.normal(size=(5, 7, 3))
+    x = rng.normal(size=(9, 11, 3))
     w = rng.normal(size=(4, 3, 3, 3))
     b = rng.normal(size=4)
-    out = N.conv3x3(x, w, b)
+    out = N.conv3x3(x, w, b, dil)
     for co in range(4):
-        ref = b[co] + sum(signal.correlate2d(x[:, :, ci], w[co, :, :, ci], mode="same") for ci in range(3))
+        k = np.zeros((2 * dil + 1, 2 * dil + 1, 3))
+        k[::dil, ::dil] = w[co].transpose(0, 1, 2)          # dilated kernel: taps dil apart
+        ref = b[co] + sum(signal.correlate2d(x[:, :, ci], k[:, :, ci], mode="same") for ci in range(3))
         assert np.allclose(out[:, :, co], ref)
 
 
@@ -42,26 +45,28 @@ def _fd(f, a, eps=1e-6):
     return g
 
 
-def test_conv_backward_finite_differences():
+@pytest.mark.parametrize("dil", [1, 2])
+def test_conv_backward_finite_differences(dil):
     rng = np.random.default_rng(2)
-    x = rng.normal(size=(4, 5, 3))
+    x = rng.normal(size=(5, 6, 3))
     w = rng.normal(size=(2, 3, 3, 3))
-    dy = rng.normal(size=(4, 5, 2))
-    f = lambda: float(np.sum(N.conv3x3(x, w, np.zeros(2)) * dy))
-    dx, dw = N.conv3x3_backward(x, w, dy)
+    dy = rng.normal(size=(5, 6, 2))
+    f = lambda: float(np.sum(N.conv3x3(x, w, np.zeros(2), dil) * dy))
+    dx, dw = N.conv3x3_backward(x, w, dy, dil)
     assert np.allclose(dx, _fd(f, x), atol=1e-5)
     assert np.allclose(dw, _fd(f, w), atol=1e-5)
 
 
-def test_cross_entropy_closed_form_and_gradient():
+@pytest.mark.parametrize("win", [1, 7])
+def test_cross_entropy_closed_form_and_gradient(win):
     h, w = 3, 4
     tx = np.arange(12).reshape(h, w) % 31
     ty = (np.arange(12).reshape(h, w) * 7) % 31
-    loss, g = N.ce_loss_grad(np.zeros((h, w, 62)), tx, ty)
-    assert loss == pytest.approx(2 * np.log(31))
+    loss, g = N.ce_loss_grad(np.zeros((h, w, 62)), tx, ty, win=win)
+    assert loss == pytest.approx(2 * np.log(31 / win))        # uniform: each window holds win / 31
     z = np.random.default_rng(3).normal(size=(h, w, 62))
-    loss, g = N.ce_loss_grad(z, tx, ty)
-    fd = _fd(lambda: N.ce_loss_grad(z, tx, ty)[0], z)
+    loss, g = N.ce_loss_grad(z, tx, ty, win=win)
+    fd = _fd(lambda: N.ce_loss_grad(z, tx, ty, win=win)[0], z)
     assert np.allclose(g, fd, atol=1e-6)
 
 
@@ -75,12 +80,12 @@ def test_network_backward_finite_differences(monkeypatch):
     tx, ty = rng.integers(0, 31, (4, 4)), rng.integers(0, 31, (4, 4))
 
     def loss():
-        z, _ = N.forward(x, params)
+        z, _ = N.forward(x, params, (1, 2, 1))
         return N.ce_loss_grad(z, tx, ty)[0]
 
-    z, acts = N.forward(x, params)
+    z, acts = N.forward(x, params, (1, 2, 1))
     _, dz = N.ce_loss_grad(z, tx, ty)
-    grads = N.backward(params, acts, dz)
+    grads = N.backward(params, acts, dz, (1, 2, 1))
     for li in (0, 2):
         assert np.allclose(grads[li]["w"], _fd(loss, params[li]["w"]), atol=1e-6)
         assert np.allclose(grads[li]["b"], _fd(loss, params[li]["b"]), atol=1e-6)
@@ -110,11 +115,16 @@ def test_pool_by_hand():
 
 def test_decode_by_hand():
     logits = np.zeros((1, 2, 62))
-    logits[0, 0, 30] = 5.0            # column 30 -> clamped to 27
-    logits[0, 0, 31 + 1] = 5.0        # row 1 -> clamped to 3
+    logits[0, 0, 30] = 5.0            # column 30 -> the last window, centre 27
+    logits[0, 0, 31 + 1] = 5.0        # row 1 -> the first window, centre 3
     logits[0, 1, 10] = 1.0
     logits[0, 1, 31 + 20] = 2.0
     c = N.decode(logits, 31, 31, 7)
     assert c.shape == (2, 4, 2)
     assert c[0, 0].tolist() == [27, 3] and c[1, 1].tolist() == [27, 3]
-    assert c[0, 2].tolist() == [10, 20] and c[1, 3].tolist() == [10, 20]
+    assert c[0, 2].tolist() == [7, 17] and c[1, 3].tolist() == [7, 17]   # first window holding the peak
+    # two peaks 6 apart: the window holding both wins over either alone
+    z = np.full((1, 1, 62), -30.0)
+    z[0, 0, 12] = z[0, 0, 18] = 3.0
+    z[0, 0, 31 + 5] = 1.0
+    assert N.decode(z, 31, 31, 7)[0, 0].tolist() == [15, 3]
