@@ -127,17 +127,36 @@ def _qt(tile):
     return px * kx * py * ky
 
 
-def tune_batch(costs, params, cache: TuneCache | None = None, reps: int = 3, verbose=False) -> list:
-    """Launch shape for every instance of a batch: one tuning per key (largest grid of a label
-    space stands in for its smaller grids of the same key), reused from the cache when present."""
+def tune_batch(costs, params, cache: TuneCache | None = None, reps: int = 3, verbose=False,
+               merge: bool = True) -> list:
+    """Launch shape for every instance of a batch.  Instances sharing a label space, dtype, mode
+    and iteration count are tuned once, on the largest of them (cached per instance key).  With
+    merge, instances that chose the same tile share one shape (that of the tile's largest
+    instance), so the batch keeps one launch class per tile instead of one per tuned key."""
     cache = cache or TuneCache(None)
-    out = []
-    for c, p in zip(costs, params):
+    keys, groups = [], {}
+    for i, (c, p) in enumerate(zip(costs, params)):
         H, W = c.shape[:2]
-        k = key_of(p["qx"], p.get("qy", 1), c.dtype, p.get("mode", 0), W, H, p.get("iterations", 1))
-        shape = cache.get(k)
-        if shape is None:
-            shape = tune(c, p, reps, verbose)
-            cache.put(k, shape)
-        out.append({x: shape[x] for x in SHAPE_KEYS})
-    return out
+        keys.append(key_of(p["qx"], p.get("qy", 1), c.dtype, p.get("mode", 0), W, H, p.get("iterations", 1)))
+        gk = (p["qx"], p.get("qy", 1), str(c.dtype), p.get("mode", 0), p.get("iterations", 1))
+        groups.setdefault(gk, []).append(i)
+    shapes = [None] * len(costs)
+    for members in groups.values():
+        if all(cache.get(keys[i]) is not None for i in members):
+            for i in members:
+                shapes[i] = cache.get(keys[i])
+            continue
+        big = max(members, key=lambda i: costs[i].numel())
+        shape = tune(costs[big], params[big], reps, verbose)
+        for i in members:
+            cache.put(keys[i], shape)
+            shapes[i] = shape
+    if merge:
+        by_tile = {}
+        for i, sh in enumerate(shapes):
+            by_tile.setdefault(sh["tile"], []).append(i)
+        for members in by_tile.values():
+            big = max(members, key=lambda i: costs[i].numel())
+            for i in members:
+                shapes[i] = shapes[big]
+    return [{x: sh[x] for x in SHAPE_KEYS} for sh in shapes]
