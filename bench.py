@@ -267,6 +267,8 @@ def main():
     ap.add_argument("--learned", type=int, default=20, metavar="N",
                     help="held-out instances of the learned-window comparison (0 skips it)")
     ap.add_argument("--refine", type=int, default=2, help="window refinement rounds of the learned path")
+    ap.add_argument("--dp-only", action="store_true",
+                    help="run only the scanline DP sweep (for hardware-counter profiles of its kernels)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the DP sweep and motion workloads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -299,6 +301,14 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {args.calibrate_copy} MiB done")
         del src, dst
+    if args.dp_only:
+        r = bench_dp(edp, torch, args.steps, args.warmup)
+        print(json.dumps({"metric": "pixel-labels/sec (scanline DP sweep)", "value": r["pixel_labels_per_s"],
+                          "unit": "pixel-labels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "int32 (int16 costs)", "data": "synthetic uniform costs",
+                          "config": {"workload": r["workload"]}, "dp_sweep": r}), flush=True)
+        return
     prob = synth.workload("stereo384x288")
     H, W, Q = prob.cost.shape
     pl = H * W * Q
