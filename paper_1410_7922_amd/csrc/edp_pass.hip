@@ -397,7 +397,6 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     const int32_t blk = (int32_t)blockIdx.x;
     const InstDesc d = a.ndesc > 0 ? uniform_desc(a.descs[find_instance(a.descs, a.ndesc, blk, 1)]) : a.one;
     const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
-    const CT* __restrict__ cost = (const CT*)d.cost;
     const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     const int32_t cells = W * H;
     const int32_t cell = (blk - d.first_block) * a.cells_per_block + wave * RPW + grp;
@@ -410,6 +409,31 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
             oy = d.centers[2 * cell + 1] - d.win / 2;
         }
     }
+    // one vector load per operand: the lane's E sums of each neighbour are contiguous (lane-major),
+    // its costs are KX-runs; a missing neighbour reads as 0 (out-of-range buffer offset)
+    const int32_t tbytes = W * H * QT * 4;
+    const int32_t lofs = l * T::E * 4;
+    int32_t acc[KY][KX], tv[KY][KX];
+#pragma unroll
+    for (int ky = 0; ky < KY; ++ky) {
+        const int32_t vy = py * KY + ky;
+        const int32_t crun = (ok && vy < d.qy && px * KX < d.qx) ? (cell * Q + vy * d.qx + px * KX) * (int32_t)sizeof(CT)
+                                                                 : OOB;
+        int32_t cw[KX];
+        load_cost_words<CT, KX>(make_rsrc(d.cost, cells * Q * (int32_t)sizeof(CT)), crun, cw);
+#pragma unroll
+        for (int kx = 0; kx < KX; ++kx) acc[ky][kx] = cw[kx];
+    }
+    const int32_t nb[4] = {ok && x > 0 ? cell - 1 : -1, ok && x + 1 < W ? cell + 1 : -1,
+                           ok && y > 0 ? cell - W : -1, ok && y + 1 < H ? cell + W : -1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        load_vec<T::E>(make_rsrc(d.t[k], tbytes), nb[k] >= 0 ? nb[k] * QT * 4 + lofs : OOB, &tv[0][0]);
+#pragma unroll
+        for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < KX; ++kx) acc[ky][kx] += tv[ky][kx];
+    }
     int32_t best = 0x7FFFFFFF, bq = 0x7FFFFFFF;
 #pragma unroll
     for (int ky = 0; ky < KY; ++ky)
@@ -417,16 +441,11 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
         for (int kx = 0; kx < KX; ++kx) {
             const int32_t vy = py * KY + ky, vx = px * KX + kx;
             const bool in = WIN ? (vx < d.win && vy < d.win) : (vx < d.qx && vy < d.qy);
-            if (ok && in) {
-                const int32_t q = vy * d.qx + vx;
-                const int e = l * T::E + ky * KX + kx;
-                int32_t v = (int32_t)cost[(size_t)cell * Q + q];
-                if (x > 0) v += d.t[0][(size_t)(cell - 1) * QT + e];
-                if (x + 1 < W) v += d.t[1][(size_t)(cell + 1) * QT + e];
-                if (y > 0) v += d.t[2][(size_t)(cell - W) * QT + e];
-                if (y + 1 < H) v += d.t[3][(size_t)(cell + W) * QT + e];
-                const int32_t lab = WIN ? (oy + vy) * d.qx_full + (ox + vx) : q;
-                if (v < best || (v == best && lab < bq)) { best = v; bq = lab; }
+            const int32_t lab = WIN ? (oy + vy) * d.qx_full + (ox + vx) : vy * d.qx + vx;
+            const int32_t v = acc[ky][kx];
+            if (ok && in && (v < best || (v == best && lab < bq))) {
+                best = v;
+                bq = lab;
             }
         }
     // smallest value, then the smallest label among the lanes holding it
