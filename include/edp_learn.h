@@ -37,14 +37,16 @@ edp_status edp_dsi_motion(const uint8_t* d_i0, const uint8_t* d_i1, int32_t W, i
                           int32_t cmax, int32_t* d_cost, void* stream);
 
 /*
- * Network input: for each block of 4 x 4 labels (ceil(qx/4) * ceil(qy/4) = 64
- * channels) the minimum cost over the block, summed over the 2 x 2 pixels of a
- * half-resolution pixel, divided in float32 by 4 * scale (scale >= 1), rounded
- * to bf16.
- *   d_cost [H][W][qy*qx] int32 (H, W even);  d_out [H/2][W/2][64] bf16
+ * Network input, bf16 [H/2][W/2][C]: per half-resolution pixel and channel a
+ * minimum of the cost over a set of labels, summed over the 2 x 2 pixels and
+ * divided in float32 by 4 * scale (scale >= 1).
+ *   mode 0: C = ceil(qx/4) * ceil(qy/4) channels, one per block of 4 x 4 labels
+ *   mode 1: C = 64 channels: the minimum over each label column (qx channels),
+ *           then over each label row (qy channels), then zeros (qx + qy <= 64)
+ *   d_cost [H][W][qy*qx] int32 (H, W even)
  */
 edp_status edp_pool_cost(const int32_t* d_cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
-                         uint16_t* d_out, void* stream);
+                         int32_t mode, uint16_t* d_out, void* stream);
 
 /*
  * 3x3 convolution with zero padding on the matrix cores (bf16 operands,
@@ -91,9 +93,10 @@ edp_status edp_ce_loss(const float* d_logits, int32_t n, int32_t ld, const int32
                        int32_t nclass, int32_t win, float* d_grad_f32, uint16_t* d_grad_bf16, float* d_loss,
                        void* stream);
 
-/* One Adam step (bias-corrected, step t >= 1) over n float32 parameters, writing their bf16 copy. */
+/* One Adam step (bias-corrected, step t >= 1) over n float32 parameters, writing their bf16 copy.
+ * Gradient elements are clipped to [-clip, clip] when clip > 0; non-finite ones count as 0. */
 edp_status edp_adam(float* d_p, const float* d_g, float* d_m, float* d_v, uint16_t* d_p_bf16, int32_t n, float lr,
-                    float beta1, float beta2, float eps, int32_t t, void* stream);
+                    float beta1, float beta2, float eps, float clip, int32_t t, void* stream);
 
 /*
  * Window centres from the logits [h][w][ld] of the half-resolution grid: for

@@ -41,19 +41,26 @@ def label_blocks(q: int, block: int = 4):
     return [(s, min(s + block, q)) for s in range(0, q, block)]
 
 
-def pool_cost(cost, qx, qy, scale, block=4):
-    """cost [H][W][qy*qx] (H, W even) -> float64 [H/2][W/2][by*bx], bf16-rounded."""
+def pool_cost(cost, qx, qy, scale, block=4, mode=0):
+    """cost [H][W][qy*qx] (H, W even) -> float64 [H/2][W/2][C], bf16-rounded.  mode 0: one channel per
+    block x block labels; mode 1: 64 channels, the minimum over each label column, then over each
+    label row, then zeros."""
     H, W, Q = cost.shape
     assert Q == qx * qy and H % 2 == 0 and W % 2 == 0
     c = np.asarray(cost, dtype=np.int64).reshape(H, W, qy, qx)
-    bx, by = label_blocks(qx, block), label_blocks(qy, block)
-    out = np.zeros((H // 2, W // 2, len(by) * len(bx)), np.float64)
-    for j, (y0, y1) in enumerate(by):
-        for i, (x0, x1) in enumerate(bx):
-            m = c[:, :, y0:y1, x0:x1].min(axis=(2, 3))               # [H][W]
-            s = m[0::2, 0::2] + m[0::2, 1::2] + m[1::2, 0::2] + m[1::2, 1::2]
-            # one correctly rounded float32 division of two exact integers
-            out[:, :, j * len(bx) + i] = s.astype(np.float32) / np.float32(4 * scale)
+    if mode == 0:
+        bx, by = label_blocks(qx, block), label_blocks(qy, block)
+        sets = [(y0, y1, x0, x1) for (y0, y1) in by for (x0, x1) in bx]
+        nch = len(sets)
+    else:
+        sets = [(0, qy, x, x + 1) for x in range(qx)] + [(y, y + 1, 0, qx) for y in range(qy)]
+        nch = 64
+    out = np.zeros((H // 2, W // 2, nch), np.float64)
+    for ch, (y0, y1, x0, x1) in enumerate(sets):
+        m = c[:, :, y0:y1, x0:x1].min(axis=(2, 3))               # [H][W]
+        s = m[0::2, 0::2] + m[0::2, 1::2] + m[1::2, 0::2] + m[1::2, 1::2]
+        # one correctly rounded float32 division of two exact integers
+        out[:, :, ch] = s.astype(np.float32) / np.float32(4 * scale)
     return bf16(out)
 
 
@@ -154,8 +161,11 @@ def backward(params, acts, dlogits, dilations=DILATIONS):
     return grads
 
 
-def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update (bias-corrected) of the float master weights, in place."""
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, clip=0.0):
+    """One Adam update (bias-corrected) of the float master weights, in place; gradient elements
+    clipped to [-clip, clip] when clip > 0."""
+    if clip > 0:
+        g = np.clip(g, -clip, clip)
     m[:] = b1 * m + (1 - b1) * g
     v[:] = b2 * v + (1 - b2) * g * g
     mh = m / (1 - b1 ** t)

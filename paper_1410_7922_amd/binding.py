@@ -336,13 +336,13 @@ def _learn_lib():
     vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
     sig = {
         "edp_dsi_motion": [vp, vp, i32, i32, i32, i32, vp, vp],
-        "edp_pool_cost": [vp, i32, i32, i32, i32, i32, vp, vp],
+        "edp_pool_cost": [vp, i32, i32, i32, i32, i32, i32, vp, vp],
         "edp_conv3x3_forward": [vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp],
         "edp_conv3x3_dgrad": [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp],
         "edp_conv3x3_wgrad": [vp, vp, i32, i32, i32, i32, i32, vp, vp],
         "edp_colsum": [vp, i32, i32, i32, vp, vp],
         "edp_ce_loss": [vp, i32, i32, vp, vp, i32, i32, vp, vp, vp, vp],
-        "edp_adam": [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, i32, vp],
+        "edp_adam": [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, f32, i32, vp],
         "edp_decode_windows": [vp, i32, i32, i32, i32, i32, i32, i32, vp, vp],
         "edp_window_targets": [vp, i32, i32, i32, vp, vp, vp],
         "edp_window_recenter": [vp, i32, i32, i32, i32, i32, vp, vp],
@@ -372,15 +372,16 @@ def dsi_motion(i0: torch.Tensor, i1: torch.Tensor, r: int, cmax: int, out: torch
     return out
 
 
-def pool_cost(cost: torch.Tensor, qx: int, qy: int, scale: int, out: torch.Tensor | None = None):
-    """Network input [H/2][W/2][64] bf16 (as int16 storage) from an int32 cost volume (edp_pool_cost)."""
+def pool_cost(cost: torch.Tensor, qx: int, qy: int, scale: int, out: torch.Tensor | None = None, mode: int = 0):
+    """Network input [H/2][W/2][C] bf16 (as int16 storage) from an int32 cost volume (edp_pool_cost):
+    mode 0 minima over 4 x 4 label blocks, mode 1 minima over label columns and rows (64 channels)."""
     _device_tensor(cost, "cost")
     H, W, _ = cost.shape
-    nch = ((qx + 3) // 4) * ((qy + 3) // 4)
+    nch = ((qx + 3) // 4) * ((qy + 3) // 4) if mode == 0 else 64
     if out is None:
         out = torch.empty((H // 2, W // 2, nch), dtype=torch.int16, device=cost.device)
-    _check(_learn_lib().edp_pool_cost(cost.data_ptr(), W, H, qx, qy, scale, out.data_ptr(), _stream(cost.device)),
-           "edp_pool_cost")
+    _check(_learn_lib().edp_pool_cost(cost.data_ptr(), W, H, qx, qy, scale, mode, out.data_ptr(),
+                                      _stream(cost.device)), "edp_pool_cost")
     return out
 
 
@@ -408,9 +409,9 @@ def ce_loss(logits, n, ld, tx, ty, nclass, grad_f32, grad_bf16, loss, win=1):
                                     _ptr(grad_bf16), _ptr(loss), _stream(logits.device)), "edp_ce_loss")
 
 
-def adam(p, g, m, v, p_bf16, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+def adam(p, g, m, v, p_bf16, lr, t, beta1=0.9, beta2=0.999, eps=1e-8, clip=0.0):
     _check(_learn_lib().edp_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(p_bf16), p.numel(), lr, beta1, beta2,
-                                 eps, t, _stream(p.device)), "edp_adam")
+                                 eps, clip, t, _stream(p.device)), "edp_adam")
 
 
 def decode_windows(logits, h, wd, ld, qx, qy, win, nclass, centers):

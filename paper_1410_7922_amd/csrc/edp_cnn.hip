@@ -53,18 +53,33 @@ __global__ void dsi_motion_kernel(const uint8_t* i0, const uint8_t* i1, int32_t 
     }
 }
 
-// One wavefront per half-resolution pixel, one lane per label block (bx * by <= 64).
+// One wavefront per half-resolution pixel, one lane per channel.  mode 0: channel = block of
+// 4 x 4 labels (bx * by <= 64), the minimum over the block; mode 1: channel c < qx is the
+// minimum over the label column c, channel qx + r the minimum over the label row r (qx + qy <=
+// 64), further channels 0.  Each minimum is summed over the 2 x 2 pixels and divided by 4 scale.
 __global__ __launch_bounds__(256) void pool_kernel(const int32_t* cost, int32_t W, int32_t H, int32_t qx,
                                                    int32_t qy, int32_t scale, int32_t nbx, int32_t nch,
-                                                   uint16_t* out) {
+                                                   int32_t mode, uint16_t* out) {
     const int32_t w2 = W / 2, h2 = H / 2;
     const int64_t opix = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int32_t lane = threadIdx.x & 63;
     if (opix >= (int64_t)w2 * h2 || lane >= nch) return;
     const int32_t X = (int32_t)(opix % w2), Y = (int32_t)(opix / w2);
-    const int32_t bxi = lane % nbx, byi = lane / nbx;
-    const int32_t x0 = bxi * 4, x1 = x0 + 4 < qx ? x0 + 4 : qx;
-    const int32_t y0 = byi * 4, y1 = y0 + 4 < qy ? y0 + 4 : qy;
+    int32_t x0, x1, y0, y1;
+    if (mode == 0) {
+        const int32_t bxi = lane % nbx, byi = lane / nbx;
+        x0 = bxi * 4;
+        x1 = x0 + 4 < qx ? x0 + 4 : qx;
+        y0 = byi * 4;
+        y1 = y0 + 4 < qy ? y0 + 4 : qy;
+    } else if (lane < qx) {
+        x0 = lane, x1 = lane + 1, y0 = 0, y1 = qy;
+    } else if (lane < qx + qy) {
+        x0 = 0, x1 = qx, y0 = lane - qx, y1 = lane - qx + 1;
+    } else {
+        out[opix * nch + lane] = 0;
+        return;
+    }
     const int32_t Q = qx * qy;
     int64_t sum = 0;
     for (int k = 0; k < 4; ++k) {
@@ -280,10 +295,14 @@ __global__ __launch_bounds__(256) void ce_kernel(const float* logits, int32_t n,
     if (threadIdx.x == 0 && loss) atomicAdd(loss, red[0] / (float)n);
 }
 
+// Adam with each gradient element clipped to [-clip, clip] (clip > 0) and non-finite elements
+// dropped, so one bad step cannot poison the moments.
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, uint16_t* pb, int32_t n, float lr,
-                            float b1, float b2, float eps, float c1, float c2) {
+                            float b1, float b2, float eps, float c1, float c2, float clip) {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float gi = g[i];
+        float gi = g[i];
+        if (!(fabsf(gi) <= 3.0e38f)) gi = 0.f;
+        if (clip > 0.f) gi = fminf(fmaxf(gi, -clip), clip);
         const float mi = b1 * m[i] + (1.f - b1) * gi;
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
         m[i] = mi;
@@ -392,10 +411,10 @@ hipError_t launch_dsi_motion(const uint8_t* i0, const uint8_t* i1, int32_t W, in
 }
 
 hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
-                       int32_t nbx, int32_t nch, uint16_t* out, hipStream_t s) {
+                       int32_t nbx, int32_t nch, int32_t mode, uint16_t* out, hipStream_t s) {
     const int64_t n = (int64_t)(W / 2) * (H / 2);
     hipLaunchKernelGGL(pool_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, cost, W, H, qx, qy, scale, nbx,
-                       nch, out);
+                       nch, mode, out);
     return hipGetLastError();
 }
 
@@ -438,10 +457,10 @@ hipError_t launch_ce(const float* logits, int32_t n, int32_t ld, const int32_t* 
 }
 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int32_t n, float lr, float b1,
-                       float b2, float eps, int32_t t, hipStream_t s) {
+                       float b2, float eps, float clip, int32_t t, hipStream_t s) {
     const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
     hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256, 1024)), dim3(256), 0, s, p, g, m, v, pb, n, lr, b1, b2,
-                       eps, c1, c2);
+                       eps, c1, c2, clip);
     return hipGetLastError();
 }
 

@@ -189,7 +189,7 @@ hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStrea
 hipError_t launch_dsi_motion(const uint8_t* i0, const uint8_t* i1, int32_t W, int32_t H, int32_t r, int32_t cmax,
                              int32_t* out, hipStream_t s);
 hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
-                       int32_t nbx, int32_t nch, uint16_t* out, hipStream_t s);
+                       int32_t nbx, int32_t nch, int32_t mode, uint16_t* out, hipStream_t s);
 hipError_t launch_conv(int32_t cin, int32_t cout_pad, const uint16_t* in, const uint16_t* w, const float* bias,
                        int32_t h, int32_t wd, int32_t cout_real, int32_t relu, int32_t dil, const uint16_t* mask,
                        int32_t ld, uint16_t* ob, float* of, hipStream_t s);
@@ -200,7 +200,7 @@ hipError_t launch_colsum(const float* a, int32_t rows, int32_t cols, int32_t ld,
 hipError_t launch_ce(const float* logits, int32_t n, int32_t ld, const int32_t* tx, const int32_t* ty,
                      int32_t nclass, int32_t win, float* gf, uint16_t* gb, float* loss, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, int32_t n, float lr, float b1,
-                       float b2, float eps, int32_t t, hipStream_t s);
+                       float b2, float eps, float clip, int32_t t, hipStream_t s);
 hipError_t launch_decode(const float* logits, int32_t h, int32_t w, int32_t ld, int32_t qx, int32_t qy, int32_t win,
                          int32_t nclass, int32_t* centers, hipStream_t s);
 hipError_t launch_targets(const int32_t* labels, int32_t W, int32_t H, int32_t qx, int32_t* tx, int32_t* ty,

@@ -23,12 +23,15 @@ edp_status edp_dsi_motion(const uint8_t* d_i0, const uint8_t* d_i1, int32_t W, i
 }
 
 edp_status edp_pool_cost(const int32_t* d_cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
-                         uint16_t* d_out, void* stream) {
-    if (!d_cost || !d_out || W < 2 || H < 2 || (W & 1) || (H & 1) || qx < 1 || qy < 1 || scale < 1)
+                         int32_t mode, uint16_t* d_out, void* stream) {
+    if (!d_cost || !d_out || W < 2 || H < 2 || (W & 1) || (H & 1) || qx < 1 || qy < 1 || scale < 1 ||
+        (mode != 0 && mode != 1))
         return EDP_E_INVALID;
     const int32_t nbx = (qx + 3) / 4, nby = (qy + 3) / 4;
-    if (nbx * nby > 64) return EDP_E_UNSUPPORTED;
-    return st(launch_pool(d_cost, W, H, qx, qy, scale, nbx, nbx * nby, d_out, (hipStream_t)stream));
+    if (mode == 0 && nbx * nby > 64) return EDP_E_UNSUPPORTED;
+    if (mode == 1 && qx + qy > 64) return EDP_E_UNSUPPORTED;
+    return st(launch_pool(d_cost, W, H, qx, qy, scale, nbx, mode == 0 ? nbx * nby : 64, mode, d_out,
+                          (hipStream_t)stream));
 }
 
 edp_status edp_conv3x3_forward(const uint16_t* d_x, const uint16_t* d_w, const float* d_b, int32_t h, int32_t w,
@@ -83,11 +86,11 @@ edp_status edp_ce_loss(const float* d_logits, int32_t n, int32_t ld, const int32
 }
 
 edp_status edp_adam(float* d_p, const float* d_g, float* d_m, float* d_v, uint16_t* d_p_bf16, int32_t n, float lr,
-                    float beta1, float beta2, float eps, int32_t t, void* stream) {
+                    float beta1, float beta2, float eps, float clip, int32_t t, void* stream) {
     if (!d_p || !d_g || !d_m || !d_v || !d_p_bf16 || n < 1 || t < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
-        !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) || !(clip >= 0.f))
         return EDP_E_INVALID;
-    return st(launch_adam(d_p, d_g, d_m, d_v, d_p_bf16, n, lr, beta1, beta2, eps, t, (hipStream_t)stream));
+    return st(launch_adam(d_p, d_g, d_m, d_v, d_p_bf16, n, lr, beta1, beta2, eps, clip, t, (hipStream_t)stream));
 }
 
 edp_status edp_decode_windows(const float* d_logits, int32_t h, int32_t w, int32_t ld, int32_t qx, int32_t qy,

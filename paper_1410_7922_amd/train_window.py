@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--decay", type=float, default=0.7, help="learning-rate factor per epoch")
     ap.add_argument("--loss-window", type=int, default=1, help="window of the training loss (1: cross entropy)")
+    ap.add_argument("--pool-mode", type=int, default=1, help="network input: 0 label blocks, 1 label rows/columns")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_1410_7922_amd", "weights", "window_net_31x31.npz"))
@@ -88,12 +89,12 @@ def main():
     ws = edp.Workspace()
     lab = torch.empty((H, W), dtype=torch.int32, device=dev)
     en = torch.empty(1, dtype=torch.int64, device=dev)
-    net = WindowNet(dev, seed=args.init_seed)
+    net = WindowNet(dev, seed=args.init_seed, pool_mode=args.pool_mode)
     t1 = time.time()
     for k, (i0, i1) in enumerate(frames):
         B.dsi_motion(torch.from_numpy(i0).to(dev), torch.from_numpy(i1).to(dev), R, CMAX, out=cost)
         edp.solve(cost, 2 * R + 1, 2 * R + 1, LAM, TRUNC, 0, 1, cost_bound=CMAX, ws=ws, labels=lab, energy=en)
-        B.pool_cost(cost, 2 * R + 1, 2 * R + 1, SCALE, out=X[k])
+        B.pool_cost(cost, 2 * R + 1, 2 * R + 1, SCALE, out=X[k], mode=args.pool_mode)
         tx, ty = net.targets(lab, 2 * R + 1)
         TX[k].copy_(tx)
         TY[k].copy_(ty)
@@ -139,7 +140,7 @@ def main():
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     net.save(args.out)
     meta = {"instances": args.instances, "size": [W, H], "seed0": args.seed0, "val": args.val,
-            "epochs": args.epochs, "lr": args.lr, "decay": args.decay, "loss_window": args.loss_window, "input_scale": SCALE, "steps": steps, "labelling_seconds": label_s,
+            "epochs": args.epochs, "lr": args.lr, "decay": args.decay, "loss_window": args.loss_window, "pool_mode": args.pool_mode, "input_scale": SCALE, "steps": steps, "labelling_seconds": label_s,
             "training_seconds": time.time() - t2, "history": history,
             "problem": {"labels": [2 * R + 1, 2 * R + 1], "cmax": CMAX, "lambda": LAM, "trunc": TRUNC,
                         "mode": "per-dimension", "iterations": 1}}

@@ -23,8 +23,12 @@ def _pad(c):
 
 
 class WindowNet:
-    def __init__(self, device, seed: int = 0, params: np.ndarray | None = None):
+    """pool_mode: the network input (edp_pool_cost mode): 0 minima over 4 x 4 label blocks, 1 minima
+    over label columns and rows."""
+
+    def __init__(self, device, seed: int = 0, params: np.ndarray | None = None, pool_mode: int = 1):
         self.device = torch.device(device)
+        self.pool_mode = pool_mode
         self.offsets = []            # (w offset, w size, b offset, b size) per layer in the flat vector
         n = 0
         for cin, cout in LAYERS:
@@ -69,12 +73,13 @@ class WindowNet:
 
     def save(self, path):
         np.savez(path, params=self.params_numpy(), layers=np.array(LAYERS, np.int32),
-                 dilations=np.array(DILATIONS, np.int32))
+                 dilations=np.array(DILATIONS, np.int32), pool_mode=np.array(self.pool_mode, np.int32))
 
     @classmethod
     def load(cls, path, device):
         with np.load(path, allow_pickle=False) as f:
-            return cls(device, params=f["params"])
+            mode = int(f["pool_mode"]) if "pool_mode" in f.files else 0
+            return cls(device, params=f["params"], pool_mode=mode)
 
     # ---- buffers ----------------------------------------------------------
     def _buffers(self, h, w):
@@ -129,9 +134,9 @@ class WindowNet:
                                 bufs["gf"][i - 1], bufs["gb"][i - 1], dilation=DILATIONS[i])
         return self.loss
 
-    def step(self, lr: float):
+    def step(self, lr: float, clip: float = 1.0):
         self.t += 1
-        B.adam(self.p, self.g, self.m, self.v, self.pb, lr, self.t)
+        B.adam(self.p, self.g, self.m, self.v, self.pb, lr, self.t, clip=clip)
 
     def train_step(self, x, tx, ty, lr, win: int = 1):
         self.forward(x)
@@ -145,7 +150,7 @@ class WindowNet:
         """Window centres [H][W][2] int32 for an int32 cost volume [H][W][qy*qx]; scale is the
         input normaliser the network was trained with."""
         H, W, _ = cost.shape
-        x = B.pool_cost(cost, qx, qy, scale, out=pooled)
+        x = B.pool_cost(cost, qx, qy, scale, out=pooled, mode=self.pool_mode)
         logits = self.forward(x)
         if centers is None:
             centers = torch.empty((H, W, 2), dtype=torch.int32, device=cost.device)

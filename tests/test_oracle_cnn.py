@@ -99,6 +99,14 @@ def test_adam_first_step_is_a_signed_learning_rate():
     assert np.allclose(p, [1.0 - 0.01, -2.0 + 0.01, 0.5 - 0.01], atol=1e-6)
 
 
+def test_adam_clip_limits_the_gradient():
+    p = np.zeros(2)
+    m, v = np.zeros(2), np.zeros(2)
+    N.adam_step(p, np.array([5.0, -0.01]), m, v, 1, 0.1, clip=0.5)
+    assert np.allclose(m, [0.05, -0.001])                 # (1 - b1) * clipped gradient
+    assert np.allclose(p, [-0.1, 0.1], atol=1e-6)
+
+
 def test_pool_by_hand():
     qx = qy = 5                       # blocks [0,4) and [4,5) per axis -> 4 channels
     cost = np.full((2, 2, 25), 100, np.int64)
@@ -111,6 +119,20 @@ def test_pool_by_hand():
     assert out[0, 0, 1] == N.bf16((100 + 60 + 100 + 100) / 400.0)
     assert out[0, 0, 2] == N.bf16(1.0)
     assert out[0, 0, 3] == N.bf16((100 + 100 + 100 + 0) / 400.0)
+
+
+def test_axis_pool_by_hand():
+    qx, qy = 3, 2
+    cost = np.full((2, 2, 6), 50, np.int64)
+    cost[0, 0, 1 * 3 + 2] = 10        # pixel (0,0): label column 2, row 1
+    cost[1, 1, 0 * 3 + 0] = 30        # pixel (1,1): label column 0, row 0
+    out = N.pool_cost(cost, qx, qy, 10, mode=1)
+    assert out.shape == (1, 1, 64)
+    assert out[0, 0, 0] == N.bf16((50 + 50 + 50 + 30) / 40.0)      # column 0
+    assert out[0, 0, 2] == N.bf16((10 + 50 + 50 + 50) / 40.0)      # column 2
+    assert out[0, 0, 3] == N.bf16((50 + 50 + 50 + 30) / 40.0)      # row 0
+    assert out[0, 0, 4] == N.bf16((10 + 50 + 50 + 50) / 40.0)      # row 1
+    assert out[0, 0, 1] == N.bf16(200 / 40.0) and np.all(out[0, 0, 5:] == 0)
 
 
 def test_decode_by_hand():
