@@ -59,38 +59,43 @@ __device__ __forceinline__ int32_t load_cost(__amdgpu_buffer_rsrc_t r, int32_t o
     else return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
 }
 
-// N consecutive int32 at byte offset off (dword aligned), widest loads first.
-template <int N>
+// Cache policy of a buffer access that must be coherent at device scope (sc1): the
+// access is performed at the level shared by all compute units of the device.
+constexpr int CPOL_DEVICE = 16;
+
+// N consecutive int32 at byte offset off (dword aligned), widest loads first; AUX is the
+// cache policy.
+template <int N, int AUX = 0>
 __device__ __forceinline__ void load_vec(__amdgpu_buffer_rsrc_t r, int32_t off, int32_t* dst) {
     if constexpr (N % 4 == 0) {
 #pragma unroll
         for (int k = 0; k < N; k += 4) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off + 4 * k, 0, 0);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off + 4 * k, 0, AUX);
             dst[k] = (int32_t)v[0]; dst[k + 1] = (int32_t)v[1]; dst[k + 2] = (int32_t)v[2]; dst[k + 3] = (int32_t)v[3];
         }
     } else if constexpr (N == 2) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
         dst[0] = (int32_t)v[0]; dst[1] = (int32_t)v[1];
     } else {
 #pragma unroll
-        for (int k = 0; k < N; ++k) dst[k] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4 * k, 0, 0);
+        for (int k = 0; k < N; ++k) dst[k] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off + 4 * k, 0, AUX);
     }
 }
-template <int N>
+template <int N, int AUX = 0>
 __device__ __forceinline__ void store_vec(__amdgpu_buffer_rsrc_t r, int32_t off, const int32_t* src) {
     if constexpr (N % 4 == 0) {
 #pragma unroll
         for (int k = 0; k < N; k += 4) {
             const uint32_t __attribute__((ext_vector_type(4))) v = {(uint32_t)src[k], (uint32_t)src[k + 1],
                                                                     (uint32_t)src[k + 2], (uint32_t)src[k + 3]};
-            __builtin_amdgcn_raw_buffer_store_b128(v, r, off + 4 * k, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(v, r, off + 4 * k, 0, AUX);
         }
     } else if constexpr (N == 2) {
         const uint32_t __attribute__((ext_vector_type(2))) v = {(uint32_t)src[0], (uint32_t)src[1]};
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, AUX);
     } else {
 #pragma unroll
-        for (int k = 0; k < N; ++k) __builtin_amdgcn_raw_buffer_store_b32((uint32_t)src[k], r, off + 4 * k, 0, 0);
+        for (int k = 0; k < N; ++k) __builtin_amdgcn_raw_buffer_store_b32((uint32_t)src[k], r, off + 4 * k, 0, AUX);
     }
 }
 

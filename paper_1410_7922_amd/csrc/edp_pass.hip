@@ -34,6 +34,8 @@
 namespace edp {
 
 constexpr int MAX_WAVES = 8;
+// s_waitcnt vmcnt(0) with the other counters left open (gfx9 encoding: expcnt 7, lgkmcnt 15)
+constexpr int WAIT_VMCNT0 = 0x0F70;
 
 // Progress counters in LDS.  Every lane reads / writes the same word; the LDS
 // operations of one wavefront are performed in issue order, which orders a
@@ -173,19 +175,19 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
             const int32_t yp = y - sy;                     // previous row in scan order
             const int32_t yn = y + sy;                     // next row in scan order
             const bool has_next = j + 1 < H;
-            // where group 0 finds the row above: memory (first wavefront of a workgroup band
-            // that is not the first), LDS (other wavefronts), nowhere (the first row)
-            const bool from_global = wave == 0 && super > 0;
-            const bool from_lds = wave > 0;
-            // the band's last scanline feeds the next wavefront (LDS) or workgroup (memory)
-            const bool to_lds = wave + 1 < NW && band + 1 < d.nbands;
-            const bool to_global = wave == NW - 1 && band + 1 < d.nbands;
+            // Roles.  Group 0 takes the row above from memory (the first wavefront of a
+            // workgroup; there is none above the first band of the scan) or from LDS (the other
+            // wavefronts).  The band's last scanline goes to LDS (the next wavefront) or to
+            // memory (the next workgroup, or nobody after the last band).  Each of the four
+            // combinations has its own copy of the step loop, so no step branches on a role.
+            const bool in_global = wave == 0;
+            const bool gin = super > 0;                    // a workgroup band above exists
+            const bool out_lds = wave + 1 < NW && band + 1 < d.nbands;
+            const bool gout = band + 1 < d.nbands;         // a band below exists
             const bool store_a = SPLIT == 1 || !beta;
-            const bool store_b = (SPLIT == 1 || beta) && (b_live || (to_global && grp == RPW - 1));
             const bool hands = grp == RPW - 1 && (SPLIT == 1 || beta);
             const int32_t* ring_in = rings + (size_t)(wave > 0 ? wave - 1 : 0) * R * QT + l;
             int32_t* ring_out = rings + (size_t)wave * R * QT + l;
-            uint32_t seen = 0;                             // columns published by the workgroup above
             // byte offsets at step 0 (column -grp) and per-step strides: at step t the lane's
             // vertex is x = x0 + sx (t - grp) of row y
             const int32_t x0 = (sx > 0 ? 0 : W - 1) - sx * grp;
@@ -205,62 +207,95 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
             // wait for exactly the slot in use instead of for every load in flight
             const int32_t nsteps = (W + RPW - 1 + PF - 1) / PF * PF;
 
-            constexpr int CW = CostWords<CK, KX>::value;
-            int32_t rc[PF][KY][CW], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
-            int32_t rsh[PF][WIN ? 2 : 1];
-            int32_t carry[KY][KX], out[KY][KX];
-#pragma unroll
-            for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = out[ky][kx] = 0;
+            auto run = [&](auto in_tag, auto out_tag) {
+                constexpr bool IG = decltype(in_tag)::value;    // row above from memory
+                constexpr bool OG = decltype(out_tag)::value;   // last scanline to memory
+                // T_b of the last scanline of a band that feeds a workgroup is stored coherent
+                // at device scope, so the consumer needs no cache write-back or invalidation
+                const bool store_b = (SPLIT == 1 || beta) && (b_live || (OG && gout && grp == RPW - 1));
+                uint32_t seen = gin ? 0u : (uint32_t)W;       // columns published by the workgroup above
+                int32_t taken = 0;                             // columns the next wavefront has taken (lower bound)
 
-            // Issue the loads of step t into one ring slot (no branch around a load).
-            auto fetch = [&](const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX],
-                             int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX], int32_t (&sh)[WIN ? 2 : 1]) {
-                if (from_global && t < W && seen < (uint32_t)t + 1) {   // wave-uniform
-                    const uint32_t need = (uint32_t)t + 1;
-                    uint32_t v = 0, spins = 0;
+                constexpr int CW = CostWords<CK, KX>::value;
+                int32_t rc[PF][KY][CW], rma[PF][KY][KX], rmb[PF][KY][KX], rb[PF][KY][KX];
+                int32_t rsh[PF][WIN ? 2 : 1];
+                int32_t carry[KY][KX], out[KY][KX];
+#pragma unroll
+                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = out[ky][kx] = rb[0][ky][kx] = 0;
+
+                // Issue the loads of step t into one ring slot (no branch around a load).
+                auto fetch = [&](const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX],
+                                 int32_t (&mb)[KY][KX], int32_t (&gb)[KY][KX], int32_t (&sh)[WIN ? 2 : 1]) {
+                    if constexpr (IG) {
+                        if (t < W && seen < (uint32_t)t + 1) {       // wave-uniform
+                            const uint32_t need = (uint32_t)t + 1;
+                            uint32_t v = 0, spins = 0;
 #pragma nounroll
-                    for (;;) {
-                        v = flag_get(progress + super - 1);
-                        v = __builtin_amdgcn_readfirstlane(v);
-                        if (v >= epoch + need) break;
-                        // give up (and let every other waiter give up) instead of hanging
-                        if (++spins > SPIN_LIMIT ||
-                            flag_get(a.error) != 0) {
-                            raise_error(a.error);
-                            v = epoch + (uint32_t)W;
-                            break;
+                            for (;;) {
+                                v = flag_get(progress + super - 1);
+                                v = __builtin_amdgcn_readfirstlane(v);
+                                if (v >= epoch + need) break;
+                                // give up (and let every other waiter give up) instead of hanging
+                                if (++spins > SPIN_LIMIT ||
+                                    flag_get(a.error) != 0) {
+                                    raise_error(a.error);
+                                    v = epoch + (uint32_t)W;
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                            seen = v - epoch;
+                            // the row is read with device-scope loads issued after this point
+                            __atomic_signal_fence(__ATOMIC_SEQ_CST);
                         }
-                        __builtin_amdgcn_s_sleep(1);
                     }
-                    seen = v - epoch;
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                }
-                // column i = t - grp of this lane's scanline; offsets move by a fixed stride per step
-                const uint32_t i = (uint32_t)(t - grp);
-                const bool act = rowok && i < (uint32_t)W;
-                const bool nxt = i + 1 < (uint32_t)W;     // the next column in scan order exists
-                const int32_t offc = act ? bc + t * dc : OOB;
-                const int32_t offa = (act && nxt && !old_a_zero) ? ba + t * dt : OOB;
-                const int32_t offb = (act && has_next && !old_b_zero) ? bb + t * dt : OOB;
-                const int32_t offg = (act && from_global && grp == 0) ? bg + t * dt : OOB;
+                    // column i = t - grp of this lane's scanline; offsets move by a fixed stride per step
+                    const uint32_t i = (uint32_t)(t - grp);
+                    const bool act = rowok && i < (uint32_t)W;
+                    const bool nxt = i + 1 < (uint32_t)W;     // the next column in scan order exists
+                    const int32_t offc = act ? bc + t * dc : OOB;
+                    const int32_t offa = (act && nxt && !old_a_zero) ? ba + t * dt : OOB;
+                    const int32_t offb = (act && has_next && !old_b_zero) ? bb + t * dt : OOB;
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, offc + crun[ky], c[ky]);
-                load_vec<E>(rs_ma, offa, &ma[0][0]);
-                load_vec<E>(rs_mb, offb, &mb[0][0]);
-                load_vec<E>(rs_b, offg, &gb[0][0]);
-                if constexpr (WIN) load_vec<2>(rs_sh, act ? bsh + t * dsh : OOB, sh);
-            };
+                    for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, offc + crun[ky], c[ky]);
+                    load_vec<E>(rs_ma, offa, &ma[0][0]);
+                    load_vec<E>(rs_mb, offb, &mb[0][0]);
+                    if constexpr (IG) {
+                        const int32_t offg = (act && gin && grp == 0) ? bg + t * dt : OOB;
+                        load_vec<E, CPOL_DEVICE>(rs_b, offg, &gb[0][0]);
+                    }
+                    if constexpr (WIN) load_vec<2>(rs_sh, act ? bsh + t * dsh : OOB, sh);
+                };
 
 #pragma unroll
-            for (int u = 0; u < PF; ++u) fetch(u, rc[u], rma[u], rmb[u], rb[u], rsh[u]);
+                for (int u = 0; u < PF; ++u) fetch(u, rc[u], rma[u], rmb[u], rb[u], rsh[u]);
 
-            for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
+                // Input of an inner wavefront: the producer's counter and the ring slot of column
+                // t, read back to back.  LDS performs the operations of the CU in arrival order and
+                // the producer writes a slot before the counter, so when the counter shows column t
+                // the slot read issued after it returns that column.  Column t + 1 is read at the
+                // end of step t, which keeps the LDS round trip off the step when the producer is
+                // ahead.
+                int32_t in_ready = 0, in_lb[KY][KX];
+                auto read_input = [&](const int32_t t) {
+                    const int32_t* slot = ring_in + (size_t)(t & (R - 1)) * QT;
+                    in_ready = lds_get(prod + wave - 1);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
-                    const int32_t s = s0 + u;
-                    {
+                    for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                        for (int kx = 0; kx < KX; ++kx)
+                            in_lb[ky][kx] = __hip_atomic_load(slot + (ky * KX + kx) * G, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+                };
+                if constexpr (!IG) read_input(0);
+
+                for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) {
+                        const int32_t s = s0 + u;
                         const int32_t i = s - grp;
                         const bool act = rowok && (uint32_t)i < (uint32_t)W;
                         // T_b of the row above at this column, for group 0 of an inner wavefront
@@ -269,24 +304,26 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
                             for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = 0;
-                        if (from_lds && s < W) {                 // wave-uniform
-                            uint32_t spins = 0;
+                        if constexpr (!IG) {
+                            if (s < W) {                                 // wave-uniform
+                                uint32_t spins = 0;
 #pragma nounroll
-                            while (lds_get(prod + wave - 1) < s + 1) {
-                                if (++spins > SPIN_LIMIT) {
-                                    raise_error(a.error);
-                                    break;
+                                while (in_ready < s + 1) {
+                                    if (++spins > SPIN_LIMIT) {
+                                        raise_error(a.error);
+                                        break;
+                                    }
+                                    read_input(s);
                                 }
+#pragma unroll
+                                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                                    for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = in_lb[ky][kx];
+                                // LDS operations of a wavefront complete in order: the slot is
+                                // read before the counter that frees it is written
+                                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                                lds_put(cons + wave, s + 1);
                             }
-                            const int32_t* slot = ring_in + (size_t)(s & (R - 1)) * QT;
-#pragma unroll
-                            for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                                for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = slot[(ky * KX + kx) * G];
-                            // LDS operations of a wavefront complete in order: the slot is
-                            // read before the counter that frees it is written
-                            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                            lds_put(cons + wave, s + 1);
                         }
                         int32_t h[KY][KX], h2[KY][KX];
 #pragma unroll
@@ -307,7 +344,7 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                     mb = beta ? x2 : x1;
                                     if (i == 0) cr = 0;
                                 }
-                                if (grp == 0) mb = from_global ? rb[u][ky][kx] : lb[ky][kx];
+                                if (grp == 0) mb = IG ? rb[u][ky][kx] : lb[ky][kx];
                                 const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + cr + mb;
                                 const int32_t d = rmb[u][ky][kx] - rma[u][ky][kx];
                                 if constexpr (SPLIT == 1) {
@@ -342,17 +379,22 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                 out[ky][kx] = tbv[ky][kx];
                             }
                         store_vec<E>(rs_a, oa, &h[0][0]);
-                        store_vec<E>(rs_b, ob, &tbv[0][0]);
+                        if constexpr (OG) store_vec<E, CPOL_DEVICE>(rs_b, ob, &tbv[0][0]);
+                        else store_vec<E>(rs_b, ob, &tbv[0][0]);
                         // hand the band's last scanline T_b to the next wavefront / workgroup
                         const int32_t il = s - (RPW - 1);
                         if (il >= 0 && il < W) {                 // wave-uniform
-                            if (to_lds) {
-                                uint32_t spins = 0;
+                            if constexpr (!OG) {
+                                // ring space: the consumer's count only grows, so the last value
+                                // read stays a valid lower bound; read LDS only when it is short
+                                if (taken < il + 1 - R) {
+                                    uint32_t spins = 0;
 #pragma nounroll
-                                while (lds_get(cons + wave + 1) < il + 1 - R) {
-                                    if (++spins > SPIN_LIMIT) {
-                                        raise_error(a.error);
-                                        break;
+                                    while ((taken = lds_get(cons + wave + 1)) < il + 1 - R) {
+                                        if (++spins > SPIN_LIMIT) {
+                                            raise_error(a.error);
+                                            break;
+                                        }
                                     }
                                 }
                                 int32_t* dst = hands ? ring_out + (size_t)(il & (R - 1)) * QT : trash + l;
@@ -362,18 +404,34 @@ __global__ __launch_bounds__(64 * MAX_WAVES) void edp_pass_kernel(const PassArgs
                                     for (int kx = 0; kx < KX; ++kx) dst[(ky * KX + kx) * G] = out[ky][kx];
                                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                                 lds_put(prod + wave, il + 1);
+                            } else {
+                                if (gout && (((il + 1) & (a.chunk - 1)) == 0 || il == W - 1)) {
+                                    // the row went out with device-scope stores: once they have
+                                    // completed the progress word may show it
+                                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                                    __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+                                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                                    if (lane == 0)
+                                        flag_put(progress + super, epoch + (uint32_t)(il + 1));
+                                }
                             }
-                            if (to_global && (((il + 1) & (a.chunk - 1)) == 0 || il == W - 1)) {
-                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                                if (lane == 0)
-                                    flag_put(progress + super, epoch + (uint32_t)(il + 1));
-                            }
+                        }
+                        if constexpr (!IG) {
+                            if (s + 1 < W) read_input(s + 1);
                         }
                         fetch(s + PF, rc[u], rma[u], rmb[u], rb[u], rsh[u]);
                     }
                 }
+            };
+            if (in_global) {
+                if (out_lds) run(std::true_type{}, std::false_type{});
+                else run(std::true_type{}, std::true_type{});
+            } else {
+                if (out_lds) run(std::false_type{}, std::false_type{});
+                else run(std::false_type{}, std::true_type{});
             }
         }
+
         // Band complete: every wavefront makes its stores visible to the device before the
         // workgroup records the scan as done for this band (read by a fused second scan).
         if (a.npass > 1 && !second) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
