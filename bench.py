@@ -321,7 +321,7 @@ def main():
     mean_launch_ms = launch_ms.mean(axis=0)
     alg_bytes = float(sum(per_pass_bytes))
     achieved = alg_bytes / (mean_launch_ms.sum() / 1e3) / 1e9
-    src_hash = kernel_source_hash(["edp_pass.hip", "edp_device.hpp"])
+    src_hash = kernel_source_hash(["edp_pass_kernel.hpp", "edp_device.hpp"])
     traffic = measured_traffic("edp_pass_stereo384x288", src_hash)
     log(f"step {ms:.3f} ms, scan launches {mean_launch_ms.round(4).tolist()} ms")
 

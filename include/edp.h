@@ -69,11 +69,13 @@ typedef struct {
 /* Optional tuning of the launch (results never depend on it).  NULL, or a
  * zero / negative field, selects the built-in choice:
  *   tile   lane tile mapping labels to lanes (edp_tiles(); -1 automatic)
- *   chunk  EDP columns between two progress publications of a workgroup
- *          (rounded up to a power of two)
+ *   chunk  EDP columns a workgroup hands to the next one between two
+ *          progress publications, at least (rounded up to a power of two)
  *   split  1: every lane runs both minimum searches of a scan step;
  *          2: the two searches run on two halves of the vertex's lanes
- *   waves  wavefronts per EDP workgroup (1..8), handing rows over in LDS
+ *   waves  compute wavefronts per EDP workgroup (1..8), handing rows over in
+ *          LDS; every workgroup has one more wavefront that moves the rows
+ *          between workgroups
  *   fuse   EDP scans per launch: 1, or 2 (P1 with P2, P3 with P4: the two
  *          scans of a pair sweep the rows in the same order, so the second
  *          follows the first a few rows behind inside one launch)

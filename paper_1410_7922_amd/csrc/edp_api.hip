@@ -115,20 +115,20 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     if (split != 1 && split != 2) return EDP_E_INVALID;
     if (split * g > 64) return EDP_E_INVALID;
     int waves = (tu && tu->waves > 0) ? tu->waves : 4;
-    if (waves > 8) return EDP_E_INVALID;
+    if (waves > MAX_WAVES) return EDP_E_INVALID;
     const int fuse = (tu && tu->fuse > 0) ? tu->fuse : 2;
     if (fuse != 1 && fuse != 2) return EDP_E_INVALID;
     L->fuse = fuse;
     L->split = split;
     L->waves = waves;
     // progress publication period and LDS ring depth are powers of two (masks, no division)
-    int chunk = (tu && tu->chunk > 0) ? tu->chunk : 4;
+    int chunk = (tu && tu->chunk > 0) ? tu->chunk : 2;
     int c2 = 1;
     while (c2 < chunk && c2 < 1024) c2 <<= 1;
     L->chunk = c2;
     const int qt = qt_of(L->tile);
     int ring = 16;
-    while (ring > 2 && (size_t)(waves - 1) * ring * qt * 4 > 48 * 1024) ring >>= 1;
+    while (ring > 2 && (size_t)(waves + 1) * ring * qt * 4 > 48 * 1024) ring >>= 1;
     L->ring = ring;
     L->rpw = 64 / (split * g);
     L->nbands = (p->height + L->rpw - 1) / L->rpw;

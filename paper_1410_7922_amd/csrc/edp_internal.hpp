@@ -28,6 +28,7 @@
 namespace edp {
 
 constexpr int NUM_TILES = 16;
+constexpr int MAX_WAVES = 8;     // wavefronts per workgroup of the scan kernel
 // The label-window solve: 8 x 8 label frames on tile 14 (4 x 2 by 4 x 2), scan kernel kind 4.
 constexpr int WIN_TILE = 14;
 constexpr int KIND_WINDOW = 4;
