@@ -73,8 +73,8 @@ typedef struct {
  *          progress publications, at least (rounded up to a power of two)
  *   split  1: every lane runs both minimum searches of a scan step;
  *          2: the two searches run on two halves of the vertex's lanes
- *   waves  compute wavefronts per EDP workgroup (1..8), handing rows over in
- *          LDS; every workgroup has one more wavefront that moves the rows
+ *   waves  compute wavefronts per EDP workgroup (1..6), handing rows over in
+ *          LDS; every workgroup has two more wavefronts that move the rows
  *          between workgroups
  *   fuse   EDP scans per launch: 1, or 2 (P1 with P2, P3 with P4: the two
  *          scans of a pair sweep the rows in the same order, so the second
@@ -88,7 +88,7 @@ typedef struct {
     int32_t tile;        /* tile id from edp_tiles(), or -1 for automatic */
     int32_t chunk;       /* EDP columns per progress publication, 0 = automatic */
     int32_t split;       /* 1 or 2, 0 = automatic */
-    int32_t waves;       /* 1..8, 0 = automatic */
+    int32_t waves;       /* 1..6, 0 = automatic */
     int32_t fuse;        /* 1 or 2, 0 = automatic */
     void* const* events; /* nullable, see above */
     int32_t n_events;    /* number of handles in events */
@@ -135,7 +135,8 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
  * neighbour's frame, so the work per vertex does not grow with Q.  win odd,
  * 1 <= win <= 8, boxes inside the label space (win/2 <= cx < qx - win/2, same
  * for cy); int32 costs.  The energy is that of the labels on the full cost.
- * tuning: tile must be -1 or 14, split 1; waves, chunk, fuse as for edp_solve.
+ * tuning: tile must be -1 or 13 (the 8 x 8 lane tile, one label per lane),
+ *         split 1; waves, chunk, fuse as for edp_solve.
  *   d_centers [H][W][2] int32;  d_labels [H][W] int32 labels of the full space
  */
 edp_status edp_window_workspace_size(const edp_problem* prob, int32_t win, const edp_tuning* tuning,

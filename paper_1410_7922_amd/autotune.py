@@ -10,7 +10,7 @@ the built-in shape.  Choices are cached in a JSON file keyed by
 Search (staged, so a key costs a few dozen solves):
   1. every tile that holds the label space with at most 4x padding, each split
      the tile allows, with 4 wavefronts per workgroup;
-  2. the best (tile, split) with 1, 2, 4 and 8 wavefronts, one or two scans per launch;
+  2. the best (tile, split) with 1, 2, 4 and 6 wavefronts, one or two scans per launch;
   3. the best so far with progress published every 1, 2, 4, 8 or 16 columns.
 """
 from __future__ import annotations
@@ -113,7 +113,7 @@ def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict
         for split in (1, 2) if 2 * px * py <= 64 else (1,):
             consider(dict(tile=t, split=split, waves=4, chunk=4, fuse=2))
     base = dict(best)
-    for waves in (1, 2, 4, 8):
+    for waves in (1, 2, 4, 6):
         for fuse in (1, 2):
             consider(dict(base, waves=waves, fuse=fuse))
     base = dict(best)

@@ -37,12 +37,18 @@ bool fits(int tile, int qx, int qy) {
     return t.px * t.kx >= qx && t.py * t.ky >= qy;
 }
 
-// Built-in choice: least padding; then vertices that fill one 16-lane row
-// (every cross-lane step of the minimum search is a single DPP instruction);
-// then fewest labels per lane.
+// Built-in choice: least padding; then, for one label dimension, vertices that fill
+// one 16-lane row (every cross-lane step of the minimum search is a single DPP
+// instruction), for two, vertices that fill the wavefront (the scan step costs the
+// same instructions whatever the lane count, so more lanes per vertex means fewer
+// labels per lane); then fewest labels per lane; then square lane grids.
 int auto_tile(int qx, int qy) {
     int best = -1;
-    auto score = [](int t) { return (group_of(t) == 16 ? 0 : 1000) + elems_of(t); };
+    auto score = [qy](int t) {
+        const int lanes = group_of(t);
+        const int pref = qy == 1 ? 16 : 64;
+        return (lanes == pref ? 0 : 1000) + 10 * elems_of(t) + (kTiles[t].px == kTiles[t].py ? 0 : 1);
+    };
     for (int t = 0; t < NUM_TILES; ++t) {
         if (!fits(t, qx, qy)) continue;
         if (best < 0 || qt_of(t) < qt_of(best) || (qt_of(t) == qt_of(best) && score(t) < score(best))) best = t;
@@ -128,7 +134,8 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     L->chunk = c2;
     const int qt = qt_of(L->tile);
     int ring = 16;
-    while (ring > 2 && (size_t)(waves + 1) * ring * qt * 4 > 48 * 1024) ring >>= 1;
+    while (ring > 4 && (size_t)(waves + 1) * ring * qt * 4 > 96 * 1024) ring >>= 1;
+    while (ring > 2 && (size_t)(waves + 1) * ring * qt * 4 > 128 * 1024) ring >>= 1;
     L->ring = ring;
     L->rpw = 64 / (split * g);
     L->nbands = (p->height + L->rpw - 1) / L->rpw;

@@ -28,9 +28,11 @@
 namespace edp {
 
 constexpr int NUM_TILES = 16;
-constexpr int MAX_WAVES = 8;     // wavefronts per workgroup of the scan kernel
-// The label-window solve: 8 x 8 label frames on tile 14 (4 x 2 by 4 x 2), scan kernel kind 4.
-constexpr int WIN_TILE = 14;
+// compute wavefronts per workgroup of the scan kernel; with its two helper wavefronts a
+// workgroup has at most 8, two per SIMD, so each may use half the register file
+constexpr int MAX_WAVES = 6;
+// The label-window solve: 8 x 8 label frames on tile 13 (8 x 1 by 8 x 1), scan kernel kind 4.
+constexpr int WIN_TILE = 13;
 constexpr int KIND_WINDOW = 4;
 constexpr int WIN_FRAME = 8;
 

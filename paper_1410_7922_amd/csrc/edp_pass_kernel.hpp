@@ -81,7 +81,7 @@ __device__ __forceinline__ void raise_error(uint32_t* error) { flag_put(error, 1
 // compute wavefronts never touch another workgroup's data, so they never wait for memory
 // operations other than their own prefetched loads.
 template <class T, class CK, int SPLIT, int PF, bool WIN = false>
-__global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const PassArgs a) {
+__global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const PassArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int CL = SPLIT * G;                  // lanes per vertex
     constexpr int RPW = 64 / CL;                   // scanlines per wavefront
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
     const int32_t lane = lane_id();
     // wavefront-uniform values live in scalar registers, so control flow on them is scalar
     const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-    const int32_t NW = (int32_t)(blockDim.x >> 6) - 1;     // compute wavefronts; wave NW helps
+    const int32_t NW = (int32_t)(blockDim.x >> 6) - 2;     // compute wavefronts; waves NW, NW + 1 help
     const int32_t grp = lane / CL;
     const bool beta = SPLIT == 2 && ((lane / G) & 1);
     const int32_t l = lane % G;
@@ -162,36 +162,32 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
         int32_t* const t_b = kb == 3 ? d.t[3] : d.t[2];
         const __amdgpu_buffer_rsrc_t rs_b = make_rsrc(t_b, tbytes);
         const int32_t nact = min(NW, d.nbands - super * NW);   // compute wavefronts with a band
-        if (wave == NW) {
-            // Helper.  Lanes move CPI columns per instruction, G lanes x E values each; a
-            // ring slot holds value (ky, kx) of vertex lane l at (ky * KX + kx) * G + l.
+        if (wave >= NW) {
+            // Helpers (wave NW: rows in, wave NW + 1: rows out).  Lanes move CPI columns per
+            // instruction, G lanes x E values each; a ring slot holds value (ky, kx) of vertex
+            // lane l at (ky * KX + kx) * G + l.
             constexpr int CPI = 64 / G;
             constexpr int NI = CPI >= 4 ? 2 : 8 / CPI; // instructions per batch
             const int32_t cg = lane / G;
-            const bool gin = super > 0;                // a workgroup band above exists
-            const bool gout = super * NW + nact < d.nbands;   // a workgroup band below exists
             const int32_t xs = sx > 0 ? 0 : W - 1;     // x of column 0
             const int32_t dtc = sx * QT * 4;           // byte stride per column
-            const int32_t j0 = super * NW * RPW;       // first scanline of the band
-            const int32_t j1 = (super * NW + nact) * RPW - 1;   // last scanline (full band if gout)
-            const int32_t b_in = gin ? cell_off(((sy > 0 ? j0 : H - 1 - j0) - sy) * W + xs, QT * 4) + lofs : OOB;
-            const int32_t b_out = gout ? cell_off((sy > 0 ? j1 : H - 1 - j1) * W + xs, QT * 4) + lofs : OOB;
-            int32_t* const ring0 = rings + l;
-            const int32_t* const ring_last = rings + (size_t)nact * R * QT + l;
-            int32_t cin = 0, cout = 0, pub = 0;
-            uint32_t seen = 0;
-            if (!gin) {
-                // nothing above the first band: ring 0 holds zeros, all columns at once
-                for (int32_t k = lane; k < R * QT; k += 64) rings[k] = 0;
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                lds_put(wr, W);
-                cin = W;
-            }
             uint32_t idle = 0;
+            if (wave == NW) {
+                const bool gin = super > 0;            // a workgroup band above exists
+                const int32_t j0 = super * NW * RPW;   // first scanline of the band
+                const int32_t b_in = gin ? cell_off(((sy > 0 ? j0 : H - 1 - j0) - sy) * W + xs, QT * 4) + lofs : OOB;
+                int32_t* const ring0 = rings + l;
+                int32_t cin = 0;
+                uint32_t seen = 0;
+                if (!gin) {
+                    // nothing above the first band: ring 0 holds zeros, all columns at once
+                    for (int32_t k = lane; k < R * QT; k += 64) rings[k] = 0;
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    lds_put(wr, W);
+                    cin = W;
+                }
 #pragma nounroll
-            while (cin < W || cout < W) {
-                bool moved = false;
-                if (cin < W) {
+                while (cin < W) {
                     if (seen <= (uint32_t)cin) {
                         const uint32_t v = __builtin_amdgcn_readfirstlane(flag_get(progress + super - 1));
                         seen = v > epoch ? v - epoch : 0u;
@@ -219,10 +215,24 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
                         __atomic_signal_fence(__ATOMIC_SEQ_CST);
                         lds_put(wr, cin + n);
                         cin += n;
-                        moved = true;
+                        idle = 0;
+                    } else {
+                        // give up (and let every other waiter give up) instead of hanging
+                        if (++idle > SPIN_LIMIT_BAND || ((idle & 1023) == 0 && flag_get(a.error) != 0)) {
+                            raise_error(a.error);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
                     }
                 }
-                if (cout < W) {
+            } else {
+                const bool gout = super * NW + nact < d.nbands;   // a workgroup band below exists
+                const int32_t j1 = (super * NW + nact) * RPW - 1;   // last scanline (full band if gout)
+                const int32_t b_out = gout ? cell_off((sy > 0 ? j1 : H - 1 - j1) * W + xs, QT * 4) + lofs : OOB;
+                const int32_t* const ring_last = rings + (size_t)nact * R * QT + l;
+                int32_t cout = 0, pub = 0;
+#pragma nounroll
+                while (cout < W) {
                     const int32_t n = min(lds_get(wr + nact) - cout, NI * CPI);
                     if (n > 0) {
 #pragma unroll
@@ -248,18 +258,14 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
                             if (lane == 0) flag_put(progress + super, epoch + (uint32_t)cout);
                             pub = cout;
                         }
-                        moved = true;
+                        idle = 0;
+                    } else {
+                        if (++idle > SPIN_LIMIT_BAND || ((idle & 1023) == 0 && flag_get(a.error) != 0)) {
+                            raise_error(a.error);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
                     }
-                }
-                if (moved) {
-                    idle = 0;
-                } else {
-                    // give up (and let every other waiter give up) instead of hanging
-                    if (++idle > SPIN_LIMIT_BAND || ((idle & 1023) == 0 && flag_get(a.error) != 0)) {
-                        raise_error(a.error);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
                 }
             }
         } else if (wave < nact) {
@@ -270,9 +276,12 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
             int32_t* const t_a = ka ? d.t[1] : d.t[0];
             int32_t* const t_ma = ka ? d.t[0] : d.t[1];
             int32_t* const t_mb = kb == 3 ? d.t[2] : d.t[3];
+            // an operand that is zero (no earlier scan) or a sum that nobody reads later gets an
+            // empty buffer: its loads return 0 and its stores are dropped, with no per-step test
             const __amdgpu_buffer_rsrc_t rs_a = make_rsrc(t_a, tbytes);
-            const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(t_ma, tbytes);
-            const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(t_mb, tbytes);
+            const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(t_ma, old_a_zero ? 0 : tbytes);
+            const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(t_mb, old_b_zero ? 0 : tbytes);
+            const __amdgpu_buffer_rsrc_t rs_bo = make_rsrc(t_b, b_live ? tbytes : 0);
             int32_t crun[KY];                              // cost byte offset of the lane's run of KX labels
             bool valid[KY][KX];
 #pragma unroll
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
             const int32_t yn = y + sy;                     // next row in scan order
             const bool has_next = j + 1 < H;
             const bool store_a = SPLIT == 1 || !beta;
-            const bool store_b = (SPLIT == 1 || beta) && b_live;
+            const bool store_b = SPLIT == 1 || beta;
             // the lanes of the band's last scanline that carry T_b hand it on
             const bool hands = grp == RPW - 1 && (SPLIT == 1 || beta);
             const int32_t* ring_in = rings + (size_t)wave * R * QT + l;
@@ -328,8 +337,8 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
                 const bool act = rowok && i < (uint32_t)W;
                 const bool nxt = i + 1 < (uint32_t)W;     // the next column in scan order exists
                 const int32_t offc = act ? bc + t * dc : OOB;
-                const int32_t offa = (act && nxt && !old_a_zero) ? ba + t * dt : OOB;
-                const int32_t offb = (act && has_next && !old_b_zero) ? bb + t * dt : OOB;
+                const int32_t offa = (act && nxt) ? ba + t * dt : OOB;
+                const int32_t offb = (act && has_next) ? bb + t * dt : OOB;
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, offc + crun[ky], c[ky]);
                 load_vec<E>(rs_ma, offa, &ma[0][0]);
@@ -353,8 +362,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
                 for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx)
-                        in_lb[ky][kx] = __hip_atomic_load(slot + (ky * KX + kx) * G, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                        in_lb[ky][kx] = slot[(ky * KX + kx) * G];
             };
             read_input(0);
 
@@ -443,7 +451,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 1)) void edp_pass_kernel(const Pa
                             out[ky][kx] = tbv[ky][kx];
                         }
                     store_vec<E>(rs_a, oa, &h[0][0]);
-                    store_vec<E>(rs_b, ob, &tbv[0][0]);
+                    store_vec<E>(rs_bo, ob, &tbv[0][0]);
                     // hand the band's last scanline T_b to the next wavefront (or the helper)
                     const int32_t il = s - (RPW - 1);
                     if (il >= 0 && il < W) {                     // wave-uniform
@@ -563,11 +571,10 @@ inline size_t win_lds_bytes(int waves) { return (size_t)waves * 2 * 64 * 2 * 4; 
 template <class T, class CK, int SPLIT>
 static hipError_t run_pass(const PassArgs& a, int grid, int waves, hipStream_t s) {
     const size_t lds = pass_lds_bytes(T::QT, waves, a.ring);
-    hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>), dim3(grid), dim3(64 * (waves + 1)), lds, s, a);
+    hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>), dim3(grid), dim3(64 * (waves + 2)), lds, s, a);
     return hipGetLastError();
 }
 
-using WinTile = Tile<4, 2, 4, 2>;
 
 
 template <class T, class CT>
@@ -580,7 +587,7 @@ template <class T, class CK, int SPLIT>
 static int pass_occupancy(int waves, size_t lds) {
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>,
-                                                     64 * (waves + 1), lds) != hipSuccess)
+                                                     64 * (waves + 2), lds) != hipSuccess)
         blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
@@ -645,6 +652,9 @@ hipError_t aggregate_tile(int dtype, const AggArgs& a, int grid, hipStream_t s) 
     using T = typename TileOf<ID>::type;
     return dtype == 1 ? run_agg<T, int16_t>(a, grid, s) : run_agg<T, int32_t>(a, grid, s);
 }
+
+// the label-window solve's 8 x 8 frames
+using WinTile = TileOf<WIN_TILE>::type;
 
 #define EDP_INSTANTIATE_TILE(id)                                                                         \
     template hipError_t pass_tile<id>(int, int, const PassArgs&, int, int, hipStream_t);                  \

@@ -11,7 +11,7 @@ EDP_INSTANTIATE_TILE(15)
 // label-window solve: 8 x 8 frames on the window tile
 hipError_t pass_win(const PassArgs& a, int grid, int waves, hipStream_t s) {
     const size_t lds = pass_lds_bytes(WinTile::QT, waves, a.ring) + win_lds_bytes(waves);
-    hipLaunchKernelGGL((edp_pass_kernel<WinTile, int32_t, 1, pass_pf<WinTile>(), true>), dim3(grid), dim3(64 * (waves + 1)),
+    hipLaunchKernelGGL((edp_pass_kernel<WinTile, int32_t, 1, pass_pf<WinTile>(), true>), dim3(grid), dim3(64 * (waves + 2)),
                        lds, s, a);
     return hipGetLastError();
 }
@@ -20,7 +20,7 @@ hipError_t pass_win(const PassArgs& a, int grid, int waves, hipStream_t s) {
 int occupancy_win(int waves, size_t lds_bytes) {
     int per_cu = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, edp_pass_kernel<WinTile, int32_t, 1, pass_pf<WinTile>(), true>, 64 * (waves + 1),
+            &per_cu, edp_pass_kernel<WinTile, int32_t, 1, pass_pf<WinTile>(), true>, 64 * (waves + 2),
             lds_bytes + win_lds_bytes(waves)) != hipSuccess || per_cu < 1)
         per_cu = 1;
     return per_cu;

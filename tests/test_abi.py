@@ -85,7 +85,7 @@ def test_tiles_and_workspace_sizes():
     p = _prob()
     bad_split = B.Tuning(2, 0, 2, 0, 0, None, 0)          # tile 2 spans 64 lanes: no room for two halves
     assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_split), ctypes.byref(n)) == -1
-    bad_waves = B.Tuning(-1, 0, 0, 9, 0, None, 0)
+    bad_waves = B.Tuning(-1, 0, 0, 7, 0, None, 0)
     assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_waves), ctypes.byref(n)) == -1
     bad_fuse = B.Tuning(-1, 0, 0, 0, 3, None, 0)
     assert lib.edp_workspace_size(ctypes.byref(p), B.OP_EDP, ctypes.byref(bad_fuse), ctypes.byref(n)) == -1

@@ -46,7 +46,7 @@ def launch_variants(qx, qy):
     for t in tiles[:1] + tiles[-1:]:
         px, kx, py, ky = edp.tile_info(t)
         for split in (1, 2) if 2 * px * py <= 64 else (1,):
-            for waves in (1, 2, 3, 8):
+            for waves in (1, 2, 3, 6):
                 out.append((t, split, waves, 1, 2 if waves % 2 else 1))
         out.append((t, 0, 0, 16, 0))
         out.append((t, 0, 1, 0, 1))
@@ -152,7 +152,7 @@ def test_edp_worked_example():
 def test_edp_stereo_workload_full_size():
     p = synth.workload("stereo384x288")
     ref = cref.edp(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode, 1, "lrms")
-    for tile, split, waves, fuse in ((-1, 0, 0, 0), (-1, 0, 0, 1), (3, 2, 8, 2), (4, 2, 4, 1), (1, 1, 2, 2),
+    for tile, split, waves, fuse in ((-1, 0, 0, 0), (-1, 0, 0, 1), (3, 2, 6, 2), (4, 2, 4, 1), (1, 1, 2, 2),
                                      (5, 1, 1, 2)):
         note(f"edp stereo384x288 tile {tile} split {split} waves {waves} fuse {fuse}")
         lab, e = gpu_edp(p, 1, tile, cost_bound=50, split=split, waves=waves, fuse=fuse)
