@@ -617,7 +617,8 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     b.qx = prob->qx;
     b.qy = prob->qy;
     const int pbytes = qt_of(tile) <= 256 ? 1 : 2;
-    b.chunk = 32768 / (qt_of(tile) * pbytes);
+    // columns per LDS chunk of the backtracking (16 scanlines per workgroup, about 32 KB)
+    b.chunk = 32768 / (16 * qt_of(tile) * pbytes);
     if (b.chunk < 1) b.chunk = 1;
     if (!mark(2)) return EDP_E_HIP;
     err = launch_dp_backtrack(tile, b, s);

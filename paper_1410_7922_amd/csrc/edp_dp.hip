@@ -161,40 +161,97 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     }
 }
 
+// Backtracking: BT_ROWS scanlines per workgroup, one lane walking each.  The choice
+// indexes of a chunk of columns of all the workgroup's scanlines are staged in LDS
+// with 16-byte loads by every lane (the block addresses do not depend on the labels);
+// then each walking lane follows its scanline through LDS, and the chunk's labels
+// leave through LDS in row-contiguous runs.
+constexpr int BT_ROWS = 16;
+
+template <class T>
+__device__ __forceinline__ int32_t tile_pos(int32_t lab, float inv_qx, int32_t qx) {
+    if constexpr (T::PY == 1 && T::KY == 1) {
+        return lab;                                  // one label dimension: lane-major order is label order
+    } else {
+        // lab < 4096 and qx <= 64: the float quotient is within 1e-3 of the true one while
+        // (lab + 0.5) / qx stays at least 1 / 128 away from an integer, so the floor is exact
+        const int32_t vy = (int32_t)((lab + 0.5f) * inv_qx);
+        const int32_t vx = lab - vy * qx;
+        const int32_t ppy = vy / T::KY, ky = vy % T::KY, ppx = vx / T::KX, kx = vx % T::KX;
+        return (ppy * T::PX + ppx) * T::E + ky * T::KX + kx;
+    }
+}
+
 template <class T, class PT>
 __global__ __launch_bounds__(64) void dp_backtrack_kernel(const BtArgs a) {
     constexpr int QT = T::QT;
+    constexpr int V16 = QT * (int)sizeof(PT) / 16;   // 16-byte pieces per column block
+    static_assert(QT * sizeof(PT) % 16 == 0, "column blocks of whole 16-byte pieces");
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint16_t tab[4096];
-    PT* buf = (PT*)smem;
-    const int32_t y = blockIdx.x;
+    const int32_t C = a.chunk;
+    PT* buf = (PT*)smem;                                         // [BT_ROWS][C][QT]
+    int32_t* lbuf = (int32_t*)(smem + (size_t)BT_ROWS * C * QT * sizeof(PT));   // [BT_ROWS][C]
     const int32_t t = threadIdx.x;
-    const int32_t W = a.W, Q = a.qx * a.qy;
-    for (int32_t q = t; q < Q; q += 64) {
-        const int32_t vy = q / a.qx, vx = q % a.qx;
-        const int32_t ppy = vy / T::KY, ky = vy % T::KY, ppx = vx / T::KX, kx = vx % T::KX;
-        tab[q] = (uint16_t)((ppy * T::PX + ppx) * T::E + ky * T::KX + kx);
-    }
-    int32_t lab = a.row_label[y];
-    int32_t* out = a.labels + (size_t)y * W;
-    if (t == 0) out[W - 1] = lab;
-    __syncthreads();
-    const size_t rowbase = (size_t)y * W * QT;
-    for (int32_t x1 = W - 1; x1 >= 1; x1 -= a.chunk) {
-        const int32_t x0 = x1 - a.chunk + 1 > 1 ? x1 - a.chunk + 1 : 1;
-        const size_t nbytes = (size_t)(x1 - x0 + 1) * QT * sizeof(PT);
-        const uint4* src = (const uint4*)((const PT*)a.ptr + rowbase + (size_t)x0 * QT);
-        uint4* dst = (uint4*)buf;
-        for (size_t k = t; k < nbytes / 16; k += 64) dst[k] = src[k];
-        __syncthreads();
-        if (t == 0) {
-            for (int32_t x = x1; x >= x0; --x) {
-                const int32_t pos = (uint32_t)lab < (uint32_t)Q ? tab[lab] : 0;
-                lab = buf[(size_t)(x - x0) * QT + pos];
-                out[x - 1] = lab;
+    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy;
+    const int32_t y0 = blockIdx.x * BT_ROWS;
+    const int32_t nrows = min(BT_ROWS, H - y0);
+    const bool walker = t < nrows;
+    const float inv_qx = 1.0f / (float)a.qx;
+    int32_t lab = walker ? a.row_label[y0 + t] : 0;
+    if (walker) a.labels[(size_t)(y0 + t) * W + W - 1] = lab;
+    // the choice indexes as one buffer (below 2^31 bytes, checked by the host): pieces
+    // outside a scanline's chunk read as zero through an out-of-range offset
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.ptr, (int32_t)((size_t)H * W * QT * sizeof(PT)));
+    uint4* dst = (uint4*)buf;
+    for (int32_t x1 = W - 1; x1 >= 1; x1 -= C) {
+        const int32_t x0 = x1 - C + 1 > 1 ? x1 - C + 1 : 1;
+        const int32_t n = x1 - x0 + 1;
+        // stage columns x0..x1 of every scanline (row r: n * V16 contiguous pieces), 8 rows x 2
+        // pieces per lane in flight at a time
+        const int32_t per_row = n * V16;
+        for (int32_t ob = 0; ob < per_row; ob += 128) {
+            for (int32_t rb = 0; rb < nrows; rb += 8) {
+                uint32_t __attribute__((ext_vector_type(4))) v[8][2];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int32_t r = rb + i, o = ob + t + 64 * j;
+                        const int32_t off = (r < nrows && o < per_row)
+                                                ? (int32_t)((((size_t)(y0 + r) * W + x0) * V16 + o) * 16)
+                                                : OOB;
+                        v[i][j] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+                    }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int32_t r = rb + i, o = ob + t + 64 * j;
+                        if (r < nrows && o < per_row) {
+                            uint4 w;
+                            w.x = v[i][j][0]; w.y = v[i][j][1]; w.z = v[i][j][2]; w.w = v[i][j][3];
+                            dst[(size_t)r * C * V16 + o] = w;
+                        }
+                    }
             }
         }
         __syncthreads();
+        if (walker) {
+            const PT* rb = buf + (size_t)t * C * QT;
+            int32_t* lb = lbuf + t * C;
+            for (int32_t x = x1; x >= x0; --x) {
+                const int32_t pos = (uint32_t)lab < (uint32_t)Q ? tile_pos<T>(lab, inv_qx, a.qx) : 0;
+                lab = rb[(size_t)(x - x0) * QT + pos];
+                lb[x - x0] = lab;                    // the label of column x - 1
+            }
+        }
+        __syncthreads();
+        for (int32_t k = t; k < nrows * n; k += 64) {
+            const int32_t r = k / n, c = k - r * n;
+            a.labels[(size_t)(y0 + r) * W + x0 - 1 + c] = lbuf[r * C + c];
+        }
+        // the next chunk's staging overwrites buf only: lbuf is read above and written after
+        // the next barrier
     }
 }
 
@@ -223,11 +280,13 @@ static hipError_t fwd_kind(int kind, const DpArgs& a, int grid, hipStream_t s) {
 
 template <class T>
 static hipError_t run_bt(const BtArgs& a, hipStream_t s) {
-    const size_t lds = (size_t)a.chunk * T::QT * (T::QT <= 256 ? 1 : 2);
-    if (T::QT <= 256)
-        hipLaunchKernelGGL((dp_backtrack_kernel<T, uint8_t>), dim3(a.H), dim3(64), lds, s, a);
+    constexpr int pbytes = T::QT <= 256 ? 1 : 2;
+    const size_t lds = (size_t)BT_ROWS * a.chunk * (T::QT * pbytes + 4);
+    const int grid = (a.H + BT_ROWS - 1) / BT_ROWS;
+    if constexpr (T::QT <= 256)
+        hipLaunchKernelGGL((dp_backtrack_kernel<T, uint8_t>), dim3(grid), dim3(64), lds, s, a);
     else
-        hipLaunchKernelGGL((dp_backtrack_kernel<T, uint16_t>), dim3(a.H), dim3(64), lds, s, a);
+        hipLaunchKernelGGL((dp_backtrack_kernel<T, uint16_t>), dim3(grid), dim3(64), lds, s, a);
     return hipGetLastError();
 }
 
