@@ -256,7 +256,7 @@ __global__ __launch_bounds__(64) void dp_backtrack_kernel(const BtArgs a) {
 }
 
 template <class T>
-constexpr int dp_pf() { return T::E <= 4 ? 4 : 2; }
+constexpr int dp_pf() { return T::E <= 4 ? 8 : 2; }
 
 template <class T, class CK>
 static hipError_t run_fwd(const DpArgs& a, int grid, hipStream_t s) {
