@@ -330,12 +330,15 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                 for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = out[ky][kx] = 0;
 
             // Issue the loads of step t into one ring slot (no branch around a load).
-            auto fetch = [&](const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX], int32_t (&mb)[KY][KX],
-                             int32_t (&sh)[WIN ? 2 : 1]) {
+            // STEADY: every scanline of the wavefront is strictly inside its row at column t
+            // (0 < t - grp < W - 1), which the caller knows for a whole round of steps
+            auto fetch = [&](auto steady, const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX],
+                             int32_t (&mb)[KY][KX], int32_t (&sh)[WIN ? 2 : 1]) {
+                constexpr bool STEADY = decltype(steady)::value;
                 // column i = t - grp of this lane's scanline; offsets move by a fixed stride per step
                 const uint32_t i = (uint32_t)(t - grp);
-                const bool act = rowok && i < (uint32_t)W;
-                const bool nxt = i + 1 < (uint32_t)W;     // the next column in scan order exists
+                const bool act = STEADY ? rowok : rowok && i < (uint32_t)W;
+                const bool nxt = STEADY || i + 1 < (uint32_t)W;     // the next column in scan order exists
                 const int32_t offc = act ? bc + t * dc : OOB;
                 const int32_t offa = (act && nxt) ? ba + t * dt : OOB;
                 const int32_t offb = (act && has_next) ? bb + t * dt : OOB;
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                 if constexpr (WIN) load_vec<2>(rs_sh, act ? bsh + t * dsh : OOB, sh);
             };
 #pragma unroll
-            for (int u = 0; u < PF; ++u) fetch(u, rc[u], rma[u], rmb[u], rsh[u]);
+            for (int u = 0; u < PF; ++u) fetch(std::false_type{}, u, rc[u], rma[u], rmb[u], rsh[u]);
 
             // Input: the producer's count and the ring slot of column t, read back to back.  LDS
             // performs the operations of the CU in arrival order and the producer writes a slot
@@ -366,117 +369,131 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             };
             read_input(0);
 
-            for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
+            auto step = [&](auto steady, const int u, const int32_t s) {
+                constexpr bool STEADY = decltype(steady)::value;
+                const int32_t i = s - grp;
+                const bool act = STEADY ? rowok : rowok && (uint32_t)i < (uint32_t)W;
+                // T_b of the row above at this column, for group 0
+                int32_t lb[KY][KX];
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
-                    const int32_t s = s0 + u;
-                    const int32_t i = s - grp;
-                    const bool act = rowok && (uint32_t)i < (uint32_t)W;
-                    // T_b of the row above at this column, for group 0
-                    int32_t lb[KY][KX];
+                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = 0;
+                if (STEADY || s < W) {                       // wave-uniform
+                    uint32_t spins = 0;
+#pragma nounroll
+                    while (in_ready < s + 1) {
+                        if (++spins > SPIN_LIMIT) {
+                            raise_error(a.error);
+                            break;
+                        }
+                        read_input(s);
+                    }
 #pragma unroll
                     for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                        for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = 0;
-                    if (s < W) {                                 // wave-uniform
+                        for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = in_lb[ky][kx];
+                    // LDS operations of a wavefront complete in order: the slot is read
+                    // before the count that frees it is written
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    lds_put(rd + wave, s + 1);
+                }
+                int32_t h[KY][KX], h2[KY][KX];
+#pragma unroll
+                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) {
+                        const int32_t v = out[ky][kx];
+                        int32_t cr, mb;
+                        if constexpr (SPLIT == 1) {
+                            cr = carry[ky][kx];
+                            mb = 0;
+                            if constexpr (RPW > 1) mb = lanes_up<(RPW > 1 ? CL : 1)>(v, lane);
+                        } else {
+                            const int32_t x1 = lanes_up<G>(v, lane);
+                            int32_t x2 = 0;
+                            if constexpr (RPW > 1) x2 = lanes_up<(RPW > 1 ? 2 * G : 1)>(v, lane);
+                            cr = beta ? x1 : v;
+                            mb = beta ? x2 : x1;
+                            if (!STEADY && i == 0) cr = 0;
+                        }
+                        if (grp == 0) mb = lb[ky][kx];
+                        const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + cr + mb;
+                        const int32_t d = rmb[u][ky][kx] - rma[u][ky][kx];
+                        if constexpr (SPLIT == 1) {
+                            h[ky][kx] = valid[ky][kx] ? ((A + d) >> 1) : PADV;
+                            h2[ky][kx] = valid[ky][kx] ? ((A - d) >> 1) : PADV;
+                        } else {
+                            h[ky][kx] = valid[ky][kx] ? ((A + (beta ? -d : d)) >> 1) : PADV;
+                        }
+                    }
+                if constexpr (WIN) {
+                    // shift codes: bytes (dx, dy) towards +x, -x (dword 0) and +y, -y (dword 1)
+                    const int32_t ca = rsh[u][0] >> (sx > 0 ? 0 : 16);
+                    const int32_t cb = rsh[u][1] >> (sy > 0 ? 0 : 16);
+                    const int32_t dxa = (int32_t)(int8_t)(ca & 0xFF), dya = (int32_t)(int8_t)((ca >> 8) & 0xFF);
+                    const int32_t dxb = (int32_t)(int8_t)(cb & 0xFF), dyb = (int32_t)(int8_t)((cb >> 8) & 0xFF);
+                    min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
+                    min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
+                } else {
+                    min_search<T>(h, li, d.clipd, joint, lane);
+                    if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
+                }
+                const int32_t o = bt + s * dt;
+                const int32_t oa = (act && store_a) ? o : OOB;
+                const int32_t ob = (act && store_b) ? o : OOB;
+                int32_t tbv[KY][KX];
+#pragma unroll
+                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) {
+                        tbv[ky][kx] = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
+                        if constexpr (SPLIT == 1) carry[ky][kx] = act ? h[ky][kx] : carry[ky][kx];
+                        out[ky][kx] = tbv[ky][kx];
+                    }
+                store_vec<E>(rs_a, oa, &h[0][0]);
+                store_vec<E>(rs_bo, ob, &tbv[0][0]);
+                // hand the band's last scanline T_b to the next wavefront (or the helper)
+                const int32_t il = s - (RPW - 1);
+                if (STEADY || (il >= 0 && il < W)) {         // wave-uniform
+                    // ring space: the consumer's count only grows, so the last value read
+                    // stays a valid lower bound; read LDS only when it is short
+                    if (taken < il + 1 - R) {
                         uint32_t spins = 0;
 #pragma nounroll
-                        while (in_ready < s + 1) {
+                        while ((taken = lds_get(rd + wave + 1)) < il + 1 - R) {
                             if (++spins > SPIN_LIMIT) {
                                 raise_error(a.error);
                                 break;
                             }
-                            read_input(s);
                         }
-#pragma unroll
-                        for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                            for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = in_lb[ky][kx];
-                        // LDS operations of a wavefront complete in order: the slot is read
-                        // before the count that frees it is written
-                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                        lds_put(rd + wave, s + 1);
                     }
-                    int32_t h[KY][KX], h2[KY][KX];
+                    int32_t* dst = hands ? ring_out + (size_t)(il & (R - 1)) * QT : trash + l;
 #pragma unroll
                     for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                        for (int kx = 0; kx < KX; ++kx) {
-                            const int32_t v = out[ky][kx];
-                            int32_t cr, mb;
-                            if constexpr (SPLIT == 1) {
-                                cr = carry[ky][kx];
-                                mb = 0;
-                                if constexpr (RPW > 1) mb = lanes_up<(RPW > 1 ? CL : 1)>(v, lane);
-                            } else {
-                                const int32_t x1 = lanes_up<G>(v, lane);
-                                int32_t x2 = 0;
-                                if constexpr (RPW > 1) x2 = lanes_up<(RPW > 1 ? 2 * G : 1)>(v, lane);
-                                cr = beta ? x1 : v;
-                                mb = beta ? x2 : x1;
-                                if (i == 0) cr = 0;
-                            }
-                            if (grp == 0) mb = lb[ky][kx];
-                            const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + cr + mb;
-                            const int32_t d = rmb[u][ky][kx] - rma[u][ky][kx];
-                            if constexpr (SPLIT == 1) {
-                                h[ky][kx] = valid[ky][kx] ? ((A + d) >> 1) : PADV;
-                                h2[ky][kx] = valid[ky][kx] ? ((A - d) >> 1) : PADV;
-                            } else {
-                                h[ky][kx] = valid[ky][kx] ? ((A + (beta ? -d : d)) >> 1) : PADV;
-                            }
-                        }
-                    if constexpr (WIN) {
-                        // shift codes: bytes (dx, dy) towards +x, -x (dword 0) and +y, -y (dword 1)
-                        const int32_t ca = rsh[u][0] >> (sx > 0 ? 0 : 16);
-                        const int32_t cb = rsh[u][1] >> (sy > 0 ? 0 : 16);
-                        const int32_t dxa = (int32_t)(int8_t)(ca & 0xFF), dya = (int32_t)(int8_t)((ca >> 8) & 0xFF);
-                        const int32_t dxb = (int32_t)(int8_t)(cb & 0xFF), dyb = (int32_t)(int8_t)((cb >> 8) & 0xFF);
-                        min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
-                        min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
-                    } else {
-                        min_search<T>(h, li, d.clipd, joint, lane);
-                        if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
+                        for (int kx = 0; kx < KX; ++kx) dst[(ky * KX + kx) * G] = out[ky][kx];
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    lds_put(wr + wave + 1, il + 1);
+                }
+                if (STEADY || s + 1 < W) read_input(s + 1);
+                fetch(steady, s + PF, rc[u], rma[u], rmb[u], rsh[u]);
+            };
+            // a steady round: its steps and the steps it prefetches for have every scanline of the
+            // wavefront strictly inside its row (s0 >= RPW, s0 + 2 PF + 1 <= W).  Only tiles with
+            // few labels per lane get the second copy of the round (the others would spill).
+            constexpr bool TWO_COPIES = E <= 2 || (E <= 4 && G <= 16);
+            for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
+                bool steady_round = false;
+                if constexpr (TWO_COPIES) steady_round = s0 >= RPW && s0 + 2 * PF + 1 <= W;
+                if (steady_round) {
+                    if constexpr (TWO_COPIES) {
+#pragma unroll
+                        for (int u = 0; u < PF; ++u) step(std::true_type{}, u, s0 + u);
                     }
-                    const int32_t o = bt + s * dt;
-                    const int32_t oa = (act && store_a) ? o : OOB;
-                    const int32_t ob = (act && store_b) ? o : OOB;
-                    int32_t tbv[KY][KX];
+                } else {
 #pragma unroll
-                    for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                        for (int kx = 0; kx < KX; ++kx) {
-                            tbv[ky][kx] = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
-                            if constexpr (SPLIT == 1) carry[ky][kx] = act ? h[ky][kx] : carry[ky][kx];
-                            out[ky][kx] = tbv[ky][kx];
-                        }
-                    store_vec<E>(rs_a, oa, &h[0][0]);
-                    store_vec<E>(rs_bo, ob, &tbv[0][0]);
-                    // hand the band's last scanline T_b to the next wavefront (or the helper)
-                    const int32_t il = s - (RPW - 1);
-                    if (il >= 0 && il < W) {                     // wave-uniform
-                        // ring space: the consumer's count only grows, so the last value read
-                        // stays a valid lower bound; read LDS only when it is short
-                        if (taken < il + 1 - R) {
-                            uint32_t spins = 0;
-#pragma nounroll
-                            while ((taken = lds_get(rd + wave + 1)) < il + 1 - R) {
-                                if (++spins > SPIN_LIMIT) {
-                                    raise_error(a.error);
-                                    break;
-                                }
-                            }
-                        }
-                        int32_t* dst = hands ? ring_out + (size_t)(il & (R - 1)) * QT : trash + l;
-#pragma unroll
-                        for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                            for (int kx = 0; kx < KX; ++kx) dst[(ky * KX + kx) * G] = out[ky][kx];
-                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                        lds_put(wr + wave + 1, il + 1);
-                    }
-                    if (s + 1 < W) read_input(s + 1);
-                    fetch(s + PF, rc[u], rma[u], rmb[u], rsh[u]);
+                    for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
                 }
             }
         }
