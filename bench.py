@@ -239,6 +239,61 @@ def bench_learned(torch, n, refine):
     return out
 
 
+def window_study(torch, n, wins=(7, 11, 15, 21), rounds=3, big=40000):
+    """Energy gap of the label-window EDP over the plain EDP for several window sizes on n
+    held-out 640 x 480 motion instances (31 x 31 labels), with the trained network's centres and
+    0 .. rounds-1 re-centring rounds.  The windowed problem is solved, for any window size, as
+    the plain EDP on the cost volume with every label outside the pixel's window given cost
+    `big` (the definition the windowed solve implements; big exceeds every in-window cost plus
+    four sums' spreads of lambda * 2T), so no window-size-specific kernel is needed."""
+    import numpy as np
+    import synth
+    import paper_1410_7922_amd as edp
+    from paper_1410_7922_amd import binding as B
+    from paper_1410_7922_amd.learned import LearnedWindowEDP
+    dev = torch.device("cuda:0")
+    solver = LearnedWindowEDP.pretrained(dev)
+    Q = 31
+    lx = (torch.arange(Q * Q, device=dev) % Q).view(1, 1, -1)
+    ly = (torch.arange(Q * Q, device=dev) // Q).view(1, 1, -1)
+    ws = edp.Workspace()
+    gaps = {w: [] for w in wins}
+    hits = {w: [] for w in wins}
+    for k in range(n):
+        i0, i1 = synth.motion_frames(seed=k, W=640, H=480, r=15)[:2]
+        cost = B.dsi_motion(torch.from_numpy(i0).to(dev), torch.from_numpy(i1).to(dev), 15, 2500)
+        lp, ep = edp.solve(cost, Q, Q, 15, 3, 0, 1, cost_bound=2500, ws=ws)
+        ep = int(ep.item())
+        net_centres = solver.windows(cost)
+        for win in wins:
+            r = win // 2
+            cen = net_centres.clone()
+            cen[..., 0].clamp_(r, Q - 1 - r)
+            cen[..., 1].clamp_(r, Q - 1 - r)
+            hit = (((lp % Q) - cen[..., 0]).abs() <= r) & (((lp // Q) - cen[..., 1]).abs() <= r)
+            hits[win].append(float(hit.float().mean()))
+            row = []
+            for _ in range(rounds):
+                inside = ((lx - cen[..., 0:1]).abs() <= r) & ((ly - cen[..., 1:2]).abs() <= r)
+                masked = torch.where(inside, cost, torch.full_like(cost, big))
+                lw, ew = edp.solve(masked, Q, Q, 15, 3, 0, 1, cost_bound=big, ws=ws)
+                row.append((int(ew.item()) - ep) / ep)
+                cen = torch.stack([(lw % Q).clamp(r, Q - 1 - r), (lw // Q).clamp(r, Q - 1 - r)], -1).to(torch.int32)
+                del inside, masked
+            gaps[win].append(row)
+            log(f"window study instance {k} window {win}: gaps {[round(100 * g, 3) for g in row]} %")
+        del cost
+        torch.cuda.empty_cache()
+    out = {}
+    for win in wins:
+        g = np.array(gaps[win])
+        out[f"{win}x{win}"] = {"mean_gap_by_round": g.mean(axis=0).tolist(), "max_gap_by_round": g.max(axis=0).tolist(),
+                               "fraction_within_0.5pct_by_round": (g <= 0.005).mean(axis=0).tolist(),
+                               "window_hit_rate": float(np.mean(hits[win]))}
+    return {"workload": "label-window study, motion 640x480, 31x31 labels, network centres",
+            "instances": n, "rounds": rounds, "outside_cost": big, "windows": out}
+
+
 def cpu_baseline(prob, budget_s=10.0):
     from oracle import cref
     H, W, Q = prob.cost.shape
@@ -267,6 +322,8 @@ def main():
     ap.add_argument("--learned", type=int, default=20, metavar="N",
                     help="held-out instances of the learned-window comparison (0 skips it)")
     ap.add_argument("--refine", type=int, default=2, help="window refinement rounds of the learned path")
+    ap.add_argument("--window-study", type=int, default=0, metavar="N",
+                    help="only the window-size study of the learned path on N instances")
     ap.add_argument("--dp-only", action="store_true",
                     help="run only the scanline DP sweep (for hardware-counter profiles of its kernels)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -301,6 +358,12 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {args.calibrate_copy} MiB done")
         del src, dst
+    if args.window_study:
+        r = window_study(torch, args.window_study)
+        print(json.dumps({"metric": "energy gap of the label-window EDP over plain EDP", "value": None,
+                          "unit": "fraction", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+                          "config": {"workload": r["workload"]}, "window_study": r}), flush=True)
+        return
     if args.dp_only:
         r = bench_dp(edp, torch, args.steps, args.warmup)
         print(json.dumps({"metric": "pixel-labels/sec (scanline DP sweep)", "value": r["pixel_labels_per_s"],

@@ -141,6 +141,34 @@ def test_edp_random_all_tiles(case):
         assert e == ref["energy"], (tile, split, waves, chunk, fuse)
 
 
+# Widths around the first steady prefetch round (a round of 8 steps runs without range tests
+# once every scanline of the wavefront is inside its row for the round and the round it
+# prefetches for: s0 >= rows per wavefront and s0 + 17 <= W), on the tiles that have the steady
+# copy, with several workgroups per scan (hand-offs through the helper wavefronts) and a last
+# workgroup whose band is partial.
+STEADY_CASES = [
+    # W, H, qx, lo, hi, dtype
+    (24, 37, 32, 0, 50, np.int16),
+    (25, 37, 32, 0, 50, np.int16),
+    (26, 45, 32, 0, 50, np.int16),
+    (33, 21, 16, 0, 30, np.int32),
+    (41, 53, 48, 0, 50, np.int16),
+    (57, 19, 20, -15, 40, np.int32),
+]
+
+
+@pytest.mark.parametrize("case", STEADY_CASES, ids=lambda c: f"{c[0]}x{c[1]}q{c[2]}")
+def test_edp_steady_rounds_and_workgroup_handoffs(case):
+    W, H, qx, lo, hi, dt = case
+    p = synth.random_problem(W * 31 + H, W, H, qx, 1, 11, 3, 0, lo, hi, dt)
+    ref = cref.edp(p.cost, qx, 1, 11, 3, 0, 2, "lrms")
+    for split, waves, chunk, fuse in ((1, 4, 0, 0), (1, 1, 1, 2), (2, 2, 3, 1), (1, 3, 16, 2)):
+        note(f"edp steady {p.name} split {split} waves {waves} chunk {chunk} fuse {fuse}")
+        lab, e = gpu_edp(p, 2, -1, chunk, split=split, waves=waves, fuse=fuse)
+        assert np.array_equal(lab, ref["labels"]), (split, waves, chunk, fuse)
+        assert e == ref["energy"], (split, waves, chunk, fuse)
+
+
 def test_edp_worked_example():
     cost = np.array([[[0, 5], [7, 0]], [[3, 1], [6, 2]]], np.int32)
     p = synth.Problem(cost, 2, 1, 1, 1, 0)
