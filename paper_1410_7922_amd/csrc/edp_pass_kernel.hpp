@@ -22,13 +22,13 @@
 //    the last scanline of a band hands T_b to the next wavefront through an
 //    LDS ring (counters in LDS).  Workgroups take whole groups of bands in
 //    scan order from a ticket counter, so the group a workgroup waits on is
-//    always held by a running workgroup.  One more wavefront per workgroup
-//    moves rows between workgroups: it stores the last band's T_b with
+//    always held by a running workgroup.  Two more wavefronts per workgroup
+//    move rows between workgroups: one stores the last band's T_b with
 //    device-scope stores and publishes the column count once they have
-//    completed, and it reads the row above the first band with device-scope
-//    loads into the first ring as the workgroup above publishes it.  The
-//    compute wavefronts thus only wait on LDS counters and on their own
-//    prefetched loads.
+//    completed, the other reads the row above the first band with
+//    device-scope loads into the first ring as the workgroup above publishes
+//    it.  The compute wavefronts thus only wait on LDS counters and on their
+//    own prefetched loads.
 // T_b written by P1 and P3 is only read inside the scan, so it reaches memory
 // only at workgroup boundaries.  Operands that do not depend on the scan (C
 // and the two "old" arrays) are prefetched PF steps ahead in a register ring.
@@ -73,13 +73,13 @@ __device__ __forceinline__ void raise_error(uint32_t* error) { flag_put(error, 1
 // window (costs outside the window are large), d.aux holds the frame shifts towards the four
 // neighbours, and each sum handed on is evaluated in the receiving vertex's frame.
 //
-// A workgroup has NW compute wavefronts and one helper wavefront (the last).  Compute
+// A workgroup has NW compute wavefronts and two helper wavefronts (the last two).  Compute
 // wavefront k reads the T_b row above its band from LDS ring k and writes its band's last
-// scanline into ring k + 1; the helper fills ring 0 from memory as the workgroup band above
-// publishes its progress (zeros above the first band) and empties the ring of the last
-// active wavefront into memory, publishing progress once its stores have completed.  The
-// compute wavefronts never touch another workgroup's data, so they never wait for memory
-// operations other than their own prefetched loads.
+// scanline into ring k + 1.  The row-in helper fills ring 0 from memory as the workgroup
+// band above publishes its progress (zeros above the first band); the row-out helper
+// empties the ring of the last active wavefront into memory and publishes progress once its
+// stores have completed.  The compute wavefronts never touch another workgroup's data, so
+// they never wait for memory operations other than their own prefetched loads.
 template <class T, class CK, int SPLIT, int PF, bool WIN = false>
 __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const PassArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
