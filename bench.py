@@ -77,10 +77,16 @@ def scan_bytes_per_pl(csize, iteration_first=True):
 
 
 def kernel_source_hash(names):
+    """Hash of the kernel sources' code: comments and whitespace do not count, so a comment
+    edit keeps the recorded counters valid while any change to the code does not."""
+    import re
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(ROOT, "paper_1410_7922_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1410_7922_amd", "csrc", n)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
