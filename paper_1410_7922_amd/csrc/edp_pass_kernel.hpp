@@ -292,7 +292,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                 for (int kx = 0; kx < KX; ++kx) valid[ky][kx] = px * KX + kx < d.qx && vy < d.qy;
             }
             const int32_t j = band * RPW + grp;            // scan-order row index
-            const bool rowok = j < H;
+            // a lane whose labels are all padding neither loads nor stores sums: its values are
+            // replaced by PADV before every use
+            const bool rowok = j < H && px * KX < d.qx && py * KY < d.qy;
             const int32_t y = sy > 0 ? j : H - 1 - j;
             const int32_t yn = y + sy;                     // next row in scan order
             const bool has_next = j + 1 < H;
@@ -547,8 +549,12 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
 #pragma unroll
         for (int kx = 0; kx < KX; ++kx) acc[ky][kx] = cw[kx];
     }
-    const int32_t nb[4] = {ok && x > 0 ? cell - 1 : -1, ok && x + 1 < W ? cell + 1 : -1,
-                           ok && y > 0 ? cell - W : -1, ok && y + 1 < H ? cell + W : -1};
+    // lanes whose labels are all padding (or, in a window solve, all outside the window) read
+    // no sums: their values never reach the argmin
+    const bool live = WIN ? (px * KX < d.win && py * KY < d.win) : (px * KX < d.qx && py * KY < d.qy);
+    const bool rd = ok && live;
+    const int32_t nb[4] = {rd && x > 0 ? cell - 1 : -1, rd && x + 1 < W ? cell + 1 : -1,
+                           rd && y > 0 ? cell - W : -1, rd && y + 1 < H ? cell + W : -1};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         load_vec<T::E>(make_rsrc(d.t[k], tbytes), nb[k] >= 0 ? nb[k] * QT * 4 + lofs : OOB, &tv[0][0]);
