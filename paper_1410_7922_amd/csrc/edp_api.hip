@@ -150,7 +150,12 @@ struct InstLayout {
     size_t tbytes;
     size_t total;
     size_t nflags;      // uint32 words, cleared before every solve
+    size_t hand_bytes;  // tagged rows between workgroup bands (cleared before every solve), or 0
 };
+
+// Tagged hand-off rows (64-bit value + tag per sum, per workgroup boundary and scan of a
+// launch) are used up to this size per instance; larger instances publish column counts.
+constexpr size_t kHandMax = (size_t)32 << 20;
 
 InstLayout inst_layout(const edp_problem* p, const Launch& la) {
     InstLayout L{};
@@ -159,17 +164,20 @@ InstLayout inst_layout(const edp_problem* p, const Launch& la) {
     for (int k = 0; k < 4; ++k) L.t[k] = k * L.tbytes;
     L.total = 4 * L.tbytes;
     L.nflags = (size_t)3 * la.nsuper;
+    const size_t hand = (size_t)2 * (la.nsuper > 1 ? la.nsuper - 1 : 0) * p->width * qt_of(la.tile) * 8;
+    L.hand_bytes = la.rpw >= 2 && hand <= kHandMax ? up(hand) : 0;
     return L;
 }
 
 int scan_launches(const edp_problem* p, const Launch& la) { return 4 / la.fuse * p->iterations; }
 
 // Single-instance workspace: T arrays, then the control words (flags, one
-// ticket counter per scan launch, the error word) that every solve clears.
+// ticket counter per scan launch, the error word) and the tagged hand-off rows,
+// which every solve clears (nclear words from ctrl).
 struct EdpLayout {
     InstLayout inst;
-    size_t ctrl;
-    size_t nflags, ntickets, nctrl;
+    size_t ctrl, hand;
+    size_t nflags, ntickets, nctrl, nclear;
     size_t total;
 };
 
@@ -180,7 +188,9 @@ EdpLayout edp_layout(const edp_problem* p, const Launch& la) {
     L.ntickets = (size_t)scan_launches(p, la);
     L.nctrl = L.nflags + L.ntickets + 1;
     L.ctrl = L.inst.total;
-    L.total = L.ctrl + up(L.nctrl * 4);
+    L.hand = L.ctrl + up(L.nctrl * 4);
+    L.total = L.hand + L.inst.hand_bytes;
+    L.nclear = (L.total - L.ctrl) / 4;
     return L;
 }
 
@@ -239,9 +249,10 @@ bool edp_offsets_fit(const edp_problem* p, int tile) {
 }
 
 InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, char* base,
-                   uint32_t* flags, const void* cost, int32_t* labels, int64_t* energy) {
+                   uint32_t* flags, char* hand, const void* cost, int32_t* labels, int64_t* energy) {
     InstDesc d{};
     d.cost = cost;
+    d.hand = L.hand_bytes ? (unsigned long long*)hand : nullptr;
     for (int k = 0; k < 4; ++k) d.t[k] = (int32_t*)(base + L.t[k]);
     d.labels = labels;
     d.energy = (unsigned long long*)energy;
@@ -414,6 +425,7 @@ struct BatchEntry {
     InstLayout L;
     size_t base;         // byte offset of the instance's T arrays in the workspace
     size_t flags_word;   // first control word of the instance's flags
+    size_t hand;         // byte offset of the instance's tagged hand-off rows
     int64_t est;         // critical-path estimate in scan steps (sort key)
 };
 
@@ -508,8 +520,12 @@ edp_status plan_batch(int32_t n, const edp_batch_item* items, BatchLayout* B) {
         word += 1;
     }
     B->ctrl_off = off;
-    B->nctrl = word;
     off += up(word * 4);
+    for (int i = 0; i < n; ++i) {
+        B->e[i].hand = off;
+        off += B->e[i].L.hand_bytes;
+    }
+    B->nctrl = (off - B->ctrl_off) / 4;        // control words and tagged rows, cleared each solve
     B->total = off;
     return EDP_OK;
 }
@@ -653,7 +669,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     uint32_t* tickets = ctrl + L.nflags;
     uint32_t* error = tickets + L.ntickets;
 
-    if (launch_fill_u32(ctrl, L.nctrl, 0, s) != hipSuccess) return EDP_E_HIP;
+    if (launch_fill_u32(ctrl, L.nclear, 0, s) != hipSuccess) return EDP_E_HIP;
     ClassRun c{};
     c.tile = la.tile;
     c.kind = cost_kind(prob, la.tile, d_cost);
@@ -664,7 +680,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
-    c.one = make_desc(prob, la, L.inst, ws, flags, d_cost, d_labels, nullptr);
+    c.one = make_desc(prob, la, L.inst, ws, flags, ws + L.hand, d_cost, d_labels, nullptr);
     c.descs = nullptr;
     c.ndesc = 1;
     c.tickets_per_pass = la.nsuper;
@@ -709,8 +725,8 @@ edp_status edp_batch_plan_create(int32_t n, const edp_batch_item* items, void* d
             const int i = k.members[m];
             const edp_batch_item& it = items[i];
             const BatchEntry& e = B.e[i];
-            InstDesc d = make_desc(&it.problem, e.la, e.L, ws + e.base, ctrl + e.flags_word, it.d_cost,
-                                   it.d_labels, it.d_energy);
+            InstDesc d = make_desc(&it.problem, e.la, e.L, ws + e.base, ctrl + e.flags_word, ws + e.hand,
+                                   it.d_cost, it.d_labels, it.d_energy);
             d.first_ticket = ticket;
             d.first_block = block;
             d.first_eblock = eblock;
@@ -842,7 +858,7 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     int32_t* cw = (int32_t*)(ws + L.cw);
     uint32_t* shifts = (uint32_t*)(ws + L.shifts);
 
-    if (launch_fill_u32(ctrl, E.nctrl, 0, s) != hipSuccess) return EDP_E_HIP;
+    if (launch_fill_u32(ctrl, E.nclear, 0, s) != hipSuccess) return EDP_E_HIP;
     if (launch_win_prep((const int32_t*)d_cost, d_centers, prob->width, prob->height, prob->qx, prob->qy, win, kWinBig,
                         cw, shifts, s) != hipSuccess)
         return EDP_E_HIP;
@@ -857,7 +873,7 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
-    c.one = make_desc(&f, la, E.inst, ws, flags, cw, d_labels, nullptr);
+    c.one = make_desc(&f, la, E.inst, ws, flags, ws + E.hand, cw, d_labels, nullptr);
     c.one.aux = shifts;
     c.one.centers = d_centers;
     c.one.win = win;

@@ -56,6 +56,8 @@ struct InstDesc {
     unsigned long long* energy;   // [1] output energy (batched energy kernel), may be null
     uint32_t* flags;              // [3][nsuper]: column progress of the first and the second scan of
                                   // a launch, then the scans completed by each workgroup band
+    unsigned long long* hand;     // [2][nsuper-1][W][QT] tagged rows handed between workgroup bands
+                                  // (first / second scan of a launch), cleared each solve; or null
     const void* aux;              // label-window solve: int8 frame shifts [H][W][4][2], else null
     const int32_t* centers;       // label-window solve: window centres [H][W][2], else null
     int32_t win, qx_full;         // label-window solve: window side, labels along x of the full space

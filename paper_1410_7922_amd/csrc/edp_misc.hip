@@ -92,9 +92,17 @@ __global__ __launch_bounds__(256) void batch_energy_kernel(const BatchEnergyArgs
     if (threadIdx.x == 0 && d.energy) atomicAdd(d.energy, (unsigned long long)sacc[0]);
 }
 
+// p[0 .. n) = v; the words from the first 16-byte boundary on go out four at a time
 __global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = v;
+    const size_t head = ((16 - ((uintptr_t)p & 15)) & 15) / 4;
+    const size_t h = head < n ? head : n;
+    const size_t nv = (n - h) / 4;
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x, step = (size_t)gridDim.x * blockDim.x;
+    if (tid < h) p[tid] = v;
+    uint4* q = (uint4*)(p + h);
+    const uint4 w = make_uint4(v, v, v, v);
+    for (size_t i = tid; i < nv; i += step) q[i] = w;
+    for (size_t i = h + 4 * nv + tid; i < n; i += step) p[i] = v;
 }
 
 __global__ __launch_bounds__(256) void sum_rows_kernel(const int64_t* rows, int32_t n, int64_t* out) {
@@ -184,8 +192,8 @@ hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hi
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    size_t grid = (n + 255) / 256;
-    if (grid > 1024) grid = 1024;
+    size_t grid = (n / 4 + 255) / 256 + 1;
+    if (grid > 2048) grid = 2048;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)grid), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }

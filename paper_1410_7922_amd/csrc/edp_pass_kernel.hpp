@@ -68,6 +68,15 @@ __device__ __forceinline__ void flag_put(uint32_t* p, uint32_t v) {
     __hip_atomic_store(glob(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void raise_error(uint32_t* error) { flag_put(error, 1u); }
+// Tagged sums handed between workgroups: (value, tag) in one 64-bit word, stored and loaded as
+// single device-scope 64-bit accesses, so a reader that sees the tag sees the value stored with it.
+typedef __attribute__((address_space(1))) unsigned long long gu64;
+__device__ __forceinline__ unsigned long long tag_get(const unsigned long long* p) {
+    return __hip_atomic_load((const gu64*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void tag_put(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store((gu64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // WIN: the label-window solve.  Every vertex holds an 8 x 8 frame of labels around its own
 // window (costs outside the window are large), d.aux holds the frame shifts towards the four
@@ -186,8 +195,68 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                     lds_put(wr, W);
                     cin = W;
                 }
+                // tagged rows (d.hand): column c of the row above carries tag epoch + c + 1 in every
+                // word; the buffer is cleared before each solve, so no other tag can match
+                const unsigned long long* const hin =
+                    d.hand && gin ? d.hand + (size_t)(((second ? 1 : 0) * (d.nsuper - 1) + super - 1) * W) * QT + l * E
+                                  : nullptr;
+                // at most 32 tagged words per lane in flight (the scan's register budget)
+                constexpr int NIT = NI * E <= 32 ? NI : (E >= 32 ? 1 : 32 / E);
 #pragma nounroll
-                while (cin < W) {
+                while (hin && cin < W) {
+                    const int32_t n = min(min(W - cin, lds_get(rd) + R - cin), NIT * CPI);
+                    int32_t got = 0;
+                    if (n > 0) {
+                        int32_t v[NIT][E];
+                        unsigned long long okm[NIT];
+#pragma unroll
+                        for (int q = 0; q < NIT; ++q) {
+                            const int32_t c = q * CPI + cg;
+                            bool good = c < n;
+                            const uint32_t tag = epoch + (uint32_t)(cin + c) + 1u;
+#pragma unroll
+                            for (int k = 0; k < E; ++k) {
+                                const unsigned long long x = c < n ? tag_get(hin + (size_t)(cin + c) * QT + k) : 0ull;
+                                v[q][k] = (int32_t)(uint32_t)x;
+                                good = good && (uint32_t)(x >> 32) == tag;
+                            }
+                            okm[q] = __ballot(good);
+                        }
+                        // columns arrive in any order: take the leading run whose every lane is tagged
+                        constexpr unsigned long long GM = G == 64 ? ~0ull : (1ull << G) - 1;
+                        bool run = true;
+#pragma unroll
+                        for (int q = 0; q < NIT; ++q)
+#pragma unroll
+                            for (int g = 0; g < CPI; ++g) {
+                                run = run && q * CPI + g < n && ((okm[q] >> (g * G)) & GM) == GM;
+                                if (run) got = q * CPI + g + 1;
+                            }
+#pragma unroll
+                        for (int q = 0; q < NIT; ++q) {
+                            const int32_t c = q * CPI + cg;
+                            if (c < got) {
+                                int32_t* slot = ring0 + (size_t)((cin + c) & (R - 1)) * QT;
+#pragma unroll
+                                for (int k = 0; k < E; ++k) slot[k * G] = v[q][k];
+                            }
+                        }
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        if (got > 0) lds_put(wr, cin + got);
+                        cin += got;
+                    }
+                    if (got > 0) {
+                        idle = 0;
+                    } else {
+                        if (++idle > SPIN_LIMIT_BAND || ((idle & 1023) == 0 && flag_get(a.error) != 0)) {
+                            raise_error(a.error);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+#pragma nounroll
+                while (!hin && cin < W) {
                     if (seen <= (uint32_t)cin) {
                         const uint32_t v = __builtin_amdgcn_readfirstlane(flag_get(progress + super - 1));
                         seen = v > epoch ? v - epoch : 0u;
@@ -230,6 +299,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                 const int32_t j1 = (super * NW + nact) * RPW - 1;   // last scanline (full band if gout)
                 const int32_t b_out = gout ? cell_off((sy > 0 ? j1 : H - 1 - j1) * W + xs, QT * 4) + lofs : OOB;
                 const int32_t* const ring_last = rings + (size_t)nact * R * QT + l;
+                unsigned long long* const hout =
+                    d.hand && gout ? d.hand + (size_t)(((second ? 1 : 0) * (d.nsuper - 1) + super) * W) * QT + l * E
+                                   : nullptr;
                 int32_t cout = 0, pub = 0;
 #pragma nounroll
                 while (cout < W) {
@@ -242,14 +314,23 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                             int32_t v[E];
 #pragma unroll
                             for (int k = 0; k < E; ++k) v[k] = slot[k * G];
-                            store_vec<E, CPOL_DEVICE>(rs_b, c < n ? b_out + (cout + c) * dtc : OOB, v);
+                            if (hout) {
+                                if (c < n) {
+                                    const unsigned long long tag = (unsigned long long)(epoch + (uint32_t)(cout + c) + 1u) << 32;
+#pragma unroll
+                                    for (int k = 0; k < E; ++k)
+                                        tag_put(hout + (size_t)(cout + c) * QT + k, tag | (uint32_t)v[k]);
+                                }
+                            } else {
+                                store_vec<E, CPOL_DEVICE>(rs_b, c < n ? b_out + (cout + c) * dtc : OOB, v);
+                            }
                         }
                         // LDS operations of a wavefront complete in order: the slots are read
                         // before the count that frees them is written
                         __atomic_signal_fence(__ATOMIC_SEQ_CST);
                         lds_put(rd + nact, cout + n);
                         cout += n;
-                        if (gout && (cout - pub >= a.chunk || cout == W)) {
+                        if (!hout && gout && (cout - pub >= a.chunk || cout == W)) {
                             // the row went out with device-scope stores: once they have
                             // completed the progress word may show it
                             __atomic_signal_fence(__ATOMIC_SEQ_CST);
