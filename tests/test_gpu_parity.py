@@ -169,6 +169,21 @@ def test_edp_steady_rounds_and_workgroup_handoffs(case):
         assert e == ref["energy"], (split, waves, chunk, fuse)
 
 
+def test_edp_reused_workspace_fresh_hand_off():
+    """Two different instances of one shape, solved one after the other in one workspace, with
+    several iterations: the rows handed between workgroups (tagged per pass and column) are
+    cleared for each solve, so the second solve never reads the first one's rows."""
+    ws = edp.Workspace()
+    for seed in (3, 4):
+        p = synth.random_problem(seed, 48, 57, 24, 1, 9, 2, 0, 0, 60, np.int16)
+        ref = cref.edp(p.cost, 24, 1, 9, 2, 0, 3, "lrms")
+        note(f"edp reused workspace {p.name} j3")
+        lab, e = edp.solve(to_dev(p.cost), 24, 1, 9, 2, 0, iterations=3, cost_bound=61, ws=ws, waves=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(lab.cpu().numpy(), ref["labels"])
+        assert int(e.item()) == ref["energy"]
+
+
 def test_edp_worked_example():
     cost = np.array([[[0, 5], [7, 0]], [[3, 1], [6, 2]]], np.int32)
     p = synth.Problem(cost, 2, 1, 1, 1, 0)
