@@ -70,7 +70,10 @@ typedef struct {
  * zero / negative field, selects the built-in choice:
  *   tile   lane tile mapping labels to lanes (edp_tiles(); -1 automatic)
  *   chunk  EDP columns a workgroup hands to the next one between two
- *          progress publications, at least (rounded up to a power of two)
+ *          progress publications, at least (rounded up to a power of two);
+ *          only where the hand-off publishes column counts (wavefronts of
+ *          one scanline, or instances whose tagged hand-off rows would
+ *          exceed 32 MB)
  *   split  1: every lane runs both minimum searches of a scan step;
  *          2: the two searches run on two halves of the vertex's lanes
  *   waves  compute wavefronts per EDP workgroup (1..6), handing rows over in
