@@ -5,12 +5,19 @@
  * baseline of the benchmark load this library.  It shares no code with the
  * GPU library and is written from the paper's definitions:
  *
- *   V(u)     truncated linear prior, Sec. 2 eq. Smooth_value_t with f(|a|)=|a|;
- *            mode 0 truncates each label dimension, mode 1 the summed distance.
+ *   V(u)     truncated prior, Sec. 2 eq. Smooth_value_t with f(|a|) = |a|
+ *            (prior 0, truncated linear) or f(|a|) = a^2 (prior 1, truncated
+ *            squared, l_1 = 2 of Sec. 5.1); mode 0 truncates each label
+ *            dimension, mode 1 the summed distance.
  *   M(h)(v)  = min_v' h(v') + V(v - v')       Sec. 2 eq. M_strf
  *            search 0: straightforward search over all v' (SFMS, the definition)
  *            search 1: the linear RMS passes of Sec. 3.2 (eqs. L_dec3, L_dec5
- *                      read as the mirror of L_dec3, L_dec6, clip of L_dec7).
+ *                      read as the mirror of L_dec3, L_dec6, clip of L_dec7);
+ *                      truncated linear prior only
+ *            search 2: the general RMS of Sec. 3.1: per label dimension the
+ *                      window minimum over |u_r| < g of eq. M_decmp1 (with the
+ *                      penalty lambda f(|u_r|) inside the minimum), then the
+ *                      clip of eq. M_decmp (per line in mode 0).
  *   DP       S(0)=C(0), S(x+1)=C(x+1)+M(S(x))  Sec. 2 eq. base, Sec. 4.1
  *   EDP      Sec. 4.2 eq. DP_2D_base with C added, S/2 as floor division,
  *            scans P1..P4 in place, eq. DP_2D_1 marginal, eq. DP_2D_2 argmin.
@@ -30,17 +37,21 @@
 #define OR_E_NOMEM -3
 
 typedef struct {
-    int qx, qy, q, lam, trunc, mode;
+    int qx, qy, q, lam, trunc, mode, prior;
 } prior_t;
 
 static int64_t iabs64(int64_t a) { return a < 0 ? -a : a; }
 static int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
+/* f of eq. Smooth_value_t */
+static int64_t prior_f(const prior_t *p, int64_t a) { return p->prior == 1 ? a * a : iabs64(a); }
+
 static int64_t prior_v(const prior_t *p, int v, int w) {
-    int64_t ax = iabs64((int64_t)(v % p->qx) - (w % p->qx));
-    int64_t ay = iabs64((int64_t)(v / p->qx) - (w / p->qx));
-    if (p->mode == 0) return (int64_t)p->lam * (imin64(ax, p->trunc) + imin64(ay, p->trunc));
-    return (int64_t)p->lam * imin64(ax + ay, p->trunc);
+    int64_t fx = prior_f(p, (int64_t)(v % p->qx) - (w % p->qx));
+    int64_t fy = prior_f(p, (int64_t)(v / p->qx) - (w / p->qx));
+    int64_t fg = prior_f(p, p->trunc);
+    if (p->mode == 0) return (int64_t)p->lam * (imin64(fx, fg) + imin64(fy, fg));
+    return (int64_t)p->lam * imin64(fx + fy, fg);
 }
 
 /* M by straightforward search; arg (nullable) receives the smallest minimising v'. */
@@ -104,21 +115,64 @@ static void msearch_lrms(const prior_t *p, const int64_t *h, int64_t *out, int64
         for (int v = 0; v < p->q; ++v) out[v] = imin64(out[v], gmin + clipd);
 }
 
+/* One line of M-bar_r (eq. M_decmp1): out(v) = min over |u| < g, v - u on the line, of
+ * line(v - u) + lambda f(|u|).  out must not alias line. */
+static void grms_line(const prior_t *p, const int64_t *line, int n, int stride, int64_t *out) {
+    for (int v = 0; v < n; ++v) {
+        int64_t best = line[(size_t)v * stride];
+        for (int u = 1; u < p->trunc; ++u) {
+            int64_t pen = (int64_t)p->lam * prior_f(p, u);
+            if (v - u >= 0) best = imin64(best, line[(size_t)(v - u) * stride] + pen);
+            if (v + u < n) best = imin64(best, line[(size_t)(v + u) * stride] + pen);
+        }
+        out[v] = best;
+    }
+}
+
+static void msearch_grms(const prior_t *p, const int64_t *h, int64_t *out, int64_t *scratch) {
+    int64_t *tmp = scratch;
+    int64_t clipd = (int64_t)p->lam * prior_f(p, p->trunc);
+    int64_t gmin = h[0];
+    for (int v = 0; v < p->q; ++v) { out[v] = h[v]; if (h[v] < gmin) gmin = h[v]; }
+    for (int vy = 0; vy < p->qy; ++vy) {           /* dimension x: lines of fixed vy */
+        int64_t *line = out + (size_t)vy * p->qx;
+        int64_t lmin = line[0];
+        for (int vx = 1; vx < p->qx; ++vx) lmin = imin64(lmin, line[vx]);
+        grms_line(p, line, p->qx, 1, tmp);
+        for (int vx = 0; vx < p->qx; ++vx) line[vx] = p->mode == 0 ? imin64(tmp[vx], lmin + clipd) : tmp[vx];
+    }
+    if (p->qy > 1) {
+        for (int vx = 0; vx < p->qx; ++vx) {       /* dimension y: lines of fixed vx */
+            int64_t *line = out + vx;
+            int64_t lmin = line[0];
+            for (int vy = 1; vy < p->qy; ++vy) lmin = imin64(lmin, line[(size_t)vy * p->qx]);
+            grms_line(p, line, p->qy, p->qx, tmp);
+            for (int vy = 0; vy < p->qy; ++vy)
+                line[(size_t)vy * p->qx] = p->mode == 0 ? imin64(tmp[vy], lmin + clipd) : tmp[vy];
+        }
+    }
+    if (p->mode == 1)
+        for (int v = 0; v < p->q; ++v) out[v] = imin64(out[v], gmin + clipd);
+}
+
 static void msearch(const prior_t *p, int search, const int64_t *h, int64_t *out, int64_t *scratch) {
     if (search == 1) msearch_lrms(p, h, out, scratch);
+    else if (search == 2) msearch_grms(p, h, out, scratch);
     else msearch_sfms(p, h, out, NULL);
 }
 
-static int check_args(int W, int H, int qx, int qy, int lam, int trunc, int mode) {
+static int check_args(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int search) {
     if (W < 1 || H < 1 || qx < 1 || qy < 1 || qx > 4096 || qy > 4096 || (int64_t)qx * qy > 4096) return 0;
-    if (lam < 0 || trunc < 1 || (mode != 0 && mode != 1)) return 0;
+    if (lam < 0 || trunc < 1 || trunc > 4096 || (mode != 0 && mode != 1)) return 0;
+    if (prior != 0 && prior != 1) return 0;
+    if (search < 0 || search > 2 || (search == 1 && prior != 0)) return 0;
     return 1;
 }
 
 /* Energy of eq. GE_objective_function; grid4 = 0: rows only, 1: 4-connected. */
-int64_t oracle_energy(int W, int H, int qx, int qy, int lam, int trunc, int mode, int grid4,
+int64_t oracle_energy(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int grid4,
                       const int32_t *cost, const int32_t *labels) {
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
     int64_t e = 0;
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
@@ -131,12 +185,13 @@ int64_t oracle_energy(int W, int H, int qx, int qy, int lam, int trunc, int mode
 }
 
 /* Scanline DP over every row.  search 0: SFMS with stored choice indexes;
- * search 1: LRMS values, and at backtracking the choice index at the chosen
- * label is found by direct search over the stored S(x-1) (the same argmin). */
-int oracle_dp_scanline(int W, int H, int qx, int qy, int lam, int trunc, int mode, int search,
+ * search 1 (LRMS) or 2 (GRMS): the values, and at backtracking the choice index
+ * at the chosen label is found by direct search over the stored S(x-1) (the
+ * same argmin). */
+int oracle_dp_scanline(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int search,
                        const int32_t *cost, int32_t *labels, int64_t *row_energy, int64_t *total) {
-    if (!check_args(W, H, qx, qy, lam, trunc, mode)) return OR_E_ARGS;
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    if (!check_args(W, H, qx, qy, lam, trunc, mode, prior, search)) return OR_E_ARGS;
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
     int Q = p.q;
     int64_t *S = malloc(sizeof(int64_t) * (size_t)W * Q);
     int64_t *m = malloc(sizeof(int64_t) * Q);
@@ -148,7 +203,7 @@ int oracle_dp_scanline(int W, int H, int qx, int qy, int lam, int trunc, int mod
         const int32_t *c = cost + (size_t)y * W * Q;
         for (int v = 0; v < Q; ++v) S[v] = c[v];
         for (int x = 1; x < W; ++x) {
-            if (search == 1) msearch_lrms(&p, S + (size_t)(x - 1) * Q, m, scratch);
+            if (search != 0) msearch(&p, search, S + (size_t)(x - 1) * Q, m, scratch);
             else msearch_sfms(&p, S + (size_t)(x - 1) * Q, m, ptr + (size_t)x * Q);
             for (int v = 0; v < Q; ++v) S[(size_t)x * Q + v] = c[(size_t)x * Q + v] + m[v];
         }
@@ -161,7 +216,7 @@ int oracle_dp_scanline(int W, int H, int qx, int qy, int lam, int trunc, int mod
         lab[W - 1] = bi;
         for (int x = W - 1; x > 0; --x) {
             int v = lab[x];
-            if (search == 1) {
+            if (search != 0) {
                 const int64_t *prev = S + (size_t)(x - 1) * Q;
                 int64_t best = prev[0] + prior_v(&p, v, 0);
                 int b = 0;
@@ -207,12 +262,12 @@ static int in_box(const int32_t *centers, int win, int W, int qx, int x, int y, 
     return vx >= c[0] - r && vx <= c[0] + r && vy >= c[1] - r && vy <= c[1] + r;
 }
 
-static int edp_core(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
+static int edp_core(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int iterations,
                     int search, const int32_t *cost, const int32_t *centers, int win, int32_t *labels,
                     int64_t *energy_out, int64_t *max_abs_out, int64_t *marginal_out) {
-    if (!check_args(W, H, qx, qy, lam, trunc, mode) || iterations < 0) return OR_E_ARGS;
+    if (!check_args(W, H, qx, qy, lam, trunc, mode, prior, search) || iterations < 0) return OR_E_ARGS;
     if (centers && (win < 1 || win % 2 == 0)) return OR_E_ARGS;
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
     int Q = p.q;
     size_t cells = (size_t)W * H;
     int64_t *S = calloc((size_t)4 * cells * Q, sizeof(int64_t));
@@ -292,39 +347,39 @@ static int edp_core(int W, int H, int qx, int qy, int lam, int trunc, int mode, 
             if (marginal_out)
                 memcpy(marginal_out + ((size_t)y * W + x) * Q, acc, sizeof(int64_t) * Q);
         }
-    *energy_out = oracle_energy(W, H, qx, qy, lam, trunc, mode, 1, cost, labels);
+    *energy_out = oracle_energy(W, H, qx, qy, lam, trunc, mode, prior, 1, cost, labels);
     *max_abs_out = maxabs;
     free(S); free(h); free(m); free(acc); free(scratch); free(nw);
     return status;
 }
 
-int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
+int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int iterations,
                int search, const int32_t *cost, int32_t *labels, int64_t *energy_out,
                int64_t *max_abs_out, int64_t *marginal_out) {
-    return edp_core(W, H, qx, qy, lam, trunc, mode, iterations, search, cost, NULL, 1, labels,
+    return edp_core(W, H, qx, qy, lam, trunc, mode, prior, iterations, search, cost, NULL, 1, labels,
                     energy_out, max_abs_out, marginal_out);
 }
 
 /* Windowed EDP: centers [H][W][2] (cx, cy) label coordinates, odd window side win. */
-int oracle_edp_window(int W, int H, int qx, int qy, int lam, int trunc, int mode, int iterations,
+int oracle_edp_window(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int iterations,
                       int search, const int32_t *cost, const int32_t *centers, int win,
                       int32_t *labels, int64_t *energy_out, int64_t *max_abs_out) {
     if (!centers) return OR_E_ARGS;
-    return edp_core(W, H, qx, qy, lam, trunc, mode, iterations, search, cost, centers, win, labels,
+    return edp_core(W, H, qx, qy, lam, trunc, mode, prior, iterations, search, cost, centers, win, labels,
                     energy_out, max_abs_out, NULL);
 }
 
-/* M on a batch of n vectors h[n][Q] (search 0: SFMS with arg (nullable); 1: LRMS). */
-int oracle_min_search(int qx, int qy, int lam, int trunc, int mode, int search, int n,
+/* M on a batch of n vectors h[n][Q] (search 0: SFMS with arg (nullable); 1: LRMS; 2: GRMS). */
+int oracle_min_search(int qx, int qy, int lam, int trunc, int mode, int prior, int search, int n,
                       const int64_t *h, int64_t *out, int32_t *arg) {
-    if (!check_args(1, 1, qx, qy, lam, trunc, mode) || n < 0) return OR_E_ARGS;
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode};
+    if (!check_args(1, 1, qx, qy, lam, trunc, mode, prior, search) || n < 0) return OR_E_ARGS;
+    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
     int64_t *scratch = malloc(sizeof(int64_t) * 8192);
     if (!scratch) return OR_E_NOMEM;
     for (int i = 0; i < n; ++i) {
         const int64_t *hi = h + (size_t)i * p.q;
         int64_t *oi = out + (size_t)i * p.q;
-        if (search == 1) msearch_lrms(&p, hi, oi, scratch);
+        if (search != 0) msearch(&p, search, hi, oi, scratch);
         else msearch_sfms(&p, hi, oi, arg ? arg + (size_t)i * p.q : NULL);
     }
     free(scratch);

@@ -4,9 +4,11 @@ Notation follows the paper (Mozerov, arXiv 1410.7922):
 
 * ``C[y][x][q]``  data cost (disparity space image), Sec. 2;
   flat label ``q = vy * qx + vx``, 0-based (the paper counts from 1).
-* ``V(u)``        truncated linear prior, Sec. 2 eq. Smooth_value_t with
-  f(|a|) = |a|; ``mode`` 1 truncates the summed distance over the label
-  dimensions as the paper does, ``mode`` 0 truncates each dimension on its own.
+* ``V(u)``        truncated prior, Sec. 2 eq. Smooth_value_t with f(|a|) = |a|
+  (``prior`` 0, truncated linear) or f(|a|) = a^2 (``prior`` 1, truncated
+  squared, the paper's l_1 = 2); ``mode`` 1 truncates the summed distance over
+  the label dimensions as the paper does, ``mode`` 0 truncates each dimension
+  on its own.
 * ``M(h)(v) = min_v' h(v') + V(v - v')``  the minimum search operator,
   Sec. 2 eq. M_strf; ``argM`` takes the smallest flat index among ties.
 * scanline DP: Sec. 2 eq. base with the zero boundary of Sec. 4.1 eq. DP_1D_2;
@@ -24,7 +26,11 @@ design notes of the repository):
 * every argmin returns the smallest flat label;
 * eq. L_dec5 (backward pass of the linear RMS) is read as the mirror of
   eq. L_dec3: S^-(v) = min over v'' > v of S(v'') + lambda (v'' - v), with
-  S^-(v_max) = +inf.
+  S^-(v_max) = +inf;
+* eq. M_decmp1 (one operator of the general RMS) adds lambda f(|u_r|) inside
+  the window minimum, not lambda f(g): with the constant the operator would be
+  a plain window minimum and eq. derivation2, from which it is derived, would
+  not hold.
 
 Every floating point question is absent: all arithmetic is on Python / int64
 integers, and every EDP sum is checked to fit in int32 (the GPU's type).
@@ -37,6 +43,8 @@ import numpy as np
 
 TRUNC_PER_DIM = 0
 TRUNC_JOINT = 1
+PRIOR_LINEAR = 0        # f(|a|) = |a|
+PRIOR_QUAD = 1          # f(|a|) = a^2
 INT32_MAX = 2**31 - 1
 
 
@@ -44,23 +52,33 @@ INT32_MAX = 2**31 - 1
 # prior and minimum search
 # ---------------------------------------------------------------------------
 
-def prior_value(ux: int, uy: int, lam: int, trunc: int, mode: int) -> int:
-    """V(u) for a label difference u = (ux, uy): Sec. 2 eq. Smooth_value_t, f(|a|) = |a|."""
-    ax, ay = abs(int(ux)), abs(int(uy))
+def prior_f(a, prior: int = PRIOR_LINEAR):
+    """The increasing function f of Sec. 2 eq. Smooth_value_t: |a|, or a^2 (Sec. 5.1, l_1 = 2)."""
+    if prior == PRIOR_LINEAR:
+        return abs(a)
+    if prior == PRIOR_QUAD:
+        return a * a
+    raise ValueError(f"unknown prior {prior}")
+
+
+def prior_value(ux: int, uy: int, lam: int, trunc: int, mode: int, prior: int = PRIOR_LINEAR) -> int:
+    """V(u) for a label difference u = (ux, uy): Sec. 2 eq. Smooth_value_t."""
+    fx, fy, fg = prior_f(int(ux), prior), prior_f(int(uy), prior), prior_f(int(trunc), prior)
     if mode == TRUNC_PER_DIM:
-        return lam * (min(ax, trunc) + min(ay, trunc))
-    return lam * min(ax + ay, trunc)
+        return lam * (min(fx, fg) + min(fy, fg))
+    return lam * min(fx + fy, fg)
 
 
-def prior_matrix(qx: int, qy: int, lam: int, trunc: int, mode: int) -> np.ndarray:
+def prior_matrix(qx: int, qy: int, lam: int, trunc: int, mode: int, prior: int = PRIOR_LINEAR) -> np.ndarray:
     """Vm[v, v'] = V(v - v') over flat labels, int64 [Q, Q]."""
-    q = np.arange(qx * qy)
+    q = np.arange(qx * qy, dtype=np.int64)
     vx, vy = q % qx, q // qx
-    ax = np.abs(vx[:, None] - vx[None, :])
-    ay = np.abs(vy[:, None] - vy[None, :])
+    fx = prior_f(vx[:, None] - vx[None, :], prior)
+    fy = prior_f(vy[:, None] - vy[None, :], prior)
+    fg = prior_f(int(trunc), prior)
     if mode == TRUNC_PER_DIM:
-        return (lam * (np.minimum(ax, trunc) + np.minimum(ay, trunc))).astype(np.int64)
-    return (lam * np.minimum(ax + ay, trunc)).astype(np.int64)
+        return (lam * (np.minimum(fx, fg) + np.minimum(fy, fg))).astype(np.int64)
+    return (lam * np.minimum(fx + fy, fg)).astype(np.int64)
 
 
 class OpCounter:
@@ -76,14 +94,14 @@ class OpCounter:
 
 
 def min_search_sfms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                    counter: OpCounter | None = None):
+                    counter: OpCounter | None = None, prior: int = PRIOR_LINEAR):
     """Straightforward minimum search (SFMS, Sec. 3 end): the definition eq. M_strf.
 
     ``h`` has shape [..., Q].  Returns (M(h), argM(h)); argM is the smallest
     flat index v' attaining the minimum.
     """
     h = np.asarray(h, dtype=np.int64)
-    vm = prior_matrix(qx, qy, lam, trunc, mode)
+    vm = prior_matrix(qx, qy, lam, trunc, mode, prior)
     tot = h[..., None, :] + vm                    # [..., v, v']
     arg = np.argmin(tot, axis=-1)                 # first minimum = smallest v'
     val = np.take_along_axis(tot, arg[..., None], axis=-1)[..., 0]
@@ -153,12 +171,76 @@ def min_search_lrms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode:
     return out.reshape(*lead, qx * qy)
 
 
+def _general_rms_line(line: list, lam: int, trunc: int, prior: int, counter: OpCounter | None):
+    """Operator M-bar_r of Sec. 3.1 eq. M_decmp1 on one line: the minimum over the window
+    |u| < g of S(v - u) + lam f(|u|).  The line is extended by g - 1 infinite entries at
+    each end, so every output label examines the whole window of 2g - 1 entries."""
+    n = len(line)
+    inf = None
+    ext = [inf] * (trunc - 1) + list(line) + [inf] * (trunc - 1)
+    out = []
+    for v in range(n):
+        best = None
+        for u in range(-(trunc - 1), trunc):
+            s = ext[v - u + trunc - 1]
+            if s is inf:
+                continue
+            t = s + lam * prior_f(u, prior)
+            best = t if best is None else min(best, t)
+        out.append(best)
+    if counter is not None:
+        counter.ops += (2 * trunc - 1) * n
+    return out
+
+
+def min_search_grms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                    counter: OpCounter | None = None, prior: int = PRIOR_QUAD) -> np.ndarray:
+    """General RMS (GRMS, Sec. 3.1) for any truncated prior f: one windowed operator per
+    label dimension and the clip of eq. M_decmp.
+
+    ``mode`` 1 (joint truncation): M = M-bar_y(M-bar_x(h)) ^ (min h + lam f(g)), eq. M_decmp
+    (the product of the per-dimension windows holds every u with f(|u|) < f(g), eq. derivation2).
+    ``mode`` 0 (per-dimension truncation): each dimension's operator is followed by the clip of
+    its own line, min h_line + lam f(g) (eq. derivation1 applied to that dimension).
+    Only the values are returned.
+    """
+    h = np.asarray(h, dtype=np.int64)
+    lead = h.shape[:-1]
+    flat = h.reshape(-1, qy, qx)
+    out = np.empty_like(flat)
+    clipd = lam * prior_f(trunc, prior)
+    for n in range(flat.shape[0]):
+        g = [[int(flat[n, vy, vx]) for vx in range(qx)] for vy in range(qy)]
+        for vy in range(qy):                                   # dimension x (r = 1)
+            line = _general_rms_line(g[vy], lam, trunc, prior, counter)
+            if mode == TRUNC_PER_DIM:
+                clip = min(g[vy]) + clipd
+                line = [min(a, clip) for a in line]
+            g[vy] = line
+        if qy > 1:                                             # dimension y (r = 2)
+            for vx in range(qx):
+                col = [g[vy][vx] for vy in range(qy)]
+                line = _general_rms_line(col, lam, trunc, prior, counter)
+                if mode == TRUNC_PER_DIM:
+                    clip = min(col) + clipd
+                    line = [min(a, clip) for a in line]
+                for vy in range(qy):
+                    g[vy][vx] = line[vy]
+        if mode == TRUNC_JOINT:
+            clip = int(flat[n].min()) + clipd
+            g = [[min(a, clip) for a in row] for row in g]
+        out[n] = np.array(g, dtype=np.int64)
+        if counter is not None:
+            counter.outputs += qx * qy
+    return out.reshape(*lead, qx * qy)
+
+
 # ---------------------------------------------------------------------------
 # energy (Sec. 2 eq. GE_objective_function)
 # ---------------------------------------------------------------------------
 
 def energy(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, trunc: int,
-           mode: int, grid4: bool) -> int:
+           mode: int, grid4: bool, prior: int = PRIOR_LINEAR) -> int:
     """E = sum_x C(x, v(x)) + sum over neighbour pairs of V(v(x') - v(x)).
 
     ``grid4`` False: horizontal pairs only (independent scanlines, eq. One_d);
@@ -172,9 +254,10 @@ def energy(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, tru
     vx, vy = labels % qx, labels // qx
 
     def pair(ax, ay):
+        fx, fy, fg = prior_f(ax, prior), prior_f(ay, prior), prior_f(trunc, prior)
         if mode == TRUNC_PER_DIM:
-            return lam * (np.minimum(ax, trunc) + np.minimum(ay, trunc))
-        return lam * np.minimum(ax + ay, trunc)
+            return lam * (np.minimum(fx, fg) + np.minimum(fy, fg))
+        return lam * np.minimum(fx + fy, fg)
 
     e += int(pair(np.abs(vx[:, 1:] - vx[:, :-1]), np.abs(vy[:, 1:] - vy[:, :-1])).sum())
     if grid4:
@@ -186,7 +269,8 @@ def energy(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, tru
 # scanline DP (Sec. 2 eq. One_d / eq. base, Sec. 4.1)
 # ---------------------------------------------------------------------------
 
-def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int):
+def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                prior: int = PRIOR_LINEAR):
     """Brute-force scanline DP: every row is an independent chain.
 
     S(0, v) = C(0, v) (zero boundary, eq. DP_1D_2), S(x+1) = C(x+1) + M(S(x)) (eq. base)
@@ -199,7 +283,7 @@ def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: 
     ptr = np.zeros((H, W, Q), np.int64)
     s = cost[:, 0, :].copy()
     for x in range(1, W):
-        m, a = min_search_sfms(s, qx, qy, lam, trunc, mode)
+        m, a = min_search_sfms(s, qx, qy, lam, trunc, mode, prior=prior)
         ptr[:, x, :] = a
         s = cost[:, x, :] + m
     row_e = s.min(axis=1)
@@ -211,7 +295,8 @@ def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: 
     return labels, row_e, int(row_e.sum())
 
 
-def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int):
+def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                     prior: int = PRIOR_LINEAR):
     """Modified DP of Sec. 4.1, eq. DP_1D_3: S_Omega(x) = M(S_1(x-1)) + C(x) + M(S_-1(x+1)).
 
     S_1 runs left to right, S_-1 right to left, both with the zero boundary.
@@ -223,16 +308,16 @@ def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
     bwd = np.zeros((W, Q), np.int64)
     fwd[0] = c[0]
     for x in range(1, W):
-        fwd[x] = c[x] + min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode)[0]
+        fwd[x] = c[x] + min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode, prior=prior)[0]
     bwd[W - 1] = c[W - 1]
     for x in range(W - 2, -1, -1):
-        bwd[x] = c[x] + min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode)[0]
+        bwd[x] = c[x] + min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode, prior=prior)[0]
     marg = c.copy()
     for x in range(W):
         if x > 0:
-            marg[x] += min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode)[0]
+            marg[x] += min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode, prior=prior)[0]
         if x < W - 1:
-            marg[x] += min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode)[0]
+            marg[x] += min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode, prior=prior)[0]
     return marg
 
 
@@ -240,7 +325,8 @@ def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
 # exhaustive enumeration (tiny inputs)
 # ---------------------------------------------------------------------------
 
-def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int):
+def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                     prior: int = PRIOR_LINEAR):
     """All Q^W labellings of one chain.  Returns (E_min, canonical optimal labelling).
 
     The canonical labelling is the reverse-lexicographic minimum among the optimal
@@ -250,7 +336,7 @@ def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
     W, Q = c.shape
     labs = np.array(list(itertools.product(range(Q), repeat=W)), dtype=np.int64)
     e = c[np.arange(W)[None, :], labs].sum(axis=1)
-    vm = prior_matrix(qx, qy, lam, trunc, mode)
+    vm = prior_matrix(qx, qy, lam, trunc, mode, prior)
     for x in range(W - 1):
         e += vm[labs[:, x + 1], labs[:, x]]
     best = e.min()
@@ -259,7 +345,8 @@ def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
     return int(best), opt[order[0]]
 
 
-def grid_exhaustive(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int) -> int:
+def grid_exhaustive(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                    prior: int = PRIOR_LINEAR) -> int:
     """Minimum 4-connected energy over all Q^(W*H) labellings of a tiny grid."""
     c = np.asarray(cost, dtype=np.int64)
     H, W, Q = c.shape
@@ -267,7 +354,7 @@ def grid_exhaustive(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mo
     labs = np.array(list(itertools.product(range(Q), repeat=n)), dtype=np.int64).reshape(-1, H, W)
     yy, xx = np.mgrid[0:H, 0:W]
     e = c[yy[None], xx[None], labs].reshape(labs.shape[0], -1).sum(axis=1)
-    vm = prior_matrix(qx, qy, lam, trunc, mode)
+    vm = prior_matrix(qx, qy, lam, trunc, mode, prior)
     e += vm[labs[:, :, 1:], labs[:, :, :-1]].reshape(labs.shape[0], -1).sum(axis=1)
     e += vm[labs[:, 1:, :], labs[:, :-1, :]].reshape(labs.shape[0], -1).sum(axis=1)
     return int(e.min())
@@ -290,7 +377,7 @@ SCANS = (
 
 
 def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-        iterations: int = 1, search: str = "sfms", trace=None):
+        iterations: int = 1, search: str = "sfms", trace=None, prior: int = PRIOR_LINEAR):
     """Literal EDP, Algorithm 1 steps 3-5 (the DSI and the prior are the inputs).
 
     For every scan P1..P4 and every vertex x in the scan's raster order, each sum
@@ -300,14 +387,18 @@ def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
     rounds of the four scans, S_Omega(x) = C(x) + sum_k M(S_k(x_k) // 2) (eq. DP_2D_1)
     and the label is its smallest argmin (eq. DP_2D_2).
 
-    ``search`` selects M: "sfms" (definition) or "lrms" (Sec. 3.2 passes).
+    ``search`` selects M: "sfms" (definition), "lrms" (Sec. 3.2 passes, linear prior only)
+    or "grms" (Sec. 3.1 windowed operators).
     ``trace`` (optional) is called after every scan as trace(iteration, scan, sums).
     Returns dict(labels, energy, marginal, sums, max_abs_sum).
     """
     c = np.asarray(cost, dtype=np.int64)
     H, W, Q = c.shape
-    msearch = {"sfms": lambda h: min_search_sfms(h, qx, qy, lam, trunc, mode)[0],
-               "lrms": lambda h: min_search_lrms(h, qx, qy, lam, trunc, mode)}[search]
+    if search == "lrms" and prior != PRIOR_LINEAR:
+        raise ValueError("the linear RMS applies to the truncated linear prior only")
+    msearch = {"sfms": lambda h: min_search_sfms(h, qx, qy, lam, trunc, mode, prior=prior)[0],
+               "lrms": lambda h: min_search_lrms(h, qx, qy, lam, trunc, mode),
+               "grms": lambda h: min_search_grms(h, qx, qy, lam, trunc, mode, prior=prior)}[search]
     sums = {k: np.zeros((H, W, Q), np.int64) for k in DIRECTIONS}
     max_abs = 0
 
@@ -345,7 +436,7 @@ def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
     labels = np.argmin(marg, axis=-1)
     if max_abs > INT32_MAX:
         raise OverflowError(f"EDP sum {max_abs} exceeds int32")
-    e = energy(c, labels, qx, qy, lam, trunc, mode, grid4=True)
+    e = energy(c, labels, qx, qy, lam, trunc, mode, grid4=True, prior=prior)
     return {"labels": labels, "energy": e, "marginal": marg, "sums": sums,
             "max_abs_sum": max_abs}
 

@@ -27,10 +27,13 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # Truncation modes of the smoothness prior (meaning is fixed by the solvers):
-#   0: per label dimension  lambda * (min(|dx|, T) + min(|dy|, T))
-#   1: joint                lambda * min(|dx| + |dy|, T)
+#   0: per label dimension  lambda * (min(f(|dx|), f(T)) + min(f(|dy|), f(T)))
+#   1: joint                lambda * min(f(|dx|) + f(|dy|), f(T))
 TRUNC_PER_DIM = 0
 TRUNC_JOINT = 1
+# Prior functions f: 0 truncated linear f(a) = a, 1 truncated squared f(a) = a^2.
+PRIOR_LINEAR = 0
+PRIOR_QUAD = 1
 
 
 @dataclass
@@ -45,6 +48,7 @@ class Problem:
     mode: int = TRUNC_PER_DIM
     name: str = ""
     meta: dict = field(default_factory=dict)
+    prior: int = PRIOR_LINEAR
 
     @property
     def height(self) -> int:
@@ -265,13 +269,20 @@ def random_problem(seed: int, W: int, H: int, qx: int, qy: int = 1, lam: int = 7
 # --------------------------------------------------------------------------
 
 def workload(name: str, seed: int = 0) -> Problem:
-    """The named workloads: chain64x48, stereo384x288, motion320x240, motion640x480."""
+    """The named workloads: chain64x48, stereo384x288, motion320x240, motion640x480, and with
+    the truncated squared prior (lambda 5, T 3, so the clip lambda T^2 = 45 is near the linear
+    workloads' lambda T): stereo384x288_sq, motion320x240_sq."""
     if name == "chain64x48":
         return chain_problem(seed)
     if name == "stereo384x288":
         return stereo_problem(seed)
     if name == "motion320x240":
         return motion_problem(seed)
+    if name in ("stereo384x288_sq", "motion320x240_sq"):
+        p = stereo_problem(seed, lam=5, trunc=3) if name.startswith("stereo") else motion_problem(seed, lam=5, trunc=3)
+        p.prior = PRIOR_QUAD
+        p.name += "_sq"
+        return p
     if name == "motion640x480":
         return motion_problem(seed, W=640, H=480, r=15)
     raise KeyError(name)
