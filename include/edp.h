@@ -5,14 +5,18 @@
  * Multidimensional Search Algorithm for Energy Minimization in Stereo and
  * Motion" (arXiv 1410.7922).
  *
- *   Energy (Sec. 2, eq. GE_objective_function with the truncated linear prior
- *   of eq. Smooth_value_t, f(|a|) = |a|):
+ *   Energy (Sec. 2, eq. GE_objective_function with the truncated prior of
+ *   eq. Smooth_value_t; f(a) = |a| for EDP_PRIOR_LINEAR, f(a) = a^2 for
+ *   EDP_PRIOR_SQUARED, the two priors of Sec. 5.1):
  *       E(v) = sum_x C(x, v(x)) + sum over neighbour pairs (x, x') V(v(x') - v(x))
- *       V(u) = lambda * (min(|ux|, T) + min(|uy|, T))   trunc_mode EDP_TRUNC_PER_DIM
- *       V(u) = lambda * min(|ux| + |uy|, T)             trunc_mode EDP_TRUNC_JOINT
+ *       V(u) = lambda * (min(f(ux), f(T)) + min(f(uy), f(T)))   trunc_mode EDP_TRUNC_PER_DIM
+ *       V(u) = lambda * min(f(ux) + f(uy), f(T))                trunc_mode EDP_TRUNC_JOINT
  *   Minimum search (Sec. 2, eq. M_strf): M(h)(v) = min_v' h(v') + V(v - v'),
- *   computed by the linear recursive minimum search of Sec. 3.2 (two passes
- *   per label dimension plus the clip of eq. L_dec7), never by the O(Q^2) scan.
+ *   never by the O(Q^2) scan: for the linear prior by the linear recursive
+ *   minimum search of Sec. 3.2 (two passes per label dimension plus the clip
+ *   of eq. L_dec7), for the squared prior by the general one of Sec. 3.1 (a
+ *   window minimum over |u| < T per label dimension plus the clip of
+ *   eq. M_decmp, 2T - 1 candidates per label and dimension).
  *
  * Conventions shared by every entry point
  *   - Cost volume: dense, row-major C[y][x][q], int16 or int32, caller-owned
@@ -50,6 +54,7 @@ typedef enum {
 
 typedef enum { EDP_I16 = 1, EDP_I32 = 2 } edp_dtype;
 typedef enum { EDP_TRUNC_PER_DIM = 0, EDP_TRUNC_JOINT = 1 } edp_trunc_mode;
+typedef enum { EDP_PRIOR_LINEAR = 0, EDP_PRIOR_SQUARED = 1 } edp_prior;
 typedef enum { EDP_OP_DP = 0, EDP_OP_EDP = 1 } edp_op;
 
 /* One energy-minimisation instance (Sec. 2). */
@@ -64,6 +69,7 @@ typedef struct {
     int32_t trunc;       /* truncation threshold T (the paper's g), 1 <= T <= 4096 */
     int32_t iterations;  /* EDP iterations j >= 1 of Algorithm 1 (ignored by the DP) */
     int32_t cost_bound;  /* promise |C| <= cost_bound; 0 = the dtype's range (int16 only) */
+    int32_t prior;       /* edp_prior: f(a) = |a| (0) or a^2 (1) */
 } edp_problem;
 
 /* Optional tuning of the launch (results never depend on it).  NULL, or a
@@ -137,7 +143,8 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
  * of 8 x 8 labels and every sum handed to a neighbour is evaluated in the
  * neighbour's frame, so the work per vertex does not grow with Q.  win odd,
  * 1 <= win <= 8, boxes inside the label space (win/2 <= cx < qx - win/2, same
- * for cy); int32 costs.  The energy is that of the labels on the full cost.
+ * for cy); int32 costs; the truncated linear prior only (EDP_E_UNSUPPORTED
+ * otherwise).  The energy is that of the labels on the full cost.
  * tuning: tile must be -1 or 13 (the 8 x 8 lane tile, one label per lane),
  *         split 1; waves, chunk, fuse as for edp_solve.
  *   d_centers [H][W][2] int32;  d_labels [H][W] int32 labels of the full space

@@ -5,5 +5,5 @@ Algorithm for Energy Minimization in Stereo and Motion", arXiv 1410.7922.
 The solvers live in ``libedp.so`` (C ABI: include/edp.h); ``binding`` marshals
 torch tensors into it.
 """
-from .binding import (TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace, dp_scanline,  # noqa: F401
-                      energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)
+from .binding import (PRIOR_LINEAR, PRIOR_SQUARED, TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace,  # noqa: F401
+                      dp_scanline, energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)

@@ -19,6 +19,8 @@ EDP_I16 = 1
 EDP_I32 = 2
 TRUNC_PER_DIM = 0
 TRUNC_JOINT = 1
+PRIOR_LINEAR = 0      # f(a) = |a|
+PRIOR_SQUARED = 1     # f(a) = a^2
 OP_DP = 0
 OP_EDP = 1
 
@@ -30,7 +32,7 @@ EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "
 
 class Problem(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "width", "height", "qx", "qy", "dtype", "trunc_mode", "lam", "trunc", "iterations", "cost_bound")]
+        "width", "height", "qx", "qy", "dtype", "trunc_mode", "lam", "trunc", "iterations", "cost_bound", "prior")]
 
 
 class Tuning(ctypes.Structure):
@@ -98,7 +100,7 @@ def _check(status: int, where: str):
 
 
 def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mode: int = TRUNC_PER_DIM,
-                 iterations: int = 1, cost_bound: int = 0) -> Problem:
+                 iterations: int = 1, cost_bound: int = 0, prior: int = PRIOR_LINEAR) -> Problem:
     if cost.dim() != 3:
         raise ValueError("cost must be [H][W][Q]")
     if cost.dtype not in (torch.int16, torch.int32):
@@ -107,7 +109,7 @@ def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mod
     if Q != qx * qy:
         raise ValueError(f"cost has {Q} labels, qx*qy = {qx * qy}")
     return Problem(W, H, qx, qy, EDP_I16 if cost.dtype == torch.int16 else EDP_I32, mode, lam, trunc,
-                   iterations, cost_bound)
+                   iterations, cost_bound, prior)
 
 
 def _tuning(tile: int, chunk: int, events=None, split: int = 0, waves: int = 0, fuse: int = 0):
@@ -174,11 +176,11 @@ _default_ws = Workspace()
 
 def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2,
                 mode: int = TRUNC_PER_DIM, cost_bound: int = 0, tile: int = -1, ws: Workspace | None = None,
-                events=None):
+                events=None, prior: int = PRIOR_LINEAR):
     """Independent scanline DP (edp_dp_scanline).  Returns (labels [H][W] int32,
     row energies [H] int64, total energy [1] int64) as device tensors."""
     _device_tensor(cost, "cost")
-    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound)
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound, prior)
     nbytes = workspace_size(prob, OP_DP, tile)
     w = (ws or _default_ws).get(nbytes, cost.device)
     H, W, _ = cost.shape
@@ -194,12 +196,12 @@ def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: 
 def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,
           iterations: int = 1, cost_bound: int = 0, tile: int = -1, chunk: int = 0,
           ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None,
-          events=None, split: int = 0, waves: int = 0, fuse: int = 0):
+          events=None, split: int = 0, waves: int = 0, fuse: int = 0, prior: int = PRIOR_LINEAR):
     """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors.
 
     ``events``: optional ctypes array of hipEvent_t handles recorded around the scan launches."""
     _device_tensor(cost, "cost")
-    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound)
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound, prior)
     nbytes = workspace_size(prob, OP_EDP, tile, chunk, split, waves, fuse)
     w = (ws or _default_ws).get(nbytes, cost.device)
     H, W, _ = cost.shape
@@ -238,13 +240,13 @@ def solve_windowed(cost: torch.Tensor, centers: torch.Tensor, win: int, qx: int,
 
 
 def energy(cost: torch.Tensor, labels: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2,
-           mode: int = TRUNC_PER_DIM, grid4: bool = True, cost_bound: int = 0):
+           mode: int = TRUNC_PER_DIM, grid4: bool = True, cost_bound: int = 0, prior: int = PRIOR_LINEAR):
     """Energy of a labelling (edp_energy).  Returns (energy [1] int64, invalid-label count [1] int64)."""
     _device_tensor(cost, "cost")
     _device_tensor(labels, "labels")
     if labels.dtype != torch.int32 or tuple(labels.shape) != tuple(cost.shape[:2]):
         raise ValueError("labels must be int32 [H][W]")
-    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound)
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound, prior)
     e = torch.empty(1, dtype=torch.int64, device=cost.device)
     bad = torch.empty(1, dtype=torch.int64, device=cost.device)
     _check(load().edp_energy(ctypes.byref(prob), cost.data_ptr(), labels.data_ptr(), int(bool(grid4)),
@@ -254,7 +256,7 @@ def energy(cost: torch.Tensor, labels: torch.Tensor, qx: int, qy: int = 1, lam: 
 
 def batch_items(costs, params, labels, energies, tunings=None):
     """ctypes array of edp_batch_item for device tensors: params[i] holds qx, qy, lam, trunc, mode,
-    iterations, cost_bound; tunings[i] (optional) holds tile, chunk, split, waves, fuse."""
+    iterations, cost_bound, prior; tunings[i] (optional) holds tile, chunk, split, waves, fuse."""
     n = len(costs)
     items = (BatchItem * n)()
     for i in range(n):
@@ -263,7 +265,7 @@ def batch_items(costs, params, labels, energies, tunings=None):
         pr = params[i]
         items[i].problem = make_problem(costs[i], pr["qx"], pr.get("qy", 1), pr["lam"], pr["trunc"],
                                         pr.get("mode", TRUNC_PER_DIM), pr.get("iterations", 1),
-                                        pr.get("cost_bound", 0))
+                                        pr.get("cost_bound", 0), pr.get("prior", PRIOR_LINEAR))
         items[i].d_cost = costs[i].data_ptr()
         items[i].d_labels = labels[i].data_ptr()
         items[i].d_energy = energies.data_ptr() + 8 * i if energies is not None else None

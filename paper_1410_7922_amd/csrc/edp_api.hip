@@ -67,9 +67,15 @@ int64_t cost_bound_of(const edp_problem* p) {
     return p->dtype == EDP_I16 ? 32768 : -1;
 }
 
+// lambda f(T): the largest distance penalty of one label dimension, the clip of M
+int64_t clip_of(const edp_problem* p) {
+    const int64_t t = p->trunc;
+    return (int64_t)p->lambda * (p->prior == EDP_PRIOR_SQUARED ? t * t : t);
+}
+
 int64_t vmax_of(const edp_problem* p) {
     const int64_t dims = (p->trunc_mode == EDP_TRUNC_PER_DIM && p->qy > 1) ? 2 : 1;
-    return (int64_t)p->lambda * p->trunc * dims;
+    return clip_of(p) * dims;
 }
 
 edp_status check_problem(const edp_problem* p, int op) {
@@ -80,6 +86,7 @@ edp_status check_problem(const edp_problem* p, int op) {
     if (p->dtype != EDP_I16 && p->dtype != EDP_I32) return EDP_E_INVALID;
     if (p->trunc_mode != EDP_TRUNC_PER_DIM && p->trunc_mode != EDP_TRUNC_JOINT) return EDP_E_INVALID;
     if (p->lambda < 0 || p->lambda > 65535 || p->trunc < 1 || p->trunc > 4096) return EDP_E_INVALID;
+    if (p->prior != EDP_PRIOR_LINEAR && p->prior != EDP_PRIOR_SQUARED) return EDP_E_INVALID;
     if (p->cost_bound < 0) return EDP_E_INVALID;
     if (op == EDP_OP_EDP) {
         if (p->iterations < 1 || p->iterations > 4096) return EDP_E_INVALID;
@@ -262,9 +269,10 @@ InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, 
     d.qx = p->qx;
     d.qy = p->qy;
     d.lam = p->lambda;
-    d.clipd = p->lambda * p->trunc;
+    d.clipd = (int32_t)clip_of(p);
     d.joint = p->trunc_mode == EDP_TRUNC_JOINT;
     d.trunc = p->trunc;
+    d.quad = p->prior == EDP_PRIOR_SQUARED;
     d.nbands = la.nbands;
     d.nsuper = la.nsuper;
     return d;
@@ -273,6 +281,7 @@ InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, 
 // Everything one launch shape needs to run its scans and the marginal.
 struct ClassRun {
     int tile, kind, dtype, split, waves, chunk, ring, fuse, iterations;
+    bool quad;                 // truncated squared prior
     InstDesc one;              // single instance (descs null)
     const InstDesc* descs;     // device descriptor slice of a batch class
     int ndesc;
@@ -285,7 +294,8 @@ struct ClassRun {
 int agg_cells_per_block(int tile) { return (64 / group_of(tile)) * 4; }
 
 int scan_grid(const ClassRun& c) {
-    const int cap = pass_capacity(c.tile, c.kind, c.split, c.waves, pass_lds_bytes(qt_of(c.tile), c.waves, c.ring));
+    const int cap =
+        pass_capacity(c.tile, c.kind, c.split, c.quad, c.waves, pass_lds_bytes(qt_of(c.tile), c.waves, c.ring));
     const int total = c.fuse * c.tickets_per_pass;
     return total < cap ? total : cap;
 }
@@ -324,7 +334,7 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
             a.ticket = c.tickets + launch;
             const bool timed = ev && ev->events && 2 * launch + 1 < ev->n_events;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch], s) != hipSuccess) return EDP_E_HIP;
-            if (launch_edp_pass(c.tile, c.kind, c.split, a, grid, c.waves, s) != hipSuccess) return EDP_E_HIP;
+            if (launch_edp_pass(c.tile, c.kind, c.split, c.quad, a, grid, c.waves, s) != hipSuccess) return EDP_E_HIP;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch + 1], s) != hipSuccess)
                 return EDP_E_HIP;
         }
@@ -366,7 +376,7 @@ edp_status win_launch(const edp_problem* prob, int32_t win, const edp_tuning* tu
     edp_status st = check_problem(prob, EDP_OP_EDP);
     if (st != EDP_OK) return st;
     if (win < 1 || win > WIN_FRAME || !(win & 1) || win > prob->qx || win > prob->qy) return EDP_E_INVALID;
-    if (prob->dtype != EDP_I32) return EDP_E_UNSUPPORTED;
+    if (prob->dtype != EDP_I32 || prob->prior != EDP_PRIOR_LINEAR) return EDP_E_UNSUPPORTED;
     if (tu && ((tu->tile >= 0 && tu->tile != WIN_TILE) || (tu->split > 1) || tu->chunk < 0 || tu->n_events < 0))
         return EDP_E_INVALID;
     edp_tuning t{};
@@ -407,6 +417,7 @@ edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t*
     e.trunc = p->trunc;
     e.joint = p->trunc_mode == EDP_TRUNC_JOINT;
     e.grid4 = grid4;
+    e.quad = p->prior == EDP_PRIOR_SQUARED;
     hipError_t err = launch_fill_u32((uint32_t*)energy, 2, 0, s);
     if (err == hipSuccess && invalid) err = launch_fill_u32((uint32_t*)invalid, 2, 0, s);
     if (err == hipSuccess) err = launch_energy(p->dtype, e, s);
@@ -431,6 +442,7 @@ struct BatchEntry {
 
 struct BatchClassPlan {
     int tile, kind, dtype, split, waves, chunk, ring, fuse, iterations;
+    bool quad;
     std::vector<int> members;   // items, longest first
     int first_desc;
     size_t tickets_word, error_word;
@@ -465,7 +477,7 @@ edp_status plan_batch(int32_t n, const edp_batch_item* items, BatchLayout* B) {
             const BatchClassPlan& k = B->classes[c];
             if (k.tile == e.la.tile && k.kind == e.kind && k.split == e.la.split && k.waves == e.la.waves &&
                 k.chunk == e.la.chunk && k.ring == e.la.ring && k.fuse == e.la.fuse &&
-                k.iterations == it.problem.iterations)
+                k.iterations == it.problem.iterations && k.quad == (it.problem.prior == EDP_PRIOR_SQUARED))
                 break;
         }
         if (c == (int)B->classes.size()) {
@@ -478,6 +490,7 @@ edp_status plan_batch(int32_t n, const edp_batch_item* items, BatchLayout* B) {
             k.chunk = e.la.chunk;
             k.ring = e.la.ring;
             k.fuse = e.la.fuse;
+            k.quad = it.problem.prior == EDP_PRIOR_SQUARED;
             k.iterations = it.problem.iterations;
             B->classes.push_back(k);
         }
@@ -610,8 +623,10 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     a.qx = prob->qx;
     a.qy = prob->qy;
     a.lam = prob->lambda;
-    a.clipd = prob->lambda * prob->trunc;
+    a.clipd = (int32_t)clip_of(prob);
     a.joint = prob->trunc_mode == EDP_TRUNC_JOINT;
+    a.trunc = prob->trunc;
+    a.quad = prob->prior == EDP_PRIOR_SQUARED;
     a.ibits = ibits_of(prob->qx * prob->qy);
     const int rows_per_block = (64 / group_of(tile)) * 4;
     const int grid = (prob->height + rows_per_block - 1) / rows_per_block;
@@ -680,6 +695,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
+    c.quad = prob->prior == EDP_PRIOR_SQUARED;
     c.one = make_desc(prob, la, L.inst, ws, flags, ws + L.hand, d_cost, d_labels, nullptr);
     c.descs = nullptr;
     c.ndesc = 1;
@@ -791,6 +807,7 @@ edp_status edp_batch_solve(const edp_batch_plan* plan, void* stream) {
         c.ring = k.ring;
         c.fuse = k.fuse;
         c.iterations = k.iterations;
+        c.quad = k.quad;
         c.descs = plan->descs + k.first_desc;
         c.ndesc = (int)k.members.size();
         c.tickets_per_pass = k.tickets_per_pass;
@@ -873,6 +890,7 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
+    c.quad = prob->prior == EDP_PRIOR_SQUARED;
     c.one = make_desc(&f, la, E.inst, ws, flags, ws + E.hand, cw, d_labels, nullptr);
     c.one.aux = shifts;
     c.one.centers = d_centers;

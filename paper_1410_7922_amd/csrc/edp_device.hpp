@@ -1,5 +1,6 @@
-// Device building blocks for gfx950: lane tiles, cross-lane exchange and the
-// linear recursive minimum search (Mozerov, arXiv 1410.7922, Sec. 3.2).
+// Device building blocks for gfx950: lane tiles, cross-lane exchange, the
+// linear recursive minimum search (Mozerov, arXiv 1410.7922, Sec. 3.2) and the
+// general one for the truncated squared prior (Sec. 3.1).
 //
 // A "lane tile" maps the labels of one DSI vertex onto a group of G = PX*PY
 // lanes of a 64-wide wavefront.  Lane (px, py) of a group holds the KY x KX
@@ -343,30 +344,30 @@ __device__ __forceinline__ int32_t scan_down(int32_t v, int32_t pos, int32_t lan
     }
 }
 
-// Value at position pos - 1 of the line, IDENT at position 0.
-template <int NL, int STEP>
+// Value at position pos - 1 of the line, FILL at position 0.
+template <int NL, int STEP, int32_t FILL = IDENT>
 __device__ __forceinline__ int32_t carry_up(int32_t v, int32_t pos, int32_t lane) {
     if constexpr (NL * STEP == 16) {
-        return __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shr(STEP), 0xF, 0xF, false);
+        return __builtin_amdgcn_update_dpp(FILL, v, dpp_row_shr(STEP), 0xF, 0xF, false);
     } else if constexpr (NL * STEP < 16) {
-        const int32_t r = __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shr(STEP), 0xF, 0xF, false);
-        return pos == 0 ? IDENT : r;
+        const int32_t r = __builtin_amdgcn_update_dpp(FILL, v, dpp_row_shr(STEP), 0xF, 0xF, false);
+        return pos == 0 ? FILL : r;
     } else {
         const int32_t r = lanes_up<STEP>(v, lane);
-        return pos == 0 ? IDENT : r;
+        return pos == 0 ? FILL : r;
     }
 }
-// Value at position pos + 1 of the line, IDENT at position NL - 1.
-template <int NL, int STEP>
+// Value at position pos + 1 of the line, FILL at position NL - 1.
+template <int NL, int STEP, int32_t FILL = IDENT>
 __device__ __forceinline__ int32_t carry_down(int32_t v, int32_t pos, int32_t lane) {
     if constexpr (NL * STEP == 16) {
-        return __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shl(STEP), 0xF, 0xF, false);
+        return __builtin_amdgcn_update_dpp(FILL, v, dpp_row_shl(STEP), 0xF, 0xF, false);
     } else if constexpr (NL * STEP < 16) {
-        const int32_t r = __builtin_amdgcn_update_dpp(IDENT, v, dpp_row_shl(STEP), 0xF, 0xF, false);
-        return pos == NL - 1 ? IDENT : r;
+        const int32_t r = __builtin_amdgcn_update_dpp(FILL, v, dpp_row_shl(STEP), 0xF, 0xF, false);
+        return pos == NL - 1 ? FILL : r;
     } else {
         const int32_t r = lanes_down<STEP>(v, lane);
-        return pos == NL - 1 ? IDENT : r;
+        return pos == NL - 1 ? FILL : r;
     }
 }
 
@@ -408,6 +409,56 @@ __device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t (&lv
     const int32_t cap = clip ? m + clipd : IDENT;
 #pragma unroll
     for (int k = 0; k < K; ++k) val[k] = imin3(p[k] + lv[k], q[k] - lv[k], cap);
+    return m;
+}
+
+// ---- general RMS on one dimension (truncated squared prior) -------------------
+// For every line along the dimension: the window minimum of eq. M_decmp1 with
+// f(a) = a^2 and the penalty inside the minimum,
+//   W(v) = min_{|u| < g} h(v - u) + lam u^2,
+// then the clip min(W, line_min + clipd) when clip is set (clipd = lam g^2).
+// The window is walked one label at a time: after u steps up[k] holds the
+// value u labels below label k of the lane and dn[k] the value u labels above
+// it (PADV past the ends of the line), so each step moves one value per
+// direction between lanes and costs two additions and a three-way minimum per
+// label.  nw = min(g, labels on the line) - 1 steps; lam u^2 is accumulated as
+// the sum of lam (2i - 1).  On packed keys lam is the penalty unit shifted
+// above the index bits.  Returns min h of the line.
+template <int NL, int K, int STEP>
+__device__ __forceinline__ int32_t quad_line(int32_t (&val)[K], const int32_t lam, const int32_t nw,
+                                             const int32_t clipd, const bool clip, const int32_t pos,
+                                             const int32_t lane) {
+    int32_t up[K], dn[K];
+    int32_t m = val[0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        up[k] = val[k];
+        dn[k] = val[k];
+        m = imin(m, val[k]);
+    }
+    if constexpr (NL > 1) m = line_min<NL, STEP>(m, lane);
+    int32_t pen = 0, inc = lam;
+    for (int32_t u = 0; u < nw; ++u) {
+        pen += inc;
+        inc += 2 * lam;
+        int32_t cu = PADV, cd = PADV;
+        if constexpr (NL > 1) {
+            cu = carry_up<NL, STEP, PADV>(up[K - 1], pos, lane);
+            cd = carry_down<NL, STEP, PADV>(dn[0], pos, lane);
+        }
+#pragma unroll
+        for (int k = K - 1; k > 0; --k) up[k] = up[k - 1];
+        up[0] = cu;
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) dn[k] = dn[k + 1];
+        dn[K - 1] = cd;
+#pragma unroll
+        for (int k = 0; k < K; ++k) val[k] = imin3(val[k], up[k] + pen, dn[k] + pen);
+    }
+    if (clip) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) val[k] = imin(val[k], m + clipd);
+    }
     return m;
 }
 
@@ -525,6 +576,48 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
             l1_line<T::PY, T::KY, T::PX>(col, li.ly, clipd, !joint, py, lane);
+#pragma unroll
+            for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
+        }
+        if (joint) {
+#pragma unroll
+            for (int ky = 0; ky < T::KY; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], gmin + clipd);
+        }
+        return gmin;
+    }
+}
+
+// The minimum search operator M for the truncated squared prior, computed by the
+// general RMS of Sec. 3.1: one window operator per label dimension (eq.
+// M_decmp1), clipped per line (per-dimension truncation) or once at
+// (min h + clipd) (joint truncation, eq. M_decmp).  nwx, nwy: window steps
+// along x and y (min(g, qx) - 1, min(g, qy) - 1).  Same contract as min_search.
+template <class T>
+__device__ __forceinline__ int32_t min_search_quad(int32_t (&h)[T::KY][T::KX], const int32_t lam,
+                                                   const int32_t nwx, const int32_t nwy, const int32_t clipd,
+                                                   const bool joint, const int32_t lane) {
+    const int32_t l = lane % T::G;
+    const int32_t px = l % T::PX, py = l / T::PX;
+    constexpr bool one_dim = T::PY * T::KY == 1;
+    int32_t rowmin = PADV;
+#pragma unroll
+    for (int ky = 0; ky < T::KY; ++ky) {
+        const int32_t lm = quad_line<T::PX, T::KX, 1>(h[ky], lam, nwx, clipd, !joint || one_dim, px, lane);
+        rowmin = imin(rowmin, lm);
+    }
+    if constexpr (one_dim) {
+        return rowmin;
+    } else {
+        int32_t gmin = rowmin;
+        if constexpr (T::PY > 1) gmin = line_min<T::PY, T::PX>(gmin, lane);
+#pragma unroll
+        for (int kx = 0; kx < T::KX; ++kx) {
+            int32_t col[T::KY];
+#pragma unroll
+            for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
+            quad_line<T::PY, T::KY, T::PX>(col, lam, nwy, clipd, !joint, py, lane);
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
         }

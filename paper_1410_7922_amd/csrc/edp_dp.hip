@@ -1,10 +1,11 @@
-// Independent-scanline DP with the linear RMS (Mozerov, arXiv 1410.7922,
-// Sec. 2 eq. One_d / eq. base, Sec. 3.2, Sec. 4.1) for gfx950.
+// Independent-scanline DP with the linear RMS or, for the truncated squared
+// prior, the general RMS (Mozerov, arXiv 1410.7922, Sec. 2 eq. One_d / eq. base,
+// Sec. 3.1, Sec. 3.2, Sec. 4.1) for gfx950.
 //
 // Forward sweep.  One lane group (G lanes) per scanline, 64/G scanlines per
 // wavefront, the label vector in registers.  Each step computes
 //   S(x) = C(x) + M(S(x-1))
-// on packed keys key = S * 2^ib + q: every operation of the linear RMS is a
+// on packed keys key = S * 2^ib + q: every operation of either RMS is a
 // min or an addition of a multiple of 2^ib, so running it on keys yields
 // M(S)(v) in the high bits and, in the low bits, the smallest label v'
 // attaining it -- the optimal choice index of Sec. 4.1, with no second
@@ -27,7 +28,7 @@ __device__ __forceinline__ int32_t pack(int32_t v, int32_t ib, int32_t q) {
     return (int32_t)(((uint32_t)v << ib) | (uint32_t)q);
 }
 
-template <class T, class CK, class PT, int PF>
+template <class T, class CK, class PT, int PF, bool QUAD>
 __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int RPW = 64 / G;
@@ -44,6 +45,8 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     const int32_t mask = (1 << ib) - 1;
     const int32_t lamk = a.lam << ib, clipk = a.clipd << ib;
     const LineIndex<T> li(lamk, lane);
+    // window steps of the general RMS along x and y (truncated squared prior)
+    const int32_t nwx = min(a.trunc, a.qx) - 1, nwy = min(a.trunc, a.qy) - 1;
     // buffer resources (see the scan kernel): lanes without an operand use offset OOB
     const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(a.cost, W * H * Q * CB);
     const __amdgpu_buffer_rsrc_t rs_p = make_rsrc(a.ptr, W * H * QT * (int32_t)sizeof(PT));
@@ -96,7 +99,8 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     auto step = [&](auto tail, const int u, const int32_t x) {
         constexpr bool TAIL = decltype(tail)::value;
         const bool live = !TAIL || x < W;
-        const int32_t g = min_search<T>(key, li, clipk, a.joint != 0, lane);
+        const int32_t g = QUAD ? min_search_quad<T>(key, lamk, nwx, nwy, clipk, a.joint != 0, lane)
+                               : min_search<T>(key, li, clipk, a.joint != 0, lane);
         const int32_t norm = g >> ib;
         if constexpr (sizeof(PT) == 1 && E % 4 == 0) {
             // four choice indexes per dword: low bytes gathered by byte permutes, then masked
@@ -258,12 +262,18 @@ __global__ __launch_bounds__(64) void dp_backtrack_kernel(const BtArgs a) {
 template <class T>
 constexpr int dp_pf() { return T::E <= 4 ? 8 : 2; }
 
+template <class T, class CK, bool QUAD>
+static void run_fwd_prior(const DpArgs& a, int grid, hipStream_t s) {
+    if constexpr (T::QT <= 256)
+        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint8_t, dp_pf<T>(), QUAD>), dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint16_t, dp_pf<T>(), QUAD>), dim3(grid), dim3(256), 0, s, a);
+}
+
 template <class T, class CK>
 static hipError_t run_fwd(const DpArgs& a, int grid, hipStream_t s) {
-    if (T::QT <= 256)
-        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint8_t, dp_pf<T>()>), dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint16_t, dp_pf<T>()>), dim3(grid), dim3(256), 0, s, a);
+    if (a.quad) run_fwd_prior<T, CK, true>(a, grid, s);
+    else run_fwd_prior<T, CK, false>(a, grid, s);
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ struct InstDesc {
     int32_t win, qx_full;         // label-window solve: window side, labels along x of the full space
     int32_t W, H, qx, qy;
     int32_t lam, clipd, joint, trunc;
+    int32_t quad;                 // 1: truncated squared prior (clipd = lam trunc^2), 0: truncated linear
     int32_t nbands, nsuper;       // wavefront bands, workgroup bands
     int32_t first_ticket;         // first workgroup band of this instance in its launch
     int32_t first_block;          // first marginal block of this instance
@@ -141,7 +142,8 @@ struct DpArgs {
     int32_t* row_label;      // [H] label at x = W-1
     int64_t* row_energy;     // [H]
     int32_t W, H, qx, qy;
-    int32_t lam, clipd, joint;
+    int32_t lam, clipd, joint, trunc;
+    int32_t quad;            // truncated squared prior (clipd = lam trunc^2)
     int32_t ibits;           // bits of the label index packed under the value
 };
 
@@ -160,6 +162,7 @@ struct EnergyArgs {
     unsigned long long* invalid;
     int32_t W, H, qx, qy;
     int32_t lam, trunc, joint, grid4;
+    int32_t quad;            // truncated squared prior
 };
 
 // Energies of every instance of a batch (4-connected): block b works on rows of
@@ -174,14 +177,15 @@ struct BatchEnergyArgs {
 // The scan kernel takes a cost kind instead: 1 int16, 2 int32, 3 int16 read in
 // 4-byte aligned pairs (needs an even KX, an even label count, and qx even
 // unless qy == 1).
-hipError_t launch_edp_pass(int tile, int kind, int split, const PassArgs& a, int grid, int waves,
+// quad: the truncated squared prior (general RMS), else the truncated linear prior
+hipError_t launch_edp_pass(int tile, int kind, int split, bool quad, const PassArgs& a, int grid, int waves,
                            hipStream_t s);
 hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
 hipError_t launch_edp_aggregate_win(const AggArgs& a, int grid, hipStream_t s);
 // label-window solve: compact 8 x 8 frame costs (big outside the window) and frame shifts
 hipError_t launch_win_prep(const int32_t* cost, const int32_t* centers, int32_t W, int32_t H, int32_t qx, int32_t qy,
                            int32_t win, int32_t big, int32_t* cw, uint32_t* shifts, hipStream_t s);
-hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s);
+hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s);   // a.quad selects the prior
 hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
 hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);
 hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s);
@@ -213,7 +217,7 @@ hipError_t launch_targets(const int32_t* labels, int32_t W, int32_t H, int32_t q
 hipError_t launch_recenter(const int32_t* labels, int64_t n, int32_t qx, int32_t qy, int32_t win, int32_t* centers,
                            hipStream_t s);
 
-int pass_capacity(int tile, int kind, int split, int waves, size_t lds_bytes);
+int pass_capacity(int tile, int kind, int split, bool quad, int waves, size_t lds_bytes);
 // LDS bytes of the pass kernel for a tile, wavefronts per workgroup and ring slots.
 size_t pass_lds_bytes(int qt, int waves, int ring);
 

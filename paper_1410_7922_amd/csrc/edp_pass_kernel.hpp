@@ -89,7 +89,7 @@ __device__ __forceinline__ void tag_put(unsigned long long* p, unsigned long lon
 // empties the ring of the last active wavefront into memory and publishes progress once its
 // stores have completed.  The compute wavefronts never touch another workgroup's data, so
 // they never wait for memory operations other than their own prefetched loads.
-template <class T, class CK, int SPLIT, int PF, bool WIN = false>
+template <class T, class CK, int SPLIT, int PF, bool WIN = false, bool QUAD = false>
 __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const PassArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int CL = SPLIT * G;                  // lanes per vertex
@@ -353,6 +353,8 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             const int32_t band = super * NW + wave;
             const bool joint = d.joint != 0;
             const LineIndex<T> li(d.lam, lane);
+            // window steps of the general RMS along x and y (truncated squared prior)
+            const int32_t nwx = min(d.trunc, d.qx) - 1, nwy = min(d.trunc, d.qy) - 1;
             const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(d.cost, W * H * Q * CB);
             int32_t* const t_a = ka ? d.t[1] : d.t[0];
             int32_t* const t_ma = ka ? d.t[0] : d.t[1];
@@ -518,6 +520,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                     const int32_t dxb = (int32_t)(int8_t)(cb & 0xFF), dyb = (int32_t)(int8_t)((cb >> 8) & 0xFF);
                     min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
                     min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
+                } else if constexpr (QUAD) {
+                    min_search_quad<T>(h, d.lam, nwx, nwy, d.clipd, joint, lane);
+                    if constexpr (SPLIT == 1) min_search_quad<T>(h2, d.lam, nwx, nwy, d.clipd, joint, lane);
                 } else {
                     min_search<T>(h, li, d.clipd, joint, lane);
                     if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
@@ -672,10 +677,11 @@ constexpr int pass_pf() { return T::E <= 4 ? 8 : (T::E <= 8 ? 4 : 2); }
 // the window solve adds a shifted-read area of 2 x 64 x 2 ints per wavefront
 inline size_t win_lds_bytes(int waves) { return (size_t)waves * 2 * 64 * 2 * 4; }
 
-template <class T, class CK, int SPLIT>
+template <class T, class CK, int SPLIT, bool QUAD>
 static hipError_t run_pass(const PassArgs& a, int grid, int waves, hipStream_t s) {
     const size_t lds = pass_lds_bytes(T::QT, waves, a.ring);
-    hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>), dim3(grid), dim3(64 * (waves + 2)), lds, s, a);
+    hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>(), false, QUAD>), dim3(grid), dim3(64 * (waves + 2)),
+                       lds, s, a);
     return hipGetLastError();
 }
 
@@ -687,52 +693,52 @@ static hipError_t run_agg(const AggArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class T, class CK, int SPLIT>
+template <class T, class CK, int SPLIT, bool QUAD>
 static int pass_occupancy(int waves, size_t lds) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CK, SPLIT, pass_pf<T>()>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CK, SPLIT, pass_pf<T>(), false, QUAD>,
                                                      64 * (waves + 2), lds) != hipSuccess)
         blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
 
 // SPLIT = 2 needs both halves of a vertex in one wavefront.
-template <class T, class CK>
+template <class T, class CK, bool QUAD>
 static hipError_t dispatch_pass(int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
     if (split == 2) {
-        if constexpr (2 * T::G <= 64) return run_pass<T, CK, 2>(a, grid, waves, s);
+        if constexpr (2 * T::G <= 64) return run_pass<T, CK, 2, QUAD>(a, grid, waves, s);
         return hipErrorInvalidValue;
     }
-    return run_pass<T, CK, 1>(a, grid, waves, s);
+    return run_pass<T, CK, 1, QUAD>(a, grid, waves, s);
 }
 
-template <class T, class CK>
+template <class T, class CK, bool QUAD>
 static int dispatch_occupancy(int split, int waves, size_t lds) {
     if (split == 2) {
-        if constexpr (2 * T::G <= 64) return pass_occupancy<T, CK, 2>(waves, lds);
+        if constexpr (2 * T::G <= 64) return pass_occupancy<T, CK, 2, QUAD>(waves, lds);
         return 1;
     }
-    return pass_occupancy<T, CK, 1>(waves, lds);
+    return pass_occupancy<T, CK, 1, QUAD>(waves, lds);
 }
 
 // cost kind: 1 int16 (element loads), 2 int32, 3 int16 in aligned pairs
-template <class T>
+template <class T, bool QUAD>
 static hipError_t dispatch_kind(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
-    if (kind == 1) return dispatch_pass<T, int16_t>(split, a, grid, waves, s);
+    if (kind == 1) return dispatch_pass<T, int16_t, QUAD>(split, a, grid, waves, s);
     if (kind == 3) {
-        if constexpr (T::KX % 2 == 0) return dispatch_pass<T, Pair16>(split, a, grid, waves, s);
+        if constexpr (T::KX % 2 == 0) return dispatch_pass<T, Pair16, QUAD>(split, a, grid, waves, s);
         return hipErrorInvalidValue;
     }
-    return dispatch_pass<T, int32_t>(split, a, grid, waves, s);
+    return dispatch_pass<T, int32_t, QUAD>(split, a, grid, waves, s);
 }
-template <class T>
+template <class T, bool QUAD>
 static int occupancy_kind(int kind, int split, int waves, size_t lds) {
-    if (kind == 1) return dispatch_occupancy<T, int16_t>(split, waves, lds);
+    if (kind == 1) return dispatch_occupancy<T, int16_t, QUAD>(split, waves, lds);
     if (kind == 3) {
-        if constexpr (T::KX % 2 == 0) return dispatch_occupancy<T, Pair16>(split, waves, lds);
+        if constexpr (T::KX % 2 == 0) return dispatch_occupancy<T, Pair16, QUAD>(split, waves, lds);
         return 1;
     }
-    return dispatch_occupancy<T, int32_t>(split, waves, lds);
+    return dispatch_occupancy<T, int32_t, QUAD>(split, waves, lds);
 }
 
 // Per-tile entry points.  Each is instantiated explicitly in one of the edp_pass_t*.hip
@@ -743,13 +749,14 @@ template <int ID> struct TileOf;
 EDP_TILE_LIST(EDP_TILE_OF)
 #undef EDP_TILE_OF
 
-template <int ID>
+// QUAD: the truncated squared prior (general RMS); otherwise the truncated linear one
+template <int ID, bool QUAD>
 hipError_t pass_tile(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
-    return dispatch_kind<typename TileOf<ID>::type>(kind, split, a, grid, waves, s);
+    return dispatch_kind<typename TileOf<ID>::type, QUAD>(kind, split, a, grid, waves, s);
 }
-template <int ID>
+template <int ID, bool QUAD>
 int occupancy_tile(int kind, int split, int waves, size_t lds) {
-    return occupancy_kind<typename TileOf<ID>::type>(kind, split, waves, lds);
+    return occupancy_kind<typename TileOf<ID>::type, QUAD>(kind, split, waves, lds);
 }
 template <int ID>
 hipError_t aggregate_tile(int dtype, const AggArgs& a, int grid, hipStream_t s) {
@@ -761,8 +768,12 @@ hipError_t aggregate_tile(int dtype, const AggArgs& a, int grid, hipStream_t s) 
 using WinTile = TileOf<WIN_TILE>::type;
 
 #define EDP_INSTANTIATE_TILE(id)                                                                         \
-    template hipError_t pass_tile<id>(int, int, const PassArgs&, int, int, hipStream_t);                  \
-    template int occupancy_tile<id>(int, int, int, size_t);                                              \
+    template hipError_t pass_tile<id, false>(int, int, const PassArgs&, int, int, hipStream_t);           \
+    template int occupancy_tile<id, false>(int, int, int, size_t);                                       \
     template hipError_t aggregate_tile<id>(int, const AggArgs&, int, hipStream_t);
+// the scan kernels of a tile for the truncated squared prior
+#define EDP_INSTANTIATE_TILE_QUAD(id)                                                                    \
+    template hipError_t pass_tile<id, true>(int, int, const PassArgs&, int, int, hipStream_t);            \
+    template int occupancy_tile<id, true>(int, int, int, size_t);
 
 }  // namespace edp

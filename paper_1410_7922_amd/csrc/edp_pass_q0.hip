@@ -1,0 +1,12 @@
+// Scan kernels of tiles 0, 1, 2, 3 for the truncated squared prior (instantiated here,
+// dispatched from edp_pass.hip).
+#include "edp_pass_kernel.hpp"
+
+namespace edp {
+
+EDP_INSTANTIATE_TILE_QUAD(0)
+EDP_INSTANTIATE_TILE_QUAD(1)
+EDP_INSTANTIATE_TILE_QUAD(2)
+EDP_INSTANTIATE_TILE_QUAD(3)
+
+}  // namespace edp

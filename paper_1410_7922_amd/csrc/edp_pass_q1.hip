@@ -1,0 +1,12 @@
+// Scan kernels of tiles 4, 5, 6, 7 for the truncated squared prior (instantiated here,
+// dispatched from edp_pass.hip).
+#include "edp_pass_kernel.hpp"
+
+namespace edp {
+
+EDP_INSTANTIATE_TILE_QUAD(4)
+EDP_INSTANTIATE_TILE_QUAD(5)
+EDP_INSTANTIATE_TILE_QUAD(6)
+EDP_INSTANTIATE_TILE_QUAD(7)
+
+}  // namespace edp

@@ -35,7 +35,7 @@ def test_status_strings():
 
 def _prob(**kw):
     d = dict(width=384, height=288, qx=32, qy=1, dtype=1, trunc_mode=0, lam=20, trunc=2, iterations=1,
-             cost_bound=50)
+             cost_bound=50, prior=0)
     d.update(kw)
     return B.Problem(*[d[f] for f, _ in B.Problem._fields_])
 
@@ -49,7 +49,8 @@ def _ws(prob, op, tile=-1):
 
 @pytest.mark.parametrize("field,value", [("width", 0), ("height", -1), ("qx", 0), ("qy", 0), ("dtype", 3),
                                          ("trunc_mode", 2), ("lam", -1), ("lam", 70000), ("trunc", 0),
-                                         ("iterations", 0), ("cost_bound", -5), ("qx", 4097)])
+                                         ("iterations", 0), ("cost_bound", -5), ("qx", 4097), ("prior", 2),
+                                         ("prior", -1)])
 def test_invalid_problems_rejected(field, value):
     st, _ = _ws(_prob(**{field: value}), B.OP_EDP)
     assert st == -1
@@ -62,6 +63,21 @@ def test_int32_costs_need_a_bound_and_range_guard():
     assert _ws(_prob(dtype=2, cost_bound=10**6), B.OP_EDP)[0] == -2
     # the DP packs the label index under the value: a huge lambda trips its guard
     assert _ws(_prob(lam=60000, trunc=4000, qx=64), B.OP_DP)[0] == -2
+
+
+def test_squared_prior_range_guard_and_window_solve():
+    """The squared prior's clip lambda T^2 enters both guards; the label-window solve is linear only."""
+    assert _ws(_prob(prior=1, lam=5, trunc=3), B.OP_EDP)[0] == 0
+    assert _ws(_prob(prior=1, lam=5, trunc=3), B.OP_DP)[0] == 0
+    # lambda T = 4000 passes with the linear prior, lambda T^2 = 800000 does not
+    assert _ws(_prob(prior=0, lam=20, trunc=200), B.OP_EDP)[0] == 0
+    assert _ws(_prob(prior=1, lam=20, trunc=200), B.OP_EDP)[0] == -2
+    assert _ws(_prob(prior=1, lam=65535, trunc=4096), B.OP_DP)[0] == -2
+    n = ctypes.c_size_t(0)
+    p = _prob(prior=1, dtype=2, qx=15, qy=15, lam=15, trunc=3, cost_bound=2500)
+    assert B.load().edp_window_workspace_size(ctypes.byref(p), 7, None, ctypes.byref(n)) == -5
+    p.prior = 0
+    assert B.load().edp_window_workspace_size(ctypes.byref(p), 7, None, ctypes.byref(n)) == 0
 
 
 def test_tiles_and_workspace_sizes():
