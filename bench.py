@@ -112,7 +112,7 @@ def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1, fuse=0
     nlaunch = (4 if fuse == 1 else 2) * iterations     # scan launches per solve
     ev = HipEvents(2 * nlaunch * steps)
     kw = dict(mode=prob.mode, iterations=iterations, cost_bound=bound, tile=tile, chunk=chunk, ws=ws,
-              labels=labels, energy=energy, fuse=fuse)
+              labels=labels, energy=energy, fuse=fuse, prior=prob.prior)
     for _ in range(warmup):
         edp.solve(cost, prob.qx, prob.qy, prob.lam, prob.trunc, **kw)
     torch.cuda.synchronize()
@@ -199,10 +199,12 @@ def bench_batch(edp, torch, steps, warmup):
             "graph_ms_per_solve": best["graph_ms_per_solve"]}
 
 
-def bench_dp(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0):
+def bench_dp(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0, prior=0):
     """Scanline DP sweep on uniform int16 costs in [0, 50]: 8192 independent scanlines of 1024
     columns and 64 labels (16 stereo frames of 1024 x 512 with 64 disparities), a bandwidth
-    workload of 1 GiB of costs."""
+    workload of 1 GiB of costs.  prior 0: truncated linear, lambda 20, T 2; prior 1: truncated
+    squared, lambda 5, T 3."""
+    lam, trunc = (20, 2) if prior == 0 else (5, 3)
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
@@ -210,12 +212,12 @@ def bench_dp(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0):
     ws = edp.Workspace()
     ev = HipEvents(4 * steps)
     for _ in range(warmup):
-        edp.dp_scanline(cost, q, 1, 20, 2, cost_bound=51, ws=ws)
+        edp.dp_scanline(cost, q, 1, lam, trunc, cost_bound=51, ws=ws, prior=prior)
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for k in range(steps):
-        edp.dp_scanline(cost, q, 1, 20, 2, cost_bound=51, ws=ws, events=ev.view(4 * k, 4))
+        edp.dp_scanline(cost, q, 1, lam, trunc, cost_bound=51, ws=ws, events=ev.view(4 * k, 4), prior=prior)
     stop.record()
     torch.cuda.synchronize()
     total = start.elapsed_time(stop) / steps
@@ -224,7 +226,8 @@ def bench_dp(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0):
     ev.close()
     pl = rows * cols * q
     fwd_bytes = pl * (2 + 1)          # int16 cost read + one-byte choice index written
-    return {"workload": f"dp_sweep{cols}x{rows}q{q}_i16", "pixel_labels_per_s": pl / (total / 1e3),
+    return {"workload": f"dp_sweep{cols}x{rows}q{q}_i16" + ("_sq" if prior else ""),
+            "pixel_labels_per_s": pl / (total / 1e3),
             "ms_per_step": total, "forward_ms": fwd, "backtrack_ms": bt,
             "forward_GBps": fwd_bytes / (fwd / 1e3) / 1e9,
             "forward_frac_of_hbm": fwd_bytes / (fwd / 1e3) / 1e9 / HBM_PEAK_GBS}
@@ -430,6 +433,16 @@ def main():
         del mr
         log("scanline DP sweep 8192 rows x 1024 columns, Q=64 int16")
         extra["dp_sweep"] = bench_dp(edp, torch, max(3, args.steps // 4), 1)
+        # the truncated squared prior (general RMS, window 2T - 1 = 5 per label)
+        for name in ("stereo384x288_sq", "motion320x240_sq"):
+            log(f"{name} (truncated squared prior, lambda 5, T 3)")
+            sp = synth.workload(name)
+            sr = bench_edp(edp, torch, sp, max(3, args.steps // 4), 1, -1, args.chunk, fuse=args.fuse)
+            spl = sp.cost.shape[0] * sp.cost.shape[1] * sp.cost.shape[2]
+            extra[name] = {"pixel_labels_per_s": spl / (sr["ms_per_step"] / 1e3), "ms_per_step": sr["ms_per_step"],
+                           "energy": sr["energy"], "mean_launch_ms": np.array(sr["launch_ms"]).mean(axis=0).tolist()}
+            del sr
+        extra["dp_sweep_sq"] = bench_dp(edp, torch, max(3, args.steps // 4), 1, prior=1)
     if not args.no_batch:
         log("batch of 64 uneven instances (hipGraph replay)")
         extra["batch64"] = bench_batch(edp, torch, max(3, args.steps // 4), 1)

@@ -73,6 +73,13 @@ int64_t clip_of(const edp_problem* p) {
     return (int64_t)p->lambda * (p->prior == EDP_PRIOR_SQUARED ? t * t : t);
 }
 
+// The minimum search kind of the scan and DP kernels for a problem (MS_*).
+int ms_of(const edp_problem* p) {
+    if (p->prior != EDP_PRIOR_SQUARED) return MS_LINEAR;
+    const int nw = std::max(std::min(p->trunc, p->qx), std::min(p->trunc, p->qy)) - 1;
+    return nw <= 2 ? MS_SQ_SHORT : MS_SQ_WALK;
+}
+
 int64_t vmax_of(const edp_problem* p) {
     const int64_t dims = (p->trunc_mode == EDP_TRUNC_PER_DIM && p->qy > 1) ? 2 : 1;
     return clip_of(p) * dims;
@@ -281,7 +288,7 @@ InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, 
 // Everything one launch shape needs to run its scans and the marginal.
 struct ClassRun {
     int tile, kind, dtype, split, waves, chunk, ring, fuse, iterations;
-    bool quad;                 // truncated squared prior
+    int ms;                    // minimum search kind MS_*
     InstDesc one;              // single instance (descs null)
     const InstDesc* descs;     // device descriptor slice of a batch class
     int ndesc;
@@ -295,7 +302,7 @@ int agg_cells_per_block(int tile) { return (64 / group_of(tile)) * 4; }
 
 int scan_grid(const ClassRun& c) {
     const int cap =
-        pass_capacity(c.tile, c.kind, c.split, c.quad, c.waves, pass_lds_bytes(qt_of(c.tile), c.waves, c.ring));
+        pass_capacity(c.tile, c.kind, c.split, c.ms, c.waves, pass_lds_bytes(qt_of(c.tile), c.waves, c.ring));
     const int total = c.fuse * c.tickets_per_pass;
     return total < cap ? total : cap;
 }
@@ -334,7 +341,7 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
             a.ticket = c.tickets + launch;
             const bool timed = ev && ev->events && 2 * launch + 1 < ev->n_events;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch], s) != hipSuccess) return EDP_E_HIP;
-            if (launch_edp_pass(c.tile, c.kind, c.split, c.quad, a, grid, c.waves, s) != hipSuccess) return EDP_E_HIP;
+            if (launch_edp_pass(c.tile, c.kind, c.split, c.ms, a, grid, c.waves, s) != hipSuccess) return EDP_E_HIP;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch + 1], s) != hipSuccess)
                 return EDP_E_HIP;
         }
@@ -442,7 +449,7 @@ struct BatchEntry {
 
 struct BatchClassPlan {
     int tile, kind, dtype, split, waves, chunk, ring, fuse, iterations;
-    bool quad;
+    int ms;
     std::vector<int> members;   // items, longest first
     int first_desc;
     size_t tickets_word, error_word;
@@ -477,7 +484,7 @@ edp_status plan_batch(int32_t n, const edp_batch_item* items, BatchLayout* B) {
             const BatchClassPlan& k = B->classes[c];
             if (k.tile == e.la.tile && k.kind == e.kind && k.split == e.la.split && k.waves == e.la.waves &&
                 k.chunk == e.la.chunk && k.ring == e.la.ring && k.fuse == e.la.fuse &&
-                k.iterations == it.problem.iterations && k.quad == (it.problem.prior == EDP_PRIOR_SQUARED))
+                k.iterations == it.problem.iterations && k.ms == ms_of(&it.problem))
                 break;
         }
         if (c == (int)B->classes.size()) {
@@ -490,7 +497,7 @@ edp_status plan_batch(int32_t n, const edp_batch_item* items, BatchLayout* B) {
             k.chunk = e.la.chunk;
             k.ring = e.la.ring;
             k.fuse = e.la.fuse;
-            k.quad = it.problem.prior == EDP_PRIOR_SQUARED;
+            k.ms = ms_of(&it.problem);
             k.iterations = it.problem.iterations;
             B->classes.push_back(k);
         }
@@ -626,7 +633,7 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     a.clipd = (int32_t)clip_of(prob);
     a.joint = prob->trunc_mode == EDP_TRUNC_JOINT;
     a.trunc = prob->trunc;
-    a.quad = prob->prior == EDP_PRIOR_SQUARED;
+    a.ms = ms_of(prob);
     a.ibits = ibits_of(prob->qx * prob->qy);
     const int rows_per_block = (64 / group_of(tile)) * 4;
     const int grid = (prob->height + rows_per_block - 1) / rows_per_block;
@@ -695,7 +702,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
-    c.quad = prob->prior == EDP_PRIOR_SQUARED;
+    c.ms = ms_of(prob);
     c.one = make_desc(prob, la, L.inst, ws, flags, ws + L.hand, d_cost, d_labels, nullptr);
     c.descs = nullptr;
     c.ndesc = 1;
@@ -807,7 +814,7 @@ edp_status edp_batch_solve(const edp_batch_plan* plan, void* stream) {
         c.ring = k.ring;
         c.fuse = k.fuse;
         c.iterations = k.iterations;
-        c.quad = k.quad;
+        c.ms = k.ms;
         c.descs = plan->descs + k.first_desc;
         c.ndesc = (int)k.members.size();
         c.tickets_per_pass = k.tickets_per_pass;
@@ -890,7 +897,7 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
-    c.quad = prob->prior == EDP_PRIOR_SQUARED;
+    c.ms = ms_of(prob);
     c.one = make_desc(&f, la, E.inst, ws, flags, ws + E.hand, cw, d_labels, nullptr);
     c.one.aux = shifts;
     c.one.centers = d_centers;

@@ -417,27 +417,87 @@ __device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t (&lv
 // f(a) = a^2 and the penalty inside the minimum,
 //   W(v) = min_{|u| < g} h(v - u) + lam u^2,
 // then the clip min(W, line_min + clipd) when clip is set (clipd = lam g^2).
-// The window is walked one label at a time: after u steps up[k] holds the
-// value u labels below label k of the lane and dn[k] the value u labels above
-// it (PADV past the ends of the line), so each step moves one value per
-// direction between lanes and costs two additions and a three-way minimum per
-// label.  nw = min(g, labels on the line) - 1 steps; lam u^2 is accumulated as
-// the sum of lam (2i - 1).  On packed keys lam is the penalty unit shifted
-// above the index bits.  Returns min h of the line.
+// A line of n labels takes nw = min(g, n) - 1 window steps on each side.  On
+// packed keys lam is the penalty unit shifted above the index bits.
+//
+// Two ways, chosen per kernel so that the step has no branch:
+//   short windows (nw <= 2, which covers g <= 3, the paper's setups): the values
+//     of the labels up to two positions below and above are fetched a whole
+//     lane at a time (one cross-lane move per register and lane hop, PADV past
+//     the ends of the line), so the moves are independent of each other, and
+//     each label takes two three-way minima; a step outside the window gets the
+//     penalty PEN_OFF, which no candidate survives;
+//   any window: the window is walked one label at a time: after u steps up[k]
+//     holds the value u labels below label k and dn[k] the value u labels above.
+
+// Penalty of a window step outside the window: above every real value, and PADV plus it
+// still fits in int32.
+constexpr int32_t PEN_OFF = 0x40000000;
+
+// Window steps and their penalties lam u^2 (u = 1, 2) along x and y.
+struct SqPen {
+    int32_t lam, nwx, nwy;
+    int32_t px[2], py[2];
+    __device__ __forceinline__ SqPen(const int32_t lam_, const int32_t g, const int32_t qx, const int32_t qy) {
+        lam = lam_;
+        nwx = min(g, qx) - 1;
+        nwy = min(g, qy) - 1;
+#pragma unroll
+        for (int u = 1; u <= 2; ++u) {
+            px[u - 1] = u <= nwx ? lam * (u * u) : PEN_OFF;
+            py[u - 1] = u <= nwy ? lam * (u * u) : PEN_OFF;
+        }
+    }
+};
+
+template <int NL, int K, int STEP, int NW>
+__device__ __forceinline__ void quad_window(int32_t (&val)[K], const int32_t (&pen)[NW], const int32_t pos,
+                                            const int32_t lane) {
+    constexpr int HOPS = (NW + K - 1) / K;
+    int32_t lo[HOPS + 1][K], hi[HOPS + 1][K];    // [h][k]: the label h lanes below / above label k
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        lo[0][k] = val[k];
+        hi[0][k] = val[k];
+    }
+#pragma unroll
+    for (int h = 1; h <= HOPS; ++h)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if constexpr (NL > 1) {
+                lo[h][k] = carry_up<NL, STEP, PADV>(lo[h - 1][k], pos, lane);
+                hi[h][k] = carry_down<NL, STEP, PADV>(hi[h - 1][k], pos, lane);
+            } else {
+                lo[h][k] = PADV;
+                hi[h][k] = PADV;
+            }
+        }
+    int32_t out[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int32_t o = val[k];
+#pragma unroll
+        for (int u = 1; u <= NW; ++u) {
+            const int jl = k - u, jh = k + u;           // lane-local label indexes
+            const int hl = jl >= 0 ? 0 : (K - 1 - jl) / K, hh = jh / K;
+            o = imin3(o, lo[hl][jl + hl * K] + pen[u - 1], hi[hh][jh - hh * K] + pen[u - 1]);
+        }
+        out[k] = o;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) val[k] = out[k];
+}
+
 template <int NL, int K, int STEP>
-__device__ __forceinline__ int32_t quad_line(int32_t (&val)[K], const int32_t lam, const int32_t nw,
-                                             const int32_t clipd, const bool clip, const int32_t pos,
-                                             const int32_t lane) {
+__device__ __forceinline__ void quad_walk(int32_t (&val)[K], const int32_t lam, const int32_t nw,
+                                          const int32_t pos, const int32_t lane) {
     int32_t up[K], dn[K];
-    int32_t m = val[0];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         up[k] = val[k];
         dn[k] = val[k];
-        m = imin(m, val[k]);
     }
-    if constexpr (NL > 1) m = line_min<NL, STEP>(m, lane);
-    int32_t pen = 0, inc = lam;
+    int32_t pen = 0, inc = lam;                      // lam u^2 as the sum of lam (2i - 1)
     for (int32_t u = 0; u < nw; ++u) {
         pen += inc;
         inc += 2 * lam;
@@ -455,6 +515,19 @@ __device__ __forceinline__ int32_t quad_line(int32_t (&val)[K], const int32_t la
 #pragma unroll
         for (int k = 0; k < K; ++k) val[k] = imin3(val[k], up[k] + pen, dn[k] + pen);
     }
+}
+
+// WALK false: nw <= 2 with the step penalties pen; WALK true: any nw.  Returns min h of the line.
+template <int NL, int K, int STEP, bool WALK>
+__device__ __forceinline__ int32_t quad_line(int32_t (&val)[K], const int32_t (&pen)[2], const int32_t lam,
+                                             const int32_t nw, const int32_t clipd, const bool clip,
+                                             const int32_t pos, const int32_t lane) {
+    int32_t m = val[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) m = imin(m, val[k]);
+    if constexpr (NL > 1) m = line_min<NL, STEP>(m, lane);
+    if constexpr (WALK) quad_walk<NL, K, STEP>(val, lam, nw, pos, lane);
+    else quad_window<NL, K, STEP, 2>(val, pen, pos, lane);
     if (clip) {
 #pragma unroll
         for (int k = 0; k < K; ++k) val[k] = imin(val[k], m + clipd);
@@ -592,19 +665,19 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
 // The minimum search operator M for the truncated squared prior, computed by the
 // general RMS of Sec. 3.1: one window operator per label dimension (eq.
 // M_decmp1), clipped per line (per-dimension truncation) or once at
-// (min h + clipd) (joint truncation, eq. M_decmp).  nwx, nwy: window steps
-// along x and y (min(g, qx) - 1, min(g, qy) - 1).  Same contract as min_search.
-template <class T>
-__device__ __forceinline__ int32_t min_search_quad(int32_t (&h)[T::KY][T::KX], const int32_t lam,
-                                                   const int32_t nwx, const int32_t nwy, const int32_t clipd,
-                                                   const bool joint, const int32_t lane) {
+// (min h + clipd) (joint truncation, eq. M_decmp).  WALK as for quad_line.
+// Same contract as min_search.
+template <class T, bool WALK>
+__device__ __forceinline__ int32_t min_search_quad(int32_t (&h)[T::KY][T::KX], const SqPen& sp,
+                                                   const int32_t clipd, const bool joint, const int32_t lane) {
     const int32_t l = lane % T::G;
     const int32_t px = l % T::PX, py = l / T::PX;
     constexpr bool one_dim = T::PY * T::KY == 1;
     int32_t rowmin = PADV;
 #pragma unroll
     for (int ky = 0; ky < T::KY; ++ky) {
-        const int32_t lm = quad_line<T::PX, T::KX, 1>(h[ky], lam, nwx, clipd, !joint || one_dim, px, lane);
+        const int32_t lm = quad_line<T::PX, T::KX, 1, WALK>(h[ky], sp.px, sp.lam, sp.nwx, clipd, !joint || one_dim,
+                                                             px, lane);
         rowmin = imin(rowmin, lm);
     }
     if constexpr (one_dim) {
@@ -617,7 +690,7 @@ __device__ __forceinline__ int32_t min_search_quad(int32_t (&h)[T::KY][T::KX], c
             int32_t col[T::KY];
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
-            quad_line<T::PY, T::KY, T::PX>(col, lam, nwy, clipd, !joint, py, lane);
+            quad_line<T::PY, T::KY, T::PX, WALK>(col, sp.py, sp.lam, sp.nwy, clipd, !joint, py, lane);
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
         }

@@ -28,7 +28,7 @@ __device__ __forceinline__ int32_t pack(int32_t v, int32_t ib, int32_t q) {
     return (int32_t)(((uint32_t)v << ib) | (uint32_t)q);
 }
 
-template <class T, class CK, class PT, int PF, bool QUAD>
+template <class T, class CK, class PT, int PF, int MS>
 __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int RPW = 64 / G;
@@ -45,8 +45,7 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     const int32_t mask = (1 << ib) - 1;
     const int32_t lamk = a.lam << ib, clipk = a.clipd << ib;
     const LineIndex<T> li(lamk, lane);
-    // window steps of the general RMS along x and y (truncated squared prior)
-    const int32_t nwx = min(a.trunc, a.qx) - 1, nwy = min(a.trunc, a.qy) - 1;
+    const SqPen sp(lamk, a.trunc, a.qx, a.qy);        // squared prior: window steps and penalties (keys)
     // buffer resources (see the scan kernel): lanes without an operand use offset OOB
     const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(a.cost, W * H * Q * CB);
     const __amdgpu_buffer_rsrc_t rs_p = make_rsrc(a.ptr, W * H * QT * (int32_t)sizeof(PT));
@@ -99,8 +98,9 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     auto step = [&](auto tail, const int u, const int32_t x) {
         constexpr bool TAIL = decltype(tail)::value;
         const bool live = !TAIL || x < W;
-        const int32_t g = QUAD ? min_search_quad<T>(key, lamk, nwx, nwy, clipk, a.joint != 0, lane)
-                               : min_search<T>(key, li, clipk, a.joint != 0, lane);
+        int32_t g;
+        if constexpr (MS == MS_LINEAR) g = min_search<T>(key, li, clipk, a.joint != 0, lane);
+        else g = min_search_quad<T, MS == MS_SQ_WALK>(key, sp, clipk, a.joint != 0, lane);
         const int32_t norm = g >> ib;
         if constexpr (sizeof(PT) == 1 && E % 4 == 0) {
             // four choice indexes per dword: low bytes gathered by byte permutes, then masked
@@ -262,18 +262,19 @@ __global__ __launch_bounds__(64) void dp_backtrack_kernel(const BtArgs a) {
 template <class T>
 constexpr int dp_pf() { return T::E <= 4 ? 8 : 2; }
 
-template <class T, class CK, bool QUAD>
-static void run_fwd_prior(const DpArgs& a, int grid, hipStream_t s) {
+template <class T, class CK, int MS>
+static void run_fwd_ms(const DpArgs& a, int grid, hipStream_t s) {
     if constexpr (T::QT <= 256)
-        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint8_t, dp_pf<T>(), QUAD>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint8_t, dp_pf<T>(), MS>), dim3(grid), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint16_t, dp_pf<T>(), QUAD>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((dp_forward_kernel<T, CK, uint16_t, dp_pf<T>(), MS>), dim3(grid), dim3(256), 0, s, a);
 }
 
 template <class T, class CK>
 static hipError_t run_fwd(const DpArgs& a, int grid, hipStream_t s) {
-    if (a.quad) run_fwd_prior<T, CK, true>(a, grid, s);
-    else run_fwd_prior<T, CK, false>(a, grid, s);
+    if (a.ms == MS_SQ_WALK) run_fwd_ms<T, CK, MS_SQ_WALK>(a, grid, s);
+    else if (a.ms == MS_SQ_SHORT) run_fwd_ms<T, CK, MS_SQ_SHORT>(a, grid, s);
+    else run_fwd_ms<T, CK, MS_LINEAR>(a, grid, s);
     return hipGetLastError();
 }
 

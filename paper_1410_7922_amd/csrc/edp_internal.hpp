@@ -35,6 +35,10 @@ constexpr int MAX_WAVES = 6;
 constexpr int WIN_TILE = 13;
 constexpr int KIND_WINDOW = 4;
 constexpr int WIN_FRAME = 8;
+// Minimum searches of the scan and DP kernels (one kernel each, so the step has no branch):
+constexpr int MS_LINEAR = 0;     // truncated linear prior: linear RMS
+constexpr int MS_SQ_SHORT = 1;   // truncated squared prior, windows of at most two steps per side
+constexpr int MS_SQ_WALK = 2;    // truncated squared prior, any window
 
 struct TileShape {
     int px, kx, py, ky;
@@ -143,7 +147,7 @@ struct DpArgs {
     int64_t* row_energy;     // [H]
     int32_t W, H, qx, qy;
     int32_t lam, clipd, joint, trunc;
-    int32_t quad;            // truncated squared prior (clipd = lam trunc^2)
+    int32_t ms;              // minimum search kind MS_* (clipd = lam trunc^2 for the squared prior)
     int32_t ibits;           // bits of the label index packed under the value
 };
 
@@ -177,15 +181,15 @@ struct BatchEnergyArgs {
 // The scan kernel takes a cost kind instead: 1 int16, 2 int32, 3 int16 read in
 // 4-byte aligned pairs (needs an even KX, an even label count, and qx even
 // unless qy == 1).
-// quad: the truncated squared prior (general RMS), else the truncated linear prior
-hipError_t launch_edp_pass(int tile, int kind, int split, bool quad, const PassArgs& a, int grid, int waves,
+// ms: minimum search kind MS_*
+hipError_t launch_edp_pass(int tile, int kind, int split, int ms, const PassArgs& a, int grid, int waves,
                            hipStream_t s);
 hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
 hipError_t launch_edp_aggregate_win(const AggArgs& a, int grid, hipStream_t s);
 // label-window solve: compact 8 x 8 frame costs (big outside the window) and frame shifts
 hipError_t launch_win_prep(const int32_t* cost, const int32_t* centers, int32_t W, int32_t H, int32_t qx, int32_t qy,
                            int32_t win, int32_t big, int32_t* cw, uint32_t* shifts, hipStream_t s);
-hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s);   // a.quad selects the prior
+hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s);   // a.ms selects the search
 hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
 hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);
 hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s);
@@ -217,7 +221,7 @@ hipError_t launch_targets(const int32_t* labels, int32_t W, int32_t H, int32_t q
 hipError_t launch_recenter(const int32_t* labels, int64_t n, int32_t qx, int32_t qy, int32_t win, int32_t* centers,
                            hipStream_t s);
 
-int pass_capacity(int tile, int kind, int split, bool quad, int waves, size_t lds_bytes);
+int pass_capacity(int tile, int kind, int split, int ms, int waves, size_t lds_bytes);
 // LDS bytes of the pass kernel for a tile, wavefronts per workgroup and ring slots.
 size_t pass_lds_bytes(int qt, int waves, int ring);
 

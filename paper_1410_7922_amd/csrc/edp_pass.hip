@@ -5,9 +5,9 @@
 
 namespace edp {
 
-template <int ID, bool QUAD>
+template <int ID, int MS>
 hipError_t pass_tile(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s);
-template <int ID, bool QUAD> int occupancy_tile(int kind, int split, int waves, size_t lds);
+template <int ID, int MS> int occupancy_tile(int kind, int split, int waves, size_t lds);
 template <int ID> hipError_t aggregate_tile(int dtype, const AggArgs& a, int grid, hipStream_t s);
 hipError_t pass_win(const PassArgs& a, int grid, int waves, hipStream_t s);
 int occupancy_win(int waves, size_t lds_bytes);
@@ -18,16 +18,17 @@ size_t pass_lds_bytes(int qt, int waves, int ring) {
     return (size_t)(2 * (MAX_WAVES + 1) + 4 + qt) * 4 + (size_t)(waves + 1) * ring * qt * 4;
 }
 
-hipError_t launch_edp_pass(int tile, int dtype, int split, bool quad, const PassArgs& a, int grid, int waves,
+hipError_t launch_edp_pass(int tile, int dtype, int split, int ms, const PassArgs& a, int grid, int waves,
                            hipStream_t s) {
     if (waves < 1 || waves > MAX_WAVES) return hipErrorInvalidValue;
     if (dtype == KIND_WINDOW)
-        return tile == WIN_TILE && split == 1 && !quad ? pass_win(a, grid, waves, s) : hipErrorInvalidValue;
+        return tile == WIN_TILE && split == 1 && ms == MS_LINEAR ? pass_win(a, grid, waves, s) : hipErrorInvalidValue;
     switch (tile) {
 #define EDP_CASE(id, px, kx, py, ky)                                                                   \
     case id:                                                                                           \
-        return quad ? pass_tile<id, true>(dtype, split, a, grid, waves, s)                              \
-                    : pass_tile<id, false>(dtype, split, a, grid, waves, s);
+        return ms == MS_SQ_WALK    ? pass_tile<id, MS_SQ_WALK>(dtype, split, a, grid, waves, s)         \
+               : ms == MS_SQ_SHORT ? pass_tile<id, MS_SQ_SHORT>(dtype, split, a, grid, waves, s)        \
+                                   : pass_tile<id, MS_LINEAR>(dtype, split, a, grid, waves, s);
         EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE
     }
@@ -47,7 +48,7 @@ hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid,
     return hipErrorInvalidValue;
 }
 
-int pass_capacity(int tile, int dtype, int split, bool quad, int waves, size_t lds_bytes) {
+int pass_capacity(int tile, int dtype, int split, int ms, int waves, size_t lds_bytes) {
     int per_cu = 1;
     if (dtype == KIND_WINDOW) {
         per_cu = occupancy_win(waves, lds_bytes);
@@ -56,8 +57,9 @@ int pass_capacity(int tile, int dtype, int split, bool quad, int waves, size_t l
     switch (tile) {
 #define EDP_CASE(id, px, kx, py, ky)                                                                \
     case id:                                                                                        \
-        per_cu = quad ? occupancy_tile<id, true>(dtype, split, waves, lds_bytes)                     \
-                      : occupancy_tile<id, false>(dtype, split, waves, lds_bytes);                   \
+        per_cu = ms == MS_SQ_WALK    ? occupancy_tile<id, MS_SQ_WALK>(dtype, split, waves, lds_bytes)  \
+                 : ms == MS_SQ_SHORT ? occupancy_tile<id, MS_SQ_SHORT>(dtype, split, waves, lds_bytes) \
+                                     : occupancy_tile<id, MS_LINEAR>(dtype, split, waves, lds_bytes);  \
         break;
         EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE

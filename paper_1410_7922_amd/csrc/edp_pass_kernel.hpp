@@ -89,7 +89,7 @@ __device__ __forceinline__ void tag_put(unsigned long long* p, unsigned long lon
 // empties the ring of the last active wavefront into memory and publishes progress once its
 // stores have completed.  The compute wavefronts never touch another workgroup's data, so
 // they never wait for memory operations other than their own prefetched loads.
-template <class T, class CK, int SPLIT, int PF, bool WIN = false, bool QUAD = false>
+template <class T, class CK, int SPLIT, int PF, bool WIN = false, int MS = MS_LINEAR>
 __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const PassArgs a) {
     constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
     constexpr int CL = SPLIT * G;                  // lanes per vertex
@@ -353,8 +353,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             const int32_t band = super * NW + wave;
             const bool joint = d.joint != 0;
             const LineIndex<T> li(d.lam, lane);
-            // window steps of the general RMS along x and y (truncated squared prior)
-            const int32_t nwx = min(d.trunc, d.qx) - 1, nwy = min(d.trunc, d.qy) - 1;
+            const SqPen sp(d.lam, d.trunc, d.qx, d.qy);   // squared prior: window steps and penalties
             const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(d.cost, W * H * Q * CB);
             int32_t* const t_a = ka ? d.t[1] : d.t[0];
             int32_t* const t_ma = ka ? d.t[0] : d.t[1];
@@ -520,9 +519,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                     const int32_t dxb = (int32_t)(int8_t)(cb & 0xFF), dyb = (int32_t)(int8_t)((cb >> 8) & 0xFF);
                     min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
                     min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
-                } else if constexpr (QUAD) {
-                    min_search_quad<T>(h, d.lam, nwx, nwy, d.clipd, joint, lane);
-                    if constexpr (SPLIT == 1) min_search_quad<T>(h2, d.lam, nwx, nwy, d.clipd, joint, lane);
+                } else if constexpr (MS != MS_LINEAR) {
+                    min_search_quad<T, MS == MS_SQ_WALK>(h, sp, d.clipd, joint, lane);
+                    if constexpr (SPLIT == 1) min_search_quad<T, MS == MS_SQ_WALK>(h2, sp, d.clipd, joint, lane);
                 } else {
                     min_search<T>(h, li, d.clipd, joint, lane);
                     if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
@@ -677,10 +676,10 @@ constexpr int pass_pf() { return T::E <= 4 ? 8 : (T::E <= 8 ? 4 : 2); }
 // the window solve adds a shifted-read area of 2 x 64 x 2 ints per wavefront
 inline size_t win_lds_bytes(int waves) { return (size_t)waves * 2 * 64 * 2 * 4; }
 
-template <class T, class CK, int SPLIT, bool QUAD>
+template <class T, class CK, int SPLIT, int MS>
 static hipError_t run_pass(const PassArgs& a, int grid, int waves, hipStream_t s) {
     const size_t lds = pass_lds_bytes(T::QT, waves, a.ring);
-    hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>(), false, QUAD>), dim3(grid), dim3(64 * (waves + 2)),
+    hipLaunchKernelGGL((edp_pass_kernel<T, CK, SPLIT, pass_pf<T>(), false, MS>), dim3(grid), dim3(64 * (waves + 2)),
                        lds, s, a);
     return hipGetLastError();
 }
@@ -693,52 +692,52 @@ static hipError_t run_agg(const AggArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class T, class CK, int SPLIT, bool QUAD>
+template <class T, class CK, int SPLIT, int MS>
 static int pass_occupancy(int waves, size_t lds) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CK, SPLIT, pass_pf<T>(), false, QUAD>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_kernel<T, CK, SPLIT, pass_pf<T>(), false, MS>,
                                                      64 * (waves + 2), lds) != hipSuccess)
         blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
 
 // SPLIT = 2 needs both halves of a vertex in one wavefront.
-template <class T, class CK, bool QUAD>
+template <class T, class CK, int MS>
 static hipError_t dispatch_pass(int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
     if (split == 2) {
-        if constexpr (2 * T::G <= 64) return run_pass<T, CK, 2, QUAD>(a, grid, waves, s);
+        if constexpr (2 * T::G <= 64) return run_pass<T, CK, 2, MS>(a, grid, waves, s);
         return hipErrorInvalidValue;
     }
-    return run_pass<T, CK, 1, QUAD>(a, grid, waves, s);
+    return run_pass<T, CK, 1, MS>(a, grid, waves, s);
 }
 
-template <class T, class CK, bool QUAD>
+template <class T, class CK, int MS>
 static int dispatch_occupancy(int split, int waves, size_t lds) {
     if (split == 2) {
-        if constexpr (2 * T::G <= 64) return pass_occupancy<T, CK, 2, QUAD>(waves, lds);
+        if constexpr (2 * T::G <= 64) return pass_occupancy<T, CK, 2, MS>(waves, lds);
         return 1;
     }
-    return pass_occupancy<T, CK, 1, QUAD>(waves, lds);
+    return pass_occupancy<T, CK, 1, MS>(waves, lds);
 }
 
 // cost kind: 1 int16 (element loads), 2 int32, 3 int16 in aligned pairs
-template <class T, bool QUAD>
+template <class T, int MS>
 static hipError_t dispatch_kind(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
-    if (kind == 1) return dispatch_pass<T, int16_t, QUAD>(split, a, grid, waves, s);
+    if (kind == 1) return dispatch_pass<T, int16_t, MS>(split, a, grid, waves, s);
     if (kind == 3) {
-        if constexpr (T::KX % 2 == 0) return dispatch_pass<T, Pair16, QUAD>(split, a, grid, waves, s);
+        if constexpr (T::KX % 2 == 0) return dispatch_pass<T, Pair16, MS>(split, a, grid, waves, s);
         return hipErrorInvalidValue;
     }
-    return dispatch_pass<T, int32_t, QUAD>(split, a, grid, waves, s);
+    return dispatch_pass<T, int32_t, MS>(split, a, grid, waves, s);
 }
-template <class T, bool QUAD>
+template <class T, int MS>
 static int occupancy_kind(int kind, int split, int waves, size_t lds) {
-    if (kind == 1) return dispatch_occupancy<T, int16_t, QUAD>(split, waves, lds);
+    if (kind == 1) return dispatch_occupancy<T, int16_t, MS>(split, waves, lds);
     if (kind == 3) {
-        if constexpr (T::KX % 2 == 0) return dispatch_occupancy<T, Pair16, QUAD>(split, waves, lds);
+        if constexpr (T::KX % 2 == 0) return dispatch_occupancy<T, Pair16, MS>(split, waves, lds);
         return 1;
     }
-    return dispatch_occupancy<T, int32_t, QUAD>(split, waves, lds);
+    return dispatch_occupancy<T, int32_t, MS>(split, waves, lds);
 }
 
 // Per-tile entry points.  Each is instantiated explicitly in one of the edp_pass_t*.hip
@@ -749,14 +748,14 @@ template <int ID> struct TileOf;
 EDP_TILE_LIST(EDP_TILE_OF)
 #undef EDP_TILE_OF
 
-// QUAD: the truncated squared prior (general RMS); otherwise the truncated linear one
-template <int ID, bool QUAD>
+// MS: the minimum search (MS_LINEAR, MS_SQ_SHORT, MS_SQ_WALK)
+template <int ID, int MS>
 hipError_t pass_tile(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
-    return dispatch_kind<typename TileOf<ID>::type, QUAD>(kind, split, a, grid, waves, s);
+    return dispatch_kind<typename TileOf<ID>::type, MS>(kind, split, a, grid, waves, s);
 }
-template <int ID, bool QUAD>
+template <int ID, int MS>
 int occupancy_tile(int kind, int split, int waves, size_t lds) {
-    return occupancy_kind<typename TileOf<ID>::type, QUAD>(kind, split, waves, lds);
+    return occupancy_kind<typename TileOf<ID>::type, MS>(kind, split, waves, lds);
 }
 template <int ID>
 hipError_t aggregate_tile(int dtype, const AggArgs& a, int grid, hipStream_t s) {
@@ -768,12 +767,14 @@ hipError_t aggregate_tile(int dtype, const AggArgs& a, int grid, hipStream_t s) 
 using WinTile = TileOf<WIN_TILE>::type;
 
 #define EDP_INSTANTIATE_TILE(id)                                                                         \
-    template hipError_t pass_tile<id, false>(int, int, const PassArgs&, int, int, hipStream_t);           \
-    template int occupancy_tile<id, false>(int, int, int, size_t);                                       \
+    template hipError_t pass_tile<id, MS_LINEAR>(int, int, const PassArgs&, int, int, hipStream_t);       \
+    template int occupancy_tile<id, MS_LINEAR>(int, int, int, size_t);                                   \
     template hipError_t aggregate_tile<id>(int, const AggArgs&, int, hipStream_t);
 // the scan kernels of a tile for the truncated squared prior
-#define EDP_INSTANTIATE_TILE_QUAD(id)                                                                    \
-    template hipError_t pass_tile<id, true>(int, int, const PassArgs&, int, int, hipStream_t);            \
-    template int occupancy_tile<id, true>(int, int, int, size_t);
+#define EDP_INSTANTIATE_TILE_SQ(id)                                                                      \
+    template hipError_t pass_tile<id, MS_SQ_SHORT>(int, int, const PassArgs&, int, int, hipStream_t);     \
+    template int occupancy_tile<id, MS_SQ_SHORT>(int, int, int, size_t);                                 \
+    template hipError_t pass_tile<id, MS_SQ_WALK>(int, int, const PassArgs&, int, int, hipStream_t);      \
+    template int occupancy_tile<id, MS_SQ_WALK>(int, int, int, size_t);
 
 }  // namespace edp

@@ -4,9 +4,9 @@
 
 namespace edp {
 
-EDP_INSTANTIATE_TILE_QUAD(0)
-EDP_INSTANTIATE_TILE_QUAD(1)
-EDP_INSTANTIATE_TILE_QUAD(2)
-EDP_INSTANTIATE_TILE_QUAD(3)
+EDP_INSTANTIATE_TILE_SQ(0)
+EDP_INSTANTIATE_TILE_SQ(1)
+EDP_INSTANTIATE_TILE_SQ(2)
+EDP_INSTANTIATE_TILE_SQ(3)
 
 }  // namespace edp

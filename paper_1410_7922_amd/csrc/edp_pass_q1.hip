@@ -4,9 +4,9 @@
 
 namespace edp {
 
-EDP_INSTANTIATE_TILE_QUAD(4)
-EDP_INSTANTIATE_TILE_QUAD(5)
-EDP_INSTANTIATE_TILE_QUAD(6)
-EDP_INSTANTIATE_TILE_QUAD(7)
+EDP_INSTANTIATE_TILE_SQ(4)
+EDP_INSTANTIATE_TILE_SQ(5)
+EDP_INSTANTIATE_TILE_SQ(6)
+EDP_INSTANTIATE_TILE_SQ(7)
 
 }  // namespace edp

@@ -4,9 +4,9 @@
 
 namespace edp {
 
-EDP_INSTANTIATE_TILE_QUAD(8)
-EDP_INSTANTIATE_TILE_QUAD(9)
-EDP_INSTANTIATE_TILE_QUAD(10)
-EDP_INSTANTIATE_TILE_QUAD(11)
+EDP_INSTANTIATE_TILE_SQ(8)
+EDP_INSTANTIATE_TILE_SQ(9)
+EDP_INSTANTIATE_TILE_SQ(10)
+EDP_INSTANTIATE_TILE_SQ(11)
 
 }  // namespace edp

@@ -4,9 +4,9 @@
 
 namespace edp {
 
-EDP_INSTANTIATE_TILE_QUAD(12)
-EDP_INSTANTIATE_TILE_QUAD(13)
-EDP_INSTANTIATE_TILE_QUAD(14)
-EDP_INSTANTIATE_TILE_QUAD(15)
+EDP_INSTANTIATE_TILE_SQ(12)
+EDP_INSTANTIATE_TILE_SQ(13)
+EDP_INSTANTIATE_TILE_SQ(14)
+EDP_INSTANTIATE_TILE_SQ(15)
 
 }  // namespace edp
