@@ -73,11 +73,13 @@ int64_t clip_of(const edp_problem* p) {
     return (int64_t)p->lambda * (p->prior == EDP_PRIOR_SQUARED ? t * t : t);
 }
 
-// The minimum search kind of the scan and DP kernels for a problem (MS_*).
+// The minimum search of the scan and DP kernels for a problem (MS_*): the general RMS
+// window where it has at most two steps per side (cheaper than the linear RMS then, for
+// either prior), else the linear RMS (linear prior) or the walked window (squared prior).
 int ms_of(const edp_problem* p) {
-    if (p->prior != EDP_PRIOR_SQUARED) return MS_LINEAR;
     const int nw = std::max(std::min(p->trunc, p->qx), std::min(p->trunc, p->qy)) - 1;
-    return nw <= 2 ? MS_SQ_SHORT : MS_SQ_WALK;
+    if (nw <= 2) return MS_WINDOW;
+    return p->prior == EDP_PRIOR_SQUARED ? MS_WALK : MS_LINEAR;
 }
 
 int64_t vmax_of(const edp_problem* p) {
@@ -279,7 +281,7 @@ InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, 
     d.clipd = (int32_t)clip_of(p);
     d.joint = p->trunc_mode == EDP_TRUNC_JOINT;
     d.trunc = p->trunc;
-    d.quad = p->prior == EDP_PRIOR_SQUARED;
+    d.squared = p->prior == EDP_PRIOR_SQUARED;
     d.nbands = la.nbands;
     d.nsuper = la.nsuper;
     return d;
@@ -424,7 +426,7 @@ edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t*
     e.trunc = p->trunc;
     e.joint = p->trunc_mode == EDP_TRUNC_JOINT;
     e.grid4 = grid4;
-    e.quad = p->prior == EDP_PRIOR_SQUARED;
+    e.squared = p->prior == EDP_PRIOR_SQUARED;
     hipError_t err = launch_fill_u32((uint32_t*)energy, 2, 0, s);
     if (err == hipSuccess && invalid) err = launch_fill_u32((uint32_t*)invalid, 2, 0, s);
     if (err == hipSuccess) err = launch_energy(p->dtype, e, s);
@@ -634,6 +636,7 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
     a.joint = prob->trunc_mode == EDP_TRUNC_JOINT;
     a.trunc = prob->trunc;
     a.ms = ms_of(prob);
+    a.squared = prob->prior == EDP_PRIOR_SQUARED;
     a.ibits = ibits_of(prob->qx * prob->qy);
     const int rows_per_block = (64 / group_of(tile)) * 4;
     const int grid = (prob->height + rows_per_block - 1) / rows_per_block;
@@ -897,7 +900,7 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
-    c.ms = ms_of(prob);
+    c.ms = MS_LINEAR;          // the window kernel runs its own search between shifted frames
     c.one = make_desc(&f, la, E.inst, ws, flags, ws + E.hand, cw, d_labels, nullptr);
     c.one.aux = shifts;
     c.one.centers = d_centers;

@@ -1,6 +1,6 @@
 // Device building blocks for gfx950: lane tiles, cross-lane exchange, the
 // linear recursive minimum search (Mozerov, arXiv 1410.7922, Sec. 3.2) and the
-// general one for the truncated squared prior (Sec. 3.1).
+// general one (Sec. 3.1).
 //
 // A "lane tile" maps the labels of one DSI vertex onto a group of G = PX*PY
 // lanes of a 64-wide wavefront.  Lane (px, py) of a group holds the KY x KX
@@ -412,13 +412,15 @@ __device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t (&lv
     return m;
 }
 
-// ---- general RMS on one dimension (truncated squared prior) -------------------
+// ---- general RMS on one dimension ------------------------------------------------
 // For every line along the dimension: the window minimum of eq. M_decmp1 with
-// f(a) = a^2 and the penalty inside the minimum,
-//   W(v) = min_{|u| < g} h(v - u) + lam u^2,
-// then the clip min(W, line_min + clipd) when clip is set (clipd = lam g^2).
-// A line of n labels takes nw = min(g, n) - 1 window steps on each side.  On
-// packed keys lam is the penalty unit shifted above the index bits.
+// the penalty inside the minimum,
+//   W(v) = min_{|u| < g} h(v - u) + lam f(u),
+// then the clip min(W, line_min + clipd) when clip is set (clipd = lam f(g)).
+// It is exact for any increasing f; here f(u) = u (truncated linear prior) or
+// u^2 (truncated squared prior).  A line of n labels takes nw = min(g, n) - 1
+// window steps on each side.  On packed keys lam is the penalty unit shifted
+// above the index bits.
 //
 // Two ways, chosen per kernel so that the step has no branch:
 //   short windows (nw <= 2, which covers g <= 3, the paper's setups): the values
@@ -426,26 +428,30 @@ __device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t (&lv
 //     lane at a time (one cross-lane move per register and lane hop, PADV past
 //     the ends of the line), so the moves are independent of each other, and
 //     each label takes two three-way minima; a step outside the window gets the
-//     penalty PEN_OFF, which no candidate survives;
-//   any window: the window is walked one label at a time: after u steps up[k]
-//     holds the value u labels below label k and dn[k] the value u labels above.
+//     penalty PEN_OFF, which no candidate survives.  For the linear prior with
+//     g <= 3 this is cheaper than the two recursions of the linear RMS;
+//   any window (squared prior): the window is walked one label at a time: after
+//     u steps up[k] holds the value u labels below label k and dn[k] the value
+//     u labels above.
 
 // Penalty of a window step outside the window: above every real value, and PADV plus it
 // still fits in int32.
 constexpr int32_t PEN_OFF = 0x40000000;
 
-// Window steps and their penalties lam u^2 (u = 1, 2) along x and y.
-struct SqPen {
+// Window steps and the penalties lam f(u) of the first two (u = 1, 2) along x and y.
+struct WinPen {
     int32_t lam, nwx, nwy;
     int32_t px[2], py[2];
-    __device__ __forceinline__ SqPen(const int32_t lam_, const int32_t g, const int32_t qx, const int32_t qy) {
+    __device__ __forceinline__ WinPen(const int32_t lam_, const int32_t g, const int32_t qx, const int32_t qy,
+                                      const bool squared) {
         lam = lam_;
         nwx = min(g, qx) - 1;
         nwy = min(g, qy) - 1;
 #pragma unroll
         for (int u = 1; u <= 2; ++u) {
-            px[u - 1] = u <= nwx ? lam * (u * u) : PEN_OFF;
-            py[u - 1] = u <= nwy ? lam * (u * u) : PEN_OFF;
+            const int32_t p = lam * (squared ? u * u : u);
+            px[u - 1] = u <= nwx ? p : PEN_OFF;
+            py[u - 1] = u <= nwy ? p : PEN_OFF;
         }
     }
 };
@@ -488,6 +494,7 @@ __device__ __forceinline__ void quad_window(int32_t (&val)[K], const int32_t (&p
     for (int k = 0; k < K; ++k) val[k] = out[k];
 }
 
+// squared prior only: lam u^2 accumulates as the sum of lam (2i - 1)
 template <int NL, int K, int STEP>
 __device__ __forceinline__ void quad_walk(int32_t (&val)[K], const int32_t lam, const int32_t nw,
                                           const int32_t pos, const int32_t lane) {
@@ -497,7 +504,7 @@ __device__ __forceinline__ void quad_walk(int32_t (&val)[K], const int32_t lam, 
         up[k] = val[k];
         dn[k] = val[k];
     }
-    int32_t pen = 0, inc = lam;                      // lam u^2 as the sum of lam (2i - 1)
+    int32_t pen = 0, inc = lam;
     for (int32_t u = 0; u < nw; ++u) {
         pen += inc;
         inc += 2 * lam;
@@ -517,9 +524,10 @@ __device__ __forceinline__ void quad_walk(int32_t (&val)[K], const int32_t lam, 
     }
 }
 
-// WALK false: nw <= 2 with the step penalties pen; WALK true: any nw.  Returns min h of the line.
+// WALK false: nw <= 2 with the step penalties pen; WALK true: any nw, squared prior.
+// Returns min h of the line.
 template <int NL, int K, int STEP, bool WALK>
-__device__ __forceinline__ int32_t quad_line(int32_t (&val)[K], const int32_t (&pen)[2], const int32_t lam,
+__device__ __forceinline__ int32_t window_line(int32_t (&val)[K], const int32_t (&pen)[2], const int32_t lam,
                                              const int32_t nw, const int32_t clipd, const bool clip,
                                              const int32_t pos, const int32_t lane) {
     int32_t m = val[0];
@@ -662,13 +670,12 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
     }
 }
 
-// The minimum search operator M for the truncated squared prior, computed by the
-// general RMS of Sec. 3.1: one window operator per label dimension (eq.
-// M_decmp1), clipped per line (per-dimension truncation) or once at
-// (min h + clipd) (joint truncation, eq. M_decmp).  WALK as for quad_line.
-// Same contract as min_search.
+// The minimum search operator M computed by the general RMS of Sec. 3.1: one
+// window operator per label dimension (eq. M_decmp1), clipped per line
+// (per-dimension truncation) or once at (min h + clipd) (joint truncation,
+// eq. M_decmp).  WALK as for window_line.  Same contract as min_search.
 template <class T, bool WALK>
-__device__ __forceinline__ int32_t min_search_quad(int32_t (&h)[T::KY][T::KX], const SqPen& sp,
+__device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KY][T::KX], const WinPen& sp,
                                                    const int32_t clipd, const bool joint, const int32_t lane) {
     const int32_t l = lane % T::G;
     const int32_t px = l % T::PX, py = l / T::PX;
@@ -676,7 +683,7 @@ __device__ __forceinline__ int32_t min_search_quad(int32_t (&h)[T::KY][T::KX], c
     int32_t rowmin = PADV;
 #pragma unroll
     for (int ky = 0; ky < T::KY; ++ky) {
-        const int32_t lm = quad_line<T::PX, T::KX, 1, WALK>(h[ky], sp.px, sp.lam, sp.nwx, clipd, !joint || one_dim,
+        const int32_t lm = window_line<T::PX, T::KX, 1, WALK>(h[ky], sp.px, sp.lam, sp.nwx, clipd, !joint || one_dim,
                                                              px, lane);
         rowmin = imin(rowmin, lm);
     }
@@ -690,7 +697,7 @@ __device__ __forceinline__ int32_t min_search_quad(int32_t (&h)[T::KY][T::KX], c
             int32_t col[T::KY];
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
-            quad_line<T::PY, T::KY, T::PX, WALK>(col, sp.py, sp.lam, sp.nwy, clipd, !joint, py, lane);
+            window_line<T::PY, T::KY, T::PX, WALK>(col, sp.py, sp.lam, sp.nwy, clipd, !joint, py, lane);
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
         }

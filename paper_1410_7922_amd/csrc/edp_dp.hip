@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
     const int32_t mask = (1 << ib) - 1;
     const int32_t lamk = a.lam << ib, clipk = a.clipd << ib;
     const LineIndex<T> li(lamk, lane);
-    const SqPen sp(lamk, a.trunc, a.qx, a.qy);        // squared prior: window steps and penalties (keys)
+    const WinPen sp(lamk, a.trunc, a.qx, a.qy, a.squared != 0);   // general RMS window (keys)
     // buffer resources (see the scan kernel): lanes without an operand use offset OOB
     const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(a.cost, W * H * Q * CB);
     const __amdgpu_buffer_rsrc_t rs_p = make_rsrc(a.ptr, W * H * QT * (int32_t)sizeof(PT));
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
         const bool live = !TAIL || x < W;
         int32_t g;
         if constexpr (MS == MS_LINEAR) g = min_search<T>(key, li, clipk, a.joint != 0, lane);
-        else g = min_search_quad<T, MS == MS_SQ_WALK>(key, sp, clipk, a.joint != 0, lane);
+        else g = min_search_window<T, MS == MS_WALK>(key, sp, clipk, a.joint != 0, lane);
         const int32_t norm = g >> ib;
         if constexpr (sizeof(PT) == 1 && E % 4 == 0) {
             // four choice indexes per dword: low bytes gathered by byte permutes, then masked
@@ -272,8 +272,8 @@ static void run_fwd_ms(const DpArgs& a, int grid, hipStream_t s) {
 
 template <class T, class CK>
 static hipError_t run_fwd(const DpArgs& a, int grid, hipStream_t s) {
-    if (a.ms == MS_SQ_WALK) run_fwd_ms<T, CK, MS_SQ_WALK>(a, grid, s);
-    else if (a.ms == MS_SQ_SHORT) run_fwd_ms<T, CK, MS_SQ_SHORT>(a, grid, s);
+    if (a.ms == MS_WALK) run_fwd_ms<T, CK, MS_WALK>(a, grid, s);
+    else if (a.ms == MS_WINDOW) run_fwd_ms<T, CK, MS_WINDOW>(a, grid, s);
     else run_fwd_ms<T, CK, MS_LINEAR>(a, grid, s);
     return hipGetLastError();
 }

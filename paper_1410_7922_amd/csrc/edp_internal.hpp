@@ -36,9 +36,9 @@ constexpr int WIN_TILE = 13;
 constexpr int KIND_WINDOW = 4;
 constexpr int WIN_FRAME = 8;
 // Minimum searches of the scan and DP kernels (one kernel each, so the step has no branch):
-constexpr int MS_LINEAR = 0;     // truncated linear prior: linear RMS
-constexpr int MS_SQ_SHORT = 1;   // truncated squared prior, windows of at most two steps per side
-constexpr int MS_SQ_WALK = 2;    // truncated squared prior, any window
+constexpr int MS_LINEAR = 0;     // truncated linear prior: linear RMS (Sec. 3.2)
+constexpr int MS_WINDOW = 1;     // general RMS (Sec. 3.1), windows of at most two steps per side, either prior
+constexpr int MS_WALK = 2;       // general RMS, any window, truncated squared prior
 
 struct TileShape {
     int px, kx, py, ky;
@@ -67,7 +67,7 @@ struct InstDesc {
     int32_t win, qx_full;         // label-window solve: window side, labels along x of the full space
     int32_t W, H, qx, qy;
     int32_t lam, clipd, joint, trunc;
-    int32_t quad;                 // 1: truncated squared prior (clipd = lam trunc^2), 0: truncated linear
+    int32_t squared;              // 1: truncated squared prior (clipd = lam trunc^2), 0: truncated linear
     int32_t nbands, nsuper;       // wavefront bands, workgroup bands
     int32_t first_ticket;         // first workgroup band of this instance in its launch
     int32_t first_block;          // first marginal block of this instance
@@ -147,7 +147,8 @@ struct DpArgs {
     int64_t* row_energy;     // [H]
     int32_t W, H, qx, qy;
     int32_t lam, clipd, joint, trunc;
-    int32_t ms;              // minimum search kind MS_* (clipd = lam trunc^2 for the squared prior)
+    int32_t ms;              // minimum search kind MS_*
+    int32_t squared;         // truncated squared prior (clipd = lam trunc^2)
     int32_t ibits;           // bits of the label index packed under the value
 };
 
@@ -166,7 +167,7 @@ struct EnergyArgs {
     unsigned long long* invalid;
     int32_t W, H, qx, qy;
     int32_t lam, trunc, joint, grid4;
-    int32_t quad;            // truncated squared prior
+    int32_t squared;         // truncated squared prior
 };
 
 // Energies of every instance of a batch (4-connected): block b works on rows of

@@ -5,14 +5,14 @@
 
 namespace edp {
 
-// V(u) of eq. Smooth_value_t with f(a) = |a| (quad false) or a^2 (quad true)
+// V(u) of eq. Smooth_value_t with f(a) = |a| (squared false) or a^2 (squared true)
 __device__ __forceinline__ int64_t prior_pair(int32_t a, int32_t b, int32_t qx, int32_t lam,
-                                              int32_t trunc, bool joint, bool quad) {
+                                              int32_t trunc, bool joint, bool squared) {
     int64_t dx = a % qx - b % qx, dy = a / qx - b / qx;
     dx = dx < 0 ? -dx : dx;
     dy = dy < 0 ? -dy : dy;
     int64_t ft = trunc;
-    if (quad) {
+    if (squared) {
         dx *= dx;
         dy *= dy;
         ft *= ft;
@@ -37,11 +37,11 @@ __global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
         acc += (int64_t)cost[idx * Q + lab];
         if (x + 1 < W) {
             const int32_t r = a.labels[idx + 1];
-            if (r >= 0 && r < Q) acc += prior_pair(lab, r, a.qx, a.lam, a.trunc, joint, a.quad != 0);
+            if (r >= 0 && r < Q) acc += prior_pair(lab, r, a.qx, a.lam, a.trunc, joint, a.squared != 0);
         }
         if (a.grid4 && y + 1 < H) {
             const int32_t d = a.labels[idx + W];
-            if (d >= 0 && d < Q) acc += prior_pair(lab, d, a.qx, a.lam, a.trunc, joint, a.quad != 0);
+            if (d >= 0 && d < Q) acc += prior_pair(lab, d, a.qx, a.lam, a.trunc, joint, a.squared != 0);
         }
     }
     __shared__ int64_t sacc[256];
@@ -81,11 +81,11 @@ __global__ __launch_bounds__(256) void batch_energy_kernel(const BatchEnergyArgs
             acc += (int64_t)cost[idx * Q + lab];
             if (x + 1 < W) {
                 const int32_t r = d.labels[idx + 1];
-                if (r >= 0 && r < Q) acc += prior_pair(lab, r, d.qx, d.lam, d.trunc, joint, d.quad != 0);
+                if (r >= 0 && r < Q) acc += prior_pair(lab, r, d.qx, d.lam, d.trunc, joint, d.squared != 0);
             }
             if (y + 1 < H) {
                 const int32_t v = d.labels[idx + W];
-                if (v >= 0 && v < Q) acc += prior_pair(lab, v, d.qx, d.lam, d.trunc, joint, d.quad != 0);
+                if (v >= 0 && v < Q) acc += prior_pair(lab, v, d.qx, d.lam, d.trunc, joint, d.squared != 0);
             }
         }
     }

@@ -353,7 +353,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             const int32_t band = super * NW + wave;
             const bool joint = d.joint != 0;
             const LineIndex<T> li(d.lam, lane);
-            const SqPen sp(d.lam, d.trunc, d.qx, d.qy);   // squared prior: window steps and penalties
+            const WinPen sp(d.lam, d.trunc, d.qx, d.qy, d.squared != 0);   // general RMS window
             const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(d.cost, W * H * Q * CB);
             int32_t* const t_a = ka ? d.t[1] : d.t[0];
             int32_t* const t_ma = ka ? d.t[0] : d.t[1];
@@ -520,8 +520,8 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                     min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
                     min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
                 } else if constexpr (MS != MS_LINEAR) {
-                    min_search_quad<T, MS == MS_SQ_WALK>(h, sp, d.clipd, joint, lane);
-                    if constexpr (SPLIT == 1) min_search_quad<T, MS == MS_SQ_WALK>(h2, sp, d.clipd, joint, lane);
+                    min_search_window<T, MS == MS_WALK>(h, sp, d.clipd, joint, lane);
+                    if constexpr (SPLIT == 1) min_search_window<T, MS == MS_WALK>(h2, sp, d.clipd, joint, lane);
                 } else {
                     min_search<T>(h, li, d.clipd, joint, lane);
                     if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
@@ -748,7 +748,7 @@ template <int ID> struct TileOf;
 EDP_TILE_LIST(EDP_TILE_OF)
 #undef EDP_TILE_OF
 
-// MS: the minimum search (MS_LINEAR, MS_SQ_SHORT, MS_SQ_WALK)
+// MS: the minimum search (MS_LINEAR, MS_WINDOW, MS_WALK)
 template <int ID, int MS>
 hipError_t pass_tile(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s) {
     return dispatch_kind<typename TileOf<ID>::type, MS>(kind, split, a, grid, waves, s);
@@ -770,11 +770,11 @@ using WinTile = TileOf<WIN_TILE>::type;
     template hipError_t pass_tile<id, MS_LINEAR>(int, int, const PassArgs&, int, int, hipStream_t);       \
     template int occupancy_tile<id, MS_LINEAR>(int, int, int, size_t);                                   \
     template hipError_t aggregate_tile<id>(int, const AggArgs&, int, hipStream_t);
-// the scan kernels of a tile for the truncated squared prior
-#define EDP_INSTANTIATE_TILE_SQ(id)                                                                      \
-    template hipError_t pass_tile<id, MS_SQ_SHORT>(int, int, const PassArgs&, int, int, hipStream_t);     \
-    template int occupancy_tile<id, MS_SQ_SHORT>(int, int, int, size_t);                                 \
-    template hipError_t pass_tile<id, MS_SQ_WALK>(int, int, const PassArgs&, int, int, hipStream_t);      \
-    template int occupancy_tile<id, MS_SQ_WALK>(int, int, int, size_t);
+// the scan kernels of a tile with the general RMS
+#define EDP_INSTANTIATE_TILE_WIN(id)                                                                      \
+    template hipError_t pass_tile<id, MS_WINDOW>(int, int, const PassArgs&, int, int, hipStream_t);     \
+    template int occupancy_tile<id, MS_WINDOW>(int, int, int, size_t);                                 \
+    template hipError_t pass_tile<id, MS_WALK>(int, int, const PassArgs&, int, int, hipStream_t);      \
+    template int occupancy_tile<id, MS_WALK>(int, int, int, size_t);
 
 }  // namespace edp

@@ -1,12 +1,12 @@
-// Scan kernels of tiles 4, 5, 6, 7 for the truncated squared prior (instantiated here,
+// Scan kernels of tiles 4, 5, 6, 7 with the general RMS (instantiated here,
 // dispatched from edp_pass.hip).
 #include "edp_pass_kernel.hpp"
 
 namespace edp {
 
-EDP_INSTANTIATE_TILE_SQ(4)
-EDP_INSTANTIATE_TILE_SQ(5)
-EDP_INSTANTIATE_TILE_SQ(6)
-EDP_INSTANTIATE_TILE_SQ(7)
+EDP_INSTANTIATE_TILE_WIN(4)
+EDP_INSTANTIATE_TILE_WIN(5)
+EDP_INSTANTIATE_TILE_WIN(6)
+EDP_INSTANTIATE_TILE_WIN(7)
 
 }  // namespace edp

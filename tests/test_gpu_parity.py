@@ -141,6 +141,33 @@ def test_edp_random_all_tiles(case):
         assert e == ref["energy"], (tile, split, waves, chunk, fuse)
 
 
+# The linear RMS scans (Sec. 3.2) run where the window of the general RMS would take more than two
+# steps per side (T >= 4 on lines of at least four labels); smaller T run the window kernels above.
+LRMS_CASES = [
+    # W, H, qx, qy, lam, T, mode, lo, hi, dtype, iterations
+    (13, 10, 16, 1, 7, 4, 0, -30, 60, np.int32, 1),
+    (29, 37, 32, 1, 9, 5, 0, 0, 50, np.int16, 2),
+    (17, 23, 50, 1, 5, 9, 0, 0, 80, np.int16, 1),
+    (10, 9, 5, 4, 5, 4, 0, -10, 40, np.int32, 1),
+    (10, 9, 6, 5, 4, 6, 1, -10, 40, np.int32, 2),
+    (12, 14, 15, 15, 7, 4, 0, 0, 2500, np.int32, 1),
+    (7, 9, 31, 31, 9, 5, 1, 0, 2500, np.int32, 1),
+    (40, 67, 64, 1, 6, 12, 0, -20, 60, np.int16, 1),
+]
+
+
+@pytest.mark.parametrize("case", LRMS_CASES, ids=lambda c: f"{c[0]}x{c[1]}q{c[2]}x{c[3]}T{c[5]}m{c[6]}j{c[10]}")
+def test_edp_linear_rms_all_tiles(case):
+    W, H, qx, qy, lam, T, mode, lo, hi, dt, j = case
+    p = synth.random_problem(W * 7 + H + j, W, H, qx, qy, lam, T, mode, lo, hi, dt)
+    ref = cref.edp(p.cost, qx, qy, lam, T, mode, j, "lrms")
+    for tile, split, waves, chunk, fuse in launch_variants(qx, qy):
+        note(f"edp lrms {p.name} j{j} tile {tile} split {split} waves {waves} chunk {chunk} fuse {fuse}")
+        lab, e = gpu_edp(p, j, tile, chunk, split=split, waves=waves, fuse=fuse)
+        assert np.array_equal(lab, ref["labels"]), (tile, split, waves, chunk, fuse)
+        assert e == ref["energy"], (tile, split, waves, chunk, fuse)
+
+
 # Widths around the first steady prefetch round (a round of 8 steps runs without range tests
 # once every scanline of the wavefront is inside its row for the round and the round it
 # prefetches for: s0 >= rows per wavefront and s0 + 17 <= W), on the tiles that have the steady
