@@ -55,7 +55,7 @@ typedef enum {
 typedef enum { EDP_I16 = 1, EDP_I32 = 2 } edp_dtype;
 typedef enum { EDP_TRUNC_PER_DIM = 0, EDP_TRUNC_JOINT = 1 } edp_trunc_mode;
 typedef enum { EDP_PRIOR_LINEAR = 0, EDP_PRIOR_SQUARED = 1 } edp_prior;
-typedef enum { EDP_OP_DP = 0, EDP_OP_EDP = 1 } edp_op;
+typedef enum { EDP_OP_DP = 0, EDP_OP_EDP = 1, EDP_OP_DP_MARGINALS = 2 } edp_op;
 
 /* One energy-minimisation instance (Sec. 2). */
 typedef struct {
@@ -122,6 +122,30 @@ edp_status edp_workspace_size(const edp_problem* prob, int32_t op, const edp_tun
 edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
                            int32_t* d_labels, int64_t* d_row_energy, int64_t* d_energy,
                            void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Scanline DP by min-marginals (Sec. 4.1, eqs. DP_1D_3 and DP_1D_5): for every
+ * row, a forward recursion S_1(x) = C(x) + M(S_1(x-1)) from S_1(0) = C(0) and a
+ * backward one S_-1(x) = C(x) + M(S_-1(x+1)) from S_-1(W-1) = C(W-1) give the
+ * marginal S_Omega(x, v) = M(S_1(x-1))(v) + C(x, v) + M(S_-1(x+1))(v) (terms
+ * off the row are 0); each label is the smallest argmin of its own column's
+ * marginal, with no stored choice indexes and no walk back.  min_v S_Omega(x, v)
+ * equals the row optimum at every x; the labels are the DP's optimal labelling
+ * wherever that is unique, and otherwise may combine several optimal labellings
+ * (their energy, from edp_energy, can then exceed the row optimum).  The
+ * forward terms are stored in 16 bits: problems whose clip distance lambda f(T)
+ * (twice that per-dimension in two label dimensions) exceeds 65535 return
+ * EDP_E_RANGE.  Workspace: edp_workspace_size with EDP_OP_DP_MARGINALS.
+ * tuning: tile as for the DP; events[0], [1] around the forward sweep, [2],
+ * [3] around the backward sweep.
+ *   d_labels      [H][W] int32 output labels
+ *   d_marginal    [H][W][Q] int32 output S_Omega(x, v) - min_v S_Omega(x, v) (nullable)
+ *   d_row_energy  [H] int64 output row optima (nullable)
+ *   d_energy      [1] int64 output: their sum (nullable)
+ */
+edp_status edp_dp_marginals(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
+                            int32_t* d_labels, int32_t* d_marginal, int64_t* d_row_energy, int64_t* d_energy,
+                            void* d_ws, size_t ws_bytes, void* stream);
 
 /*
  * Extended DP (Sec. 4.2, Algorithm 1 steps 3-5) on the 4-connected grid:

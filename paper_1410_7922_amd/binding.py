@@ -23,11 +23,12 @@ PRIOR_LINEAR = 0      # f(a) = |a|
 PRIOR_SQUARED = 1     # f(a) = a^2
 OP_DP = 0
 OP_EDP = 1
+OP_DP_MARGINALS = 2
 
 EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
            "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
            "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy", "edp_window_workspace_size",
-           "edp_solve_windowed")
+           "edp_solve_windowed", "edp_dp_marginals")
 
 
 class Problem(ctypes.Structure):
@@ -68,6 +69,7 @@ def load(path: str = LIB_PATH):
     L.edp_workspace_size.argtypes = [pprob, ctypes.c_int32, ptun, ctypes.POINTER(sz)]
     L.edp_dp_scanline.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, sz, vp]
     L.edp_solve.argtypes = [pprob, ptun, vp, vp, vp, vp, sz, vp]
+    L.edp_dp_marginals.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, vp, sz, vp]
     L.edp_energy.argtypes = [pprob, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.edp_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.edp_tile_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
@@ -84,7 +86,7 @@ def load(path: str = LIB_PATH):
     L.edp_solve_windowed.argtypes = [pprob, ptun, vp, vp, ctypes.c_int32, vp, vp, vp, sz, vp]
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
-                 "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed"):
+                 "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -191,6 +193,26 @@ def dp_scanline(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: 
                                   row_e.data_ptr(), tot.data_ptr(), w.data_ptr(), w.numel(),
                                   _stream(cost.device)), "edp_dp_scanline")
     return labels, row_e, tot
+
+
+def dp_marginals(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2,
+                 mode: int = TRUNC_PER_DIM, cost_bound: int = 0, tile: int = -1, ws: Workspace | None = None,
+                 events=None, prior: int = PRIOR_LINEAR, marginal: bool = False):
+    """Scanline DP by min-marginals (edp_dp_marginals).  Returns (labels [H][W] int32,
+    marginal excess [H][W][Q] int32 or None, row optima [H] int64, their sum [1] int64)."""
+    _device_tensor(cost, "cost")
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound, prior)
+    nbytes = workspace_size(prob, OP_DP_MARGINALS, tile)
+    w = (ws or _default_ws).get(nbytes, cost.device)
+    H, W, Q = cost.shape
+    labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    marg = torch.empty((H, W, Q), dtype=torch.int32, device=cost.device) if marginal else None
+    row_e = torch.empty(H, dtype=torch.int64, device=cost.device)
+    tot = torch.empty(1, dtype=torch.int64, device=cost.device)
+    _check(load().edp_dp_marginals(ctypes.byref(prob), _tuning(tile, 0, events), cost.data_ptr(), labels.data_ptr(),
+                                   marg.data_ptr() if marg is not None else None, row_e.data_ptr(), tot.data_ptr(),
+                                   w.data_ptr(), w.numel(), _stream(cost.device)), "edp_dp_marginals")
+    return labels, marg, row_e, tot
 
 
 def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,

@@ -103,6 +103,8 @@ edp_status check_problem(const edp_problem* p, int op) {
     }
     const int64_t b = cost_bound_of(p);
     if (b < 0) return EDP_E_INVALID;  // int32 costs need a declared bound
+    // the min-marginal DP stores its forward terms, which stay within [0, Vmax], in 16 bits
+    if (op == EDP_OP_DP_MARGINALS && vmax_of(p) > 65535) return EDP_E_RANGE;
     if (op == EDP_OP_EDP) {
         // empirical int32 guard for the EDP sums (they grow with the grid extent)
         if ((int64_t)(p->width + p->height) * (b + 4 * vmax_of(p)) * 8 >= ((int64_t)1 << 29)) return EDP_E_RANGE;
@@ -226,6 +228,20 @@ DpLayout dp_layout(const edp_problem* p, int tile) {
     L.row_energy = off;
     off += up((size_t)p->height * 8);
     L.total = off;
+    return L;
+}
+
+// Min-marginal DP: u16 forward terms [cells][QT], row optima [H] int64.
+struct DpmLayout {
+    size_t fwd, row_energy, total;
+};
+
+DpmLayout dpm_layout(const edp_problem* p, int tile) {
+    DpmLayout L{};
+    const size_t cells = (size_t)p->width * p->height;
+    L.fwd = 0;
+    L.row_energy = up(cells * (size_t)qt_of(tile) * 2);
+    L.total = L.row_energy + up((size_t)p->height * 8);
     return L;
 }
 
@@ -585,14 +601,14 @@ void release_plan(edp_batch_plan* p) {
 extern "C" {
 
 edp_status edp_workspace_size(const edp_problem* prob, int32_t op, const edp_tuning* tuning, size_t* bytes) {
-    if (!bytes || (op != EDP_OP_DP && op != EDP_OP_EDP)) return EDP_E_INVALID;
+    if (!bytes || (op != EDP_OP_DP && op != EDP_OP_EDP && op != EDP_OP_DP_MARGINALS)) return EDP_E_INVALID;
     edp_status st = check_problem(prob, op);
     if (st != EDP_OK) return st;
-    if (op == EDP_OP_DP) {
+    if (op == EDP_OP_DP || op == EDP_OP_DP_MARGINALS) {
         int tile = 0;
         st = pick_tile(prob, tuning, &tile);
         if (st != EDP_OK) return st;
-        *bytes = dp_layout(prob, tile).total;
+        *bytes = op == EDP_OP_DP ? dp_layout(prob, tile).total : dpm_layout(prob, tile).total;
         return EDP_OK;
     }
     Launch la{};
@@ -921,6 +937,65 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
         if (st != EDP_OK) return st;
         hipLaunchKernelGGL(flag_error_kernel, dim3(1), dim3(64), 0, s, error, d_energy);
         if (hipGetLastError() != hipSuccess) return EDP_E_HIP;
+    }
+    return EDP_OK;
+}
+
+edp_status edp_dp_marginals(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
+                            int32_t* d_labels, int32_t* d_marginal, int64_t* d_row_energy, int64_t* d_energy,
+                            void* d_ws, size_t ws_bytes, void* stream) {
+    edp_status st = check_problem(prob, EDP_OP_DP_MARGINALS);
+    if (st != EDP_OK) return st;
+    if (!d_cost || !d_labels) return EDP_E_INVALID;
+    if (tuning && (tuning->chunk < 0 || tuning->n_events < 0)) return EDP_E_INVALID;
+    int tile = 0;
+    st = pick_tile(prob, tuning, &tile);
+    if (st != EDP_OK) return st;
+    // 32-bit byte offsets: cost volume, forward terms, marginal output
+    const int64_t cells = (int64_t)prob->width * prob->height;
+    const int64_t q = (int64_t)prob->qx * prob->qy;
+    if (cells * qt_of(tile) * 2 >= 0x7FFF0000LL || cells * q * (prob->dtype == EDP_I16 ? 2 : 4) >= 0x7FFF0000LL ||
+        (d_marginal && cells * q * 4 >= 0x7FFF0000LL))
+        return EDP_E_UNSUPPORTED;
+    const DpmLayout L = dpm_layout(prob, tile);
+    if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0 || ws_bytes < L.total) return EDP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    DpmArgs a{};
+    a.cost = d_cost;
+    a.fwd = ws + L.fwd;
+    a.labels = d_labels;
+    a.marginal = d_marginal;
+    a.row_energy = (int64_t*)(ws + L.row_energy);
+    a.W = prob->width;
+    a.H = prob->height;
+    a.qx = prob->qx;
+    a.qy = prob->qy;
+    a.lam = prob->lambda;
+    a.clipd = (int32_t)clip_of(prob);
+    a.joint = prob->trunc_mode == EDP_TRUNC_JOINT;
+    a.trunc = prob->trunc;
+    a.ms = ms_of(prob);
+    a.squared = prob->prior == EDP_PRIOR_SQUARED;
+    const int rows_per_block = (64 / group_of(tile)) * 4;
+    const int grid = (prob->height + rows_per_block - 1) / rows_per_block;
+    // optional caller events: [0],[1] around the forward sweep, [2],[3] around the backward sweep
+    auto mark = [&](int k) -> bool {
+        return !(tuning && tuning->events && k < tuning->n_events) ||
+               hipEventRecord((hipEvent_t)tuning->events[k], s) == hipSuccess;
+    };
+    if (!mark(0)) return EDP_E_HIP;
+    hipError_t err = launch_dp_marginals(tile, prob->dtype, a, grid, true, s);
+    if (err != hipSuccess || !mark(1) || !mark(2)) return EDP_E_HIP;
+    err = launch_dp_marginals(tile, prob->dtype, a, grid, false, s);
+    if (err != hipSuccess || !mark(3)) return EDP_E_HIP;
+    if (d_row_energy) {
+        err = launch_copy_i64(a.row_energy, d_row_energy, prob->height, s);
+        if (err != hipSuccess) return EDP_E_HIP;
+    }
+    if (d_energy) {
+        err = launch_sum_rows(a.row_energy, prob->height, d_energy, s);
+        if (err != hipSuccess) return EDP_E_HIP;
     }
     return EDP_OK;
 }

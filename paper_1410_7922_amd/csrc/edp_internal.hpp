@@ -152,6 +152,18 @@ struct DpArgs {
     int32_t ibits;           // bits of the label index packed under the value
 };
 
+// The min-marginal scanline DP: forward sweep (terms F), then backward sweep (labels).
+struct DpmArgs {
+    const void* cost;
+    void* fwd;               // [H][W][QT] u16 forward terms M(S_1(x-1)) less their minimum, lane-major
+    int32_t* labels;         // [H][W]
+    int32_t* marginal;       // [H][W][Q] S_Omega less its column minimum, or null
+    int64_t* row_energy;     // [H] chain optima
+    int32_t W, H, qx, qy;
+    int32_t lam, clipd, joint, trunc;
+    int32_t ms, squared;     // minimum search kind MS_*, truncated squared prior
+};
+
 struct BtArgs {
     const void* ptr;
     const int32_t* row_label;
@@ -192,6 +204,8 @@ hipError_t launch_win_prep(const int32_t* cost, const int32_t* centers, int32_t 
                            int32_t win, int32_t big, int32_t* cw, uint32_t* shifts, hipStream_t s);
 hipError_t launch_dp_forward(int tile, int kind, const DpArgs& a, int grid, hipStream_t s);   // a.ms selects the search
 hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
+// dtype: 1 int16, 2 int32 costs
+hipError_t launch_dp_marginals(int tile, int dtype, const DpmArgs& a, int grid, bool forward, hipStream_t s);
 hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);
 hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);

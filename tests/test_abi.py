@@ -65,6 +65,16 @@ def test_int32_costs_need_a_bound_and_range_guard():
     assert _ws(_prob(lam=60000, trunc=4000, qx=64), B.OP_DP)[0] == -2
 
 
+def test_min_marginal_dp_workspace_and_term_range():
+    """The min-marginal DP stores its forward terms in 16 bits: a clip distance above 65535 is refused."""
+    st, n = _ws(_prob(), 2)
+    assert st == 0 and n >= 384 * 288 * 32 * 2
+    assert _ws(_prob(lam=20, trunc=3000, qx=2), 2)[0] == 0      # lambda T = 60000 fits
+    assert _ws(_prob(prior=1, lam=10, trunc=100, qx=4), 2)[0] == -2    # lambda T^2 = 100000
+    assert _ws(_prob(prior=1, lam=10, trunc=50, qx=4), 2)[0] == 0      # lambda T^2 = 25000
+    assert _ws(_prob(), 3)[0] == -1
+
+
 def test_squared_prior_range_guard_and_window_solve():
     """The squared prior's clip lambda T^2 enters both guards; the label-window solve is linear only."""
     assert _ws(_prob(prior=1, lam=5, trunc=3), B.OP_EDP)[0] == 0
