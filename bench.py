@@ -199,6 +199,37 @@ def bench_batch(edp, torch, steps, warmup):
             "graph_ms_per_solve": best["graph_ms_per_solve"]}
 
 
+def bench_dp_marginals(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0):
+    """The min-marginal scanline DP (labels only) on the DP sweep workload of bench_dp.  Algorithmic
+    bytes per pixel-label: forward sweep 2 B cost read + 2 B forward term written, backward sweep
+    the same two read; plus a 4 B label per pixel."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    cost = torch.randint(0, 51, (rows, cols, q), generator=g, device=dev, dtype=torch.int16)
+    ws = edp.Workspace()
+    ev = HipEvents(4 * steps)
+    for _ in range(warmup):
+        edp.dp_marginals(cost, q, 1, 20, 2, cost_bound=51, ws=ws)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for k in range(steps):
+        edp.dp_marginals(cost, q, 1, 20, 2, cost_bound=51, ws=ws, events=ev.view(4 * k, 4))
+    stop.record()
+    torch.cuda.synchronize()
+    total = start.elapsed_time(stop) / steps
+    fwd = sum(ev.ms(4 * k, 4 * k + 1) for k in range(steps)) / steps
+    bwd = sum(ev.ms(4 * k + 2, 4 * k + 3) for k in range(steps)) / steps
+    ev.close()
+    pl = rows * cols * q
+    fwd_bytes, bwd_bytes = pl * 4, pl * 4 + rows * cols * 4
+    return {"workload": f"dp_marginals{cols}x{rows}q{q}_i16", "pixel_labels_per_s": pl / (total / 1e3),
+            "ms_per_step": total, "forward_ms": fwd, "backward_ms": bwd,
+            "forward_GBps": fwd_bytes / (fwd / 1e3) / 1e9, "backward_GBps": bwd_bytes / (bwd / 1e3) / 1e9,
+            "backward_frac_of_hbm": bwd_bytes / (bwd / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
 def bench_dp(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0, prior=0):
     """Scanline DP sweep on uniform int16 costs in [0, 50]: 8192 independent scanlines of 1024
     columns and 64 labels (16 stereo frames of 1024 x 512 with 64 disparities), a bandwidth
@@ -443,6 +474,8 @@ def main():
                            "energy": sr["energy"], "mean_launch_ms": np.array(sr["launch_ms"]).mean(axis=0).tolist()}
             del sr
         extra["dp_sweep_sq"] = bench_dp(edp, torch, max(3, args.steps // 4), 1, prior=1)
+        log("min-marginal scanline DP on the same sweep")
+        extra["dp_marginals"] = bench_dp_marginals(edp, torch, max(3, args.steps // 4), 1)
     if not args.no_batch:
         log("batch of 64 uneven instances (hipGraph replay)")
         extra["batch64"] = bench_batch(edp, torch, max(3, args.steps // 4), 1)

@@ -977,6 +977,10 @@ edp_status edp_dp_marginals(const edp_problem* prob, const edp_tuning* tuning, c
     a.trunc = prob->trunc;
     a.ms = ms_of(prob);
     a.squared = prob->prior == EDP_PRIOR_SQUARED;
+    // the DP range guard keeps (cost bound + Vmax) << ibits below 2^28, so the argmin keys
+    // ((S_Omega + bias) << ibits) | label, S_Omega + bias <= 2 (cost bound + Vmax), fit
+    a.bias = (int32_t)cost_bound_of(prob);
+    a.ibits = ibits_of(prob->qx * prob->qy);
     const int rows_per_block = (64 / group_of(tile)) * 4;
     const int grid = (prob->height + rows_per_block - 1) / rows_per_block;
     // optional caller events: [0],[1] around the forward sweep, [2],[3] around the backward sweep

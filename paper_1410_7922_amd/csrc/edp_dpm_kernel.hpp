@@ -177,7 +177,8 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
                 offset += normalize(s);
             }
         } else {
-            // S_Omega(x) = F(x) + C(x) + B(x) and its smallest argmin
+            // S_Omega(x) = F(x) + C(x) + B(x) and its smallest argmin, found by one minimum over
+            // keys ((S_Omega + bias) << ibits) | label (S_Omega + bias >= 0: F, B >= 0, C >= -bias)
             int32_t mg[KY][KX], s[KY][KX];
             int32_t best = 0x7FFFFFFF;
 #pragma unroll
@@ -186,16 +187,12 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
                 for (int kx = 0; kx < KX; ++kx) {
                     s[ky][kx] = cost_elem<CK, KX>(rc[u][ky], kx) + bterm[ky][kx];
                     mg[ky][kx] = rf[u][ky * KX + kx] + s[ky][kx];
-                    if (valid[ky][kx]) best = imin(best, mg[ky][kx]);
+                    const int32_t key = (int32_t)(((uint32_t)(mg[ky][kx] + a.bias) << a.ibits) | (uint32_t)q[ky][kx]);
+                    if (valid[ky][kx]) best = imin(best, key);
                 }
-            const int32_t mmin = group_min<T>(best, lane);
-            int32_t qb = 0x7FFFFFFF;
-#pragma unroll
-            for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                for (int kx = 0; kx < KX; ++kx)
-                    if (valid[ky][kx] && mg[ky][kx] == mmin) qb = imin(qb, q[ky][kx]);
-            qb = group_min<T>(qb, lane);
+            best = group_min<T>(best, lane);
+            const int32_t qb = best & ((1 << a.ibits) - 1);
+            const int32_t mmin = (best >> a.ibits) - a.bias;
             if (live && rowok && l == 0) a.labels[y * W + x] = qb;
 #pragma unroll
             for (int ky = 0; ky < KY; ++ky)

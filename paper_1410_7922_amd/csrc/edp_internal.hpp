@@ -162,6 +162,7 @@ struct DpmArgs {
     int32_t W, H, qx, qy;
     int32_t lam, clipd, joint, trunc;
     int32_t ms, squared;     // minimum search kind MS_*, truncated squared prior
+    int32_t bias, ibits;     // argmin keys ((S_Omega + bias) << ibits) | label; bias = cost bound
 };
 
 struct BtArgs {
