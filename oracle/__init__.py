@@ -8,6 +8,8 @@ nothing else.
 
 * ``edp_ref``  -- plain numpy / Python: the definitions (straightforward
   minimum search, brute-force DP, exhaustive enumeration, literal EDP).
+* ``dsi_ref``  -- numpy: the data cost of Sec. 2 eq. Cost_value and the
+  composite three-view cost of Sec. 5.1 eq. Cost_cmp.
 * ``cref``     -- ctypes wrapper of ``edp_oracle.c``, the same definitions in
   plain C for full-size workloads (built by ``__graft_entry__.build()``).
 """
