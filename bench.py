@@ -230,6 +230,40 @@ def bench_dp_marginals(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, se
             "backward_frac_of_hbm": bwd_bytes / (bwd / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_dsi(edp, torch, steps, warmup):
+    """Data cost formation (edp_dsi): the 961-label motion volume of the learned-window workload
+    (640x480, int32, 1.18 GB written) and a three-view stereo volume of the paper's setup-2 shape
+    (450x375, 60 disparities, composite cost, int32).  Algorithmic bytes: the volume written
+    (the images are read from cache)."""
+    import synth
+    dev = torch.device("cuda:0")
+    i0, i1, _, _ = synth.motion_frames(0, 640, 480, 15)
+    rng = __import__("numpy").random.default_rng(7)
+    j0, j1, j2 = (torch.from_numpy(rng.integers(0, 256, (375, 450), dtype="uint8")).to(dev) for _ in range(3))
+    a0, a1 = torch.from_numpy(i0).to(dev), torch.from_numpy(i1).to(dev)
+    runs = {"motion640x480_q961_i32": (lambda o: edp.dsi(a0, a1, 31, 31, -15, -15, 1, 1, 2, 2500, out=o),
+                                       (480, 640, 961)),
+            "stereo3view450x375_q60_i32": (lambda o: edp.dsi(j0, j1, 60, 1, 0, 0, -1, 1, 2, 10000, i2=j2, out=o),
+                                           (375, 450, 60))}
+    out = {}
+    for name, (fn, shape) in runs.items():
+        o = torch.empty(shape, dtype=torch.int32, device=dev)
+        for _ in range(warmup):
+            fn(o)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(steps):
+            fn(o)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / steps
+        nbytes = o.numel() * 4
+        out[name] = {"ms": ms, "GBps": nbytes / (ms / 1e3) / 1e9, "frac_of_hbm": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        del o
+    return out
+
+
 def bench_dp(edp, torch, steps, warmup, rows=8192, cols=1024, q=64, seed=0, prior=0):
     """Scanline DP sweep on uniform int16 costs in [0, 50]: 8192 independent scanlines of 1024
     columns and 64 labels (16 stereo frames of 1024 x 512 with 64 disparities), a bandwidth
@@ -474,6 +508,8 @@ def main():
                            "energy": sr["energy"], "mean_launch_ms": np.array(sr["launch_ms"]).mean(axis=0).tolist()}
             del sr
         extra["dp_sweep_sq"] = bench_dp(edp, torch, max(3, args.steps // 4), 1, prior=1)
+        log("data cost formation")
+        extra["dsi"] = bench_dsi(edp, torch, max(3, args.steps // 4), 1)
         log("min-marginal scanline DP on the same sweep")
         extra["dp_marginals"] = bench_dp_marginals(edp, torch, max(3, args.steps // 4), 1)
     if not args.no_batch:

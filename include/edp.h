@@ -227,6 +227,26 @@ edp_status edp_batch_plan_info(const edp_batch_plan* plan, int32_t* n_classes, i
 void edp_batch_plan_destroy(edp_batch_plan* plan);
 
 /*
+ * Data cost (DSI) formation, Sec. 2 eq. Cost_value:
+ *   C(x, v) = min(|I1(x + v) - I0(x)|^l2, cmax),  l2 = 1 or 2,
+ * or, with a third image d_i2 (the composite three-view cost of Sec. 5.1
+ * eq. Cost_cmp, for occlusion handling):
+ *   C(x, v) = min(C_{0->1}(x, v), C_{0->2}(x, -v)).
+ * Label q = iy * qx + ix has the displacement v = (ox + sx * ix, oy + sy * iy),
+ * sx, sy = +1 or -1: rectified stereo with I1 the right image is qy = 1,
+ * ox = 0, sx = -1; motion within [-r, r]^2 is ox = oy = -r, sx = sy = 1.  A
+ * displaced position outside the image costs cmax for that view; |ox|, |oy| <=
+ * 16384.
+ *   d_i0, d_i1  [H][W] uint8 images (device); d_i2 the third view or NULL
+ *   dtype       EDP_I16 (0 <= cmax <= 32767) or EDP_I32 (cmax >= 0)
+ *   d_cost      [H][W][qx*qy] output, aligned to its element size
+ * Only a kernel launch is enqueued; no workspace.
+ */
+edp_status edp_dsi(const uint8_t* d_i0, const uint8_t* d_i1, const uint8_t* d_i2, int32_t width, int32_t height,
+                   int32_t qx, int32_t qy, int32_t ox, int32_t oy, int32_t sx, int32_t sy, int32_t l2, int32_t cmax,
+                   int32_t dtype, void* d_cost, void* stream);
+
+/*
  * Energy of a labelling (Sec. 2 eq. GE_objective_function).
  *   grid4      0: horizontal pairs only (the scanline energy), 1: 4-connected
  *   d_labels   [H][W] int32 labels; labels outside [0, Q) contribute nothing

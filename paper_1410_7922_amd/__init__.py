@@ -6,4 +6,4 @@ The solvers live in ``libedp.so`` (C ABI: include/edp.h); ``binding`` marshals
 torch tensors into it.
 """
 from .binding import (PRIOR_LINEAR, PRIOR_SQUARED, TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace,  # noqa: F401
-                      dp_marginals, dp_scanline, energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)
+                      dp_marginals, dp_scanline, dsi, energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)

@@ -28,7 +28,7 @@ OP_DP_MARGINALS = 2
 EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
            "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
            "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy", "edp_window_workspace_size",
-           "edp_solve_windowed", "edp_dp_marginals")
+           "edp_solve_windowed", "edp_dp_marginals", "edp_dsi")
 
 
 class Problem(ctypes.Structure):
@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
     L.edp_dp_scanline.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, sz, vp]
     L.edp_solve.argtypes = [pprob, ptun, vp, vp, vp, vp, sz, vp]
     L.edp_dp_marginals.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.edp_dsi.argtypes = [vp, vp, vp] + [ctypes.c_int32] * 11 + [vp, vp]
     L.edp_energy.argtypes = [pprob, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.edp_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.edp_tile_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
@@ -86,7 +87,8 @@ def load(path: str = LIB_PATH):
     L.edp_solve_windowed.argtypes = [pprob, ptun, vp, vp, ctypes.c_int32, vp, vp, vp, sz, vp]
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
-                 "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals"):
+                 "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals",
+                 "edp_dsi"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -213,6 +215,26 @@ def dp_marginals(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc:
                                    marg.data_ptr() if marg is not None else None, row_e.data_ptr(), tot.data_ptr(),
                                    w.data_ptr(), w.numel(), _stream(cost.device)), "edp_dp_marginals")
     return labels, marg, row_e, tot
+
+
+def dsi(i0: torch.Tensor, i1: torch.Tensor, qx: int, qy: int = 1, ox: int = 0, oy: int = 0, sx: int = -1,
+        sy: int = 1, l2: int = 1, cmax: int = 50, dtype=torch.int16, i2: torch.Tensor | None = None,
+        out: torch.Tensor | None = None) -> torch.Tensor:
+    """Data cost volume [H][W][qx*qy] (edp_dsi) of uint8 images; with i2 the composite three-view cost."""
+    for t, nm in ((i0, "i0"), (i1, "i1")) + (((i2, "i2"),) if i2 is not None else ()):
+        _device_tensor(t, nm)
+        if t.dtype != torch.uint8 or t.shape != i0.shape or t.dim() != 2:
+            raise ValueError(f"{nm} must be uint8 [H][W] like i0")
+    H, W = i0.shape
+    if out is None:
+        out = torch.empty((H, W, qx * qy), dtype=dtype, device=i0.device)
+    _device_tensor(out, "out")
+    code = EDP_I16 if out.dtype == torch.int16 else EDP_I32 if out.dtype == torch.int32 else 0
+    if code == 0 or tuple(out.shape) != (H, W, qx * qy):
+        raise ValueError("out must be int16 or int32 [H][W][qx*qy]")
+    _check(load().edp_dsi(i0.data_ptr(), i1.data_ptr(), i2.data_ptr() if i2 is not None else None, W, H, qx, qy,
+                          ox, oy, sx, sy, l2, cmax, code, out.data_ptr(), _stream(i0.device)), "edp_dsi")
+    return out
 
 
 def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,

@@ -1004,6 +1004,41 @@ edp_status edp_dp_marginals(const edp_problem* prob, const edp_tuning* tuning, c
     return EDP_OK;
 }
 
+edp_status edp_dsi(const uint8_t* d_i0, const uint8_t* d_i1, const uint8_t* d_i2, int32_t width, int32_t height,
+                   int32_t qx, int32_t qy, int32_t ox, int32_t oy, int32_t sx, int32_t sy, int32_t l2, int32_t cmax,
+                   int32_t dtype, void* d_cost, void* stream) {
+    if (!d_i0 || !d_i1 || !d_cost) return EDP_E_INVALID;
+    if (width < 1 || height < 1 || qx < 1 || qy < 1 || (int64_t)qx * qy > 4096) return EDP_E_INVALID;
+    if ((int64_t)width * height > (int64_t)1 << 30) return EDP_E_INVALID;
+    if ((sx != 1 && sx != -1) || (sy != 1 && sy != -1) || (l2 != 1 && l2 != 2)) return EDP_E_INVALID;
+    // displacements are kept as 16-bit halves: |ox|, |oy| <= 16384 with at most 4096 labels
+    if (ox < -16384 || ox > 16384 || oy < -16384 || oy > 16384) return EDP_E_INVALID;
+    if (dtype != EDP_I16 && dtype != EDP_I32) return EDP_E_INVALID;
+    if (cmax < 0 || (dtype == EDP_I16 && cmax > 32767)) return EDP_E_INVALID;
+    const size_t esize = dtype == EDP_I16 ? 2 : 4;
+    if ((uintptr_t)d_cost % esize != 0) return EDP_E_INVALID;
+    DsiArgs a{};
+    a.i0 = d_i0;
+    a.i1 = d_i1;
+    a.i2 = d_i2;
+    a.cost = d_cost;
+    a.W = width;
+    a.H = height;
+    a.qx = qx;
+    a.qy = qy;
+    a.ox = ox;
+    a.oy = oy;
+    a.sx = sx;
+    a.sy = sy;
+    a.l2 = l2;
+    // 255^2 fits every int32 cmax; the truncation bounds the values by the output type
+    a.cmax = cmax;
+    a.vec = ((uintptr_t)d_cost % 16) == 0;
+    a.inv_q = 1.0 / ((double)qx * qy);
+    a.inv_w = 1.0 / (double)width;
+    return hip_status(launch_dsi(a, dtype, (hipStream_t)stream));
+}
+
 edp_status edp_energy(const edp_problem* prob, const void* d_cost, const int32_t* d_labels, int32_t grid4,
                       int64_t* d_energy, int64_t* d_invalid, void* stream) {
     edp_status st = check_problem(prob, EDP_OP_DP);

@@ -191,6 +191,19 @@ struct BatchEnergyArgs {
     int32_t rows_per_block;
 };
 
+// Data cost formation: [H][W][qx*qy] costs of images i0, i1 (and i2 for the composite cost).
+struct DsiArgs {
+    const uint8_t* i0;
+    const uint8_t* i1;
+    const uint8_t* i2;       // third view or null
+    void* cost;              // int16 or int32 output
+    int32_t W, H, qx, qy;
+    int32_t ox, oy, sx, sy;  // label (ix, iy) has the displacement (ox + sx ix, oy + sy iy)
+    int32_t l2, cmax;
+    int32_t vec;             // output 16-byte aligned: vector stores
+    double inv_q, inv_w;     // 1 / (qx qy), 1 / W
+};
+
 // Launchers (return hipSuccess or the launch error).  dtype: 1 int16, 2 int32.
 // The scan kernel takes a cost kind instead: 1 int16, 2 int32, 3 int16 read in
 // 4-byte aligned pairs (needs an even KX, an even label count, and qx even
@@ -209,6 +222,7 @@ hipError_t launch_dp_backtrack(int tile, const BtArgs& a, hipStream_t s);
 hipError_t launch_dp_marginals(int tile, int dtype, const DpmArgs& a, int grid, bool forward, hipStream_t s);
 hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);
 hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s);
+hipError_t launch_dsi(const DsiArgs& a, int dtype, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_sum_rows(const int64_t* rows, int32_t n, int64_t* out, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStream_t s);

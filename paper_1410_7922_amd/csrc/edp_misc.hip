@@ -1,5 +1,6 @@
 // Energy of a labelling (Mozerov, arXiv 1410.7922, Sec. 2 eq.
-// GE_objective_function with the truncated linear or squared prior) and small helpers.
+// GE_objective_function with the truncated linear or squared prior), data cost
+// formation (Sec. 2 eq. Cost_value, Sec. 5.1 eq. Cost_cmp) and small helpers.
 #include "edp_device.hpp"
 #include "edp_internal.hpp"
 
@@ -194,6 +195,109 @@ hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hi
         hipLaunchKernelGGL(batch_energy_kernel<int16_t>, dim3(grid), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(batch_energy_kernel<int32_t>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---- data cost (DSI) formation -------------------------------------------------------------
+// Sec. 2 eq. Cost_value, min(|I1(x + v) - I0(x)|^l2, cmax), and with a third image the composite
+// cost of Sec. 5.1 eq. Cost_cmp, min(C_{0->1}(x, v), C_{0->2}(x, -v)).  Each thread forms V
+// consecutive elements of the [H][W][Q] volume (16 bytes) and stores them with one vector store.
+// The kernel is bound by its per-element instructions: the displacements of all labels sit in an
+// LDS table (dx, dy as two 16-bit halves), so an element costs a table read, the displaced
+// position and its bounds, two byte loads and the truncated difference; the step to the next
+// label, pixel and row is made of selects, so the code is straight-line and the loads of all V
+// elements are in flight together.  An out-of-image position uses the out-of-range buffer offset (the load
+// returns 0) and the element takes cmax.
+template <int L2>
+__device__ __forceinline__ int32_t dsi_view(__amdgpu_buffer_rsrc_t img, int32_t c0, int32_t x, int32_t y,
+                                            int32_t W, int32_t H, int32_t cmax) {
+    const bool ok = (uint32_t)x < (uint32_t)W && (uint32_t)y < (uint32_t)H;
+    int32_t d = (int32_t)__builtin_amdgcn_raw_buffer_load_b8(img, ok ? y * W + x : OOB, 0, 0) - c0;
+    d = d < 0 ? -d : d;
+    if constexpr (L2 == 2) d *= d;
+    d = d < cmax ? d : cmax;
+    // the truncated cost is at most cmax: raising it to cmax off the image takes no select on the
+    // loaded value, so the load is not moved under a branch
+    const int32_t floor_v = ok ? 0 : cmax;
+    return d > floor_v ? d : floor_v;
+}
+
+template <class CT, int L2, bool COMP>
+__global__ __launch_bounds__(256) void dsi_kernel(const DsiArgs a) {
+    constexpr int V = 16 / (int)sizeof(CT);
+    extern __shared__ int32_t disp[];                  // [Q] (dx & 0xFFFF) | (dy << 16)
+    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy;
+    for (int32_t i = threadIdx.x; i < Q; i += blockDim.x) {
+        const int32_t iy = i / a.qx, ix = i - iy * a.qx;
+        const int32_t dx = a.ox + a.sx * ix, dy = a.oy + a.sy * iy;
+        disp[i] = (int32_t)(((uint32_t)dx & 0xFFFFu) | ((uint32_t)dy << 16));
+    }
+    __syncthreads();
+    const int64_t n = (int64_t)W * H * Q;
+    const __amdgpu_buffer_rsrc_t r0 = make_rsrc(a.i0, W * H);
+    const __amdgpu_buffer_rsrc_t r1 = make_rsrc(a.i1, W * H);
+    const __amdgpu_buffer_rsrc_t r2 = make_rsrc(a.i2, COMP ? W * H : 0);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * V;
+    for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V; base < n; base += stride) {
+        // base / Q and pix / W through double reciprocals: (e + 1/2) / d is at least 1/(2d) away
+        // from an integer and the product's error is far below that for e < 2^50, so the floor is
+        // exact (a 64-bit integer division costs more than the 16 bytes it indexes)
+        const int64_t pix = (int64_t)(((double)base + 0.5) * a.inv_q);
+        int32_t q = (int32_t)(base - pix * Q);
+        int32_t y = (int32_t)(((double)pix + 0.5) * a.inv_w), x = (int32_t)(pix - (int64_t)y * W);
+        CT out[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            // every element loads its own I0 byte (a cache hit)
+            const int32_t c0 = (int32_t)__builtin_amdgcn_raw_buffer_load_b8(r0, y < H ? y * W + x : OOB, 0, 0);
+            const int32_t t = disp[q];
+            const int32_t dx = (int32_t)(int16_t)(t & 0xFFFF), dy = t >> 16;
+            int32_t c = dsi_view<L2>(r1, c0, x + dx, y + dy, W, H, a.cmax);
+            if constexpr (COMP) {
+                const int32_t c2 = dsi_view<L2>(r2, c0, x - dx, y - dy, W, H, a.cmax);
+                c = c < c2 ? c : c2;
+            }
+            out[k] = (CT)c;
+            // next element, with selects only: straight-line code lets every load go out first
+            const bool next_pixel = ++q == Q;
+            q = next_pixel ? 0 : q;
+            x += next_pixel ? 1 : 0;
+            const bool next_row = x == W;
+            x = next_row ? 0 : x;
+            y += next_row ? 1 : 0;
+        }
+        CT* dst = (CT*)a.cost + base;
+        if (a.vec && base + V <= n) {
+            uint4 w;
+            __builtin_memcpy(&w, out, 16);
+            *(uint4*)dst = w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (base + k < n) dst[k] = out[k];
+        }
+    }
+}
+
+template <class CT>
+static void run_dsi(const DsiArgs& a, int grid, hipStream_t s) {
+    const size_t lds = (size_t)a.qx * a.qy * 4;
+    if (a.l2 == 2) {
+        if (a.i2) hipLaunchKernelGGL((dsi_kernel<CT, 2, true>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((dsi_kernel<CT, 2, false>), dim3(grid), dim3(256), lds, s, a);
+    } else {
+        if (a.i2) hipLaunchKernelGGL((dsi_kernel<CT, 1, true>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((dsi_kernel<CT, 1, false>), dim3(grid), dim3(256), lds, s, a);
+    }
+}
+
+hipError_t launch_dsi(const DsiArgs& a, int dtype, hipStream_t s) {
+    const int V = dtype == 1 ? 8 : 4;
+    const int64_t n = (int64_t)a.W * a.H * a.qx * a.qy;
+    int64_t grid = (n / V + 255) / 256 + 1;
+    if (grid > 65536) grid = 65536;
+    if (dtype == 1) run_dsi<int16_t>(a, (int)grid, s);
+    else run_dsi<int32_t>(a, (int)grid, s);
     return hipGetLastError();
 }
 

@@ -191,7 +191,8 @@ def stereo_problem(seed: int = 0, W: int = 384, H: int = 288, Q: int = 32, lam: 
         diff = np.abs(left_n[:, d:] - right_n[:, :W - d])
         cost[:, d:, d] = np.minimum(diff, cmax)
     return Problem(np.ascontiguousarray(cost.astype(dtype)), Q, 1, lam, trunc, TRUNC_PER_DIM,
-                   name=f"stereo{W}x{H}q{Q}s{seed}", meta={"gt": disp, "frames": (left_n, right_n)})
+                   name=f"stereo{W}x{H}q{Q}s{seed}",
+                   meta={"gt": disp, "frames": (left_n.astype(np.uint8), right_n.astype(np.uint8))})
 
 
 def motion_frames(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, segments: int = 8,

@@ -65,6 +65,22 @@ def test_int32_costs_need_a_bound_and_range_guard():
     assert _ws(_prob(lam=60000, trunc=4000, qx=64), B.OP_DP)[0] == -2
 
 
+def test_dsi_rejects_bad_arguments_on_the_host():
+    L = B.load()
+    ok = dict(i0=16, i1=16, i2=None, w=8, h=4, qx=4, qy=1, ox=0, oy=0, sx=-1, sy=1, l2=1, cmax=50, dt=1, out=256)
+
+    def call(**kw):
+        d = dict(ok)
+        d.update(kw)
+        return L.edp_dsi(d["i0"], d["i1"], d["i2"], d["w"], d["h"], d["qx"], d["qy"], d["ox"], d["oy"], d["sx"],
+                         d["sy"], d["l2"], d["cmax"], d["dt"], d["out"], None)
+
+    for bad in (dict(i0=None), dict(out=None), dict(w=0), dict(qx=0), dict(qx=65, qy=65), dict(sx=2), dict(sy=0),
+                dict(l2=3), dict(cmax=-1), dict(cmax=40000), dict(dt=3), dict(out=257), dict(ox=16385),
+                dict(oy=-20000)):
+        assert call(**bad) == -1, bad
+
+
 def test_min_marginal_dp_workspace_and_term_range():
     """The min-marginal DP stores its forward terms in 16 bits: a clip distance above 65535 is refused."""
     st, n = _ws(_prob(), 2)
