@@ -916,7 +916,8 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     c.ring = la.ring;
     c.fuse = la.fuse;
     c.iterations = prob->iterations;
-    c.ms = MS_LINEAR;          // the window kernel runs its own search between shifted frames
+    // the window kernel's own search between shifted frames: the general RMS window for T <= 3
+    c.ms = prob->trunc <= 3 ? MS_WINDOW : MS_LINEAR;
     c.one = make_desc(&f, la, E.inst, ws, flags, ws + E.hand, cw, d_labels, nullptr);
     c.one.aux = shifts;
     c.one.centers = d_centers;

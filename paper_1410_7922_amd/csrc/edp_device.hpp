@@ -602,6 +602,51 @@ __device__ __forceinline__ int32_t l1_line_shift(int32_t (&val)[K], const int32_
     return m;
 }
 
+// The same between shifted frames with the general RMS window (one label per lane, windows of
+// at most two steps per side): target label j takes the source labels i = j + d - u, |u| <= nw,
+// that lie in the source frame, each plus lam |u|, read from their lanes with ds_bpermute (the
+// five reads are independent of each other), then the clip.  Source labels outside the frame
+// do not exist for the neighbour, as in l1_line_shift.  Returns min val of the line.
+template <int NL, int STEP>
+__device__ __forceinline__ int32_t window_line_shift(int32_t& val, const int32_t (&pen)[2], const int32_t nw,
+                                                     const int32_t clipd, const bool clip, const int32_t pos,
+                                                     const int32_t lane, const int32_t d) {
+    const int32_t m = line_min<NL, STEP>(val, lane);
+    const int32_t base = lane - pos * STEP;           // lane of position 0 of this line
+    const int32_t s = pos + d;
+    // a target with no source label in its window keeps PADV, which the next dimension's
+    // penalties cannot carry past int32 (joint truncation clips only at the end)
+    int32_t o = PADV;
+#pragma unroll
+    for (int u = -2; u <= 2; ++u) {
+        const int32_t i = s - u;
+        const int au = u < 0 ? -u : u;
+        const bool ok = (uint32_t)i < (uint32_t)NL && au <= nw;
+        const int32_t v = __builtin_amdgcn_ds_bpermute((base + (ok ? i : 0) * STEP) * 4, val);
+        const int32_t c = au == 0 ? v : v + pen[au - 1];
+        o = ok ? imin(o, c) : o;
+    }
+    val = clip ? imin(o, m + clipd) : o;
+    return m;
+}
+
+// M between shifted frames by the general RMS window, for tiles of one label per lane;
+// nw = T - 1 <= 2 (the frame is the source's whole label range).  Same contract as
+// min_search_shift.
+template <class T>
+__device__ __forceinline__ void min_search_shift_window(int32_t (&h)[T::KY][T::KX], const WinPen& wp,
+                                                        const int32_t clipd, const bool joint, const int32_t lane,
+                                                        const int32_t dx, const int32_t dy) {
+    static_assert(T::KX == 1 && T::KY == 1, "one label per lane");
+    const int32_t l = lane % T::G;
+    const int32_t px = l % T::PX, py = l / T::PX;
+    const int32_t rowmin = window_line_shift<T::PX, 1>(h[0][0], wp.px, wp.nwx, clipd, !joint, px, lane, dx);
+    int32_t gmin = rowmin;
+    if constexpr (T::PY > 1) gmin = line_min<T::PY, T::PX>(gmin, lane);
+    window_line_shift<T::PY, T::PX>(h[0][0], wp.py, wp.nwy, clipd, !joint, py, lane, dy);
+    if (joint) h[0][0] = imin(h[0][0], gmin + clipd);
+}
+
 // Minimum of v over the G lanes of this lane's group.
 template <class T>
 __device__ __forceinline__ int32_t group_min(int32_t v, const int32_t lane) {

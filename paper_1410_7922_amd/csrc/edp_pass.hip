@@ -9,8 +9,8 @@ template <int ID, int MS>
 hipError_t pass_tile(int kind, int split, const PassArgs& a, int grid, int waves, hipStream_t s);
 template <int ID, int MS> int occupancy_tile(int kind, int split, int waves, size_t lds);
 template <int ID> hipError_t aggregate_tile(int dtype, const AggArgs& a, int grid, hipStream_t s);
-hipError_t pass_win(const PassArgs& a, int grid, int waves, hipStream_t s);
-int occupancy_win(int waves, size_t lds_bytes);
+hipError_t pass_win(const PassArgs& a, int grid, int waves, int ms, hipStream_t s);
+int occupancy_win(int waves, int ms, size_t lds_bytes);
 hipError_t aggregate_win(const AggArgs& a, int grid, hipStream_t s);
 
 // counters, ticket word, trash slot, then one ring per compute wavefront plus the helper's
@@ -22,7 +22,8 @@ hipError_t launch_edp_pass(int tile, int dtype, int split, int ms, const PassArg
                            hipStream_t s) {
     if (waves < 1 || waves > MAX_WAVES) return hipErrorInvalidValue;
     if (dtype == KIND_WINDOW)
-        return tile == WIN_TILE && split == 1 && ms == MS_LINEAR ? pass_win(a, grid, waves, s) : hipErrorInvalidValue;
+        return tile == WIN_TILE && split == 1 && (ms == MS_LINEAR || ms == MS_WINDOW) ? pass_win(a, grid, waves, ms, s)
+                                                                                     : hipErrorInvalidValue;
     switch (tile) {
 #define EDP_CASE(id, px, kx, py, ky)                                                                   \
     case id:                                                                                           \
@@ -51,7 +52,7 @@ hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid,
 int pass_capacity(int tile, int dtype, int split, int ms, int waves, size_t lds_bytes) {
     int per_cu = 1;
     if (dtype == KIND_WINDOW) {
-        per_cu = occupancy_win(waves, lds_bytes);
+        per_cu = occupancy_win(waves, ms, lds_bytes);
         tile = -1;
     }
     switch (tile) {

@@ -517,8 +517,13 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                     const int32_t cb = rsh[u][1] >> (sy > 0 ? 0 : 16);
                     const int32_t dxa = (int32_t)(int8_t)(ca & 0xFF), dya = (int32_t)(int8_t)((ca >> 8) & 0xFF);
                     const int32_t dxb = (int32_t)(int8_t)(cb & 0xFF), dyb = (int32_t)(int8_t)((cb >> 8) & 0xFF);
-                    min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
-                    min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
+                    if constexpr (MS == MS_WINDOW) {
+                        min_search_shift_window<T>(h, sp, d.clipd, joint, lane, dxa, dya);
+                        min_search_shift_window<T>(h2, sp, d.clipd, joint, lane, dxb, dyb);
+                    } else {
+                        min_search_shift<T>(h, d.lam, d.clipd, joint, lane, dxa, dya, wscr);
+                        min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
+                    }
                 } else if constexpr (MS != MS_LINEAR) {
                     min_search_window<T, MS == MS_WALK>(h, sp, d.clipd, joint, lane);
                     if constexpr (SPLIT == 1) min_search_window<T, MS == MS_WALK>(h2, sp, d.clipd, joint, lane);

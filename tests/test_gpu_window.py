@@ -48,6 +48,10 @@ CASES = [
     (1, 9, 9, 5, 4, 2, 0, 1, False),
     (9, 1, 9, 5, 4, 2, 0, 2, False),
     (40, 37, 31, 7, 15, 3, 0, 1, True),
+    # T <= 3 runs the general RMS window between frames, larger T the linear RMS transform
+    (15, 10, 13, 5, 7, 1, 0, 1, False),
+    (17, 11, 15, 5, 9, 4, 0, 1, False),
+    (14, 12, 21, 7, 6, 6, 1, 2, True),
 ]
 
 
