@@ -259,7 +259,8 @@ def bench_dsi(edp, torch, steps, warmup):
         torch.cuda.synchronize()
         ms = start.elapsed_time(stop) / steps
         nbytes = o.numel() * 4
-        out[name] = {"ms": ms, "GBps": nbytes / (ms / 1e3) / 1e9, "frac_of_hbm": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        gbps = nbytes / (ms / 1e3) / 1e9
+        out[name] = {"ms": ms, "GBps": gbps, "frac_of_hbm": gbps / HBM_PEAK_GBS}
         del o
     return out
 

@@ -5,5 +5,6 @@ Algorithm for Energy Minimization in Stereo and Motion", arXiv 1410.7922.
 The solvers live in ``libedp.so`` (C ABI: include/edp.h); ``binding`` marshals
 torch tensors into it.
 """
-from .binding import (PRIOR_LINEAR, PRIOR_SQUARED, TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace,  # noqa: F401
-                      dp_marginals, dp_scanline, dsi, energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)
+from .binding import (  # noqa: F401
+    PRIOR_LINEAR, PRIOR_SQUARED, TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace, dp_marginals,
+    dp_scanline, dsi, energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)

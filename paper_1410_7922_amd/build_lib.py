@@ -10,9 +10,15 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libedp.so")
-SOURCES = ["edp_pass_t0.hip", "edp_pass_t1.hip", "edp_pass_t2.hip", "edp_pass_t3.hip", "edp_pass_q0.hip", "edp_pass_q1.hip",
-           "edp_pass_q2.hip", "edp_pass_q3.hip", "edp_api.hip", "edp_pass.hip",
-           "edp_dp.hip", "edp_dpm.hip", "edp_dpm_a.hip", "edp_dpm_b.hip", "edp_dpm_c.hip", "edp_misc.hip", "edp_cnn.hip", "edp_learn_api.hip"]
+SOURCES = [
+    # scan and marginal kernels: linear RMS (t*) and general RMS window kinds (q*) per tile group
+    "edp_pass_t0.hip", "edp_pass_t1.hip", "edp_pass_t2.hip", "edp_pass_t3.hip",
+    "edp_pass_q0.hip", "edp_pass_q1.hip", "edp_pass_q2.hip", "edp_pass_q3.hip",
+    "edp_api.hip", "edp_pass.hip",
+    # scanline DP: choice indexes and backtracking; min-marginals per tile group
+    "edp_dp.hip", "edp_dpm.hip", "edp_dpm_a.hip", "edp_dpm_b.hip", "edp_dpm_c.hip",
+    "edp_misc.hip", "edp_cnn.hip", "edp_learn_api.hip",
+]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

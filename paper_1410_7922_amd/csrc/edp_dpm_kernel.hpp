@@ -55,7 +55,8 @@ __device__ __forceinline__ void store_terms(__amdgpu_buffer_rsrc_t r, int32_t of
     } else {
         int32_t w[E / 2];
 #pragma unroll
-        for (int k = 0; k < E / 2; ++k) w[k] = (int32_t)(((uint32_t)v[2 * k] & 0xFFFFu) | ((uint32_t)v[2 * k + 1] << 16));
+        for (int k = 0; k < E / 2; ++k)
+            w[k] = (int32_t)(((uint32_t)v[2 * k] & 0xFFFFu) | ((uint32_t)v[2 * k + 1] << 16));
         store_vec<E / 2>(r, off, w);
     }
 }
