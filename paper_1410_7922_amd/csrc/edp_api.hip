@@ -247,10 +247,6 @@ DpmLayout dpm_layout(const edp_problem* p, int tile) {
 
 edp_status hip_status(hipError_t e) { return e == hipSuccess ? EDP_OK : EDP_E_HIP; }
 
-__global__ void flag_error_kernel(const uint32_t* error, int64_t* energy) {
-    if (threadIdx.x == 0 && *error != 0) *energy = INT64_MIN;
-}
-
 // Batch: clear the energy words before the energy kernel adds into them, and
 // mark every energy of a class whose scans gave up waiting.
 __global__ void zero_energies_kernel(const InstDesc* descs, int32_t n) {
@@ -427,8 +423,11 @@ WinLayout win_layout(const edp_problem* prob, const Launch& la) {
     return L;
 }
 
+// error (nullable): the solve's error word; zeroed: the energy word was cleared with the solve's
+// control words
 edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t* labels, int grid4,
-                          int64_t* energy, int64_t* invalid, hipStream_t s) {
+                          int64_t* energy, int64_t* invalid, hipStream_t s, const uint32_t* error = nullptr,
+                          bool zeroed = false) {
     EnergyArgs e{};
     e.cost = cost;
     e.labels = labels;
@@ -443,7 +442,8 @@ edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t*
     e.joint = p->trunc_mode == EDP_TRUNC_JOINT;
     e.grid4 = grid4;
     e.squared = p->prior == EDP_PRIOR_SQUARED;
-    hipError_t err = launch_fill_u32((uint32_t*)energy, 2, 0, s);
+    e.error = error;
+    hipError_t err = zeroed ? hipSuccess : launch_fill_u32((uint32_t*)energy, 2, 0, s);
     if (err == hipSuccess && invalid) err = launch_fill_u32((uint32_t*)invalid, 2, 0, s);
     if (err == hipSuccess) err = launch_energy(p->dtype, e, s);
     return hip_status(err);
@@ -710,7 +710,9 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     uint32_t* tickets = ctrl + L.nflags;
     uint32_t* error = tickets + L.ntickets;
 
-    if (launch_fill_u32(ctrl, L.nclear, 0, s) != hipSuccess) return EDP_E_HIP;
+    // control words, and the energy word the energy kernel adds into, cleared in one launch
+    if (launch_fill_u32_with(ctrl, L.nclear, (uint32_t*)d_energy, d_energy ? 2 : 0, 0, s) != hipSuccess)
+        return EDP_E_HIP;
     ClassRun c{};
     c.tile = la.tile;
     c.kind = cost_kind(prob, la.tile, d_cost);
@@ -734,10 +736,8 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     st = enqueue_class(c, tuning, s);
     if (st != EDP_OK) return st;
     if (d_energy) {
-        st = enqueue_energy(prob, d_cost, d_labels, 1, d_energy, nullptr, s);
+        st = enqueue_energy(prob, d_cost, d_labels, 1, d_energy, nullptr, s, error, true);
         if (st != EDP_OK) return st;
-        hipLaunchKernelGGL(flag_error_kernel, dim3(1), dim3(64), 0, s, error, d_energy);
-        if (hipGetLastError() != hipSuccess) return EDP_E_HIP;
     }
     return EDP_OK;
 }
@@ -934,10 +934,8 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     st = enqueue_class(c, tuning, s);
     if (st != EDP_OK) return st;
     if (d_energy) {
-        st = enqueue_energy(prob, d_cost, d_labels, 1, d_energy, nullptr, s);
+        st = enqueue_energy(prob, d_cost, d_labels, 1, d_energy, nullptr, s, error);
         if (st != EDP_OK) return st;
-        hipLaunchKernelGGL(flag_error_kernel, dim3(1), dim3(64), 0, s, error, d_energy);
-        if (hipGetLastError() != hipSuccess) return EDP_E_HIP;
     }
     return EDP_OK;
 }

@@ -181,6 +181,7 @@ struct EnergyArgs {
     int32_t W, H, qx, qy;
     int32_t lam, trunc, joint, grid4;
     int32_t squared;         // truncated squared prior
+    const uint32_t* error;   // the solve's error word (nonzero: energy = INT64_MIN), or null
 };
 
 // Energies of every instance of a batch (4-connected): block b works on rows of
@@ -224,6 +225,8 @@ hipError_t launch_energy(int dtype, const EnergyArgs& a, hipStream_t s);
 hipError_t launch_batch_energy(int dtype, const BatchEnergyArgs& a, int grid, hipStream_t s);
 hipError_t launch_dsi(const DsiArgs& a, int dtype, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+// the same, plus the n2 (<= 256) words at p2 in the same launch
+hipError_t launch_fill_u32_with(uint32_t* p, size_t n, uint32_t* p2, uint32_t n2, uint32_t v, hipStream_t s);
 hipError_t launch_sum_rows(const int64_t* rows, int32_t n, int64_t* out, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int32_t n, hipStream_t s);
 

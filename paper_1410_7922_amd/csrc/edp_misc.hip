@@ -58,7 +58,12 @@ __global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicAdd(a.energy, (unsigned long long)sacc[0]);
+        // a solve whose scans gave up waiting reports INT64_MIN: no block adds, block 0 stores it
+        if (a.error && *a.error != 0) {
+            if (blockIdx.x == 0) *a.energy = (unsigned long long)INT64_MIN;
+        } else {
+            atomicAdd(a.energy, (unsigned long long)sacc[0]);
+        }
         if (a.invalid) atomicAdd(a.invalid, sbad[0]);
     }
 }
@@ -101,7 +106,9 @@ __global__ __launch_bounds__(256) void batch_energy_kernel(const BatchEnergyArgs
 }
 
 // p[0 .. n) = v; the words from the first 16-byte boundary on go out four at a time
-__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+// p[0, n) = v (16-byte stores), and the few words p2[0, n2) = v as well (block 0)
+__global__ void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v, uint32_t* p2, uint32_t n2) {
+    if (blockIdx.x == 0 && threadIdx.x < n2) p2[threadIdx.x] = v;
     const size_t head = ((16 - ((uintptr_t)p & 15)) & 15) / 4;
     const size_t h = head < n ? head : n;
     const size_t nv = (n - h) / 4;
@@ -302,10 +309,14 @@ hipError_t launch_dsi(const DsiArgs& a, int dtype, hipStream_t s) {
 }
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
-    if (n == 0) return hipSuccess;
+    return launch_fill_u32_with(p, n, nullptr, 0, v, s);
+}
+
+hipError_t launch_fill_u32_with(uint32_t* p, size_t n, uint32_t* p2, uint32_t n2, uint32_t v, hipStream_t s) {
+    if (n == 0 && n2 == 0) return hipSuccess;
     size_t grid = (n / 4 + 255) / 256 + 1;
     if (grid > 2048) grid = 2048;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)grid), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)grid), dim3(256), 0, s, p, n, v, p2, n2);
     return hipGetLastError();
 }
 
