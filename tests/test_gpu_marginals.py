@@ -97,3 +97,33 @@ def test_marginals_without_marginal_output_and_workspace_reuse():
         torch.cuda.synchronize()
         assert exc is None
         assert np.array_equal(lab.cpu().numpy(), lab_ref)
+
+
+def test_data_cost_and_marginals_replay_from_a_graph():
+    """edp_dsi and edp_dp_marginals enqueue kernels only: captured into a hipGraph they give the
+    eager results on every replay, with eager work and synchronisations between the replays."""
+    m = synth.workload("motion320x240")
+    i0, i1 = (to_dev(f) for f in m.meta["frames"])
+    ws = edp.Workspace()
+    cost = torch.empty((240, 320, 225), dtype=torch.int32, device=DEV)
+    edp.dsi(i0, i1, 15, 15, -7, -7, 1, 1, 2, 2500, out=cost)
+    lab0, exc0, row0, tot0 = edp.dp_marginals(cost, 15, 15, 15, 3, 0, cost_bound=2500, ws=ws, marginal=True)
+    torch.cuda.synchronize()
+    ref = (lab0.clone(), exc0.clone(), row0.clone(), tot0.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    note("graph capture of edp_dsi + edp_dp_marginals")
+    with torch.cuda.graph(g, stream=side):
+        edp.dsi(i0, i1, 15, 15, -7, -7, 1, 1, 2, 2500, out=cost)
+        out = edp.dp_marginals(cost, 15, 15, 15, 3, 0, cost_bound=2500, ws=ws, marginal=True)
+    for r in range(3):
+        cost.zero_()
+        for t in out:
+            t.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(cost.cpu().numpy(), m.cost), r
+        for got, want in zip(out, ref):
+            assert torch.equal(got, want), r
