@@ -470,7 +470,14 @@ __device__ __forceinline__ void quad_window(int32_t (&val)[K], const int32_t (&p
     for (int h = 1; h <= HOPS; ++h)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if constexpr (NL > 1) {
+            if constexpr (NL * STEP > 16) {
+                // lines across 16-lane rows: one ds_bpermute per move (the permlane route
+                // takes a DPP rotation, two swaps and selects)
+                const int32_t u = __builtin_amdgcn_ds_bpermute((lane - STEP) * 4, lo[h - 1][k]);
+                const int32_t d = __builtin_amdgcn_ds_bpermute((lane + STEP) * 4, hi[h - 1][k]);
+                lo[h][k] = pos == 0 ? PADV : u;
+                hi[h][k] = pos == NL - 1 ? PADV : d;
+            } else if constexpr (NL > 1) {
                 lo[h][k] = carry_up<NL, STEP, PADV>(lo[h - 1][k], pos, lane);
                 hi[h][k] = carry_down<NL, STEP, PADV>(hi[h - 1][k], pos, lane);
             } else {
