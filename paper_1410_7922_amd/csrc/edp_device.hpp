@@ -11,7 +11,8 @@
 // Cross-lane exchange uses DPP inside 16-lane rows (row_shr / row_shl /
 // row_ror / mirrors / quad permutes, a few cycles each) and the gfx950
 // v_permlane16_swap / v_permlane32_swap instructions to move data between
-// rows; ds_bpermute is used by no hot loop.
+// rows, and ds_bpermute where a move crosses rows and the permlane route would
+// take several instructions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -188,19 +189,6 @@ __device__ __forceinline__ int32_t lanes_down(int32_t v, int32_t lane) {
         return (lane & 15) < 16 - N ? t : rows_down(t, lane);
     }
 }
-// Value of lane (lane ^ N) for N = 16 or 32.
-template <int N>
-__device__ __forceinline__ int32_t lanes_xor(int32_t v, int32_t lane) {
-    if constexpr (N == 32) {
-        const auto a = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-        return lane < 32 ? (int32_t)a[1] : (int32_t)a[0];
-    } else {
-        static_assert(N == 16, "xor");
-        const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-        return (lane & 16) ? (int32_t)a[0] : (int32_t)a[1];
-    }
-}
-
 // ---- lines of NL lanes, STEP lanes apart ------------------------------------
 // pos is the lane's index along its line.  Lines of x (STEP = 1) lie in one
 // lane row when NL <= 16; lines of y (STEP = PX) fill whole rows.
@@ -255,8 +243,9 @@ __device__ __forceinline__ int32_t line_min(int32_t v, int32_t lane) {
             if constexpr (STEP <= 4) v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, dpp_row_ror(4), 0xF, 0xF, false));
             if constexpr (STEP <= 8) v = mx(v, __builtin_amdgcn_update_dpp(0x7FFFFFFF, v, dpp_row_ror(8), 0xF, 0xF, false));
         }
-        if constexpr (NL * STEP >= 32) v = mx(v, lanes_xor<16>(v, lane));
-        if constexpr (NL * STEP >= 64) v = mx(v, lanes_xor<32>(v, lane));
+        // across rows: the lanes 16 and 32 apart, one ds_bpermute each
+        if constexpr (NL * STEP >= 32) v = mx(v, __builtin_amdgcn_ds_bpermute((lane ^ 16) * 4, v));
+        if constexpr (NL * STEP >= 64) v = mx(v, __builtin_amdgcn_ds_bpermute((lane ^ 32) * 4, v));
         return v;
     }
 }
