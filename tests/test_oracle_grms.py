@@ -195,3 +195,17 @@ def test_linear_rms_refuses_the_squared_prior():
         R.edp(np.zeros((2, 2, 3), np.int32), 3, 1, 1, 2, 0, search="lrms", prior=QUAD)
     with pytest.raises(RuntimeError):
         cref.min_search(np.zeros((1, 3), np.int64), 3, 1, 1, 2, 0, "lrms", prior=QUAD)
+
+
+def test_squared_prior_min_marginals():
+    """Sec. 4.1 eq. DP_1D_3 with the squared prior: min_v S_Omega(x, v) is the chain optimum at every
+    x (exhaustive enumeration), and its argmin is the optimal labelling where that is unique."""
+    for seed in range(4):
+        p = synth.random_problem(seed, 6, 2, 4, 1, 3, 3, 0, 0, 40)
+        for y in range(2):
+            best, canon = R.chain_exhaustive(p.cost[y], 4, 1, 3, 3, 0, prior=QUAD)
+            marg = R.dp_min_marginals(p.cost[y], 4, 1, 3, 3, 0, prior=QUAD)
+            assert (marg.min(axis=1) == best).all()
+            srt = np.sort(marg, axis=1)
+            if (srt[:, 0] < srt[:, 1]).all():
+                assert list(np.argmin(marg, axis=1)) == list(canon)
