@@ -9,14 +9,15 @@
 // whose smallest argmin is the label of x (eq. DP_1D_5).  No choice indexes are
 // stored and no path is walked back: every label comes out of its own column.
 //
-// Both sweeps subtract the vertex minimum from S before the minimum search, so
-// the searched vectors start at 0 and M keeps them within [0, Vmax], Vmax the
+// Both sweeps subtract from M(S) the minimum of S, which the minimum search
+// returns with no extra reduction: M(S) - min S lies within [0, Vmax], Vmax the
 // clip distance of the prior (lambda f(T), twice that for per-dimension
-// truncation in two label dimensions): the forward terms are stored in 16 bits
-// (the host refuses problems whose Vmax exceeds 65535).  Subtracting a constant per column shifts S_Omega by
-// a constant per column, which changes neither its argmin nor its excess over
-// its minimum; the row optimum is the sum of the forward sweep's subtracted
-// minima.  The minimum search is the scan kernels' (linear RMS or general RMS
+// truncation in two label dimensions), so the forward terms are stored in 16
+// bits (the host refuses problems whose Vmax exceeds 65535) and the searched
+// vectors stay within the cost range plus Vmax.  Subtracting a constant per
+// column shifts S_Omega by a constant per column, which changes neither its
+// argmin nor its excess over its minimum; the row optimum is the sum of the
+// forward sweep's subtracted minima plus the minimum of its last S.  The minimum search is the scan kernels' (linear RMS or general RMS
 // window, one kernel per kind).
 #pragma once
 
@@ -61,11 +62,12 @@ __device__ __forceinline__ void store_terms(__amdgpu_buffer_rsrc_t r, int32_t of
     }
 }
 
+// M in place; returns the minimum of h over the vertex (on entry)
 template <class T, int MS>
-__device__ __forceinline__ void msearch(int32_t (&h)[T::KY][T::KX], const LineIndex<T>& li, const WinPen& wp,
-                                        const int32_t clipd, const bool joint, const int32_t lane) {
-    if constexpr (MS == MS_LINEAR) min_search<T>(h, li, clipd, joint, lane);
-    else min_search_window<T, MS == MS_WALK>(h, wp, clipd, joint, lane);
+__device__ __forceinline__ int32_t msearch(int32_t (&h)[T::KY][T::KX], const LineIndex<T>& li, const WinPen& wp,
+                                           const int32_t clipd, const bool joint, const int32_t lane) {
+    if constexpr (MS == MS_LINEAR) return min_search<T>(h, li, clipd, joint, lane);
+    else return min_search_window<T, MS == MS_WALK>(h, wp, clipd, joint, lane);
 }
 
 // FWD: the forward sweep (stores F, writes the row optimum); else the backward sweep (labels and
@@ -119,21 +121,13 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
         for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, in ? off_add(base, crun[ky]) : OOB, rc[u][ky]);
         if constexpr (!FWD) load_terms<FT, E>(rs_f, in ? off_add(frow, x * QT * (int32_t)sizeof(FT)) : OOB, rf[u]);
     };
-    // h = s - (minimum over the vertex's labels), PADV on padding labels; returns the minimum
+    // the vector searched next: s on the real labels, PADV on padding labels
     int32_t h[KY][KX];
-    auto normalize = [&](const int32_t (&s)[KY][KX]) -> int32_t {
-        int32_t m = PADV;
+    auto set_h = [&](const int32_t (&s)[KY][KX]) {
 #pragma unroll
         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-            for (int kx = 0; kx < KX; ++kx)
-                if (valid[ky][kx]) m = imin(m, s[ky][kx]);
-        m = group_min<T>(m, lane);
-#pragma unroll
-        for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-            for (int kx = 0; kx < KX; ++kx) h[ky][kx] = valid[ky][kx] ? s[ky][kx] - m : PADV;
-        return m;
+            for (int kx = 0; kx < KX; ++kx) h[ky][kx] = valid[ky][kx] ? s[ky][kx] : PADV;
     };
 
     int64_t offset = 0;
@@ -149,7 +143,7 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
             for (int kx = 0; kx < KX; ++kx) s[ky][kx] = cost_elem<CK, KX>(c0[ky], kx);
-        offset += normalize(s);
+        set_h(s);
     } else {
 #pragma unroll
         for (int ky = 0; ky < KY; ++ky)
@@ -164,18 +158,20 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
         const bool live = !TAIL || k < W;
         const int32_t x = col(k);
         if constexpr (FWD) {
-            msearch<T, MS>(h, li, wp, a.clipd, joint, lane);         // F(x) = M(S_1(x-1))
+            // F(x) = M(S_1(x-1)) less min S_1(x-1), which the search returns: within [0, Vmax]
+            const int32_t g = msearch<T, MS>(h, li, wp, a.clipd, joint, lane);
             int32_t f[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) f[e] = (&valid[0][0])[e] ? (&h[0][0])[e] : 0;
+            for (int e = 0; e < E; ++e) f[e] = (&valid[0][0])[e] ? (&h[0][0])[e] - g : 0;
             store_terms<FT, E>(rs_f, live ? off_add(frow, x * QT * (int32_t)sizeof(FT)) : OOB, f);
-            int32_t s[KY][KX];
-#pragma unroll
-            for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                for (int kx = 0; kx < KX; ++kx) s[ky][kx] = cost_elem<CK, KX>(rc[u][ky], kx) + h[ky][kx];
             if (live) {
-                offset += normalize(s);
+                int32_t s[KY][KX];
+#pragma unroll
+                for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) s[ky][kx] = cost_elem<CK, KX>(rc[u][ky], kx) + f[ky * KX + kx];
+                set_h(s);
+                offset += g;
             }
         } else {
             // S_Omega(x) = F(x) + C(x) + B(x) and its smallest argmin, found by one minimum over
@@ -202,12 +198,13 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
                     store_i32(rs_m, (live && valid[ky][kx]) ? ((y * W + x) * Q + q[ky][kx]) * 4 : OOB,
                               mg[ky][kx] - mmin);
             if (live && x > 0) {
-                normalize(s);                                        // S_-1(x) less its minimum
-                msearch<T, MS>(h, li, wp, a.clipd, joint, lane);     // B(x-1) = M(S_-1(x))
+                // B(x-1) = M(S_-1(x)) less min S_-1(x): within [0, Vmax]
+                set_h(s);
+                const int32_t g = msearch<T, MS>(h, li, wp, a.clipd, joint, lane);
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
-                    for (int kx = 0; kx < KX; ++kx) bterm[ky][kx] = valid[ky][kx] ? h[ky][kx] : 0;
+                    for (int kx = 0; kx < KX; ++kx) bterm[ky][kx] = valid[ky][kx] ? h[ky][kx] - g : 0;
             }
         }
         fetch(k + PF, u);
@@ -224,7 +221,14 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
         for (int u = 0; u < PF; ++u) step(std::true_type{}, u, kk + u);
     }
     if constexpr (FWD) {
-        if (rowok && l == 0) a.row_energy[y] = offset;
+        // row optimum: the subtracted minima plus the minimum of the last S_1
+        int32_t m = PADV;
+#pragma unroll
+        for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < KX; ++kx) m = imin(m, h[ky][kx]);
+        m = group_min<T>(m, lane);
+        if (rowok && l == 0) a.row_energy[y] = offset + m;
     }
 }
 
