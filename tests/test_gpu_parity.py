@@ -280,3 +280,25 @@ def test_edp_motion640x480_961_labels_full_size():
         lab, e = gpu_edp(p, 1, tile, cost_bound=2500)
         assert e == g["energy"], tile
         assert hashlib.sha256(np.ascontiguousarray(lab, dtype=np.int32).tobytes()).hexdigest() == g["labels_sha256"], tile
+
+
+def test_dp_sweep_workload_full_size():
+    """The DP sweep bench workload (8192 scanlines x 1024 columns x 64 labels, int16 uniform in
+    [0, 50], drawn on the device with seed 0) in the benchmark's launch: sampled rows against the C
+    oracle (labels and row energies), every row's energy equal to the min-marginal DP's and the
+    total equal to the energy of the labels."""
+    g = torch.Generator(device=DEV)
+    g.manual_seed(0)
+    cost = torch.randint(0, 51, (8192, 1024, 64), generator=g, device=DEV, dtype=torch.int16)
+    note("dp sweep 8192x1024x64")
+    lab, row, tot = edp.dp_scanline(cost, 64, 1, 20, 2, cost_bound=51)
+    _, _, mrow, _ = edp.dp_marginals(cost, 64, 1, 20, 2, cost_bound=51)
+    e, _ = edp.energy(cost, lab, 64, 1, 20, 2, grid4=False, cost_bound=51)
+    torch.cuda.synchronize()
+    assert torch.equal(row, mrow)
+    assert int(tot.item()) == int(e.item())
+    rows = [0, 1, 4095, 8191]
+    sample = cost[rows].cpu().numpy().astype(np.int32)
+    rl, rr, _ = cref.dp_scanline(sample, 64, 1, 20, 2, 0, "lrms")
+    assert np.array_equal(lab[rows].cpu().numpy(), rl)
+    assert np.array_equal(row[rows].cpu().numpy(), rr)
