@@ -75,3 +75,14 @@ def test_dsi_full_size_workloads():
     got = edp.dsi(to_dev(i0), to_dev(i1), 15, 15, -7, -7, 1, 1, 2, 2500, dtype=torch.int32)
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), m.cost)
+
+
+def test_dsi_961_label_volume_full_size():
+    """The 961-label motion volume of the learned-window workload (640x480, int32, 1.18 GB) in the
+    benchmark's call equals the workload generator's volume."""
+    m = synth.workload("motion640x480")
+    i0, i1 = m.meta["frames"]
+    note("dsi motion640x480 961 labels")
+    got = edp.dsi(to_dev(i0), to_dev(i1), 31, 31, -15, -15, 1, 1, 2, 2500, dtype=torch.int32)
+    torch.cuda.synchronize()
+    assert torch.equal(got, to_dev(m.cost))
