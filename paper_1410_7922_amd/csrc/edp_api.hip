@@ -78,6 +78,7 @@ int64_t clip_of(const edp_problem* p) {
 // either prior), else the linear RMS (linear prior) or the walked window (squared prior).
 int ms_of(const edp_problem* p) {
     const int nw = std::max(std::min(p->trunc, p->qx), std::min(p->trunc, p->qy)) - 1;
+    if (nw <= 1) return MS_WINDOW1;
     if (nw <= 2) return MS_WINDOW;
     return p->prior == EDP_PRIOR_SQUARED ? MS_WALK : MS_LINEAR;
 }

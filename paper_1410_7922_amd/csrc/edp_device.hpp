@@ -446,7 +446,7 @@ struct WinPen {
 };
 
 template <int NL, int K, int STEP, int NW>
-__device__ __forceinline__ void quad_window(int32_t (&val)[K], const int32_t (&pen)[NW], const int32_t pos,
+__device__ __forceinline__ void quad_window(int32_t (&val)[K], const int32_t* pen, const int32_t pos,
                                             const int32_t lane) {
     constexpr int HOPS = (NW + K - 1) / K;
     int32_t lo[HOPS + 1][K], hi[HOPS + 1][K];    // [h][k]: the label h lanes below / above label k
@@ -520,9 +520,9 @@ __device__ __forceinline__ void quad_walk(int32_t (&val)[K], const int32_t lam, 
     }
 }
 
-// WALK false: nw <= 2 with the step penalties pen; WALK true: any nw, squared prior.
+// NWK 1 or 2: nw <= NWK with the step penalties pen; NWK 0: any nw walked, squared prior.
 // Returns min h of the line.
-template <int NL, int K, int STEP, bool WALK>
+template <int NL, int K, int STEP, int NWK>
 __device__ __forceinline__ int32_t window_line(int32_t (&val)[K], const int32_t (&pen)[2], const int32_t lam,
                                              const int32_t nw, const int32_t clipd, const bool clip,
                                              const int32_t pos, const int32_t lane) {
@@ -530,8 +530,8 @@ __device__ __forceinline__ int32_t window_line(int32_t (&val)[K], const int32_t 
 #pragma unroll
     for (int k = 1; k < K; ++k) m = imin(m, val[k]);
     if constexpr (NL > 1) m = line_min<NL, STEP>(m, lane);
-    if constexpr (WALK) quad_walk<NL, K, STEP>(val, lam, nw, pos, lane);
-    else quad_window<NL, K, STEP, 2>(val, pen, pos, lane);
+    if constexpr (NWK == 0) quad_walk<NL, K, STEP>(val, lam, nw, pos, lane);
+    else quad_window<NL, K, STEP, NWK>(val, pen, pos, lane);
     if (clip) {
 #pragma unroll
         for (int k = 0; k < K; ++k) val[k] = imin(val[k], m + clipd);
@@ -714,8 +714,8 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
 // The minimum search operator M computed by the general RMS of Sec. 3.1: one
 // window operator per label dimension (eq. M_decmp1), clipped per line
 // (per-dimension truncation) or once at (min h + clipd) (joint truncation,
-// eq. M_decmp).  WALK as for window_line.  Same contract as min_search.
-template <class T, bool WALK>
+// eq. M_decmp).  NWK as for window_line.  Same contract as min_search.
+template <class T, int NWK>
 __device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KY][T::KX], const WinPen& sp,
                                                    const int32_t clipd, const bool joint, const int32_t lane) {
     const int32_t l = lane % T::G;
@@ -724,7 +724,7 @@ __device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KY][T::KX],
     int32_t rowmin = PADV;
 #pragma unroll
     for (int ky = 0; ky < T::KY; ++ky) {
-        const int32_t lm = window_line<T::PX, T::KX, 1, WALK>(h[ky], sp.px, sp.lam, sp.nwx, clipd, !joint || one_dim,
+        const int32_t lm = window_line<T::PX, T::KX, 1, NWK>(h[ky], sp.px, sp.lam, sp.nwx, clipd, !joint || one_dim,
                                                              px, lane);
         rowmin = imin(rowmin, lm);
     }
@@ -738,7 +738,7 @@ __device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KY][T::KX],
             int32_t col[T::KY];
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
-            window_line<T::PY, T::KY, T::PX, WALK>(col, sp.py, sp.lam, sp.nwy, clipd, !joint, py, lane);
+            window_line<T::PY, T::KY, T::PX, NWK>(col, sp.py, sp.lam, sp.nwy, clipd, !joint, py, lane);
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
         }

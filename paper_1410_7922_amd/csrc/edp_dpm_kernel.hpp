@@ -67,7 +67,7 @@ template <class T, int MS>
 __device__ __forceinline__ int32_t msearch(int32_t (&h)[T::KY][T::KX], const LineIndex<T>& li, const WinPen& wp,
                                            const int32_t clipd, const bool joint, const int32_t lane) {
     if constexpr (MS == MS_LINEAR) return min_search<T>(h, li, clipd, joint, lane);
-    else return min_search_window<T, MS == MS_WALK>(h, wp, clipd, joint, lane);
+    else return min_search_window<T, MS == MS_WALK ? 0 : 2>(h, wp, clipd, joint, lane);
 }
 
 // FWD: the forward sweep (stores F, writes the row optimum); else the backward sweep (labels and
@@ -246,7 +246,7 @@ static void run_dpm(const DpmArgs& a, int grid, bool forward, hipStream_t s) {
 template <class T, class CK>
 static void dpm_ms(const DpmArgs& a, int grid, bool forward, hipStream_t s) {
     if (a.ms == MS_WALK) run_dpm<T, CK, MS_WALK>(a, grid, forward, s);
-    else if (a.ms == MS_WINDOW) run_dpm<T, CK, MS_WINDOW>(a, grid, forward, s);
+    else if (a.ms == MS_WINDOW || a.ms == MS_WINDOW1) run_dpm<T, CK, MS_WINDOW>(a, grid, forward, s);
     else run_dpm<T, CK, MS_LINEAR>(a, grid, forward, s);
 }
 

@@ -39,6 +39,7 @@ constexpr int WIN_FRAME = 8;
 constexpr int MS_LINEAR = 0;     // truncated linear prior: linear RMS (Sec. 3.2)
 constexpr int MS_WINDOW = 1;     // general RMS (Sec. 3.1), windows of at most two steps per side, either prior
 constexpr int MS_WALK = 2;       // general RMS, any window, truncated squared prior
+constexpr int MS_WINDOW1 = 3;    // general RMS, windows of one step per side (T <= 2), either prior
 
 struct TileShape {
     int px, kx, py, ky;

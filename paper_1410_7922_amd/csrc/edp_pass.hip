@@ -27,8 +27,9 @@ hipError_t launch_edp_pass(int tile, int dtype, int split, int ms, const PassArg
     switch (tile) {
 #define EDP_CASE(id, px, kx, py, ky)                                                                   \
     case id:                                                                                           \
-        return ms == MS_WALK    ? pass_tile<id, MS_WALK>(dtype, split, a, grid, waves, s)         \
-               : ms == MS_WINDOW ? pass_tile<id, MS_WINDOW>(dtype, split, a, grid, waves, s)        \
+        return ms == MS_WALK      ? pass_tile<id, MS_WALK>(dtype, split, a, grid, waves, s)       \
+               : ms == MS_WINDOW1 ? pass_tile<id, MS_WINDOW1>(dtype, split, a, grid, waves, s)    \
+               : ms == MS_WINDOW  ? pass_tile<id, MS_WINDOW>(dtype, split, a, grid, waves, s)      \
                                    : pass_tile<id, MS_LINEAR>(dtype, split, a, grid, waves, s);
         EDP_TILE_LIST(EDP_CASE)
 #undef EDP_CASE
@@ -58,8 +59,9 @@ int pass_capacity(int tile, int dtype, int split, int ms, int waves, size_t lds_
     switch (tile) {
 #define EDP_CASE(id, px, kx, py, ky)                                                                \
     case id:                                                                                        \
-        per_cu = ms == MS_WALK    ? occupancy_tile<id, MS_WALK>(dtype, split, waves, lds_bytes)  \
-                 : ms == MS_WINDOW ? occupancy_tile<id, MS_WINDOW>(dtype, split, waves, lds_bytes) \
+        per_cu = ms == MS_WALK      ? occupancy_tile<id, MS_WALK>(dtype, split, waves, lds_bytes)    \
+                 : ms == MS_WINDOW1 ? occupancy_tile<id, MS_WINDOW1>(dtype, split, waves, lds_bytes) \
+                 : ms == MS_WINDOW  ? occupancy_tile<id, MS_WINDOW>(dtype, split, waves, lds_bytes)   \
                                      : occupancy_tile<id, MS_LINEAR>(dtype, split, waves, lds_bytes);  \
         break;
         EDP_TILE_LIST(EDP_CASE)

@@ -525,8 +525,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                         min_search_shift<T>(h2, d.lam, d.clipd, joint, lane, dxb, dyb, wscr);
                     }
                 } else if constexpr (MS != MS_LINEAR) {
-                    min_search_window<T, MS == MS_WALK>(h, sp, d.clipd, joint, lane);
-                    if constexpr (SPLIT == 1) min_search_window<T, MS == MS_WALK>(h2, sp, d.clipd, joint, lane);
+                    constexpr int NWK = MS == MS_WALK ? 0 : (MS == MS_WINDOW1 ? 1 : 2);
+                    min_search_window<T, NWK>(h, sp, d.clipd, joint, lane);
+                    if constexpr (SPLIT == 1) min_search_window<T, NWK>(h2, sp, d.clipd, joint, lane);
                 } else {
                     min_search<T>(h, li, d.clipd, joint, lane);
                     if constexpr (SPLIT == 1) min_search<T>(h2, li, d.clipd, joint, lane);
@@ -780,6 +781,8 @@ using WinTile = TileOf<WIN_TILE>::type;
     template hipError_t pass_tile<id, MS_WINDOW>(int, int, const PassArgs&, int, int, hipStream_t);     \
     template int occupancy_tile<id, MS_WINDOW>(int, int, int, size_t);                                 \
     template hipError_t pass_tile<id, MS_WALK>(int, int, const PassArgs&, int, int, hipStream_t);      \
-    template int occupancy_tile<id, MS_WALK>(int, int, int, size_t);
+    template int occupancy_tile<id, MS_WALK>(int, int, int, size_t);                                   \
+    template hipError_t pass_tile<id, MS_WINDOW1>(int, int, const PassArgs&, int, int, hipStream_t);   \
+    template int occupancy_tile<id, MS_WINDOW1>(int, int, int, size_t);
 
 }  // namespace edp
