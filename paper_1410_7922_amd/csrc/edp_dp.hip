@@ -100,7 +100,8 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
         const bool live = !TAIL || x < W;
         int32_t g;
         if constexpr (MS == MS_LINEAR) g = min_search<T>(key, li, clipk, a.joint != 0, lane);
-        else g = min_search_window<T, MS == MS_WALK ? 0 : 2>(key, sp, clipk, a.joint != 0, lane);
+        else g = min_search_window<T, MS == MS_WALK ? 0 : (MS == MS_WINDOW1 ? 1 : 2)>(key, sp, clipk, a.joint != 0,
+                                                                                    lane);
         const int32_t norm = g >> ib;
         if constexpr (sizeof(PT) == 1 && E % 4 == 0) {
             // four choice indexes per dword: low bytes gathered by byte permutes, then masked
@@ -273,7 +274,8 @@ static void run_fwd_ms(const DpArgs& a, int grid, hipStream_t s) {
 template <class T, class CK>
 static hipError_t run_fwd(const DpArgs& a, int grid, hipStream_t s) {
     if (a.ms == MS_WALK) run_fwd_ms<T, CK, MS_WALK>(a, grid, s);
-    else if (a.ms == MS_WINDOW || a.ms == MS_WINDOW1) run_fwd_ms<T, CK, MS_WINDOW>(a, grid, s);
+    else if (a.ms == MS_WINDOW1) run_fwd_ms<T, CK, MS_WINDOW1>(a, grid, s);
+    else if (a.ms == MS_WINDOW) run_fwd_ms<T, CK, MS_WINDOW>(a, grid, s);
     else run_fwd_ms<T, CK, MS_LINEAR>(a, grid, s);
     return hipGetLastError();
 }
