@@ -576,18 +576,24 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             // wavefront strictly inside its row (s0 >= RPW, s0 + 2 PF + 1 <= W).  Only tiles with
             // few labels per lane get the second copy of the round (the others would spill).
             constexpr bool TWO_COPIES = E <= 2 || (E <= 4 && G <= 16);
-            for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
-                bool steady_round = false;
-                if constexpr (TWO_COPIES) steady_round = s0 >= RPW && s0 + 2 * PF + 1 <= W;
-                if (steady_round) {
-                    if constexpr (TWO_COPIES) {
+            // the steady rounds are one run of consecutive rounds: the rounds before it, the run
+            // and the rounds after it are three loops, each with a single copy of the round, so
+            // the prefetch registers of a round are those of the next (no copies between rounds)
+            auto is_steady = [&](int32_t s0) { return TWO_COPIES && s0 >= RPW && s0 + 2 * PF + 1 <= W; };
+            int32_t s0 = 0;
+            for (; s0 < nsteps && !is_steady(s0); s0 += PF) {
 #pragma unroll
-                        for (int u = 0; u < PF; ++u) step(std::true_type{}, u, s0 + u);
-                    }
-                } else {
+                for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
+            }
+            if constexpr (TWO_COPIES) {
+                for (; s0 < nsteps && is_steady(s0); s0 += PF) {
 #pragma unroll
-                    for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
+                    for (int u = 0; u < PF; ++u) step(std::true_type{}, u, s0 + u);
                 }
+            }
+            for (; s0 < nsteps; s0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
             }
         }
         // Band complete: every wavefront makes its stores visible to the device before the
