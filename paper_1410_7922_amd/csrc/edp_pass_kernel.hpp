@@ -576,24 +576,39 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             // wavefront strictly inside its row (s0 >= RPW, s0 + 2 PF + 1 <= W).  Only tiles with
             // few labels per lane get the second copy of the round (the others would spill).
             constexpr bool TWO_COPIES = E <= 2 || (E <= 4 && G <= 16);
-            // the steady rounds are one run of consecutive rounds: the rounds before it, the run
-            // and the rounds after it are three loops, each with a single copy of the round, so
-            // the prefetch registers of a round are those of the next (no copies between rounds)
-            auto is_steady = [&](int32_t s0) { return TWO_COPIES && s0 >= RPW && s0 + 2 * PF + 1 <= W; };
-            int32_t s0 = 0;
-            for (; s0 < nsteps && !is_steady(s0); s0 += PF) {
+            auto is_steady = [&](int32_t s0) { return s0 >= RPW && s0 + 2 * PF + 1 <= W; };
+            if constexpr (TWO_COPIES && !WIN) {
+                // the steady rounds are one run of consecutive rounds: the rounds before it, the
+                // run and the rounds after it are three loops, each with a single copy of the
+                // round, so the prefetch registers of a round are those of the next (one loop with
+                // both copies moved them between rounds, after waiting for every load in flight)
+                int32_t s0 = 0;
+                for (; s0 < nsteps && !is_steady(s0); s0 += PF) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
-            }
-            if constexpr (TWO_COPIES) {
+                    for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
+                }
                 for (; s0 < nsteps && is_steady(s0); s0 += PF) {
 #pragma unroll
                     for (int u = 0; u < PF; ++u) step(std::true_type{}, u, s0 + u);
                 }
-            }
-            for (; s0 < nsteps; s0 += PF) {
+                for (; s0 < nsteps; s0 += PF) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
+                    for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
+                }
+            } else {
+                // one loop: tiles without the steady copy, and the window solve (which ran
+                // slower as three loops)
+                for (int32_t s0 = 0; s0 < nsteps; s0 += PF) {
+                    if (TWO_COPIES && is_steady(s0)) {
+                        if constexpr (TWO_COPIES) {
+#pragma unroll
+                            for (int u = 0; u < PF; ++u) step(std::true_type{}, u, s0 + u);
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < PF; ++u) step(std::false_type{}, u, s0 + u);
+                    }
+                }
             }
         }
         // Band complete: every wavefront makes its stores visible to the device before the
