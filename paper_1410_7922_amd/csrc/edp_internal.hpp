@@ -204,6 +204,10 @@ struct DsiArgs {
     int32_t l2, cmax;
     int32_t vec;             // output 16-byte aligned: vector stores
     double inv_q, inv_w;     // 1 / (qx qy), 1 / W
+    // staged-window kernel (set by launch_dsi): segments of seg pixels, nseg per row; the
+    // windows are qy rows of pw = seg + qx - 1 pixels from displacement (dxmin, dymin)
+    int32_t seg, nseg, pw, dxmin, dxmax, dymin, dymax;
+    float inv_qf;            // 1 / (qx qy)
 };
 
 // Launchers (return hipSuccess or the launch error).  dtype: 1 int16, 2 int32.

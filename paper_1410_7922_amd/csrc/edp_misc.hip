@@ -286,6 +286,118 @@ __global__ __launch_bounds__(256) void dsi_kernel(const DsiArgs a) {
     }
 }
 
+// Staged windows: one workgroup forms the costs of a segment of up to seg pixels of one row.
+// All I1 values those pixels compare with (qy rows of pw = seg + qx - 1 pixels), and the I2
+// values of the composite cost, are read once into LDS as 16-bit values, 0xFFFF off the image;
+// a table gives each label's offset into the windows (I2's in the upper half), so an element
+// costs the table read, one or two window reads, the I0 value of its pixel and the truncated
+// difference, with no global gathers.  The segment's elements are a contiguous run of the
+// volume: whole 16-byte vectors in the middle, single elements at both ends.
+template <int L2>
+__device__ __forceinline__ int32_t window_cost(uint32_t v, int32_t c0, int32_t cmax) {
+    int32_t d = (int32_t)(v & 0xFFu) - c0;
+    d = d < 0 ? -d : d;
+    if constexpr (L2 == 2) d *= d;
+    d = d < cmax ? d : cmax;
+    return v > 255u ? cmax : d;
+}
+
+template <class CT, int L2, bool COMP>
+__global__ __launch_bounds__(256) void dsi_window_kernel(const DsiArgs a) {
+    constexpr int V = 16 / (int)sizeof(CT);
+    extern __shared__ int32_t smem[];
+    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy, PW = a.pw, NE = a.qy * a.pw;
+    int32_t* const tab = smem;                                   // [Q] window offsets
+    uint16_t* const w1 = (uint16_t*)(smem + Q);                  // [qy][pw] I1
+    uint16_t* const w2 = w1 + NE;                                // [qy][pw] I2 (COMP)
+    uint16_t* const row0 = w2 + (COMP ? NE : 0);                 // [seg] I0 of the segment
+    const int32_t y = blockIdx.x / a.nseg, x0 = (blockIdx.x - y * a.nseg) * a.seg;
+    const int32_t np = W - x0 < a.seg ? W - x0 : a.seg;
+    for (int32_t i = threadIdx.x; i < Q; i += blockDim.x) {
+        const int32_t iy = i / a.qx, ix = i - iy * a.qx;
+        const int32_t dx = a.ox + a.sx * ix, dy = a.oy + a.sy * iy;
+        const int32_t o1 = (dy - a.dymin) * PW + (dx - a.dxmin);
+        const int32_t o2 = COMP ? (a.dymax - dy) * PW + (a.dxmax - dx) : 0;
+        tab[i] = o1 | (o2 << 16);
+    }
+    // pixel x0 + p at displacement (dx, dy) reads w1[o1 + p] = I1(x0 + p + dx, y + dy) and
+    // w2[o2 + p] = I2(x0 + p - dx, y - dy)
+    for (int32_t i = threadIdx.x; i < NE; i += blockDim.x) {
+        const int32_t r = i / PW, c = i - r * PW;
+        const int32_t X1 = x0 + a.dxmin + c, Y1 = y + a.dymin + r;
+        const bool ok1 = (uint32_t)X1 < (uint32_t)W && (uint32_t)Y1 < (uint32_t)H;
+        w1[i] = ok1 ? (uint16_t)a.i1[(size_t)Y1 * W + X1] : (uint16_t)0xFFFF;
+        if constexpr (COMP) {
+            const int32_t X2 = x0 - a.dxmax + c, Y2 = y - a.dymax + r;
+            const bool ok2 = (uint32_t)X2 < (uint32_t)W && (uint32_t)Y2 < (uint32_t)H;
+            w2[i] = ok2 ? (uint16_t)a.i2[(size_t)Y2 * W + X2] : (uint16_t)0xFFFF;
+        }
+    }
+    for (int32_t i = threadIdx.x; i < np; i += blockDim.x) row0[i] = a.i0[(size_t)y * W + x0 + i];
+    __syncthreads();
+
+    auto elem = [&](int32_t p, int32_t q) -> int32_t {
+        const uint32_t t = (uint32_t)tab[q];
+        const int32_t c0 = row0[p];
+        int32_t c = window_cost<L2>(w1[(t & 0xFFFFu) + p], c0, a.cmax);
+        if constexpr (COMP) {
+            const int32_t c2 = window_cost<L2>(w2[(t >> 16) + p], c0, a.cmax);
+            c = c < c2 ? c : c2;
+        }
+        return c;
+    };
+    CT* const cost = (CT*)a.cost;
+    const int64_t E0 = ((int64_t)y * W + x0) * Q, E1 = E0 + (int64_t)np * Q;
+    int64_t A0 = (E0 + V - 1) / V * V, A1 = E1 / V * V;
+    if (A0 > A1) A0 = A1 = E1;
+    // single elements before the first and after the last whole vector
+    for (int64_t e = E0 + threadIdx.x; e < A0; e += blockDim.x) {
+        const int32_t l = (int32_t)(e - E0), p = l / Q;
+        cost[e] = (CT)elem(p, l - p * Q);
+    }
+    for (int64_t e = A1 + threadIdx.x; e < E1; e += blockDim.x) {
+        const int32_t l = (int32_t)(e - E0), p = l / Q;
+        cost[e] = (CT)elem(p, l - p * Q);
+    }
+    for (int64_t e = A0 + (int64_t)threadIdx.x * V; e < A1; e += (int64_t)blockDim.x * V) {
+        // l < seg * Q <= 2^18: the float quotient of l + 1/2 is at least 1/(2Q) from an
+        // integer and its error is below 2^-16, so the floor is exact
+        const int32_t l = (int32_t)(e - E0);
+        int32_t p = (int32_t)(((float)l + 0.5f) * a.inv_qf);
+        int32_t q = l - p * Q;
+        CT out[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            out[k] = (CT)elem(p, q);
+            const bool next_pixel = ++q == Q;
+            q = next_pixel ? 0 : q;
+            p += next_pixel ? 1 : 0;
+        }
+        uint4 w;
+        __builtin_memcpy(&w, out, 16);
+        *(uint4*)(cost + e) = w;
+    }
+}
+
+// LDS of the staged-window kernel (bytes)
+static size_t dsi_window_lds(int32_t qx, int32_t qy, int32_t seg, bool comp) {
+    const size_t ne = (size_t)qy * (size_t)(seg + qx - 1);
+    return (size_t)qx * qy * 4 + (comp ? 2 : 1) * ne * 2 + (size_t)seg * 2 + 4;
+}
+
+template <class CT>
+static void run_dsi_window(const DsiArgs& a, hipStream_t s) {
+    const size_t lds = dsi_window_lds(a.qx, a.qy, a.seg, a.i2 != nullptr);
+    const int grid = a.H * a.nseg;
+    if (a.l2 == 2) {
+        if (a.i2) hipLaunchKernelGGL((dsi_window_kernel<CT, 2, true>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((dsi_window_kernel<CT, 2, false>), dim3(grid), dim3(256), lds, s, a);
+    } else {
+        if (a.i2) hipLaunchKernelGGL((dsi_window_kernel<CT, 1, true>), dim3(grid), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((dsi_window_kernel<CT, 1, false>), dim3(grid), dim3(256), lds, s, a);
+    }
+}
+
 template <class CT>
 static void run_dsi(const DsiArgs& a, int grid, hipStream_t s) {
     const size_t lds = (size_t)a.qx * a.qy * 4;
@@ -298,8 +410,29 @@ static void run_dsi(const DsiArgs& a, int grid, hipStream_t s) {
     }
 }
 
-hipError_t launch_dsi(const DsiArgs& a, int dtype, hipStream_t s) {
+hipError_t launch_dsi(const DsiArgs& args, int dtype, hipStream_t s) {
+    DsiArgs a = args;
     const int V = dtype == 1 ? 8 : 4;
+    const int32_t Q = a.qx * a.qy, esize = dtype == 1 ? 2 : 4;
+    // staged windows when the output takes vector stores and the windows fit 64 KB of LDS:
+    // 64-pixel segments, 256 when a pixel's labels fill less than 512 bytes
+    const bool comp = a.i2 != nullptr;
+    int32_t seg = Q * esize < 512 ? 256 : 64;
+    if (dsi_window_lds(a.qx, a.qy, seg, comp) > 65536) seg = 64;
+    if (a.vec && dsi_window_lds(a.qx, a.qy, seg, comp) <= 65536) {
+        a.seg = seg;
+        a.nseg = (a.W + seg - 1) / seg;
+        a.pw = seg + a.qx - 1;
+        const int32_t dx1 = a.ox + a.sx * (a.qx - 1), dy1 = a.oy + a.sy * (a.qy - 1);
+        a.dxmin = a.ox < dx1 ? a.ox : dx1;
+        a.dxmax = a.ox < dx1 ? dx1 : a.ox;
+        a.dymin = a.oy < dy1 ? a.oy : dy1;
+        a.dymax = a.oy < dy1 ? dy1 : a.oy;
+        a.inv_qf = 1.0f / (float)Q;
+        if (dtype == 1) run_dsi_window<int16_t>(a, s);
+        else run_dsi_window<int32_t>(a, s);
+        return hipGetLastError();
+    }
     const int64_t n = (int64_t)a.W * a.H * a.qx * a.qy;
     int64_t grid = (n / V + 255) / 256 + 1;
     if (grid > 65536) grid = 65536;

@@ -31,6 +31,14 @@ CASES = [
     (26, 19, 7, 7, -3, -3, 1, 1, 2, 2500, True, torch.int32),      # three-view motion
     (17, 13, 3, 5, 2, -7, -1, 1, 1, 255, True, torch.int16),
     (64, 3, 100, 1, 10, 0, -1, 1, 1, 30000, False, torch.int16),   # labels reaching past the image
+    # staged windows: 256-pixel segments, ragged last segment, segment starts off the 16-byte grid
+    (300, 7, 9, 9, -4, -4, 1, 1, 2, 2500, True, torch.int32),
+    (150, 4, 33, 1, 0, 0, -1, 1, 1, 50, False, torch.int16),
+    (270, 3, 13, 1, 0, 0, -1, 1, 1, 40, False, torch.int16),
+    (70, 2, 700, 1, -350, 0, 1, 1, 1, 255, True, torch.int16),     # 64-pixel segments, wide windows
+    (200, 5, 31, 31, -15, -15, 1, 1, 2, 2500, False, torch.int32),  # the 961-label window shape
+    # windows larger than 64 KB of LDS: the per-element kernel
+    (40, 30, 1, 1100, 0, -550, 1, 1, 1, 90, False, torch.int16),
 ]
 
 
