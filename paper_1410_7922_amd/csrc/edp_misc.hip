@@ -307,8 +307,10 @@ __global__ __launch_bounds__(256) void dsi_window_kernel(const DsiArgs a) {
     constexpr int V = 16 / (int)sizeof(CT);
     extern __shared__ int32_t smem[];
     const int32_t W = a.W, H = a.H, Q = a.qx * a.qy, PW = a.pw, NE = a.qy * a.pw;
-    int32_t* const tab = smem;                                   // [Q] window offsets
-    uint16_t* const w1 = (uint16_t*)(smem + Q);                  // [qy][pw] I1
+    // [Q] window offsets, label q at q + q / 4: the 4 consecutive labels of a lane's vector sit
+    // 5 words from the next lane's, so the lanes of a wavefront read 32 different banks
+    int32_t* const tab = smem;
+    uint16_t* const w1 = (uint16_t*)(smem + Q + (Q >> 2) + 1);   // [qy][pw] I1
     uint16_t* const w2 = w1 + NE;                                // [qy][pw] I2 (COMP)
     uint16_t* const row0 = w2 + (COMP ? NE : 0);                 // [seg] I0 of the segment
     const int32_t y = blockIdx.x / a.nseg, x0 = (blockIdx.x - y * a.nseg) * a.seg;
@@ -318,7 +320,7 @@ __global__ __launch_bounds__(256) void dsi_window_kernel(const DsiArgs a) {
         const int32_t dx = a.ox + a.sx * ix, dy = a.oy + a.sy * iy;
         const int32_t o1 = (dy - a.dymin) * PW + (dx - a.dxmin);
         const int32_t o2 = COMP ? (a.dymax - dy) * PW + (a.dxmax - dx) : 0;
-        tab[i] = o1 | (o2 << 16);
+        tab[i + (i >> 2)] = o1 | (o2 << 16);
     }
     // pixel x0 + p at displacement (dx, dy) reads w1[o1 + p] = I1(x0 + p + dx, y + dy) and
     // w2[o2 + p] = I2(x0 + p - dx, y - dy)
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(256) void dsi_window_kernel(const DsiArgs a) {
     __syncthreads();
 
     auto elem = [&](int32_t p, int32_t q) -> int32_t {
-        const uint32_t t = (uint32_t)tab[q];
+        const uint32_t t = (uint32_t)tab[q + (q >> 2)];
         const int32_t c0 = row0[p];
         int32_t c = window_cost<L2>(w1[(t & 0xFFFFu) + p], c0, a.cmax);
         if constexpr (COMP) {
@@ -382,7 +384,8 @@ __global__ __launch_bounds__(256) void dsi_window_kernel(const DsiArgs a) {
 // LDS of the staged-window kernel (bytes)
 static size_t dsi_window_lds(int32_t qx, int32_t qy, int32_t seg, bool comp) {
     const size_t ne = (size_t)qy * (size_t)(seg + qx - 1);
-    return (size_t)qx * qy * 4 + (comp ? 2 : 1) * ne * 2 + (size_t)seg * 2 + 4;
+    const size_t q = (size_t)qx * qy;
+    return (q + q / 4 + 1) * 4 + (comp ? 2 : 1) * ne * 2 + (size_t)seg * 2 + 4;
 }
 
 template <class CT>
