@@ -408,8 +408,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE {world}); a multi-GPU sharding is described in DESIGN.md but not built",
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); it has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

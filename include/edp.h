@@ -49,7 +49,7 @@ typedef enum {
     EDP_E_RANGE = -2,       /* the int32 range guard failed for these parameters */
     EDP_E_WORKSPACE = -3,   /* workspace missing, misaligned or too small */
     EDP_E_HIP = -4,         /* a HIP runtime call or kernel launch failed */
-    EDP_E_UNSUPPORTED = -5  /* valid problem outside what this build implements */
+    EDP_E_UNSUPPORTED = -5  /* valid problem outside what the library implements */
 } edp_status;
 
 typedef enum { EDP_I16 = 1, EDP_I32 = 2 } edp_dtype;

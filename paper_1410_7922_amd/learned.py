@@ -1,6 +1,6 @@
 """Learned-window EDP: the window network proposes a label window per pixel, the
 EDP runs over the windows only (edp_solve_windowed), and the plain EDP remains
-the fallback and the judge: an instance whose windowed energy exceeds the
+the fallback and the reference: an instance whose windowed energy exceeds the
 plain energy by more than ``max_gap`` is solved again by the plain EDP.
 
 All steps run in the library's kernels; this module sequences them.
