@@ -230,6 +230,18 @@ def test_edp_stereo_workload_full_size():
         assert e == ref["energy"]
 
 
+def test_edp_stereo_1280x720_q64_many_bands():
+    """A larger stereo solve: 64 disparities (another launch tile), 45 bands of 16 scanlines, so
+    44 workgroup hand-offs per scan, against the C oracle (a few seconds on one core)."""
+    p = synth.stereo_problem(seed=3, W=1280, H=720, Q=64)
+    bound = int(p.cost.max()) + 1
+    ref = cref.edp(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode, 1, "lrms")
+    note("edp stereo 1280x720 q64")
+    lab, e = gpu_edp(p, 1, cost_bound=bound)
+    assert np.array_equal(lab, ref["labels"])
+    assert e == ref["energy"]
+
+
 def test_edp_motion_workload_full_size():
     p = synth.workload("motion320x240")
     ref = cref.edp(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode, 1, "lrms")
