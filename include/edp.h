@@ -32,6 +32,19 @@
  *     host before anything is enqueued; nothing is written on error.
  *   - Integer arithmetic only: results are bit-exact and deterministic.
  *     Every argmin takes the smallest flat label.
+ *   - Label spaces: the EDP scans hold a vertex's labels on one lane tile
+ *     (edp_tiles()); the largest tiles take 256 labels along one dimension
+ *     (qy == 1) and 32 x 32 labels in two dimensions.  Larger label spaces
+ *     return EDP_E_UNSUPPORTED from the EDP and DP calls (edp_dsi and
+ *     edp_energy take up to 4096 labels).
+ *   - Bounded waits: the EDP scans of one solve run as a pipelined wavefront
+ *     whose workgroups wait for each other.  Every such wait gives up after a
+ *     bounded number of polls (of the order of a second) instead of hanging the
+ *     device.  A solve whose wait gave up has invalid labels; it sets its
+ *     status word (d_status) to EDP_E_TIMEOUT and its energy word to INT64_MIN.
+ *     The call itself has returned EDP_OK by then (the wait happens on the
+ *     device), so callers that need to know read the status word after the
+ *     stream is synchronised.
  */
 #ifndef EDP_H
 #define EDP_H
@@ -49,7 +62,8 @@ typedef enum {
     EDP_E_RANGE = -2,       /* the int32 range guard failed for these parameters */
     EDP_E_WORKSPACE = -3,   /* workspace missing, misaligned or too small */
     EDP_E_HIP = -4,         /* a HIP runtime call or kernel launch failed */
-    EDP_E_UNSUPPORTED = -5  /* valid problem outside what the library implements */
+    EDP_E_UNSUPPORTED = -5, /* valid problem outside what the library implements */
+    EDP_E_TIMEOUT = -6      /* device status word only: a scan's bounded wait gave up */
 } edp_status;
 
 typedef enum { EDP_I16 = 1, EDP_I32 = 2 } edp_dtype;
@@ -153,11 +167,14 @@ edp_status edp_dp_marginals(const edp_problem* prob, const edp_tuning* tuning, c
  * cost added and S/2 taken as floor division), then the marginal of eq. DP_2D_1
  * and its smallest argmin (eq. DP_2D_2).
  *   d_labels  [H][W] int32 output labels
- *   d_energy  [1] int64 output: 4-connected energy of d_labels (nullable)
+ *   d_energy  [1] int64 output: 4-connected energy of d_labels (nullable);
+ *             INT64_MIN when a scan's bounded wait gave up
+ *   d_status  [1] int32 output (nullable): EDP_OK, or EDP_E_TIMEOUT when a
+ *             scan's bounded wait gave up (labels and energy are then invalid)
  */
 edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
-                     int32_t* d_labels, int64_t* d_energy, void* d_ws, size_t ws_bytes,
-                     void* stream);
+                     int32_t* d_labels, int64_t* d_energy, int32_t* d_status, void* d_ws,
+                     size_t ws_bytes, void* stream);
 
 /*
  * Label-window EDP: the EDP of edp_solve restricted, at every vertex x, to the
@@ -167,8 +184,10 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
  * of 8 x 8 labels and every sum handed to a neighbour is evaluated in the
  * neighbour's frame, so the work per vertex does not grow with Q.  win odd,
  * 1 <= win <= 8, boxes inside the label space (win/2 <= cx < qx - win/2, same
- * for cy); int32 costs; the truncated linear prior only (EDP_E_UNSUPPORTED
- * otherwise).  The energy is that of the labels on the full cost.
+ * for cy); qx - win <= 127 and qy - win <= 127 (the shifts between
+ * neighbouring frames are kept in 8 bits); int32 costs; the truncated linear
+ * prior only (EDP_E_UNSUPPORTED otherwise).  The energy is that of the labels
+ * on the full cost; d_energy and d_status as for edp_solve.
  * tuning: tile must be -1 or 13 (the 8 x 8 lane tile, one label per lane),
  *         split 1; waves, chunk, fuse as for edp_solve.
  *   d_centers [H][W][2] int32;  d_labels [H][W] int32 labels of the full space
@@ -177,7 +196,7 @@ edp_status edp_window_workspace_size(const edp_problem* prob, int32_t win, const
                                      size_t* bytes);
 edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
                               const int32_t* d_centers, int32_t win, int32_t* d_labels, int64_t* d_energy,
-                              void* d_ws, size_t ws_bytes, void* stream);
+                              int32_t* d_status, void* d_ws, size_t ws_bytes, void* stream);
 
 /*
  * Batches: many independent EDP instances (Algorithm 1 each, any mix of grid
@@ -192,7 +211,8 @@ typedef struct {
     edp_problem problem;
     const void* d_cost;    /* [H][W][Q] cost volume */
     int32_t* d_labels;     /* [H][W] int32 output labels */
-    int64_t* d_energy;     /* [1] int64 output: 4-connected energy (nullable) */
+    int64_t* d_energy;     /* [1] int64 output: 4-connected energy (nullable; INT64_MIN on timeout) */
+    int32_t* d_status;     /* [1] int32 output status word as for edp_solve (nullable) */
     edp_tuning tuning;     /* launch shape of this instance (events ignored) */
 } edp_batch_item;
 

@@ -191,3 +191,34 @@ def decode(logits, qx, qy, win, nclass=31, rel=1e-5):
         out.append(np.argmax(ok, axis=2) + r)
     c = np.stack(out, axis=-1)
     return np.repeat(np.repeat(c, 2, axis=0), 2, axis=1).astype(np.int32)
+
+
+def recenter(labels, qx, qy, win):
+    """Window centres [H][W][2] = (cx, cy) re-centred on a labelling: each label's column and row,
+    clamped so the win x win window stays inside the qx x qy label space."""
+    lab = np.asarray(labels, dtype=np.int64)
+    r = win // 2
+    cx = np.clip(lab % qx, r, qx - 1 - r)
+    cy = np.clip(lab // qx, r, qy - 1 - r)
+    return np.stack([cx, cy], axis=-1).astype(np.int32)
+
+
+def params_from_flat(flat, layers=LAYERS):
+    """Per-layer weights [Cout][3][3][Cin] and biases [Cout] from one flat float32 vector that holds,
+    layer after layer, the weights then the biases."""
+    flat = np.asarray(flat, dtype=np.float32)
+    out, n = [], 0
+    for cin, cout in layers:
+        nw = cout * 9 * cin
+        out.append({"w": flat[n:n + nw].reshape(cout, 3, 3, cin), "b": flat[n + nw:n + nw + cout]})
+        n += nw + cout
+    assert n == flat.size, "parameter vector does not match the layers"
+    return out
+
+
+def network_centres(cost, qx, qy, params, scale, win, pool_mode=1):
+    """Window centres [H][W][2] the network proposes for an int32 cost volume [H][W][qy*qx]: the
+    pooled input, the forward pass and the window decoding above."""
+    x = pool_cost(cost, qx, qy, scale, mode=pool_mode)
+    logits, _ = forward(x, params)
+    return decode(logits, qx, qy, win)

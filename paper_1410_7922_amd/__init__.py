@@ -6,5 +6,6 @@ The solvers live in ``libedp.so`` (C ABI: include/edp.h); ``binding`` marshals
 torch tensors into it.
 """
 from .binding import (  # noqa: F401
-    PRIOR_LINEAR, PRIOR_SQUARED, TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace, dp_marginals,
-    dp_scanline, dsi, energy, load, solve, solve_windowed, tile_info, tiles, workspace_size)
+    EDP_E_TIMEOUT, PRIOR_LINEAR, PRIOR_SQUARED, TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace,
+    check_status, dp_marginals, dp_scanline, dsi, energy, load, solve, solve_windowed, tile_info, tiles,
+    workspace_size)

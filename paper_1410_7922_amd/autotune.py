@@ -54,15 +54,17 @@ class TuneCache:
 
 
 def _time_solve(cost, p, shape, reps, ws, labels, energy):
+    status = torch.empty(1, dtype=torch.int32, device=cost.device)
     kw = dict(mode=p["mode"], iterations=p.get("iterations", 1), cost_bound=p["cost_bound"], ws=ws,
-              labels=labels, energy=energy, **{k: shape[k] for k in SHAPE_KEYS})
-    B.solve(cost, p["qx"], p["qy"], p["lam"], p["trunc"], **kw)      # warm-up
+              labels=labels, energy=energy, status=status, **{k: shape[k] for k in SHAPE_KEYS})
+    B.solve(cost, p["qx"], p["qy"], p["lam"], p["trunc"], **kw)      # warm-up (waits, checks the status)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(reps):
-        B.solve(cost, p["qx"], p["qy"], p["lam"], p["trunc"], **kw)
+        B.solve(cost, p["qx"], p["qy"], p["lam"], p["trunc"], check=False, **kw)
     stop.record()
     torch.cuda.synchronize()
+    B.check_status(status, "edp_solve")
     return start.elapsed_time(stop) / reps
 
 

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libedp.so")
 
 EDP_OK = 0
+EDP_E_TIMEOUT = -6    # status word of a solve whose scans gave up waiting (results invalid)
 EDP_I16 = 1
 EDP_I32 = 2
 TRUNC_PER_DIM = 0
@@ -44,7 +45,7 @@ class Tuning(ctypes.Structure):
 
 class BatchItem(ctypes.Structure):
     _fields_ = [("problem", Problem), ("d_cost", ctypes.c_void_p), ("d_labels", ctypes.c_void_p),
-                ("d_energy", ctypes.c_void_p), ("tuning", Tuning)]
+                ("d_energy", ctypes.c_void_p), ("d_status", ctypes.c_void_p), ("tuning", Tuning)]
 
 
 class EdpError(RuntimeError):
@@ -68,7 +69,7 @@ def load(path: str = LIB_PATH):
     pprob, ptun = ctypes.POINTER(Problem), ctypes.POINTER(Tuning)
     L.edp_workspace_size.argtypes = [pprob, ctypes.c_int32, ptun, ctypes.POINTER(sz)]
     L.edp_dp_scanline.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, sz, vp]
-    L.edp_solve.argtypes = [pprob, ptun, vp, vp, vp, vp, sz, vp]
+    L.edp_solve.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, sz, vp]
     L.edp_dp_marginals.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, vp, sz, vp]
     L.edp_dsi.argtypes = [vp, vp, vp] + [ctypes.c_int32] * 11 + [vp, vp]
     L.edp_energy.argtypes = [pprob, vp, vp, ctypes.c_int32, vp, vp, vp]
@@ -84,7 +85,7 @@ def load(path: str = LIB_PATH):
     L.edp_batch_plan_destroy.argtypes = [vp]
     L.edp_batch_plan_destroy.restype = None
     L.edp_window_workspace_size.argtypes = [pprob, ctypes.c_int32, ptun, ctypes.POINTER(sz)]
-    L.edp_solve_windowed.argtypes = [pprob, ptun, vp, vp, ctypes.c_int32, vp, vp, vp, sz, vp]
+    L.edp_solve_windowed.argtypes = [pprob, ptun, vp, vp, ctypes.c_int32, vp, vp, vp, vp, sz, vp]
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
                  "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals",
@@ -101,6 +102,15 @@ def status_string(status: int) -> str:
 def _check(status: int, where: str):
     if status != EDP_OK:
         raise EdpError(status, where)
+
+
+def check_status(status, where: str = "solve"):
+    """Raise EdpError if a solve's device status word (a tensor, or its value) is not EDP_OK.
+    Reading a device tensor waits for the solve."""
+    values = status.flatten().tolist() if isinstance(status, torch.Tensor) else [int(status)]
+    for v in values:
+        if int(v) != EDP_OK:
+            raise EdpError(int(v), where)
 
 
 def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mode: int = TRUNC_PER_DIM,
@@ -131,6 +141,10 @@ def _device_tensor(t: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a GPU tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
 
 
 def _stream(dev) -> int:
@@ -240,10 +254,14 @@ def dsi(i0: torch.Tensor, i1: torch.Tensor, qx: int, qy: int = 1, ox: int = 0, o
 def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,
           iterations: int = 1, cost_bound: int = 0, tile: int = -1, chunk: int = 0,
           ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None,
-          events=None, split: int = 0, waves: int = 0, fuse: int = 0, prior: int = PRIOR_LINEAR):
+          events=None, split: int = 0, waves: int = 0, fuse: int = 0, prior: int = PRIOR_LINEAR,
+          status: torch.Tensor | None = None, check: bool = True):
     """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors.
 
-    ``events``: optional ctypes array of hipEvent_t handles recorded around the scan launches."""
+    ``events``: optional ctypes array of hipEvent_t handles recorded around the scan launches.
+    ``status``: optional [1] int32 device tensor receiving the solve's status word.  ``check``:
+    wait for the solve and raise EdpError if its scans gave up waiting (EDP_E_TIMEOUT); with
+    check=False the call only enqueues and the caller reads ``status`` (check_status) later."""
     _device_tensor(cost, "cost")
     prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound, prior)
     nbytes = workspace_size(prob, OP_EDP, tile, chunk, split, waves, fuse)
@@ -253,17 +271,23 @@ def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 
         labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
     if energy is None:
         energy = torch.empty(1, dtype=torch.int64, device=cost.device)
+    if status is None and check:
+        status = torch.empty(1, dtype=torch.int32, device=cost.device)
     _check(load().edp_solve(ctypes.byref(prob), _tuning(tile, chunk, events, split, waves, fuse), cost.data_ptr(),
-                            labels.data_ptr(),
-                            energy.data_ptr(), w.data_ptr(), w.numel(), _stream(cost.device)), "edp_solve")
+                            labels.data_ptr(), energy.data_ptr(), _ptr(status), w.data_ptr(), w.numel(),
+                            _stream(cost.device)), "edp_solve")
+    if check:
+        check_status(status, "edp_solve")
     return labels, energy
 
 
 def solve_windowed(cost: torch.Tensor, centers: torch.Tensor, win: int, qx: int, qy: int, lam: int = 15,
                    trunc: int = 3, mode: int = TRUNC_PER_DIM, iterations: int = 1, cost_bound: int = 0,
                    ws: Workspace | None = None, labels: torch.Tensor | None = None,
-                   energy: torch.Tensor | None = None, events=None, waves: int = 0, chunk: int = 0, fuse: int = 0):
-    """Label-window EDP (edp_solve_windowed).  Returns (labels [H][W] int32, energy [1] int64)."""
+                   energy: torch.Tensor | None = None, events=None, waves: int = 0, chunk: int = 0, fuse: int = 0,
+                   status: torch.Tensor | None = None, check: bool = True):
+    """Label-window EDP (edp_solve_windowed).  Returns (labels [H][W] int32, energy [1] int64);
+    ``status`` and ``check`` as for solve()."""
     _device_tensor(cost, "cost")
     _device_tensor(centers, "centers")
     prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound)
@@ -277,9 +301,13 @@ def solve_windowed(cost: torch.Tensor, centers: torch.Tensor, win: int, qx: int,
         labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
     if energy is None:
         energy = torch.empty(1, dtype=torch.int64, device=cost.device)
+    if status is None and check:
+        status = torch.empty(1, dtype=torch.int32, device=cost.device)
     _check(load().edp_solve_windowed(ctypes.byref(prob), tu, cost.data_ptr(), centers.data_ptr(), win,
-                                     labels.data_ptr(), energy.data_ptr(), w.data_ptr(), w.numel(),
+                                     labels.data_ptr(), energy.data_ptr(), _ptr(status), w.data_ptr(), w.numel(),
                                      _stream(cost.device)), "edp_solve_windowed")
+    if check:
+        check_status(status, "edp_solve_windowed")
     return labels, energy
 
 
@@ -298,7 +326,7 @@ def energy(cost: torch.Tensor, labels: torch.Tensor, qx: int, qy: int = 1, lam: 
     return e, bad
 
 
-def batch_items(costs, params, labels, energies, tunings=None):
+def batch_items(costs, params, labels, energies, tunings=None, statuses=None):
     """ctypes array of edp_batch_item for device tensors: params[i] holds qx, qy, lam, trunc, mode,
     iterations, cost_bound, prior; tunings[i] (optional) holds tile, chunk, split, waves, fuse."""
     n = len(costs)
@@ -313,6 +341,7 @@ def batch_items(costs, params, labels, energies, tunings=None):
         items[i].d_cost = costs[i].data_ptr()
         items[i].d_labels = labels[i].data_ptr()
         items[i].d_energy = energies.data_ptr() + 8 * i if energies is not None else None
+        items[i].d_status = statuses.data_ptr() + 4 * i if statuses is not None else None
         tu = (tunings[i] if tunings else None) or {}
         items[i].tuning = Tuning(tu.get("tile", -1), tu.get("chunk", 0), tu.get("split", 0), tu.get("waves", 0),
                                  tu.get("fuse", 0), None, 0)
@@ -329,14 +358,16 @@ class BatchPlan:
     """A batch of EDP instances bound to their device tensors (edp_batch_plan_create).
 
     ``solve()`` enqueues kernels only, so it may be captured into a hipGraph
-    (torch.cuda.graph) and replayed; outputs land in ``labels[i]`` and ``energies[i]``."""
+    (torch.cuda.graph) and replayed; outputs land in ``labels[i]``, ``energies[i]`` and the status
+    words ``statuses[i]`` (``check()`` raises if a solve's scans gave up waiting)."""
 
     def __init__(self, costs, params, tunings=None, device=None):
         self.device = device or costs[0].device
         self.costs = list(costs)
         self.labels = [torch.empty(tuple(c.shape[:2]), dtype=torch.int32, device=self.device) for c in costs]
         self.energies = torch.empty(len(costs), dtype=torch.int64, device=self.device)
-        self.items = batch_items(self.costs, params, self.labels, self.energies, tunings)
+        self.statuses = torch.empty(len(costs), dtype=torch.int32, device=self.device)
+        self.items = batch_items(self.costs, params, self.labels, self.energies, tunings, self.statuses)
         nbytes = batch_workspace_size(self.items)
         self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p(None)
@@ -347,6 +378,10 @@ class BatchPlan:
     def solve(self):
         _check(load().edp_batch_solve(self.handle, _stream(self.device)), "edp_batch_solve")
         return self.labels, self.energies
+
+    def check(self):
+        """Wait for the last solve and raise EdpError if any instance's scans gave up waiting."""
+        check_status(self.statuses, "edp_batch_solve")
 
     def info(self) -> tuple:
         c, l = ctypes.c_int32(), ctypes.c_int32()
@@ -399,10 +434,6 @@ def _learn_lib():
         f.restype = ctypes.c_int32
     L._learn_ready = True
     return L
-
-
-def _ptr(t):
-    return None if t is None else t.data_ptr()
 
 
 def dsi_motion(i0: torch.Tensor, i1: torch.Tensor, r: int, cmax: int, out: torch.Tensor | None = None):

@@ -14,6 +14,8 @@
 
 namespace edp {
 
+static_assert(STATUS_TIMEOUT == EDP_E_TIMEOUT, "status word value of a timed-out solve");
+
 namespace {
 
 const TileShape kTiles[NUM_TILES] = {
@@ -366,6 +368,7 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
     g.descs = c.descs;
     g.ndesc = a.ndesc;
     g.cells_per_block = c.cells_per_block;
+    g.error = c.error;
     const hipError_t e = c.kind == KIND_WINDOW ? launch_edp_aggregate_win(g, c.agg_blocks, s)
                                                : launch_edp_aggregate(c.tile, c.dtype, g, c.agg_blocks, s);
     return e == hipSuccess ? EDP_OK : EDP_E_HIP;
@@ -398,6 +401,8 @@ edp_status win_launch(const edp_problem* prob, int32_t win, const edp_tuning* tu
     edp_status st = check_problem(prob, EDP_OP_EDP);
     if (st != EDP_OK) return st;
     if (win < 1 || win > WIN_FRAME || !(win & 1) || win > prob->qx || win > prob->qy) return EDP_E_INVALID;
+    // neighbouring centres differ by at most q - win labels per axis; the frame shifts are int8
+    if (prob->qx - win > 127 || prob->qy - win > 127) return EDP_E_UNSUPPORTED;
     if (prob->dtype != EDP_I32 || prob->prior != EDP_PRIOR_LINEAR) return EDP_E_UNSUPPORTED;
     if (tu && ((tu->tile >= 0 && tu->tile != WIN_TILE) || (tu->split > 1) || tu->chunk < 0 || tu->n_events < 0))
         return EDP_E_INVALID;
@@ -693,7 +698,7 @@ edp_status edp_dp_scanline(const edp_problem* prob, const edp_tuning* tuning, co
 }
 
 edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost, int32_t* d_labels,
-                     int64_t* d_energy, void* d_ws, size_t ws_bytes, void* stream) {
+                     int64_t* d_energy, int32_t* d_status, void* d_ws, size_t ws_bytes, void* stream) {
     edp_status st = check_problem(prob, EDP_OP_EDP);
     if (st != EDP_OK) return st;
     if (!d_cost || !d_labels) return EDP_E_INVALID;
@@ -726,6 +731,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     c.iterations = prob->iterations;
     c.ms = ms_of(prob);
     c.one = make_desc(prob, la, L.inst, ws, flags, ws + L.hand, d_cost, d_labels, nullptr);
+    c.one.status = d_status;
     c.descs = nullptr;
     c.ndesc = 1;
     c.tickets_per_pass = la.nsuper;
@@ -770,6 +776,7 @@ edp_status edp_batch_plan_create(int32_t n, const edp_batch_item* items, void* d
             const BatchEntry& e = B.e[i];
             InstDesc d = make_desc(&it.problem, e.la, e.L, ws + e.base, ctrl + e.flags_word, ws + e.hand,
                                    it.d_cost, it.d_labels, it.d_energy);
+            d.status = it.d_status;
             d.first_ticket = ticket;
             d.first_block = block;
             d.first_eblock = eblock;
@@ -885,7 +892,7 @@ edp_status edp_window_workspace_size(const edp_problem* prob, int32_t win, const
 
 edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
                               const int32_t* d_centers, int32_t win, int32_t* d_labels, int64_t* d_energy,
-                              void* d_ws, size_t ws_bytes, void* stream) {
+                              int32_t* d_status, void* d_ws, size_t ws_bytes, void* stream) {
     Launch la{};
     edp_status st = win_launch(prob, win, tuning, &la);
     if (st != EDP_OK) return st;
@@ -924,6 +931,7 @@ edp_status edp_solve_windowed(const edp_problem* prob, const edp_tuning* tuning,
     c.one.centers = d_centers;
     c.one.win = win;
     c.one.qx_full = prob->qx;
+    c.one.status = d_status;
     c.descs = nullptr;
     c.ndesc = 1;
     c.tickets_per_pass = la.nsuper;
@@ -1076,6 +1084,7 @@ const char* edp_status_string(int32_t status) {
         case EDP_E_WORKSPACE: return "workspace missing, misaligned or too small";
         case EDP_E_HIP: return "HIP runtime error";
         case EDP_E_UNSUPPORTED: return "unsupported problem";
+        case EDP_E_TIMEOUT: return "a scan's bounded wait gave up (results invalid)";
     }
     return "unknown status";
 }

@@ -13,7 +13,8 @@
 
 namespace edp {
 
-namespace {
+// The network's kernels and helpers (a named namespace, so traces show the kernel names).
+namespace cnn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -53,18 +54,48 @@ __global__ void dsi_motion_kernel(const uint8_t* i0, const uint8_t* i1, int32_t 
     }
 }
 
-// One wavefront per half-resolution pixel, one lane per channel.  mode 0: channel = block of
-// 4 x 4 labels (bx * by <= 64), the minimum over the block; mode 1: channel c < qx is the
-// minimum over the label column c, channel qx + r the minimum over the label row r (qx + qy <=
-// 64), further channels 0.  Each minimum is summed over the 2 x 2 pixels and divided by 4 scale.
+// Network input.  One wavefront per half-resolution pixel.  The label blocks of its 2 x 2
+// pixels (Q <= 1024 int32 each) are read with coalesced dword loads -- lane l takes labels l,
+// l + 64, ..., all loads of the four pixels in flight together -- into the wavefront's LDS area
+// [4][Q]; then lane c takes channel c.  mode 0: channel = block of 4 x 4 labels (bx * by <= 64),
+// the minimum over the block; mode 1: channel c < qx is the minimum over the label column c,
+// channel qx + r the minimum over the label row r (qx + qy <= 64), further channels 0.  Each
+// minimum is summed over the 2 x 2 pixels and divided by 4 scale (one float32 division).
+constexpr int POOL_QMAX = 1024;
 __global__ __launch_bounds__(256) void pool_kernel(const int32_t* cost, int32_t W, int32_t H, int32_t qx,
                                                    int32_t qy, int32_t scale, int32_t nbx, int32_t nch,
                                                    int32_t mode, uint16_t* out) {
+    extern __shared__ int32_t pool_lds[];          // [4 wavefronts][4 pixels][Q]
+    constexpr int NL = POOL_QMAX / 64;             // loads per lane and pixel at most
     const int32_t w2 = W / 2, h2 = H / 2;
-    const int64_t opix = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int32_t lane = threadIdx.x & 63;
-    if (opix >= (int64_t)w2 * h2 || lane >= nch) return;
+    const int32_t wave = (int32_t)(threadIdx.x >> 6), lane = (int32_t)(threadIdx.x & 63);
+    const int64_t opix = (int64_t)blockIdx.x * 4 + wave;
+    if (opix >= (int64_t)w2 * h2) return;          // the whole wavefront leaves; no workgroup barrier follows
     const int32_t X = (int32_t)(opix % w2), Y = (int32_t)(opix / w2);
+    const int32_t Q = qx * qy;
+    int32_t* buf = pool_lds + (size_t)wave * 4 * Q;
+    int32_t v[4][NL];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int32_t* c = cost + ((int64_t)(2 * Y + (k >> 1)) * W + (2 * X + (k & 1))) * Q;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int32_t i = lane + 64 * j;
+            v[k][j] = i < Q ? __builtin_nontemporal_load(c + i) : 0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int32_t i = lane + 64 * j;
+            if (i < Q) buf[k * Q + i] = v[k][j];
+        }
+    // the wavefront's LDS writes are performed before its reads below (LDS executes a wavefront's
+    // operations in order); the fence keeps the compiler from moving the reads above the writes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane >= nch) return;
     int32_t x0, x1, y0, y1;
     if (mode == 0) {
         const int32_t bxi = lane % nbx, byi = lane / nbx;
@@ -80,11 +111,9 @@ __global__ __launch_bounds__(256) void pool_kernel(const int32_t* cost, int32_t 
         out[opix * nch + lane] = 0;
         return;
     }
-    const int32_t Q = qx * qy;
     int64_t sum = 0;
     for (int k = 0; k < 4; ++k) {
-        const int64_t pix = (int64_t)(2 * Y + (k >> 1)) * W + (2 * X + (k & 1));
-        const int32_t* c = cost + pix * Q;
+        const int32_t* c = buf + k * Q;
         int32_t m = 0x7FFFFFFF;
         for (int32_t vy = y0; vy < y1; ++vy)
             for (int32_t vx = x0; vx < x1; ++vx) m = min(m, c[vy * qx + vx]);
@@ -400,7 +429,9 @@ hipError_t run_wgrad(const uint16_t* dy, const uint16_t* x, int32_t h, int32_t w
     return hipGetLastError();
 }
 
-}  // namespace
+}  // namespace cnn
+
+using namespace cnn;
 
 hipError_t launch_dsi_motion(const uint8_t* i0, const uint8_t* i1, int32_t W, int32_t H, int32_t r, int32_t cmax,
                              int32_t* out, hipStream_t s) {
@@ -413,8 +444,10 @@ hipError_t launch_dsi_motion(const uint8_t* i0, const uint8_t* i1, int32_t W, in
 hipError_t launch_pool(const int32_t* cost, int32_t W, int32_t H, int32_t qx, int32_t qy, int32_t scale,
                        int32_t nbx, int32_t nch, int32_t mode, uint16_t* out, hipStream_t s) {
     const int64_t n = (int64_t)(W / 2) * (H / 2);
-    hipLaunchKernelGGL(pool_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, cost, W, H, qx, qy, scale, nbx,
-                       nch, mode, out);
+    if (qx * qy > POOL_QMAX) return hipErrorInvalidValue;
+    const size_t lds = (size_t)4 * 4 * qx * qy * sizeof(int32_t);
+    hipLaunchKernelGGL(pool_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), lds, s, cost, W, H, qx, qy, scale,
+                       nbx, nch, mode, out);
     return hipGetLastError();
 }
 

@@ -52,6 +52,8 @@ TileShape tile_shape(int tile);
 constexpr uint32_t SPIN_LIMIT = 1u << 21;
 // The second scan of a fused pair waits for whole workgroup bands of the first.
 constexpr uint32_t SPIN_LIMIT_BAND = 1u << 22;
+// Value of a solve's status word when one of its bounded waits gave up (EDP_E_TIMEOUT of edp.h).
+constexpr int32_t STATUS_TIMEOUT = -6;
 
 // One instance of the EDP solve (a batch holds many of them).
 struct InstDesc {
@@ -65,6 +67,7 @@ struct InstDesc {
                                   // (first / second scan of a launch), cleared each solve; or null
     const void* aux;              // label-window solve: int8 frame shifts [H][W][4][2], else null
     const int32_t* centers;       // label-window solve: window centres [H][W][2], else null
+    int32_t* status;              // [1] output status word of the solve (0 or STATUS_TIMEOUT), may be null
     int32_t win, qx_full;         // label-window solve: window side, labels along x of the full space
     int32_t W, H, qx, qy;
     int32_t lam, clipd, joint, trunc;
@@ -139,6 +142,8 @@ struct AggArgs {
     const InstDesc* descs;
     int32_t ndesc;
     int32_t cells_per_block;
+    const uint32_t* error;   // error word of the scans (nonzero: a wait gave up); the first block of
+                             // each instance writes the instance's status word from it
 };
 
 struct DpArgs {

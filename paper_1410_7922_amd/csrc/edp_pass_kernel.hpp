@@ -636,6 +636,9 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
     const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     const int32_t cells = W * H;
+    // the scans ran before this launch on the same stream: their error word is final
+    if (threadIdx.x == 0 && blk == d.first_block && d.status)
+        *d.status = (a.error && *a.error != 0) ? STATUS_TIMEOUT : 0;
     const int32_t cell = (blk - d.first_block) * a.cells_per_block + wave * RPW + grp;
     const bool ok = cell < cells;
     const int32_t y = ok ? cell / W : 0, x = ok ? cell % W : 0;

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     assert B.status_string(0) == "ok"
-    for s in (-1, -2, -3, -4, -5):
+    for s in (-1, -2, -3, -4, -5, -6):
         assert B.status_string(s) != "unknown status"
     assert B.status_string(42) == "unknown status"
 
@@ -145,13 +145,37 @@ def test_workspace_and_pointer_errors_are_host_side():
     st, need = _ws(p, B.OP_EDP)
     assert st == 0
     # too small, misaligned, null: rejected before any launch
-    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, fake, need - 1, None) == -3
-    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, ctypes.c_void_p((1 << 40) + 8), need, None) == -3
-    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, None, need, None) == -3
-    assert lib.edp_solve(ctypes.byref(p), None, None, fake, fake, fake, need, None) == -1
+    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, fake, fake, need - 1, None) == -3
+    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, fake, ctypes.c_void_p((1 << 40) + 8), need,
+                         None) == -3
+    assert lib.edp_solve(ctypes.byref(p), None, fake, fake, fake, None, None, need, None) == -3
+    assert lib.edp_solve(ctypes.byref(p), None, None, fake, fake, fake, fake, need, None) == -1
     assert lib.edp_dp_scanline(ctypes.byref(p), None, fake, None, None, None, fake, 1 << 30, None) == -1
     assert lib.edp_energy(ctypes.byref(p), fake, fake, 2, fake, None, None) == -1
-    assert lib.edp_solve(None, None, fake, fake, fake, fake, need, None) == -1
+    assert lib.edp_solve(None, None, fake, fake, fake, fake, fake, need, None) == -1
+
+
+def test_window_shift_codes_fit_eight_bits():
+    # neighbouring window centres differ by up to q - win labels, kept as int8 frame shifts
+    lib = B.load()
+    n = ctypes.c_size_t(0)
+    ok = _prob(width=12, height=10, qx=134, qy=9, dtype=2, cost_bound=100, lam=5, trunc=3)
+    assert lib.edp_window_workspace_size(ctypes.byref(ok), 7, None, ctypes.byref(n)) == 0
+    wide = _prob(width=12, height=10, qx=135, qy=9, dtype=2, cost_bound=100, lam=5, trunc=3)
+    assert lib.edp_window_workspace_size(ctypes.byref(wide), 7, None, ctypes.byref(n)) == -5
+    tall = _prob(width=12, height=10, qx=9, qy=135, dtype=2, cost_bound=100, lam=5, trunc=3)
+    assert lib.edp_window_workspace_size(ctypes.byref(tall), 7, None, ctypes.byref(n)) == -5
+
+
+def test_status_word_check_raises_on_timeout():
+    import torch
+    B.check_status(torch.zeros(3, dtype=torch.int32))
+    B.check_status(0)
+    with pytest.raises(B.EdpError) as e:
+        B.check_status(torch.tensor([0, B.EDP_E_TIMEOUT, 0], dtype=torch.int32), "batch")
+    assert e.value.status == B.EDP_E_TIMEOUT and "gave up" in str(e.value)
+    with pytest.raises(B.EdpError):
+        B.check_status(B.EDP_E_TIMEOUT)
 
 
 def _items(probs, fake=1 << 40):
@@ -161,6 +185,7 @@ def _items(probs, fake=1 << 40):
         items[i].d_cost = fake
         items[i].d_labels = fake + (1 << 30)
         items[i].d_energy = None
+        items[i].d_status = None
         items[i].tuning = B.Tuning(-1, 0, 0, 0, 0, None, 0)
     return items
 

@@ -1,6 +1,10 @@
 """GPU parity of the batched persistent solve (edp_batch_plan_create / edp_batch_solve):
 every instance bit-exact against the CPU oracle or against the single-instance solve, eagerly
 and replayed from a captured hipGraph."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -90,7 +94,13 @@ def test_batch_graph_replays_match_eager():
 
 
 def test_batch_workload_64_instances():
+    """Every instance of the 64-instance batch against the C oracle's energy and label hash
+    (tests/golden/edp_batch64.json, written by tests/golden/make_batch64.py from oracle/ and synth/
+    only), and against the single-instance solve."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "edp_batch64.json")) as f:
+        golden = json.load(f)["instances"]
     probs = synth.batch_problems(64)
+    assert len(golden) == len(probs)
     costs = [torch.from_numpy(p.cost).to(DEV) for p in probs]
     bounds = [50 if p.cost.dtype == np.int16 else 2500 for p in probs]
     params = [params_of(p, 1, b) for p, b in zip(probs, bounds)]
@@ -99,19 +109,16 @@ def test_batch_workload_64_instances():
     note(f"batch workload: 64 instances, {classes} classes, {launches} launches")
     labels, energies = plan.solve()
     torch.cuda.synchronize()
+    plan.check()
+    for i, p in enumerate(probs):
+        g = golden[i]
+        assert g["cost_sha256"] == p.sha256(), f"instance {i}: the generator's cost volume changed"
+        lab = np.ascontiguousarray(labels[i].cpu().numpy(), np.int32)
+        assert hashlib.sha256(lab.tobytes()).hexdigest() == g["labels_sha256"], f"instance {i} ({p.name}) labels"
+        assert int(energies[i].item()) == g["energy"], f"instance {i} ({p.name}) energy"
     ws = edp.Workspace()
     for i, p in enumerate(probs):
         lab, e = edp.solve(costs[i], p.qx, p.qy, p.lam, p.trunc, p.mode, 1, cost_bound=bounds[i], ws=ws)
-        torch.cuda.synchronize()
         assert torch.equal(lab, labels[i]), i
         assert int(e.item()) == int(energies[i].item()), i
-    # the oracle on the smallest instance of each kind
-    picks = [min((i for i, p in enumerate(probs) if p.qy == 1), key=lambda i: probs[i].pixel_labels),
-             min((i for i, p in enumerate(probs) if p.qy > 1), key=lambda i: probs[i].pixel_labels)]
-    for i in picks:
-        p = probs[i]
-        note(f"batch workload oracle check {p.name}")
-        ref = cref.edp(p.cost, p.qx, p.qy, p.lam, p.trunc, p.mode, 1, "lrms")
-        assert np.array_equal(labels[i].cpu().numpy(), ref["labels"]), i
-        assert int(energies[i].item()) == ref["energy"], i
     plan.close()

@@ -83,3 +83,36 @@ def test_gap_judge_and_fallback():
     assert not out["fallback"] and out["energy"] == int(e_w.item())
     assert torch.equal(out["labels"], lab_w)
     assert out["gap"] == pytest.approx((int(e_w.item()) - int(e_p.item())) / int(e_p.item()))
+
+
+def test_windowed_solve_640x480_equals_oracle_golden():
+    """The full-size windowed solve (640x480, 961 labels, 7x7 windows) with the network's centres
+    as the oracle computes them (cnn_ref forward pass on the committed weights), and one round
+    re-centred on its labels, against the oracle's energies and label hashes
+    (tests/golden/edp_window640x480_q961.json, written by make_window640x480_q961.py)."""
+    import hashlib
+    import json
+    import os
+    from oracle import cnn_ref
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "edp_window640x480_q961.json")) as f:
+        g = json.load(f)
+    p = synth.workload("motion640x480")
+    assert p.sha256() == g["cost_sha256"]
+    weights = os.path.join(os.path.dirname(here), "paper_1410_7922_amd", "weights", "window_net_31x31.npz")
+    with np.load(weights, allow_pickle=False) as f:
+        params = cnn_ref.params_from_flat(f["params"])
+        mode = int(f["pool_mode"])
+    note("oracle network centres 640x480")
+    cen = cnn_ref.network_centres(p.cost, 31, 31, params, g["scale"], g["win"], mode)
+    sha = lambda a: hashlib.sha256(np.ascontiguousarray(a, np.int32).tobytes()).hexdigest()
+    assert sha(cen) == g["rounds"][0]["centres_sha256"], "the oracle's centres differ from the golden's"
+    cost = torch.from_numpy(p.cost).to(DEV)
+    cen_t = torch.from_numpy(cen).to(DEV)
+    for rnd in g["rounds"]:
+        note(f"windowed solve 640x480 against the oracle golden, centres {rnd['centres_sha256'][:12]}")
+        assert sha(cen_t.cpu().numpy()) == rnd["centres_sha256"]
+        lab, e = B.solve_windowed(cost, cen_t, g["win"], 31, 31, g["lam"], g["trunc"], g["mode"], 1, cost_bound=2500)
+        assert int(e.item()) == rnd["energy"]
+        assert sha(lab.cpu().numpy()) == rnd["labels_sha256"]
+        cen_t = B.window_recenter(lab, 31, 31, g["win"], torch.empty_like(cen_t))

@@ -90,3 +90,16 @@ def test_motion_31x31_mid_size_matches_oracle():
     lab, e = gpu_win(p, cen, 7, cost_bound=2500)
     ref = cref.edp_window(p.cost, cen, 7, 31, 31, p.lam, p.trunc, p.mode, 1)
     assert np.array_equal(lab, ref["labels"]) and e == ref["energy"]
+
+
+def test_wide_label_axis_at_the_shift_limit():
+    # centres along x anywhere in [3, 130]: neighbouring frames differ by up to 127 labels, the
+    # largest shift the frames' 8-bit shift codes hold (qx - win = 127)
+    p = synth.random_problem(91, 12, 10, 134, 9, 5, 3, 0, 0, 400)
+    rng = np.random.default_rng(91)
+    cen = centers_for(rng, 10, 12, 134, 9, 7)
+    cen[0, 0, 0], cen[0, 1, 0] = 3, 130
+    note("window 12x10 with 134x9 labels, shifts up to 127")
+    lab, e = gpu_win(p, cen, 7)
+    ref = cref.edp_window(p.cost, cen, 7, 134, 9, 5, 3, 0, 1)
+    assert np.array_equal(lab, ref["labels"]) and e == ref["energy"]
