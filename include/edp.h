@@ -177,6 +177,24 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
                      size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): edp_solve with its
+ * workspace in a static device array of EDP_STATIC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends.  The call
+ * allocates nothing.  Problems whose EDP workspace (edp_workspace_size with
+ * EDP_OP_EDP and the same tuning) exceeds the array return EDP_E_WORKSPACE
+ * before anything is enqueued; for example stereo 384 x 288 with 32
+ * disparities (about 60 MB) fits.  stream must belong to the current device
+ * (EDP_E_INVALID otherwise).  Every call on one GPU uses that GPU's single
+ * array, so calls that overlap on one GPU (on different streams or from
+ * different host threads) race and give wrong results; calls one after another
+ * on one stream are fine.  Arguments and results as for edp_solve.
+ */
+#define EDP_STATIC_SCRATCH_BYTES (64u << 20)
+edp_status edp_solve_static(const edp_problem* prob, const edp_tuning* tuning, const void* d_cost,
+                            int32_t* d_labels, int64_t* d_energy, int32_t* d_status, void* stream);
+
+/*
  * Label-window EDP: the EDP of edp_solve restricted, at every vertex x, to the
  * win x win box of labels centred on d_centers[y][x] = (cx, cy) -- by
  * definition the plain EDP on the cost volume with every label outside the

@@ -29,7 +29,7 @@ OP_DP_MARGINALS = 2
 EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
            "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
            "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy", "edp_window_workspace_size",
-           "edp_solve_windowed", "edp_dp_marginals", "edp_dsi")
+           "edp_solve_windowed", "edp_dp_marginals", "edp_dsi", "edp_solve_static")
 
 
 class Problem(ctypes.Structure):
@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
     L.edp_workspace_size.argtypes = [pprob, ctypes.c_int32, ptun, ctypes.POINTER(sz)]
     L.edp_dp_scanline.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, sz, vp]
     L.edp_solve.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, sz, vp]
+    L.edp_solve_static.argtypes = [pprob, ptun, vp, vp, vp, vp, vp]
     L.edp_dp_marginals.argtypes = [pprob, ptun, vp, vp, vp, vp, vp, vp, sz, vp]
     L.edp_dsi.argtypes = [vp, vp, vp] + [ctypes.c_int32] * 11 + [vp, vp]
     L.edp_energy.argtypes = [pprob, vp, vp, ctypes.c_int32, vp, vp, vp]
@@ -89,7 +90,7 @@ def load(path: str = LIB_PATH):
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
                  "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals",
-                 "edp_dsi"):
+                 "edp_dsi", "edp_solve_static"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -278,6 +279,31 @@ def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 
                             _stream(cost.device)), "edp_solve")
     if check:
         check_status(status, "edp_solve")
+    return labels, energy
+
+
+def solve_static(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2, mode: int = TRUNC_PER_DIM,
+                 iterations: int = 1, cost_bound: int = 0, labels: torch.Tensor | None = None,
+                 energy: torch.Tensor | None = None, status: torch.Tensor | None = None, check: bool = True,
+                 prior: int = PRIOR_LINEAR, tile: int = -1, chunk: int = 0, split: int = 0, waves: int = 0,
+                 fuse: int = 0):
+    """EDP with the library's static workspace (edp_solve_static): the library allocates nothing;
+    pass ``labels``, ``energy`` and ``status`` to allocate nothing here either.  Returns (labels, energy)
+    as solve()."""
+    _device_tensor(cost, "cost")
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound, prior)
+    H, W, _ = cost.shape
+    if labels is None:
+        labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
+    if energy is None:
+        energy = torch.empty(1, dtype=torch.int64, device=cost.device)
+    if status is None and check:
+        status = torch.empty(1, dtype=torch.int32, device=cost.device)
+    _check(load().edp_solve_static(ctypes.byref(prob), _tuning(tile, chunk, None, split, waves, fuse), cost.data_ptr(),
+                                   labels.data_ptr(), energy.data_ptr(), _ptr(status), _stream(cost.device)),
+           "edp_solve_static")
+    if check:
+        check_status(status, "edp_solve_static")
     return labels, energy
 
 

@@ -220,3 +220,15 @@ def test_batch_workspace_and_host_side_errors():
     assert lib.edp_batch_solve(None, None) == -1
     assert lib.edp_batch_plan_info(None, None, None) == -1
     lib.edp_batch_plan_destroy(None)
+
+
+def test_static_workspace_solve_refuses_problems_beyond_its_array():
+    # the 961-label motion workload needs gigabytes of workspace: refused on the host, before any
+    # device work (no GPU needed)
+    lib = B.load()
+    fake = ctypes.c_void_p(1 << 40)
+    big = _prob(width=640, height=480, qx=31, qy=31, dtype=2, cost_bound=2500, lam=15, trunc=3)
+    assert lib.edp_solve_static(ctypes.byref(big), None, fake, fake, None, None, None) == -3
+    assert lib.edp_solve_static(None, None, fake, fake, None, None, None) == -1
+    bad = _prob(trunc=0)
+    assert lib.edp_solve_static(ctypes.byref(bad), None, fake, fake, None, None, None) == -1
