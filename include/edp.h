@@ -33,10 +33,12 @@
  *   - Integer arithmetic only: results are bit-exact and deterministic.
  *     Every argmin takes the smallest flat label.
  *   - Label spaces: the EDP scans hold a vertex's labels on one lane tile
- *     (edp_tiles()); the largest tiles take 256 labels along one dimension
- *     (qy == 1) and 32 x 32 labels in two dimensions.  Larger label spaces
- *     return EDP_E_UNSUPPORTED from the EDP and DP calls (edp_dsi and
- *     edp_energy take up to 4096 labels).
+ *     (edp_tiles()) or, for two label dimensions with a window search
+ *     (T <= 3), on a wide tile of several wavefronts (edp_wide_tiles()); the
+ *     largest tiles take 256 labels along one dimension (qy == 1) and
+ *     32 x 32 labels in two dimensions.  Larger label spaces return
+ *     EDP_E_UNSUPPORTED from the EDP and DP calls (edp_dsi and edp_energy
+ *     take up to 4096 labels).
  *   - Bounded waits: the EDP scans of one solve run as a pipelined wavefront
  *     whose workgroups wait for each other.  Every such wait gives up after a
  *     bounded number of polls (of the order of a second) instead of hanging the
@@ -88,7 +90,8 @@ typedef struct {
 
 /* Optional tuning of the launch (results never depend on it).  NULL, or a
  * zero / negative field, selects the built-in choice:
- *   tile   lane tile mapping labels to lanes (edp_tiles(); -1 automatic)
+ *   tile   lane tile mapping labels to lanes (edp_tiles(), or for the EDP
+ *          scans also edp_wide_tiles(); -1 automatic)
  *   chunk  EDP columns a workgroup hands to the next one between two
  *          progress publications, at least (rounded up to a power of two);
  *          only where the hand-off publishes column counts (wavefronts of
@@ -98,7 +101,9 @@ typedef struct {
  *          2: the two searches run on two halves of the vertex's lanes
  *   waves  compute wavefronts per EDP workgroup (1..6), handing rows over in
  *          LDS; every workgroup has two more wavefronts that move the rows
- *          between workgroups
+ *          between workgroups.  Wide tiles: scanlines per workgroup (at most
+ *          12 / (its wavefronts per vertex)); rows go between workgroups as
+ *          tagged words
  *   fuse   EDP scans per launch: 1, or 2 (P1 with P2, P3 with P4: the two
  *          scans of a pair sweep the rows in the same order, so the second
  *          follows the first a few rows behind inside one launch)
@@ -298,7 +303,16 @@ edp_status edp_energy(const edp_problem* prob, const void* d_cost, const int32_t
  * (nullable) and returns how many exist; a negative value is an edp_status. */
 int32_t edp_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max);
 
-/* Shape of a tile: lanes px * py per cell, labels kx * ky per lane. */
+/* Wide-vertex tiles of the EDP scans usable for a (qx, qy) label space (two
+ * label dimensions, truncation T <= 3 so the minimum search is the general RMS
+ * window of at most two steps per side, Sec. 3.1).  A vertex takes py / 4
+ * wavefronts, each holding 4 ky label rows of 16 kx labels; its scans exchange
+ * the label rows at slab edges through LDS at every step (Sec. 3 eq. M_decmp:
+ * one window per label dimension).  Same return convention as edp_tiles(). */
+int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max);
+
+/* Shape of a tile (edp_tiles() or edp_wide_tiles()): lanes px * py per cell,
+ * labels kx * ky per lane. */
 edp_status edp_tile_info(int32_t tile, int32_t* px, int32_t* kx, int32_t* py, int32_t* ky);
 
 /* Static text for a status code. */

@@ -29,7 +29,7 @@ OP_DP_MARGINALS = 2
 EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
            "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
            "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy", "edp_window_workspace_size",
-           "edp_solve_windowed", "edp_dp_marginals", "edp_dsi", "edp_solve_static")
+           "edp_solve_windowed", "edp_dp_marginals", "edp_dsi", "edp_solve_static", "edp_wide_tiles")
 
 
 class Problem(ctypes.Structure):
@@ -75,6 +75,7 @@ def load(path: str = LIB_PATH):
     L.edp_dsi.argtypes = [vp, vp, vp] + [ctypes.c_int32] * 11 + [vp, vp]
     L.edp_energy.argtypes = [pprob, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.edp_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    L.edp_wide_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.edp_tile_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
     L.edp_status_string.argtypes = [ctypes.c_int32]
     L.edp_status_string.restype = ctypes.c_char_p
@@ -90,7 +91,7 @@ def load(path: str = LIB_PATH):
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
                  "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals",
-                 "edp_dsi", "edp_solve_static"):
+                 "edp_dsi", "edp_solve_static", "edp_wide_tiles"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -168,6 +169,17 @@ def tiles(qx: int, qy: int = 1) -> list:
         raise EdpError(n, "edp_tiles")
     ids = (ctypes.c_int32 * max(n, 1))()
     L.edp_tiles(qx, qy, ids, n)
+    return list(ids[:n])
+
+
+def wide_tiles(qx: int, qy: int) -> list:
+    """Wide-vertex tiles (a vertex on several wavefronts) of the EDP scans for a label space."""
+    L = load()
+    n = L.edp_wide_tiles(qx, qy, None, 0)
+    if n < 0:
+        raise EdpError(n, "edp_wide_tiles")
+    ids = (ctypes.c_int32 * max(n, 1))()
+    L.edp_wide_tiles(qx, qy, ids, n)
     return list(ids[:n])
 
 

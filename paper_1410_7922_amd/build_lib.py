@@ -15,6 +15,8 @@ SOURCES = [
     "edp_pass_t0.hip", "edp_pass_t1.hip", "edp_pass_t2.hip", "edp_pass_t3.hip",
     "edp_pass_q0.hip", "edp_pass_q1.hip", "edp_pass_q2.hip", "edp_pass_q3.hip",
     "edp_api.hip", "edp_pass.hip",
+    # scans and marginal of the wide-vertex tiles (a vertex on several wavefronts)
+    "edp_pass_mv.hip",
     # edp_solve with its workspace in a static device array (callers that cannot allocate)
     "edp_static.hip",
     # scanline DP: choice indexes and backtracking; min-marginals per tile group

@@ -18,11 +18,18 @@ static_assert(STATUS_TIMEOUT == EDP_E_TIMEOUT, "status word value of a timed-out
 
 namespace {
 
-const TileShape kTiles[NUM_TILES] = {
+// single-wavefront tiles, then the wide-vertex tiles as 16 x (4 NV) lane grids
+const TileShape kTiles[NUM_ALL_TILES] = {
 #define EDP_ROW(id, px, kx, py, ky) {px, kx, py, ky},
     EDP_TILE_LIST(EDP_ROW)
 #undef EDP_ROW
+#define EDP_MV_ROW(id, kx, ky, nv) {16, kx, 4 * nv, ky},
+    EDP_MV_TILE_LIST(EDP_MV_ROW)
+#undef EDP_MV_ROW
 };
+
+bool is_wide(int tile) { return tile >= NUM_TILES && tile < NUM_ALL_TILES; }
+int wide_nv(int tile) { return kTiles[tile].py / 4; }
 
 constexpr size_t kAlign = 256;
 size_t up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
@@ -128,14 +135,79 @@ edp_status pick_tile(const edp_problem* p, const edp_tuning* tu, int* tile) {
 }
 
 struct Launch {
-    int tile, split, waves, chunk, ring, fuse;
+    int tile, split, waves, chunk, ring, fuse;   // wide tiles: waves = scanlines per workgroup
     int rpw;            // scanlines per wavefront
     int nbands, nsuper;
 };
 
+// Tags of the wide tiles' hand-off words (scan, workgroup band, column) must stay distinct
+// within a solve.
+bool wide_tags_fit(const edp_problem* p, int64_t nsuper) {
+    return (int64_t)4 * p->iterations * nsuper * ((int64_t)p->width + 1) + p->width + 2 < ((int64_t)1 << 32);
+}
+
+// Launch shape of the wide-vertex scans: scanlines per workgroup (at most 12 wavefronts) and
+// LDS ring depth (largest power of two up to 8 that fits the 160 KB of LDS with the exchange
+// planes).
+edp_status pick_wide_launch(const edp_problem* p, const edp_tuning* tu, int tile, Launch* L) {
+    const int ms = ms_of(p);
+    if (ms != MS_WINDOW && ms != MS_WINDOW1) return EDP_E_UNSUPPORTED;
+    if (tu && tu->split > 1) return EDP_E_INVALID;
+    const int nv = wide_nv(tile);
+    const int max_rows = MV_MAX_WAVES / nv;
+    constexpr size_t kLds = 160 * 1024;
+    int rows = max_rows;
+    // built-in: the most scanlines whose exchange planes and rings of 4 slots fit the LDS
+    while (rows > 1 && pass_mv_lds_bytes(tile, ms, rows, 4) > kLds) --rows;
+    if (tu && tu->waves > 0) rows = tu->waves;
+    if (rows > max_rows) return EDP_E_INVALID;
+    const int fuse = (tu && tu->fuse > 0) ? tu->fuse : 2;
+    if (fuse != 1 && fuse != 2) return EDP_E_INVALID;
+    int ring = 8;
+    while (ring > 2 && pass_mv_lds_bytes(tile, ms, rows, ring) > kLds) ring >>= 1;
+    if (pass_mv_lds_bytes(tile, ms, rows, ring) > kLds) return EDP_E_UNSUPPORTED;
+    L->tile = tile;
+    L->split = 1;
+    L->waves = rows;
+    L->fuse = fuse;
+    L->chunk = 1;
+    L->ring = ring;
+    L->rpw = 1;
+    L->nbands = p->height;
+    L->nsuper = (p->height + rows - 1) / rows;
+    if (!wide_tags_fit(p, L->nsuper)) return EDP_E_UNSUPPORTED;
+    return EDP_OK;
+}
+
+// Built-in choice for the EDP scans: a wide-vertex tile where a single-wavefront tile would
+// hold 8 or more labels per lane (two label dimensions, window search), the fewest padded
+// labels first, then the most wavefronts per vertex; else the single-wavefront choice.
+int auto_scan_tile(const edp_problem* p) {
+    const int t = auto_tile(p->qx, p->qy);
+    const int ms = ms_of(p);
+    if (p->qy < 2 || (ms != MS_WINDOW && ms != MS_WINDOW1) || (t >= 0 && elems_of(t) < 8)) return t;
+    int best = -1;
+    for (int w = NUM_TILES; w < NUM_ALL_TILES; ++w) {
+        if (!fits(w, p->qx, p->qy)) continue;
+        if (best < 0 || qt_of(w) < qt_of(best) || (qt_of(w) == qt_of(best) && wide_nv(w) > wide_nv(best))) best = w;
+    }
+    if (best < 0) return t;
+    Launch la{};
+    return pick_wide_launch(p, nullptr, best, &la) == EDP_OK ? best : t;
+}
+
 // Launch shape of the EDP scans for a problem and an optional tuning.
 edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
-    edp_status st = pick_tile(p, tu, &L->tile);
+    const int want = (tu && tu->tile >= 0) ? tu->tile : auto_scan_tile(p);
+    if (want < 0) return EDP_E_UNSUPPORTED;
+    if (is_wide(want)) {
+        if (!fits(want, p->qx, p->qy)) return EDP_E_INVALID;
+        return pick_wide_launch(p, tu, want, L);
+    }
+    edp_tuning t1{};
+    if (tu) t1 = *tu;
+    t1.tile = want;
+    edp_status st = pick_tile(p, &t1, &L->tile);
     if (st != EDP_OK) return st;
     const int g = group_of(L->tile);
     int split = (tu && tu->split > 0) ? tu->split : 1;
@@ -187,6 +259,8 @@ InstLayout inst_layout(const edp_problem* p, const Launch& la) {
     L.nflags = (size_t)3 * la.nsuper;
     const size_t hand = (size_t)2 * (la.nsuper > 1 ? la.nsuper - 1 : 0) * p->width * qt_of(la.tile) * 8;
     L.hand_bytes = la.rpw >= 2 && hand <= kHandMax ? up(hand) : 0;
+    // wide tiles: two rows per scan of a launch, used by alternate workgroup bands
+    if (is_wide(la.tile)) L.hand_bytes = la.nsuper > 1 ? up((size_t)4 * p->width * qt_of(la.tile) * 8) : 0;
     return L;
 }
 
@@ -315,11 +389,13 @@ struct ClassRun {
     uint32_t* error;
 };
 
-int agg_cells_per_block(int tile) { return (64 / group_of(tile)) * 4; }
+int agg_cells_per_block(int tile) { return is_wide(tile) ? 4 : (64 / group_of(tile)) * 4; }
 
 int scan_grid(const ClassRun& c) {
     const int cap =
-        pass_capacity(c.tile, c.kind, c.split, c.ms, c.waves, pass_lds_bytes(qt_of(c.tile), c.waves, c.ring));
+        is_wide(c.tile)
+            ? pass_mv_capacity(c.tile, c.kind, c.ms, c.waves, pass_mv_lds_bytes(c.tile, c.ms, c.waves, c.ring))
+            : pass_capacity(c.tile, c.kind, c.split, c.ms, c.waves, pass_lds_bytes(qt_of(c.tile), c.waves, c.ring));
     const int total = c.fuse * c.tickets_per_pass;
     return total < cap ? total : cap;
 }
@@ -358,7 +434,9 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
             a.ticket = c.tickets + launch;
             const bool timed = ev && ev->events && 2 * launch + 1 < ev->n_events;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch], s) != hipSuccess) return EDP_E_HIP;
-            if (launch_edp_pass(c.tile, c.kind, c.split, c.ms, a, grid, c.waves, s) != hipSuccess) return EDP_E_HIP;
+            const hipError_t le = is_wide(c.tile) ? launch_edp_pass_mv(c.tile, c.kind, c.ms, a, grid, c.waves, s)
+                                                  : launch_edp_pass(c.tile, c.kind, c.split, c.ms, a, grid, c.waves, s);
+            if (le != hipSuccess) return EDP_E_HIP;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch + 1], s) != hipSuccess)
                 return EDP_E_HIP;
         }
@@ -370,6 +448,7 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
     g.cells_per_block = c.cells_per_block;
     g.error = c.error;
     const hipError_t e = c.kind == KIND_WINDOW ? launch_edp_aggregate_win(g, c.agg_blocks, s)
+                         : is_wide(c.tile)     ? launch_edp_aggregate_mv(c.tile, c.dtype, g, c.agg_blocks, s)
                                                : launch_edp_aggregate(c.tile, c.dtype, g, c.agg_blocks, s);
     return e == hipSuccess ? EDP_OK : EDP_E_HIP;
 }
@@ -1067,8 +1146,19 @@ int32_t edp_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
     return n;
 }
 
+int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
+    if (qx < 1 || qy < 1 || max < 0) return EDP_E_INVALID;
+    int n = 0;
+    for (int t = NUM_TILES; t < NUM_ALL_TILES; ++t) {
+        if (!fits(t, qx, qy)) continue;
+        if (ids && n < max) ids[n] = t;
+        ++n;
+    }
+    return n;
+}
+
 edp_status edp_tile_info(int32_t tile, int32_t* px, int32_t* kx, int32_t* py, int32_t* ky) {
-    if (tile < 0 || tile >= NUM_TILES || !px || !kx || !py || !ky) return EDP_E_INVALID;
+    if (tile < 0 || tile >= NUM_ALL_TILES || !px || !kx || !py || !ky) return EDP_E_INVALID;
     *px = kTiles[tile].px;
     *kx = kTiles[tile].kx;
     *py = kTiles[tile].py;

@@ -25,9 +25,23 @@
     X(14, 4, 2, 4, 2)    \
     X(15, 4, 8, 16, 2)
 
+// Wide-vertex tiles of the EDP scans for two-dimensional label spaces: id, KX, KY, NV.
+// A vertex takes NV wavefronts; each holds 4 KY label rows of 16 KX labels (lane px of lane
+// row r: KX x KY labels), so the tile holds (16 KX) x (4 KY NV) labels and its lane-major
+// layout is that of a 16 x (4 NV) lane grid.  Ids follow the single-wavefront tiles.
+#define EDP_MV_TILE_LIST(X) \
+    X(16, 2, 2, 4)          \
+    X(17, 2, 4, 2)          \
+    X(18, 1, 2, 2)
+
 namespace edp {
 
 constexpr int NUM_TILES = 16;
+constexpr int NUM_MV_TILES = 3;
+constexpr int NUM_ALL_TILES = NUM_TILES + NUM_MV_TILES;
+// A wide-vertex tile holds at most this many scanlines per workgroup times its wavefronts
+// per vertex: 12 wavefronts (768 lanes).
+constexpr int MV_MAX_WAVES = 12;
 // compute wavefronts per workgroup of the scan kernel; with its two helper wavefronts a
 // workgroup has at most 8, two per SIMD, so each may use half the register file
 constexpr int MAX_WAVES = 6;
@@ -265,6 +279,11 @@ hipError_t launch_recenter(const int32_t* labels, int64_t n, int32_t qx, int32_t
                            hipStream_t s);
 
 int pass_capacity(int tile, int kind, int split, int ms, int waves, size_t lds_bytes);
+// Wide-vertex scans (tiles NUM_TILES ...): rows = scanlines per workgroup; window kinds only.
+hipError_t launch_edp_pass_mv(int tile, int kind, int ms, const PassArgs& a, int grid, int rows, hipStream_t s);
+hipError_t launch_edp_aggregate_mv(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
+size_t pass_mv_lds_bytes(int tile, int ms, int rows, int ring);
+int pass_mv_capacity(int tile, int kind, int ms, int rows, size_t lds_bytes);
 // LDS bytes of the pass kernel for a tile, wavefronts per workgroup and ring slots.
 size_t pass_lds_bytes(int qt, int waves, int ring);
 

@@ -280,14 +280,15 @@ def test_energy_kernel_matches_oracle():
 def test_edp_motion640x480_961_labels_full_size():
     """The 961-label motion workload 640x480 (the plain solve of the learned-window comparison) at
     full size, against the C oracle's result stored by tests/golden/make_motion640x480_q961.py:
-    energy and labels (SHA-256), under the built-in launch and the other 31x31 tile."""
+    energy and labels (SHA-256), under the built-in launch (a wide tile: four wavefronts per
+    vertex), the single-wavefront 32x32 tiles and the wide tile of two wavefronts per vertex."""
     import hashlib
     import json
     import os
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "edp_motion640x480_q961.json")))
     p = synth.workload("motion640x480")
     assert p.sha256() == g["cost_sha256"]
-    for tile in (-1, 15):
+    for tile in (-1, 12, 15, 17):
         note(f"edp motion640x480 961 labels tile {tile}")
         lab, e = gpu_edp(p, 1, tile, cost_bound=2500)
         assert e == g["energy"], tile
