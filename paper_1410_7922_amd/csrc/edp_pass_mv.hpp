@@ -26,8 +26,8 @@
 // A workgroup holds RW consecutive scanlines of one scan, each on NV wavefronts.
 // Scanline k hands T_b to scanline k + 1 through an LDS ring per wavefront slab;
 // the last scanline of the workgroup stores it as tagged 64-bit words (value and
-// a tag naming scan, workgroup band and column) that the first scanline of the
-// next workgroup polls, two row buffers per scan of a launch used alternately by
+// a tag naming scan, workgroup band and column; word-major, so every store is a
+// whole run of sectors) that two helper wavefronts of the next workgroup poll, two row buffers per scan of a launch used alternately by
 // consecutive workgroup bands (a band writes column c only after the band below
 // the previous user of the buffer has read column c: it needs that band's result
 // at column c first).  Workgroups take bands in scan order from a ticket counter,
@@ -86,13 +86,18 @@ __device__ __forceinline__ int32_t min_dpp(int32_t v, const int32_t src) {
 // Smallest of N consecutive LDS counters (N = 1, 2, 4; 4 N-byte aligned), read with one access.
 template <int N>
 __device__ __forceinline__ int32_t lds_min_ctr(const int32_t* p) {
+    // an explicit LDS pointer: a generic one would become a flat access, which also counts as a
+    // vector memory operation and makes waits for it wait for the prefetched loads too
+    typedef __attribute__((address_space(3))) const volatile int32_t lds_i32;
     if constexpr (N == 4) {
         typedef int32_t v4 __attribute__((ext_vector_type(4)));
-        const v4 v = *(const volatile v4*)p;
+        typedef __attribute__((address_space(3))) const volatile v4 lds_v4;
+        const v4 v = *(lds_v4*)(lds_i32*)p;
         return imin(imin(v[0], v[1]), imin(v[2], v[3]));
     } else if constexpr (N == 2) {
         typedef int32_t v2 __attribute__((ext_vector_type(2)));
-        const v2 v = *(const volatile v2*)p;
+        typedef __attribute__((address_space(3))) const volatile v2 lds_v2;
+        const v2 v = *(lds_v2*)(lds_i32*)p;
         return imin(v[0], v[1]);
     } else {
         return lds_get(p);
@@ -248,9 +253,10 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                 for (int v = 0; v < NV; ++v)
                     if (v % 2 == hx) lds_put(wr + v, W);
             } else if (hx < NV) {
-                // the band above's row: [W][QT] tagged words, lane-major per slab
+                // the band above's row: [W][NV][E][64] tagged words (word k of lane l of slab w at
+                // (w E + k) 64 + l, so a wavefront's access to word k is 512 contiguous bytes)
                 const unsigned long long* const hrow0 = d.hand + (size_t)(sc * 2 + ((super - 1) & 1)) * hrow;
-                const unsigned long long* const hin = hrow0 + lane * E;
+                const unsigned long long* const hin = hrow0 + lane;
                 int32_t cin = 0, taken = 0;
                 uint32_t spins = 0;
                 bool dead = false;
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         const int32_t pc = lane / NS, pi = lane % NS;
                         const bool probe = pc < n && hx + 2 * pi < NV;
                         const unsigned long long pw =
-                            probe ? tag_get(hrow0 + (size_t)(cin + pc) * QT + (size_t)((hx + 2 * pi) * 64 + 63) * E + E - 1)
+                            probe ? tag_get(hrow0 + (size_t)(cin + pc) * QT + (size_t)((hx + 2 * pi) * E + E - 1) * 64 + 63)
                                   : 0ull;
                         const bool pok = !probe || (uint32_t)(pw >> 32) == tag_in + (uint32_t)(cin + pc);
                         const unsigned long long pm = __ballot(pok);
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
 #pragma unroll
                                     for (int k = 0; k < E; ++k)
                                         v[c][i][k] = (c < ready && hx + 2 * i < NV)
-                                                         ? tag_get(hin + (size_t)(cin + c) * QT + (hx + 2 * i) * 64 * E + k)
+                                                         ? tag_get(hin + (size_t)(cin + c) * QT + ((hx + 2 * i) * E + k) * 64)
                                                          : 0ull;
                             bool run = true;
 #pragma unroll
@@ -385,7 +391,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             const bool to_ring = row + 1 < nact;
             const bool to_mem = !to_ring && gout;
             int32_t* const ring_out = rings + (size_t)(row + 1 < RW ? row + 1 : row) * R * QT + w * 64 * E + lane * E;
-            unsigned long long* const hout = d.hand + (size_t)(sc * 2 + (super & 1)) * hrow + (size_t)(w * 64 + lane) * E;
+            unsigned long long* const hout = d.hand + (size_t)(sc * 2 + (super & 1)) * hrow + (size_t)w * 64 * E + lane;
             int32_t* const wr_in = wr + row * NV + w;
             int32_t* const rd_in = rd + row * NV + w;
             int32_t* const wr_out = wr + (row + 1) * NV + w;
@@ -533,9 +539,11 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                     // the vertex minimum of the sums equals the minimum of the x results (their
                     // window includes the label itself, with no clip in joint mode)
                     int32_t g = cmin[0];
+                    if (joint) {
 #pragma unroll
-                    for (int kx = 1; kx < KX; ++kx) g = imin(g, cmin[kx]);
-                    g = line_min<16, 1>(g, lane);
+                        for (int kx = 1; kx < KX; ++kx) g = imin(g, cmin[kx]);
+                        g = line_min<16, 1>(g, lane);
+                    }
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx) {
                         int32_t e[KY + 2 * HB];
@@ -588,7 +596,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         for (int ky = 0; ky < KY; ++ky)
 #pragma unroll
                             for (int kx = 0; kx < KX; ++kx)
-                                tag_put(hout + (size_t)s * QT + ky * KX + kx, tg | (uint32_t)h2[ky][kx]);
+                                tag_put(hout + (size_t)s * QT + (ky * KX + kx) * 64, tg | (uint32_t)h2[ky][kx]);
                     }
                 }
                 if (!CHECK || s + 1 < W) read_input(s + 1);
