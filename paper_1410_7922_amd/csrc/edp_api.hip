@@ -430,6 +430,7 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
                 d.old_b_zero = (it == 0 && (q == 0 || q == 1)) ? 1 : 0;  // -y before P3
                 d.b_live = (q == 1 || q == 3) ? 1 : 0;  // T+y of P1 and T-y of P3 die inside their scan
                 d.pass_index = it * 4 + q;
+                d.marginal = (is_wide(c.tile) && q == 3 && it == c.iterations - 1) ? 1 : 0;
             }
             a.ticket = c.tickets + launch;
             const bool timed = ev && ev->events && 2 * launch + 1 < ev->n_events;
@@ -441,6 +442,8 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
                 return EDP_E_HIP;
         }
     }
+    if (is_wide(c.tile) && c.kind != KIND_WINDOW)
+        return launch_status(c.one, c.descs, c.descs ? c.ndesc : 0, c.error, s) == hipSuccess ? EDP_OK : EDP_E_HIP;
     AggArgs g{};
     g.one = c.one;
     g.descs = c.descs;

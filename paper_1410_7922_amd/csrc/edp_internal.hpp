@@ -92,6 +92,11 @@ struct InstDesc {
     int32_t first_eblock;         // first energy block of this instance
 };
 
+// Status word of every instance of a launch class after its scans (wide tiles, whose last scan
+// forms the labels itself): STATUS_TIMEOUT if a wait gave up, else 0.
+hipError_t launch_status(const InstDesc& one, const InstDesc* descs, int32_t ndesc, const uint32_t* error,
+                         hipStream_t s);
+
 // Locate the instance of a ticket or block: descs sorted by the key, ndesc >= 1;
 // by: 0 tickets, 1 marginal blocks, 2 energy blocks.
 __device__ __forceinline__ int32_t find_instance(const InstDesc* descs, int32_t ndesc, int32_t key,
@@ -128,6 +133,8 @@ struct PassDir {
     int32_t old_b_zero;      // the other y-direction array still holds its initial zeros
     int32_t b_live;          // the y-direction sum is read by later scans: store it everywhere
     int32_t pass_index;      // scans since the flags were cleared
+    int32_t marginal;        // wide tiles, last P4: form the marginal of eq. DP_2D_1 and its smallest
+                             // argmin at every vertex (all its terms are at hand) and store no sums
 };
 
 // One launch of the scan kernel: one scan, or two consecutive scans that sweep

@@ -94,6 +94,24 @@ int pass_mv_capacity(int tile, int kind, int ms, int rows, size_t lds_bytes) {
     return per_cu * cus;
 }
 
+// Status words after the scans of a launch class whose last scan formed the labels.
+__global__ __launch_bounds__(256) void status_kernel(const InstDesc one, const InstDesc* descs, int32_t ndesc,
+                                                     const uint32_t* error) {
+    const int32_t v = (error && *error != 0) ? STATUS_TIMEOUT : 0;
+    if (ndesc == 0) {
+        if (threadIdx.x == 0 && one.status) *one.status = v;
+        return;
+    }
+    for (int32_t i = threadIdx.x; i < ndesc; i += blockDim.x)
+        if (descs[i].status) *descs[i].status = v;
+}
+
+hipError_t launch_status(const InstDesc& one, const InstDesc* descs, int32_t ndesc, const uint32_t* error,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(status_kernel, dim3(1), dim3(256), 0, s, one, descs, ndesc, error);
+    return hipGetLastError();
+}
+
 hipError_t launch_edp_aggregate_mv(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s) {
     switch (tile) {
 #define EDP_CASE(id, kx, ky, nv)                                                                           \

@@ -356,10 +356,12 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             int32_t* const t_ma = ka ? d.t[0] : d.t[1];
             int32_t* const t_mb = kb == 3 ? d.t[2] : d.t[3];
             const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(d.cost, W * H * Q * CB);
-            const __amdgpu_buffer_rsrc_t rs_a = make_rsrc(t_a, tbytes);
+            // the last P4 forms the labels and leaves its sums unstored (nothing reads them later)
+            const bool marg = pd.marginal != 0;
+            const __amdgpu_buffer_rsrc_t rs_a = make_rsrc(t_a, marg ? 0 : tbytes);
             const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(t_ma, pd.old_a_zero ? 0 : tbytes);
             const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(t_mb, pd.old_b_zero ? 0 : tbytes);
-            const __amdgpu_buffer_rsrc_t rs_bo = make_rsrc(t_b, pd.b_live ? tbytes : 0);
+            const __amdgpu_buffer_rsrc_t rs_bo = make_rsrc(t_b, pd.b_live && !marg ? tbytes : 0);
             const bool joint = d.joint != 0;
             const int32_t clipd = d.clipd;
             const WinPen wp(d.lam, d.trunc, d.qx, d.qy, d.squared != 0);
@@ -384,6 +386,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             const int32_t ba = bt + dt;
             const int32_t bb = cell_off(yn * W + x0, QT * 4) + lofs;
             const int32_t nsteps = (W + PF - 1) / PF * PF;
+            int32_t* const lab_row = d.labels + (size_t)y * W + x0;   // labels of the row (last P4)
 
             // T_b of the scanline above through ring `row`; this scanline's T_b into ring row + 1 or,
             // for the band's last scanline, as tagged words for the band below
@@ -481,6 +484,28 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                 const int32_t par = s & 1;
                 int32_t* const u1 = xrow + (par * 2 + 0) * XS;
                 int32_t* const u2 = xrow + (par * 2 + 1) * XS;
+                if (marg) {
+                    // marginal of eq. DP_2D_1 at this vertex: C + T_-x(x + 1) + T_-y(y + 1) (this scan's
+                    // own sums) + T_+x(x - 1) + T_+y(y - 1) (the sums it reads), so A + both old sums;
+                    // this wavefront's smallest value and, among the labels holding it, the smallest label
+                    int32_t bv = 0x7FFFFFFF, bl = 0x7FFFFFFF;
+#pragma unroll
+                    for (int ky = 0; ky < KY; ++ky)
+#pragma unroll
+                        for (int kx = 0; kx < KX; ++kx) {
+                            const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + carry[ky][kx] + lb[ky * KX + kx];
+                            const int32_t v = A + rma[u][ky][kx] + rmb[u][ky][kx];
+                            const bool better = valid[ky][kx] && v < bv;   // labels rise with (ky, kx)
+                            bv = better ? v : bv;
+                            bl = better ? (vy0 + ky) * d.qx + vx0 + kx : bl;
+                        }
+                    const int32_t wv = rows_min4(line_min<16, 1>(bv, lane));
+                    const int32_t wl = rows_min4(line_min<16, 1>(bv == wv ? bl : 0x7FFFFFFF, lane));
+                    if (lane == 0) {
+                        u1[PLANE + NV * QXP + w] = wv;
+                        u2[PLANE + NV * QXP + w] = wl;
+                    }
+                }
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky) {
                     if (ky < HB || ky >= KY - HB) {
@@ -522,6 +547,16 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                     }
                 }
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (marg && w == 0) {
+                    int32_t fv = u1[PLANE + NV * QXP], fl = u2[PLANE + NV * QXP];
+#pragma unroll
+                    for (int v = 1; v < NV; ++v) {
+                        const int32_t ov = u1[PLANE + NV * QXP + v], ol = u2[PLANE + NV * QXP + v];
+                        fl = ov < fv ? ol : (ov == fv ? imin(fl, ol) : fl);
+                        fv = imin(fv, ov);
+                    }
+                    if (lane == 0 && live) lab_row[sx * s] = fl;
+                }
                 // ---- window along y: own rows plus HB rows above and below; clip at the column
                 // minimum (per-dimension truncation) or at the vertex minimum (joint truncation)
 #pragma unroll
