@@ -156,8 +156,9 @@ edp_status pick_wide_launch(const edp_problem* p, const edp_tuning* tu, int tile
     const int nv = wide_nv(tile);
     const int max_rows = MV_MAX_WAVES / nv;
     constexpr size_t kLds = 160 * 1024;
-    int rows = max_rows;
-    // built-in: the most scanlines whose exchange planes and rings of 4 slots fit the LDS
+    // built-in: 8 compute wavefronts per workgroup (two per SIMD: a third scanline per workgroup
+    // saves workgroup hand-offs but costs more in shared issue slots), as many as fit the LDS
+    int rows = std::min(max_rows, std::max(1, 8 / nv));
     while (rows > 1 && pass_mv_lds_bytes(tile, ms, rows, 4) > kLds) --rows;
     if (tu && tu->waves > 0) rows = tu->waves;
     if (rows > max_rows) return EDP_E_INVALID;

@@ -104,6 +104,18 @@ __device__ __forceinline__ int32_t lds_min_ctr(const int32_t* p) {
     }
 }
 
+// Minima over the four 16-lane rows of the wavefront of two values at once (every lane gets both):
+// one swap halves across 32 lanes with each value in one half, the rest as in rows_min4.
+__device__ __forceinline__ void rows_min4x2(int32_t& p, int32_t& q) {
+    const auto a = __builtin_amdgcn_permlane32_swap(p, q, false, false);   // [p0 p1 q0 q1], [p2 p3 q2 q3]
+    int32_t m = imin((int32_t)a[0], (int32_t)a[1]);                        // [p01' p13' q02' q13'] by row
+    const auto b = __builtin_amdgcn_permlane16_swap(m, m, false, false);   // [m0 m0 m2 m2], [m1 m1 m3 m3]
+    m = imin((int32_t)b[0], (int32_t)b[1]);                                // rows 0,1: min p; rows 2,3: min q
+    const auto c = __builtin_amdgcn_permlane32_swap(m, m, false, false);   // [m0 m1 m0 m1], [m2 m3 m2 m3]
+    p = (int32_t)c[0];
+    q = (int32_t)c[1];
+}
+
 // Minimum over the four 16-lane rows of the wavefront (every lane gets it).
 __device__ __forceinline__ int32_t rows_min4(int32_t v) {
     const auto a = __builtin_amdgcn_permlane32_swap(v, v, false, false);   // [r0 r1 r0 r1], [r2 r3 r2 r3]
@@ -116,9 +128,11 @@ __device__ __forceinline__ int32_t rows_min4(int32_t v) {
 // steps u = 1..NWK with penalties pen[u-1] (PEN_OFF disables a step), then the clip at the
 // line minimum + clipd when clip is set.  A candidate from another lane is taken by a min with a
 // DPP source (a lane whose source lies outside the row keeps its value).  Returns min h of the line.
+// clipx: the clip offset, or 2^30 for no clip (every value lies below line minimum + 2^30, and the
+// sum stays inside int32 since values lie below PADV).
 template <int K, int NWK>
-__device__ __forceinline__ int32_t xwin16(int32_t (&h)[K], const int32_t (&pen)[2], const int32_t clipd,
-                                          const bool clip, const int32_t lane) {
+__device__ __forceinline__ int32_t xwin16(int32_t (&h)[K], const int32_t (&pen)[2], const int32_t clipx,
+                                          const int32_t lane) {
     int32_t m = h[0];
 #pragma unroll
     for (int k = 1; k < K; ++k) m = imin(m, h[k]);
@@ -155,7 +169,7 @@ __device__ __forceinline__ int32_t xwin16(int32_t (&h)[K], const int32_t (&pen)[
         }
         o[k] = v;
     }
-    const int32_t cap = clip ? m + clipd : IDENT;
+    const int32_t cap = m + clipx;
 #pragma unroll
     for (int k = 0; k < K; ++k) h[k] = imin(o[k], cap);
     return m;
@@ -364,6 +378,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             const __amdgpu_buffer_rsrc_t rs_bo = make_rsrc(t_b, pd.b_live && !marg ? tbytes : 0);
             const bool joint = d.joint != 0;
             const int32_t clipd = d.clipd;
+            const int32_t clipx = joint ? 0x40000000 : clipd;   // x lines clip only per dimension
             const WinPen wp(d.lam, d.trunc, d.qx, d.qy, d.squared != 0);
             int32_t crun[KY];
             bool valid[KY][KX];
@@ -454,9 +469,12 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                 for (int k = 0; k < E; ++k) lb[k] = 0;
                 if (live) {
                     uint32_t spins = 0;
+                    // a waiting wavefront sleeps between polls, leaving its SIMD's issue slots to the
+                    // wavefronts of the other scanlines
 #pragma nounroll
-                    while (!dead && in_ready < s + 1) {
-                        if (give_up(spins)) break;
+                    while (in_ready < s + 1) {
+                        if (dead || give_up(spins)) break;
+                        __builtin_amdgcn_s_sleep(1);
                         read_input(s);
                     }
 #pragma unroll
@@ -477,8 +495,8 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                 // ---- window along x (lane rows), both sums
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky) {
-                    xwin16<KX, NWK>(h[ky], wp.px, clipd, !joint, lane);
-                    xwin16<KX, NWK>(h2[ky], wp.px, clipd, !joint, lane);
+                    xwin16<KX, NWK>(h[ky], wp.px, clipx, lane);
+                    xwin16<KX, NWK>(h2[ky], wp.px, clipx, lane);
                 }
                 // ---- exchange: label rows next to the lane rows' edges, column minima per wavefront
                 const int32_t par = s & 1;
@@ -527,23 +545,22 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         c1[kx] = imin(c1[kx], h[ky][kx]);
                         c2[kx] = imin(c2[kx], h2[ky][kx]);
                     }
-                    c1[kx] = rows_min4(c1[kx]);
-                    c2[kx] = rows_min4(c2[kx]);
+                    rows_min4x2(c1[kx], c2[kx]);
                 }
-                if (lr == 0) {
+                // every lane row holds the same minima: all write them (no branch)
 #pragma unroll
-                    for (int kx = 0; kx < KX; ++kx) {
-                        u1[PLANE + w * QXP + vx0 + kx] = c1[kx];
-                        u2[PLANE + w * QXP + vx0 + kx] = c2[kx];
-                    }
+                for (int kx = 0; kx < KX; ++kx) {
+                    u1[PLANE + w * QXP + vx0 + kx] = c1[kx];
+                    u2[PLANE + w * QXP + vx0 + kx] = c2[kx];
                 }
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 lds_put(xc_row + w, s + 1);
                 {
                     uint32_t spins = 0;
 #pragma nounroll
-                    while (!dead && lds_min_ctr<NV>(xc_row) < s + 1) {
-                        if (give_up(spins)) break;
+                    while (lds_min_ctr<NV>(xc_row) < s + 1) {
+                        if (dead || give_up(spins)) break;
+                        __builtin_amdgcn_s_sleep(1);
                     }
                 }
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -614,8 +631,9 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         if (taken < s + 1 - R) {
                             uint32_t spins = 0;
 #pragma nounroll
-                            while (!dead && (taken = lds_get(rd_out)) < s + 1 - R) {
-                                if (give_up(spins)) break;
+                            while ((taken = lds_get(rd_out)) < s + 1 - R) {
+                                if (dead || give_up(spins)) break;
+                                __builtin_amdgcn_s_sleep(1);
                             }
                         }
                         int32_t* dst = ring_out + (size_t)(s & (R - 1)) * QT;
