@@ -102,7 +102,7 @@ typedef struct {
  *   waves  compute wavefronts per EDP workgroup (1..6), handing rows over in
  *          LDS; every workgroup has two more wavefronts that move the rows
  *          between workgroups.  Wide tiles: scanlines per workgroup (at most
- *          12 / (its wavefronts per vertex)); rows go between workgroups as
+ *          8 / (its wavefronts per vertex)); rows go between workgroups as
  *          tagged words
  *   fuse   EDP scans per launch: 1, or 2 (P1 with P2, P3 with P4: the two
  *          scans of a pair sweep the rows in the same order, so the second

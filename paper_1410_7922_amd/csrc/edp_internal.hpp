@@ -41,7 +41,7 @@ constexpr int NUM_MV_TILES = 3;
 constexpr int NUM_ALL_TILES = NUM_TILES + NUM_MV_TILES;
 // A wide-vertex tile holds at most this many scanlines per workgroup times its wavefronts
 // per vertex: 12 wavefronts (768 lanes).
-constexpr int MV_MAX_WAVES = 12;
+constexpr int MV_MAX_WAVES = 8;
 // compute wavefronts per workgroup of the scan kernel; with its two helper wavefronts a
 // workgroup has at most 8, two per SIMD, so each may use half the register file
 constexpr int MAX_WAVES = 6;

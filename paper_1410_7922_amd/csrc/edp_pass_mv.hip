@@ -12,7 +12,7 @@ EDP_MV_TILE_LIST(EDP_MV_OF)
 
 // Prefetch depth in steps: the loads of a step are few, so several steps stay in flight.
 template <class M>
-constexpr int mv_pf() { return 2; }
+constexpr int mv_pf() { return M::E <= 4 ? 4 : 2; }
 
 template <class M, class CK, int MS>
 static hipError_t run_mv(const PassArgs& a, int grid, int rows, hipStream_t s) {

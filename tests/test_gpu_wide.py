@@ -49,6 +49,11 @@ CASES = [
 ]
 
 
+def max_rows(tile):
+    # at most 8 compute wavefronts per workgroup (py / 4 per scanline)
+    return 8 // (edp.tile_info(tile)[2] // 4)
+
+
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}q{c[2]}x{c[3]}m{c[6]}p{c[7]}j{c[11]}")
 def test_wide_tiles_against_oracle(case):
     W, H, qx, qy, lam, T, mode, prior, lo, hi, dt, j = case
@@ -57,7 +62,7 @@ def test_wide_tiles_against_oracle(case):
     tiles = edp.wide_tiles(qx, qy)
     assert tiles
     for tile in tiles:
-        for waves, fuse in ((0, 0), (1, 2), (2, 1), (3, 2)):
+        for waves, fuse in ((0, 0), (1, 2), (2, 1), (max_rows(tile), 2)):
             note(f"wide {p.name} prior {prior} j{j} tile {tile} rows {waves} fuse {fuse}")
             lab, e = gpu_edp(p, j, tile, waves, fuse, prior)
             assert np.array_equal(lab, ref["labels"]), (tile, waves, fuse)
