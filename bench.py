@@ -144,11 +144,15 @@ def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1, fuse=0
             "energy": int(energy.item()), "cost": cost}
 
 
-def scan_roofline(prob, r, traffic_key=None):
+SCAN_SOURCES = ["edp_pass_kernel.hpp", "edp_device.hpp", "edp_pass_mv.hpp"]
+
+
+def scan_roofline(prob, r, traffic_key=None, kernel="edp_pass_kernel"):
     """Roofline of the EDP scan kernel: algorithmic bytes of the scans of one solve (all eight old-sum
     reads counted) over the summed duration of the scan launches, timed by HIP events on the
     benchmark's stream; traffic: HBM bytes per launch from the recorded rocprofv3 counters, while
-    the kernel's source is unchanged since they were taken."""
+    the kernel's source is unchanged since they were taken.  With the wide tiles the last scan also
+    forms the marginal and the labels; the marginal's bytes are not counted here."""
     import numpy as np
     H, W, Q = prob.cost.shape
     pl = H * W * Q
@@ -157,9 +161,9 @@ def scan_roofline(prob, r, traffic_key=None):
     launch_ms = np.array(r["launch_ms"]).mean(axis=0)          # [scan launches]
     alg_bytes = float(sum(per_scan) * pl)
     achieved = alg_bytes / (launch_ms.sum() / 1e3) / 1e9
-    src_hash = kernel_source_hash(["edp_pass_kernel.hpp", "edp_device.hpp"])
+    src_hash = kernel_source_hash(SCAN_SOURCES)
     traffic = measured_traffic(traffic_key, src_hash) if traffic_key else None
-    return {"bound": "hbm", "kernel": f"edp_pass_kernel ({len(launch_ms)} scan launches per solve)",
+    return {"bound": "hbm", "kernel": f"{kernel} ({len(launch_ms)} scan launches per solve)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "alg_bytes_per_pl_scans": sum(per_scan),
             "alg_bytes_per_launch": alg_bytes / len(launch_ms), "mean_launch_ms": launch_ms.tolist(),
@@ -446,6 +450,38 @@ def window_study(torch, n, wins=(7, 11, 15, 21), rounds=3, big=40000):
             "instances": n, "rounds": rounds, "outside_cost": big, "proposals": out}
 
 
+def bench_paper_shapes(edp, torch, steps, warmup):
+    """The shapes of the paper's timed setups (Sec. 5.1, Table 2), with synthetic images in place of
+    the Middlebury pairs: setup 1, stereo 450x375 with 60 disparities and the truncated linear prior
+    g = 5 (linear RMS), and setup 3, motion 320x265 with 15x27 labels, g = 3.  The paper's sequential
+    CPU times per EDP iteration are quoted beside them for context (other hardware)."""
+    import synth
+    out = {}
+    for key, prob, paper_s in (
+            ("S1_stereo450x375q60_g5", synth.stereo_problem(seed=0, W=450, H=375, Q=60, lam=20, trunc=5), 2.3),
+            ("S3_motion320x265q15x27_g3", synth.motion_problem(seed=0, W=320, H=265, r=7, ry=13, lam=15, trunc=3),
+             10.8)):
+        r = bench_edp(edp, torch, prob, steps, warmup, -1, 0)
+        H, W, Q = prob.cost.shape
+        out[key] = {"ms_per_step": r["ms_per_step"], "pixel_labels_per_s": W * H * Q / (r["ms_per_step"] / 1e3),
+                    "energy": r["energy"], "labels": [prob.qx, prob.qy],
+                    "paper_lrms_s_per_iteration_core_duo_3_16ghz": paper_s}
+        del r
+    return out
+
+
+def bench_iterations(edp, torch, prob, iters=(1, 2, 4, 8, 16)):
+    """Energy and time of the solve for several EDP iteration counts j (the paper's energy-versus-
+    iteration experiments, Sec. 5.1)."""
+    import numpy as np
+    out = []
+    for j in iters:
+        r = bench_edp(edp, torch, prob, 2, 1, -1, 0, iterations=j)
+        out.append({"iterations": j, "energy": r["energy"], "ms_per_solve": r["ms_per_step"]})
+        del r
+    return out
+
+
 def cpu_baseline(prob, rows=None, budget_s=10.0):
     """The C oracle (one thread, general RMS minimum search) timed on the first `rows` rows of the
     workload's cost volume (all rows if None), repeated until budget_s has passed."""
@@ -535,7 +571,7 @@ def main():
         f"{args.steps} timed steps")
     r = bench_edp(edp, torch, prob, args.steps, args.warmup, args.tile, args.chunk, fuse=args.fuse)
     ms = r["ms_per_step"]
-    roof = scan_roofline(prob, r, "edp_pass_motion640x480q961")
+    roof = scan_roofline(prob, r, "edp_pass_motion640x480q961", kernel="edp_pass_mv_kernel")
     log(f"step {ms:.3f} ms, scan launches {[round(x, 4) for x in roof['mean_launch_ms']]} ms")
     golden = os.path.join(ROOT, "tests", "golden", "edp_motion640x480_q961.json")
     with open(golden) as f:
@@ -599,6 +635,10 @@ def main():
         extra["dsi"] = bench_dsi(edp, torch, max(3, args.steps // 4), 1)
         log("min-marginal scanline DP on the same sweep")
         extra["dp_marginals"] = bench_dp_marginals(edp, torch, max(3, args.steps // 4), 1)
+        log("the paper's setup shapes (stereo 450x375x60 g=5, motion 320x265 with 15x27 labels g=3)")
+        extra["paper_shapes"] = bench_paper_shapes(edp, torch, max(3, args.steps // 4), 1)
+        log("energy against the number of EDP iterations (motion 640x480, 961 labels)")
+        extra["energy_vs_iterations"] = bench_iterations(edp, torch, prob)
     if not args.no_batch:
         log("batch of 64 uneven instances (hipGraph replay)")
         extra["batch64"] = bench_batch(edp, torch, max(3, args.steps // 4), 1)

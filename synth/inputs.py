@@ -196,23 +196,24 @@ def stereo_problem(seed: int = 0, W: int = 384, H: int = 288, Q: int = 32, lam: 
 
 
 def motion_frames(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, segments: int = 8,
-                  sigma: float = 4.0):
+                  sigma: float = 4.0, ry: int | None = None):
     """Two 8-bit frames with affine motion over Voronoi segments, and the planted flow.
 
     Returns (i0, i1, fu, fv): uint8 [H][W] frames where I1(x + fu, y + fv) shows I0(x, y),
-    and the integer flow components in [-r, r].
+    and the integer flow components in [-r, r] (fu) and [-ry, ry] (fv, ry = r by default).
     """
+    ry = r if ry is None else ry
     rng = np.random.default_rng(seed)
     img0 = textured_image(rng, W, H)
     seg, sx, sy = voronoi_segments(rng, W, H, segments)
     u0 = rng.uniform(-r, r, segments)
-    v0 = rng.uniform(-r, r, segments)
+    v0 = rng.uniform(-ry, ry, segments)
     ux, uy = (rng.uniform(-1, 1, (2, segments)) * (r / 2.0) / np.array([[W], [H]]))
-    vx, vy = (rng.uniform(-1, 1, (2, segments)) * (r / 2.0) / np.array([[W], [H]]))
+    vx, vy = (rng.uniform(-1, 1, (2, segments)) * (ry / 2.0) / np.array([[W], [H]]))
     depth = rng.permutation(segments)
     yy, xx = np.mgrid[0:H, 0:W]
     fu = np.clip(np.rint(u0[seg] + ux[seg] * (xx - sx[seg]) + uy[seg] * (yy - sy[seg])), -r, r)
-    fv = np.clip(np.rint(v0[seg] + vx[seg] * (xx - sx[seg]) + vy[seg] * (yy - sy[seg])), -r, r)
+    fv = np.clip(np.rint(v0[seg] + vx[seg] * (xx - sx[seg]) + vy[seg] * (yy - sy[seg])), -ry, ry)
     fu = fu.astype(np.int64)
     fv = fv.astype(np.int64)
     img1 = _forward_splat(img0, xx + fu, yy + fv, depth[seg], rng)
@@ -221,38 +222,42 @@ def motion_frames(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, segment
     return i0, i1, fu, fv
 
 
-def motion_cost(i0: np.ndarray, i1: np.ndarray, r: int, cmax: int) -> np.ndarray:
-    """Truncated squared difference cost [H][W][(2r+1)^2] int64: label q = (dy + r)(2r + 1) + (dx + r)
-    compares I0(x, y) with I1(x + dx, y + dy); a displaced position outside the frame costs cmax."""
+def motion_cost(i0: np.ndarray, i1: np.ndarray, r: int, cmax: int, ry: int | None = None) -> np.ndarray:
+    """Truncated squared difference cost [H][W][(2r+1)(2ry+1)] int64 (ry = r by default): label
+    q = (dy + ry)(2r + 1) + (dx + r) compares I0(x, y) with I1(x + dx, y + dy); a displaced position
+    outside the frame costs cmax."""
+    ry = r if ry is None else ry
     H, W = i0.shape
     n = 2 * r + 1
+    m = max(r, ry)
     a = i0.astype(np.float64)
-    pad = np.full((H + 2 * r, W + 2 * r), np.nan)
-    pad[r:r + H, r:r + W] = i1
-    cost = np.empty((n * n, H, W), np.int64)
-    for dy in range(-r, r + 1):
+    pad = np.full((H + 2 * m, W + 2 * m), np.nan)
+    pad[m:m + H, m:m + W] = i1
+    cost = np.empty((n * (2 * ry + 1), H, W), np.int64)
+    for dy in range(-ry, ry + 1):
         for dx in range(-r, r + 1):
-            sh = pad[r + dy:r + dy + H, r + dx:r + dx + W]
+            sh = pad[m + dy:m + dy + H, m + dx:m + dx + W]
             d2 = (a - sh) ** 2
             cq = np.where(np.isnan(d2), cmax, np.minimum(np.nan_to_num(d2, nan=0.0), cmax))
-            cost[(dy + r) * n + (dx + r)] = cq.astype(np.int64)
+            cost[(dy + ry) * n + (dx + r)] = cq.astype(np.int64)
     return np.ascontiguousarray(np.moveaxis(cost, 0, -1))
 
 
 def motion_problem(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, lam: int = 15,
                    trunc: int = 3, cmax: int = 2500, segments: int = 8, sigma: float = 4.0,
-                   mode: int = TRUNC_PER_DIM, dtype=np.int32) -> Problem:
+                   mode: int = TRUNC_PER_DIM, dtype=np.int32, ry: int | None = None) -> Problem:
     """Two frames with affine motion over Voronoi segments, truncated squared difference cost.
 
-    Labels: q = (dy + r) * (2r + 1) + (dx + r), the cost of q at pixel (x, y)
+    Labels: q = (dy + ry) * (2r + 1) + (dx + r) (ry = r by default), the cost of q at pixel (x, y)
     compares I0(x, y) with I1(x + dx, y + dy).
     """
+    ry_ = r if ry is None else ry
     n = 2 * r + 1
-    i0, i1, fu, fv = motion_frames(seed, W, H, r, segments, sigma)
-    cost = np.ascontiguousarray(motion_cost(i0, i1, r, cmax).astype(dtype))
-    gt = (fv + r) * n + (fu + r)
-    return Problem(cost, n, n, lam, trunc, mode, name=f"motion{W}x{H}r{r}s{seed}",
-                   meta={"gt": gt, "frames": (i0, i1)})
+    i0, i1, fu, fv = motion_frames(seed, W, H, r, segments, sigma, ry=ry_)
+    cost = np.ascontiguousarray(motion_cost(i0, i1, r, cmax, ry=ry_).astype(dtype))
+    gt = (fv + ry_) * n + (fu + r)
+    name = f"motion{W}x{H}r{r}s{seed}" if ry_ == r else f"motion{W}x{H}r{r}x{ry_}s{seed}"
+    return Problem(cost, n, 2 * ry_ + 1, lam, trunc, mode, name=name, meta={"gt": gt, "frames": (i0, i1)})
 
 
 def random_problem(seed: int, W: int, H: int, qx: int, qy: int = 1, lam: int = 7, trunc: int = 2,
