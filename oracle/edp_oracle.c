@@ -5,6 +5,8 @@
  * baseline of the benchmark load this library.  It shares no code with the
  * GPU library and is written from the paper's definitions:
  *
+ *   labels   flat q = (vz * qy + vy) * qx + vx over R = 1, 2 or 3 label
+ *            dimensions (qz = 1 below three; Sec. 2 defines the search for any R).
  *   V(u)     truncated prior, Sec. 2 eq. Smooth_value_t with f(|a|) = |a|
  *            (prior 0, truncated linear) or f(|a|) = a^2 (prior 1, truncated
  *            squared, l_1 = 2 of Sec. 5.1); mode 0 truncates each label
@@ -18,6 +20,7 @@
  *                      window minimum over |u_r| < g of eq. M_decmp1 (with the
  *                      penalty lambda f(|u_r|) inside the minimum), then the
  *                      clip of eq. M_decmp (per line in mode 0).
+ *            Searches 1 and 2 take the dimensions in the order x, y, z.
  *   DP       S(0)=C(0), S(x+1)=C(x+1)+M(S(x))  Sec. 2 eq. base, Sec. 4.1
  *   EDP      Sec. 4.2 eq. DP_2D_base with C added, S/2 as floor division,
  *            scans P1..P4 in place, eq. DP_2D_1 marginal, eq. DP_2D_2 argmin.
@@ -37,8 +40,13 @@
 #define OR_E_NOMEM -3
 
 typedef struct {
-    int qx, qy, q, lam, trunc, mode, prior;
+    int qx, qy, qz, q, lam, trunc, mode, prior;
 } prior_t;
+
+static prior_t make_prior(int qx, int qy, int qz, int lam, int trunc, int mode, int prior) {
+    prior_t p = {qx, qy, qz, qx * qy * qz, lam, trunc, mode, prior};
+    return p;
+}
 
 static int64_t iabs64(int64_t a) { return a < 0 ? -a : a; }
 static int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
@@ -46,12 +54,29 @@ static int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 /* f of eq. Smooth_value_t */
 static int64_t prior_f(const prior_t *p, int64_t a) { return p->prior == 1 ? a * a : iabs64(a); }
 
+/* coordinate r (0 x, 1 y, 2 z) of flat label v */
+static int coord(const prior_t *p, int v, int r) {
+    if (r == 0) return v % p->qx;
+    if (r == 1) return (v / p->qx) % p->qy;
+    return v / (p->qx * p->qy);
+}
+
 static int64_t prior_v(const prior_t *p, int v, int w) {
-    int64_t fx = prior_f(p, (int64_t)(v % p->qx) - (w % p->qx));
-    int64_t fy = prior_f(p, (int64_t)(v / p->qx) - (w / p->qx));
-    int64_t fg = prior_f(p, p->trunc);
-    if (p->mode == 0) return (int64_t)p->lam * (imin64(fx, fg) + imin64(fy, fg));
-    return (int64_t)p->lam * imin64(fx + fy, fg);
+    int64_t fg = prior_f(p, p->trunc), sum = 0, trunc_each = 0;
+    for (int r = 0; r < 3; ++r) {
+        int64_t f = prior_f(p, (int64_t)coord(p, v, r) - coord(p, w, r));
+        sum += f;
+        trunc_each += imin64(f, fg);
+    }
+    if (p->mode == 0) return (int64_t)p->lam * trunc_each;
+    return (int64_t)p->lam * imin64(sum, fg);
+}
+
+/* Lines of the label grid along dimension r: length n, label stride st; a line starts
+ * at every label whose coordinate r is 0. */
+static void line_shape(const prior_t *p, int r, int *n, int *st) {
+    *n = r == 0 ? p->qx : r == 1 ? p->qy : p->qz;
+    *st = r == 0 ? 1 : r == 1 ? p->qx : p->qx * p->qy;
 }
 
 /* M by straightforward search; arg (nullable) receives the smallest minimising v'. */
@@ -92,23 +117,18 @@ static void msearch_lrms(const prior_t *p, const int64_t *h, int64_t *out, int64
     int64_t lam = p->lam, clipd = (int64_t)p->lam * p->trunc;
     int64_t gmin = h[0];
     for (int v = 0; v < p->q; ++v) { out[v] = h[v]; if (h[v] < gmin) gmin = h[v]; }
-    for (int vy = 0; vy < p->qy; ++vy) {           /* dimension x: lines of fixed vy */
-        int64_t *line = out + (size_t)vy * p->qx;
-        int64_t lmin = line[0];
-        for (int vx = 1; vx < p->qx; ++vx) lmin = imin64(lmin, line[vx]);
-        lrms_line(line, p->qx, 1, lam, plus, minus);
-        if (p->mode == 0)
-            for (int vx = 0; vx < p->qx; ++vx) line[vx] = imin64(line[vx], lmin + clipd);
-    }
-    if (p->qy > 1) {
-        for (int vx = 0; vx < p->qx; ++vx) {       /* dimension y: lines of fixed vx */
-            int64_t *line = out + vx;
+    for (int r = 0; r < 3; ++r) {                  /* dimensions x, y, z in turn */
+        int n, st;
+        line_shape(p, r, &n, &st);
+        if (r > 0 && n == 1) continue;
+        for (int v0 = 0; v0 < p->q; ++v0) {
+            if (coord(p, v0, r) != 0) continue;
+            int64_t *line = out + v0;
             int64_t lmin = line[0];
-            for (int vy = 1; vy < p->qy; ++vy) lmin = imin64(lmin, line[(size_t)vy * p->qx]);
-            lrms_line(line, p->qy, p->qx, lam, plus, minus);
+            for (int i = 1; i < n; ++i) lmin = imin64(lmin, line[(size_t)i * st]);
+            lrms_line(line, n, st, lam, plus, minus);
             if (p->mode == 0)
-                for (int vy = 0; vy < p->qy; ++vy)
-                    line[(size_t)vy * p->qx] = imin64(line[(size_t)vy * p->qx], lmin + clipd);
+                for (int i = 0; i < n; ++i) line[(size_t)i * st] = imin64(line[(size_t)i * st], lmin + clipd);
         }
     }
     if (p->mode == 1)
@@ -134,21 +154,18 @@ static void msearch_grms(const prior_t *p, const int64_t *h, int64_t *out, int64
     int64_t clipd = (int64_t)p->lam * prior_f(p, p->trunc);
     int64_t gmin = h[0];
     for (int v = 0; v < p->q; ++v) { out[v] = h[v]; if (h[v] < gmin) gmin = h[v]; }
-    for (int vy = 0; vy < p->qy; ++vy) {           /* dimension x: lines of fixed vy */
-        int64_t *line = out + (size_t)vy * p->qx;
-        int64_t lmin = line[0];
-        for (int vx = 1; vx < p->qx; ++vx) lmin = imin64(lmin, line[vx]);
-        grms_line(p, line, p->qx, 1, tmp);
-        for (int vx = 0; vx < p->qx; ++vx) line[vx] = p->mode == 0 ? imin64(tmp[vx], lmin + clipd) : tmp[vx];
-    }
-    if (p->qy > 1) {
-        for (int vx = 0; vx < p->qx; ++vx) {       /* dimension y: lines of fixed vx */
-            int64_t *line = out + vx;
+    for (int r = 0; r < 3; ++r) {                  /* dimensions x, y, z in turn */
+        int n, st;
+        line_shape(p, r, &n, &st);
+        if (r > 0 && n == 1) continue;
+        for (int v0 = 0; v0 < p->q; ++v0) {
+            if (coord(p, v0, r) != 0) continue;
+            int64_t *line = out + v0;
             int64_t lmin = line[0];
-            for (int vy = 1; vy < p->qy; ++vy) lmin = imin64(lmin, line[(size_t)vy * p->qx]);
-            grms_line(p, line, p->qy, p->qx, tmp);
-            for (int vy = 0; vy < p->qy; ++vy)
-                line[(size_t)vy * p->qx] = p->mode == 0 ? imin64(tmp[vy], lmin + clipd) : tmp[vy];
+            for (int i = 1; i < n; ++i) lmin = imin64(lmin, line[(size_t)i * st]);
+            grms_line(p, line, n, st, tmp);
+            for (int i = 0; i < n; ++i)
+                line[(size_t)i * st] = p->mode == 0 ? imin64(tmp[i], lmin + clipd) : tmp[i];
         }
     }
     if (p->mode == 1)
@@ -161,8 +178,10 @@ static void msearch(const prior_t *p, int search, const int64_t *h, int64_t *out
     else msearch_sfms(p, h, out, NULL);
 }
 
-static int check_args(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int search) {
-    if (W < 1 || H < 1 || qx < 1 || qy < 1 || qx > 4096 || qy > 4096 || (int64_t)qx * qy > 4096) return 0;
+static int check_args(int W, int H, int qx, int qy, int qz, int lam, int trunc, int mode, int prior, int search) {
+    if (W < 1 || H < 1 || qx < 1 || qy < 1 || qz < 1 || qx > 4096 || qy > 4096 || qz > 4096 ||
+        (int64_t)qx * qy * qz > 4096)
+        return 0;
     if (lam < 0 || trunc < 1 || trunc > 4096 || (mode != 0 && mode != 1)) return 0;
     if (prior != 0 && prior != 1) return 0;
     if (search < 0 || search > 2 || (search == 1 && prior != 0)) return 0;
@@ -170,9 +189,9 @@ static int check_args(int W, int H, int qx, int qy, int lam, int trunc, int mode
 }
 
 /* Energy of eq. GE_objective_function; grid4 = 0: rows only, 1: 4-connected. */
-int64_t oracle_energy(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int grid4,
+int64_t oracle_energy(int W, int H, int qx, int qy, int qz, int lam, int trunc, int mode, int prior, int grid4,
                       const int32_t *cost, const int32_t *labels) {
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
+    prior_t p = make_prior(qx, qy, qz, lam, trunc, mode, prior);
     int64_t e = 0;
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
@@ -188,10 +207,10 @@ int64_t oracle_energy(int W, int H, int qx, int qy, int lam, int trunc, int mode
  * search 1 (LRMS) or 2 (GRMS): the values, and at backtracking the choice index
  * at the chosen label is found by direct search over the stored S(x-1) (the
  * same argmin). */
-int oracle_dp_scanline(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int search,
+int oracle_dp_scanline(int W, int H, int qx, int qy, int qz, int lam, int trunc, int mode, int prior, int search,
                        const int32_t *cost, int32_t *labels, int64_t *row_energy, int64_t *total) {
-    if (!check_args(W, H, qx, qy, lam, trunc, mode, prior, search)) return OR_E_ARGS;
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
+    if (!check_args(W, H, qx, qy, qz, lam, trunc, mode, prior, search)) return OR_E_ARGS;
+    prior_t p = make_prior(qx, qy, qz, lam, trunc, mode, prior);
     int Q = p.q;
     int64_t *S = malloc(sizeof(int64_t) * (size_t)W * Q);
     int64_t *m = malloc(sizeof(int64_t) * Q);
@@ -258,16 +277,16 @@ static int in_box(const int32_t *centers, int win, int W, int qx, int x, int y, 
     if (!centers) return 1;
     const int32_t *c = centers + ((size_t)y * W + x) * 2;
     int r = win / 2;
-    int vx = v % qx, vy = v / qx;
+    int vx = v % qx, vy = v / qx;            /* windows are defined on two-dimensional label spaces */
     return vx >= c[0] - r && vx <= c[0] + r && vy >= c[1] - r && vy <= c[1] + r;
 }
 
-static int edp_core(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int iterations,
-                    int search, const int32_t *cost, const int32_t *centers, int win, int32_t *labels,
-                    int64_t *energy_out, int64_t *max_abs_out, int64_t *marginal_out) {
-    if (!check_args(W, H, qx, qy, lam, trunc, mode, prior, search) || iterations < 0) return OR_E_ARGS;
-    if (centers && (win < 1 || win % 2 == 0)) return OR_E_ARGS;
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
+static int edp_core(int W, int H, int qx, int qy, int qz, int lam, int trunc, int mode, int prior,
+                    int iterations, int search, const int32_t *cost, const int32_t *centers, int win,
+                    int32_t *labels, int64_t *energy_out, int64_t *max_abs_out, int64_t *marginal_out) {
+    if (!check_args(W, H, qx, qy, qz, lam, trunc, mode, prior, search) || iterations < 0) return OR_E_ARGS;
+    if (centers && (win < 1 || win % 2 == 0 || qz != 1)) return OR_E_ARGS;
+    prior_t p = make_prior(qx, qy, qz, lam, trunc, mode, prior);
     int Q = p.q;
     size_t cells = (size_t)W * H;
     int64_t *S = calloc((size_t)4 * cells * Q, sizeof(int64_t));
@@ -347,16 +366,16 @@ static int edp_core(int W, int H, int qx, int qy, int lam, int trunc, int mode, 
             if (marginal_out)
                 memcpy(marginal_out + ((size_t)y * W + x) * Q, acc, sizeof(int64_t) * Q);
         }
-    *energy_out = oracle_energy(W, H, qx, qy, lam, trunc, mode, prior, 1, cost, labels);
+    *energy_out = oracle_energy(W, H, qx, qy, qz, lam, trunc, mode, prior, 1, cost, labels);
     *max_abs_out = maxabs;
     free(S); free(h); free(m); free(acc); free(scratch); free(nw);
     return status;
 }
 
-int oracle_edp(int W, int H, int qx, int qy, int lam, int trunc, int mode, int prior, int iterations,
+int oracle_edp(int W, int H, int qx, int qy, int qz, int lam, int trunc, int mode, int prior, int iterations,
                int search, const int32_t *cost, int32_t *labels, int64_t *energy_out,
                int64_t *max_abs_out, int64_t *marginal_out) {
-    return edp_core(W, H, qx, qy, lam, trunc, mode, prior, iterations, search, cost, NULL, 1, labels,
+    return edp_core(W, H, qx, qy, qz, lam, trunc, mode, prior, iterations, search, cost, NULL, 1, labels,
                     energy_out, max_abs_out, marginal_out);
 }
 
@@ -365,15 +384,15 @@ int oracle_edp_window(int W, int H, int qx, int qy, int lam, int trunc, int mode
                       int search, const int32_t *cost, const int32_t *centers, int win,
                       int32_t *labels, int64_t *energy_out, int64_t *max_abs_out) {
     if (!centers) return OR_E_ARGS;
-    return edp_core(W, H, qx, qy, lam, trunc, mode, prior, iterations, search, cost, centers, win, labels,
+    return edp_core(W, H, qx, qy, 1, lam, trunc, mode, prior, iterations, search, cost, centers, win, labels,
                     energy_out, max_abs_out, NULL);
 }
 
 /* M on a batch of n vectors h[n][Q] (search 0: SFMS with arg (nullable); 1: LRMS; 2: GRMS). */
-int oracle_min_search(int qx, int qy, int lam, int trunc, int mode, int prior, int search, int n,
+int oracle_min_search(int qx, int qy, int qz, int lam, int trunc, int mode, int prior, int search, int n,
                       const int64_t *h, int64_t *out, int32_t *arg) {
-    if (!check_args(1, 1, qx, qy, lam, trunc, mode, prior, search) || n < 0) return OR_E_ARGS;
-    prior_t p = {qx, qy, qx * qy, lam, trunc, mode, prior};
+    if (!check_args(1, 1, qx, qy, qz, lam, trunc, mode, prior, search) || n < 0) return OR_E_ARGS;
+    prior_t p = make_prior(qx, qy, qz, lam, trunc, mode, prior);
     int64_t *scratch = malloc(sizeof(int64_t) * 8192);
     if (!scratch) return OR_E_NOMEM;
     for (int i = 0; i < n; ++i) {

@@ -3,7 +3,9 @@
 Notation follows the paper (Mozerov, arXiv 1410.7922):
 
 * ``C[y][x][q]``  data cost (disparity space image), Sec. 2;
-  flat label ``q = vy * qx + vx``, 0-based (the paper counts from 1).
+  flat label ``q = (vz * qy + vy) * qx + vx``, 0-based (the paper counts from 1);
+  the label space has R = 1, 2 or 3 dimensions (``qz`` = 1 unless R = 3: the
+  paper defines the search for any R, Sec. 2 and Sec. 3 eq. M_decmp).
 * ``V(u)``        truncated prior, Sec. 2 eq. Smooth_value_t with f(|a|) = |a|
   (``prior`` 0, truncated linear) or f(|a|) = a^2 (``prior`` 1, truncated
   squared, the paper's l_1 = 2); ``mode`` 1 truncates the summed distance over
@@ -30,7 +32,11 @@ design notes of the repository):
 * eq. M_decmp1 (one operator of the general RMS) adds lambda f(|u_r|) inside
   the window minimum, not lambda f(g): with the constant the operator would be
   a plain window minimum and eq. derivation2, from which it is derived, would
-  not hold.
+  not hold;
+* with three label dimensions the recursive searches apply their operators in
+  the order x, y, z (eq. M_decmp nests them for any R; every order gives the
+  same values), each followed by its per-line clip under per-dimension
+  truncation.
 
 Every floating point question is absent: all arithmetic is on Python / int64
 integers, and every EDP sum is checked to fit in int32 (the GPU's type).
@@ -61,24 +67,23 @@ def prior_f(a, prior: int = PRIOR_LINEAR):
     raise ValueError(f"unknown prior {prior}")
 
 
-def prior_value(ux: int, uy: int, lam: int, trunc: int, mode: int, prior: int = PRIOR_LINEAR) -> int:
-    """V(u) for a label difference u = (ux, uy): Sec. 2 eq. Smooth_value_t."""
-    fx, fy, fg = prior_f(int(ux), prior), prior_f(int(uy), prior), prior_f(int(trunc), prior)
-    if mode == TRUNC_PER_DIM:
-        return lam * (min(fx, fg) + min(fy, fg))
-    return lam * min(fx + fy, fg)
+def label_coords(q, qx: int, qy: int):
+    """(vx, vy, vz) of flat labels q = (vz * qy + vy) * qx + vx."""
+    return q % qx, (q // qx) % qy, q // (qx * qy)
 
 
-def prior_matrix(qx: int, qy: int, lam: int, trunc: int, mode: int, prior: int = PRIOR_LINEAR) -> np.ndarray:
+def prior_matrix(qx: int, qy: int, lam: int, trunc: int, mode: int, prior: int = PRIOR_LINEAR,
+                 qz: int = 1) -> np.ndarray:
     """Vm[v, v'] = V(v - v') over flat labels, int64 [Q, Q]."""
-    q = np.arange(qx * qy, dtype=np.int64)
-    vx, vy = q % qx, q // qx
+    q = np.arange(qx * qy * qz, dtype=np.int64)
+    vx, vy, vz = label_coords(q, qx, qy)
     fx = prior_f(vx[:, None] - vx[None, :], prior)
     fy = prior_f(vy[:, None] - vy[None, :], prior)
+    fz = prior_f(vz[:, None] - vz[None, :], prior)
     fg = prior_f(int(trunc), prior)
     if mode == TRUNC_PER_DIM:
-        return (lam * (np.minimum(fx, fg) + np.minimum(fy, fg))).astype(np.int64)
-    return (lam * np.minimum(fx + fy, fg)).astype(np.int64)
+        return (lam * (np.minimum(fx, fg) + np.minimum(fy, fg) + np.minimum(fz, fg))).astype(np.int64)
+    return (lam * np.minimum(fx + fy + fz, fg)).astype(np.int64)
 
 
 class OpCounter:
@@ -94,14 +99,14 @@ class OpCounter:
 
 
 def min_search_sfms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                    counter: OpCounter | None = None, prior: int = PRIOR_LINEAR):
+                    counter: OpCounter | None = None, prior: int = PRIOR_LINEAR, qz: int = 1):
     """Straightforward minimum search (SFMS, Sec. 3 end): the definition eq. M_strf.
 
     ``h`` has shape [..., Q].  Returns (M(h), argM(h)); argM is the smallest
     flat index v' attaining the minimum.
     """
     h = np.asarray(h, dtype=np.int64)
-    vm = prior_matrix(qx, qy, lam, trunc, mode, prior)
+    vm = prior_matrix(qx, qy, lam, trunc, mode, prior, qz)
     tot = h[..., None, :] + vm                    # [..., v, v']
     arg = np.argmin(tot, axis=-1)                 # first minimum = smallest v'
     val = np.take_along_axis(tot, arg[..., None], axis=-1)[..., 0]
@@ -129,46 +134,61 @@ def _linear_rms_line(line: list, lam: int, counter: OpCounter | None):
     return out
 
 
+def _lines(g, dims, r):
+    """Index lists of the lines of the label grid g along dimension r (0 x, 1 y, 2 z)."""
+    qx, qy, qz = dims
+    if r == 0:
+        return [[(vz, vy, vx) for vx in range(qx)] for vz in range(qz) for vy in range(qy)]
+    if r == 1:
+        return [[(vz, vy, vx) for vy in range(qy)] for vz in range(qz) for vx in range(qx)]
+    return [[(vz, vy, vx) for vz in range(qz)] for vy in range(qy) for vx in range(qx)]
+
+
+def _separable_search(h, qx, qy, qz, lam, trunc, mode, clipd, line_op, counter):
+    """Eq. M_decmp: the one-dimensional operator line_op along every label dimension r = 1..R in
+    turn; per-dimension truncation clips each line at its own minimum + clipd after its operator
+    (eq. derivation1 applied to that dimension), joint truncation clips once at min h + clipd."""
+    h = np.asarray(h, dtype=np.int64)
+    lead = h.shape[:-1]
+    dims = (qx, qy, qz)
+    flat = h.reshape(-1, qz, qy, qx)
+    out = np.empty_like(flat)
+    for n in range(flat.shape[0]):
+        g = {(vz, vy, vx): int(flat[n, vz, vy, vx]) for vz in range(qz) for vy in range(qy) for vx in range(qx)}
+        for r in range(3):
+            if dims[r] == 1 and r > 0:
+                continue                      # a dimension of one label has no operator
+            for idx in _lines(g, dims, r):
+                line = [g[i] for i in idx]
+                res = line_op(line)
+                if mode == TRUNC_PER_DIM:
+                    clip = min(line) + clipd
+                    res = [min(a, clip) for a in res]
+                for i, a in zip(idx, res):
+                    g[i] = a
+        if mode == TRUNC_JOINT:
+            clip = int(flat[n].min()) + clipd
+            g = {i: min(a, clip) for i, a in g.items()}
+        for (vz, vy, vx), a in g.items():
+            out[n, vz, vy, vx] = a
+        if counter is not None:
+            counter.outputs += qx * qy * qz
+    return out.reshape(*lead, qx * qy * qz)
+
+
 def min_search_lrms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                    counter: OpCounter | None = None) -> np.ndarray:
+                    counter: OpCounter | None = None, qz: int = 1) -> np.ndarray:
     """Linear RMS (LRMS, Sec. 3.2): per-dimension L_r passes and the clip of eq. L_dec7.
 
     ``mode`` 1 (joint truncation, the paper's prior): M = L_y(L_x(h)) ^ (min h + lam*T),
     eq. L_dec7.  ``mode`` 0 (per-dimension truncation): each dimension's prior is a
     one-dimensional truncated linear prior, so the decomposition of eq. derivation2 applies
     per dimension with its own clip (eq. derivation1 applied to that dimension):
-    M = clip_y(L_y(clip_x(L_x(h)))).  Only the values are returned.
+    M = clip_y(L_y(clip_x(L_x(h)))).  With a third label dimension (``qz`` > 1) L_z follows
+    in the same way.  Only the values are returned.
     """
-    h = np.asarray(h, dtype=np.int64)
-    lead = h.shape[:-1]
-    flat = h.reshape(-1, qy, qx)
-    out = np.empty_like(flat)
-    for n in range(flat.shape[0]):
-        g = [[int(flat[n, vy, vx]) for vx in range(qx)] for vy in range(qy)]
-        # dimension x (r = 1): lines of fixed vy
-        for vy in range(qy):
-            line = _linear_rms_line(g[vy], lam, counter)
-            if mode == TRUNC_PER_DIM:
-                clip = min(g[vy]) + lam * trunc
-                line = [min(a, clip) for a in line]
-            g[vy] = line
-        # dimension y (r = 2): lines of fixed vx
-        if qy > 1:
-            for vx in range(qx):
-                col = [g[vy][vx] for vy in range(qy)]
-                line = _linear_rms_line(col, lam, counter)
-                if mode == TRUNC_PER_DIM:
-                    clip = min(col) + lam * trunc
-                    line = [min(a, clip) for a in line]
-                for vy in range(qy):
-                    g[vy][vx] = line[vy]
-        if mode == TRUNC_JOINT:
-            clip = int(flat[n].min()) + lam * trunc
-            g = [[min(a, clip) for a in row] for row in g]
-        out[n] = np.array(g, dtype=np.int64)
-        if counter is not None:
-            counter.outputs += qx * qy
-    return out.reshape(*lead, qx * qy)
+    return _separable_search(h, qx, qy, qz, lam, trunc, mode, lam * trunc,
+                             lambda line: _linear_rms_line(line, lam, counter), counter)
 
 
 def _general_rms_line(line: list, lam: int, trunc: int, prior: int, counter: OpCounter | None):
@@ -194,7 +214,7 @@ def _general_rms_line(line: list, lam: int, trunc: int, prior: int, counter: OpC
 
 
 def min_search_grms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                    counter: OpCounter | None = None, prior: int = PRIOR_QUAD) -> np.ndarray:
+                    counter: OpCounter | None = None, prior: int = PRIOR_QUAD, qz: int = 1) -> np.ndarray:
     """General RMS (GRMS, Sec. 3.1) for any truncated prior f: one windowed operator per
     label dimension and the clip of eq. M_decmp.
 
@@ -202,37 +222,10 @@ def min_search_grms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode:
     (the product of the per-dimension windows holds every u with f(|u|) < f(g), eq. derivation2).
     ``mode`` 0 (per-dimension truncation): each dimension's operator is followed by the clip of
     its own line, min h_line + lam f(g) (eq. derivation1 applied to that dimension).
-    Only the values are returned.
+    The dimensions run x, y, then z (``qz`` > 1).  Only the values are returned.
     """
-    h = np.asarray(h, dtype=np.int64)
-    lead = h.shape[:-1]
-    flat = h.reshape(-1, qy, qx)
-    out = np.empty_like(flat)
-    clipd = lam * prior_f(trunc, prior)
-    for n in range(flat.shape[0]):
-        g = [[int(flat[n, vy, vx]) for vx in range(qx)] for vy in range(qy)]
-        for vy in range(qy):                                   # dimension x (r = 1)
-            line = _general_rms_line(g[vy], lam, trunc, prior, counter)
-            if mode == TRUNC_PER_DIM:
-                clip = min(g[vy]) + clipd
-                line = [min(a, clip) for a in line]
-            g[vy] = line
-        if qy > 1:                                             # dimension y (r = 2)
-            for vx in range(qx):
-                col = [g[vy][vx] for vy in range(qy)]
-                line = _general_rms_line(col, lam, trunc, prior, counter)
-                if mode == TRUNC_PER_DIM:
-                    clip = min(col) + clipd
-                    line = [min(a, clip) for a in line]
-                for vy in range(qy):
-                    g[vy][vx] = line[vy]
-        if mode == TRUNC_JOINT:
-            clip = int(flat[n].min()) + clipd
-            g = [[min(a, clip) for a in row] for row in g]
-        out[n] = np.array(g, dtype=np.int64)
-        if counter is not None:
-            counter.outputs += qx * qy
-    return out.reshape(*lead, qx * qy)
+    return _separable_search(h, qx, qy, qz, lam, trunc, mode, lam * prior_f(trunc, prior),
+                             lambda line: _general_rms_line(line, lam, trunc, prior, counter), counter)
 
 
 # ---------------------------------------------------------------------------
@@ -240,7 +233,7 @@ def min_search_grms(h: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode:
 # ---------------------------------------------------------------------------
 
 def energy(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, trunc: int,
-           mode: int, grid4: bool, prior: int = PRIOR_LINEAR) -> int:
+           mode: int, grid4: bool, prior: int = PRIOR_LINEAR, qz: int = 1) -> int:
     """E = sum_x C(x, v(x)) + sum over neighbour pairs of V(v(x') - v(x)).
 
     ``grid4`` False: horizontal pairs only (independent scanlines, eq. One_d);
@@ -251,17 +244,19 @@ def energy(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, tru
     H, W, _ = cost.shape
     yy, xx = np.mgrid[0:H, 0:W]
     e = int(cost[yy, xx, labels].astype(np.int64).sum())
-    vx, vy = labels % qx, labels // qx
+    vx, vy, vz = label_coords(labels, qx, qy)
 
-    def pair(ax, ay):
-        fx, fy, fg = prior_f(ax, prior), prior_f(ay, prior), prior_f(trunc, prior)
+    def pair(ax, ay, az):
+        fx, fy, fz, fg = prior_f(ax, prior), prior_f(ay, prior), prior_f(az, prior), prior_f(trunc, prior)
         if mode == TRUNC_PER_DIM:
-            return lam * (np.minimum(fx, fg) + np.minimum(fy, fg))
-        return lam * np.minimum(fx + fy, fg)
+            return lam * (np.minimum(fx, fg) + np.minimum(fy, fg) + np.minimum(fz, fg))
+        return lam * np.minimum(fx + fy + fz, fg)
 
-    e += int(pair(np.abs(vx[:, 1:] - vx[:, :-1]), np.abs(vy[:, 1:] - vy[:, :-1])).sum())
+    e += int(pair(np.abs(vx[:, 1:] - vx[:, :-1]), np.abs(vy[:, 1:] - vy[:, :-1]),
+                  np.abs(vz[:, 1:] - vz[:, :-1])).sum())
     if grid4:
-        e += int(pair(np.abs(vx[1:, :] - vx[:-1, :]), np.abs(vy[1:, :] - vy[:-1, :])).sum())
+        e += int(pair(np.abs(vx[1:, :] - vx[:-1, :]), np.abs(vy[1:, :] - vy[:-1, :]),
+                      np.abs(vz[1:, :] - vz[:-1, :])).sum())
     return e
 
 
@@ -270,7 +265,7 @@ def energy(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, tru
 # ---------------------------------------------------------------------------
 
 def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                prior: int = PRIOR_LINEAR):
+                prior: int = PRIOR_LINEAR, qz: int = 1):
     """Brute-force scanline DP: every row is an independent chain.
 
     S(0, v) = C(0, v) (zero boundary, eq. DP_1D_2), S(x+1) = C(x+1) + M(S(x)) (eq. base)
@@ -283,7 +278,7 @@ def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: 
     ptr = np.zeros((H, W, Q), np.int64)
     s = cost[:, 0, :].copy()
     for x in range(1, W):
-        m, a = min_search_sfms(s, qx, qy, lam, trunc, mode, prior=prior)
+        m, a = min_search_sfms(s, qx, qy, lam, trunc, mode, prior=prior, qz=qz)
         ptr[:, x, :] = a
         s = cost[:, x, :] + m
     row_e = s.min(axis=1)
@@ -296,7 +291,7 @@ def dp_scanline(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: 
 
 
 def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                     prior: int = PRIOR_LINEAR):
+                     prior: int = PRIOR_LINEAR, qz: int = 1):
     """Modified DP of Sec. 4.1, eq. DP_1D_3: S_Omega(x) = M(S_1(x-1)) + C(x) + M(S_-1(x+1)).
 
     S_1 runs left to right, S_-1 right to left, both with the zero boundary.
@@ -308,16 +303,16 @@ def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
     bwd = np.zeros((W, Q), np.int64)
     fwd[0] = c[0]
     for x in range(1, W):
-        fwd[x] = c[x] + min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode, prior=prior)[0]
+        fwd[x] = c[x] + min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode, prior=prior, qz=qz)[0]
     bwd[W - 1] = c[W - 1]
     for x in range(W - 2, -1, -1):
-        bwd[x] = c[x] + min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode, prior=prior)[0]
+        bwd[x] = c[x] + min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode, prior=prior, qz=qz)[0]
     marg = c.copy()
     for x in range(W):
         if x > 0:
-            marg[x] += min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode, prior=prior)[0]
+            marg[x] += min_search_sfms(fwd[x - 1], qx, qy, lam, trunc, mode, prior=prior, qz=qz)[0]
         if x < W - 1:
-            marg[x] += min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode, prior=prior)[0]
+            marg[x] += min_search_sfms(bwd[x + 1], qx, qy, lam, trunc, mode, prior=prior, qz=qz)[0]
     return marg
 
 
@@ -326,7 +321,7 @@ def dp_min_marginals(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
 # ---------------------------------------------------------------------------
 
 def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                     prior: int = PRIOR_LINEAR):
+                     prior: int = PRIOR_LINEAR, qz: int = 1):
     """All Q^W labellings of one chain.  Returns (E_min, canonical optimal labelling).
 
     The canonical labelling is the reverse-lexicographic minimum among the optimal
@@ -336,7 +331,7 @@ def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
     W, Q = c.shape
     labs = np.array(list(itertools.product(range(Q), repeat=W)), dtype=np.int64)
     e = c[np.arange(W)[None, :], labs].sum(axis=1)
-    vm = prior_matrix(qx, qy, lam, trunc, mode, prior)
+    vm = prior_matrix(qx, qy, lam, trunc, mode, prior, qz)
     for x in range(W - 1):
         e += vm[labs[:, x + 1], labs[:, x]]
     best = e.min()
@@ -346,7 +341,7 @@ def chain_exhaustive(cost_row: np.ndarray, qx: int, qy: int, lam: int, trunc: in
 
 
 def grid_exhaustive(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-                    prior: int = PRIOR_LINEAR) -> int:
+                    prior: int = PRIOR_LINEAR, qz: int = 1) -> int:
     """Minimum 4-connected energy over all Q^(W*H) labellings of a tiny grid."""
     c = np.asarray(cost, dtype=np.int64)
     H, W, Q = c.shape
@@ -354,7 +349,7 @@ def grid_exhaustive(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mo
     labs = np.array(list(itertools.product(range(Q), repeat=n)), dtype=np.int64).reshape(-1, H, W)
     yy, xx = np.mgrid[0:H, 0:W]
     e = c[yy[None], xx[None], labs].reshape(labs.shape[0], -1).sum(axis=1)
-    vm = prior_matrix(qx, qy, lam, trunc, mode, prior)
+    vm = prior_matrix(qx, qy, lam, trunc, mode, prior, qz)
     e += vm[labs[:, :, 1:], labs[:, :, :-1]].reshape(labs.shape[0], -1).sum(axis=1)
     e += vm[labs[:, 1:, :], labs[:, :-1, :]].reshape(labs.shape[0], -1).sum(axis=1)
     return int(e.min())
@@ -377,7 +372,7 @@ SCANS = (
 
 
 def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-        iterations: int = 1, search: str = "sfms", trace=None, prior: int = PRIOR_LINEAR):
+        iterations: int = 1, search: str = "sfms", trace=None, prior: int = PRIOR_LINEAR, qz: int = 1):
     """Literal EDP, Algorithm 1 steps 3-5 (the DSI and the prior are the inputs).
 
     For every scan P1..P4 and every vertex x in the scan's raster order, each sum
@@ -396,9 +391,9 @@ def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
     H, W, Q = c.shape
     if search == "lrms" and prior != PRIOR_LINEAR:
         raise ValueError("the linear RMS applies to the truncated linear prior only")
-    msearch = {"sfms": lambda h: min_search_sfms(h, qx, qy, lam, trunc, mode, prior=prior)[0],
-               "lrms": lambda h: min_search_lrms(h, qx, qy, lam, trunc, mode),
-               "grms": lambda h: min_search_grms(h, qx, qy, lam, trunc, mode, prior=prior)}[search]
+    msearch = {"sfms": lambda h: min_search_sfms(h, qx, qy, lam, trunc, mode, prior=prior, qz=qz)[0],
+               "lrms": lambda h: min_search_lrms(h, qx, qy, lam, trunc, mode, qz=qz),
+               "grms": lambda h: min_search_grms(h, qx, qy, lam, trunc, mode, prior=prior, qz=qz)}[search]
     sums = {k: np.zeros((H, W, Q), np.int64) for k in DIRECTIONS}
     max_abs = 0
 
@@ -436,7 +431,7 @@ def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
     labels = np.argmin(marg, axis=-1)
     if max_abs > INT32_MAX:
         raise OverflowError(f"EDP sum {max_abs} exceeds int32")
-    e = energy(c, labels, qx, qy, lam, trunc, mode, grid4=True, prior=prior)
+    e = energy(c, labels, qx, qy, lam, trunc, mode, grid4=True, prior=prior, qz=qz)
     return {"labels": labels, "energy": e, "marginal": marg, "sums": sums,
             "max_abs_sum": max_abs}
 

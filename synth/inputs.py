@@ -2,8 +2,9 @@
 
 Every generator is a pure function of its seed (numpy ``default_rng``).  The
 outputs are integer cost volumes ``C[y][x][q]`` (the disparity space image of
-Sec. 2) with the flat label ``q = vy * qx + vx``, plus the smoothness
-parameters of the workload.  Nothing here minimises an energy.
+Sec. 2) with the flat label ``q = (vz * qy + vy) * qx + vx`` (qz = 1 below three
+label dimensions), plus the smoothness parameters of the workload.  Nothing here
+minimises an energy.
 
 Workload recipes (shapes and value distributions follow the paper's stereo
 and motion experiments of Sec. 5.1; the Middlebury images themselves are not
@@ -17,6 +18,9 @@ used, textured synthetic pairs stand in for them):
   (eq. Cost_value with l2 = 1).
 * ``motion_problem``  -- 2D disparity space (dx, dy in [-r, r]): affine motion
   over Voronoi segments, truncated squared difference cost (l2 = 2).
+* ``motion_offset_problem`` -- 3D disparity space (dx, dy, b): the motion frames
+  with a brightness offset per segment, b one of ``levels`` offset steps; the
+  cost compares I0 + offset with the displaced I1 (truncated squared difference).
 * ``random_problem``  -- uniform random costs of any shape, for parity sweeps.
 """
 from __future__ import annotations
@@ -27,8 +31,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # Truncation modes of the smoothness prior (meaning is fixed by the solvers):
-#   0: per label dimension  lambda * (min(f(|dx|), f(T)) + min(f(|dy|), f(T)))
-#   1: joint                lambda * min(f(|dx|) + f(|dy|), f(T))
+#   0: per label dimension  lambda * (min(f(|dx|), f(T)) + min(f(|dy|), f(T)) [+ min(f(|dz|), f(T))])
+#   1: joint                lambda * min(f(|dx|) + f(|dy|) [+ f(|dz|)], f(T))
 TRUNC_PER_DIM = 0
 TRUNC_JOINT = 1
 # Prior functions f: 0 truncated linear f(a) = a, 1 truncated squared f(a) = a^2.
@@ -49,6 +53,7 @@ class Problem:
     name: str = ""
     meta: dict = field(default_factory=dict)
     prior: int = PRIOR_LINEAR
+    qz: int = 1                 # labels along a third label dimension
 
     @property
     def height(self) -> int:
@@ -60,7 +65,7 @@ class Problem:
 
     @property
     def q(self) -> int:
-        return self.qx * self.qy
+        return self.qx * self.qy * self.qz
 
     @property
     def pixel_labels(self) -> int:
@@ -202,6 +207,12 @@ def motion_frames(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, segment
     Returns (i0, i1, fu, fv): uint8 [H][W] frames where I1(x + fu, y + fv) shows I0(x, y),
     and the integer flow components in [-r, r] (fu) and [-ry, ry] (fv, ry = r by default).
     """
+    return _motion_frames(seed, W, H, r, segments, sigma, ry, 1, 0)[:4]
+
+
+def _motion_frames(seed, W, H, r, segments, sigma, ry, levels, step):
+    """motion_frames with a brightness offset per segment when levels > 1: I1(x + fu, y + fv)
+    shows I0(x, y) + (fb - levels // 2) step, fb in [0, levels).  Returns (i0, i1, fu, fv, fb)."""
     ry = r if ry is None else ry
     rng = np.random.default_rng(seed)
     img0 = textured_image(rng, W, H)
@@ -216,10 +227,15 @@ def motion_frames(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, segment
     fv = np.clip(np.rint(v0[seg] + vx[seg] * (xx - sx[seg]) + vy[seg] * (yy - sy[seg])), -ry, ry)
     fu = fu.astype(np.int64)
     fv = fv.astype(np.int64)
-    img1 = _forward_splat(img0, xx + fu, yy + fv, depth[seg], rng)
+    fb = np.full((H, W), levels // 2, np.int64)
+    src = img0
+    if levels > 1:
+        fb = rng.integers(0, levels, segments)[seg]
+        src = img0 + (fb - levels // 2) * float(step)
+    img1 = _forward_splat(src, xx + fu, yy + fv, depth[seg], rng)
     i0 = _noisy_u8(rng, img0, sigma).astype(np.uint8)
     i1 = _noisy_u8(rng, img1, sigma).astype(np.uint8)
-    return i0, i1, fu, fv
+    return i0, i1, fu, fv, fb
 
 
 def motion_cost(i0: np.ndarray, i1: np.ndarray, r: int, cmax: int, ry: int | None = None) -> np.ndarray:
@@ -260,14 +276,51 @@ def motion_problem(seed: int = 0, W: int = 320, H: int = 240, r: int = 7, lam: i
     return Problem(cost, n, 2 * ry_ + 1, lam, trunc, mode, name=name, meta={"gt": gt, "frames": (i0, i1)})
 
 
+def motion_offset_cost(i0: np.ndarray, i1: np.ndarray, r: int, levels: int, step: int, cmax: int) -> np.ndarray:
+    """Truncated squared difference cost [H][W][(2r+1)^2 levels] int64 of a motion with a brightness
+    offset: label q = (b (2r + 1) + dy + r)(2r + 1) + dx + r compares I0(x, y) + (b - levels // 2) step
+    with I1(x + dx, y + dy); a displaced position outside the frame costs cmax."""
+    H, W = i0.shape
+    n = 2 * r + 1
+    a = i0.astype(np.float64)
+    pad = np.full((H + 2 * r, W + 2 * r), np.nan)
+    pad[r:r + H, r:r + W] = i1
+    cost = np.empty((levels * n * n, H, W), np.int64)
+    for b in range(levels):
+        ab = a + (b - levels // 2) * float(step)
+        for dy in range(-r, r + 1):
+            for dx in range(-r, r + 1):
+                sh = pad[r + dy:r + dy + H, r + dx:r + dx + W]
+                d2 = (ab - sh) ** 2
+                cq = np.where(np.isnan(d2), cmax, np.minimum(np.nan_to_num(d2, nan=0.0), cmax))
+                cost[(b * n + dy + r) * n + dx + r] = cq.astype(np.int64)
+    return np.ascontiguousarray(np.moveaxis(cost, 0, -1))
+
+
+def motion_offset_problem(seed: int = 0, W: int = 320, H: int = 240, r: int = 3, levels: int = 7, step: int = 6,
+                          lam: int = 40, trunc: int = 3, cmax: int = 2500, segments: int = 8, sigma: float = 4.0,
+                          mode: int = TRUNC_PER_DIM, dtype=np.int32) -> Problem:
+    """A three-dimensional disparity space: motion (dx, dy in [-r, r]) and a brightness offset
+    (levels steps of ``step`` grey levels) over Voronoi segments, truncated squared difference cost.
+
+    Labels: q = (b * (2r + 1) + dy + r) * (2r + 1) + dx + r, so qx = qy = 2r + 1 and qz = levels.
+    """
+    n = 2 * r + 1
+    i0, i1, fu, fv, fb = _motion_frames(seed, W, H, r, segments, sigma, r, levels, step)
+    cost = np.ascontiguousarray(motion_offset_cost(i0, i1, r, levels, step, cmax).astype(dtype))
+    gt = (fb * n + fv + r) * n + fu + r
+    return Problem(cost, n, n, lam, trunc, mode, name=f"motionoff{W}x{H}r{r}b{levels}s{seed}",
+                   meta={"gt": gt, "frames": (i0, i1)}, qz=levels)
+
+
 def random_problem(seed: int, W: int, H: int, qx: int, qy: int = 1, lam: int = 7, trunc: int = 2,
                    mode: int = TRUNC_PER_DIM, lo: int = 0, hi: int = 100,
-                   dtype=np.int32) -> Problem:
+                   dtype=np.int32, qz: int = 1) -> Problem:
     """Uniform random integer costs in [lo, hi] of any shape."""
     rng = np.random.default_rng(seed)
-    cost = rng.integers(lo, hi + 1, size=(H, W, qx * qy), dtype=np.int64).astype(dtype)
-    return Problem(np.ascontiguousarray(cost), qx, qy, lam, trunc, mode,
-                   name=f"rand{W}x{H}q{qx}x{qy}s{seed}")
+    cost = rng.integers(lo, hi + 1, size=(H, W, qx * qy * qz), dtype=np.int64).astype(dtype)
+    name = f"rand{W}x{H}q{qx}x{qy}s{seed}" if qz == 1 else f"rand{W}x{H}q{qx}x{qy}x{qz}s{seed}"
+    return Problem(np.ascontiguousarray(cost), qx, qy, lam, trunc, mode, name=name, qz=qz)
 
 
 # --------------------------------------------------------------------------
@@ -277,7 +330,8 @@ def random_problem(seed: int, W: int, H: int, qx: int, qy: int = 1, lam: int = 7
 def workload(name: str, seed: int = 0) -> Problem:
     """The named workloads: chain64x48, stereo384x288, motion320x240, motion640x480, and with
     the truncated squared prior (lambda 5, T 3, so the clip lambda T^2 = 45 is near the linear
-    workloads' lambda T): stereo384x288_sq, motion320x240_sq."""
+    workloads' lambda T): stereo384x288_sq, motion320x240_sq; three label dimensions (7 x 7 motion
+    and 7 brightness offsets, 343 labels): motion_offset320x240, motion_offset640x480."""
     if name == "chain64x48":
         return chain_problem(seed)
     if name == "stereo384x288":
@@ -291,6 +345,10 @@ def workload(name: str, seed: int = 0) -> Problem:
         return p
     if name == "motion640x480":
         return motion_problem(seed, W=640, H=480, r=15)
+    if name == "motion_offset320x240":
+        return motion_offset_problem(seed)
+    if name == "motion_offset640x480":
+        return motion_offset_problem(seed, W=640, H=480)
     raise KeyError(name)
 
 
