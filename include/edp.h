@@ -11,6 +11,8 @@
  *       E(v) = sum_x C(x, v(x)) + sum over neighbour pairs (x, x') V(v(x') - v(x))
  *       V(u) = lambda * (min(f(ux), f(T)) + min(f(uy), f(T)))   trunc_mode EDP_TRUNC_PER_DIM
  *       V(u) = lambda * min(f(ux) + f(uy), f(T))                trunc_mode EDP_TRUNC_JOINT
+ *   with a third term in uz for a three-dimensional disparity space (Sec. 2
+ *   defines the energy for a disparity vector of any dimension R).
  *   Minimum search (Sec. 2, eq. M_strf): M(h)(v) = min_v' h(v') + V(v - v'),
  *   never by the O(Q^2) scan: for the linear prior by the linear recursive
  *   minimum search of Sec. 3.2 (two passes per label dimension plus the clip
@@ -21,7 +23,8 @@
  * Conventions shared by every entry point
  *   - Cost volume: dense, row-major C[y][x][q], int16 or int32, caller-owned
  *     device memory, aligned to the element size.  Labels are flat and 0-based:
- *     q = vy * qx + vx (stereo: qy = 1).
+ *     q = (vz * qy + vy) * qx + vx (stereo: qy = 1; two label dimensions:
+ *     qz = 1, so q = vy * qx + vx).
  *   - All d_* pointers are device pointers owned by the caller; the library
  *     allocates nothing.  Scratch memory is the caller's workspace d_ws of at
  *     least edp_workspace_size() bytes, 256-byte aligned; its contents are
@@ -35,10 +38,13 @@
  *   - Label spaces: the EDP scans hold a vertex's labels on one lane tile
  *     (edp_tiles()) or, for two label dimensions with a window search
  *     (T <= 3), on a wide tile of several wavefronts (edp_wide_tiles()); the
- *     largest tiles take 256 labels along one dimension (qy == 1) and
- *     32 x 32 labels in two dimensions.  Larger label spaces return
- *     EDP_E_UNSUPPORTED from the EDP and DP calls (edp_dsi and edp_energy
- *     take up to 4096 labels).
+ *     largest tiles take 256 labels along one dimension (qy == 1),
+ *     32 x 32 labels in two dimensions and 8 x 8 x 8 in three
+ *     (edp_tiles_3d()).  Larger label spaces return EDP_E_UNSUPPORTED from
+ *     the EDP and DP calls (edp_dsi and edp_energy take up to 4096 labels).
+ *     Three label dimensions (qz > 1) are taken by edp_solve, edp_batch_*,
+ *     edp_energy and edp_workspace_size with EDP_OP_EDP; the scanline DP
+ *     calls and the label-window solve return EDP_E_UNSUPPORTED for them.
  *   - Bounded waits: the EDP scans of one solve run as a pipelined wavefront
  *     whose workgroups wait for each other.  Every such wait gives up after a
  *     bounded number of polls (of the order of a second) instead of hanging the
@@ -80,12 +86,13 @@ typedef struct {
     int32_t qx;          /* labels along the first label dimension, >= 1 */
     int32_t qy;          /* labels along the second label dimension, >= 1 (1 for stereo) */
     int32_t dtype;       /* edp_dtype of the cost volume */
-    int32_t trunc_mode;  /* edp_trunc_mode; the two modes coincide when qy == 1 */
+    int32_t trunc_mode;  /* edp_trunc_mode; the two modes coincide with one label dimension */
     int32_t lambda;      /* prior weight, 0 <= lambda <= 65535 */
     int32_t trunc;       /* truncation threshold T (the paper's g), 1 <= T <= 4096 */
     int32_t iterations;  /* EDP iterations j >= 1 of Algorithm 1 (ignored by the DP) */
     int32_t cost_bound;  /* promise |C| <= cost_bound; 0 = the dtype's range (int16 only) */
     int32_t prior;       /* edp_prior: f(a) = |a| (0) or a^2 (1) */
+    int32_t qz;          /* labels along a third label dimension; 0 or 1 = none (R <= 2) */
 } edp_problem;
 
 /* Optional tuning of the launch (results never depend on it).  NULL, or a
@@ -311,9 +318,21 @@ int32_t edp_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max);
  * one window per label dimension).  Same return convention as edp_tiles(). */
 int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max);
 
-/* Shape of a tile (edp_tiles() or edp_wide_tiles()): lanes px * py per cell,
- * labels kx * ky per lane. */
+/* Lane tiles of the EDP scans usable for a (qx, qy, qz) label space with three
+ * label dimensions.  Lane (px, py) of a vertex holds its kx * ky labels at each
+ * of the kz labels of the third dimension, so the operator of that dimension
+ * (one per label dimension, Sec. 3 eq. M_decmp) works inside the lane.  Same
+ * return convention as edp_tiles(). */
+int32_t edp_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t max);
+
+/* Shape of a tile (edp_tiles(), edp_wide_tiles() or edp_tiles_3d()): lanes
+ * px * py per cell, labels kx * ky per lane at each of its edp_tile_depth()
+ * labels along the third dimension. */
 edp_status edp_tile_info(int32_t tile, int32_t* px, int32_t* kx, int32_t* py, int32_t* ky);
+
+/* Labels kz along the third label dimension that a tile holds in every lane
+ * (1 for the tiles of one or two label dimensions). */
+edp_status edp_tile_depth(int32_t tile, int32_t* kz);
 
 /* Static text for a status code. */
 const char* edp_status_string(int32_t status);

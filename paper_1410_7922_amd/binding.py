@@ -29,12 +29,14 @@ OP_DP_MARGINALS = 2
 EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
            "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
            "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy", "edp_window_workspace_size",
-           "edp_solve_windowed", "edp_dp_marginals", "edp_dsi", "edp_solve_static", "edp_wide_tiles")
+           "edp_solve_windowed", "edp_dp_marginals", "edp_dsi", "edp_solve_static", "edp_wide_tiles",
+           "edp_tiles_3d", "edp_tile_depth")
 
 
 class Problem(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
-        "width", "height", "qx", "qy", "dtype", "trunc_mode", "lam", "trunc", "iterations", "cost_bound", "prior")]
+        "width", "height", "qx", "qy", "dtype", "trunc_mode", "lam", "trunc", "iterations", "cost_bound", "prior",
+        "qz")]
 
 
 class Tuning(ctypes.Structure):
@@ -77,6 +79,8 @@ def load(path: str = LIB_PATH):
     L.edp_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.edp_wide_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.edp_tile_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
+    L.edp_tiles_3d.argtypes = [ctypes.c_int32] * 3 + [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    L.edp_tile_depth.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.edp_status_string.argtypes = [ctypes.c_int32]
     L.edp_status_string.restype = ctypes.c_char_p
     pitem = ctypes.POINTER(BatchItem)
@@ -91,7 +95,7 @@ def load(path: str = LIB_PATH):
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
                  "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals",
-                 "edp_dsi", "edp_solve_static", "edp_wide_tiles"):
+                 "edp_dsi", "edp_solve_static", "edp_wide_tiles", "edp_tiles_3d", "edp_tile_depth"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -116,16 +120,16 @@ def check_status(status, where: str = "solve"):
 
 
 def make_problem(cost: torch.Tensor, qx: int, qy: int, lam: int, trunc: int, mode: int = TRUNC_PER_DIM,
-                 iterations: int = 1, cost_bound: int = 0, prior: int = PRIOR_LINEAR) -> Problem:
+                 iterations: int = 1, cost_bound: int = 0, prior: int = PRIOR_LINEAR, qz: int = 1) -> Problem:
     if cost.dim() != 3:
         raise ValueError("cost must be [H][W][Q]")
     if cost.dtype not in (torch.int16, torch.int32):
         raise ValueError("cost must be int16 or int32")
     H, W, Q = cost.shape
-    if Q != qx * qy:
-        raise ValueError(f"cost has {Q} labels, qx*qy = {qx * qy}")
+    if Q != qx * qy * qz:
+        raise ValueError(f"cost has {Q} labels, qx*qy*qz = {qx * qy * qz}")
     return Problem(W, H, qx, qy, EDP_I16 if cost.dtype == torch.int16 else EDP_I32, mode, lam, trunc,
-                   iterations, cost_bound, prior)
+                   iterations, cost_bound, prior, qz)
 
 
 def _tuning(tile: int, chunk: int, events=None, split: int = 0, waves: int = 0, fuse: int = 0):
@@ -183,10 +187,28 @@ def wide_tiles(qx: int, qy: int) -> list:
     return list(ids[:n])
 
 
+def tiles_3d(qx: int, qy: int, qz: int) -> list:
+    """Lane tiles of the EDP scans for a label space with three label dimensions."""
+    L = load()
+    n = L.edp_tiles_3d(qx, qy, qz, None, 0)
+    if n < 0:
+        raise EdpError(n, "edp_tiles_3d")
+    ids = (ctypes.c_int32 * max(n, 1))()
+    L.edp_tiles_3d(qx, qy, qz, ids, n)
+    return list(ids[:n])
+
+
 def tile_info(tile: int) -> tuple:
     v = [ctypes.c_int32() for _ in range(4)]
     _check(load().edp_tile_info(tile, *[ctypes.byref(x) for x in v]), "edp_tile_info")
     return tuple(x.value for x in v)
+
+
+def tile_depth(tile: int) -> int:
+    """Labels along the third label dimension that a tile holds per lane (1 below three dimensions)."""
+    kz = ctypes.c_int32()
+    _check(load().edp_tile_depth(tile, ctypes.byref(kz)), "edp_tile_depth")
+    return kz.value
 
 
 class Workspace:
@@ -268,15 +290,16 @@ def solve(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 
           iterations: int = 1, cost_bound: int = 0, tile: int = -1, chunk: int = 0,
           ws: Workspace | None = None, labels: torch.Tensor | None = None, energy: torch.Tensor | None = None,
           events=None, split: int = 0, waves: int = 0, fuse: int = 0, prior: int = PRIOR_LINEAR,
-          status: torch.Tensor | None = None, check: bool = True):
+          status: torch.Tensor | None = None, check: bool = True, qz: int = 1):
     """EDP (edp_solve).  Returns (labels [H][W] int32, energy [1] int64) as device tensors.
+    ``qz``: labels along a third label dimension (cost [H][W][qx*qy*qz]).
 
     ``events``: optional ctypes array of hipEvent_t handles recorded around the scan launches.
     ``status``: optional [1] int32 device tensor receiving the solve's status word.  ``check``:
     wait for the solve and raise EdpError if its scans gave up waiting (EDP_E_TIMEOUT); with
     check=False the call only enqueues and the caller reads ``status`` (check_status) later."""
     _device_tensor(cost, "cost")
-    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound, prior)
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound, prior, qz)
     nbytes = workspace_size(prob, OP_EDP, tile, chunk, split, waves, fuse)
     w = (ws or _default_ws).get(nbytes, cost.device)
     H, W, _ = cost.shape
@@ -298,12 +321,12 @@ def solve_static(cost: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc:
                  iterations: int = 1, cost_bound: int = 0, labels: torch.Tensor | None = None,
                  energy: torch.Tensor | None = None, status: torch.Tensor | None = None, check: bool = True,
                  prior: int = PRIOR_LINEAR, tile: int = -1, chunk: int = 0, split: int = 0, waves: int = 0,
-                 fuse: int = 0):
+                 fuse: int = 0, qz: int = 1):
     """EDP with the library's static workspace (edp_solve_static): the library allocates nothing;
     pass ``labels``, ``energy`` and ``status`` to allocate nothing here either.  Returns (labels, energy)
     as solve()."""
     _device_tensor(cost, "cost")
-    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound, prior)
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, iterations, cost_bound, prior, qz)
     H, W, _ = cost.shape
     if labels is None:
         labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
@@ -350,13 +373,14 @@ def solve_windowed(cost: torch.Tensor, centers: torch.Tensor, win: int, qx: int,
 
 
 def energy(cost: torch.Tensor, labels: torch.Tensor, qx: int, qy: int = 1, lam: int = 20, trunc: int = 2,
-           mode: int = TRUNC_PER_DIM, grid4: bool = True, cost_bound: int = 0, prior: int = PRIOR_LINEAR):
+           mode: int = TRUNC_PER_DIM, grid4: bool = True, cost_bound: int = 0, prior: int = PRIOR_LINEAR,
+           qz: int = 1):
     """Energy of a labelling (edp_energy).  Returns (energy [1] int64, invalid-label count [1] int64)."""
     _device_tensor(cost, "cost")
     _device_tensor(labels, "labels")
     if labels.dtype != torch.int32 or tuple(labels.shape) != tuple(cost.shape[:2]):
         raise ValueError("labels must be int32 [H][W]")
-    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound, prior)
+    prob = make_problem(cost, qx, qy, lam, trunc, mode, 1, cost_bound, prior, qz)
     e = torch.empty(1, dtype=torch.int64, device=cost.device)
     bad = torch.empty(1, dtype=torch.int64, device=cost.device)
     _check(load().edp_energy(ctypes.byref(prob), cost.data_ptr(), labels.data_ptr(), int(bool(grid4)),
@@ -366,7 +390,7 @@ def energy(cost: torch.Tensor, labels: torch.Tensor, qx: int, qy: int = 1, lam: 
 
 def batch_items(costs, params, labels, energies, tunings=None, statuses=None):
     """ctypes array of edp_batch_item for device tensors: params[i] holds qx, qy, lam, trunc, mode,
-    iterations, cost_bound, prior; tunings[i] (optional) holds tile, chunk, split, waves, fuse."""
+    iterations, cost_bound, prior, qz; tunings[i] (optional) holds tile, chunk, split, waves, fuse."""
     n = len(costs)
     items = (BatchItem * n)()
     for i in range(n):
@@ -375,7 +399,7 @@ def batch_items(costs, params, labels, energies, tunings=None, statuses=None):
         pr = params[i]
         items[i].problem = make_problem(costs[i], pr["qx"], pr.get("qy", 1), pr["lam"], pr["trunc"],
                                         pr.get("mode", TRUNC_PER_DIM), pr.get("iterations", 1),
-                                        pr.get("cost_bound", 0), pr.get("prior", PRIOR_LINEAR))
+                                        pr.get("cost_bound", 0), pr.get("prior", PRIOR_LINEAR), pr.get("qz", 1))
         items[i].d_cost = costs[i].data_ptr()
         items[i].d_labels = labels[i].data_ptr()
         items[i].d_energy = energies.data_ptr() + 8 * i if energies is not None else None

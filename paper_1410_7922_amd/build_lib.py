@@ -17,6 +17,8 @@ SOURCES = [
     "edp_api.hip", "edp_pass.hip",
     # scans and marginal of the wide-vertex tiles (a vertex on several wavefronts)
     "edp_pass_mv.hip",
+    # scans and marginal of the tiles of three-dimensional label spaces
+    "edp_pass_z.hip",
     # edp_solve with its workspace in a static device array (callers that cannot allocate)
     "edp_static.hip",
     # scanline DP: choice indexes and backtracking; min-marginals per tile group

@@ -18,32 +18,42 @@ static_assert(STATUS_TIMEOUT == EDP_E_TIMEOUT, "status word value of a timed-out
 
 namespace {
 
-// single-wavefront tiles, then the wide-vertex tiles as 16 x (4 NV) lane grids
+// single-wavefront tiles, the wide-vertex tiles as 16 x (4 NV) lane grids, then the
+// single-wavefront tiles of three-dimensional label spaces
 const TileShape kTiles[NUM_ALL_TILES] = {
-#define EDP_ROW(id, px, kx, py, ky) {px, kx, py, ky},
+#define EDP_ROW(id, px, kx, py, ky) {px, kx, py, ky, 1},
     EDP_TILE_LIST(EDP_ROW)
 #undef EDP_ROW
-#define EDP_MV_ROW(id, kx, ky, nv) {16, kx, 4 * nv, ky},
+#define EDP_MV_ROW(id, kx, ky, nv) {16, kx, 4 * nv, ky, 1},
     EDP_MV_TILE_LIST(EDP_MV_ROW)
 #undef EDP_MV_ROW
+#define EDP_ROW3(id, px, kx, py, ky, kz) {px, kx, py, ky, kz},
+    EDP_TILE3_LIST(EDP_ROW3)
+#undef EDP_ROW3
 };
 
-bool is_wide(int tile) { return tile >= NUM_TILES && tile < NUM_ALL_TILES; }
+bool is_wide(int tile) { return tile >= NUM_TILES && tile < FIRST_TILE3; }
+// tiles of the single-wavefront scan kernel (two- and three-dimensional label spaces)
+bool is_regular(int tile) { return (tile >= 0 && tile < NUM_TILES) || (tile >= FIRST_TILE3 && tile < NUM_ALL_TILES); }
 int wide_nv(int tile) { return kTiles[tile].py / 4; }
+
+// labels along the third label dimension (0 in the problem means none)
+int qz_of(const edp_problem* p) { return p->qz > 1 ? p->qz : 1; }
+int64_t labels_of(const edp_problem* p) { return (int64_t)p->qx * p->qy * qz_of(p); }
 
 constexpr size_t kAlign = 256;
 size_t up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 int qt_of(int tile) {
     const TileShape& t = kTiles[tile];
-    return t.px * t.py * t.kx * t.ky;
+    return t.px * t.py * t.kx * t.ky * t.kz;
 }
 int group_of(int tile) { return kTiles[tile].px * kTiles[tile].py; }
-int elems_of(int tile) { return kTiles[tile].kx * kTiles[tile].ky; }
+int elems_of(int tile) { return kTiles[tile].kx * kTiles[tile].ky * kTiles[tile].kz; }
 
-bool fits(int tile, int qx, int qy) {
+bool fits(int tile, int qx, int qy, int qz = 1) {
     const TileShape& t = kTiles[tile];
-    return t.px * t.kx >= qx && t.py * t.ky >= qy;
+    return t.px * t.kx >= qx && t.py * t.ky >= qy && t.kz >= qz;
 }
 
 // Built-in choice: least padding; then, for one label dimension, vertices that fill
@@ -51,15 +61,16 @@ bool fits(int tile, int qx, int qy) {
 // instruction), for two, vertices that fill the wavefront (the scan step costs the
 // same instructions whatever the lane count, so more lanes per vertex means fewer
 // labels per lane); then fewest labels per lane; then square lane grids.
-int auto_tile(int qx, int qy) {
+// Three label dimensions take the tiles of three-dimensional label spaces only.
+int auto_tile(int qx, int qy, int qz = 1) {
     int best = -1;
-    auto score = [qy](int t) {
+    auto score = [qy, qz](int t) {
         const int lanes = group_of(t);
-        const int pref = qy == 1 ? 16 : 64;
+        const int pref = qy == 1 && qz == 1 ? 16 : 64;
         return (lanes == pref ? 0 : 1000) + 10 * elems_of(t) + (kTiles[t].px == kTiles[t].py ? 0 : 1);
     };
-    for (int t = 0; t < NUM_TILES; ++t) {
-        if (!fits(t, qx, qy)) continue;
+    for (int t = 0; t < NUM_ALL_TILES; ++t) {
+        if (!is_regular(t) || (qz > 1) != (kTiles[t].kz > 1) || !fits(t, qx, qy, qz)) continue;
         if (best < 0 || qt_of(t) < qt_of(best) || (qt_of(t) == qt_of(best) && score(t) < score(best))) best = t;
     }
     return best;
@@ -86,22 +97,27 @@ int64_t clip_of(const edp_problem* p) {
 // window where it has at most two steps per side (cheaper than the linear RMS then, for
 // either prior), else the linear RMS (linear prior) or the walked window (squared prior).
 int ms_of(const edp_problem* p) {
-    const int nw = std::max(std::min(p->trunc, p->qx), std::min(p->trunc, p->qy)) - 1;
+    const int nw = std::max({std::min(p->trunc, p->qx), std::min(p->trunc, p->qy), std::min(p->trunc, qz_of(p))}) - 1;
     if (nw <= 1) return MS_WINDOW1;
     if (nw <= 2) return MS_WINDOW;
     return p->prior == EDP_PRIOR_SQUARED ? MS_WALK : MS_LINEAR;
 }
 
 int64_t vmax_of(const edp_problem* p) {
-    const int64_t dims = (p->trunc_mode == EDP_TRUNC_PER_DIM && p->qy > 1) ? 2 : 1;
+    const int64_t dims = p->trunc_mode == EDP_TRUNC_PER_DIM ? 1 + (p->qy > 1) + (qz_of(p) > 1) : 1;
     return clip_of(p) * dims;
 }
 
+// op: an edp_op, or OP_ENERGY (the energy of a labelling: no int32 range guard applies)
+constexpr int OP_ENERGY = -1;
+
 edp_status check_problem(const edp_problem* p, int op) {
     if (!p) return EDP_E_INVALID;
-    if (p->width < 1 || p->height < 1 || p->qx < 1 || p->qy < 1) return EDP_E_INVALID;
+    if (p->width < 1 || p->height < 1 || p->qx < 1 || p->qy < 1 || p->qz < 0) return EDP_E_INVALID;
     if ((int64_t)p->width * p->height > (int64_t)1 << 30) return EDP_E_INVALID;
-    if ((int64_t)p->qx * p->qy > 4096) return EDP_E_INVALID;
+    if (labels_of(p) > 4096) return EDP_E_INVALID;
+    // three label dimensions: the EDP solve and the energy
+    if (qz_of(p) > 1 && op != EDP_OP_EDP && op != OP_ENERGY) return EDP_E_UNSUPPORTED;
     if (p->dtype != EDP_I16 && p->dtype != EDP_I32) return EDP_E_INVALID;
     if (p->trunc_mode != EDP_TRUNC_PER_DIM && p->trunc_mode != EDP_TRUNC_JOINT) return EDP_E_INVALID;
     if (p->lambda < 0 || p->lambda > 65535 || p->trunc < 1 || p->trunc > 4096) return EDP_E_INVALID;
@@ -118,7 +134,7 @@ edp_status check_problem(const edp_problem* p, int op) {
     if (op == EDP_OP_EDP) {
         // empirical int32 guard for the EDP sums (they grow with the grid extent)
         if ((int64_t)(p->width + p->height) * (b + 4 * vmax_of(p)) * 8 >= ((int64_t)1 << 29)) return EDP_E_RANGE;
-    } else {
+    } else if (op != OP_ENERGY) {
         const int64_t q = (int64_t)p->qx * p->qy;
         const int64_t span = b + vmax_of(p) + (int64_t)p->lambda * (p->qx + p->qy + 64);
         if ((span << ibits_of((int)q)) >= ((int64_t)1 << 28)) return EDP_E_RANGE;
@@ -127,9 +143,9 @@ edp_status check_problem(const edp_problem* p, int op) {
 }
 
 edp_status pick_tile(const edp_problem* p, const edp_tuning* tu, int* tile) {
-    int t = (tu && tu->tile >= 0) ? tu->tile : auto_tile(p->qx, p->qy);
+    int t = (tu && tu->tile >= 0) ? tu->tile : auto_tile(p->qx, p->qy, qz_of(p));
     if (t < 0) return EDP_E_UNSUPPORTED;
-    if (t >= NUM_TILES || !fits(t, p->qx, p->qy)) return EDP_E_INVALID;
+    if (!is_regular(t) || !fits(t, p->qx, p->qy, qz_of(p))) return EDP_E_INVALID;
     *tile = t;
     return EDP_OK;
 }
@@ -184,11 +200,11 @@ edp_status pick_wide_launch(const edp_problem* p, const edp_tuning* tu, int tile
 // hold 8 or more labels per lane (two label dimensions, window search), the fewest padded
 // labels first, then the most wavefronts per vertex; else the single-wavefront choice.
 int auto_scan_tile(const edp_problem* p) {
-    const int t = auto_tile(p->qx, p->qy);
+    const int t = auto_tile(p->qx, p->qy, qz_of(p));
     const int ms = ms_of(p);
-    if (p->qy < 2 || (ms != MS_WINDOW && ms != MS_WINDOW1) || (t >= 0 && elems_of(t) < 8)) return t;
+    if (p->qy < 2 || qz_of(p) > 1 || (ms != MS_WINDOW && ms != MS_WINDOW1) || (t >= 0 && elems_of(t) < 8)) return t;
     int best = -1;
-    for (int w = NUM_TILES; w < NUM_ALL_TILES; ++w) {
+    for (int w = NUM_TILES; w < FIRST_TILE3; ++w) {
         if (!fits(w, p->qx, p->qy)) continue;
         if (best < 0 || qt_of(w) < qt_of(best) || (qt_of(w) == qt_of(best) && wide_nv(w) > wide_nv(best))) best = w;
     }
@@ -202,7 +218,7 @@ edp_status pick_launch(const edp_problem* p, const edp_tuning* tu, Launch* L) {
     const int want = (tu && tu->tile >= 0) ? tu->tile : auto_scan_tile(p);
     if (want < 0) return EDP_E_UNSUPPORTED;
     if (is_wide(want)) {
-        if (!fits(want, p->qx, p->qy)) return EDP_E_INVALID;
+        if (!fits(want, p->qx, p->qy, qz_of(p))) return EDP_E_INVALID;
         return pick_wide_launch(p, tu, want, L);
     }
     edp_tuning t1{};
@@ -341,8 +357,8 @@ __global__ void flag_error_batch_kernel(const uint32_t* error, const InstDesc* d
 // lane's run of labels starts on a 4-byte boundary.
 int cost_kind(const edp_problem* p, int tile, const void* cost) {
     int kind = p->dtype == EDP_I16 ? 1 : 2;
-    if (kind == 1 && kTiles[tile].kx % 2 == 0 && (p->qx * p->qy) % 2 == 0 &&
-        (p->qy == 1 || p->qx % 2 == 0) && ((uintptr_t)cost % 4) == 0)
+    if (kind == 1 && kTiles[tile].kx % 2 == 0 && labels_of(p) % 2 == 0 &&
+        ((p->qy == 1 && qz_of(p) == 1) || p->qx % 2 == 0) && ((uintptr_t)cost % 4) == 0)
         kind = 3;
     return kind;
 }
@@ -351,7 +367,7 @@ int cost_kind(const edp_problem* p, int tile, const void* cost) {
 bool edp_offsets_fit(const edp_problem* p, int tile) {
     const int64_t cells = (int64_t)p->width * p->height;
     return cells * qt_of(tile) * 4 < 0x7FFF0000LL &&
-           cells * p->qx * p->qy * (p->dtype == EDP_I16 ? 2 : 4) < 0x7FFF0000LL;
+           cells * labels_of(p) * (p->dtype == EDP_I16 ? 2 : 4) < 0x7FFF0000LL;
 }
 
 InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, char* base,
@@ -367,6 +383,7 @@ InstDesc make_desc(const edp_problem* p, const Launch& la, const InstLayout& L, 
     d.H = p->height;
     d.qx = p->qx;
     d.qy = p->qy;
+    d.qz = qz_of(p);
     d.lam = p->lambda;
     d.clipd = (int32_t)clip_of(p);
     d.joint = p->trunc_mode == EDP_TRUNC_JOINT;
@@ -484,6 +501,7 @@ edp_status win_launch(const edp_problem* prob, int32_t win, const edp_tuning* tu
     edp_status st = check_problem(prob, EDP_OP_EDP);
     if (st != EDP_OK) return st;
     if (win < 1 || win > WIN_FRAME || !(win & 1) || win > prob->qx || win > prob->qy) return EDP_E_INVALID;
+    if (qz_of(prob) > 1) return EDP_E_UNSUPPORTED;   // windows of two-dimensional label spaces
     // neighbouring centres differ by at most q - win labels per axis; the frame shifts are int8
     if (prob->qx - win > 127 || prob->qy - win > 127) return EDP_E_UNSUPPORTED;
     if (prob->dtype != EDP_I32 || prob->prior != EDP_PRIOR_LINEAR) return EDP_E_UNSUPPORTED;
@@ -526,6 +544,7 @@ edp_status enqueue_energy(const edp_problem* p, const void* cost, const int32_t*
     e.H = p->height;
     e.qx = p->qx;
     e.qy = p->qy;
+    e.qz = qz_of(p);
     e.lam = p->lambda;
     e.trunc = p->trunc;
     e.joint = p->trunc_mode == EDP_TRUNC_JOINT;
@@ -1132,8 +1151,7 @@ edp_status edp_dsi(const uint8_t* d_i0, const uint8_t* d_i1, const uint8_t* d_i2
 
 edp_status edp_energy(const edp_problem* prob, const void* d_cost, const int32_t* d_labels, int32_t grid4,
                       int64_t* d_energy, int64_t* d_invalid, void* stream) {
-    edp_status st = check_problem(prob, EDP_OP_DP);
-    if (st == EDP_E_RANGE) st = EDP_OK;  // the energy itself is accumulated in int64
+    edp_status st = check_problem(prob, OP_ENERGY);   // the energy itself is accumulated in int64
     if (st != EDP_OK) return st;
     if (!d_cost || !d_labels || !d_energy || (grid4 != 0 && grid4 != 1)) return EDP_E_INVALID;
     return enqueue_energy(prob, d_cost, d_labels, grid4, d_energy, d_invalid, (hipStream_t)stream);
@@ -1153,12 +1171,29 @@ int32_t edp_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
 int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
     if (qx < 1 || qy < 1 || max < 0) return EDP_E_INVALID;
     int n = 0;
-    for (int t = NUM_TILES; t < NUM_ALL_TILES; ++t) {
+    for (int t = NUM_TILES; t < FIRST_TILE3; ++t) {
         if (!fits(t, qx, qy)) continue;
         if (ids && n < max) ids[n] = t;
         ++n;
     }
     return n;
+}
+
+int32_t edp_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t max) {
+    if (qx < 1 || qy < 1 || qz < 1 || max < 0) return EDP_E_INVALID;
+    int n = 0;
+    for (int t = FIRST_TILE3; t < NUM_ALL_TILES; ++t) {
+        if (!fits(t, qx, qy, qz)) continue;
+        if (ids && n < max) ids[n] = t;
+        ++n;
+    }
+    return n;
+}
+
+edp_status edp_tile_depth(int32_t tile, int32_t* kz) {
+    if (tile < 0 || tile >= NUM_ALL_TILES || !kz) return EDP_E_INVALID;
+    *kz = kTiles[tile].kz;
+    return EDP_OK;
 }
 
 edp_status edp_tile_info(int32_t tile, int32_t* px, int32_t* kx, int32_t* py, int32_t* ky) {

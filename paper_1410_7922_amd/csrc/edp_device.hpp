@@ -6,7 +6,9 @@
 // lanes of a 64-wide wavefront.  Lane (px, py) of a group holds the KY x KX
 // block of labels vy = py*KY + ky, vx = px*KX + kx, so a line of the label
 // space along x lies in consecutive lanes of one lane row and a line along y
-// in lanes PX apart.
+// in lanes PX apart.  A three-dimensional label space repeats the block for
+// vz = 0 .. KZ-1 in every lane: the lane's KR = KZ*KY rows of KX labels are
+// row r = kz*KY + ky, and a line along z lies inside one lane.
 //
 // Cross-lane exchange uses DPP inside 16-lane rows (row_shr / row_shl /
 // row_ror / mirrors / quad permutes, a few cycles each) and the gfx950
@@ -26,11 +28,12 @@ namespace edp {
 // value, and adding the largest distance penalty to it cannot overflow int32.
 constexpr int32_t PADV = 0x3FFFFFFF;
 
-template <int PX_, int KX_, int PY_, int KY_>
+template <int PX_, int KX_, int PY_, int KY_, int KZ_ = 1>
 struct Tile {
-    static constexpr int PX = PX_, KX = KX_, PY = PY_, KY = KY_;
+    static constexpr int PX = PX_, KX = KX_, PY = PY_, KY = KY_, KZ = KZ_;
+    static constexpr int KR = KZ * KY;         // rows of KX labels per lane
     static constexpr int G = PX * PY;          // lanes per vertex
-    static constexpr int E = KX * KY;          // labels per lane
+    static constexpr int E = KX * KR;          // labels per lane
     static constexpr int QT = G * E;           // padded labels per vertex
     static_assert(G >= 1 && G <= 64 && (64 % G) == 0, "group must divide the wavefront");
     static_assert((PX & (PX - 1)) == 0 && (PY & (PY - 1)) == 0, "power-of-two lane grid");
@@ -427,20 +430,22 @@ __device__ __forceinline__ int32_t l1_line(int32_t (&val)[K], const int32_t (&lv
 // still fits in int32.
 constexpr int32_t PEN_OFF = 0x40000000;
 
-// Window steps and the penalties lam f(u) of the first two (u = 1, 2) along x and y.
+// Window steps and the penalties lam f(u) of the first two (u = 1, 2) along x, y and z.
 struct WinPen {
-    int32_t lam, nwx, nwy;
-    int32_t px[2], py[2];
+    int32_t lam, nwx, nwy, nwz;
+    int32_t px[2], py[2], pz[2];
     __device__ __forceinline__ WinPen(const int32_t lam_, const int32_t g, const int32_t qx, const int32_t qy,
-                                      const bool squared) {
+                                      const bool squared, const int32_t qz = 1) {
         lam = lam_;
         nwx = min(g, qx) - 1;
         nwy = min(g, qy) - 1;
+        nwz = min(g, qz) - 1;
 #pragma unroll
         for (int u = 1; u <= 2; ++u) {
             const int32_t p = lam * (squared ? u * u : u);
             px[u - 1] = u <= nwx ? p : PEN_OFF;
             py[u - 1] = u <= nwy ? p : PEN_OFF;
+            pz[u - 1] = u <= nwz ? p : PEN_OFF;
         }
     }
 };
@@ -651,10 +656,10 @@ __device__ __forceinline__ int32_t group_min(int32_t v, const int32_t lane) {
     return v;
 }
 
-// Distance offsets of the lane's labels along x and y: lam * vx and lam * vy.
+// Distance offsets of the lane's labels along x, y and z: lam * vx, lam * vy and lam * vz.
 template <class T>
 struct LineIndex {
-    int32_t lx[T::KX], ly[T::KY];
+    int32_t lx[T::KX], ly[T::KY], lz[T::KZ];
     __device__ __forceinline__ LineIndex(const int32_t lam, const int32_t lane) {
         const int32_t l = lane % T::G;
         const int32_t px = l % T::PX, py = l / T::PX;
@@ -662,6 +667,8 @@ struct LineIndex {
         for (int k = 0; k < T::KX; ++k) lx[k] = lam * (px * T::KX + k);
 #pragma unroll
         for (int k = 0; k < T::KY; ++k) ly[k] = lam * (py * T::KY + k);
+#pragma unroll
+        for (int k = 0; k < T::KZ; ++k) lz[k] = lam * k;
     }
 };
 
@@ -671,20 +678,21 @@ struct LineIndex {
 //     L1 transform of its lines clipped at (line minimum + clipd), the
 //     decomposition of eq. derivation2 applied per dimension;
 //   joint == true (truncation of the summed distance, the paper's prior):
-//     L_y(L_x(h)) clipped at (min h + clipd), eq. L_dec7.
-// h holds the lane's KY x KX labels; padding labels must hold PADV on entry.
-// Returns min h over the whole vertex (the group).
+//     L_z(L_y(L_x(h))) clipped at (min h + clipd), eq. L_dec7.
+// h holds the lane's KR rows of KX labels; padding labels must hold PADV on entry.
+// The dimensions run x, y, z: a padding plane of z (vz >= qz) is all PADV until the z
+// operator, so it never reaches a real label.  Returns min h over the whole vertex.
 template <class T>
-__device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const LineIndex<T>& li,
+__device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KR][T::KX], const LineIndex<T>& li,
                                               const int32_t clipd, const bool joint, const int32_t lane) {
     const int32_t l = lane % T::G;
     const int32_t px = l % T::PX, py = l / T::PX;
-    constexpr bool one_dim = T::PY * T::KY == 1;
+    constexpr bool one_dim = T::PY * T::KY == 1 && T::KZ == 1;
     int32_t rowmin = PADV;
 #pragma unroll
-    for (int ky = 0; ky < T::KY; ++ky) {
+    for (int r = 0; r < T::KR; ++r) {
         // with a single label dimension the final clip is the per-line clip
-        const int32_t lm = l1_line<T::PX, T::KX, 1>(h[ky], li.lx, clipd, !joint || one_dim, px, lane);
+        const int32_t lm = l1_line<T::PX, T::KX, 1>(h[r], li.lx, clipd, !joint || one_dim, px, lane);
         rowmin = imin(rowmin, lm);
     }
     if constexpr (one_dim) {
@@ -692,20 +700,37 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
     } else {
         int32_t gmin = rowmin;
         if constexpr (T::PY > 1) gmin = line_min<T::PY, T::PX>(gmin, lane);
+        if constexpr (T::PY * T::KY > 1) {
 #pragma unroll
-        for (int kx = 0; kx < T::KX; ++kx) {
-            int32_t col[T::KY];
+            for (int kz = 0; kz < T::KZ; ++kz)
 #pragma unroll
-            for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
-            l1_line<T::PY, T::KY, T::PX>(col, li.ly, clipd, !joint, py, lane);
+                for (int kx = 0; kx < T::KX; ++kx) {
+                    int32_t col[T::KY];
 #pragma unroll
-            for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
+                    for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[kz * T::KY + ky][kx];
+                    l1_line<T::PY, T::KY, T::PX>(col, li.ly, clipd, !joint, py, lane);
+#pragma unroll
+                    for (int ky = 0; ky < T::KY; ++ky) h[kz * T::KY + ky][kx] = col[ky];
+                }
         }
-        if (joint) {
+        if constexpr (T::KZ > 1) {
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky)
 #pragma unroll
-                for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], gmin + clipd);
+                for (int kx = 0; kx < T::KX; ++kx) {
+                    int32_t zl[T::KZ];
+#pragma unroll
+                    for (int kz = 0; kz < T::KZ; ++kz) zl[kz] = h[kz * T::KY + ky][kx];
+                    l1_line<1, T::KZ, 1>(zl, li.lz, clipd, !joint, 0, lane);
+#pragma unroll
+                    for (int kz = 0; kz < T::KZ; ++kz) h[kz * T::KY + ky][kx] = zl[kz];
+                }
+        }
+        if (joint) {
+#pragma unroll
+            for (int r = 0; r < T::KR; ++r)
+#pragma unroll
+                for (int kx = 0; kx < T::KX; ++kx) h[r][kx] = imin(h[r][kx], gmin + clipd);
         }
         return gmin;
     }
@@ -716,15 +741,15 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KY][T::KX], const 
 // (per-dimension truncation) or once at (min h + clipd) (joint truncation,
 // eq. M_decmp).  NWK as for window_line.  Same contract as min_search.
 template <class T, int NWK>
-__device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KY][T::KX], const WinPen& sp,
+__device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KR][T::KX], const WinPen& sp,
                                                    const int32_t clipd, const bool joint, const int32_t lane) {
     const int32_t l = lane % T::G;
     const int32_t px = l % T::PX, py = l / T::PX;
-    constexpr bool one_dim = T::PY * T::KY == 1;
+    constexpr bool one_dim = T::PY * T::KY == 1 && T::KZ == 1;
     int32_t rowmin = PADV;
 #pragma unroll
-    for (int ky = 0; ky < T::KY; ++ky) {
-        const int32_t lm = window_line<T::PX, T::KX, 1, NWK>(h[ky], sp.px, sp.lam, sp.nwx, clipd, !joint || one_dim,
+    for (int r = 0; r < T::KR; ++r) {
+        const int32_t lm = window_line<T::PX, T::KX, 1, NWK>(h[r], sp.px, sp.lam, sp.nwx, clipd, !joint || one_dim,
                                                              px, lane);
         rowmin = imin(rowmin, lm);
     }
@@ -733,20 +758,37 @@ __device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KY][T::KX],
     } else {
         int32_t gmin = rowmin;
         if constexpr (T::PY > 1) gmin = line_min<T::PY, T::PX>(gmin, lane);
+        if constexpr (T::PY * T::KY > 1) {
 #pragma unroll
-        for (int kx = 0; kx < T::KX; ++kx) {
-            int32_t col[T::KY];
+            for (int kz = 0; kz < T::KZ; ++kz)
 #pragma unroll
-            for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[ky][kx];
-            window_line<T::PY, T::KY, T::PX, NWK>(col, sp.py, sp.lam, sp.nwy, clipd, !joint, py, lane);
+                for (int kx = 0; kx < T::KX; ++kx) {
+                    int32_t col[T::KY];
 #pragma unroll
-            for (int ky = 0; ky < T::KY; ++ky) h[ky][kx] = col[ky];
+                    for (int ky = 0; ky < T::KY; ++ky) col[ky] = h[kz * T::KY + ky][kx];
+                    window_line<T::PY, T::KY, T::PX, NWK>(col, sp.py, sp.lam, sp.nwy, clipd, !joint, py, lane);
+#pragma unroll
+                    for (int ky = 0; ky < T::KY; ++ky) h[kz * T::KY + ky][kx] = col[ky];
+                }
         }
-        if (joint) {
+        if constexpr (T::KZ > 1) {
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky)
 #pragma unroll
-                for (int kx = 0; kx < T::KX; ++kx) h[ky][kx] = imin(h[ky][kx], gmin + clipd);
+                for (int kx = 0; kx < T::KX; ++kx) {
+                    int32_t zl[T::KZ];
+#pragma unroll
+                    for (int kz = 0; kz < T::KZ; ++kz) zl[kz] = h[kz * T::KY + ky][kx];
+                    window_line<1, T::KZ, 1, NWK>(zl, sp.pz, sp.lam, sp.nwz, clipd, !joint, 0, lane);
+#pragma unroll
+                    for (int kz = 0; kz < T::KZ; ++kz) h[kz * T::KY + ky][kx] = zl[kz];
+                }
+        }
+        if (joint) {
+#pragma unroll
+            for (int r = 0; r < T::KR; ++r)
+#pragma unroll
+                for (int kx = 0; kx < T::KX; ++kx) h[r][kx] = imin(h[r][kx], gmin + clipd);
         }
         return gmin;
     }

@@ -34,13 +34,24 @@
     X(17, 2, 4, 2)          \
     X(18, 1, 2, 2)
 
+// Single-wavefront tiles of three-dimensional label spaces: id, PX, KX, PY, KY, KZ.  Lane
+// (px, py) holds the KX x KY labels of the two-dimensional tile at each of the KZ labels
+// vz = 0 .. KZ-1 of the third dimension, so a line along z lies inside one lane.  Ids follow
+// the wide-vertex tiles.
+#define EDP_TILE3_LIST(X)  \
+    X(19, 8, 1, 8, 1, 8)   \
+    X(20, 4, 1, 4, 1, 4)   \
+    X(21, 4, 2, 4, 2, 4)
+
 namespace edp {
 
 constexpr int NUM_TILES = 16;
 constexpr int NUM_MV_TILES = 3;
-constexpr int NUM_ALL_TILES = NUM_TILES + NUM_MV_TILES;
+constexpr int NUM_TILES3 = 3;
+constexpr int FIRST_TILE3 = NUM_TILES + NUM_MV_TILES;
+constexpr int NUM_ALL_TILES = FIRST_TILE3 + NUM_TILES3;
 // A wide-vertex tile holds at most this many scanlines per workgroup times its wavefronts
-// per vertex: 12 wavefronts (768 lanes).
+// per vertex: 8 wavefronts (512 lanes).
 constexpr int MV_MAX_WAVES = 8;
 // compute wavefronts per workgroup of the scan kernel; with its two helper wavefronts a
 // workgroup has at most 8, two per SIMD, so each may use half the register file
@@ -56,7 +67,7 @@ constexpr int MS_WALK = 2;       // general RMS, any window, truncated squared p
 constexpr int MS_WINDOW1 = 3;    // general RMS, windows of one step per side (T <= 2), either prior
 
 struct TileShape {
-    int px, kx, py, ky;
+    int px, kx, py, ky, kz;
 };
 TileShape tile_shape(int tile);
 
@@ -84,6 +95,7 @@ struct InstDesc {
     int32_t* status;              // [1] output status word of the solve (0 or STATUS_TIMEOUT), may be null
     int32_t win, qx_full;         // label-window solve: window side, labels along x of the full space
     int32_t W, H, qx, qy;
+    int32_t qz;                   // labels along the third label dimension (1: none)
     int32_t lam, clipd, joint, trunc;
     int32_t squared;              // 1: truncated squared prior (clipd = lam trunc^2), 0: truncated linear
     int32_t nbands, nsuper;       // wavefront bands, workgroup bands
@@ -206,6 +218,7 @@ struct EnergyArgs {
     unsigned long long* energy;
     unsigned long long* invalid;
     int32_t W, H, qx, qy;
+    int32_t qz;              // labels along the third label dimension (1: none)
     int32_t lam, trunc, joint, grid4;
     int32_t squared;         // truncated squared prior
     const uint32_t* error;   // the solve's error word (nonzero: energy = INT64_MIN), or null

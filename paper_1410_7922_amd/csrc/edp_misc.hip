@@ -6,25 +6,29 @@
 
 namespace edp {
 
-// V(u) of eq. Smooth_value_t with f(a) = |a| (squared false) or a^2 (squared true)
-__device__ __forceinline__ int64_t prior_pair(int32_t a, int32_t b, int32_t qx, int32_t lam,
+// V(u) of eq. Smooth_value_t with f(a) = |a| (squared false) or a^2 (squared true) between flat
+// labels a and b = (vz qy + vy) qx + vx (qxy = qx qy; a two-dimensional space has vz = 0)
+__device__ __forceinline__ int64_t prior_pair(int32_t a, int32_t b, int32_t qx, int32_t qxy, int32_t lam,
                                               int32_t trunc, bool joint, bool squared) {
-    int64_t dx = a % qx - b % qx, dy = a / qx - b / qx;
+    const int32_t ra = a % qxy, rb = b % qxy;
+    int64_t dx = ra % qx - rb % qx, dy = ra / qx - rb / qx, dz = a / qxy - b / qxy;
     dx = dx < 0 ? -dx : dx;
     dy = dy < 0 ? -dy : dy;
+    dz = dz < 0 ? -dz : dz;
     int64_t ft = trunc;
     if (squared) {
         dx *= dx;
         dy *= dy;
+        dz *= dz;
         ft *= ft;
     }
-    if (joint) return (int64_t)lam * (dx + dy < ft ? dx + dy : ft);
-    return (int64_t)lam * ((dx < ft ? dx : ft) + (dy < ft ? dy : ft));
+    if (joint) return (int64_t)lam * (dx + dy + dz < ft ? dx + dy + dz : ft);
+    return (int64_t)lam * ((dx < ft ? dx : ft) + (dy < ft ? dy : ft) + (dz < ft ? dz : ft));
 }
 
 template <class CT>
 __global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
-    const int32_t W = a.W, H = a.H, Q = a.qx * a.qy;
+    const int32_t W = a.W, H = a.H, QXY = a.qx * a.qy, Q = QXY * a.qz;
     const CT* __restrict__ cost = (const CT*)a.cost;
     const bool joint = a.joint != 0;
     int64_t acc = 0;
@@ -38,11 +42,11 @@ __global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
         acc += (int64_t)cost[idx * Q + lab];
         if (x + 1 < W) {
             const int32_t r = a.labels[idx + 1];
-            if (r >= 0 && r < Q) acc += prior_pair(lab, r, a.qx, a.lam, a.trunc, joint, a.squared != 0);
+            if (r >= 0 && r < Q) acc += prior_pair(lab, r, a.qx, QXY, a.lam, a.trunc, joint, a.squared != 0);
         }
         if (a.grid4 && y + 1 < H) {
             const int32_t d = a.labels[idx + W];
-            if (d >= 0 && d < Q) acc += prior_pair(lab, d, a.qx, a.lam, a.trunc, joint, a.squared != 0);
+            if (d >= 0 && d < Q) acc += prior_pair(lab, d, a.qx, QXY, a.lam, a.trunc, joint, a.squared != 0);
         }
     }
     __shared__ int64_t sacc[256];
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
 template <class CT>
 __global__ __launch_bounds__(256) void batch_energy_kernel(const BatchEnergyArgs a) {
     const InstDesc d = uniform_desc(a.descs[find_instance(a.descs, a.ndesc, (int32_t)blockIdx.x, 2)]);
-    const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
+    const int32_t W = d.W, H = d.H, QXY = d.qx * d.qy, Q = QXY * d.qz;
     const CT* __restrict__ cost = (const CT*)d.cost;
     const bool joint = d.joint != 0;
     const int32_t y0 = ((int32_t)blockIdx.x - d.first_eblock) * a.rows_per_block;
@@ -87,11 +91,11 @@ __global__ __launch_bounds__(256) void batch_energy_kernel(const BatchEnergyArgs
             acc += (int64_t)cost[idx * Q + lab];
             if (x + 1 < W) {
                 const int32_t r = d.labels[idx + 1];
-                if (r >= 0 && r < Q) acc += prior_pair(lab, r, d.qx, d.lam, d.trunc, joint, d.squared != 0);
+                if (r >= 0 && r < Q) acc += prior_pair(lab, r, d.qx, QXY, d.lam, d.trunc, joint, d.squared != 0);
             }
             if (y + 1 < H) {
                 const int32_t v = d.labels[idx + W];
-                if (v >= 0 && v < Q) acc += prior_pair(lab, v, d.qx, d.lam, d.trunc, joint, d.squared != 0);
+                if (v >= 0 && v < Q) acc += prior_pair(lab, v, d.qx, QXY, d.lam, d.trunc, joint, d.squared != 0);
             }
         }
     }

@@ -32,6 +32,9 @@ hipError_t launch_edp_pass(int tile, int dtype, int split, int ms, const PassArg
                : ms == MS_WINDOW  ? pass_tile<id, MS_WINDOW>(dtype, split, a, grid, waves, s)      \
                                    : pass_tile<id, MS_LINEAR>(dtype, split, a, grid, waves, s);
         EDP_TILE_LIST(EDP_CASE)
+#define EDP_CASE3(id, px, kx, py, ky, kz) EDP_CASE(id, px, kx, py, ky)
+        EDP_TILE3_LIST(EDP_CASE3)
+#undef EDP_CASE3
 #undef EDP_CASE
     }
     return hipErrorInvalidValue;
@@ -45,6 +48,9 @@ hipError_t launch_edp_aggregate(int tile, int dtype, const AggArgs& a, int grid,
     case id:                         \
         return aggregate_tile<id>(dtype, a, grid, s);
         EDP_TILE_LIST(EDP_CASE)
+#define EDP_CASE3(id, px, kx, py, ky, kz) EDP_CASE(id, px, kx, py, ky)
+        EDP_TILE3_LIST(EDP_CASE3)
+#undef EDP_CASE3
 #undef EDP_CASE
     }
     return hipErrorInvalidValue;
@@ -65,6 +71,9 @@ int pass_capacity(int tile, int dtype, int split, int ms, int waves, size_t lds_
                                      : occupancy_tile<id, MS_LINEAR>(dtype, split, waves, lds_bytes);  \
         break;
         EDP_TILE_LIST(EDP_CASE)
+#define EDP_CASE3(id, px, kx, py, ky, kz) EDP_CASE(id, px, kx, py, ky)
+        EDP_TILE3_LIST(EDP_CASE3)
+#undef EDP_CASE3
 #undef EDP_CASE
     }
     int dev = 0, cus = 1;

@@ -91,7 +91,7 @@ __device__ __forceinline__ void tag_put(unsigned long long* p, unsigned long lon
 // they never wait for memory operations other than their own prefetched loads.
 template <class T, class CK, int SPLIT, int PF, bool WIN = false, int MS = MS_LINEAR>
 __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const PassArgs a) {
-    constexpr int G = T::G, KX = T::KX, KY = T::KY, E = T::E, QT = T::QT;
+    constexpr int G = T::G, KX = T::KX, KR = T::KR, E = T::E, QT = T::QT;
     constexpr int CL = SPLIT * G;                  // lanes per vertex
     constexpr int RPW = 64 / CL;                   // scanlines per wavefront
     constexpr int CB = CostBytes<CK>::value;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
         const int32_t pass_index = second ? a.dir[1].pass_index : a.dir[0].pass_index;
         const InstDesc d = a.ndesc > 0 ? uniform_desc(a.descs[find_instance(a.descs, a.ndesc, rem, 0)]) : a.one;
         const int32_t super = rem - d.first_ticket;
-        const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
+        const int32_t W = d.W, H = d.H, Q = d.qx * d.qy * d.qz;
         uint32_t* const progress = d.flags + (second ? d.nsuper : 0);
         uint32_t* const done = d.flags + 2 * d.nsuper;
         const uint32_t epoch = (uint32_t)pass_index * (uint32_t)(W + 1);
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             const int32_t band = super * NW + wave;
             const bool joint = d.joint != 0;
             const LineIndex<T> li(d.lam, lane);
-            const WinPen sp(d.lam, d.trunc, d.qx, d.qy, d.squared != 0);   // general RMS window
+            const WinPen sp(d.lam, d.trunc, d.qx, d.qy, d.squared != 0, d.qz);   // general RMS window
             const __amdgpu_buffer_rsrc_t rs_c = make_rsrc(d.cost, W * H * Q * CB);
             int32_t* const t_a = ka ? d.t[1] : d.t[0];
             int32_t* const t_ma = ka ? d.t[0] : d.t[1];
@@ -364,19 +364,20 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             const __amdgpu_buffer_rsrc_t rs_ma = make_rsrc(t_ma, old_a_zero ? 0 : tbytes);
             const __amdgpu_buffer_rsrc_t rs_mb = make_rsrc(t_mb, old_b_zero ? 0 : tbytes);
             const __amdgpu_buffer_rsrc_t rs_bo = make_rsrc(t_b, b_live ? tbytes : 0);
-            int32_t crun[KY];                              // cost byte offset of the lane's run of KX labels
-            bool valid[KY][KX];
+            int32_t crun[KR];                              // cost byte offset of the lane's run of KX labels
+            bool valid[KR][KX];
 #pragma unroll
-            for (int ky = 0; ky < KY; ++ky) {
-                const int32_t vy = py * KY + ky;
-                crun[ky] = (vy < d.qy && px * KX < d.qx) ? (vy * d.qx + px * KX) * CB : OOB;
+            for (int r = 0; r < KR; ++r) {                 // row r: vz = r / KY, vy = py KY + r % KY
+                const int32_t vy = py * T::KY + r % T::KY, vz = r / T::KY;
+                const bool rin = vy < d.qy && vz < d.qz;
+                crun[r] = (rin && px * KX < d.qx) ? ((vz * d.qy + vy) * d.qx + px * KX) * CB : OOB;
 #pragma unroll
-                for (int kx = 0; kx < KX; ++kx) valid[ky][kx] = px * KX + kx < d.qx && vy < d.qy;
+                for (int kx = 0; kx < KX; ++kx) valid[r][kx] = px * KX + kx < d.qx && rin;
             }
             const int32_t j = band * RPW + grp;            // scan-order row index
             // a lane whose labels are all padding neither loads nor stores sums: its values are
             // replaced by PADV before every use
-            const bool rowok = j < H && px * KX < d.qx && py * KY < d.qy;
+            const bool rowok = j < H && px * KX < d.qx && py * T::KY < d.qy;
             const int32_t y = sy > 0 ? j : H - 1 - j;
             const int32_t yn = y + sy;                     // next row in scan order
             const bool has_next = j + 1 < H;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             // window solve: frame-shift codes of the vertex (8 bytes per vertex)
             const int32_t bsh = cell_off(y * W + x0, 8), dsh = sx * 8;
             const __amdgpu_buffer_rsrc_t rs_sh = make_rsrc(d.aux, WIN ? W * H * 8 : 0);
-            int32_t* const wscr = rings + (size_t)(NW + 1) * R * QT + (size_t)wave * 2 * 64 * (KX > KY ? KX : KY);
+            int32_t* const wscr = rings + (size_t)(NW + 1) * R * QT + (size_t)wave * 2 * 64 * (KX > KR ? KX : KR);
             // steps rounded up to whole prefetch rounds: the extra steps touch nothing (every lane
             // is past the end of its row), and a fixed count of loads per step lets the compiler
             // wait for exactly the slot in use instead of for every load in flight
@@ -405,19 +406,19 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             int32_t taken = 0;                             // columns the next wavefront has taken (lower bound)
 
             constexpr int CW = CostWords<CK, KX>::value;
-            int32_t rc[PF][KY][CW], rma[PF][KY][KX], rmb[PF][KY][KX];
+            int32_t rc[PF][KR][CW], rma[PF][KR][KX], rmb[PF][KR][KX];
             int32_t rsh[PF][WIN ? 2 : 1];
-            int32_t carry[KY][KX], out[KY][KX];
+            int32_t carry[KR][KX], out[KR][KX];
 #pragma unroll
-            for (int ky = 0; ky < KY; ++ky)
+            for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
                 for (int kx = 0; kx < KX; ++kx) carry[ky][kx] = out[ky][kx] = 0;
 
             // Issue the loads of step t into one ring slot (no branch around a load).
             // STEADY: every scanline of the wavefront is strictly inside its row at column t
             // (0 < t - grp < W - 1), which the caller knows for a whole round of steps
-            auto fetch = [&](auto steady, const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX],
-                             int32_t (&mb)[KY][KX], int32_t (&sh)[WIN ? 2 : 1]) {
+            auto fetch = [&](auto steady, const int32_t t, int32_t (&c)[KR][CW], int32_t (&ma)[KR][KX],
+                             int32_t (&mb)[KR][KX], int32_t (&sh)[WIN ? 2 : 1]) {
                 constexpr bool STEADY = decltype(steady)::value;
                 // column i = t - grp of this lane's scanline; offsets move by a fixed stride per step
                 const uint32_t i = (uint32_t)(t - grp);
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                 const int32_t offa = (act && nxt) ? ba + t * dt : OOB;
                 const int32_t offb = (act && has_next) ? bb + t * dt : OOB;
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, offc + crun[ky], c[ky]);
+                for (int ky = 0; ky < KR; ++ky) load_cost_words<CK, KX>(rs_c, offc + crun[ky], c[ky]);
                 load_vec<E>(rs_ma, offa, &ma[0][0]);
                 load_vec<E>(rs_mb, offb, &mb[0][0]);
                 if constexpr (WIN) load_vec<2>(rs_sh, act ? bsh + t * dsh : OOB, sh);
@@ -440,13 +441,13 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
             // before its count, so when the count shows column t the slot read issued after it
             // returns that column.  Column t + 1 is read at the end of step t, which keeps the
             // LDS round trip off the step when the producer is ahead.
-            int32_t in_ready = 0, in_lb[KY][KX];
+            int32_t in_ready = 0, in_lb[KR][KX];
             auto read_input = [&](const int32_t t) {
                 const int32_t* slot = ring_in + (size_t)(t & (R - 1)) * QT;
                 in_ready = lds_get(wr + wave);
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky)
+                for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx)
                         in_lb[ky][kx] = slot[(ky * KX + kx) * G];
@@ -458,9 +459,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                 const int32_t i = s - grp;
                 const bool act = STEADY ? rowok : rowok && (uint32_t)i < (uint32_t)W;
                 // T_b of the row above at this column, for group 0
-                int32_t lb[KY][KX];
+                int32_t lb[KR][KX];
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky)
+                for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = 0;
                 if (STEADY || s < W) {                       // wave-uniform
@@ -474,7 +475,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                         read_input(s);
                     }
 #pragma unroll
-                    for (int ky = 0; ky < KY; ++ky)
+                    for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
                         for (int kx = 0; kx < KX; ++kx) lb[ky][kx] = in_lb[ky][kx];
                     // LDS operations of a wavefront complete in order: the slot is read
@@ -482,9 +483,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
                     lds_put(rd + wave, s + 1);
                 }
-                int32_t h[KY][KX], h2[KY][KX];
+                int32_t h[KR][KX], h2[KR][KX];
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky)
+                for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx) {
                         const int32_t v = out[ky][kx];
@@ -535,9 +536,9 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                 const int32_t o = bt + s * dt;
                 const int32_t oa = (act && store_a) ? o : OOB;
                 const int32_t ob = (act && store_b) ? o : OOB;
-                int32_t tbv[KY][KX];
+                int32_t tbv[KR][KX];
 #pragma unroll
-                for (int ky = 0; ky < KY; ++ky)
+                for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
                     for (int kx = 0; kx < KX; ++kx) {
                         tbv[ky][kx] = SPLIT == 1 ? h2[ky][kx] : h[ky][kx];
@@ -563,7 +564,7 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
                     }
                     int32_t* dst = hands ? ring_out + (size_t)(il & (R - 1)) * QT : trash + l;
 #pragma unroll
-                    for (int ky = 0; ky < KY; ++ky)
+                    for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
                         for (int kx = 0; kx < KX; ++kx) dst[(ky * KX + kx) * G] = out[ky][kx];
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -626,14 +627,14 @@ __global__ __launch_bounds__(64 * (MAX_WAVES + 2)) void edp_pass_kernel(const Pa
 // solve; only the win x win window counts, and the label is read through the centre.
 template <class T, class CT, bool WIN = false>
 __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
-    constexpr int G = T::G, KX = T::KX, KY = T::KY, QT = T::QT;
+    constexpr int G = T::G, KX = T::KX, KR = T::KR, QT = T::QT;
     constexpr int RPW = 64 / G;
     const int32_t lane = lane_id();
     const int32_t grp = lane / G, l = lane % G;
     const int32_t px = l % T::PX, py = l / T::PX;
     const int32_t blk = (int32_t)blockIdx.x;
     const InstDesc d = a.ndesc > 0 ? uniform_desc(a.descs[find_instance(a.descs, a.ndesc, blk, 1)]) : a.one;
-    const int32_t W = d.W, H = d.H, Q = d.qx * d.qy;
+    const int32_t W = d.W, H = d.H, Q = d.qx * d.qy * d.qz;
     const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
     const int32_t cells = W * H;
     // the scans ran before this launch on the same stream: their error word is final
@@ -653,20 +654,21 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     // its costs are KX-runs; a missing neighbour reads as 0 (out-of-range buffer offset)
     const int32_t tbytes = W * H * QT * 4;
     const int32_t lofs = l * T::E * 4;
-    int32_t acc[KY][KX], tv[KY][KX];
+    int32_t acc[KR][KX], tv[KR][KX];
 #pragma unroll
-    for (int ky = 0; ky < KY; ++ky) {
-        const int32_t vy = py * KY + ky;
-        const int32_t crun = (ok && vy < d.qy && px * KX < d.qx) ? (cell * Q + vy * d.qx + px * KX) * (int32_t)sizeof(CT)
-                                                                 : OOB;
+    for (int r = 0; r < KR; ++r) {                 // row r: vz = r / KY, vy = py KY + r % KY
+        const int32_t vy = py * T::KY + r % T::KY, vz = r / T::KY;
+        const int32_t crun = (ok && vy < d.qy && vz < d.qz && px * KX < d.qx)
+                                 ? (cell * Q + (vz * d.qy + vy) * d.qx + px * KX) * (int32_t)sizeof(CT)
+                                 : OOB;
         int32_t cw[KX];
         load_cost_words<CT, KX>(make_rsrc(d.cost, cells * Q * (int32_t)sizeof(CT)), crun, cw);
 #pragma unroll
-        for (int kx = 0; kx < KX; ++kx) acc[ky][kx] = cw[kx];
+        for (int kx = 0; kx < KX; ++kx) acc[r][kx] = cw[kx];
     }
     // lanes whose labels are all padding (or, in a window solve, all outside the window) read
     // no sums: their values never reach the argmin
-    const bool live = WIN ? (px * KX < d.win && py * KY < d.win) : (px * KX < d.qx && py * KY < d.qy);
+    const bool live = WIN ? (px * KX < d.win && py * T::KY < d.win) : (px * KX < d.qx && py * T::KY < d.qy);
     const bool rd = ok && live;
     const int32_t nb[4] = {rd && x > 0 ? cell - 1 : -1, rd && x + 1 < W ? cell + 1 : -1,
                            rd && y > 0 ? cell - W : -1, rd && y + 1 < H ? cell + W : -1};
@@ -674,19 +676,19 @@ __global__ __launch_bounds__(256) void edp_aggregate_kernel(const AggArgs a) {
     for (int k = 0; k < 4; ++k) {
         load_vec<T::E>(make_rsrc(d.t[k], tbytes), nb[k] >= 0 ? nb[k] * QT * 4 + lofs : OOB, &tv[0][0]);
 #pragma unroll
-        for (int ky = 0; ky < KY; ++ky)
+        for (int ky = 0; ky < KR; ++ky)
 #pragma unroll
             for (int kx = 0; kx < KX; ++kx) acc[ky][kx] += tv[ky][kx];
     }
     int32_t best = 0x7FFFFFFF, bq = 0x7FFFFFFF;
 #pragma unroll
-    for (int ky = 0; ky < KY; ++ky)
+    for (int r = 0; r < KR; ++r)
 #pragma unroll
         for (int kx = 0; kx < KX; ++kx) {
-            const int32_t vy = py * KY + ky, vx = px * KX + kx;
-            const bool in = WIN ? (vx < d.win && vy < d.win) : (vx < d.qx && vy < d.qy);
-            const int32_t lab = WIN ? (oy + vy) * d.qx_full + (ox + vx) : vy * d.qx + vx;
-            const int32_t v = acc[ky][kx];
+            const int32_t vy = py * T::KY + r % T::KY, vz = r / T::KY, vx = px * KX + kx;
+            const bool in = WIN ? (vx < d.win && vy < d.win) : (vx < d.qx && vy < d.qy && vz < d.qz);
+            const int32_t lab = WIN ? (oy + vy) * d.qx_full + (ox + vx) : (vz * d.qy + vy) * d.qx + vx;
+            const int32_t v = acc[r][kx];
             if (ok && in && (v < best || (v == best && lab < bq))) {
                 best = v;
                 bq = lab;
@@ -777,6 +779,10 @@ template <int ID> struct TileOf;
     template <> struct TileOf<id> { using type = Tile<px, kx, py, ky>; };
 EDP_TILE_LIST(EDP_TILE_OF)
 #undef EDP_TILE_OF
+#define EDP_TILE3_OF(id, px, kx, py, ky, kz) \
+    template <> struct TileOf<id> { using type = Tile<px, kx, py, ky, kz>; };
+EDP_TILE3_LIST(EDP_TILE3_OF)
+#undef EDP_TILE3_OF
 
 // MS: the minimum search (MS_LINEAR, MS_WINDOW, MS_WALK)
 template <int ID, int MS>

@@ -35,7 +35,7 @@ def test_status_strings():
 
 def _prob(**kw):
     d = dict(width=384, height=288, qx=32, qy=1, dtype=1, trunc_mode=0, lam=20, trunc=2, iterations=1,
-             cost_bound=50, prior=0)
+             cost_bound=50, prior=0, qz=1)
     d.update(kw)
     return B.Problem(*[d[f] for f, _ in B.Problem._fields_])
 
@@ -50,7 +50,7 @@ def _ws(prob, op, tile=-1):
 @pytest.mark.parametrize("field,value", [("width", 0), ("height", -1), ("qx", 0), ("qy", 0), ("dtype", 3),
                                          ("trunc_mode", 2), ("lam", -1), ("lam", 70000), ("trunc", 0),
                                          ("iterations", 0), ("cost_bound", -5), ("qx", 4097), ("prior", 2),
-                                         ("prior", -1)])
+                                         ("prior", -1), ("qz", -1), ("qz", 129)])
 def test_invalid_problems_rejected(field, value):
     st, _ = _ws(_prob(**{field: value}), B.OP_EDP)
     assert st == -1
@@ -232,3 +232,29 @@ def test_static_workspace_solve_refuses_problems_beyond_its_array():
     assert lib.edp_solve_static(None, None, fake, fake, None, None, None) == -1
     bad = _prob(trunc=0)
     assert lib.edp_solve_static(ctypes.byref(bad), None, fake, fake, None, None, None) == -1
+
+
+def test_three_label_dimensions_on_the_host():
+    """qz > 1: the EDP solve takes 3D label spaces on the tiles of edp_tiles_3d (z inside a lane);
+    the DP calls and the label-window solve refuse them; qz = 0 means one or two dimensions."""
+    assert B.tiles_3d(7, 7, 7) == [19]
+    assert B.tiles_3d(4, 4, 4) == [19, 20, 21] and B.tiles_3d(8, 8, 4) == [19, 21]
+    assert B.tiles_3d(9, 2, 2) == [] and B.tiles_3d(2, 2, 9) == []
+    assert B.tile_info(19) == (8, 1, 8, 1) and B.tile_depth(19) == 8
+    assert B.tile_depth(21) == 4 and B.tile_depth(16) == 1 and B.tile_depth(0) == 1
+    p3 = dict(qx=7, qy=7, qz=7, dtype=2, cost_bound=2500, lam=40, trunc=3)
+    st, n = _ws(_prob(**p3), B.OP_EDP)
+    assert st == 0 and n >= 4 * 384 * 288 * 512 * 4
+    assert _ws(_prob(**p3), B.OP_EDP, 19)[0] == 0
+    assert _ws(_prob(**p3), B.OP_EDP, 21)[0] == -1        # 8 x 8 x 4 labels: qz = 7 does not fit
+    assert _ws(_prob(**p3), B.OP_EDP, 13)[0] == -1        # a two-dimensional tile
+    assert _ws(_prob(**p3), B.OP_EDP, 16)[0] == -1        # a wide tile
+    assert _ws(_prob(**p3), B.OP_DP)[0] == -5
+    assert _ws(_prob(**p3), 2)[0] == -5
+    assert _ws(_prob(qx=9, qy=9, qz=5, dtype=2, cost_bound=2500), B.OP_EDP)[0] == -5   # no tile holds 9 x 9 x 5
+    assert _ws(_prob(qx=16, qy=16, qz=17), B.OP_EDP)[0] == -1                          # 4352 labels
+    # qz = 0 and qz = 1 are the same problem
+    assert _ws(_prob(qz=0), B.OP_EDP) == _ws(_prob(qz=1), B.OP_EDP)
+    n = ctypes.c_size_t(0)
+    pw = _prob(prior=0, dtype=2, qx=15, qy=15, lam=15, trunc=3, cost_bound=2500, qz=2)
+    assert B.load().edp_window_workspace_size(ctypes.byref(pw), 7, None, ctypes.byref(n)) == -5
