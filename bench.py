@@ -124,7 +124,7 @@ def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1, fuse=0
     nlaunch = (4 if fuse == 1 else 2) * iterations     # scan launches per solve
     ev = HipEvents(2 * nlaunch * steps)
     kw = dict(mode=prob.mode, iterations=iterations, cost_bound=bound, tile=tile, chunk=chunk, ws=ws,
-              labels=labels, energy=energy, fuse=fuse, prior=prob.prior, status=status, check=False)
+              labels=labels, energy=energy, fuse=fuse, prior=prob.prior, status=status, check=False, qz=prob.qz)
     for _ in range(warmup):
         edp.solve(cost, prob.qx, prob.qy, prob.lam, prob.trunc, **kw)
     torch.cuda.synchronize()
@@ -502,6 +502,26 @@ def cpu_baseline(prob, rows=None, budget_s=10.0):
                       f"plain EDP j=1, x{reps} ({dt:.2f} s each); {os.cpu_count()} host cores available"}, ref
 
 
+def bench_r3(edp, torch, steps, warmup):
+    """EDP over a three-dimensional label space: the 640 x 480 motion-with-brightness-offset
+    workload, 7 x 7 motion labels and 7 offset levels (343 labels, padded to 8 x 8 x 8 in the
+    lanes of tile 19), lambda 40, T 3 per dimension, j = 1."""
+    import numpy as np
+    import synth
+    prob = synth.workload("motion_offset640x480")
+    H, W, Q = prob.cost.shape
+    pl = H * W * Q
+    r = bench_edp(edp, torch, prob, steps, warmup, -1, 0)
+    roof = scan_roofline(prob, r, "edp_pass_motionoffset640x480q343", kernel="edp_pass_kernel, tile 19 (8x8x8)")
+    return {"workload": "plain EDP, motion with a brightness offset 640x480, 7x7x7 labels (dx, dy in [-3, 3], "
+                        "7 offset levels of 6 grey levels), int32 truncated squared-difference costs (cmax 2500), "
+                        "lambda 40, T 3 per dimension, j=1",
+            "data": "synthetic (seeded frame pair with 8 affine-motion segments, per-segment brightness offset)",
+            "pixel_labels_per_s": pl / (r["ms_per_step"] / 1e3), "ms_per_step": r["ms_per_step"],
+            "energy": r["energy"], "labels": Q, "padded_labels": 512, "roofline": roof,
+            "labels_sha256": hashlib.sha256(np.ascontiguousarray(r["labels"], np.int32).tobytes()).hexdigest()}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +536,8 @@ def main():
     ap.add_argument("--refine", type=int, default=0, help="window refinement rounds of the learned path")
     ap.add_argument("--window-study", type=int, default=0, metavar="N",
                     help="only the window-size study of the learned path on N instances")
+    ap.add_argument("--r3-only", action="store_true",
+                    help="only the EDP solve over three label dimensions (640x480, 7x7x7 labels)")
     ap.add_argument("--dp-only", action="store_true",
                     help="run only the scanline DP sweep (for hardware-counter profiles of its kernels)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -555,6 +577,15 @@ def main():
         print(json.dumps({"metric": "energy gap of the label-window EDP over plain EDP", "value": None,
                           "unit": "fraction", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
                           "config": {"workload": r["workload"]}, "window_study": r}), flush=True)
+        return
+    if args.r3_only:
+        r3 = bench_r3(edp, torch, args.steps, args.warmup)
+        print(json.dumps({"metric": "pixel-labels/sec (EDP, three label dimensions)", "value": r3["pixel_labels_per_s"],
+                          "unit": "pixel-labels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": r3["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "int32", "data": r3["data"],
+                          "config": {"workload": r3["workload"]}, "roofline": r3["roofline"],
+                          "r3": r3}), flush=True)
         return
     if args.dp_only:
         r = bench_dp(edp, torch, args.steps, args.warmup)
@@ -639,6 +670,8 @@ def main():
         extra["paper_shapes"] = bench_paper_shapes(edp, torch, max(3, args.steps // 4), 1)
         log("energy against the number of EDP iterations (motion 640x480, 961 labels)")
         extra["energy_vs_iterations"] = bench_iterations(edp, torch, prob)
+        log("three label dimensions: motion with a brightness offset 640x480, 7x7x7 labels")
+        extra["motion_offset640x480"] = bench_r3(edp, torch, max(3, args.steps // 4), 1)
     if not args.no_batch:
         log("batch of 64 uneven instances (hipGraph replay)")
         extra["batch64"] = bench_batch(edp, torch, max(3, args.steps // 4), 1)
