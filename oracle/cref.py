@@ -40,6 +40,10 @@ def lib():
         L.oracle_edp_window.argtypes = [i32] * 10 + [i32p, i32p, i32, i32p, i64p, i64p]
         L.oracle_min_search.restype = ctypes.c_int
         L.oracle_min_search.argtypes = [i32] * 9 + [i64p, i64p, i32p]
+        L.oracle_energy_volume.restype = ctypes.c_int64
+        L.oracle_energy_volume.argtypes = [i32] * 9 + [i32p, i32p]
+        L.oracle_edp_volume.restype = ctypes.c_int
+        L.oracle_edp_volume.argtypes = [i32] * 11 + [i32p, i32p, i64p, i64p, i64p]
         _lib = L
     return _lib
 
@@ -131,3 +135,33 @@ def edp_window(cost, centers, win, qx, qy, lam, trunc, mode, iterations=1, searc
     if rc != 0:
         raise RuntimeError(f"oracle_edp_window failed: {rc}")
     return {"labels": labels, "energy": int(e[0]), "max_abs_sum": int(mx[0])}
+
+
+def energy_volume(cost, labels, qx, qy, lam, trunc, mode, prior: int = 0) -> int:
+    """6-connected energy of labels [Z][H][W] on cost [Z][H][W][Q]."""
+    c = _cost32(cost)
+    Z, H, W, _ = c.shape
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    return int(lib().oracle_energy_volume(W, H, Z, qx, qy, lam, trunc, mode, prior, _p32(c), _p32(lab)))
+
+
+def edp_volume(cost, qx, qy, lam, trunc, mode, iterations=1, search: str = "lrms", marginal=False, prior: int = 0):
+    """EDP on a volume cost [Z][H][W][Q] (D = 3).  Returns dict(labels int32 [Z][H][W], energy,
+    max_abs_sum, marginal (optional int64 [Z][H][W][Q]))."""
+    c = _cost32(cost)
+    Z, H, W, Q = c.shape
+    labels = np.zeros((Z, H, W), np.int32)
+    e = np.zeros(1, np.int64)
+    mx = np.zeros(1, np.int64)
+    marg = np.zeros((Z, H, W, Q), np.int64) if marginal else None
+    rc = lib().oracle_edp_volume(W, H, Z, qx, qy, lam, trunc, mode, prior, iterations, SEARCH[search], _p32(c),
+                                 _p32(labels), _p64(e), _p64(mx),
+                                 _p64(marg) if marginal else ctypes.POINTER(ctypes.c_int64)())
+    if rc == -2:
+        raise OverflowError("EDP sum exceeds int32")
+    if rc != 0:
+        raise RuntimeError(f"oracle_edp_volume failed: {rc}")
+    out = {"labels": labels, "energy": int(e[0]), "max_abs_sum": int(mx[0])}
+    if marginal:
+        out["marginal"] = marg
+    return out

@@ -26,6 +26,10 @@
  *            scans P1..P4 in place, eq. DP_2D_1 marginal, eq. DP_2D_2 argmin.
  *   windowed EDP: the same on a cost volume masked by a sentinel outside a
  *            per-vertex label box (the definition of the label-window solve).
+ *   volume EDP (D = 3): eq. DP_2D_base and eq. DP_2D_1 in their general form,
+ *            K = {+-x, +-y, +-z}, S/3 as floor division, the eight raster scans
+ *            of a volume (x innermost; x order alternating fastest, then y,
+ *            then z), 6-connected energy.
  *
  * All sums are computed and stored in int64 and range-checked against int32
  * (the check's failure is reported, never wrapped).  Single threaded.
@@ -403,4 +407,124 @@ int oracle_min_search(int qx, int qy, int qz, int lam, int trunc, int mode, int 
     }
     free(scratch);
     return OR_OK;
+}
+
+/* ---- EDP on a volume (D = 3) ---------------------------------------------- */
+
+static int64_t floor_div3(int64_t s) { return s >= 0 ? s / 3 : -((-s + 2) / 3); }
+
+/* Energy of eq. GE_objective_function on a 6-connected volume cost[Z][H][W][Q]. */
+int64_t oracle_energy_volume(int W, int H, int Z, int qx, int qy, int lam, int trunc, int mode, int prior,
+                             const int32_t *cost, const int32_t *labels) {
+    prior_t p = make_prior(qx, qy, 1, lam, trunc, mode, prior);
+    int64_t e = 0;
+    for (int z = 0; z < Z; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                size_t i = ((size_t)z * H + y) * W + x;
+                int l = labels[i];
+                e += cost[i * p.q + l];
+                if (x + 1 < W) e += prior_v(&p, labels[i + 1], l);
+                if (y + 1 < H) e += prior_v(&p, labels[i + W], l);
+                if (z + 1 < Z) e += prior_v(&p, labels[i + (size_t)W * H], l);
+            }
+    return e;
+}
+
+/* direction k: 0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z; predecessor x_k = x - sgn(k) e_|k| */
+static const int VDX[6] = {1, -1, 0, 0, 0, 0};
+static const int VDY[6] = {0, 0, 1, -1, 0, 0};
+static const int VDZ[6] = {0, 0, 0, 0, 1, -1};
+static const int VOPP[6] = {1, 0, 3, 2, 5, 4};
+
+/* Literal EDP on a volume: labels [Z][H][W]; marginal_out [Z][H][W][Q] int64 (nullable). */
+int oracle_edp_volume(int W, int H, int Z, int qx, int qy, int lam, int trunc, int mode, int prior,
+                      int iterations, int search, const int32_t *cost, int32_t *labels, int64_t *energy_out,
+                      int64_t *max_abs_out, int64_t *marginal_out) {
+    if (Z < 1 || !check_args(W, H, qx, qy, 1, lam, trunc, mode, prior, search) || iterations < 0) return OR_E_ARGS;
+    prior_t p = make_prior(qx, qy, 1, lam, trunc, mode, prior);
+    int Q = p.q;
+    size_t cells = (size_t)W * H * Z;
+    int64_t *S = calloc((size_t)6 * cells * Q, sizeof(int64_t));
+    int64_t *h = malloc(sizeof(int64_t) * Q);
+    int64_t *m = malloc(sizeof(int64_t) * 6 * Q);
+    int64_t *acc = malloc(sizeof(int64_t) * Q);
+    int64_t *scratch = malloc(sizeof(int64_t) * 8192);
+    int64_t *nw = malloc(sizeof(int64_t) * 3 * Q);
+    if (!S || !h || !m || !acc || !scratch || !nw) {
+        free(S); free(h); free(m); free(acc); free(scratch); free(nw);
+        return OR_E_NOMEM;
+    }
+    int64_t maxabs = 0;
+    int status = OR_OK;
+    for (int it = 0; it < iterations; ++it) {
+        for (int scan = 0; scan < 8; ++scan) {
+            const int sx = (scan & 1) ? -1 : 1, sy = (scan & 2) ? -1 : 1, sz = (scan & 4) ? -1 : 1;
+            const int comp[3] = {sx > 0 ? 0 : 1, sy > 0 ? 2 : 3, sz > 0 ? 4 : 5};
+            for (int zi = 0; zi < Z; ++zi) {
+                int z = sz > 0 ? zi : Z - 1 - zi;
+                for (int yi = 0; yi < H; ++yi) {
+                    int y = sy > 0 ? yi : H - 1 - yi;
+                    for (int xi = 0; xi < W; ++xi) {
+                        int x = sx > 0 ? xi : W - 1 - xi;
+                        for (int k = 0; k < 6; ++k) {   /* m_k = M(S_k(x_k) / 3), 0 off the grid */
+                            int px = x - VDX[k], py = y - VDY[k], pz = z - VDZ[k];
+                            int64_t *mk = m + (size_t)k * Q;
+                            if (px < 0 || px >= W || py < 0 || py >= H || pz < 0 || pz >= Z) {
+                                for (int v = 0; v < Q; ++v) mk[v] = 0;
+                                continue;
+                            }
+                            const int64_t *sk = S + ((size_t)k * cells + ((size_t)pz * H + py) * W + px) * Q;
+                            for (int v = 0; v < Q; ++v) h[v] = floor_div3(sk[v]);
+                            msearch(&p, search, h, mk, scratch);
+                        }
+                        size_t cell = ((size_t)z * H + y) * W + x;
+                        const int32_t *c = cost + cell * Q;
+                        for (int j = 0; j < 3; ++j) {   /* eq. DP_2D_base with C added */
+                            int kp = comp[j];
+                            for (int v = 0; v < Q; ++v) {
+                                int64_t s = c[v];
+                                for (int k = 0; k < 6; ++k)
+                                    if (k != VOPP[kp]) s += m[(size_t)k * Q + v];
+                                s -= m[(size_t)VOPP[kp] * Q + v];
+                                nw[(size_t)j * Q + v] = s;
+                            }
+                        }
+                        for (int j = 0; j < 3; ++j) {
+                            int64_t *dst = S + ((size_t)comp[j] * cells + cell) * Q;
+                            for (int v = 0; v < Q; ++v) {
+                                int64_t s = nw[(size_t)j * Q + v];
+                                if (iabs64(s) > maxabs) maxabs = iabs64(s);
+                                if (s > INT32_MAX || s < INT32_MIN) status = OR_E_RANGE;
+                                dst[v] = s;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int z = 0; z < Z; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {               /* eq. DP_2D_1 with C, eq. DP_2D_2 */
+                size_t cell = ((size_t)z * H + y) * W + x;
+                const int32_t *c = cost + cell * Q;
+                for (int v = 0; v < Q; ++v) acc[v] = c[v];
+                for (int k = 0; k < 6; ++k) {
+                    int px = x - VDX[k], py = y - VDY[k], pz = z - VDZ[k];
+                    if (px < 0 || px >= W || py < 0 || py >= H || pz < 0 || pz >= Z) continue;
+                    const int64_t *sk = S + ((size_t)k * cells + ((size_t)pz * H + py) * W + px) * Q;
+                    for (int v = 0; v < Q; ++v) h[v] = floor_div3(sk[v]);
+                    msearch(&p, search, h, m, scratch);
+                    for (int v = 0; v < Q; ++v) acc[v] += m[v];
+                }
+                int bi = 0;
+                for (int v = 1; v < Q; ++v) if (acc[v] < acc[bi]) bi = v;
+                labels[cell] = bi;
+                if (marginal_out) memcpy(marginal_out + cell * Q, acc, sizeof(int64_t) * Q);
+            }
+    *energy_out = oracle_energy_volume(W, H, Z, qx, qy, lam, trunc, mode, prior, cost, labels);
+    *max_abs_out = maxabs;
+    free(S); free(h); free(m); free(acc); free(scratch); free(nw);
+    return status;
 }

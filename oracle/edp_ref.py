@@ -14,7 +14,8 @@ Notation follows the paper (Mozerov, arXiv 1410.7922):
 * ``M(h)(v) = min_v' h(v') + V(v - v')``  the minimum search operator,
   Sec. 2 eq. M_strf; ``argM`` takes the smallest flat index among ties.
 * scanline DP: Sec. 2 eq. base with the zero boundary of Sec. 4.1 eq. DP_1D_2;
-* EDP: Sec. 4.2 eqs. DP_2D_1, DP_2D_base, DP_2D_2 and Algorithm 1.
+* EDP: Sec. 4.2 eqs. DP_2D_1, DP_2D_base, DP_2D_2 and Algorithm 1; on a volume (D = 3) the same
+  equations in their general form (2D directional sums, normalisation 1/D).
 
 Readings where the paper is silent or garbled (each one is listed in the
 design notes of the repository):
@@ -33,6 +34,9 @@ design notes of the repository):
   the window minimum, not lambda f(g): with the constant the operator would be
   a plain window minimum and eq. derivation2, from which it is derived, would
   not hold;
+* a volume (D = 3) is scanned by the eight raster scans with x innermost, the
+  x order alternating fastest, then y, then z (the generalisation of P1..P4),
+  each computing the sums of its three directions; S / 3 is floor division;
 * with three label dimensions the recursive searches apply their operators in
   the order x, y, z (eq. M_decmp nests them for any R; every order gives the
   same values), each followed by its per-line clip under per-dimension
@@ -372,7 +376,8 @@ SCANS = (
 
 
 def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
-        iterations: int = 1, search: str = "sfms", trace=None, prior: int = PRIOR_LINEAR, qz: int = 1):
+        iterations: int = 1, search: str = "sfms", trace=None, prior: int = PRIOR_LINEAR, qz: int = 1,
+        divisor: int = 2):
     """Literal EDP, Algorithm 1 steps 3-5 (the DSI and the prior are the inputs).
 
     For every scan P1..P4 and every vertex x in the scan's raster order, each sum
@@ -385,6 +390,8 @@ def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
     ``search`` selects M: "sfms" (definition), "lrms" (Sec. 3.2 passes, linear prior only)
     or "grms" (Sec. 3.1 windowed operators).
     ``trace`` (optional) is called after every scan as trace(iteration, scan, sums).
+    ``divisor`` is the normalisation D of eq. DP_2D_1 (2 for an image; other values serve only to
+    compare with the volume solve, whose D is 3).
     Returns dict(labels, energy, marginal, sums, max_abs_sum).
     """
     c = np.asarray(cost, dtype=np.int64)
@@ -401,7 +408,7 @@ def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
         dx, dy = DIRECTIONS[k]
         px, py = x - dx, y - dy
         if 0 <= px < W and 0 <= py < H:
-            return msearch(sums[k][py, px] // 2)
+            return msearch(sums[k][py, px] // divisor)
         return np.zeros(Q, np.int64)
 
     for it in range(iterations):
@@ -434,6 +441,114 @@ def edp(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
     e = energy(c, labels, qx, qy, lam, trunc, mode, grid4=True, prior=prior, qz=qz)
     return {"labels": labels, "energy": e, "marginal": marg, "sums": sums,
             "max_abs_sum": max_abs}
+
+
+# ---------------------------------------------------------------------------
+# EDP on a three-dimensional grid (D = 3; Sec. 4.2 in the general form)
+# ---------------------------------------------------------------------------
+
+# k in K = {+-1, +-2, +-3}: unit step (dx, dy, dz) of sgn(k) along axis |k|.
+DIRECTIONS3 = {"+x": (1, 0, 0), "-x": (-1, 0, 0), "+y": (0, 1, 0), "-y": (0, -1, 0),
+               "+z": (0, 0, 1), "-z": (0, 0, -1)}
+OPPOSITE3 = {"+x": "-x", "-x": "+x", "+y": "-y", "-y": "+y", "+z": "-z", "-z": "+z"}
+
+
+def volume_scans():
+    """The eight raster scans of a volume: loops x (innermost), y, z, each incrementing or
+    decrementing; the x order alternates fastest, then y, then z, as P1..P4 do for an image.
+    A scan with directions (sx, sy, sz) computes the sums S_{sx x}, S_{sy y}, S_{sz z}."""
+    out = []
+    for sz in (1, -1):
+        for sy in (1, -1):
+            for sx in (1, -1):
+                out.append((sx, sy, sz, ("+x" if sx > 0 else "-x", "+y" if sy > 0 else "-y",
+                                         "+z" if sz > 0 else "-z")))
+    return tuple(out)
+
+
+def edp_volume(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+               iterations: int = 1, search: str = "sfms", trace=None, prior: int = PRIOR_LINEAR):
+    """Literal EDP on a volume C[z][y][x][q] (D = 3): eq. DP_2D_base with K = {+-x, +-y, +-z}
+    and the normalisation 1/D = 1/3 (floor division), the data cost added, the eight scans of
+    volume_scans() in place, then eq. DP_2D_1 and the smallest argmin of eq. DP_2D_2:
+        S_k'(x) = C(x) + sum_{k != -k'} M(S_k(x_k) // 3) - M(S_-k'(x_-k') // 3),
+    x_k = x - sgn(k) e_|k|, M(.) = 0 off the grid, every S_k = 0 before the first scan.
+    ``trace`` (optional) is called after every scan as trace(iteration, scan, sums).
+    Returns dict(labels [Z][H][W], energy (6-connected), marginal, sums, max_abs_sum)."""
+    c = np.asarray(cost, dtype=np.int64)
+    Z, H, W, Q = c.shape
+    if search == "lrms" and prior != PRIOR_LINEAR:
+        raise ValueError("the linear RMS applies to the truncated linear prior only")
+    msearch = {"sfms": lambda h: min_search_sfms(h, qx, qy, lam, trunc, mode, prior=prior)[0],
+               "lrms": lambda h: min_search_lrms(h, qx, qy, lam, trunc, mode),
+               "grms": lambda h: min_search_grms(h, qx, qy, lam, trunc, mode, prior=prior)}[search]
+    sums = {k: np.zeros((Z, H, W, Q), np.int64) for k in DIRECTIONS3}
+    max_abs = 0
+
+    def m_term(k, x, y, z):
+        dx, dy, dz = DIRECTIONS3[k]
+        px, py, pz = x - dx, y - dy, z - dz
+        if 0 <= px < W and 0 <= py < H and 0 <= pz < Z:
+            return msearch(sums[k][pz, py, px] // 3)
+        return np.zeros(Q, np.int64)
+
+    for it in range(iterations):
+        for scan, (sx, sy, sz, computed) in enumerate(volume_scans()):
+            for z in (range(Z) if sz > 0 else range(Z - 1, -1, -1)):
+                for y in (range(H) if sy > 0 else range(H - 1, -1, -1)):
+                    for x in (range(W) if sx > 0 else range(W - 1, -1, -1)):
+                        m = {k: m_term(k, x, y, z) for k in DIRECTIONS3}
+                        new = {}
+                        for kp in computed:
+                            acc = c[z, y, x].copy()
+                            for k in DIRECTIONS3:
+                                if k != OPPOSITE3[kp]:
+                                    acc = acc + m[k]
+                            new[kp] = acc - m[OPPOSITE3[kp]]
+                        for kp, val in new.items():
+                            sums[kp][z, y, x] = val
+                            max_abs = max(max_abs, int(np.abs(val).max()))
+            if trace is not None:
+                trace(it, scan, {k: v.copy() for k, v in sums.items()})
+    marg = c.copy()
+    for z in range(Z):
+        for y in range(H):
+            for x in range(W):
+                for k in DIRECTIONS3:
+                    marg[z, y, x] += m_term(k, x, y, z)
+    labels = np.argmin(marg, axis=-1)
+    if max_abs > INT32_MAX:
+        raise OverflowError(f"EDP sum {max_abs} exceeds int32")
+    e = energy_volume(c, labels, qx, qy, lam, trunc, mode, prior=prior)
+    return {"labels": labels, "energy": e, "marginal": marg, "sums": sums, "max_abs_sum": max_abs}
+
+
+def energy_volume(cost: np.ndarray, labels: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                  prior: int = PRIOR_LINEAR) -> int:
+    """Energy of eq. GE_objective_function on a 6-connected volume: data costs plus V over every
+    pair of voxels one step apart along x, y or z."""
+    c = np.asarray(cost, dtype=np.int64)
+    labels = np.asarray(labels, dtype=np.int64)
+    Z, H, W, Q = c.shape
+    zz, yy, xx = np.mgrid[0:Z, 0:H, 0:W]
+    e = int(c[zz, yy, xx, labels].sum())
+    vm = prior_matrix(qx, qy, lam, trunc, mode, prior)
+    e += int(vm[labels[:, :, 1:], labels[:, :, :-1]].sum())
+    e += int(vm[labels[:, 1:, :], labels[:, :-1, :]].sum())
+    e += int(vm[labels[1:, :, :], labels[:-1, :, :]].sum())
+    return e
+
+
+def volume_exhaustive(cost: np.ndarray, qx: int, qy: int, lam: int, trunc: int, mode: int,
+                      prior: int = PRIOR_LINEAR) -> int:
+    """Minimum 6-connected energy over all Q^(W*H*Z) labellings of a tiny volume."""
+    c = np.asarray(cost, dtype=np.int64)
+    Z, H, W, Q = c.shape
+    best = None
+    for lab in itertools.product(range(Q), repeat=Z * H * W):
+        e = energy_volume(c, np.array(lab).reshape(Z, H, W), qx, qy, lam, trunc, mode, prior)
+        best = e if best is None else min(best, e)
+    return best
 
 
 def wta(cost: np.ndarray) -> np.ndarray:

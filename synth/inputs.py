@@ -22,6 +22,9 @@ used, textured synthetic pairs stand in for them):
   with a brightness offset per segment, b one of ``levels`` offset steps; the
   cost compares I0 + offset with the displaced I1 (truncated squared difference).
 * ``random_problem``  -- uniform random costs of any shape, for parity sweeps.
+* ``volume_problem``  -- a three-dimensional grid (D = 3): a noisy volume over
+  3D Voronoi cells of constant intensity level, truncated squared difference
+  cost to each of Q levels (denoising of a tomography-like volume).
 """
 from __future__ import annotations
 
@@ -54,14 +57,19 @@ class Problem:
     meta: dict = field(default_factory=dict)
     prior: int = PRIOR_LINEAR
     qz: int = 1                 # labels along a third label dimension
+    # cost [Z][H][W][Q] for a volume (D = 3): height and width read the last grid axes
 
     @property
     def height(self) -> int:
-        return int(self.cost.shape[0])
+        return int(self.cost.shape[-3])
 
     @property
     def width(self) -> int:
-        return int(self.cost.shape[1])
+        return int(self.cost.shape[-2])
+
+    @property
+    def depth(self) -> int:
+        return int(self.cost.shape[0]) if self.cost.ndim == 4 else 1
 
     @property
     def q(self) -> int:
@@ -69,7 +77,7 @@ class Problem:
 
     @property
     def pixel_labels(self) -> int:
-        return self.height * self.width * self.q
+        return self.depth * self.height * self.width * self.q
 
     def sha256(self) -> str:
         return hashlib.sha256(np.ascontiguousarray(self.cost).tobytes()).hexdigest()
@@ -313,6 +321,37 @@ def motion_offset_problem(seed: int = 0, W: int = 320, H: int = 240, r: int = 3,
                    meta={"gt": gt, "frames": (i0, i1)}, qz=levels)
 
 
+def random_volume(seed: int, W: int, H: int, Z: int, qx: int, qy: int = 1, lam: int = 7, trunc: int = 2,
+                  mode: int = TRUNC_PER_DIM, lo: int = 0, hi: int = 100, dtype=np.int32) -> Problem:
+    """Uniform random integer costs in [lo, hi] on a volume [Z][H][W][Q]."""
+    rng = np.random.default_rng(seed)
+    cost = rng.integers(lo, hi + 1, size=(Z, H, W, qx * qy), dtype=np.int64).astype(dtype)
+    return Problem(np.ascontiguousarray(cost), qx, qy, lam, trunc, mode, name=f"vol{W}x{H}x{Z}q{qx}x{qy}s{seed}")
+
+
+def volume_problem(seed: int = 0, W: int = 128, H: int = 128, Z: int = 128, Q: int = 32, cells: int = 24,
+                   sigma: float = 10.0, lam: int = 60, trunc: int = 3, cmax: int = 2500, dtype=np.int16) -> Problem:
+    """A noisy volume over 3D Voronoi cells, each of one of Q intensity levels (level q is grey
+    value round(q * 255 / (Q - 1))), Gaussian noise sigma; label q costs
+    min((I - level_q)^2, cmax).  Planted labels in meta["gt"]."""
+    rng = np.random.default_rng(seed)
+    cz, cy, cx = rng.uniform(0, Z, cells), rng.uniform(0, H, cells), rng.uniform(0, W, cells)
+    lev = rng.integers(0, Q, cells)
+    zz, yy, xx = np.mgrid[0:Z, 0:H, 0:W]
+    best = np.full((Z, H, W), np.inf)
+    gt = np.zeros((Z, H, W), np.int64)
+    for k in range(cells):
+        d2 = (xx - cx[k]) ** 2 + (yy - cy[k]) ** 2 + (zz - cz[k]) ** 2
+        closer = d2 < best
+        gt[closer] = lev[k]
+        best[closer] = d2[closer]
+    levels = np.rint(np.arange(Q) * 255.0 / (Q - 1))
+    img = np.clip(np.rint(levels[gt] + rng.normal(0.0, sigma, size=gt.shape)), 0, 255)
+    cost = np.minimum((img[..., None] - levels[None, None, None, :]) ** 2, cmax).astype(dtype)
+    return Problem(np.ascontiguousarray(cost), Q, 1, lam, trunc, TRUNC_PER_DIM,
+                   name=f"volume{W}x{H}x{Z}q{Q}s{seed}", meta={"gt": gt})
+
+
 def random_problem(seed: int, W: int, H: int, qx: int, qy: int = 1, lam: int = 7, trunc: int = 2,
                    mode: int = TRUNC_PER_DIM, lo: int = 0, hi: int = 100,
                    dtype=np.int32, qz: int = 1) -> Problem:
@@ -349,6 +388,8 @@ def workload(name: str, seed: int = 0) -> Problem:
         return motion_offset_problem(seed)
     if name == "motion_offset640x480":
         return motion_offset_problem(seed, W=640, H=480)
+    if name == "volume128q32":
+        return volume_problem(seed)
     raise KeyError(name)
 
 
