@@ -132,3 +132,21 @@ def test_volume_workload_crop():
     w = np.argmin(p.cost, axis=-1)
     assert r["energy"] < 0.7 * cref.energy_volume(p.cost, w, 32, 1, p.lam, p.trunc, p.mode)
     assert (r["labels"] == p.meta["gt"]).mean() > 0.8
+
+
+def test_sums_grow_geometrically_with_the_volume_extent():
+    """The cardinality argument of eq. DP_2D_base_1 balances only at D = 2: with D = 3 the supports
+    of the summed terms count (2 x H Z + W H Z) / 3 voxels instead of x H Z, and the sums grow
+    geometrically with the extent of the volume.  Recorded on the volume workload after one
+    iteration: doubling the side of a cube multiplies the largest sum by more than 30 (8 -> 16,
+    12 -> 24), while on images of the same costs 2.25 times the side adds less than half."""
+    peak = {}
+    for n in (8, 12, 16, 24):
+        p = synth.volume_problem(0, W=n, H=n, Z=n)
+        peak[n] = cref.edp_volume(p.cost, 32, 1, p.lam, p.trunc, p.mode, 1, "grms")["max_abs_sum"]
+    assert peak[16] > 30 * peak[8] and peak[24] > 30 * peak[12], peak
+    flat = []
+    for n in (16, 36):
+        img = synth.volume_problem(0, W=n, H=n, Z=1).cost[0]
+        flat.append(cref.edp(img, 32, 1, 60, 3, 0, 1, "grms")["max_abs_sum"])
+    assert flat[1] < 1.5 * flat[0], flat
