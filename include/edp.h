@@ -35,13 +35,16 @@
  *     host before anything is enqueued; nothing is written on error.
  *   - Integer arithmetic only: results are bit-exact and deterministic.
  *     Every argmin takes the smallest flat label.
- *   - Label spaces: the EDP scans hold a vertex's labels on one lane tile
- *     (edp_tiles()) or, for two label dimensions with a window search
- *     (T <= 3), on a wide tile of several wavefronts (edp_wide_tiles()); the
- *     largest tiles take 256 labels along one dimension (qy == 1),
- *     32 x 32 labels in two dimensions and 8 x 8 x 8 in three
- *     (edp_tiles_3d()).  Larger label spaces return EDP_E_UNSUPPORTED from
- *     the EDP and DP calls (edp_dsi and edp_energy take up to 4096 labels).
+ *   - Label spaces (at most 4096 labels): the EDP scans hold a vertex's
+ *     labels on one lane tile (edp_tiles()) or, for two label dimensions
+ *     with a window search (T <= 3), on a wide tile of several wavefronts
+ *     (edp_wide_tiles()).  Supported: one label dimension up to 256 labels
+ *     (qy == 1); two dimensions up to 32 x 32 with any T, up to 64 x 64
+ *     (64 x 32, 32 x 64) with T <= 3; three dimensions up to 8 x 8 x 8
+ *     (edp_tiles_3d()).  The scanline DP calls take the single-wavefront
+ *     tiles only (256 labels in one dimension, 32 x 32 in two).  Other label
+ *     spaces return EDP_E_UNSUPPORTED (edp_dsi and edp_energy take any label
+ *     space of up to 4096 labels).
  *     Three label dimensions (qz > 1) are taken by edp_solve, edp_batch_*,
  *     edp_energy and edp_workspace_size with EDP_OP_EDP; the scanline DP
  *     calls and the label-window solve return EDP_E_UNSUPPORTED for them.

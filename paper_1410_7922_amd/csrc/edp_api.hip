@@ -18,23 +18,39 @@ static_assert(STATUS_TIMEOUT == EDP_E_TIMEOUT, "status word value of a timed-out
 
 namespace {
 
-// single-wavefront tiles, the wide-vertex tiles as 16 x (4 NV) lane grids, then the
-// single-wavefront tiles of three-dimensional label spaces
-const TileShape kTiles[NUM_ALL_TILES] = {
-#define EDP_ROW(id, px, kx, py, ky) {px, kx, py, ky, 1},
+// Tiles by id: single-wavefront tiles (one or two label dimensions), the wide-vertex tiles as
+// 16 x (4 NV) lane grids, the single-wavefront tiles of three-dimensional label spaces.
+enum TileKind { TK_NONE = 0, TK_REG = 1, TK_WIDE = 2, TK_3D = 3 };
+struct TileRow {
+    TileShape s;
+    int kind;
+};
+struct TileTable {
+    TileRow t[NUM_ALL_TILES];
+};
+constexpr TileTable make_tiles() {
+    TileTable r{};
+#define EDP_ROW(id, px, kx, py, ky) r.t[id] = TileRow{{px, kx, py, ky, 1}, TK_REG};
     EDP_TILE_LIST(EDP_ROW)
 #undef EDP_ROW
-#define EDP_MV_ROW(id, kx, ky, nv) {16, kx, 4 * nv, ky, 1},
+#define EDP_MV_ROW(id, kx, ky, nv) r.t[id] = TileRow{{16, kx, 4 * nv, ky, 1}, TK_WIDE};
     EDP_MV_TILE_LIST(EDP_MV_ROW)
 #undef EDP_MV_ROW
-#define EDP_ROW3(id, px, kx, py, ky, kz) {px, kx, py, ky, kz},
+#define EDP_ROW3(id, px, kx, py, ky, kz) r.t[id] = TileRow{{px, kx, py, ky, kz}, TK_3D};
     EDP_TILE3_LIST(EDP_ROW3)
 #undef EDP_ROW3
+    return r;
+}
+constexpr TileTable kTileTable = make_tiles();
+struct TileIndex {
+    const TileShape& operator[](int id) const { return kTileTable.t[id].s; }
 };
+constexpr TileIndex kTiles{};
+int kind_of(int tile) { return tile >= 0 && tile < NUM_ALL_TILES ? kTileTable.t[tile].kind : TK_NONE; }
 
-bool is_wide(int tile) { return tile >= NUM_TILES && tile < FIRST_TILE3; }
+bool is_wide(int tile) { return kind_of(tile) == TK_WIDE; }
 // tiles of the single-wavefront scan kernel (two- and three-dimensional label spaces)
-bool is_regular(int tile) { return (tile >= 0 && tile < NUM_TILES) || (tile >= FIRST_TILE3 && tile < NUM_ALL_TILES); }
+bool is_regular(int tile) { return kind_of(tile) == TK_REG || kind_of(tile) == TK_3D; }
 int wide_nv(int tile) { return kTiles[tile].py / 4; }
 
 // labels along the third label dimension (0 in the problem means none)
@@ -70,7 +86,7 @@ int auto_tile(int qx, int qy, int qz = 1) {
         return (lanes == pref ? 0 : 1000) + 10 * elems_of(t) + (kTiles[t].px == kTiles[t].py ? 0 : 1);
     };
     for (int t = 0; t < NUM_ALL_TILES; ++t) {
-        if (!is_regular(t) || (qz > 1) != (kTiles[t].kz > 1) || !fits(t, qx, qy, qz)) continue;
+        if (!is_regular(t) || (qz > 1) != (kind_of(t) == TK_3D) || !fits(t, qx, qy, qz)) continue;
         if (best < 0 || qt_of(t) < qt_of(best) || (qt_of(t) == qt_of(best) && score(t) < score(best))) best = t;
     }
     return best;
@@ -204,8 +220,8 @@ int auto_scan_tile(const edp_problem* p) {
     const int ms = ms_of(p);
     if (p->qy < 2 || qz_of(p) > 1 || (ms != MS_WINDOW && ms != MS_WINDOW1) || (t >= 0 && elems_of(t) < 8)) return t;
     int best = -1;
-    for (int w = NUM_TILES; w < FIRST_TILE3; ++w) {
-        if (!fits(w, p->qx, p->qy)) continue;
+    for (int w = 0; w < NUM_ALL_TILES; ++w) {
+        if (!is_wide(w) || !fits(w, p->qx, p->qy)) continue;
         if (best < 0 || qt_of(w) < qt_of(best) || (qt_of(w) == qt_of(best) && wide_nv(w) > wide_nv(best))) best = w;
     }
     if (best < 0) return t;
@@ -1160,8 +1176,8 @@ edp_status edp_energy(const edp_problem* prob, const void* d_cost, const int32_t
 int32_t edp_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
     if (qx < 1 || qy < 1 || max < 0) return EDP_E_INVALID;
     int n = 0;
-    for (int t = 0; t < NUM_TILES; ++t) {
-        if (!fits(t, qx, qy)) continue;
+    for (int t = 0; t < NUM_ALL_TILES; ++t) {
+        if (kind_of(t) != TK_REG || !fits(t, qx, qy)) continue;
         if (ids && n < max) ids[n] = t;
         ++n;
     }
@@ -1171,8 +1187,8 @@ int32_t edp_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
 int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
     if (qx < 1 || qy < 1 || max < 0) return EDP_E_INVALID;
     int n = 0;
-    for (int t = NUM_TILES; t < FIRST_TILE3; ++t) {
-        if (!fits(t, qx, qy)) continue;
+    for (int t = 0; t < NUM_ALL_TILES; ++t) {
+        if (!is_wide(t) || !fits(t, qx, qy)) continue;
         if (ids && n < max) ids[n] = t;
         ++n;
     }
@@ -1182,8 +1198,8 @@ int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
 int32_t edp_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t max) {
     if (qx < 1 || qy < 1 || qz < 1 || max < 0) return EDP_E_INVALID;
     int n = 0;
-    for (int t = FIRST_TILE3; t < NUM_ALL_TILES; ++t) {
-        if (!fits(t, qx, qy, qz)) continue;
+    for (int t = 0; t < NUM_ALL_TILES; ++t) {
+        if (kind_of(t) != TK_3D || !fits(t, qx, qy, qz)) continue;
         if (ids && n < max) ids[n] = t;
         ++n;
     }
@@ -1191,13 +1207,13 @@ int32_t edp_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t m
 }
 
 edp_status edp_tile_depth(int32_t tile, int32_t* kz) {
-    if (tile < 0 || tile >= NUM_ALL_TILES || !kz) return EDP_E_INVALID;
+    if (kind_of(tile) == TK_NONE || !kz) return EDP_E_INVALID;
     *kz = kTiles[tile].kz;
     return EDP_OK;
 }
 
 edp_status edp_tile_info(int32_t tile, int32_t* px, int32_t* kx, int32_t* py, int32_t* ky) {
-    if (tile < 0 || tile >= NUM_ALL_TILES || !px || !kx || !py || !ky) return EDP_E_INVALID;
+    if (kind_of(tile) == TK_NONE || !px || !kx || !py || !ky) return EDP_E_INVALID;
     *px = kTiles[tile].px;
     *kx = kTiles[tile].kx;
     *py = kTiles[tile].py;

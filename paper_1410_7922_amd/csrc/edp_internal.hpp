@@ -25,14 +25,18 @@
     X(14, 4, 2, 4, 2)    \
     X(15, 4, 8, 16, 2)
 
-// Wide-vertex tiles of the EDP scans for two-dimensional label spaces: id, KX, KY, NV.
+// Wide-vertex tiles of the EDP scans for two-dimensional label spaces: id, KX, KY, NV (ids 16-18,
+// then 22-24 after the three-dimensional tiles).
 // A vertex takes NV wavefronts; each holds 4 KY label rows of 16 KX labels (lane px of lane
 // row r: KX x KY labels), so the tile holds (16 KX) x (4 KY NV) labels and its lane-major
 // layout is that of a 16 x (4 NV) lane grid.  Ids follow the single-wavefront tiles.
 #define EDP_MV_TILE_LIST(X) \
     X(16, 2, 2, 4)          \
     X(17, 2, 4, 2)          \
-    X(18, 1, 2, 2)
+    X(18, 1, 2, 2)          \
+    X(22, 4, 2, 8)          \
+    X(23, 4, 2, 4)          \
+    X(24, 2, 2, 8)
 
 // Single-wavefront tiles of three-dimensional label spaces: id, PX, KX, PY, KY, KZ.  Lane
 // (px, py) holds the KX x KY labels of the two-dimensional tile at each of the KZ labels
@@ -46,10 +50,7 @@
 namespace edp {
 
 constexpr int NUM_TILES = 16;
-constexpr int NUM_MV_TILES = 3;
-constexpr int NUM_TILES3 = 3;
-constexpr int FIRST_TILE3 = NUM_TILES + NUM_MV_TILES;
-constexpr int NUM_ALL_TILES = FIRST_TILE3 + NUM_TILES3;
+constexpr int NUM_ALL_TILES = 25;   // every id of the three tile lists is below this
 // A wide-vertex tile holds at most this many scanlines per workgroup times its wavefronts
 // per vertex: 8 wavefronts (512 lanes).
 constexpr int MV_MAX_WAVES = 8;

@@ -10,9 +10,10 @@ template <int ID> struct MvTileOf;
 EDP_MV_TILE_LIST(EDP_MV_OF)
 #undef EDP_MV_OF
 
-// Prefetch depth in steps: the loads of a step are few, so several steps stay in flight.
+// Prefetch depth in steps: the loads of a step are few, so several steps stay in flight (fewer
+// where a lane holds more labels, or the helpers of eight slabs need more registers).
 template <class M>
-constexpr int mv_pf() { return M::E <= 4 ? 4 : 2; }
+constexpr int mv_pf() { return M::E <= 4 && M::NV <= 4 ? 4 : 2; }
 
 template <class M, class CK, int MS>
 static hipError_t run_mv(const PassArgs& a, int grid, int rows, hipStream_t s) {

@@ -59,7 +59,7 @@ constexpr int MV_HDR = 4 + 3 * MV_CTR;
 // wavefront [NV][QXP] and the vertex minima of each wavefront [NV].
 template <class M, int HB>
 constexpr int mv_xs() {
-    return (M::QYP + 2 * HB) * M::QXP + M::NV * M::QXP + 4;
+    return (M::QYP + 2 * HB) * M::QXP + M::NV * M::QXP + (M::NV > 4 ? M::NV : 4);
 }
 
 template <class M, int HB>
@@ -83,13 +83,20 @@ __device__ __forceinline__ int32_t min_dpp(int32_t v, const int32_t src) {
     return v;
 }
 
-// Smallest of N consecutive LDS counters (N = 1, 2, 4; 4 N-byte aligned), read with one access.
+// Smallest of N consecutive LDS counters (N = 1, 2, 4, 8; 4 N-byte aligned up to 16 bytes), read
+// with one access (two for N = 8).
 template <int N>
 __device__ __forceinline__ int32_t lds_min_ctr(const int32_t* p) {
     // an explicit LDS pointer: a generic one would become a flat access, which also counts as a
     // vector memory operation and makes waits for it wait for the prefetched loads too
     typedef __attribute__((address_space(3))) const volatile int32_t lds_i32;
-    if constexpr (N == 4) {
+    if constexpr (N == 8) {
+        typedef int32_t v4 __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(3))) const volatile v4 lds_v4;
+        const v4 a = *(lds_v4*)(lds_i32*)p;
+        const v4 b = *(lds_v4*)(lds_i32*)(p + 4);
+        return imin(imin(imin(a[0], a[1]), imin(a[2], a[3])), imin(imin(b[0], b[1]), imin(b[2], b[3])));
+    } else if constexpr (N == 4) {
         typedef int32_t v4 __attribute__((ext_vector_type(4)));
         typedef __attribute__((address_space(3))) const volatile v4 lds_v4;
         const v4 v = *(lds_v4*)(lds_i32*)p;
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             __builtin_amdgcn_s_setprio(3);
             const int32_t hx = wave - RW * NV;             // 0 or 1
             constexpr int NS = NV / 2 > 0 ? NV / 2 : 1;    // slabs per helper
-            constexpr int NC = NS * E <= 8 ? 4 : 2;        // columns per poll
+            constexpr int NC = NS * E <= 8 ? 4 : (NS * E <= 16 ? 2 : 1);   // columns per poll
             if (super == 0) {
                 for (int32_t k = hx * 64 + lane; k < R * QT; k += 128) rings[k] = 0;
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);

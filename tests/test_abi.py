@@ -115,7 +115,11 @@ def test_tiles_and_workspace_sizes():
     st, n = _ws(_prob(qx=200, qy=1), B.OP_EDP)
     assert st == 0
     st, n = _ws(_prob(qx=40, qy=40), B.OP_EDP)
-    assert st == -5                                  # 1600 labels: no tile compiled for 40 x 40
+    assert st == 0                                   # 1600 labels: the 64 x 64 wide tile (T = 2)
+    assert _ws(_prob(qx=40, qy=40, trunc=5), B.OP_EDP)[0] == -5   # the linear RMS: no tile beyond 32 x 32
+    assert _ws(_prob(qx=64, qy=64, dtype=2, cost_bound=100), B.OP_EDP)[0] == 0
+    assert B.wide_tiles(64, 64) == [22] and B.wide_tiles(33, 20) == [22, 23] and B.wide_tiles(20, 33) == [22, 24]
+    assert B.tile_info(22) == (16, 4, 32, 2) and B.tile_depth(22) == 1
     for tile in B.tiles(32):
         st, n = _ws(_prob(), B.OP_EDP, tile)
         px, kx, py, ky = B.tile_info(tile)
@@ -208,7 +212,7 @@ def test_batch_workspace_and_host_side_errors():
     nocost = _items(probs)
     nocost[1].d_cost = None
     assert lib.edp_batch_workspace_size(3, nocost, ctypes.byref(n)) == -1
-    wide = _items([_prob(qx=40, qy=40)])
+    wide = _items([_prob(qx=40, qy=40, trunc=5)])          # no tile for the linear RMS at 40 x 40
     assert lib.edp_batch_workspace_size(1, wide, ctypes.byref(n)) == -5
     plan = ctypes.c_void_p(None)
     assert lib.edp_batch_workspace_size(3, items, ctypes.byref(n)) == 0

@@ -46,6 +46,10 @@ CASES = [
     (29, 1, 16, 16, 7, 3, 0, 0, 0, 200, np.int32, 1),      # single row
     (15, 16, 2, 2, 3, 2, 0, 0, 0, 20, np.int32, 1),        # tiny label space on a wide tile
     (6, 41, 31, 31, 15, 3, 0, 0, 0, 2500, np.int32, 1),    # tall: many workgroup bands, partial last
+    (6, 7, 64, 64, 5, 2, 0, 0, 0, 300, np.int32, 1),       # 4096 labels, eight wavefronts per vertex
+    (7, 9, 40, 40, 6, 3, 1, 0, 0, 200, np.int16, 1),       # 1600 labels padded to 64 x 64, joint
+    (9, 5, 57, 23, 4, 3, 0, 1, 0, 300, np.int32, 2),       # 64 x 32 tile, squared prior, two iterations
+    (5, 11, 20, 50, 6, 3, 0, 0, -50, 100, np.int32, 1),    # 32 x 64 tile, negative costs
 ]
 
 
@@ -62,7 +66,8 @@ def test_wide_tiles_against_oracle(case):
     tiles = edp.wide_tiles(qx, qy)
     assert tiles
     for tile in tiles:
-        for waves, fuse in ((0, 0), (1, 2), (2, 1), (max_rows(tile), 2)):
+        mr = max_rows(tile)
+        for waves, fuse in sorted({(0, 0), (1, 2), (min(2, mr), 1), (mr, 2)}):
             note(f"wide {p.name} prior {prior} j{j} tile {tile} rows {waves} fuse {fuse}")
             lab, e = gpu_edp(p, j, tile, waves, fuse, prior)
             assert np.array_equal(lab, ref["labels"]), (tile, waves, fuse)
