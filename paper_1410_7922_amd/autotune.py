@@ -8,10 +8,14 @@ the built-in shape.  Choices are cached in a JSON file keyed by
 ``qx x qy : dtype : mode : W x H : iterations``.
 
 Search (staged, so a key costs a few dozen solves):
-  1. every tile that holds the label space with at most 4x padding, each split
-     the tile allows, with 4 wavefronts per workgroup;
-  2. the best (tile, split) with 1, 2, 4 and 6 wavefronts, one or two scans per launch;
-  3. the best so far with progress published every 1, 2, 4, 8 or 16 columns.
+  1. every single-wavefront tile that holds the label space with at most 4x padding, each
+     split the tile allows, with 4 wavefronts per workgroup; and every wide tile (a vertex on
+     several wavefronts; two label dimensions with a window search) with its built-in
+     scanlines per workgroup;
+  2. the best (tile, split) with 1, 2, 4 and 6 wavefronts (wide tiles: 1 up to the most
+     scanlines per workgroup), one or two scans per launch;
+  3. the best so far with progress published every 1, 2, 4, 8 or 16 columns (single-wavefront
+     tiles).
 """
 from __future__ import annotations
 
@@ -99,9 +103,11 @@ def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict
 
     q = qx * qy
     tiles = [t for t in B.tiles(qx, qy)]
-    qts = {t: _qt(t) for t in tiles}
+    wide = [t for t in B.wide_tiles(qx, qy)] if qy > 1 and p["trunc"] <= 3 else []
+    qts = {t: _qt(t) for t in tiles + wide}
     small = min(qts.values())
     tiles = [t for t in tiles if qts[t] <= max(4 * q, small)]
+    wide = [t for t in wide if qts[t] <= max(4 * q, small)]
     best, best_ms = None, float("inf")
 
     def consider(shape):
@@ -114,7 +120,15 @@ def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict
         px, kx, py, ky = B.tile_info(t)
         for split in (1, 2) if 2 * px * py <= 64 else (1,):
             consider(dict(tile=t, split=split, waves=4, chunk=4, fuse=2))
+    for t in wide:
+        consider(dict(tile=t, split=1, waves=0, chunk=0, fuse=2))
     base = dict(best)
+    if base["tile"] in wide:
+        rows = 8 // (B.tile_info(base["tile"])[2] // 4)     # scanlines of NV wavefronts, 8 at most
+        for waves in range(1, rows + 1):
+            for fuse in (1, 2):
+                consider(dict(base, waves=waves, fuse=fuse))
+        return dict(best, ms=best_ms)
     for waves in (1, 2, 4, 6):
         for fuse in (1, 2):
             consider(dict(base, waves=waves, fuse=fuse))

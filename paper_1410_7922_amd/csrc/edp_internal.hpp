@@ -231,6 +231,8 @@ struct BatchEnergyArgs {
     const InstDesc* descs;
     int32_t ndesc;
     int32_t rows_per_block;
+    const uint32_t* error;   // the class's error word: nonzero, every energy is INT64_MIN
+    int32_t status;          // 1: the first block of each instance also writes its status word
 };
 
 // Data cost formation: [H][W][qx*qy] costs of images i0, i1 (and i2 for the composite cost).

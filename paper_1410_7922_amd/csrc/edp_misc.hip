@@ -73,10 +73,20 @@ __global__ __launch_bounds__(256) void energy_kernel(const EnergyArgs a) {
 }
 
 // Energies of a batch class: block b covers rows_per_block rows of the instance
-// that holds it and adds its share to that instance's energy word.
+// that holds it and adds its share to that instance's energy word.  The scans ran before this
+// launch on the same stream, so their error word is final: if it is set, the first block of each
+// instance stores INT64_MIN and no block adds.  With a.status the first block also writes the
+// instance's status word (classes whose last scan formed the labels).
 template <class CT>
 __global__ __launch_bounds__(256) void batch_energy_kernel(const BatchEnergyArgs a) {
     const InstDesc d = uniform_desc(a.descs[find_instance(a.descs, a.ndesc, (int32_t)blockIdx.x, 2)]);
+    const bool failed = a.error && *a.error != 0;
+    const bool first = (int32_t)blockIdx.x == d.first_eblock;
+    if (threadIdx.x == 0 && first) {
+        if (a.status && d.status) *d.status = failed ? STATUS_TIMEOUT : 0;
+        if (failed && d.energy) *d.energy = (unsigned long long)INT64_MIN;
+    }
+    if (failed) return;
     const int32_t W = d.W, H = d.H, QXY = d.qx * d.qy, Q = QXY * d.qz;
     const CT* __restrict__ cost = (const CT*)d.cost;
     const bool joint = d.joint != 0;

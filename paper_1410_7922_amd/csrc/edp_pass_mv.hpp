@@ -268,7 +268,15 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             constexpr int NS = NV / 2 > 0 ? NV / 2 : 1;    // slabs per helper
             constexpr int NC = NS * E <= 8 ? 4 : (NS * E <= 16 ? 2 : 1);   // columns per poll
             if (super == 0) {
-                for (int32_t k = hx * 64 + lane; k < R * QT; k += 128) rings[k] = 0;
+                // zeros above the first band: each helper clears the ring words of exactly the
+                // slabs whose count it publishes (slab v: 64 E words per slot from v 64 E), so a
+                // slab's wavefront never reads words the other helper has not cleared yet (the
+                // ring still holds the workgroup's previous band)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v % 2 == hx)
+                        for (int32_t k = lane; k < R * 64 * E; k += 64)
+                            rings[(k / (64 * E)) * QT + v * 64 * E + k % (64 * E)] = 0;
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
                 for (int v = 0; v < NV; ++v)

@@ -122,3 +122,29 @@ def test_batch_workload_64_instances():
         assert torch.equal(lab, labels[i]), i
         assert int(e.item()) == int(energies[i].item()), i
     plan.close()
+
+
+@pytest.mark.parametrize("fuse", [2, 1])
+def test_wide_tiles_repeated_batch_solves(fuse):
+    """The motion instances of up to 16 x 16 labels of the 64-instance workload on the two-wavefront
+    wide tile with one scanline per workgroup (every scanline a workgroup band: workgroups move
+    between instances and bands all the time), solved five times in one plan: every solve equals
+    the C oracle's golden.  The first band of a scan takes zeros from its ring; the ring must not
+    show the workgroup's previous band to either wavefront of the vertex."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "edp_batch64.json")) as f:
+        golden = json.load(f)["instances"]
+    probs = synth.batch_problems(64)
+    idx = [i for i in range(64) if i % 2 == 1 and probs[i].qx <= 16]
+    costs = [torch.from_numpy(probs[i].cost).to(DEV) for i in idx]
+    params = [params_of(probs[i], 1, 2500) for i in idx]
+    plan = edp.BatchPlan(costs, params, [dict(tile=18, waves=1, fuse=fuse)] * len(idx))
+    note(f"wide tile 18, one scanline per workgroup, fuse {fuse}: {len(idx)} instances x 5 solves")
+    for rep in range(5):
+        labels, energies = plan.solve()
+        torch.cuda.synchronize()
+        plan.check()
+        for j, i in enumerate(idx):
+            lab = np.ascontiguousarray(labels[j].cpu().numpy(), np.int32)
+            assert hashlib.sha256(lab.tobytes()).hexdigest() == golden[i]["labels_sha256"], (rep, i)
+            assert int(energies[j].item()) == golden[i]["energy"], (rep, i)
+    plan.close()
