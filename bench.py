@@ -144,10 +144,12 @@ def bench_edp(edp, torch, prob, steps, warmup, tile, chunk, iterations=1, fuse=0
             "energy": int(energy.item()), "cost": cost}
 
 
-SCAN_SOURCES = ["edp_pass_kernel.hpp", "edp_device.hpp", "edp_pass_mv.hpp"]
+# the sources each scan kernel is built from: its recorded counters stay valid while these are unchanged
+SCAN_SOURCES = {"edp_pass_kernel": ["edp_pass_kernel.hpp", "edp_device.hpp"],
+                "edp_pass_mv_kernel": ["edp_pass_kernel.hpp", "edp_device.hpp", "edp_pass_mv.hpp"]}
 
 
-def scan_roofline(prob, r, traffic_key=None, kernel="edp_pass_kernel"):
+def scan_roofline(prob, r, traffic_key=None, kernel="edp_pass_kernel", note=""):
     """Roofline of the EDP scan kernel: algorithmic bytes of the scans of one solve (all eight old-sum
     reads counted) over the summed duration of the scan launches, timed by HIP events on the
     benchmark's stream; traffic: HBM bytes per launch from the recorded rocprofv3 counters, while
@@ -161,9 +163,9 @@ def scan_roofline(prob, r, traffic_key=None, kernel="edp_pass_kernel"):
     launch_ms = np.array(r["launch_ms"]).mean(axis=0)          # [scan launches]
     alg_bytes = float(sum(per_scan) * pl)
     achieved = alg_bytes / (launch_ms.sum() / 1e3) / 1e9
-    src_hash = kernel_source_hash(SCAN_SOURCES)
+    src_hash = kernel_source_hash(SCAN_SOURCES[kernel])
     traffic = measured_traffic(traffic_key, src_hash) if traffic_key else None
-    return {"bound": "hbm", "kernel": f"{kernel} ({len(launch_ms)} scan launches per solve)",
+    return {"bound": "hbm", "kernel": f"{kernel}{note} ({len(launch_ms)} scan launches per solve)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "alg_bytes_per_pl_scans": sum(per_scan),
             "alg_bytes_per_launch": alg_bytes / len(launch_ms), "mean_launch_ms": launch_ms.tolist(),
@@ -512,7 +514,7 @@ def bench_r3(edp, torch, steps, warmup):
     H, W, Q = prob.cost.shape
     pl = H * W * Q
     r = bench_edp(edp, torch, prob, steps, warmup, -1, 0)
-    roof = scan_roofline(prob, r, "edp_pass_motionoffset640x480q343", kernel="edp_pass_kernel, tile 19 (8x8x8)")
+    roof = scan_roofline(prob, r, "edp_pass_motionoffset640x480q343", note=", tile 19 (8x8x8)")
     return {"workload": "plain EDP, motion with a brightness offset 640x480, 7x7x7 labels (dx, dy in [-3, 3], "
                         "7 offset levels of 6 grey levels), int32 truncated squared-difference costs (cmax 2500), "
                         "lambda 40, T 3 per dimension, j=1",
