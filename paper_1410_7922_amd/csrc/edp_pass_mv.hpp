@@ -67,22 +67,6 @@ constexpr size_t mv_lds_bytes_t(int rows, int ring) {
     return ((size_t)MV_HDR + (size_t)rows * 4 * mv_xs<M, HB>() + (size_t)rows * ring * M::QT) * 4;
 }
 
-// min(v, value of the lane n to the left / right in the same 16-lane row); a lane whose source lies
-// outside the row keeps v.  One v_min_i32 with a DPP source; the s_nop gives the source register
-// the two wait states a DPP read needs after a VALU write.
-template <int CTRL>
-__device__ __forceinline__ int32_t min_dpp(int32_t v, const int32_t src) {
-    if constexpr (CTRL == 0x111)
-        asm volatile("s_nop 1\n\tv_min_i32_dpp %0, %1, %0 row_shr:1 row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src));
-    else if constexpr (CTRL == 0x112)
-        asm volatile("s_nop 1\n\tv_min_i32_dpp %0, %1, %0 row_shr:2 row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src));
-    else if constexpr (CTRL == 0x101)
-        asm volatile("s_nop 1\n\tv_min_i32_dpp %0, %1, %0 row_shl:1 row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src));
-    else
-        asm volatile("s_nop 1\n\tv_min_i32_dpp %0, %1, %0 row_shl:2 row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src));
-    return v;
-}
-
 // Smallest of N consecutive LDS counters (N = 1, 2, 4, 8; 4 N-byte aligned up to 16 bytes), read
 // with one access (two for N = 8).
 template <int N>
@@ -131,55 +115,139 @@ __device__ __forceinline__ int32_t rows_min4(int32_t v) {
     return imin((int32_t)b[0], (int32_t)b[1]);
 }
 
-// Window minimum along x of the lane's K labels on each 16-lane row (one x-line per row):
-// steps u = 1..NWK with penalties pen[u-1] (PEN_OFF disables a step), then the clip at the
-// line minimum + clipd when clip is set.  A candidate from another lane is taken by a min with a
-// DPP source (a lane whose source lies outside the row keeps its value).  Returns min h of the line.
-// clipx: the clip offset, or 2^30 for no clip (every value lies below line minimum + 2^30, and the
-// sum stays inside int32 since values lie below PADV).
+// The window candidates along x of one 16-lane row: o[k] = min over |u| <= NWK of h[k + u] + pen[u - 1]
+// (h[k] itself for u = 0), the labels k + u of the row lying in this lane or the lanes to the left and
+// right (a lane whose source lies outside the row keeps its value).  One asm block per label count:
+// the penalised candidates are formed first and every DPP read comes at least two instructions after
+// the VALU write of its source, so the block needs no wait states of its own.
+#define EDP_DPP_MIN(o, p, ctl) "v_min_i32_dpp " o ", " p ", " o " " ctl " row_mask:0xf bank_mask:0xf\n\t"
 template <int K, int NWK>
-__device__ __forceinline__ int32_t xwin16(int32_t (&h)[K], const int32_t (&pen)[2], const int32_t clipx,
-                                          const int32_t lane) {
-    int32_t m = h[0];
-#pragma unroll
-    for (int k = 1; k < K; ++k) m = imin(m, h[k]);
-    m = line_min<16, 1>(m, lane);
-    int32_t p[NWK][K], o[K];
-#pragma unroll
-    for (int u = 0; u < NWK; ++u)
-#pragma unroll
-        for (int k = 0; k < K; ++k) p[u][k] = h[k] + pen[u];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        int32_t v = h[k];
-#pragma unroll
-        for (int u = 1; u <= NWK; ++u) {
-            const int jl = k - u, jr = k + u;
-            if (jl >= 0) v = imin(v, p[u - 1][jl]);
-            if (jr < K) v = imin(v, p[u - 1][jr]);
-        }
-#pragma unroll
-        for (int u = 1; u <= NWK; ++u) {
-            const int jl = k - u, jr = k + u;
-            if (jl < 0) {
-                const int n = (-jl + K - 1) / K;          // lanes to the left
-                const int jj = jl + n * K;
-                if (n == 1) v = min_dpp<dpp_row_shr(1)>(v, p[u - 1][jj]);
-                else v = min_dpp<dpp_row_shr(2)>(v, p[u - 1][jj]);
-            }
-            if (jr >= K) {
-                const int n = jr / K;                      // lanes to the right
-                const int jj = jr - n * K;
-                if (n == 1) v = min_dpp<dpp_row_shl(1)>(v, p[u - 1][jj]);
-                else v = min_dpp<dpp_row_shl(2)>(v, p[u - 1][jj]);
-            }
-        }
-        o[k] = v;
+__device__ __forceinline__ void xwin_candidates(const int32_t (&h)[K], const int32_t (&pen)[2], int32_t (&o)[K]) {
+    if constexpr (K == 1 && NWK == 1) {
+        int32_t p0;
+        asm volatile("v_add_u32 %1, %3, %2\n\t"
+                     "v_mov_b32 %0, %2\n\t"
+                     "s_nop 0\n\t"
+                     EDP_DPP_MIN("%0", "%1", "row_shr:1")
+                     EDP_DPP_MIN("%0", "%1", "row_shl:1")
+                     : "=&v"(o[0]), "=&v"(p0) : "v"(h[0]), "s"(pen[0]));
+    } else if constexpr (K == 1 && NWK == 2) {
+        int32_t p0, p1;
+        asm volatile("v_add_u32 %1, %4, %3\n\t"
+                     "v_add_u32 %2, %5, %3\n\t"
+                     "v_mov_b32 %0, %3\n\t"
+                     EDP_DPP_MIN("%0", "%1", "row_shr:1")
+                     EDP_DPP_MIN("%0", "%2", "row_shr:2")
+                     EDP_DPP_MIN("%0", "%1", "row_shl:1")
+                     EDP_DPP_MIN("%0", "%2", "row_shl:2")
+                     : "=&v"(o[0]), "=&v"(p0), "=&v"(p1) : "v"(h[0]), "s"(pen[0]), "s"(pen[1]));
+    } else if constexpr (K == 2 && NWK == 1) {
+        int32_t p00, p01;
+        // %0 o0, %1 o1, %2 p00, %3 p01, %4 h0, %5 h1, %6 pen0
+        asm volatile("v_add_u32 %3, %6, %5\n\t"
+                     "v_add_u32 %2, %6, %4\n\t"
+                     "v_min_i32 %0, %4, %3\n\t"
+                     "v_min_i32 %1, %5, %2\n\t"
+                     EDP_DPP_MIN("%0", "%3", "row_shr:1")
+                     EDP_DPP_MIN("%1", "%2", "row_shl:1")
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(p00), "=&v"(p01)
+                     : "v"(h[0]), "v"(h[1]), "s"(pen[0]));
+    } else if constexpr (K == 2 && NWK == 2) {
+        int32_t p00, p01, p10, p11;
+        // %0 o0, %1 o1, %2 p00, %3 p01, %4 p10, %5 p11, %6 h0, %7 h1, %8 pen0, %9 pen1
+        asm volatile("v_add_u32 %3, %8, %7\n\t"
+                     "v_add_u32 %4, %9, %6\n\t"
+                     "v_add_u32 %2, %8, %6\n\t"
+                     "v_add_u32 %5, %9, %7\n\t"
+                     "v_min_i32 %0, %6, %3\n\t"
+                     "v_min_i32 %1, %7, %2\n\t"
+                     EDP_DPP_MIN("%0", "%3", "row_shr:1")
+                     EDP_DPP_MIN("%1", "%2", "row_shl:1")
+                     EDP_DPP_MIN("%0", "%4", "row_shr:1")
+                     EDP_DPP_MIN("%1", "%5", "row_shr:1")
+                     EDP_DPP_MIN("%0", "%4", "row_shl:1")
+                     EDP_DPP_MIN("%1", "%5", "row_shl:1")
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(p00), "=&v"(p01), "=&v"(p10), "=&v"(p11)
+                     : "v"(h[0]), "v"(h[1]), "s"(pen[0]), "s"(pen[1]));
+    } else if constexpr (K == 4 && NWK == 1) {
+        int32_t p00, p01, p02, p03;
+        // %0-%3 o0-o3, %4-%7 p00-p03, %8-%11 h0-h3, %12 pen0
+        asm volatile("v_add_u32 %7, %12, %11\n\t"
+                     "v_add_u32 %4, %12, %8\n\t"
+                     "v_add_u32 %5, %12, %9\n\t"
+                     "v_add_u32 %6, %12, %10\n\t"
+                     "v_min_i32 %0, %8, %5\n\t"
+                     "v_min3_i32 %1, %9, %4, %6\n\t"
+                     "v_min3_i32 %2, %10, %5, %7\n\t"
+                     "v_min_i32 %3, %11, %6\n\t"
+                     EDP_DPP_MIN("%0", "%7", "row_shr:1")
+                     EDP_DPP_MIN("%3", "%4", "row_shl:1")
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]),
+                       "=&v"(p00), "=&v"(p01), "=&v"(p02), "=&v"(p03)
+                     : "v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "s"(pen[0]));
+    } else {
+        static_assert(K == 4 && NWK == 2, "label counts per lane: 1, 2, 4");
+        int32_t p00, p01, p02, p03, p10, p11, p12, p13;
+        // %0-%3 o0-o3, %4-%7 p00-p03, %8-%11 p10-p13, %12-%15 h0-h3, %16 pen0, %17 pen1
+        asm volatile("v_add_u32 %7, %16, %15\n\t"       // p03
+                     "v_add_u32 %10, %17, %14\n\t"      // p12
+                     "v_add_u32 %11, %17, %15\n\t"      // p13
+                     "v_add_u32 %8, %17, %12\n\t"       // p10
+                     "v_add_u32 %4, %16, %12\n\t"       // p00
+                     "v_add_u32 %9, %17, %13\n\t"       // p11
+                     "v_add_u32 %5, %16, %13\n\t"       // p01
+                     "v_add_u32 %6, %16, %14\n\t"       // p02
+                     "v_min3_i32 %0, %12, %5, %10\n\t"  // k0: p01, p12
+                     "v_min3_i32 %1, %13, %4, %6\n\t"   // k1: p00, p02, then p13
+                     "v_min3_i32 %2, %14, %5, %7\n\t"   // k2: p01, p03, then p10
+                     "v_min3_i32 %3, %15, %6, %9\n\t"   // k3: p02, p11
+                     "v_min_i32 %1, %1, %11\n\t"
+                     "v_min_i32 %2, %2, %8\n\t"
+                     EDP_DPP_MIN("%0", "%7", "row_shr:1")
+                     EDP_DPP_MIN("%0", "%10", "row_shr:1")
+                     EDP_DPP_MIN("%1", "%11", "row_shr:1")
+                     EDP_DPP_MIN("%2", "%8", "row_shl:1")
+                     EDP_DPP_MIN("%3", "%4", "row_shl:1")
+                     EDP_DPP_MIN("%3", "%9", "row_shl:1")
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]),
+                       "=&v"(p00), "=&v"(p01), "=&v"(p02), "=&v"(p03),
+                       "=&v"(p10), "=&v"(p11), "=&v"(p12), "=&v"(p13)
+                     : "v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "s"(pen[0]), "s"(pen[1]));
     }
+}
+#undef EDP_DPP_MIN
+
+// Minimum of each of N x-lines (the lane's K labels on each 16-lane row), all N computed before
+// any is used: the DPP moves of the N chains interleave (no wait states between them), and
+// the last move of each chain stays in the block of its minimum, where the two fuse.
+template <int K, int N>
+__device__ __forceinline__ void xline_mins(const int32_t (*const (&rows)[N])[K], int32_t (&m)[N], const int32_t lane) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        int32_t v = (*rows[i])[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) v = imin(v, (*rows[i])[k]);
+        m[i] = line_min<16, 1>(v, lane);
+    }
+    if constexpr (N == 4) asm volatile("" : "+v"(m[0]), "+v"(m[1]), "+v"(m[2]), "+v"(m[3]));
+    else if constexpr (N == 8)
+        asm volatile("" : "+v"(m[0]), "+v"(m[1]), "+v"(m[2]), "+v"(m[3]), "+v"(m[4]), "+v"(m[5]), "+v"(m[6]), "+v"(m[7]));
+    else
+#pragma unroll
+        for (int i = 0; i < N; ++i) asm volatile("" : "+v"(m[i]));
+}
+
+// Window minimum along x of the lane's K labels on one 16-lane row (one x-line per row): steps
+// u = 1..NWK with penalties pen[u-1] (PEN_OFF disables a step), then the clip at the line minimum
+// m + clipx.  clipx: the clip offset, or 2^30 for no clip (every value lies below line minimum +
+// 2^30, and the sum stays inside int32 since values lie below PADV).
+template <int K, int NWK>
+__device__ __forceinline__ void xwin16(int32_t (&h)[K], const int32_t (&pen)[2], const int32_t m, const int32_t clipx) {
+    int32_t o[K];
+    xwin_candidates<K, NWK>(h, pen, o);
     const int32_t cap = m + clipx;
 #pragma unroll
     for (int k = 0; k < K; ++k) h[k] = imin(o[k], cap);
-    return m;
 }
 
 template <class M, class CK, int MS, int PF>
@@ -508,10 +576,20 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         h2[ky][kx] = valid[ky][kx] ? ((A - dd) >> 1) : PADV;
                     }
                 // ---- window along x (lane rows), both sums
+                int32_t xm[2 * KY];
+                {
+                    const int32_t (*rows[2 * KY])[KX];
+#pragma unroll
+                    for (int ky = 0; ky < KY; ++ky) {
+                        rows[2 * ky] = &h[ky];
+                        rows[2 * ky + 1] = &h2[ky];
+                    }
+                    xline_mins<KX, 2 * KY>(rows, xm, lane);
+                }
 #pragma unroll
                 for (int ky = 0; ky < KY; ++ky) {
-                    xwin16<KX, NWK>(h[ky], wp.px, clipx, lane);
-                    xwin16<KX, NWK>(h2[ky], wp.px, clipx, lane);
+                    xwin16<KX, NWK>(h[ky], wp.px, xm[2 * ky], clipx);
+                    xwin16<KX, NWK>(h2[ky], wp.px, xm[2 * ky + 1], clipx);
                 }
                 // ---- exchange: label rows next to the lane rows' edges, column minima per wavefront
                 const int32_t par = s & 1;
