@@ -506,15 +506,17 @@ def cpu_baseline(prob, rows=None, budget_s=10.0):
 
 def bench_r3(edp, torch, steps, warmup):
     """EDP over a three-dimensional label space: the 640 x 480 motion-with-brightness-offset
-    workload, 7 x 7 motion labels and 7 offset levels (343 labels, padded to 8 x 8 x 8 in the
-    lanes of tile 19), lambda 40, T 3 per dimension, j = 1."""
+    workload, 7 x 7 motion labels and 7 offset levels (343 labels, padded to 8 x 8 x 8 on the
+    built-in wide tile 25: 8 x 8 lanes, two offset levels per lane on each of four wavefronts),
+    lambda 40, T 3 per dimension, j = 1."""
     import numpy as np
     import synth
     prob = synth.workload("motion_offset640x480")
     H, W, Q = prob.cost.shape
     pl = H * W * Q
     r = bench_edp(edp, torch, prob, steps, warmup, -1, 0)
-    roof = scan_roofline(prob, r, "edp_pass_motionoffset640x480q343", note=", tile 19 (8x8x8)")
+    roof = scan_roofline(prob, r, "edp_pass_motionoffset640x480q343", kernel="edp_pass_mv_kernel",
+                         note=", tile 25 (8x8x8 labels over four wavefronts)")
     return {"workload": "plain EDP, motion with a brightness offset 640x480, 7x7x7 labels (dx, dy in [-3, 3], "
                         "7 offset levels of 6 grey levels), int32 truncated squared-difference costs (cmax 2500), "
                         "lambda 40, T 3 per dimension, j=1",

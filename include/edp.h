@@ -41,7 +41,8 @@
  *     (edp_wide_tiles()).  Supported: one label dimension up to 256 labels
  *     (qy == 1); two dimensions up to 32 x 32 with any T, up to 64 x 64
  *     (64 x 32, 32 x 64) with T <= 3; three dimensions up to 8 x 8 x 8
- *     (edp_tiles_3d()).  The scanline DP calls take the single-wavefront
+ *     (edp_tiles_3d(), and with T <= 3 also edp_wide_tiles_3d()).  The
+ *     scanline DP calls take the single-wavefront
  *     tiles only (256 labels in one dimension, 32 x 32 in two).  Other label
  *     spaces return EDP_E_UNSUPPORTED (edp_dsi and edp_energy take any label
  *     space of up to 4096 labels).
@@ -101,7 +102,8 @@ typedef struct {
 /* Optional tuning of the launch (results never depend on it).  NULL, or a
  * zero / negative field, selects the built-in choice:
  *   tile   lane tile mapping labels to lanes (edp_tiles(), or for the EDP
- *          scans also edp_wide_tiles(); -1 automatic)
+ *          scans also edp_wide_tiles(), edp_tiles_3d() and
+ *          edp_wide_tiles_3d(); -1 automatic)
  *   chunk  EDP columns a workgroup hands to the next one between two
  *          progress publications, at least (rounded up to a power of two);
  *          only where the hand-off publishes column counts (wavefronts of
@@ -328,13 +330,27 @@ int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max);
  * return convention as edp_tiles(). */
 int32_t edp_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t max);
 
-/* Shape of a tile (edp_tiles(), edp_wide_tiles() or edp_tiles_3d()): lanes
- * px * py per cell, labels kx * ky per lane at each of its edp_tile_depth()
- * labels along the third dimension. */
+/* Wide-vertex tiles of the EDP scans usable for a (qx, qy, qz) label space with
+ * three label dimensions and truncation T <= 3 (the general RMS window of at
+ * most two steps per side, Sec. 3.1).  A vertex of up to 8 x 8 x kz labels
+ * (edp_tile_depth()) takes several wavefronts, each holding every (x, y) label
+ * at a few labels of the third dimension: the operators along x and y work
+ * inside the wavefront, the one along z exchanges the wavefronts' labels through
+ * LDS at every step (Sec. 3 eq. M_decmp).  Same return convention as
+ * edp_tiles(). */
+int32_t edp_wide_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t max);
+
+/* Shape of a tile (edp_tiles(), edp_wide_tiles(), edp_tiles_3d() or
+ * edp_wide_tiles_3d()): lanes px * py per cell, labels kx * ky per lane at each
+ * of its edp_tile_depth() labels along the third dimension (for the wide tiles
+ * the labels of all wavefronts of a vertex: 4 py wavefronts of 16 px lanes in
+ * two dimensions; 8 x 8 lanes per wavefront, the edp_tile_depth() labels along
+ * z spread over the wavefronts in three). */
 edp_status edp_tile_info(int32_t tile, int32_t* px, int32_t* kx, int32_t* py, int32_t* ky);
 
-/* Labels kz along the third label dimension that a tile holds in every lane
- * (1 for the tiles of one or two label dimensions). */
+/* Labels kz along the third label dimension that a tile holds (every lane of
+ * a tile of edp_tiles_3d(); all wavefronts of a vertex together for a tile of
+ * edp_wide_tiles_3d(); 1 for the tiles of one or two label dimensions). */
 edp_status edp_tile_depth(int32_t tile, int32_t* kz);
 
 /* Static text for a status code. */

@@ -8,4 +8,4 @@ torch tensors into it.
 from .binding import (  # noqa: F401
     EDP_E_TIMEOUT, PRIOR_LINEAR, PRIOR_SQUARED, TRUNC_JOINT, TRUNC_PER_DIM, BatchPlan, EdpError, Workspace,
     check_status, dp_marginals, dp_scanline, dsi, energy, load, solve, solve_windowed, tile_depth, tile_info, tiles,
-    tiles_3d, wide_tiles, workspace_size)
+    tiles_3d, wide_tiles, wide_tiles_3d, workspace_size)

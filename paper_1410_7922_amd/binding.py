@@ -30,7 +30,7 @@ EXPORTS = ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "
            "edp_tile_info", "edp_status_string", "edp_batch_workspace_size", "edp_batch_plan_create",
            "edp_batch_solve", "edp_batch_plan_info", "edp_batch_plan_destroy", "edp_window_workspace_size",
            "edp_solve_windowed", "edp_dp_marginals", "edp_dsi", "edp_solve_static", "edp_wide_tiles",
-           "edp_tiles_3d", "edp_tile_depth")
+           "edp_tiles_3d", "edp_wide_tiles_3d", "edp_tile_depth")
 
 
 class Problem(ctypes.Structure):
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
     L.edp_wide_tiles.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.edp_tile_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
     L.edp_tiles_3d.argtypes = [ctypes.c_int32] * 3 + [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    L.edp_wide_tiles_3d.argtypes = [ctypes.c_int32] * 3 + [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.edp_tile_depth.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.edp_status_string.argtypes = [ctypes.c_int32]
     L.edp_status_string.restype = ctypes.c_char_p
@@ -95,7 +96,8 @@ def load(path: str = LIB_PATH):
     for name in ("edp_workspace_size", "edp_dp_scanline", "edp_solve", "edp_energy", "edp_tiles",
                  "edp_tile_info", "edp_batch_workspace_size", "edp_batch_plan_create", "edp_batch_solve",
                  "edp_batch_plan_info", "edp_window_workspace_size", "edp_solve_windowed", "edp_dp_marginals",
-                 "edp_dsi", "edp_solve_static", "edp_wide_tiles", "edp_tiles_3d", "edp_tile_depth"):
+                 "edp_dsi", "edp_solve_static", "edp_wide_tiles", "edp_tiles_3d", "edp_wide_tiles_3d",
+                 "edp_tile_depth"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -204,8 +206,19 @@ def tile_info(tile: int) -> tuple:
     return tuple(x.value for x in v)
 
 
+def wide_tiles_3d(qx: int, qy: int, qz: int) -> list:
+    """Wide-vertex tiles of the EDP scans for a label space with three label dimensions."""
+    L = load()
+    n = L.edp_wide_tiles_3d(qx, qy, qz, None, 0)
+    if n < 0:
+        raise EdpError(n, "edp_wide_tiles_3d")
+    ids = (ctypes.c_int32 * max(n, 1))()
+    L.edp_wide_tiles_3d(qx, qy, qz, ids, n)
+    return list(ids[:n])
+
+
 def tile_depth(tile: int) -> int:
-    """Labels along the third label dimension that a tile holds per lane (1 below three dimensions)."""
+    """Labels along the third label dimension that a tile holds (1 below three dimensions)."""
     kz = ctypes.c_int32()
     _check(load().edp_tile_depth(tile, ctypes.byref(kz)), "edp_tile_depth")
     return kz.value

@@ -19,26 +19,32 @@ static_assert(STATUS_TIMEOUT == EDP_E_TIMEOUT, "status word value of a timed-out
 namespace {
 
 // Tiles by id: single-wavefront tiles (one or two label dimensions), the wide-vertex tiles as
-// 16 x (4 NV) lane grids, the single-wavefront tiles of three-dimensional label spaces.
-enum TileKind { TK_NONE = 0, TK_REG = 1, TK_WIDE = 2, TK_3D = 3 };
+// 16 x (4 NV) lane grids, the single-wavefront tiles of three-dimensional label spaces, the
+// wide-vertex tiles of three-dimensional label spaces (8 x 8 lanes, the third dimension over
+// the NV wavefronts).
+enum TileKind { TK_NONE = 0, TK_REG = 1, TK_WIDE = 2, TK_3D = 3, TK_WIDE3 = 4 };
 struct TileRow {
     TileShape s;
     int kind;
+    int nv;     // wavefronts per vertex
 };
 struct TileTable {
     TileRow t[NUM_ALL_TILES];
 };
 constexpr TileTable make_tiles() {
     TileTable r{};
-#define EDP_ROW(id, px, kx, py, ky) r.t[id] = TileRow{{px, kx, py, ky, 1}, TK_REG};
+#define EDP_ROW(id, px, kx, py, ky) r.t[id] = TileRow{{px, kx, py, ky, 1}, TK_REG, 1};
     EDP_TILE_LIST(EDP_ROW)
 #undef EDP_ROW
-#define EDP_MV_ROW(id, kx, ky, nv) r.t[id] = TileRow{{16, kx, 4 * nv, ky, 1}, TK_WIDE};
+#define EDP_MV_ROW(id, kx, ky, nv) r.t[id] = TileRow{{16, kx, 4 * nv, ky, 1}, TK_WIDE, nv};
     EDP_MV_TILE_LIST(EDP_MV_ROW)
 #undef EDP_MV_ROW
-#define EDP_ROW3(id, px, kx, py, ky, kz) r.t[id] = TileRow{{px, kx, py, ky, kz}, TK_3D};
+#define EDP_ROW3(id, px, kx, py, ky, kz) r.t[id] = TileRow{{px, kx, py, ky, kz}, TK_3D, 1};
     EDP_TILE3_LIST(EDP_ROW3)
 #undef EDP_ROW3
+#define EDP_MV3_ROW(id, kz, nv) r.t[id] = TileRow{{8, 1, 8, 1, kz * nv}, TK_WIDE3, nv};
+    EDP_MV3_TILE_LIST(EDP_MV3_ROW)
+#undef EDP_MV3_ROW
     return r;
 }
 constexpr TileTable kTileTable = make_tiles();
@@ -48,10 +54,11 @@ struct TileIndex {
 constexpr TileIndex kTiles{};
 int kind_of(int tile) { return tile >= 0 && tile < NUM_ALL_TILES ? kTileTable.t[tile].kind : TK_NONE; }
 
-bool is_wide(int tile) { return kind_of(tile) == TK_WIDE; }
+// tiles of the wide-vertex scan kernel (two- and three-dimensional label spaces)
+bool is_wide(int tile) { return kind_of(tile) == TK_WIDE || kind_of(tile) == TK_WIDE3; }
 // tiles of the single-wavefront scan kernel (two- and three-dimensional label spaces)
 bool is_regular(int tile) { return kind_of(tile) == TK_REG || kind_of(tile) == TK_3D; }
-int wide_nv(int tile) { return kTiles[tile].py / 4; }
+int wide_nv(int tile) { return kTileTable.t[tile].nv; }
 
 // labels along the third label dimension (0 in the problem means none)
 int qz_of(const edp_problem* p) { return p->qz > 1 ? p->qz : 1; }
@@ -212,18 +219,20 @@ edp_status pick_wide_launch(const edp_problem* p, const edp_tuning* tu, int tile
     return EDP_OK;
 }
 
-// Built-in choice for the EDP scans: with two label dimensions and a window search, a wide-vertex
-// tile unless a single-wavefront tile needs fewer padded labels (a vertex on two or more
-// wavefronts shortens the dependent step: measured 2.2 against 2.7 ms for 15x15 labels at
-// 320x240, 9.3 against 17 ms for 31x31 at 640x480); among wide tiles the fewest padded labels,
-// then the most wavefronts per vertex.  Otherwise the single-wavefront choice.
+// Built-in choice for the EDP scans: with two or three label dimensions and a window search, a
+// wide-vertex tile unless a single-wavefront tile needs fewer padded labels (a vertex on two or
+// more wavefronts shortens the dependent step: measured 2.2 against 2.7 ms for 15x15 labels at
+// 320x240, 9.3 against 17 ms for 31x31 at 640x480, 8.7 against 13.1 ms for 7x7x7 at 640x480);
+// among wide tiles the fewest padded labels, then the most wavefronts per vertex.  Otherwise the
+// single-wavefront choice.
 int auto_scan_tile(const edp_problem* p) {
     const int t = auto_tile(p->qx, p->qy, qz_of(p));
     const int ms = ms_of(p);
-    if (p->qy < 2 || qz_of(p) > 1 || (ms != MS_WINDOW && ms != MS_WINDOW1)) return t;
+    const bool three = qz_of(p) > 1;
+    if ((!three && p->qy < 2) || (ms != MS_WINDOW && ms != MS_WINDOW1)) return t;
     int best = -1;
     for (int w = 0; w < NUM_ALL_TILES; ++w) {
-        if (!is_wide(w) || !fits(w, p->qx, p->qy)) continue;
+        if (kind_of(w) != (three ? TK_WIDE3 : TK_WIDE) || !fits(w, p->qx, p->qy, qz_of(p))) continue;
         if (best < 0 || qt_of(w) < qt_of(best) || (qt_of(w) == qt_of(best) && wide_nv(w) > wide_nv(best))) best = w;
     }
     if (best < 0 || (t >= 0 && qt_of(t) < qt_of(best))) return t;
@@ -1189,7 +1198,7 @@ int32_t edp_wide_tiles(int32_t qx, int32_t qy, int32_t* ids, int32_t max) {
     if (qx < 1 || qy < 1 || max < 0) return EDP_E_INVALID;
     int n = 0;
     for (int t = 0; t < NUM_ALL_TILES; ++t) {
-        if (!is_wide(t) || !fits(t, qx, qy)) continue;
+        if (kind_of(t) != TK_WIDE || !fits(t, qx, qy)) continue;
         if (ids && n < max) ids[n] = t;
         ++n;
     }
@@ -1201,6 +1210,17 @@ int32_t edp_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t m
     int n = 0;
     for (int t = 0; t < NUM_ALL_TILES; ++t) {
         if (kind_of(t) != TK_3D || !fits(t, qx, qy, qz)) continue;
+        if (ids && n < max) ids[n] = t;
+        ++n;
+    }
+    return n;
+}
+
+int32_t edp_wide_tiles_3d(int32_t qx, int32_t qy, int32_t qz, int32_t* ids, int32_t max) {
+    if (qx < 1 || qy < 1 || qz < 1 || max < 0) return EDP_E_INVALID;
+    int n = 0;
+    for (int t = 0; t < NUM_ALL_TILES; ++t) {
+        if (kind_of(t) != TK_WIDE3 || !fits(t, qx, qy, qz)) continue;
         if (ids && n < max) ids[n] = t;
         ++n;
     }

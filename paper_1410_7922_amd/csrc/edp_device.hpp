@@ -736,13 +736,12 @@ __device__ __forceinline__ int32_t min_search(int32_t (&h)[T::KR][T::KX], const 
     }
 }
 
-// The minimum search operator M computed by the general RMS of Sec. 3.1: one
-// window operator per label dimension (eq. M_decmp1), clipped per line
-// (per-dimension truncation) or once at (min h + clipd) (joint truncation,
-// eq. M_decmp).  NWK as for window_line.  Same contract as min_search.
+// The windows along x and y of min_search_window (each of the lane's KZ slices of a tile of a
+// three-dimensional label space); the clips per line unless joint.  Returns min h over the
+// wavefront's labels.
 template <class T, int NWK>
-__device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KR][T::KX], const WinPen& sp,
-                                                   const int32_t clipd, const bool joint, const int32_t lane) {
+__device__ __forceinline__ int32_t min_search_xy(int32_t (&h)[T::KR][T::KX], const WinPen& sp, const int32_t clipd,
+                                                 const bool joint, const int32_t lane) {
     const int32_t l = lane % T::G;
     const int32_t px = l % T::PX, py = l / T::PX;
     constexpr bool one_dim = T::PY * T::KY == 1 && T::KZ == 1;
@@ -753,10 +752,8 @@ __device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KR][T::KX],
                                                              px, lane);
         rowmin = imin(rowmin, lm);
     }
-    if constexpr (one_dim) {
-        return rowmin;
-    } else {
-        int32_t gmin = rowmin;
+    int32_t gmin = rowmin;
+    if constexpr (!one_dim) {
         if constexpr (T::PY > 1) gmin = line_min<T::PY, T::PX>(gmin, lane);
         if constexpr (T::PY * T::KY > 1) {
 #pragma unroll
@@ -771,6 +768,22 @@ __device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KR][T::KX],
                     for (int ky = 0; ky < T::KY; ++ky) h[kz * T::KY + ky][kx] = col[ky];
                 }
         }
+    }
+    return gmin;
+}
+
+// The minimum search operator M computed by the general RMS of Sec. 3.1: one
+// window operator per label dimension (eq. M_decmp1), clipped per line
+// (per-dimension truncation) or once at (min h + clipd) (joint truncation,
+// eq. M_decmp).  NWK as for window_line.  Same contract as min_search.
+template <class T, int NWK>
+__device__ __forceinline__ int32_t min_search_window(int32_t (&h)[T::KR][T::KX], const WinPen& sp,
+                                                   const int32_t clipd, const bool joint, const int32_t lane) {
+    constexpr bool one_dim = T::PY * T::KY == 1 && T::KZ == 1;
+    const int32_t gmin = min_search_xy<T, NWK>(h, sp, clipd, joint, lane);
+    if constexpr (one_dim) {
+        return gmin;
+    } else {
         if constexpr (T::KZ > 1) {
 #pragma unroll
             for (int ky = 0; ky < T::KY; ++ky)

@@ -47,10 +47,16 @@
     X(20, 4, 1, 4, 1, 4)   \
     X(21, 4, 2, 4, 2, 4)
 
+// Wide-vertex tiles of three-dimensional label spaces: id, KZ, NV.  A vertex of up to
+// 8 x 8 x (KZ NV) labels takes NV wavefronts; lane px + 8 py of wavefront w holds the labels
+// (px, py, vz) for the KZ labels vz = w KZ ... w KZ + KZ - 1 of the third dimension.
+#define EDP_MV3_TILE_LIST(X) \
+    X(25, 2, 4)
+
 namespace edp {
 
 constexpr int NUM_TILES = 16;
-constexpr int NUM_ALL_TILES = 25;   // every id of the three tile lists is below this
+constexpr int NUM_ALL_TILES = 26;   // every id of the four tile lists is below this
 // A wide-vertex tile holds at most this many scanlines per workgroup times its wavefronts
 // per vertex: 8 wavefronts (512 lanes).
 constexpr int MV_MAX_WAVES = 8;

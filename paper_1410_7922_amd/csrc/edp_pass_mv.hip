@@ -9,6 +9,10 @@ template <int ID> struct MvTileOf;
     template <> struct MvTileOf<id> { using type = MvTile<kx, ky, nv>; };
 EDP_MV_TILE_LIST(EDP_MV_OF)
 #undef EDP_MV_OF
+#define EDP_MV3_OF(id, kz, nv) \
+    template <> struct MvTileOf<id> { using type = MvTile3<kz, nv>; };
+EDP_MV3_TILE_LIST(EDP_MV3_OF)
+#undef EDP_MV3_OF
 
 // Prefetch depth in steps: the loads of a step are few, so several steps stay in flight (fewer
 // where a lane holds more labels, or the helpers of eight slabs need more registers).
@@ -60,6 +64,9 @@ hipError_t launch_edp_pass_mv(int tile, int kind, int ms, const PassArgs& a, int
         return ms == MS_WINDOW1 ? kind_mv<MvTileOf<id>::type, MS_WINDOW1>(kind, a, grid, rows, s)          \
                                 : kind_mv<MvTileOf<id>::type, MS_WINDOW>(kind, a, grid, rows, s);
         EDP_MV_TILE_LIST(EDP_CASE)
+#define EDP_CASE3(id, kz, nv) EDP_CASE(id, 1, kz, nv)
+        EDP_MV3_TILE_LIST(EDP_CASE3)
+#undef EDP_CASE3
 #undef EDP_CASE
     }
     return hipErrorInvalidValue;
@@ -72,6 +79,9 @@ size_t pass_mv_lds_bytes(int tile, int ms, int rows, int ring) {
         return ms == MS_WINDOW1 ? mv_lds_bytes_t<MvTileOf<id>::type, 1>(rows, ring)       \
                                 : mv_lds_bytes_t<MvTileOf<id>::type, 2>(rows, ring);
         EDP_MV_TILE_LIST(EDP_CASE)
+#define EDP_CASE3(id, kz, nv) EDP_CASE(id, 1, kz, nv)
+        EDP_MV3_TILE_LIST(EDP_CASE3)
+#undef EDP_CASE3
 #undef EDP_CASE
     }
     return 0;
@@ -86,6 +96,9 @@ int pass_mv_capacity(int tile, int kind, int ms, int rows, size_t lds_bytes) {
                                   : kind_occ<MvTileOf<id>::type, MS_WINDOW>(kind, rows, lds_bytes);   \
         break;
         EDP_MV_TILE_LIST(EDP_CASE)
+#define EDP_CASE3(id, kz, nv) EDP_CASE(id, 1, kz, nv)
+        EDP_MV3_TILE_LIST(EDP_CASE3)
+#undef EDP_CASE3
 #undef EDP_CASE
     }
     int dev = 0, cus = 1;

@@ -41,6 +41,7 @@ namespace edp {
 
 template <int KX_, int KY_, int NV_>
 struct MvTile {
+    static constexpr bool D3 = false;
     static constexpr int KX = KX_, KY = KY_, NV = NV_;
     static constexpr int QXP = 16 * KX;           // labels along x: one 16-lane row
     static constexpr int SY = 4 * KY;             // label rows per wavefront
@@ -48,6 +49,28 @@ struct MvTile {
     static constexpr int E = KX * KY;             // labels per lane
     static constexpr int QT = QXP * QYP;          // labels per vertex (padded)
     using Lane = Tile<16, KX, 4, KY>;             // layout inside one wavefront
+    // exchange plane: PH rows (y) of PW words (x), then the column minima of each wavefront
+    static constexpr int PW = QXP, PH = QYP, CM = NV * QXP;
+};
+
+// A vertex of a three-dimensional label space on NV wavefronts: wavefront w holds the slices
+// vz = w KZ ... w KZ + KZ - 1 of the 8 x 8 (x, y) labels, lane px + 8 py the labels (px, py)
+// of its KZ slices (a tile of three-dimensional label spaces, Tile<8, 1, 8, 1, KZ>, per
+// wavefront).  The windows along x and y stay inside the wavefront; the window along z runs
+// across the wavefronts through an exchange plane of whole slices.  The label arrays of the
+// kernel take the slices as rows (KY = KZ, KX = 1).
+template <int KZ_, int NV_>
+struct MvTile3 {
+    static constexpr bool D3 = true;
+    static constexpr int KX = 1, KY = KZ_, NV = NV_;
+    static constexpr int QXP = 8, QYP = 8, QZP = NV * KZ_;
+    static constexpr int SY = 0;                  // (two-dimensional layouts only)
+    static constexpr int E = KZ_;
+    static constexpr int QT = QXP * QYP * QZP;
+    using Lane = Tile<8, 1, 8, 1, KZ_>;
+    // exchange plane: PH slices of 64 words, then each wavefront's per-lane minimum over its
+    // slices [NV][64] and its minimum over all its labels [NV]
+    static constexpr int PW = 64, PH = QZP, CM = NV * 64 + NV;
 };
 
 // LDS words of the control area: ticket, then three counter arrays of MV_CTR words.
@@ -56,10 +79,11 @@ constexpr int MV_HDR = 4 + 3 * MV_CTR;
 
 // Exchange unit of one scanline, one step parity and one of the two searches: the plane of
 // x results [QYP + 2 HB][QXP] (HB rows of PADV above and below), the column minima of each
-// wavefront [NV][QXP] and the vertex minima of each wavefront [NV].
+// wavefront [NV][QXP] and the vertex minima of each wavefront [NV] (three label dimensions: the
+// plane of slices [QZP + 2 HB][64] and the minima that MvTile3 lists, then the vertex minima).
 template <class M, int HB>
 constexpr int mv_xs() {
-    return (M::QYP + 2 * HB) * M::QXP + M::NV * M::QXP + (M::NV > 4 ? M::NV : 4);
+    return (M::PH + 2 * HB) * M::PW + M::CM + (M::NV > 4 ? M::NV : 4);
 }
 
 template <class M, int HB>
@@ -258,7 +282,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
     constexpr int NWK = MS == MS_WINDOW1 ? 1 : 2;    // window steps per side
     constexpr int HB = NWK;                          // halo rows of the y window
     constexpr int XS = mv_xs<M, HB>();
-    constexpr int PLANE = (M::QYP + 2 * HB) * QXP;
+    constexpr int PLANE = (M::PH + 2 * HB) * M::PW;
     extern __shared__ int32_t lds[];
     int32_t* const misc = lds;                       // [0] ticket broadcast
     int32_t* const wr = lds + 4;                     // [r * NV + w] columns written into ring r
@@ -277,10 +301,10 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
     const int32_t lofs = (w * 64 + lane) * E * 4;    // lane-major vertex layout
 
     // the halo rows of every exchange plane hold PADV for the whole launch
-    for (int32_t k = threadIdx.x; k < RW * 4 * 2 * HB * QXP; k += blockDim.x) {
-        const int32_t unit = k / (2 * HB * QXP), e = k % (2 * HB * QXP);
-        const int32_t r = e / QXP, c = e % QXP;
-        xch[unit * XS + (r < HB ? r : M::QYP + r) * QXP + c] = PADV;
+    for (int32_t k = threadIdx.x; k < RW * 4 * 2 * HB * M::PW; k += blockDim.x) {
+        const int32_t unit = k / (2 * HB * M::PW), e = k % (2 * HB * M::PW);
+        const int32_t r = e / M::PW, c = e % M::PW;
+        xch[unit * XS + (r < HB ? r : M::PH + r) * M::PW + c] = PADV;
     }
 
     for (;;) {
@@ -445,7 +469,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (row < nact) {
-            const int32_t Q = d.qx * d.qy;
+            const int32_t Q = M::D3 ? d.qx * d.qy * d.qz : d.qx * d.qy;
             const int32_t sx = pd.sx, sy = pd.sy, ka = pd.ka, kb = pd.kb;
             const int32_t tbytes = W * H * QT * 4;
             int32_t* const t_b = kb == 3 ? d.t[3] : d.t[2];
@@ -462,17 +486,31 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             const bool joint = d.joint != 0;
             const int32_t clipd = d.clipd;
             const int32_t clipx = joint ? 0x40000000 : clipd;   // x lines clip only per dimension
-            const WinPen wp(d.lam, d.trunc, d.qx, d.qy, d.squared != 0);
+            const WinPen wp(d.lam, d.trunc, d.qx, d.qy, d.squared != 0, M::D3 ? d.qz : 1);
             int32_t crun[KY];
             bool valid[KY][KX];
+            // three label dimensions: lane (px3, py3) of slab w, row ky = slice w KY + ky
+            const int32_t px3 = lane & 7, py3 = lane >> 3;
+            int32_t lab3[KY];                              // flat label of each slice (marginal)
+            if constexpr (M::D3) {
 #pragma unroll
-            for (int ky = 0; ky < KY; ++ky) {
-                const int32_t vy = vy0 + ky;
-                crun[ky] = (vy < d.qy && vx0 < d.qx) ? (vy * d.qx + vx0) * CB : OOB;
+                for (int ky = 0; ky < KY; ++ky) {
+                    const int32_t vz = w * KY + ky;
+                    lab3[ky] = (vz * d.qy + py3) * d.qx + px3;
+                    valid[ky][0] = px3 < d.qx && py3 < d.qy && vz < d.qz;
+                    crun[ky] = valid[ky][0] ? lab3[ky] * CB : OOB;
+                }
+            } else {
 #pragma unroll
-                for (int kx = 0; kx < KX; ++kx) valid[ky][kx] = vx0 + kx < d.qx && vy < d.qy;
+                for (int ky = 0; ky < KY; ++ky) {
+                    const int32_t vy = vy0 + ky;
+                    crun[ky] = (vy < d.qy && vx0 < d.qx) ? (vy * d.qx + vx0) * CB : OOB;
+#pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) valid[ky][kx] = vx0 + kx < d.qx && vy < d.qy;
+                }
             }
-            const bool rowok = vx0 < d.qx && vy0 < d.qy;   // the lane holds a real label
+            // the lane holds a real label
+            const bool rowok = M::D3 ? (px3 < d.qx && py3 < d.qy && w * KY < d.qz) : (vx0 < d.qx && vy0 < d.qy);
             const int32_t j = super * RW + row;             // scan-order row index
             const int32_t y = sy > 0 ? j : H - 1 - j;
             const int32_t yn = y + sy;
@@ -575,138 +613,236 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         h[ky][kx] = valid[ky][kx] ? ((A + dd) >> 1) : PADV;
                         h2[ky][kx] = valid[ky][kx] ? ((A - dd) >> 1) : PADV;
                     }
-                // ---- window along x (lane rows), both sums
-                int32_t xm[2 * KY];
-                {
-                    const int32_t (*rows[2 * KY])[KX];
+                if constexpr (M::D3) {
+                    // ---- windows along x and y inside the wavefront (each of its slices), both sums
+                    const int32_t g1 = min_search_xy<typename M::Lane, NWK>(h, wp, clipd, joint, lane);
+                    const int32_t g2 = min_search_xy<typename M::Lane, NWK>(h2, wp, clipd, joint, lane);
+                    const int32_t par = s & 1;
+                    int32_t* const u1 = xrow + (par * 2 + 0) * XS;
+                    int32_t* const u2 = xrow + (par * 2 + 1) * XS;
+                    if (marg) {
+                        // marginal of eq. DP_2D_1 at this vertex (as for two label dimensions)
+                        int32_t bv = 0x7FFFFFFF, bl = 0x7FFFFFFF;
+#pragma unroll
+                        for (int ky = 0; ky < KY; ++ky) {
+                            const int32_t A = cost_elem<CK, KX>(rc[u][ky], 0) + carry[ky][0] + lb[ky];
+                            const int32_t v = A + rma[u][ky][0] + rmb[u][ky][0];
+                            const bool better = valid[ky][0] && v < bv;   // labels rise with ky
+                            bv = better ? v : bv;
+                            bl = better ? lab3[ky] : bl;
+                        }
+                        const int32_t wv = rows_min4(line_min<16, 1>(bv, lane));
+                        const int32_t wl = rows_min4(line_min<16, 1>(bv == wv ? bl : 0x7FFFFFFF, lane));
+                        if (lane == 0) {
+                            u1[PLANE + M::CM + w] = wv;
+                            u2[PLANE + M::CM + w] = wl;
+                        }
+                    }
+                    // ---- exchange: the wavefront's slices, its per-lane minimum over them (the
+                    // clip of the z-lines) and its minimum over all its labels (the joint clip)
+                    int32_t m1 = h[0][0], m2 = h2[0][0];
 #pragma unroll
                     for (int ky = 0; ky < KY; ++ky) {
-                        rows[2 * ky] = &h[ky];
-                        rows[2 * ky + 1] = &h2[ky];
+                        u1[(HB + w * KY + ky) * 64 + lane] = h[ky][0];
+                        u2[(HB + w * KY + ky) * 64 + lane] = h2[ky][0];
+                        m1 = imin(m1, h[ky][0]);
+                        m2 = imin(m2, h2[ky][0]);
                     }
-                    xline_mins<KX, 2 * KY>(rows, xm, lane);
-                }
-#pragma unroll
-                for (int ky = 0; ky < KY; ++ky) {
-                    xwin16<KX, NWK>(h[ky], wp.px, xm[2 * ky], clipx);
-                    xwin16<KX, NWK>(h2[ky], wp.px, xm[2 * ky + 1], clipx);
-                }
-                // ---- exchange: label rows next to the lane rows' edges, column minima per wavefront
-                const int32_t par = s & 1;
-                int32_t* const u1 = xrow + (par * 2 + 0) * XS;
-                int32_t* const u2 = xrow + (par * 2 + 1) * XS;
-                if (marg) {
-                    // marginal of eq. DP_2D_1 at this vertex: C + T_-x(x + 1) + T_-y(y + 1) (this scan's
-                    // own sums) + T_+x(x - 1) + T_+y(y - 1) (the sums it reads), so A + both old sums;
-                    // this wavefront's smallest value and, among the labels holding it, the smallest label
-                    int32_t bv = 0x7FFFFFFF, bl = 0x7FFFFFFF;
-#pragma unroll
-                    for (int ky = 0; ky < KY; ++ky)
-#pragma unroll
-                        for (int kx = 0; kx < KX; ++kx) {
-                            const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + carry[ky][kx] + lb[ky * KX + kx];
-                            const int32_t v = A + rma[u][ky][kx] + rmb[u][ky][kx];
-                            const bool better = valid[ky][kx] && v < bv;   // labels rise with (ky, kx)
-                            bv = better ? v : bv;
-                            bl = better ? (vy0 + ky) * d.qx + vx0 + kx : bl;
-                        }
-                    const int32_t wv = rows_min4(line_min<16, 1>(bv, lane));
-                    const int32_t wl = rows_min4(line_min<16, 1>(bv == wv ? bl : 0x7FFFFFFF, lane));
+                    u1[PLANE + w * 64 + lane] = m1;
+                    u2[PLANE + w * 64 + lane] = m2;
                     if (lane == 0) {
-                        u1[PLANE + NV * QXP + w] = wv;
-                        u2[PLANE + NV * QXP + w] = wl;
+                        u1[PLANE + NV * 64 + w] = g1;
+                        u2[PLANE + NV * 64 + w] = g2;
                     }
-                }
-#pragma unroll
-                for (int ky = 0; ky < KY; ++ky) {
-                    if (ky < HB || ky >= KY - HB) {
-                        const int32_t o = (HB + vy0 + ky) * QXP + vx0;
-#pragma unroll
-                        for (int kx = 0; kx < KX; ++kx) {
-                            u1[o + kx] = h[ky][kx];
-                            u2[o + kx] = h2[ky][kx];
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    lds_put(xc_row + w, s + 1);
+                    {
+                        uint32_t spins = 0;
+#pragma nounroll
+                        while (lds_min_ctr<NV>(xc_row) < s + 1) {
+                            if (dead || give_up(spins)) break;
+                            __builtin_amdgcn_s_sleep(1);
                         }
                     }
-                }
-                int32_t c1[KX], c2[KX];
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    if (marg && w == 0) {
+                        int32_t fv = u1[PLANE + M::CM], fl = u2[PLANE + M::CM];
 #pragma unroll
-                for (int kx = 0; kx < KX; ++kx) {
-                    c1[kx] = h[0][kx];
-                    c2[kx] = h2[0][kx];
-#pragma unroll
-                    for (int ky = 1; ky < KY; ++ky) {
-                        c1[kx] = imin(c1[kx], h[ky][kx]);
-                        c2[kx] = imin(c2[kx], h2[ky][kx]);
+                        for (int v = 1; v < NV; ++v) {
+                            const int32_t ov = u1[PLANE + M::CM + v], ol = u2[PLANE + M::CM + v];
+                            fl = ov < fv ? ol : (ov == fv ? imin(fl, ol) : fl);
+                            fv = imin(fv, ov);
+                        }
+                        if (lane == 0 && live) lab_row[sx * s] = fl;
                     }
-                    rows_min4x2(c1[kx], c2[kx]);
-                }
-                // every lane row holds the same minima: all write them (no branch)
+                    // ---- window along z: own slices plus HB slices below and above; clip at the
+                    // z-line minimum (per-dimension truncation), or at the vertex minimum after the
+                    // window (joint truncation)
 #pragma unroll
-                for (int kx = 0; kx < KX; ++kx) {
-                    u1[PLANE + w * QXP + vx0 + kx] = c1[kx];
-                    u2[PLANE + w * QXP + vx0 + kx] = c2[kx];
-                }
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                lds_put(xc_row + w, s + 1);
-                {
-                    uint32_t spins = 0;
-#pragma nounroll
-                    while (lds_min_ctr<NV>(xc_row) < s + 1) {
-                        if (dead || give_up(spins)) break;
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                if (marg && w == 0) {
-                    int32_t fv = u1[PLANE + NV * QXP], fl = u2[PLANE + NV * QXP];
-#pragma unroll
-                    for (int v = 1; v < NV; ++v) {
-                        const int32_t ov = u1[PLANE + NV * QXP + v], ol = u2[PLANE + NV * QXP + v];
-                        fl = ov < fv ? ol : (ov == fv ? imin(fl, ol) : fl);
-                        fv = imin(fv, ov);
-                    }
-                    if (lane == 0 && live) lab_row[sx * s] = fl;
-                }
-                // ---- window along y: own rows plus HB rows above and below; clip at the column
-                // minimum (per-dimension truncation) or at the vertex minimum (joint truncation)
-#pragma unroll
-                for (int srch = 0; srch < 2; ++srch) {
-                    int32_t (&hv)[KY][KX] = srch ? h2 : h;
-                    const int32_t* const un = srch ? u2 : u1;
-                    int32_t cmin[KX];
-#pragma unroll
-                    for (int kx = 0; kx < KX; ++kx) {
-                        int32_t m = un[PLANE + vx0 + kx];
-#pragma unroll
-                        for (int v = 1; v < NV; ++v) m = imin(m, un[PLANE + v * QXP + vx0 + kx]);
-                        cmin[kx] = m;
-                    }
-                    // the vertex minimum of the sums equals the minimum of the x results (their
-                    // window includes the label itself, with no clip in joint mode)
-                    int32_t g = cmin[0];
-                    if (joint) {
-#pragma unroll
-                        for (int kx = 1; kx < KX; ++kx) g = imin(g, cmin[kx]);
-                        g = line_min<16, 1>(g, lane);
-                    }
-#pragma unroll
-                    for (int kx = 0; kx < KX; ++kx) {
+                    for (int srch = 0; srch < 2; ++srch) {
+                        int32_t (&hv)[KY][KX] = srch ? h2 : h;
+                        const int32_t* const un = srch ? u2 : u1;
+                        const int32_t* const ez = un + w * KY * 64 + lane;   // slices w KY - HB ..
                         int32_t e[KY + 2 * HB];
 #pragma unroll
-                        for (int k = 0; k < HB; ++k) {
-                            e[k] = un[(vy0 + k) * QXP + vx0 + kx];                  // row vy0 - HB + k
-                            e[HB + KY + k] = un[(HB + vy0 + KY + k) * QXP + vx0 + kx];   // row vy0 + KY + k
-                        }
+                        for (int i = 0; i < KY + 2 * HB; ++i) e[i] = ez[i * 64];
+                        int32_t cap = 0x7FFFFFFF;
+                        if (!joint) {
+                            int32_t zm = un[PLANE + lane];
 #pragma unroll
-                        for (int ky = 0; ky < KY; ++ky) e[HB + ky] = hv[ky][kx];
-                        const int32_t cap = (joint ? g : cmin[kx]) + clipd;
+                            for (int v = 1; v < NV; ++v) zm = imin(zm, un[PLANE + v * 64 + lane]);
+                            cap = zm + clipd;
+                        }
 #pragma unroll
                         for (int ky = 0; ky < KY; ++ky) {
                             int32_t o = imin(e[HB + ky], cap);
 #pragma unroll
                             for (int st = 1; st <= NWK; ++st)
-                                o = imin3(o, e[HB + ky - st] + wp.py[st - 1], e[HB + ky + st] + wp.py[st - 1]);
-                            hv[ky][kx] = o;
+                                o = imin3(o, e[HB + ky - st] + wp.pz[st - 1], e[HB + ky + st] + wp.pz[st - 1]);
+                            hv[ky][0] = o;
+                        }
+                        if (joint) {
+                            int32_t g = un[PLANE + NV * 64];
+#pragma unroll
+                            for (int v = 1; v < NV; ++v) g = imin(g, un[PLANE + NV * 64 + v]);
+#pragma unroll
+                            for (int ky = 0; ky < KY; ++ky) hv[ky][0] = imin(hv[ky][0], g + clipd);
+                        }
+                    }
+                } else {
+                    // ---- window along x (lane rows), both sums
+                    int32_t xm[2 * KY];
+                    {
+                        const int32_t (*rows[2 * KY])[KX];
+    #pragma unroll
+                        for (int ky = 0; ky < KY; ++ky) {
+                            rows[2 * ky] = &h[ky];
+                            rows[2 * ky + 1] = &h2[ky];
+                        }
+                        xline_mins<KX, 2 * KY>(rows, xm, lane);
+                    }
+    #pragma unroll
+                    for (int ky = 0; ky < KY; ++ky) {
+                        xwin16<KX, NWK>(h[ky], wp.px, xm[2 * ky], clipx);
+                        xwin16<KX, NWK>(h2[ky], wp.px, xm[2 * ky + 1], clipx);
+                    }
+                    // ---- exchange: label rows next to the lane rows' edges, column minima per wavefront
+                    const int32_t par = s & 1;
+                    int32_t* const u1 = xrow + (par * 2 + 0) * XS;
+                    int32_t* const u2 = xrow + (par * 2 + 1) * XS;
+                    if (marg) {
+                        // marginal of eq. DP_2D_1 at this vertex: C + T_-x(x + 1) + T_-y(y + 1) (this scan's
+                        // own sums) + T_+x(x - 1) + T_+y(y - 1) (the sums it reads), so A + both old sums;
+                        // this wavefront's smallest value and, among the labels holding it, the smallest label
+                        int32_t bv = 0x7FFFFFFF, bl = 0x7FFFFFFF;
+    #pragma unroll
+                        for (int ky = 0; ky < KY; ++ky)
+    #pragma unroll
+                            for (int kx = 0; kx < KX; ++kx) {
+                                const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + carry[ky][kx] + lb[ky * KX + kx];
+                                const int32_t v = A + rma[u][ky][kx] + rmb[u][ky][kx];
+                                const bool better = valid[ky][kx] && v < bv;   // labels rise with (ky, kx)
+                                bv = better ? v : bv;
+                                bl = better ? (vy0 + ky) * d.qx + vx0 + kx : bl;
+                            }
+                        const int32_t wv = rows_min4(line_min<16, 1>(bv, lane));
+                        const int32_t wl = rows_min4(line_min<16, 1>(bv == wv ? bl : 0x7FFFFFFF, lane));
+                        if (lane == 0) {
+                            u1[PLANE + NV * QXP + w] = wv;
+                            u2[PLANE + NV * QXP + w] = wl;
+                        }
+                    }
+    #pragma unroll
+                    for (int ky = 0; ky < KY; ++ky) {
+                        if (ky < HB || ky >= KY - HB) {
+                            const int32_t o = (HB + vy0 + ky) * QXP + vx0;
+    #pragma unroll
+                            for (int kx = 0; kx < KX; ++kx) {
+                                u1[o + kx] = h[ky][kx];
+                                u2[o + kx] = h2[ky][kx];
+                            }
+                        }
+                    }
+                    int32_t c1[KX], c2[KX];
+    #pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) {
+                        c1[kx] = h[0][kx];
+                        c2[kx] = h2[0][kx];
+    #pragma unroll
+                        for (int ky = 1; ky < KY; ++ky) {
+                            c1[kx] = imin(c1[kx], h[ky][kx]);
+                            c2[kx] = imin(c2[kx], h2[ky][kx]);
+                        }
+                        rows_min4x2(c1[kx], c2[kx]);
+                    }
+                    // every lane row holds the same minima: all write them (no branch)
+    #pragma unroll
+                    for (int kx = 0; kx < KX; ++kx) {
+                        u1[PLANE + w * QXP + vx0 + kx] = c1[kx];
+                        u2[PLANE + w * QXP + vx0 + kx] = c2[kx];
+                    }
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    lds_put(xc_row + w, s + 1);
+                    {
+                        uint32_t spins = 0;
+    #pragma nounroll
+                        while (lds_min_ctr<NV>(xc_row) < s + 1) {
+                            if (dead || give_up(spins)) break;
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    if (marg && w == 0) {
+                        int32_t fv = u1[PLANE + NV * QXP], fl = u2[PLANE + NV * QXP];
+    #pragma unroll
+                        for (int v = 1; v < NV; ++v) {
+                            const int32_t ov = u1[PLANE + NV * QXP + v], ol = u2[PLANE + NV * QXP + v];
+                            fl = ov < fv ? ol : (ov == fv ? imin(fl, ol) : fl);
+                            fv = imin(fv, ov);
+                        }
+                        if (lane == 0 && live) lab_row[sx * s] = fl;
+                    }
+                    // ---- window along y: own rows plus HB rows above and below; clip at the column
+                    // minimum (per-dimension truncation) or at the vertex minimum (joint truncation)
+    #pragma unroll
+                    for (int srch = 0; srch < 2; ++srch) {
+                        int32_t (&hv)[KY][KX] = srch ? h2 : h;
+                        const int32_t* const un = srch ? u2 : u1;
+                        int32_t cmin[KX];
+    #pragma unroll
+                        for (int kx = 0; kx < KX; ++kx) {
+                            int32_t m = un[PLANE + vx0 + kx];
+    #pragma unroll
+                            for (int v = 1; v < NV; ++v) m = imin(m, un[PLANE + v * QXP + vx0 + kx]);
+                            cmin[kx] = m;
+                        }
+                        // the vertex minimum of the sums equals the minimum of the x results (their
+                        // window includes the label itself, with no clip in joint mode)
+                        int32_t g = cmin[0];
+                        if (joint) {
+    #pragma unroll
+                            for (int kx = 1; kx < KX; ++kx) g = imin(g, cmin[kx]);
+                            g = line_min<16, 1>(g, lane);
+                        }
+    #pragma unroll
+                        for (int kx = 0; kx < KX; ++kx) {
+                            int32_t e[KY + 2 * HB];
+    #pragma unroll
+                            for (int k = 0; k < HB; ++k) {
+                                e[k] = un[(vy0 + k) * QXP + vx0 + kx];                  // row vy0 - HB + k
+                                e[HB + KY + k] = un[(HB + vy0 + KY + k) * QXP + vx0 + kx];   // row vy0 + KY + k
+                            }
+    #pragma unroll
+                            for (int ky = 0; ky < KY; ++ky) e[HB + ky] = hv[ky][kx];
+                            const int32_t cap = (joint ? g : cmin[kx]) + clipd;
+    #pragma unroll
+                            for (int ky = 0; ky < KY; ++ky) {
+                                int32_t o = imin(e[HB + ky], cap);
+    #pragma unroll
+                                for (int st = 1; st <= NWK; ++st)
+                                    o = imin3(o, e[HB + ky - st] + wp.py[st - 1], e[HB + ky + st] + wp.py[st - 1]);
+                                hv[ky][kx] = o;
+                            }
                         }
                     }
                 }

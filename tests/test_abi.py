@@ -239,14 +239,22 @@ def test_static_workspace_solve_refuses_problems_beyond_its_array():
 
 
 def test_three_label_dimensions_on_the_host():
-    """qz > 1: the EDP solve takes 3D label spaces on the tiles of edp_tiles_3d (z inside a lane);
+    """qz > 1: the EDP solve takes 3D label spaces on the tiles of edp_tiles_3d (z inside a lane) and
+    of edp_wide_tiles_3d (z across the wavefronts of a vertex);
     the DP calls and the label-window solve refuse them; qz = 0 means one or two dimensions."""
     assert B.tiles_3d(7, 7, 7) == [19]
     assert B.tiles_3d(4, 4, 4) == [19, 20, 21] and B.tiles_3d(8, 8, 4) == [19, 21]
     assert B.tiles_3d(9, 2, 2) == [] and B.tiles_3d(2, 2, 9) == []
     assert B.tile_info(19) == (8, 1, 8, 1) and B.tile_depth(19) == 8
     assert B.tile_depth(21) == 4 and B.tile_depth(16) == 1 and B.tile_depth(0) == 1
+    # the wide-vertex tile of three label dimensions: 8 x 8 lanes, z over four wavefronts
+    assert B.wide_tiles_3d(7, 7, 7) == [25] and B.wide_tiles_3d(8, 8, 8) == [25] and B.wide_tiles_3d(2, 2, 2) == [25]
+    assert B.wide_tiles_3d(9, 1, 2) == [] and B.wide_tiles_3d(1, 1, 9) == []
+    assert B.tile_info(25) == (8, 1, 8, 1) and B.tile_depth(25) == 8
+    assert 25 not in B.wide_tiles(8, 8) and 25 not in B.tiles_3d(7, 7, 7)
     p3 = dict(qx=7, qy=7, qz=7, dtype=2, cost_bound=2500, lam=40, trunc=3)
+    assert _ws(_prob(**p3), B.OP_EDP, 25)[0] == 0
+    assert _ws(_prob(**{**p3, "trunc": 5}), B.OP_EDP, 25)[0] == -5   # wide tiles: window search, T <= 3
     st, n = _ws(_prob(**p3), B.OP_EDP)
     assert st == 0 and n >= 4 * 384 * 288 * 512 * 4
     assert _ws(_prob(**p3), B.OP_EDP, 19)[0] == 0

@@ -1,6 +1,7 @@
 """GPU parity of the EDP solve over three label dimensions (the tiles of edp_tiles_3d: every lane
-holds its labels at each label of the third dimension, whose operator runs inside the lane)
-against the C oracle, bit-exact: labels and energy.
+holds its labels at each label of the third dimension, whose operator runs inside the lane; the
+wide tile of edp_wide_tiles_3d: the third dimension spread over the wavefronts of a vertex, its
+operator exchanging them through LDS) against the C oracle, bit-exact: labels and energy.
 
 Cases cover every 3D tile, the four minimum searches the scans compile (general RMS windows of
 one and two steps, the linear RMS, the walked window of the squared prior), both truncation
@@ -63,12 +64,18 @@ def test_three_dimensional_tiles_against_oracle(case):
     p = synth.random_problem(W * 17 + H * 5 + qx + qy + qz + j, W, H, qx, qy, lam, T, mode, lo, hi, dt, qz=qz)
     ref = cref.edp(p.cost, qx, qy, lam, T, mode, j, search_of((T, prior)), prior=prior, qz=qz)
     tiles = edp.tiles_3d(qx, qy, qz)
-    assert tiles
-    for tile in [-1] + tiles:
+    wide = edp.wide_tiles_3d(qx, qy, qz)
+    assert tiles and wide
+    for tile in [-1] + tiles + (wide if T <= 3 else []):
         note(f"r3 {p.name} T{T} mode {mode} prior {prior} j{j} tile {tile}")
         lab, e = gpu_edp(p, qz, j, tile, prior)
         assert np.array_equal(lab, ref["labels"]), tile
         assert e == ref["energy"], tile
+    if T > 3:
+        # the wide tiles take the window search of at most two steps per side only
+        with pytest.raises(edp.EdpError) as err:
+            gpu_edp(p, qz, j, wide[0], prior)
+        assert err.value.status == -5
 
 
 @pytest.mark.parametrize("split,waves,fuse", [(2, 0, 0), (1, 1, 1), (2, 3, 2)])
@@ -81,6 +88,17 @@ def test_lane_splits_and_launch_shapes(split, waves, fuse):
         note(f"r3 split {split} waves {waves} fuse {fuse} tile {tile}")
         lab, e = gpu_edp(p, 4, 1, tile, split=split, waves=waves, fuse=fuse)
         assert np.array_equal(lab, ref["labels"]) and e == ref["energy"], tile
+
+
+@pytest.mark.parametrize("waves,fuse", [(1, 1), (2, 2), (1, 2)])
+def test_wide_tile_launch_shapes(waves, fuse):
+    """The wide 3D tile with one or two scanlines per workgroup and one or two scans per launch,
+    on a grid of several workgroup bands with a ragged last band, j = 2: the same labels."""
+    p = synth.random_problem(91, 23, 17, 7, 6, 9, 3, 0, 0, 400, np.int32, qz=5)
+    ref = cref.edp(p.cost, 7, 6, 9, 3, 0, 2, "grms", qz=5)
+    note(f"r3 wide tile rows {waves} fuse {fuse}")
+    lab, e = gpu_edp(p, 5, 2, 25, waves=waves, fuse=fuse)
+    assert np.array_equal(lab, ref["labels"]) and e == ref["energy"]
 
 
 def test_lambda_zero_is_winner_take_all():
@@ -128,6 +146,27 @@ def test_batch_mixes_two_and_three_dimensional_instances():
         ref = cref.edp(q.cost, q.qx, q.qy, q.lam, q.trunc, q.mode, 1, "grms", qz=q.qz)
         assert np.array_equal(labels[i].cpu().numpy(), ref["labels"]), i
         assert int(energies[i].item()) == ref["energy"], i
+
+
+def test_full_size_offset_workload_against_golden():
+    """The 640 x 480 workload with 343 labels at full size, on the built-in tile and on each tile of
+    three label dimensions: labels and energy equal the C oracle's (its golden, written by
+    tests/golden/make_motion_offset640x480_q343.py)."""
+    import hashlib
+    import json
+    import os
+    p = synth.workload("motion_offset640x480")
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "edp_motion_offset640x480_q343.json")) as f:
+        g = json.load(f)
+    assert g["cost_sha256"] == p.sha256()
+    cost = torch.from_numpy(p.cost).to(DEV)
+    for tile in [-1] + edp.tiles_3d(7, 7, 7) + edp.wide_tiles_3d(7, 7, 7):
+        note(f"r3 640x480 q343 golden tile {tile}")
+        lab, e = edp.solve(cost, 7, 7, p.lam, p.trunc, p.mode, iterations=1, cost_bound=2501, qz=7, tile=tile)
+        torch.cuda.synchronize()
+        sha = hashlib.sha256(np.ascontiguousarray(lab.cpu().numpy(), np.int32).tobytes()).hexdigest()
+        assert sha == g["labels_sha256"] and int(e.item()) == g["energy"], tile
 
 
 def test_full_size_offset_workload_properties():
