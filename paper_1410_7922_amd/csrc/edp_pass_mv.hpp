@@ -1,5 +1,5 @@
 // EDP scans (Mozerov, arXiv 1410.7922, Sec. 4.2) with a vertex spread over several
-// wavefronts, for two-dimensional label spaces.
+// wavefronts, for two- and three-dimensional label spaces.
 //
 // The scans compute the same T-form recursion as edp_pass_kernel (see there):
 //   A   = C + T_a(x - sx, y) + T_b(x, y - sy)
@@ -23,12 +23,17 @@
 //  * everything else of the step (the sums, the loads and stores, the hand-off of
 //    T_b to the next scanline) concerns the wavefront's own slab only.
 //
+// Three label dimensions (MvTile3): wavefront w holds slices of the third dimension,
+// all 8 x 8 (x, y) labels of each on its lanes; the windows along x and y run inside
+// the wavefront, the one along z through the exchange plane, which then holds whole
+// slices.
+//
 // A workgroup holds RW consecutive scanlines of one scan, each on NV wavefronts.
 // Scanline k hands T_b to scanline k + 1 through an LDS ring per wavefront slab;
 // the last scanline of the workgroup stores it as tagged 64-bit words (value and
 // a tag naming scan, workgroup band and column; word-major, so every store is a
-// whole run of sectors) that two helper wavefronts of the next workgroup poll, two row buffers per scan of a launch used alternately by
-// consecutive workgroup bands (a band writes column c only after the band below
+// whole run of sectors) that two helper wavefronts of the next workgroup poll, two
+// row buffers per scan of a launch used alternately by consecutive workgroup bands (a band writes column c only after the band below
 // the previous user of the buffer has read column c: it needs that band's result
 // at column c first).  Workgroups take bands in scan order from a ticket counter,
 // as in edp_pass_kernel; the fused second scan of a launch waits for whole bands
