@@ -1,19 +1,20 @@
 """Launch-shape autotuner for the EDP solver (tile, split, waves, chunk, fuse).
 
 The library's results never depend on the launch shape; only its speed does.
-For a label space (qx, qy), a cost dtype and a grid size, the tuner times
-candidate shapes of ``edp_solve`` on the caller's own cost volume and keeps the
-fastest, checking that every candidate returns the same labels and energy as
+For a label space (qx, qy, qz), a prior, a cost dtype and a grid size, the tuner
+times candidate shapes of ``edp_solve`` on the caller's own cost volume and keeps
+the fastest, checking that every candidate returns the same labels and energy as
 the built-in shape.  Choices are cached in a JSON file keyed by
-``qx x qy : dtype : mode : W x H : iterations``.
+``qx x qy : dtype : mode : W x H : iterations``, with ``:z<qz>`` for three label
+dimensions and ``:p<prior>`` for the squared prior appended.
 
 Search (staged, so a key costs a few dozen solves):
   1. every single-wavefront tile that holds the label space with at most 4x padding, each
      split the tile allows, with 4 wavefronts per workgroup; and every wide tile (a vertex on
-     several wavefronts; two label dimensions with a window search) with its built-in
-     scanlines per workgroup;
-  2. the best (tile, split) with 1, 2, 4 and 6 wavefronts (wide tiles: 1 up to the most
-     scanlines per workgroup), one or two scans per launch;
+     several wavefronts; two or three label dimensions with a window search) with its
+     built-in scanlines per workgroup;
+  2. the best (tile, split) with 1, 2, 4 and 6 wavefronts (wide tiles: 1 up to 8 scanlines
+     per workgroup, as many as the tile takes), one or two scans per launch;
   3. the best so far with progress published every 1, 2, 4, 8 or 16 columns (single-wavefront
      tiles).
 """
@@ -29,9 +30,14 @@ from . import binding as B
 SHAPE_KEYS = ("tile", "split", "waves", "chunk", "fuse")
 
 
-def key_of(qx, qy, dtype, mode, W, H, iterations=1) -> str:
+def key_of(qx, qy, dtype, mode, W, H, iterations=1, qz=1, prior=0) -> str:
     d = "i16" if dtype in (torch.int16, "i16", 1) else "i32"
-    return f"{qx}x{qy}:{d}:{mode}:{W}x{H}:{iterations}"
+    k = f"{qx}x{qy}:{d}:{mode}:{W}x{H}:{iterations}"
+    if qz > 1:
+        k += f":z{qz}"
+    if prior:
+        k += f":p{prior}"
+    return k
 
 
 class TuneCache:
@@ -60,7 +66,8 @@ class TuneCache:
 def _time_solve(cost, p, shape, reps, ws, labels, energy):
     status = torch.empty(1, dtype=torch.int32, device=cost.device)
     kw = dict(mode=p["mode"], iterations=p.get("iterations", 1), cost_bound=p["cost_bound"], ws=ws,
-              labels=labels, energy=energy, status=status, **{k: shape[k] for k in SHAPE_KEYS})
+              labels=labels, energy=energy, status=status, qz=p["qz"], prior=p["prior"],
+              **{k: shape[k] for k in SHAPE_KEYS})
     B.solve(cost, p["qx"], p["qy"], p["lam"], p["trunc"], **kw)      # warm-up (waits, checks the status)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
@@ -75,13 +82,14 @@ def _time_solve(cost, p, shape, reps, ws, labels, energy):
 def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict:
     """Fastest launch shape for one instance (cost on the GPU, params as for BatchPlan)."""
     qx, qy = params["qx"], params.get("qy", 1)
-    p = dict(params, qy=qy, mode=params.get("mode", B.TRUNC_PER_DIM))
+    qz = max(params.get("qz", 1), 1)
+    p = dict(params, qy=qy, qz=qz, mode=params.get("mode", B.TRUNC_PER_DIM), prior=params.get("prior", B.PRIOR_LINEAR))
     ws = B.Workspace()
     H, W = cost.shape[:2]
     labels = torch.empty((H, W), dtype=torch.int32, device=cost.device)
     energy = torch.empty(1, dtype=torch.int64, device=cost.device)
     ref_l, ref_e = B.solve(cost, qx, qy, p["lam"], p["trunc"], p["mode"], p.get("iterations", 1),
-                           cost_bound=p["cost_bound"])
+                           cost_bound=p["cost_bound"], qz=qz, prior=p["prior"])
     torch.cuda.synchronize()
     seen = {}
 
@@ -98,12 +106,17 @@ def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict
             raise RuntimeError(f"launch shape {shape} changed the result")
         seen[k] = ms
         if verbose:
-            print(f"[tune] {key_of(qx, qy, cost.dtype, p['mode'], W, H)} {shape} {ms:.3f} ms", flush=True)
+            print(f"[tune] {key_of(qx, qy, cost.dtype, p['mode'], W, H, 1, qz, p['prior'])} {shape} {ms:.3f} ms",
+                  flush=True)
         return ms
 
-    q = qx * qy
-    tiles = [t for t in B.tiles(qx, qy)]
-    wide = [t for t in B.wide_tiles(qx, qy)] if qy > 1 and p["trunc"] <= 3 else []
+    q = qx * qy * qz
+    if qz > 1:
+        tiles = B.tiles_3d(qx, qy, qz)
+        wide = B.wide_tiles_3d(qx, qy, qz) if p["trunc"] <= 3 else []
+    else:
+        tiles = B.tiles(qx, qy)
+        wide = B.wide_tiles(qx, qy) if qy > 1 and p["trunc"] <= 3 else []
     qts = {t: _qt(t) for t in tiles + wide}
     small = min(qts.values())
     tiles = [t for t in tiles if qts[t] <= max(4 * q, small)]
@@ -122,10 +135,13 @@ def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict
             consider(dict(tile=t, split=split, waves=4, chunk=4, fuse=2))
     for t in wide:
         consider(dict(tile=t, split=1, waves=0, chunk=0, fuse=2))
+    if best is None:
+        # no shape ran (the built-in shape is the only one for this problem)
+        return dict(tile=-1, split=0, waves=0, chunk=0, fuse=0, ms=None)
     base = dict(best)
     if base["tile"] in wide:
-        rows = 8 // (B.tile_info(base["tile"])[2] // 4)     # scanlines of NV wavefronts, 8 at most
-        for waves in range(1, rows + 1):
+        # scanlines per workgroup: the library refuses more than the tile's wavefronts allow
+        for waves in range(1, 9):
             for fuse in (1, 2):
                 consider(dict(base, waves=waves, fuse=fuse))
         return dict(best, ms=best_ms)
@@ -140,7 +156,7 @@ def tune(cost: torch.Tensor, params: dict, reps: int = 3, verbose=False) -> dict
 
 def _qt(tile):
     px, kx, py, ky = B.tile_info(tile)
-    return px * kx * py * ky
+    return px * kx * py * ky * B.tile_depth(tile)
 
 
 def tune_batch(costs, params, cache: TuneCache | None = None, reps: int = 3, verbose=False,
@@ -153,8 +169,9 @@ def tune_batch(costs, params, cache: TuneCache | None = None, reps: int = 3, ver
     keys, groups = [], {}
     for i, (c, p) in enumerate(zip(costs, params)):
         H, W = c.shape[:2]
-        keys.append(key_of(p["qx"], p.get("qy", 1), c.dtype, p.get("mode", 0), W, H, p.get("iterations", 1)))
-        gk = (p["qx"], p.get("qy", 1), str(c.dtype), p.get("mode", 0), p.get("iterations", 1))
+        qz, prior = max(p.get("qz", 1), 1), p.get("prior", 0)
+        keys.append(key_of(p["qx"], p.get("qy", 1), c.dtype, p.get("mode", 0), W, H, p.get("iterations", 1), qz, prior))
+        gk = (p["qx"], p.get("qy", 1), qz, prior, str(c.dtype), p.get("mode", 0), p.get("iterations", 1))
         groups.setdefault(gk, []).append(i)
     shapes = [None] * len(costs)
     for members in groups.values():
