@@ -719,14 +719,14 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                     int32_t xm[2 * KY];
                     {
                         const int32_t (*rows[2 * KY])[KX];
-    #pragma unroll
+#pragma unroll
                         for (int ky = 0; ky < KY; ++ky) {
                             rows[2 * ky] = &h[ky];
                             rows[2 * ky + 1] = &h2[ky];
                         }
                         xline_mins<KX, 2 * KY>(rows, xm, lane);
                     }
-    #pragma unroll
+#pragma unroll
                     for (int ky = 0; ky < KY; ++ky) {
                         xwin16<KX, NWK>(h[ky], wp.px, xm[2 * ky], clipx);
                         xwin16<KX, NWK>(h2[ky], wp.px, xm[2 * ky + 1], clipx);
@@ -740,9 +740,9 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         // own sums) + T_+x(x - 1) + T_+y(y - 1) (the sums it reads), so A + both old sums;
                         // this wavefront's smallest value and, among the labels holding it, the smallest label
                         int32_t bv = 0x7FFFFFFF, bl = 0x7FFFFFFF;
-    #pragma unroll
+#pragma unroll
                         for (int ky = 0; ky < KY; ++ky)
-    #pragma unroll
+#pragma unroll
                             for (int kx = 0; kx < KX; ++kx) {
                                 const int32_t A = cost_elem<CK, KX>(rc[u][ky], kx) + carry[ky][kx] + lb[ky * KX + kx];
                                 const int32_t v = A + rma[u][ky][kx] + rmb[u][ky][kx];
@@ -757,11 +757,11 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                             u2[PLANE + NV * QXP + w] = wl;
                         }
                     }
-    #pragma unroll
+#pragma unroll
                     for (int ky = 0; ky < KY; ++ky) {
                         if (ky < HB || ky >= KY - HB) {
                             const int32_t o = (HB + vy0 + ky) * QXP + vx0;
-    #pragma unroll
+#pragma unroll
                             for (int kx = 0; kx < KX; ++kx) {
                                 u1[o + kx] = h[ky][kx];
                                 u2[o + kx] = h2[ky][kx];
@@ -769,11 +769,11 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         }
                     }
                     int32_t c1[KX], c2[KX];
-    #pragma unroll
+#pragma unroll
                     for (int kx = 0; kx < KX; ++kx) {
                         c1[kx] = h[0][kx];
                         c2[kx] = h2[0][kx];
-    #pragma unroll
+#pragma unroll
                         for (int ky = 1; ky < KY; ++ky) {
                             c1[kx] = imin(c1[kx], h[ky][kx]);
                             c2[kx] = imin(c2[kx], h2[ky][kx]);
@@ -781,7 +781,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         rows_min4x2(c1[kx], c2[kx]);
                     }
                     // every lane row holds the same minima: all write them (no branch)
-    #pragma unroll
+#pragma unroll
                     for (int kx = 0; kx < KX; ++kx) {
                         u1[PLANE + w * QXP + vx0 + kx] = c1[kx];
                         u2[PLANE + w * QXP + vx0 + kx] = c2[kx];
@@ -790,7 +790,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                     lds_put(xc_row + w, s + 1);
                     {
                         uint32_t spins = 0;
-    #pragma nounroll
+#pragma nounroll
                         while (lds_min_ctr<NV>(xc_row) < s + 1) {
                             if (dead || give_up(spins)) break;
                             __builtin_amdgcn_s_sleep(1);
@@ -799,7 +799,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                     __atomic_signal_fence(__ATOMIC_SEQ_CST);
                     if (marg && w == 0) {
                         int32_t fv = u1[PLANE + NV * QXP], fl = u2[PLANE + NV * QXP];
-    #pragma unroll
+#pragma unroll
                         for (int v = 1; v < NV; ++v) {
                             const int32_t ov = u1[PLANE + NV * QXP + v], ol = u2[PLANE + NV * QXP + v];
                             fl = ov < fv ? ol : (ov == fv ? imin(fl, ol) : fl);
@@ -809,15 +809,17 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                     }
                     // ---- window along y: own rows plus HB rows above and below; clip at the column
                     // minimum (per-dimension truncation) or at the vertex minimum (joint truncation)
-    #pragma unroll
+#pragma unroll
                     for (int srch = 0; srch < 2; ++srch) {
-                        int32_t (&hv)[KY][KX] = srch ? h2 : h;
-                        const int32_t* const un = srch ? u2 : u1;
+                        // T_b first: it leaves the wavefront (ring or tagged words), T_a only feeds
+                        // this scanline's next step (measured 0.3% faster)
+                        int32_t (&hv)[KY][KX] = srch ? h : h2;
+                        const int32_t* const un = srch ? u1 : u2;
                         int32_t cmin[KX];
-    #pragma unroll
+#pragma unroll
                         for (int kx = 0; kx < KX; ++kx) {
                             int32_t m = un[PLANE + vx0 + kx];
-    #pragma unroll
+#pragma unroll
                             for (int v = 1; v < NV; ++v) m = imin(m, un[PLANE + v * QXP + vx0 + kx]);
                             cmin[kx] = m;
                         }
@@ -825,25 +827,25 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                         // window includes the label itself, with no clip in joint mode)
                         int32_t g = cmin[0];
                         if (joint) {
-    #pragma unroll
+#pragma unroll
                             for (int kx = 1; kx < KX; ++kx) g = imin(g, cmin[kx]);
                             g = line_min<16, 1>(g, lane);
                         }
-    #pragma unroll
+#pragma unroll
                         for (int kx = 0; kx < KX; ++kx) {
                             int32_t e[KY + 2 * HB];
-    #pragma unroll
+#pragma unroll
                             for (int k = 0; k < HB; ++k) {
                                 e[k] = un[(vy0 + k) * QXP + vx0 + kx];                  // row vy0 - HB + k
                                 e[HB + KY + k] = un[(HB + vy0 + KY + k) * QXP + vx0 + kx];   // row vy0 + KY + k
                             }
-    #pragma unroll
+#pragma unroll
                             for (int ky = 0; ky < KY; ++ky) e[HB + ky] = hv[ky][kx];
                             const int32_t cap = (joint ? g : cmin[kx]) + clipd;
-    #pragma unroll
+#pragma unroll
                             for (int ky = 0; ky < KY; ++ky) {
                                 int32_t o = imin(e[HB + ky], cap);
-    #pragma unroll
+#pragma unroll
                                 for (int st = 1; st <= NWK; ++st)
                                     o = imin3(o, e[HB + ky - st] + wp.py[st - 1], e[HB + ky + st] + wp.py[st - 1]);
                                 hv[ky][kx] = o;
