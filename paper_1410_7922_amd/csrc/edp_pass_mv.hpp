@@ -474,6 +474,9 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (row < nact) {
+            // the band's last scanline hands its row to the next band: it goes first on its SIMDs
+            // (0.3% faster side by side)
+            if (row == nact - 1) __builtin_amdgcn_s_setprio(1);
             const int32_t Q = M::D3 ? d.qx * d.qy * d.qz : d.qx * d.qy;
             const int32_t sx = pd.sx, sy = pd.sy, ka = pd.ka, kb = pd.kb;
             const int32_t tbytes = W * H * QT * 4;
@@ -901,6 +904,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                 for (int u = 0; u < PF; ++u) step(std::true_type{}, u, s0 + u);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         // band complete (see edp_pass_kernel)
         if (a.npass > 1 && !second) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
