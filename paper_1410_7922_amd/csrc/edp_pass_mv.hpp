@@ -530,7 +530,9 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
             const int32_t ba = bt + dt;
             const int32_t bb = cell_off(yn * W + x0, QT * 4) + lofs;
             const int32_t nsteps = (W + PF - 1) / PF * PF;
-            int32_t* const lab_row = d.labels + (size_t)y * W + x0;   // labels of the row (last P4)
+            // labels of the row (last P4), written as global (not flat) stores: a flat store also
+            // counts against the LDS wait counter, so the next LDS wait would wait for it
+            gu32* const lab_row = (gu32*)(d.labels + (size_t)y * W + x0);
 
             // T_b of the scanline above through ring `row`; this scanline's T_b into ring row + 1 or,
             // for the band's last scanline, as tagged words for the band below
@@ -681,7 +683,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                             fl = ov < fv ? ol : (ov == fv ? imin(fl, ol) : fl);
                             fv = imin(fv, ov);
                         }
-                        if (lane == 0 && live) lab_row[sx * s] = fl;
+                        if (lane == 0 && live) lab_row[sx * s] = (uint32_t)fl;
                     }
                     // ---- window along z: own slices plus HB slices below and above; clip at the
                     // z-line minimum (per-dimension truncation), or at the vertex minimum after the
@@ -808,7 +810,7 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                             fl = ov < fv ? ol : (ov == fv ? imin(fl, ol) : fl);
                             fv = imin(fv, ov);
                         }
-                        if (lane == 0 && live) lab_row[sx * s] = fl;
+                        if (lane == 0 && live) lab_row[sx * s] = (uint32_t)fl;
                     }
                     // ---- window along y: own rows plus HB rows above and below; clip at the column
                     // minimum (per-dimension truncation) or at the vertex minimum (joint truncation)
