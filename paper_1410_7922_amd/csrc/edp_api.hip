@@ -426,7 +426,14 @@ struct ClassRun {
     int agg_blocks, cells_per_block;
     uint32_t* tickets;         // one counter per scan launch
     uint32_t* error;
+    int64_t sums_bytes;        // bytes of one array of sums over the class's instances
 };
+
+// Memory-side cache (Infinity Cache) of the device: where one array of sums is larger, a later scan
+// finds none of it there, and the wide-tile scans stream the sums with non-temporal accesses.
+constexpr int64_t kMallBytes = (int64_t)256 << 20;
+
+int64_t sums_bytes_of(const edp_problem& p, int tile) { return (int64_t)p.width * p.height * qt_of(tile) * 4; }
 
 int agg_cells_per_block(int tile) { return is_wide(tile) ? 4 : (64 / group_of(tile)) * 4; }
 
@@ -474,7 +481,8 @@ edp_status enqueue_class(const ClassRun& c, const edp_tuning* ev, hipStream_t s)
             a.ticket = c.tickets + launch;
             const bool timed = ev && ev->events && 2 * launch + 1 < ev->n_events;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch], s) != hipSuccess) return EDP_E_HIP;
-            const hipError_t le = is_wide(c.tile) ? launch_edp_pass_mv(c.tile, c.kind, c.ms, a, grid, c.waves, s)
+            const hipError_t le = is_wide(c.tile) ? launch_edp_pass_mv(c.tile, c.kind, c.ms, a, grid, c.waves, s,
+                                                                       c.sums_bytes > kMallBytes)
                                                   : launch_edp_pass(c.tile, c.kind, c.split, c.ms, a, grid, c.waves, s);
             if (le != hipSuccess) return EDP_E_HIP;
             if (timed && hipEventRecord((hipEvent_t)ev->events[2 * launch + 1], s) != hipSuccess)
@@ -604,6 +612,7 @@ struct BatchClassPlan {
     int first_desc;
     size_t tickets_word, error_word;
     int tickets_per_pass, agg_blocks, cells_per_block, energy_blocks;
+    int64_t sums_bytes;
 };
 
 struct BatchLayout {
@@ -674,8 +683,10 @@ edp_status plan_batch(int32_t n, const edp_batch_item* items, BatchLayout* B) {
         first_desc += (int)k.members.size();
         k.cells_per_block = agg_cells_per_block(k.tile);
         int64_t tickets = 0, blocks = 0, eblocks = 0;
+        k.sums_bytes = 0;
         for (int i : k.members) {
             const edp_problem& p = items[i].problem;
+            k.sums_bytes += sums_bytes_of(p, k.tile);
             tickets += B->e[i].la.nsuper;
             blocks += ((int64_t)p.width * p.height + k.cells_per_block - 1) / k.cells_per_block;
             eblocks += (p.height + kEnergyRows - 1) / kEnergyRows;
@@ -858,6 +869,7 @@ edp_status edp_solve(const edp_problem* prob, const edp_tuning* tuning, const vo
     c.ms = ms_of(prob);
     c.one = make_desc(prob, la, L.inst, ws, flags, ws + L.hand, d_cost, d_labels, nullptr);
     c.one.status = d_status;
+    c.sums_bytes = sums_bytes_of(*prob, la.tile);
     c.descs = nullptr;
     c.ndesc = 1;
     c.tickets_per_pass = la.nsuper;
@@ -975,6 +987,7 @@ edp_status edp_batch_solve(const edp_batch_plan* plan, void* stream) {
         c.cells_per_block = k.cells_per_block;
         c.tickets = ctrl + k.tickets_word;
         c.error = ctrl + k.error_word;
+        c.sums_bytes = k.sums_bytes;
         edp_status st = enqueue_class(c, nullptr, cs);
         if (st != EDP_OK) return st;
         BatchEnergyArgs ea{};

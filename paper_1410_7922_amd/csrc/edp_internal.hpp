@@ -309,7 +309,9 @@ hipError_t launch_recenter(const int32_t* labels, int64_t n, int32_t qx, int32_t
 
 int pass_capacity(int tile, int kind, int split, int ms, int waves, size_t lds_bytes);
 // Wide-vertex scans (tiles NUM_TILES ...): rows = scanlines per workgroup; window kinds only.
-hipError_t launch_edp_pass_mv(int tile, int kind, int ms, const PassArgs& a, int grid, int rows, hipStream_t s);
+// nt: non-temporal loads and stores of the sums (int32 costs)
+hipError_t launch_edp_pass_mv(int tile, int kind, int ms, const PassArgs& a, int grid, int rows, hipStream_t s,
+                              bool nt);
 hipError_t launch_edp_aggregate_mv(int tile, int dtype, const AggArgs& a, int grid, hipStream_t s);
 size_t pass_mv_lds_bytes(int tile, int ms, int rows, int ring);
 int pass_mv_capacity(int tile, int kind, int ms, int rows, size_t lds_bytes);

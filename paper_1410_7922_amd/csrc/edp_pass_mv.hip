@@ -19,31 +19,33 @@ EDP_MV3_TILE_LIST(EDP_MV3_OF)
 template <class M>
 constexpr int mv_pf() { return M::E <= 4 && M::NV <= 4 ? 4 : 2; }
 
-template <class M, class CK, int MS>
+template <class M, class CK, int MS, bool NT = false>
 static hipError_t run_mv(const PassArgs& a, int grid, int rows, hipStream_t s) {
     const size_t lds = mv_lds_bytes_t<M, MS == MS_WINDOW1 ? 1 : 2>(rows, a.ring);
-    hipLaunchKernelGGL((edp_pass_mv_kernel<M, CK, MS, mv_pf<M>()>), dim3(grid), dim3(64 * (M::NV * rows + 2)), lds, s, a);
+    hipLaunchKernelGGL((edp_pass_mv_kernel<M, CK, MS, mv_pf<M>(), NT>), dim3(grid), dim3(64 * (M::NV * rows + 2)), lds,
+                       s, a);
     return hipGetLastError();
 }
 
 template <class M, class CK, int MS>
 static int occ_mv(int rows, size_t lds) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_mv_kernel<M, CK, MS, mv_pf<M>()>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, edp_pass_mv_kernel<M, CK, MS, mv_pf<M>(), false>,
                                                      64 * (M::NV * rows + 2), lds) != hipSuccess)
         blocks = 1;
     return blocks < 1 ? 1 : blocks;
 }
 
-// cost kind: 1 int16 (element loads), 2 int32, 3 int16 in aligned pairs
+// cost kind: 1 int16 (element loads), 2 int32, 3 int16 in aligned pairs; nt: non-temporal sums
+// (instantiated for int32 costs, the large motion volumes)
 template <class M, int MS>
-static hipError_t kind_mv(int kind, const PassArgs& a, int grid, int rows, hipStream_t s) {
+static hipError_t kind_mv(int kind, const PassArgs& a, int grid, int rows, hipStream_t s, bool nt) {
     if (kind == 1) return run_mv<M, int16_t, MS>(a, grid, rows, s);
     if (kind == 3) {
         if constexpr (M::KX % 2 == 0) return run_mv<M, Pair16, MS>(a, grid, rows, s);
         return hipErrorInvalidValue;
     }
-    return run_mv<M, int32_t, MS>(a, grid, rows, s);
+    return nt ? run_mv<M, int32_t, MS, true>(a, grid, rows, s) : run_mv<M, int32_t, MS>(a, grid, rows, s);
 }
 template <class M, int MS>
 static int kind_occ(int kind, int rows, size_t lds) {
@@ -55,14 +57,15 @@ static int kind_occ(int kind, int rows, size_t lds) {
     return occ_mv<M, int32_t, MS>(rows, lds);
 }
 
-hipError_t launch_edp_pass_mv(int tile, int kind, int ms, const PassArgs& a, int grid, int rows, hipStream_t s) {
+hipError_t launch_edp_pass_mv(int tile, int kind, int ms, const PassArgs& a, int grid, int rows, hipStream_t s,
+                              bool nt) {
     if (ms != MS_WINDOW && ms != MS_WINDOW1) return hipErrorInvalidValue;
     switch (tile) {
 #define EDP_CASE(id, kx, ky, nv)                                                                          \
     case id:                                                                                              \
         if (rows < 1 || rows * nv > MV_MAX_WAVES) return hipErrorInvalidValue;                            \
-        return ms == MS_WINDOW1 ? kind_mv<MvTileOf<id>::type, MS_WINDOW1>(kind, a, grid, rows, s)          \
-                                : kind_mv<MvTileOf<id>::type, MS_WINDOW>(kind, a, grid, rows, s);
+        return ms == MS_WINDOW1 ? kind_mv<MvTileOf<id>::type, MS_WINDOW1>(kind, a, grid, rows, s, nt)      \
+                                : kind_mv<MvTileOf<id>::type, MS_WINDOW>(kind, a, grid, rows, s, nt);
         EDP_MV_TILE_LIST(EDP_CASE)
 #define EDP_CASE3(id, kz, nv) EDP_CASE(id, 1, kz, nv)
         EDP_MV3_TILE_LIST(EDP_CASE3)

@@ -279,7 +279,9 @@ __device__ __forceinline__ void xwin16(int32_t (&h)[K], const int32_t (&pen)[2],
     for (int k = 0; k < K; ++k) h[k] = imin(o[k], cap);
 }
 
-template <class M, class CK, int MS, int PF>
+// NT: the sums' loads and stores are non-temporal (the host sets it where one array of sums
+// outgrows the memory-side cache, so nothing would be found there again).
+template <class M, class CK, int MS, int PF, bool NT>
 __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(const PassArgs a) {
     constexpr int KX = M::KX, KY = M::KY, NV = M::NV, E = M::E, QT = M::QT, QXP = M::QXP, SY = M::SY;
     constexpr int CB = CostBytes<CK>::value;
@@ -566,10 +568,11 @@ __global__ __launch_bounds__(64 * (MV_MAX_WAVES + 2)) void edp_pass_mv_kernel(co
                 return dead;
             };
 
-            // the sums stream: each is read once by a later scan, so their loads and stores are
-            // non-temporal (1.7% faster on the 961-label solve; the same on the costs, which the
-            // fused second scan reads again, was 2% slower)
-            constexpr int SUMS_NT = 2;
+            // each sum is read once, by a later scan: where the arrays outgrow the memory-side
+            // cache their loads and stores are non-temporal (1.7% faster on the 961-label solve
+            // 640x480; 3% slower at 320x240 with 256 labels, whose sums the cache still holds;
+            // non-temporal cost loads, which the fused second scan repeats, were 2% slower)
+            constexpr int SUMS_NT = NT ? 2 : 0;
             auto fetch = [&](const int32_t t, int32_t (&c)[KY][CW], int32_t (&ma)[KY][KX], int32_t (&mb)[KY][KX]) {
                 const bool act = rowok && t < W;
                 const int32_t offc = act ? bc + t * dc : OOB;
