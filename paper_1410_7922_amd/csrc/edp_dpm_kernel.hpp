@@ -24,22 +24,24 @@
 #include <type_traits>
 
 #include "edp_device.hpp"
+#include "edp_stream.hpp"
 #include "edp_internal.hpp"
 
 namespace edp {
 
 __device__ __forceinline__ int32_t off_add(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
 
-// E forward terms of one lane (contiguous, FT each) at byte offset off.
+// E forward terms of one lane (contiguous, FT each) at byte offset off; non-temporal loads, like
+// those of the costs: the backward sweep reads each once (1.21 -> 1.19 ms on 8192 x 1024 x 64)
 template <class FT, int E>
 __device__ __forceinline__ void load_terms(__amdgpu_buffer_rsrc_t r, int32_t off, int32_t (&v)[E]) {
     if constexpr (sizeof(FT) == 4) {
-        load_vec<E>(r, off, v);
+        load_vec<E, CPOL_NT>(r, off, v);
     } else if constexpr (E == 1) {
-        v[0] = (int32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        v[0] = (int32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, CPOL_NT);
     } else {
         int32_t w[E / 2];
-        load_vec<E / 2>(r, off, w);
+        load_vec<E / 2, CPOL_NT>(r, off, w);
 #pragma unroll
         for (int k = 0; k < E / 2; ++k) {
             v[2 * k] = w[k] & 0xFFFF;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
         const int32_t x = col(k);
         const int32_t base = in ? off_add(crow, x * Q * CB) : OOB;
 #pragma unroll
-        for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, in ? off_add(base, crun[ky]) : OOB, rc[u][ky]);
+        for (int ky = 0; ky < KY; ++ky) load_cost_words_nt<CK, KX>(rs_c, in ? off_add(base, crun[ky]) : OOB, rc[u][ky]);
         if constexpr (!FWD) load_terms<FT, E>(rs_f, in ? off_add(frow, x * QT * (int32_t)sizeof(FT)) : OOB, rf[u]);
     };
     // the vector searched next: s on the real labels, PADV on padding labels
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(256) void dpm_kernel(const DpmArgs a) {
     if constexpr (FWD) {
         int32_t c0[KY][CW];
 #pragma unroll
-        for (int ky = 0; ky < KY; ++ky) load_cost_words<CK, KX>(rs_c, off_add(crow, crun[ky]), c0[ky]);
+        for (int ky = 0; ky < KY; ++ky) load_cost_words_nt<CK, KX>(rs_c, off_add(crow, crun[ky]), c0[ky]);
         const int32_t zero[E] = {};
         store_terms<FT, E>(rs_f, frow, zero);          // F(0) = 0
         int32_t s[KY][KX];
